@@ -1,0 +1,863 @@
+/*
+ * pamc_oracle.c -- plain single-threaded CPU oracle for augmented PAMC.
+ *
+ * TEST INFRASTRUCTURE ONLY (see pamc_oracle.h).  Nothing here is tuned: each
+ * step follows the paper's order and notation so that it can be read against
+ * the paper.  Build with -ffp-contract=off: every floating-point value that
+ * decides an integer (thresholds, resampling weights, the inverse
+ * temperature) is produced by a fixed sequence of IEEE-754 operations.
+ */
+#include "pamc_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11).  Each round multiplies counter words 0 and 2   */
+/* by the two round multipliers, xors the high halves with the other two    */
+/* counter words and the round key, and the key advances by the two Weyl    */
+/* constants between rounds.                                                */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)PHILOX_M0 * x0;
+    uint64_t p1 = (uint64_t)PHILOX_M1 * x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)p1;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)p0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    k0 += PHILOX_W0;
+    k1 += PHILOX_W1;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static void philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                   uint32_t out[4]) {
+  uint32_t ctr[4] = {c0, c1, c2, c3};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exponential: Cody & Waite argument reduction (W. J. Cody, W. Waite,      */
+/* "Software Manual for the Elementary Functions", 1980):                   */
+/*   x = k ln2 + r, |r| <= ln2/2, with ln2 split in a high part whose       */
+/*   product with k is exact and a low correction;                         */
+/* e^r by its Taylor series to degree 13 in Horner form with fused          */
+/* multiply-adds; then scaling by 2^k done in exact power-of-two steps so   */
+/* that a subnormal result is rounded once.                                 */
+/* ------------------------------------------------------------------------ */
+static double pow2i(int k) { /* 2^k for -1022 <= k <= 1023 */
+  uint64_t bits = (uint64_t)(k + 1023) << 52;
+  double d;
+  memcpy(&d, &bits, sizeof d);
+  return d;
+}
+
+double orc_pexp(double x) {
+  const double inv_ln2 = 1.4426950408889634;
+  const double ln2_hi = 0.6931471803691238;     /* 32 significant bits */
+  const double ln2_lo = 1.9082149292705877e-10;
+  if (x != x) return x;
+  if (x > 709.8) return INFINITY;
+  if (x < -745.5) return 0.0;
+  double k = rint(x * inv_ln2);
+  double r = (x - k * ln2_hi) - k * ln2_lo;
+  /* 1/j! for j = 13 .. 2 */
+  double p = 1.6059043836821613e-10;
+  p = fma(p, r, 2.08767569878681e-09);
+  p = fma(p, r, 2.505210838544172e-08);
+  p = fma(p, r, 2.755731922398589e-07);
+  p = fma(p, r, 2.7557319223985893e-06);
+  p = fma(p, r, 2.48015873015873e-05);
+  p = fma(p, r, 0.0001984126984126984);
+  p = fma(p, r, 0.001388888888888889);
+  p = fma(p, r, 0.008333333333333333);
+  p = fma(p, r, 0.041666666666666664);
+  p = fma(p, r, 0.16666666666666666);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  int ki = (int)k;
+  if (ki > 1000) return (p * pow2i(ki - 200)) * pow2i(200);
+  if (ki < -1000) return (p * pow2i(ki + 200)) * pow2i(-200);
+  return p * pow2i(ki);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Acceptance thresholds.  x = s_k h_k, the energy change of a flip is 2x.  */
+/* Heat bath (Eq. 4): the new spin is +1 with probability                   */
+/* (1 + tanh(beta h))/2, so the flip probability is 1/(1 + e^{2 beta x}).   */
+/* Metropolis: min(1, e^{-2 beta x}).  A flip happens iff a uniform 32-bit  */
+/* word u satisfies u < T, T = min(floor(p 2^32), 2^32 - 1); Metropolis     */
+/* moves with x <= 0 are always taken.                                      */
+/* ------------------------------------------------------------------------ */
+uint32_t orc_threshold(double beta, int32_t rule, int64_t x) {
+  double t = 2.0 * beta;
+  double p;
+  if (rule == ORC_RULE_METROPOLIS) {
+    if (x <= 0) return 0xFFFFFFFFu;
+    p = orc_pexp(-(t * (double)x));
+  } else {
+    double e = orc_pexp(t * (double)x);
+    p = 1.0 / (1.0 + e);
+  }
+  double q = floor(p * 4294967296.0);
+  if (q >= 4294967295.0) return 0xFFFFFFFFu;
+  return (uint32_t)q;
+}
+
+static int flip_decision(uint32_t u, double beta, int32_t rule, int64_t x) {
+  if (rule == ORC_RULE_METROPOLIS && x <= 0) return 1;
+  return u < orc_threshold(beta, rule, x);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Instance                                                                 */
+/* ------------------------------------------------------------------------ */
+struct orc {
+  int32_t n, nnz, R, rule, shuffle, dense;
+  uint64_t seed;
+  /* graph in internal ids */
+  int32_t *row_ptr, *col, *J;
+  int32_t ncls, *class_ptr;
+  int32_t *to_input, *to_internal;
+  int64_t W, X;
+  /* population, slot-major [R][n] */
+  int8_t* s;
+  int32_t* h;
+  int64_t* E;
+  int32_t* family;
+  uint32_t gs, g_rs, g_cl;
+  int64_t mstar;
+  int8_t* best; /* internal ids */
+  /* Max-3-Cut embedding: original graph (input ids) */
+  int32_t m3_n;
+  int32_t *m3_row_ptr, *m3_col, *m3_w;
+};
+
+static void set_err(char* err, int32_t errlen, const char* msg) {
+  if (err && errlen > 0) {
+    strncpy(err, msg, (size_t)errlen - 1);
+    err[errlen - 1] = 0;
+  }
+}
+
+int32_t orc_colour(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* colour) {
+  /* c(v) = least k >= 0 not used by a neighbour u < v, v ascending. */
+  int32_t ncls = 0;
+  int32_t* seen = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  for (int32_t k = 0; k <= n; ++k) seen[k] = -1;
+  for (int32_t v = 0; v < n; ++v) {
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      int32_t u = col[e];
+      if (u < v) seen[colour[u]] = v;
+    }
+    int32_t k = 0;
+    while (seen[k] == v) ++k;
+    colour[v] = k;
+    if (k + 1 > ncls) ncls = k + 1;
+  }
+  free(seen);
+  return ncls;
+}
+
+static int validate_csr(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                        const int32_t* w, char* err, int32_t errlen) {
+  if (n <= 0) { set_err(err, errlen, "n must be positive"); return 0; }
+  if (row_ptr[0] != 0) { set_err(err, errlen, "row_ptr[0] != 0"); return 0; }
+  for (int32_t v = 0; v < n; ++v)
+    if (row_ptr[v + 1] < row_ptr[v]) { set_err(err, errlen, "row_ptr not monotone"); return 0; }
+  int32_t nnz = row_ptr[n];
+  for (int32_t e = 0; e < nnz; ++e) {
+    if (col[e] < 0 || col[e] >= n) { set_err(err, errlen, "column out of range"); return 0; }
+    if (w[e] == 0) { set_err(err, errlen, "zero weight"); return 0; }
+  }
+  /* self loops, duplicates, symmetry: dense scan per row (slow and plain) */
+  int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* wt = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  for (int32_t v = 0; v < n; ++v) mark[v] = -1;
+  int ok = 1;
+  for (int32_t v = 0; v < n && ok; ++v) {
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      int32_t u = col[e];
+      if (u == v) { set_err(err, errlen, "self loop"); ok = 0; break; }
+      if (mark[u] == v) { set_err(err, errlen, "duplicate edge"); ok = 0; break; }
+      mark[u] = v;
+      wt[u] = w[e];
+    }
+    if (!ok) break;
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1] && ok; ++e) {
+      int32_t u = col[e];
+      int found = 0;
+      for (int32_t f = row_ptr[u]; f < row_ptr[u + 1]; ++f)
+        if (col[f] == v) { found = (w[f] == wt[u]); break; }
+      if (!found) { set_err(err, errlen, "not symmetric"); ok = 0; }
+    }
+  }
+  free(mark);
+  free(wt);
+  return ok;
+}
+
+static orc* alloc_orc(int32_t n, int32_t R) {
+  orc* o = (orc*)calloc(1, sizeof(orc));
+  o->n = n;
+  o->R = R;
+  o->s = (int8_t*)calloc((size_t)R * n, 1);
+  o->h = (int32_t*)calloc((size_t)R * n, sizeof(int32_t));
+  o->E = (int64_t*)calloc((size_t)R, sizeof(int64_t));
+  o->family = (int32_t*)calloc((size_t)R, sizeof(int32_t));
+  o->best = (int8_t*)calloc((size_t)n, 1);
+  o->to_input = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+  o->to_internal = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+  return o;
+}
+
+/* Population initialisation (Algorithm 1, initialization): uniform random
+ * spins, local fields by Eq. 3, energies H = -1/2 sum_v s_v h_v, M* = 0 with
+ * the all-(+1) configuration (cut 0) as the best. */
+static void init_population(orc* o) {
+  int32_t n = o->n;
+  for (int32_t r = 0; r < o->R; ++r) {
+    int8_t* s = o->s + (size_t)r * n;
+    for (int32_t v = 0; v < n; ++v) {
+      uint32_t out[4];
+      philox(o->seed, (uint32_t)(v >> 2), 0u, (uint32_t)r, ORC_TAG_INIT, out);
+      s[v] = (out[v & 3] < 0x80000000u) ? 1 : -1;
+    }
+    int32_t* h = o->h + (size_t)r * n;
+    int64_t twoE = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      int64_t acc = 0;
+      for (int32_t e = o->row_ptr[v]; e < o->row_ptr[v + 1]; ++e)
+        acc += (int64_t)o->J[e] * s[o->col[e]];
+      h[v] = (int32_t)acc;
+      twoE += (int64_t)s[v] * acc;
+    }
+    o->E[r] = -twoE / 2;
+    o->family[r] = r;
+  }
+  o->mstar = 0;
+  for (int32_t v = 0; v < n; ++v) o->best[v] = 1;
+  o->gs = o->g_rs = o->g_cl = 0;
+}
+
+/* Builds the internal graph from a validated CSR over input ids.  colour
+ * classes give the sweep order; internal id = rank in (class, input id). */
+static void build_graph(orc* o, const int32_t* row_ptr, const int32_t* col,
+                        const int32_t* Jin, int32_t dense) {
+  int32_t n = o->n, nnz = row_ptr[n];
+  o->nnz = nnz;
+  o->dense = dense;
+  int32_t* colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (dense) {
+    for (int32_t v = 0; v < n; ++v) colour[v] = v;
+    o->ncls = n;
+  } else {
+    o->ncls = orc_colour(n, row_ptr, col, colour);
+  }
+  o->class_ptr = (int32_t*)calloc((size_t)o->ncls + 1, sizeof(int32_t));
+  for (int32_t v = 0; v < n; ++v) o->class_ptr[colour[v] + 1]++;
+  for (int32_t k = 0; k < o->ncls; ++k) o->class_ptr[k + 1] += o->class_ptr[k];
+  int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)o->ncls);
+  for (int32_t k = 0; k < o->ncls; ++k) fill[k] = o->class_ptr[k];
+  for (int32_t v = 0; v < n; ++v) { /* ascending input id within a class */
+    int32_t iv = fill[colour[v]]++;
+    o->to_internal[v] = iv;
+    o->to_input[iv] = v;
+  }
+  free(fill);
+  free(colour);
+  o->row_ptr = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  o->col = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+  o->J = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+  o->row_ptr[0] = 0;
+  int64_t W = 0, X = 0;
+  for (int32_t iv = 0; iv < n; ++iv) {
+    int32_t v = o->to_input[iv];
+    int32_t base = o->row_ptr[iv];
+    int32_t deg = row_ptr[v + 1] - row_ptr[v];
+    int64_t absum = 0;
+    for (int32_t e = 0; e < deg; ++e) {
+      int32_t u = col[row_ptr[v] + e];
+      o->col[base + e] = o->to_internal[u];
+      o->J[base + e] = Jin[row_ptr[v] + e];
+      absum += llabs((long long)Jin[row_ptr[v] + e]);
+      if (u > v) W += -(int64_t)Jin[row_ptr[v] + e];
+    }
+    if (absum > X) X = absum;
+    o->row_ptr[iv + 1] = base + deg;
+  }
+  o->W = W;
+  o->X = X;
+}
+
+orc* orc_create_sparse(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                       const int32_t* w, int32_t objective, int32_t replicas,
+                       uint64_t seed, int32_t rule, int32_t shuffle_classes,
+                       char* err, int32_t errlen) {
+  if (replicas <= 0) { set_err(err, errlen, "replicas must be positive"); return NULL; }
+  if (!validate_csr(n, row_ptr, col, w, err, errlen)) return NULL;
+  int32_t nnz = row_ptr[n];
+  int32_t* Jin = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+  int64_t X = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    int64_t a = 0;
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      Jin[e] = (objective == ORC_OBJ_MAXCUT) ? -w[e] : w[e];
+      a += llabs((long long)w[e]);
+    }
+    if (a > X) X = a;
+  }
+  if (2 * X >= 2147483647LL) { free(Jin); set_err(err, errlen, "local field range exceeds int32"); return NULL; }
+  orc* o = alloc_orc(n, replicas);
+  o->seed = seed;
+  o->rule = rule;
+  o->shuffle = shuffle_classes;
+  build_graph(o, row_ptr, col, Jin, 0);
+  free(Jin);
+  init_population(o);
+  return o;
+}
+
+orc* orc_create_dense(int32_t n, const int8_t* J, int32_t objective,
+                      int32_t replicas, uint64_t seed, int32_t rule,
+                      char* err, int32_t errlen) {
+  if (n <= 0 || replicas <= 0) { set_err(err, errlen, "bad size"); return NULL; }
+  for (int32_t i = 0; i < n; ++i) {
+    if (J[(size_t)i * n + i] != 0) { set_err(err, errlen, "nonzero diagonal"); return NULL; }
+    for (int32_t j = 0; j < i; ++j)
+      if (J[(size_t)i * n + j] != J[(size_t)j * n + i]) { set_err(err, errlen, "not symmetric"); return NULL; }
+  }
+  int64_t nnz = 0;
+  for (size_t k = 0; k < (size_t)n * n; ++k) nnz += (J[k] != 0);
+  int32_t* rp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t* cl = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+  int32_t* jj = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+  int32_t p = 0;
+  rp[0] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t j = 0; j < n; ++j) {
+      int8_t v = J[(size_t)i * n + j];
+      if (v) { cl[p] = j; jj[p] = (objective == ORC_OBJ_MAXCUT) ? -(int32_t)v : (int32_t)v; ++p; }
+    }
+    rp[i + 1] = p;
+  }
+  orc* o = alloc_orc(n, replicas);
+  o->seed = seed;
+  o->rule = rule;
+  o->shuffle = 0;
+  build_graph(o, rp, cl, jj, 1);
+  free(rp); free(cl); free(jj);
+  init_population(o);
+  return o;
+}
+
+void orc_dense_random(int32_t n, uint64_t seed, int8_t* J) {
+  for (int32_t i = 0; i < n; ++i) {
+    J[(size_t)i * n + i] = 0;
+    for (int32_t j = i + 1; j < n; ++j) {
+      uint32_t out[4];
+      philox(seed, (uint32_t)i, (uint32_t)j, 0u, ORC_TAG_DENSE, out);
+      int8_t v = (out[0] & 1u) ? 1 : -1;
+      J[(size_t)i * n + j] = v;
+      J[(size_t)j * n + i] = v;
+    }
+  }
+}
+
+/* Max-3-Cut as an Ising problem: spins x_{i,a} (a = 0,1,2) one-hot encode
+ * the label of vertex i, plus one ancilla spin that carries the linear
+ * terms.  With weighted degree d_i and penalty A_i = floor(d_i/3) + 1,
+ * f = sum_i A_i (1 - sum_a x_ia)^2 + sum_{(i,j)} w_ij sum_a x_ia x_ja is
+ * minimised only by one-hot states, where it equals W - cut3.  Writing
+ * x = (1 + s)/2 and multiplying the linear terms by the ancilla gives
+ * J_{(i,a),anc} = -(2 A_i + d_i), J_{(i,a),(i,b)} = -2 A_i,
+ * J_{(i,a),(j,a)} = -w_ij, and H = 4 f - (4 sum A + 3 W) when s_anc = +1.
+ * Embedded input ids: (i,a) -> 3i + a, ancilla -> 3n. */
+orc* orc_create_max3cut(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                        const int32_t* w, int32_t replicas, uint64_t seed,
+                        int32_t rule, int32_t shuffle_classes,
+                        char* err, int32_t errlen) {
+  if (!validate_csr(n, row_ptr, col, w, err, errlen)) return NULL;
+  int32_t nnz = row_ptr[n];
+  for (int32_t e = 0; e < nnz; ++e)
+    if (w[e] <= 0) { set_err(err, errlen, "Max-3-Cut needs positive weights"); return NULL; }
+  int32_t N = 3 * n + 1;
+  int64_t* d = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) d[i] += w[e];
+  /* per embedded vertex (i,a): 2 same-vertex partners + deg(i) + ancilla */
+  int64_t enn = 0;
+  for (int32_t i = 0; i < n; ++i) enn += 3 * (3 + (int64_t)(row_ptr[i + 1] - row_ptr[i]));
+  enn += 3 * (int64_t)n; /* ancilla row */
+  int32_t* rp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N + 1));
+  int32_t* cl = (int32_t*)malloc(sizeof(int32_t) * (size_t)enn);
+  int32_t* jj = (int32_t*)malloc(sizeof(int32_t) * (size_t)enn);
+  int64_t p = 0;
+  int64_t X = 0;
+  rp[0] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t A = d[i] / 3 + 1;
+    for (int32_t a = 0; a < 3; ++a) {
+      int64_t absum = 0;
+      for (int32_t b = 0; b < 3; ++b)
+        if (b != a) { cl[p] = 3 * i + b; jj[p] = (int32_t)(-2 * A); absum += 2 * A; ++p; }
+      for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        cl[p] = 3 * col[e] + a; jj[p] = -w[e]; absum += w[e]; ++p;
+      }
+      cl[p] = 3 * n; jj[p] = (int32_t)(-(2 * A + d[i])); absum += 2 * A + d[i]; ++p;
+      if (absum > X) X = absum;
+      rp[3 * i + a + 1] = (int32_t)p;
+    }
+  }
+  int64_t absum = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t A = d[i] / 3 + 1;
+    for (int32_t a = 0; a < 3; ++a) { cl[p] = 3 * i + a; jj[p] = (int32_t)(-(2 * A + d[i])); absum += 2 * A + d[i]; ++p; }
+  }
+  if (absum > X) X = absum;
+  rp[N] = (int32_t)p;
+  free(d);
+  if (2 * X >= 2147483647LL) {
+    free(rp); free(cl); free(jj);
+    set_err(err, errlen, "local field range exceeds int32");
+    return NULL;
+  }
+  orc* o = alloc_orc(N, replicas);
+  o->seed = seed;
+  o->rule = rule;
+  o->shuffle = shuffle_classes;
+  build_graph(o, rp, cl, jj, 0);
+  free(rp); free(cl); free(jj);
+  o->m3_n = n;
+  o->m3_row_ptr = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  o->m3_col = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+  o->m3_w = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+  memcpy(o->m3_row_ptr, row_ptr, sizeof(int32_t) * ((size_t)n + 1));
+  memcpy(o->m3_col, col, sizeof(int32_t) * (size_t)nnz);
+  memcpy(o->m3_w, w, sizeof(int32_t) * (size_t)nnz);
+  init_population(o);
+  return o;
+}
+
+void orc_destroy(orc* o) {
+  if (!o) return;
+  free(o->row_ptr); free(o->col); free(o->J); free(o->class_ptr);
+  free(o->to_input); free(o->to_internal);
+  free(o->s); free(o->h); free(o->E); free(o->family); free(o->best);
+  free(o->m3_row_ptr); free(o->m3_col); free(o->m3_w);
+  free(o);
+}
+
+int32_t orc_n(const orc* o) { return o->n; }
+int32_t orc_replicas(const orc* o) { return o->R; }
+int32_t orc_num_classes(const orc* o) { return o->ncls; }
+int64_t orc_W(const orc* o) { return o->W; }
+int64_t orc_X(const orc* o) { return o->X; }
+void orc_internal_ids(const orc* o, int32_t* t) { memcpy(t, o->to_internal, sizeof(int32_t) * (size_t)o->n); }
+void orc_class_ptr(const orc* o, int32_t* c) { memcpy(c, o->class_ptr, sizeof(int32_t) * ((size_t)o->ncls + 1)); }
+void orc_counters(const orc* o, uint32_t* c) { c[0] = o->gs; c[1] = o->g_rs; c[2] = o->g_cl; }
+
+/* ------------------------------------------------------------------------ */
+/* Monte Carlo sweep (Eqs. 3-4; "all spins sequentially updated once in a   */
+/* randomized order").  Classes of the colouring hold mutually uncoupled     */
+/* spins, so the spins of a class can be visited in any order; the order of  */
+/* the classes is a fresh Fisher-Yates permutation each sweep.  Dense        */
+/* instances use the fixed order 0..n-1.                                     */
+/* ------------------------------------------------------------------------ */
+static void class_order(const orc* o, uint32_t gs, int32_t* order) {
+  for (int32_t k = 0; k < o->ncls; ++k) order[k] = k;
+  if (!o->shuffle) return;
+  for (int32_t i = o->ncls - 1; i >= 1; --i) {
+    uint32_t out[4];
+    philox(o->seed, (uint32_t)i, gs, 0u, ORC_TAG_ORDER, out);
+    int32_t j = (int32_t)(((uint64_t)out[0] * (uint64_t)(i + 1)) >> 32);
+    int32_t t = order[i]; order[i] = order[j]; order[j] = t;
+  }
+}
+
+static void flip_spin(orc* o, int32_t r, int32_t v) {
+  int8_t* s = o->s + (size_t)r * o->n;
+  int32_t* h = o->h + (size_t)r * o->n;
+  s[v] = (int8_t)-s[v];
+  for (int32_t e = o->row_ptr[v]; e < o->row_ptr[v + 1]; ++e)
+    h[o->col[e]] += 2 * o->J[e] * s[v];
+}
+
+void orc_sweep(orc* o, double beta, int32_t nsweeps) {
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)o->ncls);
+  for (int32_t sw = 0; sw < nsweeps; ++sw) {
+    class_order(o, o->gs, order);
+    for (int32_t ci = 0; ci < o->ncls; ++ci) {
+      int32_t c = order[ci];
+      for (int32_t v = o->class_ptr[c]; v < o->class_ptr[c + 1]; ++v) {
+        for (int32_t r = 0; r < o->R; ++r) {
+          int64_t x = (int64_t)o->s[(size_t)r * o->n + v] * o->h[(size_t)r * o->n + v];
+          uint32_t out[4];
+          philox(o->seed, (uint32_t)(v >> 2), o->gs, (uint32_t)r, ORC_TAG_SWEEP, out);
+          if (flip_decision(out[v & 3], beta, o->rule, x)) {
+            o->E[r] += 2 * x;
+            flip_spin(o, r, v);
+          }
+        }
+      }
+    }
+    o->gs++;
+  }
+  free(order);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Resampling (Eqs. 1-2).  Replica j receives on average                    */
+/* tau_j = e^{-Delta E_j} / Q copies with Q = (1/R) sum_j e^{-Delta E_j}, so */
+/* sum_j tau_j = R and the population size stays R.  Multinomial: R         */
+/* independent draws of a parent with probability proportional to its       */
+/* weight.  Weights are shifted by the extreme energy (exact in exponent    */
+/* arithmetic) and quantised to q_j = floor(w_j 2^48) so that the draw is   */
+/* an exact integer computation; children are ordered by parent.            */
+/* ------------------------------------------------------------------------ */
+double orc_resample(orc* o, double delta, int32_t* parents_out) {
+  int32_t R = o->R, n = o->n;
+  int64_t Eref = o->E[0];
+  for (int32_t r = 1; r < R; ++r) {
+    if (delta >= 0 ? (o->E[r] < Eref) : (o->E[r] > Eref)) Eref = o->E[r];
+  }
+  double* w = (double*)malloc(sizeof(double) * (size_t)R);
+  uint64_t* P = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)R);
+  double wsum = 0.0;
+  uint64_t Q = 0;
+  for (int32_t r = 0; r < R; ++r) {
+    double a = delta * (double)(o->E[r] - Eref);
+    w[r] = orc_pexp(-a);
+    wsum += w[r];
+    uint64_t q = (uint64_t)floor(w[r] * 281474976710656.0); /* 2^48 */
+    Q += q;
+    P[r] = Q;
+  }
+  double lnq = -delta * (double)Eref + log(wsum) - log((double)R);
+  int32_t* parent = (int32_t*)malloc(sizeof(int32_t) * (size_t)R);
+  for (int32_t k = 0; k < R; ++k) {
+    uint32_t out[4];
+    philox(o->seed, (uint32_t)(k >> 1), o->g_rs, 0u, ORC_TAG_RS, out);
+    uint64_t u = (k & 1) ? ((uint64_t)out[2] | ((uint64_t)out[3] << 32))
+                         : ((uint64_t)out[0] | ((uint64_t)out[1] << 32));
+    uint64_t y = (uint64_t)(((unsigned __int128)u * Q) >> 64);
+    int32_t j = 0;
+    while (P[j] <= y) ++j; /* least j with P_j > y */
+    parent[k] = j;
+  }
+  /* order children by parent (counting sort) */
+  int32_t* cnt = (int32_t*)calloc((size_t)R, sizeof(int32_t));
+  for (int32_t k = 0; k < R; ++k) cnt[parent[k]]++;
+  int32_t k = 0;
+  for (int32_t j = 0; j < R; ++j)
+    for (int32_t c = 0; c < cnt[j]; ++c) parent[k++] = j;
+  free(cnt);
+  int8_t* s2 = (int8_t*)malloc((size_t)R * n);
+  int32_t* h2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)R * n);
+  int64_t* E2 = (int64_t*)malloc(sizeof(int64_t) * (size_t)R);
+  int32_t* f2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)R);
+  for (int32_t c = 0; c < R; ++c) {
+    int32_t p = parent[c];
+    memcpy(s2 + (size_t)c * n, o->s + (size_t)p * n, (size_t)n);
+    memcpy(h2 + (size_t)c * n, o->h + (size_t)p * n, sizeof(int32_t) * (size_t)n);
+    E2[c] = o->E[p];
+    f2[c] = o->family[p];
+  }
+  free(o->s); free(o->h); free(o->E); free(o->family);
+  o->s = s2; o->h = h2; o->E = E2; o->family = f2;
+  if (parents_out) memcpy(parents_out, parent, sizeof(int32_t) * (size_t)R);
+  free(parent); free(w); free(P);
+  o->g_rs++;
+  return lnq;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Non-local cluster move (Sec. "Augmented PAMC", NCM; Algorithm 1).  For    */
+/* each of the n_top lowest-energy replicas: iso-sites are spins with local  */
+/* field exactly 0 (flipping one leaves H unchanged).  The iso-sites are     */
+/* randomly permuted; the first is selected and each later one is added if  */
+/* it has zero coupling to every selected site.  This is repeated            */
+/* mis_trials times and the largest set (earliest trial on ties) is flipped  */
+/* at once; the set is independent, so H does not change.                   */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint32_t key; int32_t v; } keyed;
+static int cmp_keyed(const void* a, const void* b) {
+  const keyed* x = (const keyed*)a;
+  const keyed* y = (const keyed*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->v < y->v ? -1 : (x->v > y->v);
+}
+typedef struct { int64_t E; int32_t r; } eslot;
+static int cmp_eslot(const void* a, const void* b) {
+  const eslot* x = (const eslot*)a;
+  const eslot* y = (const eslot*)b;
+  if (x->E != y->E) return x->E < y->E ? -1 : 1;
+  return x->r < y->r ? -1 : (x->r > y->r);
+}
+
+int32_t orc_cluster(orc* o, int32_t n_top, int32_t mis_trials, int32_t* chosen_sizes) {
+  int32_t R = o->R, n = o->n;
+  if (n_top > R) n_top = R;
+  if (n_top < 0) n_top = 0;
+  eslot* es = (eslot*)malloc(sizeof(eslot) * (size_t)R);
+  for (int32_t r = 0; r < R; ++r) { es[r].E = o->E[r]; es[r].r = r; }
+  qsort(es, (size_t)R, sizeof(eslot), cmp_eslot);
+  keyed* iso = (keyed*)malloc(sizeof(keyed) * (size_t)n);
+  int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* sel = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* best = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t total = 0;
+  for (int32_t i = 0; i < n_top; ++i) {
+    int32_t r = es[i].r;
+    int32_t* h = o->h + (size_t)r * n;
+    int32_t nbest = 0;
+    for (int32_t t = 0; t < mis_trials; ++t) {
+      int32_t m = 0;
+      for (int32_t v = 0; v < n; ++v) {
+        if (h[v] != 0) continue;
+        uint32_t out[4];
+        philox(o->seed, (uint32_t)v, o->g_cl, (uint32_t)r, (uint32_t)ORC_TAG_CL | ((uint32_t)t << 8), out);
+        iso[m].key = out[0];
+        iso[m].v = v;
+        ++m;
+      }
+      qsort(iso, (size_t)m, sizeof(keyed), cmp_keyed);
+      for (int32_t v = 0; v < n; ++v) mark[v] = 0;
+      int32_t ns = 0;
+      for (int32_t q = 0; q < m; ++q) {
+        int32_t v = iso[q].v;
+        int ok = 1;
+        for (int32_t e = o->row_ptr[v]; e < o->row_ptr[v + 1]; ++e)
+          if (mark[o->col[e]]) { ok = 0; break; }
+        if (ok) { mark[v] = 1; sel[ns++] = v; }
+      }
+      if (ns > nbest) { nbest = ns; memcpy(best, sel, sizeof(int32_t) * (size_t)ns); }
+    }
+    int64_t dE = 0;
+    for (int32_t q = 0; q < nbest; ++q) {
+      int32_t v = best[q];
+      dE += 2 * (int64_t)o->s[(size_t)r * n + v] * h[v];
+      flip_spin(o, r, v);
+    }
+    if (dE != 0) { fprintf(stderr, "oracle: cluster move changed the energy\n"); abort(); }
+    if (chosen_sizes) chosen_sizes[i] = nbest;
+    total += nbest;
+  }
+  free(es); free(iso); free(mark); free(sel); free(best);
+  o->g_cl++;
+  return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Best cut (Algorithm 1: M* <- max(M*, max Cut(P))).  Lowest slot on ties.  */
+/* ------------------------------------------------------------------------ */
+int64_t orc_update_best(orc* o) {
+  int32_t rbest = 0;
+  int64_t m = (o->W - o->E[0]) / 2;
+  for (int32_t r = 1; r < o->R; ++r) {
+    int64_t c = (o->W - o->E[r]) / 2;
+    if (c > m) { m = c; rbest = r; }
+  }
+  if (m > o->mstar) {
+    o->mstar = m;
+    memcpy(o->best, o->s + (size_t)rbest * o->n, (size_t)o->n);
+  }
+  return o->mstar;
+}
+
+void orc_best(const orc* o, int64_t* cut, int64_t* energy, int8_t* spins) {
+  if (cut) *cut = o->mstar;
+  if (energy) *energy = o->W - 2 * o->mstar;
+  if (spins)
+    for (int32_t v = 0; v < o->n; ++v) spins[v] = o->best[o->to_internal[v]];
+}
+
+void orc_get_state(const orc* o, int8_t* spins, int32_t* fields, int64_t* energies,
+                   int32_t* family) {
+  int32_t n = o->n;
+  for (int32_t r = 0; r < o->R; ++r) {
+    for (int32_t v = 0; v < n; ++v) {
+      int32_t iv = o->to_internal[v];
+      if (spins) spins[(size_t)r * n + v] = o->s[(size_t)r * n + iv];
+      if (fields) fields[(size_t)r * n + v] = o->h[(size_t)r * n + iv];
+    }
+    if (energies) energies[r] = o->E[r];
+    if (family) family[r] = o->family[r];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive temperature control (Algorithm 1 and Sec. "Augmented PAMC").     */
+/* After a step, with no cooldown and at least win_long recorded values:     */
+/*   strong stagnation (<= max_s distinct in the short window and <= max_l   */
+/*   in the long one): beta <- reheat*beta, Delta <- +dbeta, enable NCM;     */
+/*   mild stagnation (short window stalled, long window not): reverse the    */
+/*   beta update if beta > beta0;                                            */
+/*   otherwise keep cooling.  Then restart every z_rst steps or advance.     */
+/* Returns event bits (bit2 strong, bit3 mild, bit4 restart).               */
+/* ------------------------------------------------------------------------ */
+static int32_t distinct_tail(const int64_t* hist, int32_t len, int32_t w) {
+  int32_t d = 0;
+  for (int32_t i = len - w; i < len; ++i) {
+    int dup = 0;
+    for (int32_t j = len - w; j < i; ++j)
+      if (hist[j] == hist[i]) { dup = 1; break; }
+    if (!dup) ++d;
+  }
+  return d;
+}
+
+int32_t orc_controller_step(orc_ctrl* c, const orc_schedule* s, int64_t mstar) {
+  int32_t ev = 0;
+  /* record M* (the window never needs more than win_long values) */
+  if (c->hist_len == s->win_long) {
+    memmove(c->hist, c->hist + 1, sizeof(int64_t) * (size_t)(s->win_long - 1));
+    c->hist_len--;
+  }
+  c->hist[c->hist_len++] = mstar;
+  if (s->augmented && c->cooldown == 0 && c->hist_len >= s->win_long) {
+    int32_t ds = distinct_tail(c->hist, c->hist_len, s->win_short);
+    int32_t dl = distinct_tail(c->hist, c->hist_len, s->win_long);
+    if (ds <= s->max_distinct_short && dl <= s->max_distinct_long) {
+      c->beta = s->reheat * c->beta;
+      c->delta = s->dbeta;
+      c->enable = 1;
+      ev |= 4;
+    } else if (ds <= s->max_distinct_short) {
+      if (c->beta > s->beta0) {
+        c->delta = -s->dbeta;
+        ev |= 8;
+      } else if (s->literal_break) {
+        c->stop = 1;
+      } else {
+        c->delta = s->dbeta;
+      }
+    } else {
+      c->delta = s->dbeta;
+    }
+  }
+  if (s->z_rst > 0 && c->z >= s->z_rst) {
+    c->cycle++;
+    c->z = 1;
+    c->beta = s->beta0;
+    c->delta = s->dbeta;
+    c->enable = 0;
+    c->cooldown = 0;
+    c->hist_len = 0;
+    ev |= 16;
+  } else {
+    c->z++;
+    c->beta = c->beta + c->delta;
+    if (c->cooldown > 0) c->cooldown--;
+  }
+  return ev;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1 (augmented PAMC); with augmented = 0 it is conventional PAMC  */
+/* on the schedule beta0, beta0 + dbeta, ...; with resample = 0 it is        */
+/* independent chains (SA).                                                  */
+/* ------------------------------------------------------------------------ */
+void orc_anneal(orc* o, const orc_schedule* s, orc_result* res, orc_trace* tr) {
+  orc_ctrl c;
+  memset(&c, 0, sizeof c);
+  c.z = 1;
+  c.beta = s->beta0;
+  c.delta = s->dbeta;
+  memset(res, 0, sizeof *res);
+  res->step_reached = -1;
+  int32_t step;
+  for (step = 0; step < s->steps; ++step) {
+    if (s->stop_at_target && o->mstar >= s->target) break;
+    int32_t ev = 0;
+    double lnq = 0.0;
+    if (c.z > 1 && s->resample) {
+      lnq = orc_resample(o, c.delta, NULL);
+      res->sum_lnq += lnq;
+      ev |= 1;
+      if (s->augmented && c.enable && c.cooldown == 0) {
+        orc_cluster(o, s->n_top, s->mis_trials, NULL);
+        c.enable = 0;
+        c.cooldown = s->tau;
+        ev |= 2;
+        res->n_cluster_moves++;
+      }
+    }
+    double beta_used = c.beta;
+    orc_sweep(o, c.beta, s->sweeps);
+    int64_t m = orc_update_best(o);
+    if (res->step_reached < 0 && m >= s->target) res->step_reached = step;
+    ev |= orc_controller_step(&c, s, m);
+    if (ev & 4) res->n_reheats++;
+    if (ev & 8) res->n_reversals++;
+    if (ev & 16) res->n_restarts++;
+    if (tr) {
+      if (tr->mstar) tr->mstar[step] = m;
+      if (tr->beta) tr->beta[step] = beta_used;
+      if (tr->lnq) tr->lnq[step] = lnq;
+      if (tr->events) tr->events[step] = ev;
+    }
+    if (c.stop) { ++step; break; }
+  }
+  res->steps_run = step;
+  res->best_cut = o->mstar;
+  res->best_energy = o->W - 2 * o->mstar;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Max-3-Cut decode: undo the global-flip gauge with the ancilla, then the   */
+/* label of vertex i is the a with x_{i,a} = +1 (the lowest such a if more   */
+/* than one, 0 if none).                                                     */
+/* ------------------------------------------------------------------------ */
+int64_t orc_max3cut_value(const orc* o, const int32_t* labels) {
+  int64_t cut = 0;
+  for (int32_t i = 0; i < o->m3_n; ++i)
+    for (int32_t e = o->m3_row_ptr[i]; e < o->m3_row_ptr[i + 1]; ++e) {
+      int32_t j = o->m3_col[e];
+      if (j > i && labels[i] != labels[j]) cut += o->m3_w[e];
+    }
+  return cut;
+}
+
+int64_t orc_max3cut_decode(const orc* o, const int8_t* spins, int32_t* labels) {
+  int32_t n = o->m3_n;
+  int g = spins[3 * n] < 0 ? -1 : 1;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t lab = 0;
+    for (int32_t a = 2; a >= 0; --a)
+      if (g * spins[3 * i + a] > 0) lab = a;
+    labels[i] = lab;
+  }
+  return orc_max3cut_value(o, labels);
+}
+
+/* Mean normalised pairwise Hamming distance with d_H = min(d, 1 - d)
+ * (Supplement, Hamming distance). */
+double orc_mean_pair_distance(const orc* o) {
+  int32_t R = o->R, n = o->n;
+  if (R < 2) return 0.0;
+  double acc = 0.0;
+  for (int32_t a = 0; a < R; ++a)
+    for (int32_t b = a + 1; b < R; ++b) {
+      int32_t dd = 0;
+      for (int32_t v = 0; v < n; ++v) dd += o->s[(size_t)a * n + v] != o->s[(size_t)b * n + v];
+      double d = (double)dd / n;
+      acc += d < 1.0 - d ? d : 1.0 - d;
+    }
+  return acc / ((double)R * (R - 1) / 2.0);
+}

@@ -1,0 +1,146 @@
+/*
+ * pamc_oracle.h -- plain, slow, single-threaded CPU oracle for augmented
+ * Population Annealing Monte Carlo (PAMC).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists so that the GPU library can be
+ * checked against an obviously-correct implementation of the same method.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no code, header, table or constant generator with
+ * the GPU library: every routine here (Philox, the exponential, colouring,
+ * sweep, resampling, cluster move, controller, dense path, Max-3-Cut
+ * embedding) is written independently from the paper and from the published
+ * definitions it names.
+ *
+ * Paper: "Leveraging Population Dynamics to Steer Efficient Search in
+ * Large-Scale Combinatorial Optimization" (Khan, Redding, Shukla).
+ *
+ * Conventions fixed by the paper or, where it is silent, by the readings
+ * listed in the design notes:
+ *   - H(s) = -sum_{i<j} J_ij s_i s_j  (Introduction; each pair once).
+ *   - Max-Cut: J = -w, cut = (W - H)/2 with W = sum_{i<j} w_ij.
+ *   - local field h_k = sum_j J_kj s_j (Eq. 3); flipping s_k changes H by
+ *     2 s_k h_k.
+ *   - heat-bath update of Eq. 4 flips with probability 1/(1+e^{2 beta s h}).
+ *   - resampling weights of Eqs. 1-2, multinomial, population size kept at R.
+ *   - control loop of Algorithm 1 with the adaptive rule of Sec. "Augmented
+ *     PAMC" (windows 25/40, <=3 distinct / >5 distinct, factor 0.8).
+ */
+#ifndef PAMC_ORACLE_H
+#define PAMC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* RNG stream tags (fourth Philox counter word). */
+enum { ORC_TAG_INIT = 0, ORC_TAG_SWEEP = 1, ORC_TAG_RS = 2, ORC_TAG_CL = 3,
+       ORC_TAG_ORDER = 4, ORC_TAG_DENSE = 5 };
+
+enum { ORC_RULE_HEATBATH = 0, ORC_RULE_METROPOLIS = 1 };
+enum { ORC_OBJ_MAXCUT = 0, ORC_OBJ_ISING = 1 };
+
+typedef struct orc orc;
+
+typedef struct {
+  double beta0, dbeta;
+  int32_t steps, sweeps;
+  int32_t z_rst;          /* restart period (Algorithm 1); <=0 means never */
+  int32_t augmented;      /* 1: adaptive control + cluster moves */
+  int32_t resample;       /* 1: PAMC, 0: independent chains (SA) */
+  int32_t win_short, win_long, max_distinct_short, max_distinct_long;
+  double reheat;          /* 0.8 */
+  int32_t tau, n_top, mis_trials;
+  int64_t target;         /* target cut MC* */
+  int32_t stop_at_target; /* 1: loop "while M* < MC*" */
+  int32_t literal_break;  /* 1: end the run where Algorithm 1 prints "break" */
+} orc_schedule;
+
+typedef struct {
+  int64_t best_cut, best_energy;
+  int32_t steps_run, step_reached;
+  double sum_lnq;
+  int32_t n_cluster_moves, n_reheats, n_reversals, n_restarts;
+} orc_result;
+
+/* Optional per-step trace (arrays of length steps, may be NULL). */
+typedef struct {
+  int64_t* mstar;     /* M* after the step */
+  double* beta;       /* beta used for the sweeps of the step */
+  double* lnq;        /* ln Q of the step's resampling (0 if none) */
+  int32_t* events;    /* bit0 resampled, bit1 cluster move, bit2 strong, bit3 mild, bit4 restart */
+} orc_trace;
+
+/* ---- primitives exposed for pins ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_pexp(double x);
+uint32_t orc_threshold(double beta, int32_t rule, int64_t x);
+/* first-fit colouring in vertex order; colour[v] out; returns number of classes */
+int32_t orc_colour(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* colour);
+/* dense +-1 couplings from a counter-based hash of (seed, i, j) */
+void orc_dense_random(int32_t n, uint64_t seed, int8_t* J);
+
+/* ---- instances ---- */
+/* Sparse symmetric CSR (both directions stored, no self loops, no
+ * duplicates, no zero weights).  Returns NULL on invalid input (err filled). */
+orc* orc_create_sparse(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                       const int32_t* w, int32_t objective, int32_t replicas,
+                       uint64_t seed, int32_t rule, int32_t shuffle_classes,
+                       char* err, int32_t errlen);
+/* Dense int8 couplings J (n*n, row-major, symmetric, zero diagonal);
+ * sequential vertex order 0..n-1. */
+orc* orc_create_dense(int32_t n, const int8_t* J, int32_t objective,
+                      int32_t replicas, uint64_t seed, int32_t rule,
+                      char* err, int32_t errlen);
+/* Max-3-Cut through a one-hot Ising embedding with one ancilla spin. */
+orc* orc_create_max3cut(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                        const int32_t* w, int32_t replicas, uint64_t seed,
+                        int32_t rule, int32_t shuffle_classes,
+                        char* err, int32_t errlen);
+void orc_destroy(orc* o);
+
+/* Instance facts. */
+int32_t orc_n(const orc* o);
+int32_t orc_replicas(const orc* o);
+int32_t orc_num_classes(const orc* o);
+int64_t orc_W(const orc* o);
+int64_t orc_X(const orc* o);
+/* internal id of each input vertex (the sweep order key) */
+void orc_internal_ids(const orc* o, int32_t* to_internal);
+void orc_class_ptr(const orc* o, int32_t* class_ptr);
+
+/* ---- steps of the method ---- */
+void orc_sweep(orc* o, double beta, int32_t nsweeps);
+double orc_resample(orc* o, double delta, int32_t* parents /* R, may be NULL */);
+int32_t orc_cluster(orc* o, int32_t n_top, int32_t mis_trials,
+                    int32_t* chosen_sizes /* n_top, may be NULL */);
+int64_t orc_update_best(orc* o);
+void orc_best(const orc* o, int64_t* cut, int64_t* energy, int8_t* spins);
+void orc_get_state(const orc* o, int8_t* spins, int32_t* fields, int64_t* energies,
+                   int32_t* family);
+void orc_counters(const orc* o, uint32_t* c3 /* gs, g_rs, g_cl */);
+void orc_anneal(orc* o, const orc_schedule* s, orc_result* r, orc_trace* t);
+
+/* Max-3-Cut decode of a spin vector of the embedded instance (input order of
+ * the embedded vertices).  labels: n entries in {0,1,2}.  Returns the 3-cut. */
+int64_t orc_max3cut_decode(const orc* o, const int8_t* spins, int32_t* labels);
+/* 3-cut of a labelling of the original graph. */
+int64_t orc_max3cut_value(const orc* o, const int32_t* labels);
+
+/* Controller: one application of the adaptive rule + schedule advance to a
+ * state given explicitly (for table-driven tests). */
+typedef struct {
+  double beta, delta;
+  int32_t z, cycle, cooldown, enable, hist_len, stop;
+  int64_t hist[64];
+} orc_ctrl;
+int32_t orc_controller_step(orc_ctrl* c, const orc_schedule* s, int64_t mstar);
+
+/* Hamming-distance diagnostic: normalised pairwise distance with the
+ * global-flip symmetry folded in (Supplement, Hamming distance). */
+double orc_mean_pair_distance(const orc* o);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
