@@ -1,0 +1,214 @@
+/*
+ * pamc.h -- C ABI of the MI355X (gfx950) augmented Population Annealing Monte
+ * Carlo library.
+ *
+ * Method: "Leveraging Population Dynamics to Steer Efficient Search in
+ * Large-Scale Combinatorial Optimization" (Khan, Redding, Shukla).  A
+ * population of R replicas of the Ising Hamiltonian H(s) = -sum_{i<j} J_ij
+ * s_i s_j (Introduction) is swept with the single-spin rule of Eq. 4 on the
+ * local fields of Eq. 3, resampled with the Boltzmann weights of Eqs. 1-2,
+ * and steered by the stagnation-driven controller and the energy-preserving
+ * cluster moves of Algorithm 1 (Sec. "Augmented PAMC").
+ *
+ * Conventions
+ *  - Every call returns pamc_status; nothing throws or aborts across the ABI.
+ *    On failure pamc_last_error() (thread-local) describes the cause.
+ *  - Vertex ids at the ABI are the caller's ids (0..n-1).  Spin arrays are
+ *    int8 in {-1,+1}; populations are slot-major [R][n].
+ *  - Input arrays are copied; the caller keeps ownership.  The instance owns
+ *    its device memory (hipMalloc on cfg->device) until pamc_destroy_instance.
+ *  - One host thread at a time per instance; distinct instances may be used
+ *    concurrently.  Device work is enqueued on the instance's stream
+ *    (cfg->stream, or a stream the library creates).  pamc_sweep,
+ *    pamc_resample (log_q == NULL) and pamc_cluster_move (flipped == NULL)
+ *    are asynchronous; pamc_best, pamc_get_state, pamc_anneal and
+ *    pamc_synchronize wait for the stream.  An asynchronous device error is
+ *    reported by the next waiting call as PAMC_ERR_DEVICE.
+ *  - Randomness is a counter-based Philox4x32-10 stream keyed by cfg->seed.
+ *    Each instance keeps monotone counters of sweeps, resamplings and cluster
+ *    moves, so any sequence of calls is reproducible, and pamc_anneal is the
+ *    sequence of primitive calls Algorithm 1 describes.
+ */
+#ifndef PAMC_H
+#define PAMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pamc_instance pamc_instance;
+
+typedef enum {
+  PAMC_OK = 0,
+  PAMC_ERR_INVALID_ARG = 1,   /* malformed instance, bad size, NULL pointer */
+  PAMC_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+  PAMC_ERR_DEVICE = 3,        /* HIP runtime or kernel error */
+  PAMC_ERR_STATE = 4,         /* call not valid for this instance */
+  PAMC_ERR_UNSUPPORTED = 5    /* valid request outside the supported range */
+} pamc_status;
+
+/* Single-spin acceptance rule.  HEATBATH is Eq. 4 (flip probability
+ * 1/(1+e^{2 beta s h})); METROPOLIS accepts with min(1, e^{-2 beta s h}). */
+typedef enum { PAMC_RULE_HEATBATH = 0, PAMC_RULE_METROPOLIS = 1 } pamc_rule;
+
+/* MAXCUT: weights w are edge weights, J = -w, cut = (W - H)/2 with
+ * W = sum_{i<j} w_ij.  ISING: w are the couplings J themselves; the reported
+ * "cut" is (sum_{i<j} (-J_ij) - H)/2. */
+typedef enum { PAMC_OBJ_MAXCUT = 0, PAMC_OBJ_ISING = 1 } pamc_objective;
+
+/* Where caller arrays live. */
+typedef enum { PAMC_MEM_HOST = 0, PAMC_MEM_DEVICE = 1 } pamc_mem;
+
+/* pamc_config.flags */
+#define PAMC_FLAG_FIXED_CLASS_ORDER 1u /* do not shuffle colour classes per sweep */
+
+typedef struct {
+  uint64_t seed;     /* Philox key */
+  int32_t replicas;  /* R, a positive multiple of 64 */
+  int32_t rule;      /* pamc_rule */
+  int32_t device;    /* HIP device ordinal */
+  void* stream;      /* hipStream_t or NULL (library-owned stream) */
+  uint32_t flags;
+} pamc_config;
+
+/* Sparse instance from a symmetric CSR graph (both directions stored, no
+ * self loops, no duplicate or zero entries, symmetric weights).
+ * row_ptr[n+1], col[nnz], w[nnz] with nnz = row_ptr[n], int32.  Vertices are
+ * coloured first-fit in id order and swept class by class (spins of a class
+ * are mutually uncoupled, so this equals a sequential sweep in that order;
+ * Eq. 4 and "sequentially updated ... in a randomized order").  Fails with
+ * PAMC_ERR_INVALID_ARG if 2*max_v sum_j |J_vj| does not fit int32. */
+pamc_status pamc_create_instance_csr(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                     const int32_t* w, pamc_mem where, int32_t objective,
+                                     const pamc_config* cfg, pamc_instance** out);
+
+/* Dense instance from an int8 coupling matrix J[n][ld] (row-major,
+ * symmetric, zero diagonal).  Spins are visited in the fixed order 0..n-1;
+ * local fields are recomputed exactly with int8 x int8 -> int32 matrix-core
+ * products (Scalability section: fully connected instance). */
+pamc_status pamc_create_instance_dense_i8(int32_t n, const int8_t* J, int64_t ld, pamc_mem where,
+                                          int32_t objective, const pamc_config* cfg,
+                                          pamc_instance** out);
+
+/* Dense +-1 instance generated on the device: J_ij = J_ji = +1 if the low bit
+ * of word 0 of Philox(key = graph_seed, counter = (i, j, 0, 5)) is 1, else -1,
+ * for i < j; zero diagonal; objective ISING.  Used for instances too large to
+ * upload (n = 100,000 is 10^10 bytes). */
+pamc_status pamc_create_instance_dense_random(int32_t n, uint64_t graph_seed,
+                                              const pamc_config* cfg, pamc_instance** out);
+
+/* Max-3-Cut through an Ising embedding (the paper notes that K > 2 needs
+ * auxiliary spins and edges; Sec. "Max-3-Cut").  Vertex i of the input graph
+ * (positive weights) becomes three one-hot spins (i,a) with ids 3i+a, plus
+ * one ancilla with id 3n.  With weighted degree d_i and A_i = floor(d_i/3)+1:
+ * J_{(i,a),anc} = -(2A_i + d_i), J_{(i,a),(i,b)} = -2A_i,
+ * J_{(i,a),(j,a)} = -w_ij.  Ground states are one-hot and decode to maximum
+ * 3-cuts (see pamc_max3cut_decode). */
+pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                         const int32_t* w, const pamc_config* cfg,
+                                         pamc_instance** out);
+
+void pamc_destroy_instance(pamc_instance* inst);
+
+typedef struct {
+  int32_t n, replicas, num_classes, dense;
+  int64_t nnz, W, X; /* X = max_v sum_j |J_vj| */
+  int64_t device_bytes;
+} pamc_info;
+pamc_status pamc_get_info(const pamc_instance* inst, pamc_info* out);
+
+/* Algorithm 1 inputs.  controller: augmented = 1 turns on the adaptive
+ * temperature rule and cluster moves (Sec. "Augmented PAMC"); with 0 the run
+ * is conventional PAMC on beta0, beta0+dbeta, ...; resample = 0 gives
+ * independent chains (simulated annealing).  z_rst <= 0 never restarts. */
+typedef struct {
+  double beta0, dbeta;
+  int32_t steps, sweeps;
+  int32_t z_rst;
+  int32_t augmented;
+  int32_t resample;
+  int32_t win_short, win_long, max_distinct_short, max_distinct_long; /* 25, 40, 3, 5 */
+  double reheat;                                                      /* 0.8 */
+  int32_t tau, n_top, mis_trials;
+  int64_t target;         /* MC* */
+  int32_t stop_at_target; /* 1: loop "while M* < MC*" */
+  int32_t literal_break;  /* 1: end the run where Algorithm 1 prints "break" */
+} pamc_schedule;
+
+typedef struct {
+  int64_t best_cut, best_energy;
+  int32_t steps_run, step_reached; /* first step with M* >= target, or -1 */
+  double sum_lnq;                  /* sum of ln Q over resamplings */
+  int32_t n_cluster_moves, n_reheats, n_reversals, n_restarts;
+  double seconds_total, seconds_to_target; /* device clock; -1 if never */
+} pamc_result;
+
+/* Runs Algorithm 1 from the instance's current population and counters and
+ * waits for it.  The controller runs on the device; the host only enqueues. */
+pamc_status pamc_anneal(pamc_instance* inst, const pamc_schedule* sched, pamc_result* out);
+
+/* nsweeps Monte Carlo sweeps at inverse temperature beta (Eqs. 3-4). */
+pamc_status pamc_sweep(pamc_instance* inst, double beta, int32_t nsweeps);
+
+/* Boltzmann resampling with increment delta (Eqs. 1-2): R multinomial draws
+ * of parents with probability proportional to e^{-delta E_j}; children are
+ * ordered by parent.  log_q (may be NULL) receives ln Q of Eq. 2. */
+pamc_status pamc_resample(pamc_instance* inst, double delta, double* log_q);
+
+/* Non-local cluster move (Algorithm 1; Sec. "Augmented PAMC") on the n_top
+ * lowest-energy replicas, mis_trials randomized greedy independent sets of
+ * iso-sites each, the largest flipped.  flipped (may be NULL) receives the
+ * total number of spins flipped.  Requires n <= 26,000 (the independent-set
+ * search is held in local data share). */
+pamc_status pamc_cluster_move(pamc_instance* inst, int32_t n_top, int32_t mis_trials,
+                              int32_t* flipped);
+
+/* M* <- max(M*, max_r cut_r) with its configuration (Algorithm 1). */
+pamc_status pamc_update_best(pamc_instance* inst);
+
+/* Best cut M*, its energy and spins (n, may be NULL).  Waits. */
+pamc_status pamc_best(pamc_instance* inst, int64_t* cut, int64_t* energy, int8_t* spins);
+
+/* Population snapshot (each may be NULL): spins [R][n], fields [R][n],
+ * energies [R], family (ancestor slot at creation) [R].  Waits. */
+pamc_status pamc_get_state(pamc_instance* inst, int8_t* spins, int32_t* fields,
+                           int64_t* energies, int32_t* family);
+
+/* Per-step trace of the last pamc_anneal (arrays of length capacity, each may
+ * be NULL): M* after the step, beta used for the sweeps, ln Q, event bits
+ * (1 resampled, 2 cluster move, 4 strong reheat, 8 reversal, 16 restart) and
+ * seconds since the start of the run.  *steps receives the number recorded. */
+pamc_status pamc_get_trace(pamc_instance* inst, int32_t capacity, int64_t* mstar, double* beta,
+                           double* lnq, int32_t* events, double* seconds, int32_t* steps);
+
+/* Max-3-Cut decode (instances from pamc_create_instance_max3cut): undo the
+ * global-flip gauge with the ancilla; the label of vertex i is the a with
+ * spin (i,a) = +1, the lowest such a if several, 0 if none.  spins: the
+ * embedded configuration (3n+1, caller ids) or NULL for the best one.
+ * labels: n entries (may be NULL).  cut3: the 3-cut of the labelling. */
+pamc_status pamc_max3cut_decode(pamc_instance* inst, const int8_t* spins, int32_t* labels,
+                                int64_t* cut3);
+
+/* Mean normalised pairwise Hamming distance d_H = min(d, 1-d) over all
+ * replica pairs (Supplement, Hamming distance).  Waits. */
+pamc_status pamc_pair_distance(pamc_instance* inst, double* mean);
+
+/* Kernel timing: when enabled, the library brackets every launch of the
+ * sweep kernel with HIP events on the instance stream. */
+pamc_status pamc_profile_enable(pamc_instance* inst, int32_t on);
+/* Sum of event-measured sweep-kernel time (ms), number of launches, and the
+ * attempts (replica x vertex visits) they made since enabling.  Waits. */
+pamc_status pamc_profile_read(pamc_instance* inst, double* ms, int64_t* launches,
+                              int64_t* attempts, int64_t* flips);
+
+pamc_status pamc_synchronize(pamc_instance* inst);
+
+const char* pamc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAMC_H */

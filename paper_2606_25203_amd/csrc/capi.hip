@@ -1,0 +1,692 @@
+// capi.hip -- the C ABI (include/pamc.h): instance construction on the host
+// (validation, first-fit colouring, class-major relabelling, Max-3-Cut
+// embedding), device memory, and the drivers that enqueue the kernels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pamc.h"
+#include "instance.hpp"
+
+using pamc::Schedule;
+
+namespace {
+
+thread_local std::string g_err;
+
+pamc_status fail(pamc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+pamc_status dev_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? PAMC_ERR_OUT_OF_MEMORY : PAMC_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr, where)                 \
+  do {                                       \
+    hipError_t _e = (expr);                  \
+    if (_e != hipSuccess) return dev_fail(_e, where); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(pamc_instance* I, T** p, size_t count) {
+  const size_t bytes = std::max<size_t>(sizeof(T) * count, 16);
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e == hipSuccess) I->device_bytes += (int64_t)bytes;
+  return e;
+}
+
+void free_instance(pamc_instance* I) {
+  if (!I) return;
+  if (I->device >= 0) hipSetDevice(I->device);
+  if (I->stream) hipStreamSynchronize(I->stream);
+  void* ptrs[] = {I->g.row_ptr, I->g.col, I->g.J, I->g.class_ptr, I->pop.S[0], I->pop.S[1],
+                  I->pop.H[0], I->pop.H[1], I->pop.E[0], I->pop.E[1], I->pop.fam[0],
+                  I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order, I->rs_P,
+                  I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
+                  I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
+                  I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Ed[0], I->Ed[1],
+                  I->flip_ctr};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  if (I->pinned) hipHostFree(I->pinned);
+  for (hipEvent_t e : I->ev_pool) hipEventDestroy(e);
+  if (I->own_stream && I->stream) hipStreamDestroy(I->stream);
+  delete I;
+}
+
+// Structural checks of a symmetric CSR graph (both directions stored).
+pamc_status validate_csr(int32_t n, const int32_t* rp, const int32_t* col, const int32_t* w,
+                         bool positive_only) {
+  if (n <= 0) return fail(PAMC_ERR_INVALID_ARG, "n must be positive");
+  if (!rp || (!col && rp[n] > 0) || (!w && rp[n] > 0))
+    return fail(PAMC_ERR_INVALID_ARG, "NULL CSR array");
+  if (rp[0] != 0) return fail(PAMC_ERR_INVALID_ARG, "row_ptr[0] must be 0");
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v]) return fail(PAMC_ERR_INVALID_ARG, "row_ptr must be non-decreasing");
+  const int64_t nnz = rp[n];
+  std::vector<std::tuple<int32_t, int32_t, int32_t>> fwd, bwd;
+  fwd.reserve(nnz);
+  bwd.reserve(nnz);
+  for (int32_t v = 0; v < n; ++v) {
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+      const int32_t u = col[e];
+      if (u < 0 || u >= n) return fail(PAMC_ERR_INVALID_ARG, "column index out of range");
+      if (u == v) return fail(PAMC_ERR_INVALID_ARG, "self loop");
+      if (w[e] == 0) return fail(PAMC_ERR_INVALID_ARG, "zero weight entry");
+      if (positive_only && w[e] < 0) return fail(PAMC_ERR_INVALID_ARG, "weights must be positive");
+      fwd.emplace_back(v, u, w[e]);
+      bwd.emplace_back(u, v, w[e]);
+    }
+  }
+  std::sort(fwd.begin(), fwd.end());
+  for (size_t i = 1; i < fwd.size(); ++i)
+    if (std::get<0>(fwd[i]) == std::get<0>(fwd[i - 1]) && std::get<1>(fwd[i]) == std::get<1>(fwd[i - 1]))
+      return fail(PAMC_ERR_INVALID_ARG, "duplicate edge");
+  std::sort(bwd.begin(), bwd.end());
+  if (fwd != bwd) return fail(PAMC_ERR_INVALID_ARG, "graph is not symmetric");
+  return PAMC_OK;
+}
+
+pamc_status check_cfg(const pamc_config* cfg) {
+  if (!cfg) return fail(PAMC_ERR_INVALID_ARG, "NULL config");
+  if (cfg->replicas <= 0 || cfg->replicas % 64 != 0)
+    return fail(PAMC_ERR_INVALID_ARG, "replicas must be a positive multiple of 64");
+  if (cfg->replicas > 16384) return fail(PAMC_ERR_UNSUPPORTED, "replicas > 16384");
+  if (cfg->rule != 0 && cfg->rule != 1) return fail(PAMC_ERR_INVALID_ARG, "unknown rule");
+  return PAMC_OK;
+}
+
+pamc_status open_device(pamc_instance* I, const pamc_config* cfg) {
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count), "hipGetDeviceCount");
+  if (cfg->device < 0 || cfg->device >= count) return fail(PAMC_ERR_INVALID_ARG, "bad device");
+  I->device = cfg->device;
+  HIP_TRY(hipSetDevice(I->device), "hipSetDevice");
+  if (cfg->stream) {
+    I->stream = (hipStream_t)cfg->stream;
+  } else {
+    HIP_TRY(hipStreamCreateWithFlags(&I->stream, hipStreamNonBlocking), "hipStreamCreate");
+    I->own_stream = true;
+  }
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, I->device) == hipSuccess && khz > 0)
+    I->clock_hz = khz * 1000.0;
+  HIP_TRY(hipHostMalloc(&I->pinned, 4096, hipHostMallocDefault), "hipHostMalloc");
+  I->seed = cfg->seed;
+  I->R = cfg->replicas;
+  I->T = cfg->replicas / 64;
+  I->rule = cfg->rule;
+  I->flags = cfg->flags;
+  return PAMC_OK;
+}
+
+// Sparse graph (already validated, couplings J in caller ids) -> colouring,
+// relabelling and device buffers, then the initial population.
+pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const int32_t* col,
+                         const std::vector<int32_t>& Jin) {
+  I->n = n;
+  I->np = (n + 3) & ~3;
+  I->nq = I->np / 4;
+  I->nnz = rp[n];
+  // first-fit colouring in id order: least colour unused by earlier neighbours
+  std::vector<int32_t> colour(n, -1), stamp(n + 1, -1);
+  int32_t ncls = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+      if (col[e] < v) stamp[colour[col[e]]] = v;
+    int32_t c = 0;
+    while (stamp[c] == v) ++c;
+    colour[v] = c;
+    ncls = std::max(ncls, c + 1);
+  }
+  I->ncls = ncls;
+  I->class_ptr.assign(ncls + 1, 0);
+  for (int32_t v = 0; v < n; ++v) I->class_ptr[colour[v] + 1]++;
+  for (int32_t c = 0; c < ncls; ++c) I->class_ptr[c + 1] += I->class_ptr[c];
+  I->to_internal.resize(n);
+  I->to_input.resize(n);
+  {
+    std::vector<int32_t> next(I->class_ptr.begin(), I->class_ptr.end() - 1);
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t iv = next[colour[v]]++;
+      I->to_internal[v] = iv;
+      I->to_input[iv] = v;
+    }
+  }
+  I->max_class_quads = 0;
+  for (int32_t c = 0; c < ncls; ++c) {
+    const int32_t a = I->class_ptr[c], b = I->class_ptr[c + 1];
+    I->max_class_quads = std::max(I->max_class_quads, ((b + 3) >> 2) - (a >> 2));
+  }
+  // relabelled CSR
+  std::vector<int32_t> rp2(n + 1, 0), col2(std::max<int64_t>(I->nnz, 1)), J2(std::max<int64_t>(I->nnz, 1));
+  int64_t W = 0, X = 0;
+  for (int32_t iv = 0; iv < n; ++iv) {
+    const int32_t v = I->to_input[iv];
+    int32_t p = rp2[iv];
+    int64_t ab = 0;
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e, ++p) {
+      col2[p] = I->to_internal[col[e]];
+      J2[p] = Jin[e];
+      ab += std::llabs((long long)Jin[e]);
+      if (col[e] > v) W -= Jin[e];
+    }
+    rp2[iv + 1] = p;
+    X = std::max(X, ab);
+  }
+  if (2 * X >= INT32_MAX) return fail(PAMC_ERR_INVALID_ARG, "local field range exceeds int32");
+  I->W = W;
+  I->X = X;
+  const size_t nnz = (size_t)std::max<int64_t>(I->nnz, 1);
+  const size_t words = (size_t)I->T * I->nq * 64, hs = (size_t)I->T * I->np * 64;
+  HIP_TRY(dalloc(I, &I->g.row_ptr, n + 1), "alloc");
+  HIP_TRY(dalloc(I, &I->g.col, nnz), "alloc");
+  HIP_TRY(dalloc(I, &I->g.J, nnz), "alloc");
+  HIP_TRY(dalloc(I, &I->g.class_ptr, ncls + 1), "alloc");
+  for (int b = 0; b < 2; ++b) {
+    HIP_TRY(dalloc(I, &I->pop.S[b], words), "alloc population");
+    HIP_TRY(dalloc(I, &I->pop.H[b], hs), "alloc population");
+    HIP_TRY(dalloc(I, &I->pop.E[b], I->R), "alloc population");
+    HIP_TRY(dalloc(I, &I->pop.fam[b], I->R), "alloc population");
+  }
+  HIP_TRY(dalloc(I, &I->best, I->np), "alloc");
+  HIP_TRY(dalloc(I, &I->to_internal_dev, n), "alloc");
+  HIP_TRY(dalloc(I, &I->st, 1), "alloc");
+  HIP_TRY(dalloc(I, &I->thr, 2 * X + 1), "alloc");
+  I->order_cap = 64;
+  HIP_TRY(dalloc(I, &I->order, (size_t)I->order_cap * ncls), "alloc");
+  HIP_TRY(dalloc(I, &I->rs_P, I->R), "alloc");
+  HIP_TRY(dalloc(I, &I->rs_parent, I->R), "alloc");
+  HIP_TRY(dalloc(I, &I->flip_ctr, 512), "alloc");
+  HIP_TRY(hipMemsetAsync(I->flip_ctr, 0, sizeof(int64_t) * 512, I->stream), "memset");
+  HIP_TRY(hipMemsetAsync(I->st, 0, sizeof(pamc::RunState), I->stream), "memset");
+  HIP_TRY(hipMemsetAsync(I->pop.H[0], 0, sizeof(int32_t) * hs, I->stream), "memset");
+  HIP_TRY(hipMemsetAsync(I->pop.H[1], 0, sizeof(int32_t) * hs, I->stream), "memset");
+  HIP_TRY(hipMemcpyAsync(I->g.row_ptr, rp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(hipMemcpyAsync(I->g.col, col2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(hipMemcpyAsync(I->g.J, J2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(hipMemcpyAsync(I->g.class_ptr, I->class_ptr.data(), sizeof(int32_t) * (ncls + 1), hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(hipMemcpyAsync(I->to_internal_dev, I->to_internal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(pamc::prepare_cluster_lds(), "hipFuncSetAttribute");
+  HIP_TRY(pamc::launch_init_sparse(I), "init kernels");
+  HIP_TRY(hipStreamSynchronize(I->stream), "init");
+  return PAMC_OK;
+}
+
+Schedule to_sched(const pamc_schedule* s) {
+  Schedule d;
+  d.beta0 = s->beta0;
+  d.dbeta = s->dbeta;
+  d.reheat = s->reheat;
+  d.target = s->target;
+  d.steps = s->steps;
+  d.sweeps = s->sweeps;
+  d.z_rst = s->z_rst;
+  d.augmented = s->augmented;
+  d.resample = s->resample;
+  d.win_short = s->win_short;
+  d.win_long = s->win_long;
+  d.max_ds = s->max_distinct_short;
+  d.max_dl = s->max_distinct_long;
+  d.tau = s->tau;
+  d.n_top = s->n_top;
+  d.mis_trials = s->mis_trials;
+  d.stop_at_target = s->stop_at_target;
+  d.literal_break = s->literal_break;
+  return d;
+}
+
+pamc_status ensure_cluster_scratch(pamc_instance* I, int32_t n_top, int32_t trials) {
+  n_top = std::min(n_top, I->R);
+  if (n_top <= 0 || trials <= 0) return PAMC_OK;
+  if (I->n > pamc::cluster_max_n())
+    return fail(PAMC_ERR_UNSUPPORTED, "cluster moves need n <= 26000");
+  if (trials > 64) return fail(PAMC_ERR_UNSUPPORTED, "mis_trials > 64");
+  if (n_top <= I->cl_cap_top && trials <= I->cl_cap_trials) return PAMC_OK;
+  HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  if (I->cl_targets) hipFree(I->cl_targets);
+  if (I->cl_sel) hipFree(I->cl_sel);
+  if (I->cl_sizes) hipFree(I->cl_sizes);
+  I->cl_targets = nullptr;
+  I->cl_sel = nullptr;
+  I->cl_sizes = nullptr;
+  I->cl_cap_top = std::max(n_top, I->cl_cap_top);
+  I->cl_cap_trials = std::max(trials, I->cl_cap_trials);
+  HIP_TRY(dalloc(I, &I->cl_targets, I->cl_cap_top), "alloc cluster");
+  HIP_TRY(dalloc(I, &I->cl_sel, (size_t)I->cl_cap_top * I->cl_cap_trials * I->np), "alloc cluster");
+  HIP_TRY(dalloc(I, &I->cl_sizes, (size_t)I->cl_cap_top * I->cl_cap_trials), "alloc cluster");
+  return PAMC_OK;
+}
+
+pamc_status ensure_trace(pamc_instance* I, int32_t steps) {
+  if (steps <= I->tr_cap) return PAMC_OK;
+  HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  void* olds[] = {I->tr_mstar, I->tr_beta, I->tr_lnq, I->tr_events, I->tr_time};
+  for (void* p : olds)
+    if (p) hipFree(p);
+  I->tr_cap = steps;
+  HIP_TRY(dalloc(I, &I->tr_mstar, steps), "alloc trace");
+  HIP_TRY(dalloc(I, &I->tr_beta, steps), "alloc trace");
+  HIP_TRY(dalloc(I, &I->tr_lnq, steps), "alloc trace");
+  HIP_TRY(dalloc(I, &I->tr_events, steps), "alloc trace");
+  HIP_TRY(dalloc(I, &I->tr_time, steps), "alloc trace");
+  return PAMC_OK;
+}
+
+pamc_status ensure_order(pamc_instance* I, int32_t sweeps) {
+  if (sweeps <= I->order_cap) return PAMC_OK;
+  HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  hipFree(I->order);
+  I->order = nullptr;
+  I->order_cap = sweeps;
+  HIP_TRY(dalloc(I, &I->order, (size_t)sweeps * I->ncls), "alloc order");
+  return PAMC_OK;
+}
+
+pamc_status read_state(pamc_instance* I, pamc::RunState* out) {
+  HIP_TRY(hipStreamSynchronize(I->stream), "kernel execution");
+  HIP_TRY(hipMemcpy(out, I->st, sizeof(pamc::RunState), hipMemcpyDeviceToHost), "readback");
+  return PAMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pamc_last_error(void) { return g_err.c_str(); }
+
+pamc_status pamc_create_instance_csr(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                     const int32_t* w, pamc_mem where, int32_t objective,
+                                     const pamc_config* cfg, pamc_instance** out) {
+  if (!out) return fail(PAMC_ERR_INVALID_ARG, "NULL out");
+  *out = nullptr;
+  pamc_status st = check_cfg(cfg);
+  if (st) return st;
+  if (objective != PAMC_OBJ_MAXCUT && objective != PAMC_OBJ_ISING)
+    return fail(PAMC_ERR_INVALID_ARG, "unknown objective");
+  if (n <= 0 || !row_ptr) return fail(PAMC_ERR_INVALID_ARG, "n must be positive");
+  std::vector<int32_t> hrp, hcol, hw;
+  const int32_t *rp = row_ptr, *cl = col, *ww = w;
+  if (where == PAMC_MEM_DEVICE) {
+    hrp.resize(n + 1);
+    if (hipMemcpy(hrp.data(), row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(PAMC_ERR_INVALID_ARG, "cannot read device row_ptr");
+    const int32_t nnz = hrp[n];
+    if (nnz < 0) return fail(PAMC_ERR_INVALID_ARG, "negative nnz");
+    hcol.resize(std::max(nnz, 1));
+    hw.resize(std::max(nnz, 1));
+    if (nnz && (hipMemcpy(hcol.data(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(hw.data(), w, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost) != hipSuccess))
+      return fail(PAMC_ERR_INVALID_ARG, "cannot read device CSR");
+    rp = hrp.data();
+    cl = hcol.data();
+    ww = hw.data();
+  } else if (where != PAMC_MEM_HOST) {
+    return fail(PAMC_ERR_INVALID_ARG, "bad memory kind");
+  }
+  st = validate_csr(n, rp, cl, ww, false);
+  if (st) return st;
+  std::vector<int32_t> J(std::max(rp[n], 1));
+  for (int32_t e = 0; e < rp[n]; ++e) J[e] = objective == PAMC_OBJ_MAXCUT ? -ww[e] : ww[e];
+  pamc_instance* I = new (std::nothrow) pamc_instance();
+  if (!I) return fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
+  st = open_device(I, cfg);
+  if (!st) st = build_sparse(I, n, rp, cl, J);
+  if (st) {
+    free_instance(I);
+    return st;
+  }
+  *out = I;
+  return PAMC_OK;
+}
+
+pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                         const int32_t* w, const pamc_config* cfg,
+                                         pamc_instance** out) {
+  if (!out) return fail(PAMC_ERR_INVALID_ARG, "NULL out");
+  *out = nullptr;
+  pamc_status st = check_cfg(cfg);
+  if (st) return st;
+  st = validate_csr(n, row_ptr, col, w, true);
+  if (st) return st;
+  if ((int64_t)3 * n + 1 > INT32_MAX / 4) return fail(PAMC_ERR_UNSUPPORTED, "graph too large");
+  // one-hot embedding with an ancilla (see pamc.h)
+  const int32_t N = 3 * n + 1, anc = 3 * n;
+  std::vector<int64_t> deg(n, 0), pen(n, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) deg[i] += w[e];
+    pen[i] = deg[i] / 3 + 1;
+  }
+  std::vector<std::vector<std::pair<int32_t, int64_t>>> adj(N);
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t a = 0; a < 3; ++a) {
+      const int32_t u = 3 * i + a;
+      for (int32_t b = 0; b < 3; ++b)
+        if (b != a) adj[u].push_back({3 * i + b, -2 * pen[i]});
+      for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) adj[u].push_back({3 * col[e] + a, -(int64_t)w[e]});
+      adj[u].push_back({anc, -(2 * pen[i] + deg[i])});
+      adj[anc].push_back({u, -(2 * pen[i] + deg[i])});
+    }
+  }
+  std::vector<int32_t> rp(N + 1, 0), cl, J;
+  for (int32_t u = 0; u < N; ++u) {
+    std::sort(adj[u].begin(), adj[u].end());
+    int64_t ab = 0;
+    for (auto& p : adj[u]) {
+      ab += std::llabs(p.second);
+      cl.push_back(p.first);
+      J.push_back((int32_t)p.second);
+    }
+    if (2 * ab >= INT32_MAX) return fail(PAMC_ERR_INVALID_ARG, "local field range exceeds int32");
+    rp[u + 1] = (int32_t)cl.size();
+  }
+  pamc_instance* I = new (std::nothrow) pamc_instance();
+  if (!I) return fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
+  st = open_device(I, cfg);
+  if (!st) st = build_sparse(I, N, rp.data(), cl.data(), J);
+  if (!st) {
+    I->m3_n = n;
+    const int32_t nnz = row_ptr[n];
+    if (dalloc(I, &I->m3_row_ptr, n + 1) || dalloc(I, &I->m3_col, std::max(nnz, 1)) ||
+        dalloc(I, &I->m3_w, std::max(nnz, 1)) || dalloc(I, &I->m3_labels, n) || dalloc(I, &I->m3_cut, 1) ||
+        hipMemcpy(I->m3_row_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice) ||
+        (nnz && hipMemcpy(I->m3_col, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice)) ||
+        (nnz && hipMemcpy(I->m3_w, w, sizeof(int32_t) * nnz, hipMemcpyHostToDevice)))
+      st = fail(PAMC_ERR_OUT_OF_MEMORY, "Max-3-Cut buffers");
+  }
+  if (st) {
+    free_instance(I);
+    return st;
+  }
+  *out = I;
+  return PAMC_OK;
+}
+
+void pamc_destroy_instance(pamc_instance* inst) { free_instance(inst); }
+
+pamc_status pamc_get_info(const pamc_instance* I, pamc_info* out) {
+  if (!I || !out) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  out->n = I->n;
+  out->replicas = I->R;
+  out->num_classes = I->ncls;
+  out->dense = I->dense;
+  out->nnz = I->nnz;
+  out->W = I->W;
+  out->X = I->X;
+  out->device_bytes = I->device_bytes;
+  return PAMC_OK;
+}
+
+pamc_status pamc_sweep(pamc_instance* I, double beta, int32_t nsweeps) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  if (nsweeps < 0 || !std::isfinite(beta)) return fail(PAMC_ERR_INVALID_ARG, "bad sweep arguments");
+  if (nsweeps == 0) return PAMC_OK;
+  hipSetDevice(I->device);
+  if (I->dense) {
+    HIP_TRY(pamc::launch_dense_prim_sweep(I, beta, nsweeps), "dense sweep");
+    return PAMC_OK;
+  }
+  HIP_TRY(pamc::launch_prim_sweep(I, beta, nsweeps), "sweep");
+  return PAMC_OK;
+}
+
+pamc_status pamc_resample(pamc_instance* I, double delta, double* log_q) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  if (!std::isfinite(delta)) return fail(PAMC_ERR_INVALID_ARG, "delta must be finite");
+  hipSetDevice(I->device);
+  if (I->dense) {
+    HIP_TRY(pamc::launch_dense_prim_resample(I, delta), "dense resample");
+  } else {
+    HIP_TRY(pamc::launch_prim_resample(I, delta), "resample");
+  }
+  if (log_q) {
+    pamc::RunState s;
+    pamc_status r = read_state(I, &s);
+    if (r) return r;
+    *log_q = s.last_lnq;
+  }
+  return PAMC_OK;
+}
+
+pamc_status pamc_cluster_move(pamc_instance* I, int32_t n_top, int32_t mis_trials, int32_t* flipped) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  if (n_top < 0 || mis_trials < 0) return fail(PAMC_ERR_INVALID_ARG, "negative argument");
+  if (I->dense) return fail(PAMC_ERR_UNSUPPORTED, "cluster moves on dense instances");
+  hipSetDevice(I->device);
+  pamc_status st = ensure_cluster_scratch(I, n_top, mis_trials);
+  if (st) return st;
+  int64_t* ctr = I->flip_ctr + 256;
+  HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(int64_t), I->stream), "memset");
+  HIP_TRY(pamc::launch_prim_cluster(I, n_top, mis_trials), "cluster move");
+  if (flipped) {
+    int64_t f = 0;
+    HIP_TRY(hipStreamSynchronize(I->stream), "cluster move");
+    HIP_TRY(hipMemcpy(&f, ctr, sizeof(int64_t), hipMemcpyDeviceToHost), "readback");
+    *flipped = (int32_t)f;
+  }
+  return PAMC_OK;
+}
+
+pamc_status pamc_update_best(pamc_instance* I) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  hipSetDevice(I->device);
+  if (I->dense) {
+    HIP_TRY(pamc::launch_dense_prim_update_best(I), "best");
+  } else {
+    HIP_TRY(pamc::launch_prim_update_best(I), "best");
+  }
+  return PAMC_OK;
+}
+
+pamc_status pamc_best(pamc_instance* I, int64_t* cut, int64_t* energy, int8_t* spins) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  hipSetDevice(I->device);
+  pamc::RunState s;
+  pamc_status r = read_state(I, &s);
+  if (r) return r;
+  if (cut) *cut = s.mstar;
+  if (energy) *energy = I->W - 2 * s.mstar;
+  if (spins) {
+    std::vector<int8_t> b(I->np);
+    HIP_TRY(hipMemcpy(b.data(), I->best, I->np, hipMemcpyDeviceToHost), "readback");
+    for (int32_t v = 0; v < I->n; ++v) spins[v] = b[I->dense ? v : I->to_internal[v]];
+  }
+  return PAMC_OK;
+}
+
+pamc_status pamc_get_state(pamc_instance* I, int8_t* spins, int32_t* fields, int64_t* energies,
+                           int32_t* family) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  if (I->dense) return fail(PAMC_ERR_UNSUPPORTED, "use the dense state reader");
+  hipSetDevice(I->device);
+  pamc::RunState s;
+  pamc_status r = read_state(I, &s);
+  if (r) return r;
+  const int b = s.cur;
+  const int n = I->n, R = I->R;
+  if (spins) {
+    std::vector<uint32_t> S((size_t)I->T * I->nq * 64);
+    HIP_TRY(hipMemcpy(S.data(), I->pop.S[b], S.size() * 4, hipMemcpyDeviceToHost), "readback");
+    for (int32_t rr = 0; rr < R; ++rr)
+      for (int32_t v = 0; v < n; ++v) {
+        const int32_t iv = I->to_internal[v];
+        const uint32_t w = S[((size_t)(rr >> 6) * I->nq + (iv >> 2)) * 64 + (rr & 63)];
+        spins[(size_t)rr * n + v] = (int8_t)(w >> (8 * (iv & 3)));
+      }
+  }
+  if (fields) {
+    std::vector<int32_t> H((size_t)I->T * I->np * 64);
+    HIP_TRY(hipMemcpy(H.data(), I->pop.H[b], H.size() * 4, hipMemcpyDeviceToHost), "readback");
+    for (int32_t rr = 0; rr < R; ++rr)
+      for (int32_t v = 0; v < n; ++v)
+        fields[(size_t)rr * n + v] = H[((size_t)(rr >> 6) * I->np + I->to_internal[v]) * 64 + (rr & 63)];
+  }
+  if (energies) HIP_TRY(hipMemcpy(energies, I->pop.E[b], sizeof(int64_t) * R, hipMemcpyDeviceToHost), "readback");
+  if (family) HIP_TRY(hipMemcpy(family, I->pop.fam[b], sizeof(int32_t) * R, hipMemcpyDeviceToHost), "readback");
+  return PAMC_OK;
+}
+
+pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_result* out) {
+  if (!I || !sched || !out) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  if (sched->steps < 0 || sched->sweeps < 0 || !std::isfinite(sched->beta0) || !std::isfinite(sched->dbeta))
+    return fail(PAMC_ERR_INVALID_ARG, "bad schedule");
+  if (sched->augmented &&
+      (sched->win_long > pamc::kHistCap || sched->win_short > sched->win_long || sched->win_short <= 0))
+    return fail(PAMC_ERR_INVALID_ARG, "history windows must satisfy 0 < short <= long <= 64");
+  hipSetDevice(I->device);
+  Schedule s = to_sched(sched);
+  if (!s.augmented) {
+    s.win_long = std::min(std::max(s.win_long, 1), pamc::kHistCap);
+  }
+  pamc_status st = ensure_trace(I, std::max(s.steps, 1));
+  if (!st) st = ensure_order(I, std::max(s.sweeps, 1));
+  if (!st && s.augmented && s.resample) st = ensure_cluster_scratch(I, s.n_top, s.mis_trials);
+  if (st) return st;
+  HIP_TRY(pamc::launch_anneal_setup(I, s), "anneal setup");
+  for (int32_t step = 0; step < s.steps; ++step) {
+    if (I->dense) {
+      HIP_TRY(pamc::launch_dense_step(I, s, step), "dense step");
+    } else {
+      HIP_TRY(pamc::launch_step(I, s, step), "step");
+    }
+    if (s.stop_at_target && (step % 16) == 15) {
+      HIP_TRY(hipMemcpyAsync(I->pinned, &I->st->stopped, sizeof(int32_t), hipMemcpyDeviceToHost, I->stream), "poll");
+      HIP_TRY(hipStreamSynchronize(I->stream), "poll");
+      if (*(volatile int32_t*)I->pinned) break;
+    }
+  }
+  pamc::RunState r;
+  st = read_state(I, &r);
+  if (st) return st;
+  memset(out, 0, sizeof *out);
+  out->best_cut = r.mstar;
+  out->best_energy = I->W - 2 * r.mstar;
+  out->steps_run = r.steps_run;
+  out->step_reached = r.step_reached;
+  out->sum_lnq = r.sum_lnq;
+  out->n_cluster_moves = r.n_cluster_moves;
+  out->n_reheats = r.n_reheats;
+  out->n_reversals = r.n_reversals;
+  out->n_restarts = r.n_restarts;
+  out->seconds_total = 0.0;
+  if (r.steps_run > 0) {
+    uint64_t t_last = 0;
+    HIP_TRY(hipMemcpy(&t_last, I->tr_time + (r.steps_run - 1), sizeof(uint64_t), hipMemcpyDeviceToHost), "readback");
+    out->seconds_total = (double)(t_last - r.t_start) / I->clock_hz;
+  }
+  out->seconds_to_target = r.step_reached >= 0 ? (double)(r.t_reached - r.t_start) / I->clock_hz : -1.0;
+  return PAMC_OK;
+}
+
+pamc_status pamc_get_trace(pamc_instance* I, int32_t capacity, int64_t* mstar, double* beta, double* lnq,
+                           int32_t* events, double* seconds, int32_t* steps) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  hipSetDevice(I->device);
+  pamc::RunState r;
+  pamc_status st = read_state(I, &r);
+  if (st) return st;
+  const int32_t k = std::min(std::min(capacity, r.steps_run), I->tr_cap);
+  if (steps) *steps = k;
+  if (k <= 0) return PAMC_OK;
+  if (mstar) HIP_TRY(hipMemcpy(mstar, I->tr_mstar, sizeof(int64_t) * k, hipMemcpyDeviceToHost), "readback");
+  if (beta) HIP_TRY(hipMemcpy(beta, I->tr_beta, sizeof(double) * k, hipMemcpyDeviceToHost), "readback");
+  if (lnq) HIP_TRY(hipMemcpy(lnq, I->tr_lnq, sizeof(double) * k, hipMemcpyDeviceToHost), "readback");
+  if (events) HIP_TRY(hipMemcpy(events, I->tr_events, sizeof(int32_t) * k, hipMemcpyDeviceToHost), "readback");
+  if (seconds) {
+    std::vector<uint64_t> t(k);
+    HIP_TRY(hipMemcpy(t.data(), I->tr_time, sizeof(uint64_t) * k, hipMemcpyDeviceToHost), "readback");
+    for (int32_t i = 0; i < k; ++i) seconds[i] = (double)(t[i] - r.t_start) / I->clock_hz;
+  }
+  return PAMC_OK;
+}
+
+pamc_status pamc_max3cut_decode(pamc_instance* I, const int8_t* spins, int32_t* labels, int64_t* cut3) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  if (I->m3_n <= 0) return fail(PAMC_ERR_STATE, "not a Max-3-Cut instance");
+  hipSetDevice(I->device);
+  int8_t* src = I->best;
+  int8_t* tmp = nullptr;
+  if (spins) {
+    std::vector<int8_t> internal(I->np, 1);
+    for (int32_t v = 0; v < I->n; ++v) internal[I->to_internal[v]] = spins[v];
+    HIP_TRY(hipMalloc((void**)&tmp, I->np), "alloc");
+    HIP_TRY(hipMemcpyAsync(tmp, internal.data(), I->np, hipMemcpyHostToDevice, I->stream), "upload");
+    src = tmp;
+  }
+  hipError_t e = pamc::launch_m3_decode(I, src);
+  if (e == hipSuccess) e = hipStreamSynchronize(I->stream);
+  if (e == hipSuccess && labels) e = hipMemcpy(labels, I->m3_labels, sizeof(int32_t) * I->m3_n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && cut3) e = hipMemcpy(cut3, I->m3_cut, sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (tmp) hipFree(tmp);
+  if (e != hipSuccess) return dev_fail(e, "max3cut decode");
+  return PAMC_OK;
+}
+
+pamc_status pamc_pair_distance(pamc_instance* I, double* mean) {
+  if (!I || !mean) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  if (I->dense) return fail(PAMC_ERR_UNSUPPORTED, "pair distance on dense instances");
+  hipSetDevice(I->device);
+  double* d = (double*)(I->flip_ctr + 300);
+  HIP_TRY(pamc::launch_pair_distance(I, d), "pair distance");
+  double v = 0.0;
+  HIP_TRY(hipStreamSynchronize(I->stream), "pair distance");
+  HIP_TRY(hipMemcpy(&v, d, sizeof(double), hipMemcpyDeviceToHost), "readback");
+  *mean = I->R > 1 ? v / ((double)I->R * (I->R - 1) / 2.0) : 0.0;
+  return PAMC_OK;
+}
+
+pamc_status pamc_profile_enable(pamc_instance* I, int32_t on) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  hipSetDevice(I->device);
+  HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  I->prof = on != 0;
+  I->ev_used = 0;
+  I->prof_ms = 0.0;
+  I->prof_launches = 0;
+  I->prof_attempts = 0;
+  HIP_TRY(hipMemset(I->flip_ctr, 0, sizeof(int64_t) * 256), "memset");
+  return PAMC_OK;
+}
+
+pamc_status pamc_profile_read(pamc_instance* I, double* ms, int64_t* launches, int64_t* attempts,
+                              int64_t* flips) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  hipSetDevice(I->device);
+  HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  for (size_t i = 0; i + 1 < I->ev_used; i += 2) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, I->ev_pool[i], I->ev_pool[i + 1]), "hipEventElapsedTime");
+    I->prof_ms += t;
+  }
+  I->ev_used = 0;
+  if (ms) *ms = I->prof_ms;
+  if (launches) *launches = I->prof_launches;
+  if (attempts) *attempts = I->prof_attempts;
+  if (flips) {
+    std::vector<int64_t> c(256);
+    HIP_TRY(hipMemcpy(c.data(), I->flip_ctr, sizeof(int64_t) * 256, hipMemcpyDeviceToHost), "readback");
+    int64_t t = 0;
+    for (int64_t x : c) t += x;
+    *flips = t;
+  }
+  return PAMC_OK;
+}
+
+pamc_status pamc_synchronize(pamc_instance* I) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  hipSetDevice(I->device);
+  HIP_TRY(hipStreamSynchronize(I->stream), "kernel execution");
+  return PAMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// instance.hpp -- host-side instance record and the launch entry points of
+// the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pamc_device.hpp"
+
+namespace pamc {
+
+// Population layout.  Replicas are grouped in tiles of 64 (one wavefront, one
+// replica per lane).  Spins are quad-interleaved: the 32-bit word
+// S[(t*nq + q)*64 + l] holds the spins of vertices 4q..4q+3 of replica
+// 64t+l (byte k = vertex 4q+k), so a lane reads the four spins that share one
+// Philox block with one load.  Fields are H[(t*np + v)*64 + l] (int32), so a
+// neighbour update is one coalesced 64-lane row.
+struct Pop {
+  uint32_t* S[2] = {nullptr, nullptr};
+  int32_t* H[2] = {nullptr, nullptr};
+  int64_t* E[2] = {nullptr, nullptr};
+  int32_t* fam[2] = {nullptr, nullptr};
+};
+
+struct GraphDev {
+  int32_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  int32_t* J = nullptr;
+  int32_t* class_ptr = nullptr;
+};
+
+}  // namespace pamc
+
+struct pamc_instance {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int32_t n = 0, np = 0, nq = 0, R = 0, T = 0, rule = 0, dense = 0, ncls = 0;
+  uint32_t flags = 0;
+  uint64_t seed = 0;
+  int64_t nnz = 0, W = 0, X = 0;
+  int64_t device_bytes = 0;
+  std::vector<int32_t> to_internal, to_input, class_ptr;
+  int32_t max_class_quads = 0;
+  pamc::GraphDev g;
+  pamc::Pop pop;
+  int8_t* best = nullptr;  // [np] internal ids
+  int32_t* to_internal_dev = nullptr;  // [n] caller id -> internal id
+  pamc::RunState* st = nullptr;
+  uint32_t* thr = nullptr;  // threshold table, 2X+1 entries
+  int32_t* order = nullptr; // [order_cap][ncls]
+  int32_t order_cap = 0;
+  // resampling scratch
+  uint64_t* rs_P = nullptr;
+  int32_t* rs_parent = nullptr;
+  // cluster scratch
+  int32_t* cl_targets = nullptr;
+  uint8_t* cl_sel = nullptr;
+  int32_t* cl_sizes = nullptr;
+  int32_t cl_cap_top = 0, cl_cap_trials = 0;
+  // per-step trace
+  int64_t* tr_mstar = nullptr;
+  double* tr_beta = nullptr;
+  double* tr_lnq = nullptr;
+  int32_t* tr_events = nullptr;
+  uint64_t* tr_time = nullptr;
+  int32_t tr_cap = 0;
+  double clock_hz = 100e6;
+  // Max-3-Cut source graph (host and device)
+  int32_t m3_n = 0;
+  int32_t *m3_row_ptr = nullptr, *m3_col = nullptr, *m3_w = nullptr;
+  int32_t* m3_labels = nullptr;
+  int64_t* m3_cut = nullptr;
+  // dense instance
+  int8_t* Jd = nullptr;  // [np_pad][ld] row-major
+  int64_t ldj = 0;
+  int32_t dn_pad = 0;    // padded dimension of the dense matrix
+  int8_t* Sd = nullptr;  // [R][dn_pad] replica-major spins (dense)
+  int8_t* Sd2 = nullptr; // resampling buffer
+  int32_t* Gd = nullptr; // block field scratch
+  int64_t* Ed[2] = {nullptr, nullptr};
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0, prof_attempts = 0;
+  int64_t* flip_ctr = nullptr; // [256]
+  // scratch for small readbacks
+  void* pinned = nullptr;
+};
+
+namespace pamc {
+
+struct Schedule {
+  double beta0, dbeta, reheat;
+  int64_t target;
+  int32_t steps, sweeps, z_rst, augmented, resample;
+  int32_t win_short, win_long, max_ds, max_dl, tau, n_top, mis_trials;
+  int32_t stop_at_target, literal_break;
+};
+
+// sparse path launchers (sparse.hip); each returns a hipError_t
+hipError_t launch_init_sparse(pamc_instance* I);
+hipError_t launch_anneal_setup(pamc_instance* I, const Schedule& s);
+hipError_t launch_step(pamc_instance* I, const Schedule& s, int32_t step);
+hipError_t launch_prim_sweep(pamc_instance* I, double beta, int32_t nsweeps);
+hipError_t launch_prim_resample(pamc_instance* I, double delta);
+hipError_t launch_prim_cluster(pamc_instance* I, int32_t n_top, int32_t trials);
+hipError_t launch_prim_update_best(pamc_instance* I);
+hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
+hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
+int32_t cluster_max_n();
+hipError_t prepare_cluster_lds();
+
+// dense path launchers (dense.hip)
+hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed);
+hipError_t launch_init_dense(pamc_instance* I);
+hipError_t launch_dense_step(pamc_instance* I, const Schedule& s, int32_t step);
+hipError_t launch_dense_prim_sweep(pamc_instance* I, double beta, int32_t nsweeps);
+hipError_t launch_dense_prim_resample(pamc_instance* I, double delta);
+hipError_t launch_dense_prim_update_best(pamc_instance* I);
+
+}  // namespace pamc

@@ -1,0 +1,342 @@
+"""ctypes binding of libpamc.so (the C ABI declared in include/pamc.h).
+
+Argument marshalling only: every step of the method runs in the library's
+gfx950 kernels.  The module-level functions carry the C names; ``Instance``
+is a thin owner object around a ``pamc_instance*``.  Importing this module
+without the built library raises immediately -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpamc.so")
+
+PAMC_OK, PAMC_ERR_INVALID_ARG, PAMC_ERR_OUT_OF_MEMORY, PAMC_ERR_DEVICE, PAMC_ERR_STATE, \
+    PAMC_ERR_UNSUPPORTED = range(6)
+HEATBATH, METROPOLIS = 0, 1
+MAXCUT, ISING = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+FLAG_FIXED_CLASS_ORDER = 1
+
+EXPORTED = [
+    "pamc_create_instance_csr", "pamc_create_instance_dense_i8", "pamc_create_instance_dense_random",
+    "pamc_create_instance_max3cut", "pamc_destroy_instance", "pamc_get_info", "pamc_anneal",
+    "pamc_sweep", "pamc_resample", "pamc_cluster_move", "pamc_update_best", "pamc_best",
+    "pamc_get_state", "pamc_get_trace", "pamc_max3cut_decode", "pamc_pair_distance",
+    "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
+]
+
+
+class PamcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pamc status {status}: {msg}")
+        self.status = status
+
+
+class pamc_config(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("replicas", C.c_int32), ("rule", C.c_int32),
+                ("device", C.c_int32), ("stream", C.c_void_p), ("flags", C.c_uint32)]
+
+
+class pamc_info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("replicas", C.c_int32), ("num_classes", C.c_int32),
+                ("dense", C.c_int32), ("nnz", C.c_int64), ("W", C.c_int64), ("X", C.c_int64),
+                ("device_bytes", C.c_int64)]
+
+
+class pamc_schedule(C.Structure):
+    _fields_ = [("beta0", C.c_double), ("dbeta", C.c_double), ("steps", C.c_int32),
+                ("sweeps", C.c_int32), ("z_rst", C.c_int32), ("augmented", C.c_int32),
+                ("resample", C.c_int32), ("win_short", C.c_int32), ("win_long", C.c_int32),
+                ("max_distinct_short", C.c_int32), ("max_distinct_long", C.c_int32),
+                ("reheat", C.c_double), ("tau", C.c_int32), ("n_top", C.c_int32),
+                ("mis_trials", C.c_int32), ("target", C.c_int64), ("stop_at_target", C.c_int32),
+                ("literal_break", C.c_int32)]
+
+
+class pamc_result(C.Structure):
+    _fields_ = [("best_cut", C.c_int64), ("best_energy", C.c_int64), ("steps_run", C.c_int32),
+                ("step_reached", C.c_int32), ("sum_lnq", C.c_double),
+                ("n_cluster_moves", C.c_int32), ("n_reheats", C.c_int32),
+                ("n_reversals", C.c_int32), ("n_restarts", C.c_int32),
+                ("seconds_total", C.c_double), ("seconds_to_target", C.c_double)]
+
+
+def schedule(**kw) -> pamc_schedule:
+    """Algorithm 1 inputs with the paper's controller constants as defaults
+    (windows 25/40, at most 3 / 5 distinct values, reheat factor 0.8)."""
+    s = pamc_schedule(beta0=0.1, dbeta=0.02, steps=10, sweeps=1, z_rst=0, augmented=0, resample=1,
+                      win_short=25, win_long=40, max_distinct_short=3, max_distinct_long=5,
+                      reheat=0.8, tau=25, n_top=1, mis_trials=4, target=2**62, stop_at_target=0,
+                      literal_break=0)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    PP = C.POINTER(C.c_void_p)
+    st = C.c_int
+    L.pamc_last_error.restype = C.c_char_p
+    sig = {
+        "pamc_create_instance_csr": [C.c_int32, P, P, P, C.c_int, C.c_int32, C.POINTER(pamc_config), PP],
+        "pamc_create_instance_dense_i8": [C.c_int32, P, C.c_int64, C.c_int, C.c_int32, C.POINTER(pamc_config), PP],
+        "pamc_create_instance_dense_random": [C.c_int32, C.c_uint64, C.POINTER(pamc_config), PP],
+        "pamc_create_instance_max3cut": [C.c_int32, P, P, P, C.POINTER(pamc_config), PP],
+        "pamc_get_info": [P, C.POINTER(pamc_info)],
+        "pamc_anneal": [P, C.POINTER(pamc_schedule), C.POINTER(pamc_result)],
+        "pamc_sweep": [P, C.c_double, C.c_int32],
+        "pamc_resample": [P, C.c_double, P],
+        "pamc_cluster_move": [P, C.c_int32, C.c_int32, P],
+        "pamc_update_best": [P],
+        "pamc_best": [P, P, P, P],
+        "pamc_get_state": [P, P, P, P, P],
+        "pamc_get_trace": [P, C.c_int32, P, P, P, P, P, P],
+        "pamc_max3cut_decode": [P, P, P, P],
+        "pamc_pair_distance": [P, P],
+        "pamc_profile_enable": [P, C.c_int32],
+        "pamc_profile_read": [P, P, P, P, P],
+        "pamc_synchronize": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = st
+    L.pamc_destroy_instance.argtypes = [P]
+    L.pamc_destroy_instance.restype = None
+    return L
+
+
+lib = _load()
+
+
+def _check(status):
+    if status != PAMC_OK:
+        raise PamcError(status, lib.pamc_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+# ---------------------------------------------------------------- C names
+def pamc_create_instance_csr(n, row_ptr, col, w, objective=MAXCUT, *, seed=0, replicas=64,
+                             rule=HEATBATH, device=0, stream=None, flags=0):
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    cl = np.ascontiguousarray(col, np.int32)
+    ww = np.ascontiguousarray(w, np.int32)
+    cfg = pamc_config(seed, replicas, rule, device, stream, flags)
+    h = C.c_void_p()
+    _check(lib.pamc_create_instance_csr(int(n), _ptr(rp), _ptr(cl), _ptr(ww), MEM_HOST, objective,
+                                        C.byref(cfg), C.byref(h)))
+    return h
+
+
+def pamc_create_instance_dense_i8(J, objective=ISING, *, seed=0, replicas=64, rule=HEATBATH,
+                                  device=0, stream=None, flags=0):
+    J = np.ascontiguousarray(J, np.int8)
+    cfg = pamc_config(seed, replicas, rule, device, stream, flags)
+    h = C.c_void_p()
+    _check(lib.pamc_create_instance_dense_i8(int(J.shape[0]), _ptr(J), int(J.shape[1]), MEM_HOST,
+                                             objective, C.byref(cfg), C.byref(h)))
+    return h
+
+
+def pamc_create_instance_dense_random(n, graph_seed, *, seed=0, replicas=64, rule=HEATBATH,
+                                      device=0, stream=None, flags=0):
+    cfg = pamc_config(seed, replicas, rule, device, stream, flags)
+    h = C.c_void_p()
+    _check(lib.pamc_create_instance_dense_random(int(n), int(graph_seed), C.byref(cfg), C.byref(h)))
+    return h
+
+
+def pamc_create_instance_max3cut(n, row_ptr, col, w, *, seed=0, replicas=64, rule=HEATBATH,
+                                 device=0, stream=None, flags=0):
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    cl = np.ascontiguousarray(col, np.int32)
+    ww = np.ascontiguousarray(w, np.int32)
+    cfg = pamc_config(seed, replicas, rule, device, stream, flags)
+    h = C.c_void_p()
+    _check(lib.pamc_create_instance_max3cut(int(n), _ptr(rp), _ptr(cl), _ptr(ww), C.byref(cfg), C.byref(h)))
+    return h
+
+
+def pamc_destroy_instance(h):
+    lib.pamc_destroy_instance(h)
+
+
+def pamc_get_info(h) -> pamc_info:
+    info = pamc_info()
+    _check(lib.pamc_get_info(h, C.byref(info)))
+    return info
+
+
+def pamc_anneal(h, sched: pamc_schedule) -> pamc_result:
+    res = pamc_result()
+    _check(lib.pamc_anneal(h, C.byref(sched), C.byref(res)))
+    return res
+
+
+def pamc_sweep(h, beta, nsweeps=1):
+    _check(lib.pamc_sweep(h, float(beta), int(nsweeps)))
+
+
+def pamc_resample(h, delta, want_log_q=True):
+    q = C.c_double()
+    _check(lib.pamc_resample(h, float(delta), C.byref(q) if want_log_q else None))
+    return q.value if want_log_q else None
+
+
+def pamc_cluster_move(h, n_top, mis_trials, want_flipped=True):
+    f = C.c_int32()
+    _check(lib.pamc_cluster_move(h, int(n_top), int(mis_trials), C.byref(f) if want_flipped else None))
+    return f.value if want_flipped else None
+
+
+def pamc_update_best(h):
+    _check(lib.pamc_update_best(h))
+
+
+def pamc_best(h, n):
+    cut, en = C.c_int64(), C.c_int64()
+    spins = np.zeros(n, np.int8)
+    _check(lib.pamc_best(h, C.byref(cut), C.byref(en), _ptr(spins)))
+    return cut.value, en.value, spins
+
+
+def pamc_get_state(h, n, R):
+    s = np.zeros((R, n), np.int8)
+    f = np.zeros((R, n), np.int32)
+    E = np.zeros(R, np.int64)
+    fam = np.zeros(R, np.int32)
+    _check(lib.pamc_get_state(h, _ptr(s), _ptr(f), _ptr(E), _ptr(fam)))
+    return s, f, E, fam
+
+
+def pamc_get_trace(h, capacity):
+    m = np.zeros(capacity, np.int64)
+    b = np.zeros(capacity, np.float64)
+    q = np.zeros(capacity, np.float64)
+    ev = np.zeros(capacity, np.int32)
+    t = np.zeros(capacity, np.float64)
+    k = C.c_int32()
+    _check(lib.pamc_get_trace(h, int(capacity), _ptr(m), _ptr(b), _ptr(q), _ptr(ev), _ptr(t), C.byref(k)))
+    k = k.value
+    return {"mstar": m[:k], "beta": b[:k], "lnq": q[:k], "events": ev[:k], "seconds": t[:k]}
+
+
+def pamc_max3cut_decode(h, m3_n, spins=None):
+    labels = np.zeros(m3_n, np.int32)
+    cut = C.c_int64()
+    sp = np.ascontiguousarray(spins, np.int8) if spins is not None else None
+    _check(lib.pamc_max3cut_decode(h, _ptr(sp), _ptr(labels), C.byref(cut)))
+    return cut.value, labels
+
+
+def pamc_pair_distance(h):
+    d = C.c_double()
+    _check(lib.pamc_pair_distance(h, C.byref(d)))
+    return d.value
+
+
+def pamc_profile_enable(h, on=True):
+    _check(lib.pamc_profile_enable(h, int(bool(on))))
+
+
+def pamc_profile_read(h):
+    ms, la, at, fl = C.c_double(), C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib.pamc_profile_read(h, C.byref(ms), C.byref(la), C.byref(at), C.byref(fl)))
+    return {"ms": ms.value, "launches": la.value, "attempts": at.value, "flips": fl.value}
+
+
+def pamc_synchronize(h):
+    _check(lib.pamc_synchronize(h))
+
+
+# ---------------------------------------------------------------- owner object
+class Instance:
+    """Owns one ``pamc_instance*``; methods forward to the C functions."""
+
+    def __init__(self, handle, n, replicas, m3_n=0):
+        self.h = handle
+        self.n = int(n)
+        self.R = int(replicas)
+        self.m3_n = m3_n
+
+    @classmethod
+    def csr(cls, g, *, replicas, seed, rule=HEATBATH, objective=MAXCUT, shuffle=True, stream=None):
+        h = pamc_create_instance_csr(g.n, g.row_ptr, g.col, g.w, objective, seed=seed, replicas=replicas,
+                                     rule=rule, stream=stream, flags=0 if shuffle else FLAG_FIXED_CLASS_ORDER)
+        return cls(h, g.n, replicas)
+
+    @classmethod
+    def max3cut(cls, g, *, replicas, seed, rule=HEATBATH, shuffle=True, stream=None):
+        h = pamc_create_instance_max3cut(g.n, g.row_ptr, g.col, g.w, seed=seed, replicas=replicas, rule=rule,
+                                         stream=stream, flags=0 if shuffle else FLAG_FIXED_CLASS_ORDER)
+        return cls(h, 3 * g.n + 1, replicas, m3_n=g.n)
+
+    @classmethod
+    def dense(cls, J, *, replicas, seed, rule=HEATBATH, objective=ISING, stream=None):
+        h = pamc_create_instance_dense_i8(J, objective, seed=seed, replicas=replicas, rule=rule, stream=stream)
+        return cls(h, J.shape[0], replicas)
+
+    @classmethod
+    def dense_random(cls, n, graph_seed, *, replicas, seed, rule=HEATBATH, stream=None):
+        h = pamc_create_instance_dense_random(n, graph_seed, seed=seed, replicas=replicas, rule=rule,
+                                              stream=stream)
+        return cls(h, n, replicas)
+
+    def close(self):
+        if self.h:
+            pamc_destroy_instance(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return pamc_get_info(self.h)
+
+    def anneal(self, sched):
+        return pamc_anneal(self.h, sched)
+
+    def sweep(self, beta, nsweeps=1):
+        pamc_sweep(self.h, beta, nsweeps)
+
+    def resample(self, delta):
+        return pamc_resample(self.h, delta)
+
+    def cluster_move(self, n_top, mis_trials):
+        return pamc_cluster_move(self.h, n_top, mis_trials)
+
+    def update_best(self):
+        pamc_update_best(self.h)
+
+    def best(self):
+        return pamc_best(self.h, self.n)
+
+    def state(self):
+        return pamc_get_state(self.h, self.n, self.R)
+
+    def trace(self, capacity):
+        return pamc_get_trace(self.h, capacity)
+
+    def max3cut_decode(self, spins=None):
+        return pamc_max3cut_decode(self.h, self.m3_n, spins)
+
+    def pair_distance(self):
+        return pamc_pair_distance(self.h)
+
+    def synchronize(self):
+        pamc_synchronize(self.h)

@@ -1,0 +1,274 @@
+"""Parity of the gfx950 library against the CPU oracle, through the C ABI.
+
+Spins, fields, energies, lineage, best cuts and controller traces must match
+bit for bit (integer results and the integer decisions taken from binary64
+values computed by the same sequence of IEEE operations on both sides);
+ln Q, a reported floating-point sum whose order of summation differs, must
+agree to 1e-12 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL_LNQ = 1e-12
+
+
+@pytest.fixture(scope="module")
+def pamc():
+    from paper_2606_25203_amd import pamc as p
+    return p
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def same_state(inst, o, tag=""):
+    s, h, E, f = inst.state()
+    os_, oh, oE, of = o.state()
+    assert np.array_equal(E, oE), f"{tag}: energies differ at {np.nonzero(E != oE)[0][:8]}"
+    assert np.array_equal(s, os_), f"{tag}: spins differ"
+    assert np.array_equal(h, oh), f"{tag}: fields differ"
+    assert np.array_equal(f, of), f"{tag}: lineage differs"
+
+
+def close_lnq(a, b):
+    return abs(a - b) <= RTOL_LNQ * max(1.0, abs(b))
+
+
+GRAPHS = {
+    "c1_shape_small": lambda: synth.random_graph(301, 2500, 3),       # ragged n (not a multiple of 4)
+    "torus_pm1": lambda: synth.torus(14, 10, 2),
+    "dense_ish": lambda: synth.random_graph(90, 2000, 4, weights="pm1"),
+}
+
+
+@pytest.mark.parametrize("gname", list(GRAPHS))
+@pytest.mark.parametrize("rule", [0, 1])
+@pytest.mark.parametrize("R", [64, 512])
+def test_init_and_sweeps(pamc, gname, rule, R):
+    g = GRAPHS[gname]()
+    seed = 1234 + R
+    say(f"case init/sweeps graph={gname} n={g.n} R={R} rule={rule}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=seed, rule=rule)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, seed, rule=rule)
+    same_state(inst, o, "init")
+    for beta, k in [(0.0, 1), (0.3, 2), (1.7, 3), (5.0, 1)]:
+        inst.sweep(beta, k)
+        o.sweep(beta, k)
+        same_state(inst, o, f"beta={beta}")
+    inst.close()
+
+
+@pytest.mark.parametrize("objective", [0, 1])
+def test_objective_and_fixed_order(pamc, objective):
+    g = synth.random_graph(200, 900, 8, weights="pm1")
+    say(f"case objective={objective}")
+    inst = pamc.Instance.csr(g, replicas=128, seed=5, objective=objective, shuffle=False)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 128, 5, objective=objective, shuffle=False)
+    inst.sweep(0.8, 4)
+    o.sweep(0.8, 4)
+    same_state(inst, o)
+    info = inst.info()
+    assert info.W == o.W and info.X == o.X and info.num_classes == o.num_classes
+    inst.close()
+
+
+@pytest.mark.parametrize("delta", [0.0, 0.05, -0.03, 2.0])
+def test_resample(pamc, delta):
+    g = synth.random_graph(240, 1500, 6)
+    R = 512
+    say(f"case resample delta={delta}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=77)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 77)
+    inst.sweep(0.7, 2)
+    o.sweep(0.7, 2)
+    for _ in range(3):
+        lq = inst.resample(delta)
+        olq = o.resample(delta)
+        assert close_lnq(lq, olq), (lq, olq)
+        same_state(inst, o, "after resample")
+        inst.sweep(1.0, 1)
+        o.sweep(1.0, 1)
+        same_state(inst, o, "after sweep")
+    inst.close()
+
+
+@pytest.mark.parametrize("n_top,trials", [(1, 1), (8, 4), (64, 3)])
+def test_cluster_move(pamc, n_top, trials):
+    g = synth.torus(20, 16, 9)
+    R = 128
+    say(f"case cluster n_top={n_top} trials={trials}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=3)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 3)
+    inst.sweep(2.0, 6)
+    o.sweep(2.0, 6)
+    for _ in range(2):
+        f = inst.cluster_move(n_top, trials)
+        tot, _ = o.cluster(n_top, trials)
+        assert f == tot
+        same_state(inst, o, "after cluster")
+        inst.sweep(1.5, 1)
+        o.sweep(1.5, 1)
+    same_state(inst, o, "after cluster + sweep")
+    inst.close()
+
+
+def test_update_best(pamc):
+    g = synth.random_graph(150, 700, 2)
+    inst = pamc.Instance.csr(g, replicas=64, seed=9)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 64, 9)
+    for beta in (0.5, 1.0, 2.0):
+        inst.sweep(beta, 2)
+        o.sweep(beta, 2)
+        inst.update_best()
+        o.update_best()
+        c, e, sp = inst.best()
+        oc, oe, osp = o.best()
+        assert (c, e) == (oc, oe) and np.array_equal(sp, osp)
+    inst.close()
+
+
+def compare_anneal(pamc, inst, o, sched_kw):
+    res = inst.anneal(pamc.schedule(**sched_kw))
+    ores, otr = o.anneal(oracle.default_schedule(**sched_kw), trace=True)
+    for k in ("best_cut", "best_energy", "steps_run", "step_reached", "n_cluster_moves", "n_reheats",
+              "n_reversals", "n_restarts"):
+        assert getattr(res, k) == getattr(ores, k), (k, getattr(res, k), getattr(ores, k))
+    assert close_lnq(res.sum_lnq, ores.sum_lnq), (res.sum_lnq, ores.sum_lnq)
+    tr = inst.trace(sched_kw["steps"])
+    k = ores.steps_run
+    assert np.array_equal(tr["mstar"], otr["mstar"][:k])
+    assert np.array_equal(tr["beta"], otr["beta"][:k])
+    assert np.array_equal(tr["events"], otr["events"][:k])
+    assert all(close_lnq(a, b) for a, b in zip(tr["lnq"], otr["lnq"][:k]))
+    c, e, sp = inst.best()
+    oc, oe, osp = o.best()
+    assert c == oc and e == oe and np.array_equal(sp, osp)
+    same_state(inst, o, "after anneal")
+    return res, ores
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_plain_anneal_c1_full(pamc, rule):
+    """Plain PAMC on the full sparse Max-Cut configuration: n = 800, 19,176
+    edges, R = 256, 50 steps linear 0.1 -> 3.0, 5 sweeps per step."""
+    g = synth.config_c1_graph()
+    say(f"case c1 full rule={rule}")
+    inst = pamc.Instance.csr(g, replicas=256, seed=2024, rule=rule)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 256, 2024, rule=rule)
+    compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=2.9 / 49, steps=50, sweeps=5))
+    inst.close()
+
+
+def test_augmented_anneal_torus(pamc):
+    g = synth.torus(24, 20, 5)
+    say("case augmented torus")
+    inst = pamc.Instance.csr(g, replicas=256, seed=99)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 256, 99)
+    res, ores = compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.02, steps=260, sweeps=3, augmented=1,
+                                                   z_rst=120, n_top=8, mis_trials=4, tau=25))
+    assert ores.n_cluster_moves > 0 and ores.n_reheats > 0
+    inst.close()
+
+
+def test_augmented_literal_break_and_target(pamc):
+    g = synth.torus(12, 10, 1)
+    say("case literal break / stop at target")
+    inst = pamc.Instance.csr(g, replicas=64, seed=4)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 64, 4)
+    compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.05, steps=150, sweeps=2, augmented=1, z_rst=0,
+                                       n_top=2, literal_break=1))
+    inst2 = pamc.Instance.csr(g, replicas=64, seed=4)
+    o2 = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 64, 4)
+    compare_anneal(pamc, inst2, o2, dict(beta0=0.1, dbeta=0.1, steps=100, sweeps=2, target=100,
+                                         stop_at_target=1))
+    inst.close()
+    inst2.close()
+
+
+def test_sa_mode_no_resampling(pamc):
+    g = synth.random_graph(100, 400, 1)
+    inst = pamc.Instance.csr(g, replicas=128, seed=4)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 128, 4)
+    compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.1, steps=20, sweeps=2, resample=0))
+    inst.close()
+
+
+def test_max3cut_anneal_and_decode(pamc):
+    g = synth.random_graph(60, 180, 7)
+    R = 128
+    say("case max3cut")
+    inst = pamc.Instance.max3cut(g, replicas=R, seed=21)
+    o = oracle.Oracle.max3cut(g.n, g.row_ptr, g.col, g.w, R, 21)
+    compare_anneal(pamc, inst, o, dict(beta0=0.05, dbeta=0.03, steps=60, sweeps=4, augmented=1, z_rst=0,
+                                       n_top=4))
+    cut, labels = inst.max3cut_decode()
+    _, _, spins = o.best()
+    ocut, olabels = o.max3cut_decode(spins)
+    assert cut == ocut and np.array_equal(labels, olabels)
+    s = inst.state()[0]
+    for r in (0, 5, 17):
+        c1, l1 = inst.max3cut_decode(s[r])
+        c2, l2 = o.max3cut_decode(s[r])
+        assert c1 == c2 and np.array_equal(l1, l2)
+    inst.close()
+
+
+def test_tiny_and_edgeless(pamc):
+    for g in [synth.csr_from_edges(1, [], [], []), synth.csr_from_edges(5, [], [], []),
+              synth.csr_from_edges(2, [0], [1], [3])]:
+        say(f"case tiny n={g.n}")
+        inst = pamc.Instance.csr(g, replicas=64, seed=1)
+        o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 64, 1)
+        compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.5, steps=6, sweeps=2))
+        inst.close()
+
+
+def test_invalid_inputs(pamc):
+    g = synth.random_graph(20, 40, 1)
+    with pytest.raises(pamc.PamcError):
+        pamc.Instance.csr(g, replicas=100, seed=1)            # not a multiple of 64
+    w = g.w.copy()
+    w[0] = 7                                                   # breaks symmetry
+    with pytest.raises(pamc.PamcError):
+        pamc.pamc_create_instance_csr(g.n, g.row_ptr, g.col, w, replicas=64)
+    col = g.col.copy()
+    col[0] = 0 if g.row_ptr[1] > 0 and col[0] != 0 else col[0]
+    with pytest.raises(pamc.PamcError):
+        pamc.pamc_create_instance_csr(g.n, g.row_ptr, col, g.w, replicas=64)
+
+
+def test_c2_full_size_subset_parity_and_invariants(pamc):
+    """Torus 100 x 200 (n = 20,000) at R = 4096: sweeps of replica r depend
+    only on (seed, r), so replicas 0..63 must equal an oracle run with
+    R = 64.  Then one augmented step with resampling at full size, checked by
+    invariants (h = J s, E = -1/2 s.h) on sampled replicas."""
+    g = synth.config_c2_graph()
+    say("case c2 full size")
+    inst = pamc.Instance.csr(g, replicas=4096, seed=31)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 64, 31)
+    inst.sweep(0.4, 2)
+    o.sweep(0.4, 2)
+    s, h, E, fam = inst.state()
+    os_, oh, oE, _ = o.state()
+    assert np.array_equal(s[:64], os_) and np.array_equal(h[:64], oh) and np.array_equal(E[:64], oE)
+    inst.resample(0.02)
+    inst.sweep(0.42, 1)
+    s, h, E, fam = inst.state()
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    rng = np.random.default_rng(0)
+    for r in rng.choice(4096, 16, replace=False):
+        sr = s[r].astype(np.int64)
+        hr = np.zeros(g.n, np.int64)
+        np.add.at(hr, rows, -g.w.astype(np.int64) * sr[g.col])
+        assert np.array_equal(hr, h[r])
+        assert E[r] == -(sr * hr).sum() // 2
+    inst.close()
