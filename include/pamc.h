@@ -64,6 +64,13 @@ typedef enum { PAMC_MEM_HOST = 0, PAMC_MEM_DEVICE = 1 } pamc_mem;
 
 /* pamc_config.flags */
 #define PAMC_FLAG_FIXED_CLASS_ORDER 1u /* do not shuffle colour classes per sweep */
+/* Local-field storage of sparse instances.  PUSH keeps every field (Eq. 3)
+ * in an int32 array updated by each flip; PULL keeps no field array and sums
+ * the neighbours' spins when a spin is visited.  The integer fields, hence
+ * every decision and the trajectory, are the same; the default picks PULL
+ * when the average degree is at most 16. */
+#define PAMC_FLAG_FIELDS_PUSH 2u
+#define PAMC_FLAG_FIELDS_PULL 4u
 
 typedef struct {
   uint64_t seed;     /* Philox key */
@@ -113,8 +120,13 @@ pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, cons
 
 void pamc_destroy_instance(pamc_instance* inst);
 
+/* Re-draws the population from a new Philox key (Algorithm 1,
+ * initialization: random spins, their fields and energies, M* = 0) and
+ * resets the RNG counters, keeping the instance's graph and buffers. */
+pamc_status pamc_reset_population(pamc_instance* inst, uint64_t seed);
+
 typedef struct {
-  int32_t n, replicas, num_classes, dense;
+  int32_t n, replicas, num_classes, dense, pull;
   int64_t nnz, W, X; /* X = max_v sum_j |J_vj| */
   int64_t device_bytes;
 } pamc_info;

@@ -3,6 +3,7 @@
 // embedding), device memory, and the drivers that enqueue the kernels.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -55,7 +56,7 @@ void free_instance(pamc_instance* I) {
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
                   I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
                   I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Ed[0], I->Ed[1],
-                  I->flip_ctr};
+                  I->flip_ctr, I->H_scratch};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (I->pinned) hipHostFree(I->pinned);
@@ -169,7 +170,9 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
     I->max_class_quads = std::max(I->max_class_quads, ((b + 3) >> 2) - (a >> 2));
   }
   // relabelled CSR
-  std::vector<int32_t> rp2(n + 1, 0), col2(std::max<int64_t>(I->nnz, 1)), J2(std::max<int64_t>(I->nnz, 1));
+  // CSR arrays carry trailing padding (vertex 0, coupling 0) so that the
+  // sweep kernels may read a few entries past the last row.
+  std::vector<int32_t> rp2(n + 1, 0), col2(I->nnz + 16, 0), J2(I->nnz + 16, 0);
   int64_t W = 0, X = 0;
   for (int32_t iv = 0; iv < n; ++iv) {
     const int32_t v = I->to_input[iv];
@@ -187,7 +190,30 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
   if (2 * X >= INT32_MAX) return fail(PAMC_ERR_INVALID_ARG, "local field range exceeds int32");
   I->W = W;
   I->X = X;
-  const size_t nnz = (size_t)std::max<int64_t>(I->nnz, 1);
+  I->small_j = 1;
+  for (int32_t e = 0; e < rp[n]; ++e)
+    if (std::llabs((long long)Jin[e]) >= (1 << 23)) I->small_j = 0;
+  // Field storage: kept incrementally (push) or gathered at visit time
+  // (pull); both give the same integer fields and the same trajectory.
+  if (I->flags & PAMC_FLAG_FIELDS_PUSH)
+    I->pull = 0;
+  else if (I->flags & PAMC_FLAG_FIELDS_PULL)
+    I->pull = 1;
+  else
+    I->pull = (I->nnz <= 16 * (int64_t)n) ? 1 : 0;
+  // Tiles per wavefront: share the per-vertex scalar work among up to 4
+  // tiles while keeping enough work-groups to fill the chip.
+  {
+    const int64_t chunks = (I->max_class_quads + 15) / 16;
+    I->tpw = 1;
+    for (int t : {4, 2})
+      if (I->T % t == 0 && (I->T / t) * chunks >= 1024) { I->tpw = t; break; }
+    if (const char* e = getenv("PAMC_TPW")) {
+      const int t = atoi(e);
+      if ((t == 1 || t == 2 || t == 4) && I->T % t == 0) I->tpw = t;
+    }
+  }
+  const size_t nnz = (size_t)I->nnz + 16;
   const size_t words = (size_t)I->T * I->nq * 64, hs = (size_t)I->T * I->np * 64;
   HIP_TRY(dalloc(I, &I->g.row_ptr, n + 1), "alloc");
   HIP_TRY(dalloc(I, &I->g.col, nnz), "alloc");
@@ -195,7 +221,7 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
   HIP_TRY(dalloc(I, &I->g.class_ptr, ncls + 1), "alloc");
   for (int b = 0; b < 2; ++b) {
     HIP_TRY(dalloc(I, &I->pop.S[b], words), "alloc population");
-    HIP_TRY(dalloc(I, &I->pop.H[b], hs), "alloc population");
+    if (!I->pull) HIP_TRY(dalloc(I, &I->pop.H[b], hs), "alloc population");
     HIP_TRY(dalloc(I, &I->pop.E[b], I->R), "alloc population");
     HIP_TRY(dalloc(I, &I->pop.fam[b], I->R), "alloc population");
   }
@@ -210,8 +236,10 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
   HIP_TRY(dalloc(I, &I->flip_ctr, 512), "alloc");
   HIP_TRY(hipMemsetAsync(I->flip_ctr, 0, sizeof(int64_t) * 512, I->stream), "memset");
   HIP_TRY(hipMemsetAsync(I->st, 0, sizeof(pamc::RunState), I->stream), "memset");
-  HIP_TRY(hipMemsetAsync(I->pop.H[0], 0, sizeof(int32_t) * hs, I->stream), "memset");
-  HIP_TRY(hipMemsetAsync(I->pop.H[1], 0, sizeof(int32_t) * hs, I->stream), "memset");
+  if (!I->pull) {
+    HIP_TRY(hipMemsetAsync(I->pop.H[0], 0, sizeof(int32_t) * hs, I->stream), "memset");
+    HIP_TRY(hipMemsetAsync(I->pop.H[1], 0, sizeof(int32_t) * hs, I->stream), "memset");
+  }
   HIP_TRY(hipMemcpyAsync(I->g.row_ptr, rp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->g.col, col2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->g.J, J2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
@@ -290,6 +318,17 @@ pamc_status ensure_order(pamc_instance* I, int32_t sweeps) {
   I->order = nullptr;
   I->order_cap = sweeps;
   HIP_TRY(dalloc(I, &I->order, (size_t)sweeps * I->ncls), "alloc order");
+  return PAMC_OK;
+}
+
+// Folds the recorded sweep-launch event pairs into the running total.
+pamc_status resolve_events(pamc_instance* I) {
+  for (size_t i = 0; i + 1 < I->ev_used; i += 2) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, I->ev_pool[i], I->ev_pool[i + 1]), "hipEventElapsedTime");
+    I->prof_ms += t;
+  }
+  I->ev_used = 0;
   return PAMC_OK;
 }
 
@@ -414,12 +453,25 @@ pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, cons
 
 void pamc_destroy_instance(pamc_instance* inst) { free_instance(inst); }
 
+pamc_status pamc_reset_population(pamc_instance* I, uint64_t seed) {
+  if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+  hipSetDevice(I->device);
+  I->seed = seed;
+  if (I->dense) {
+    HIP_TRY(pamc::launch_init_dense(I), "init kernels");
+  } else {
+    HIP_TRY(pamc::launch_init_sparse(I), "init kernels");
+  }
+  return PAMC_OK;
+}
+
 pamc_status pamc_get_info(const pamc_instance* I, pamc_info* out) {
   if (!I || !out) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
   out->n = I->n;
   out->replicas = I->R;
   out->num_classes = I->ncls;
   out->dense = I->dense;
+  out->pull = I->pull;
   out->nnz = I->nnz;
   out->W = I->W;
   out->X = I->X;
@@ -526,7 +578,15 @@ pamc_status pamc_get_state(pamc_instance* I, int8_t* spins, int32_t* fields, int
   }
   if (fields) {
     std::vector<int32_t> H((size_t)I->T * I->np * 64);
-    HIP_TRY(hipMemcpy(H.data(), I->pop.H[b], H.size() * 4, hipMemcpyDeviceToHost), "readback");
+    const int32_t* src = I->pop.H[b];
+    if (I->pull) {
+      if (!I->H_scratch) HIP_TRY(dalloc(I, &I->H_scratch, H.size()), "alloc fields");
+      I->host_cur = b;
+      HIP_TRY(pamc::launch_fields(I, I->H_scratch), "fields");
+      HIP_TRY(hipStreamSynchronize(I->stream), "fields");
+      src = I->H_scratch;
+    }
+    HIP_TRY(hipMemcpy(H.data(), src, H.size() * 4, hipMemcpyDeviceToHost), "readback");
     for (int32_t rr = 0; rr < R; ++rr)
       for (int32_t v = 0; v < n; ++v)
         fields[(size_t)rr * n + v] = H[((size_t)(rr >> 6) * I->np + I->to_internal[v]) * 64 + (rr & 63)];
@@ -567,6 +627,7 @@ pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_resul
   }
   pamc::RunState r;
   st = read_state(I, &r);
+  if (!st && I->prof) st = resolve_events(I);
   if (st) return st;
   memset(out, 0, sizeof *out);
   out->best_cut = r.mstar;
@@ -663,12 +724,8 @@ pamc_status pamc_profile_read(pamc_instance* I, double* ms, int64_t* launches, i
   if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
   hipSetDevice(I->device);
   HIP_TRY(hipStreamSynchronize(I->stream), "sync");
-  for (size_t i = 0; i + 1 < I->ev_used; i += 2) {
-    float t = 0.f;
-    HIP_TRY(hipEventElapsedTime(&t, I->ev_pool[i], I->ev_pool[i + 1]), "hipEventElapsedTime");
-    I->prof_ms += t;
-  }
-  I->ev_used = 0;
+  pamc_status st = resolve_events(I);
+  if (st) return st;
   if (ms) *ms = I->prof_ms;
   if (launches) *launches = I->prof_launches;
   if (attempts) *attempts = I->prof_attempts;

@@ -45,6 +45,11 @@ struct pamc_instance {
   int64_t device_bytes = 0;
   std::vector<int32_t> to_internal, to_input, class_ptr;
   int32_t max_class_quads = 0;
+  int32_t pull = 0;       // 1: fields gathered at visit time (no field array)
+  int32_t tpw = 1;        // replica tiles per wavefront in the gathered-field sweep
+  int32_t small_j = 0;    // 1: every |J| < 2^23 (24-bit multiplies are exact)
+  int32_t host_cur = 0;   // population buffer index last read back
+  int32_t* H_scratch = nullptr;  // fields for snapshots in pull mode
   pamc::GraphDev g;
   pamc::Pop pop;
   int8_t* best = nullptr;  // [np] internal ids
@@ -113,6 +118,7 @@ hipError_t launch_prim_cluster(pamc_instance* I, int32_t n_top, int32_t trials);
 hipError_t launch_prim_update_best(pamc_instance* I);
 hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
 hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
+hipError_t launch_fields(pamc_instance* I, int32_t* H);
 int32_t cluster_max_n();
 hipError_t prepare_cluster_lds();
 

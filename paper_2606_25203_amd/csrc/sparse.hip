@@ -31,6 +31,11 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   return v;
 }
 
+__device__ __forceinline__ int32_t spin_at(const uint32_t* S, int nq, int tile, int v, int lane) {
+  const uint32_t w = S[((size_t)tile * nq + (v >> 2)) * kLanes + lane];
+  return (int32_t)(int8_t)(w >> (8 * (v & 3)));
+}
+
 // blockIdx -> (tile, chunk).  Work-groups are dealt round-robin to the eight
 // XCDs, so tile t is kept on XCD t % 8 when T is a multiple of 8: all field
 // atomics of a tile then meet in one L2.
@@ -45,6 +50,44 @@ __device__ __forceinline__ void tile_chunk(int T, int& tile, int& chunk) {
     chunk = b / T;
   }
 }
+
+
+// Field of Eq. 3 for vertex v of replica lane `lane` of a tile, gathered
+// from the neighbours' spin words.  Neighbours are taken four at a time with
+// unconditional loads (the CSR arrays carry kCsrPad trailing entries, and an
+// entry past the row is a valid vertex id), and the couplings of entries past
+// the row are masked to zero, so the loop body has no per-entry branches.
+// Srow points at the tile's spin words + lane.
+constexpr int kCsrPad = 8;
+template <bool SMALLJ>
+__device__ __forceinline__ int32_t gather_field(const int32_t* __restrict__ col,
+                                                const int32_t* __restrict__ J, int e0, int e1,
+                                                const uint32_t* __restrict__ Srow) {
+  int32_t h = 0;
+  for (int e = e0; e < e1; e += 4) {
+    const int cnt = e1 - e;
+    int j[4];
+    int32_t c[4];
+    uint32_t w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = col[e + u];
+      c[u] = J[e + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = Srow[(uint32_t)(j[u] >> 2) * (uint32_t)kLanes];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t cu = u < cnt ? c[u] : 0;
+      const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[u], 8u * (uint32_t)(j[u] & 3), 8u);
+      // couplings below 2^23 in magnitude use the full-rate 24-bit multiply
+      h += SMALLJ ? __mul24(cu, sv) : cu * sv;
+    }
+  }
+  return h;
+}
+
+constexpr int kThrLds = 2048;  // threshold entries staged in LDS when they fit
 
 struct SweepArgs {
   const int32_t* row_ptr;
@@ -74,25 +117,38 @@ struct SweepArgs {
 // a class are mutually uncoupled, so no field read here is written here.
 // ---------------------------------------------------------------------------
 template <int RULE>
-__global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int sweep_idx, int phase) {
+__global__ void __launch_bounds__(256) k_sweep(const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const int32_t* __restrict__ Jc,
+                                                  const int32_t* __restrict__ class_ptr,
+                                                  const int32_t* __restrict__ order,
+                                                  const uint32_t* __restrict__ thr_g, SweepArgs a,
+                                                  int sweep_idx, int phase) {
   __shared__ int64_t red[kSweepWaves][kLanes];
   __shared__ int32_t fred[kSweepWaves];
+  __shared__ uint32_t thr_s[kThrLds];
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
   uint32_t* __restrict__ S = cur ? a.S1 : a.S0;
   int32_t* __restrict__ H = cur ? a.H1 : a.H0;
   int64_t* __restrict__ E = cur ? a.E1 : a.E0;
-  const int cls = a.order[sweep_idx * a.ncls + phase];
-  const int v0 = a.class_ptr[cls], v1 = a.class_ptr[cls + 1];
+  const int cls = order[sweep_idx * a.ncls + phase];
+  const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
   const int q0 = v0 >> 2;
   const int nqc = ((v1 + 3) >> 2) - q0;
   int tile, chunk;
   tile_chunk(a.T, tile, chunk);
   if (chunk * kQuadsPerBlock >= nqc) return;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
-  const int64_t Xt = st->table_x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t Xt = (int32_t)st->table_x;
+  const bool thr_lds = 2 * Xt + 1 <= kThrLds;
+  if (thr_lds)
+    for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
+  __syncthreads();
+  const uint32_t* __restrict__ thr = thr_lds ? thr_s : a.thr;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t r = (uint32_t)(tile * kLanes + lane);
   const size_t hbase = (size_t)tile * a.np;
   int64_t dE = 0;
@@ -112,9 +168,8 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int sweep_idx, int p
       const int32_t h = H[(hbase + v) * kLanes + lane];
       const int32_t s = (int32_t)(int8_t)(sw >> (8 * k));
       const int32_t x = s * h;
-      int64_t xi = x;
-      xi = xi < -Xt ? -Xt : (xi > Xt ? Xt : xi);
-      const uint32_t T = a.thr[xi + Xt];
+      const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
+      const uint32_t T = thr[xi + Xt];
       const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, k) < T);
       const int32_t snew = -s;
       if (flip) {
@@ -124,11 +179,11 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int sweep_idx, int p
         ++nflip;
       }
       if (__ballot(flip)) {
-        const int e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
+        const int e0 = row_ptr[v], e1 = row_ptr[v + 1];
         const int32_t d = 2 * snew;
         for (int e = e0; e < e1; ++e) {
-          const int j = a.col[e];
-          const int32_t add = a.J[e] * d;
+          const int j = col[e];
+          const int32_t add = Jc[e] * d;
           if (flip)
             __hip_atomic_fetch_add(&H[(hbase + j) * kLanes + lane], add, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -156,6 +211,154 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a, int sweep_idx, int p
       __hip_atomic_fetch_add((unsigned long long*)&a.flip_ctr[blockIdx.x & 255],
                              (unsigned long long)f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Same class phase with the local field of Eq. 3 gathered at visit time from
+// the neighbours' spins instead of being kept in a field array.  The integer
+// h and hence every decision are identical to the incremental form; what
+// changes is the memory traffic: no field array and no atomics, only spin
+// words (one byte per replica and vertex), which suits low-degree graphs.
+// ---------------------------------------------------------------------------
+// Fields of one vertex for TPW tiles at once: the scalar work (CSR entries,
+// neighbour offsets, coupling masks) is shared by the tiles, the spin loads
+// and arithmetic are per tile.  Srow0 points at the first tile's spin words
+// + lane; tiles are tstride words apart.
+template <bool SMALLJ, int TPW>
+__device__ __forceinline__ void gather_fields(const int32_t* __restrict__ col,
+                                              const int32_t* __restrict__ J, int e0, int e1,
+                                              const uint32_t* __restrict__ Srow0, uint32_t tstride,
+                                              int32_t (&h)[TPW]) {
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) h[t] = 0;
+  for (int e = e0; e < e1; e += 4) {
+    const int cnt = e1 - e;
+    int j[4];
+    int32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = col[e + u];
+      c[u] = u < cnt ? J[e + u] : 0;
+    }
+    uint32_t w[TPW][4];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        w[t][u] = Srow0[(uint32_t)t * tstride + (uint32_t)(j[u] >> 2) * (uint32_t)kLanes];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[t][u], 8u * (uint32_t)(j[u] & 3), 8u);
+        h[t] += SMALLJ ? __mul24(c[u], sv) : c[u] * sv;
+      }
+  }
+}
+
+template <int RULE, bool SMALLJ, int TPW>
+__global__ void __launch_bounds__(256) k_sweep_pull(const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const int32_t* __restrict__ Jc,
+                                                  const int32_t* __restrict__ class_ptr,
+                                                  const int32_t* __restrict__ order,
+                                                  const uint32_t* __restrict__ thr_g, SweepArgs a,
+                                                  int sweep_idx, int phase) {
+  __shared__ int64_t red[kSweepWaves][TPW][kLanes];
+  __shared__ int32_t fred[kSweepWaves];
+  __shared__ uint32_t thr_s[kThrLds];
+  RunState* st = a.st;
+  if (!st->active) return;
+  const int cur = st->cur;
+  uint32_t* __restrict__ S = cur ? a.S1 : a.S0;
+  int64_t* __restrict__ E = cur ? a.E1 : a.E0;
+  const int cls = order[sweep_idx * a.ncls + phase];
+  const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
+  const int q0 = v0 >> 2;
+  const int nqc = ((v1 + 3) >> 2) - q0;
+  int group, chunk;
+  tile_chunk(a.T / TPW, group, chunk);
+  if (chunk * kQuadsPerBlock >= nqc) return;
+  const uint32_t gs = st->gs + (uint32_t)sweep_idx;
+  const int32_t Xt = (int32_t)st->table_x;
+  const bool thr_lds = 2 * Xt + 1 <= kThrLds;
+  if (thr_lds)
+    for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
+  __syncthreads();
+  const uint32_t* __restrict__ thr = thr_lds ? thr_s : thr_g;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile0 = group * TPW;
+  const uint32_t tstride = (uint32_t)a.nq * kLanes;
+  uint32_t* __restrict__ Srow0 = S + (size_t)tile0 * tstride + lane;
+  int64_t dE[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) dE[t] = 0;
+  int32_t nflip = 0;
+  for (int i = 0; i < kQuadsPerWave; ++i) {
+    const int qi = chunk * kQuadsPerBlock + i * kSweepWaves + wave;
+    if (qi >= nqc) break;
+    const int q = q0 + qi;
+    uint32_t sw[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) sw[t] = Srow0[(uint32_t)t * tstride + (uint32_t)q * kLanes];
+    int32_t h[4][TPW];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int v = 4 * q + k;
+      if (v >= v0 && v < v1) {
+        gather_fields<SMALLJ, TPW>(col, Jc, row_ptr[v], row_ptr[v + 1], Srow0, tstride, h[k]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) h[k][t] = 0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const uint32_t r = (uint32_t)((tile0 + t) * kLanes + lane);
+      const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, a.k0, a.k1);
+      bool dirty = false;
+      uint32_t swt = sw[t];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int v = 4 * q + k;
+        if (v < v0 || v >= v1) continue;
+        const int32_t s = (int32_t)(int8_t)(swt >> (8 * k));
+        const int32_t x = s * h[k][t];
+        const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
+        const uint32_t T = thr[xi + Xt];
+        const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, k) < T);
+        if (flip) {
+          dE[t] += 2 * (int64_t)x;
+          swt ^= (0xFEu << (8 * k));  // +1 (0x01) <-> -1 (0xFF)
+          dirty = true;
+          ++nflip;
+        }
+      }
+      if (dirty) Srow0[(uint32_t)t * tstride + (uint32_t)q * kLanes] = swt;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) red[wave][t][lane] = dE[t];
+  if (a.flip_ctr) {
+    int32_t wf = nflip;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wf += __shfl_xor(wf, o, 64);
+    if (lane == 0) fred[wave] = wf;
+  }
+  __syncthreads();
+  if (wave < TPW) {
+    const int t = wave;
+    const int64_t sum = red[0][t][lane] + red[1][t][lane] + red[2][t][lane] + red[3][t][lane];
+    if (sum != 0)
+      __hip_atomic_fetch_add((unsigned long long*)&E[(tile0 + t) * kLanes + lane],
+                             (unsigned long long)sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (a.flip_ctr && threadIdx.x == 0) {
+    const int64_t f = (int64_t)fred[0] + fred[1] + fred[2] + fred[3];
+    __hip_atomic_fetch_add((unsigned long long*)&a.flip_ctr[blockIdx.x & 255], (unsigned long long)f,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -188,11 +391,6 @@ __global__ void __launch_bounds__(256) k_init_spins(uint32_t* S, int32_t* fam, i
   }
 }
 
-__device__ __forceinline__ int32_t spin_at(const uint32_t* S, int nq, int tile, int v, int lane) {
-  const uint32_t w = S[((size_t)tile * nq + (v >> 2)) * kLanes + lane];
-  return (int32_t)(int8_t)(w >> (8 * (v & 3)));
-}
-
 // h = J s per (tile, vertex) row; accumulates -s h / 2 into E.
 __global__ void __launch_bounds__(256) k_init_fields(const int32_t* row_ptr, const int32_t* col,
                                                      const int32_t* J, const uint32_t* S, int32_t* H,
@@ -207,12 +405,12 @@ __global__ void __launch_bounds__(256) k_init_fields(const int32_t* row_ptr, con
     int64_t h = 0;
     for (int e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
       h += (int64_t)J[e] * spin_at(S, nq, tile, col[e], lane);
-    H[((size_t)tile * np + v) * kLanes + lane] = (int32_t)h;
+    if (H) H[((size_t)tile * np + v) * kLanes + lane] = (int32_t)h;
     acc += h * spin_at(S, nq, tile, v, lane);
   }
   red[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0) {
+  if (wave == 0 && E) {
     const int64_t t = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
     if (t != 0)
       __hip_atomic_fetch_add((unsigned long long*)&E[tile * kLanes + lane],
@@ -660,6 +858,7 @@ __global__ void __launch_bounds__(256) k_rs_gather(GatherArgs a) {
     const int q = qb + qi;
     if (q >= a.nq) break;
     Sd[((size_t)tile * a.nq + q) * kLanes + lane] = Ss[((size_t)pt * a.nq + q) * kLanes + pl];
+    if (!Hs) continue;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
@@ -682,18 +881,41 @@ __global__ void __launch_bounds__(256) k_rs_gather(GatherArgs a) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_cl_select(RunState* st, int64_t* E0, int64_t* E1,
                                                     int32_t R, int32_t* targets) {
+  __shared__ int64_t es[4096];
   if (!st->active || !st->do_cluster) return;
   const int buf = st->cur ^ st->do_resample;
   const int64_t* E = buf ? E1 : E0;
   const int n_top = min(st->cl_n_top, R);
-  for (int r = threadIdx.x; r < R; r += blockDim.x) {
-    const int64_t e = E[r];
-    int rank = 0;
-    for (int q = 0; q < R; ++q) {
-      const int64_t f = E[q];
-      rank += (f < e) || (f == e && q < r);
+  constexpr int kPer = kRsMaxR / 1024;
+  int64_t mine[kPer];
+  int rank[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int r = threadIdx.x + i * 1024;
+    mine[i] = r < R ? E[r] : 0;
+    rank[i] = 0;
+  }
+  for (int base = 0; base < R; base += 4096) {
+    const int len = min(4096, R - base);
+    __syncthreads();
+    for (int q = threadIdx.x; q < len; q += 1024) es[q] = E[base + q];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int r = threadIdx.x + i * 1024;
+      if (r >= R) continue;
+      int c = 0;
+      for (int q = 0; q < len; ++q) {
+        const int64_t f = es[q];
+        c += (f < mine[i]) || (f == mine[i] && base + q < r);
+      }
+      rank[i] += c;
     }
-    if (rank < n_top) targets[rank] = r;
+  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int r = threadIdx.x + i * 1024;
+    if (r < R && rank[i] < n_top) targets[rank[i]] = r;
   }
 }
 
@@ -724,6 +946,7 @@ __global__ void __launch_bounds__(1024) k_cl_mis(ClArgs a) {
   if (i >= min(st->cl_n_top, (int)(gridDim.x / a.trials))) return;
   const int buf = st->cur ^ st->do_resample;
   const int32_t* H = buf ? a.H1 : a.H0;
+  const uint32_t* S = buf ? a.S1 : a.S0;
   uint32_t* key = (uint32_t*)lds;
   uint8_t* state = lds + sizeof(uint32_t) * (size_t)a.np;
   const int r = a.targets[i];
@@ -731,7 +954,16 @@ __global__ void __launch_bounds__(1024) k_cl_mis(ClArgs a) {
   const uint32_t g = st->g_cl;
   for (int v = threadIdx.x; v < a.np; v += blockDim.x) {
     uint8_t s = kOut;
-    if (v < a.n && H[((size_t)tile * a.np + v) * kLanes + lane] == 0) {
+    int32_t h = 1;
+    if (v < a.n) {
+      if (H) {
+        h = H[((size_t)tile * a.np + v) * kLanes + lane];
+      } else {
+        h = 0;
+        for (int e = a.row_ptr[v]; e < a.row_ptr[v + 1]; ++e) h += a.J[e] * spin_at(S, a.nq, tile, a.col[e], lane);
+      }
+    }
+    if (v < a.n && h == 0) {
       s = kUnd;
       key[v] = philox10((uint32_t)v, g, (uint32_t)r, kTagCluster | ((uint32_t)t << 8), a.k0, a.k1).a;
     }
@@ -803,7 +1035,8 @@ __global__ void __launch_bounds__(256) k_cl_apply(ClArgs a, int64_t* flipped) {
     int8_t* sb = (int8_t*)&S[((size_t)tile * a.nq + (v >> 2)) * kLanes + lane] + (v & 3);
     const int32_t snew = -(int32_t)*sb;
     *sb = (int8_t)snew;
-    for (int e = a.row_ptr[v]; e < a.row_ptr[v + 1]; ++e)
+    if (H)
+      for (int e = a.row_ptr[v]; e < a.row_ptr[v + 1]; ++e)
       __hip_atomic_fetch_add(&H[((size_t)tile * a.np + a.col[e]) * kLanes + lane], 2 * a.J[e] * snew,
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ++mine;
@@ -910,6 +1143,20 @@ static hipEvent_t next_event(pamc_instance* I) {
   return I->ev_pool[I->ev_used++];
 }
 
+using PullKernel = void (*)(const int32_t*, const int32_t*, const int32_t*, const int32_t*,
+                           const int32_t*, const uint32_t*, SweepArgs, int, int);
+
+template <int RULE, bool SMALLJ>
+static PullKernel pull_kernel_t(int tpw) {
+  return tpw == 4 ? k_sweep_pull<RULE, SMALLJ, 4>
+                  : (tpw == 2 ? k_sweep_pull<RULE, SMALLJ, 2> : k_sweep_pull<RULE, SMALLJ, 1>);
+}
+
+static PullKernel pull_kernel(const pamc_instance* I) {
+  if (I->rule == 1) return I->small_j ? pull_kernel_t<1, true>(I->tpw) : pull_kernel_t<1, false>(I->tpw);
+  return I->small_j ? pull_kernel_t<0, true>(I->tpw) : pull_kernel_t<0, false>(I->tpw);
+}
+
 // Sweeps of one step (or primitive): thresholds + class orders, then
 // nsweeps x ncls phase launches.
 static hipError_t launch_sweeps(pamc_instance* I, int32_t nsweeps) {
@@ -930,10 +1177,15 @@ static hipError_t launch_sweeps(pamc_instance* I, int32_t nsweeps) {
           e0 = next_event(I);
           hipEventRecord(e0, I->stream);
         }
-        if (I->rule == 1)
-          k_sweep<1><<<grid, 256, 0, I->stream>>>(a, s, p);
-        else
-          k_sweep<0><<<grid, 256, 0, I->stream>>>(a, s, p);
+        if (I->pull) {
+          pull_kernel(I)<<<grid / I->tpw, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J,
+                                                               I->g.class_ptr, I->order, I->thr, a,
+                                                               s, p);
+        } else if (I->rule == 1) {
+          k_sweep<1><<<grid, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J, I->g.class_ptr, I->order, I->thr, a, s, p);
+        } else {
+          k_sweep<0><<<grid, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J, I->g.class_ptr, I->order, I->thr, a, s, p);
+        }
         if (I->prof) {
           e1 = next_event(I);
           hipEventRecord(e1, I->stream);
@@ -966,6 +1218,15 @@ hipError_t launch_init_sparse(pamc_instance* I) {
                                                        I->T);
   k_init_finish<<<(std::max(I->R, I->np) + 255) / 256, 256, 0, I->stream>>>(I->pop.E[0], I->R,
                                                                              I->st, I->best, I->np);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields(pamc_instance* I, int32_t* H) {
+  const int vchunks = (I->n + 63) / 64;
+  // current buffer index is read by the host before this call
+  k_init_fields<<<I->T * vchunks, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J,
+                                                       I->pop.S[I->host_cur], H, nullptr, I->n,
+                                                       I->np, I->nq, I->T);
   return hipGetLastError();
 }
 

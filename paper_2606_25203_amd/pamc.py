@@ -21,10 +21,12 @@ HEATBATH, METROPOLIS = 0, 1
 MAXCUT, ISING = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 FLAG_FIXED_CLASS_ORDER = 1
+FLAG_FIELDS_PUSH = 2
+FLAG_FIELDS_PULL = 4
 
 EXPORTED = [
     "pamc_create_instance_csr", "pamc_create_instance_dense_i8", "pamc_create_instance_dense_random",
-    "pamc_create_instance_max3cut", "pamc_destroy_instance", "pamc_get_info", "pamc_anneal",
+    "pamc_create_instance_max3cut", "pamc_destroy_instance", "pamc_reset_population", "pamc_get_info", "pamc_anneal",
     "pamc_sweep", "pamc_resample", "pamc_cluster_move", "pamc_update_best", "pamc_best",
     "pamc_get_state", "pamc_get_trace", "pamc_max3cut_decode", "pamc_pair_distance",
     "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
@@ -44,7 +46,7 @@ class pamc_config(C.Structure):
 
 class pamc_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("replicas", C.c_int32), ("num_classes", C.c_int32),
-                ("dense", C.c_int32), ("nnz", C.c_int64), ("W", C.c_int64), ("X", C.c_int64),
+                ("dense", C.c_int32), ("pull", C.c_int32), ("nnz", C.c_int64), ("W", C.c_int64), ("X", C.c_int64),
                 ("device_bytes", C.c_int64)]
 
 
@@ -92,6 +94,7 @@ def _load():
         "pamc_create_instance_dense_random": [C.c_int32, C.c_uint64, C.POINTER(pamc_config), PP],
         "pamc_create_instance_max3cut": [C.c_int32, P, P, P, C.POINTER(pamc_config), PP],
         "pamc_get_info": [P, C.POINTER(pamc_info)],
+        "pamc_reset_population": [P, C.c_uint64],
         "pamc_anneal": [P, C.POINTER(pamc_schedule), C.POINTER(pamc_result)],
         "pamc_sweep": [P, C.c_double, C.c_int32],
         "pamc_resample": [P, C.c_double, P],
@@ -171,6 +174,10 @@ def pamc_create_instance_max3cut(n, row_ptr, col, w, *, seed=0, replicas=64, rul
 
 def pamc_destroy_instance(h):
     lib.pamc_destroy_instance(h)
+
+
+def pamc_reset_population(h, seed):
+    _check(lib.pamc_reset_population(h, int(seed)))
 
 
 def pamc_get_info(h) -> pamc_info:
@@ -272,15 +279,19 @@ class Instance:
         self.m3_n = m3_n
 
     @classmethod
-    def csr(cls, g, *, replicas, seed, rule=HEATBATH, objective=MAXCUT, shuffle=True, stream=None):
+    def csr(cls, g, *, replicas, seed, rule=HEATBATH, objective=MAXCUT, shuffle=True, stream=None, fields=None):
+        flags = 0 if shuffle else FLAG_FIXED_CLASS_ORDER
+        flags |= {None: 0, "push": FLAG_FIELDS_PUSH, "pull": FLAG_FIELDS_PULL}[fields]
         h = pamc_create_instance_csr(g.n, g.row_ptr, g.col, g.w, objective, seed=seed, replicas=replicas,
-                                     rule=rule, stream=stream, flags=0 if shuffle else FLAG_FIXED_CLASS_ORDER)
+                                     rule=rule, stream=stream, flags=flags)
         return cls(h, g.n, replicas)
 
     @classmethod
-    def max3cut(cls, g, *, replicas, seed, rule=HEATBATH, shuffle=True, stream=None):
+    def max3cut(cls, g, *, replicas, seed, rule=HEATBATH, shuffle=True, stream=None, fields=None):
+        flags = 0 if shuffle else FLAG_FIXED_CLASS_ORDER
+        flags |= {None: 0, "push": FLAG_FIELDS_PUSH, "pull": FLAG_FIELDS_PULL}[fields]
         h = pamc_create_instance_max3cut(g.n, g.row_ptr, g.col, g.w, seed=seed, replicas=replicas, rule=rule,
-                                         stream=stream, flags=0 if shuffle else FLAG_FIXED_CLASS_ORDER)
+                                         stream=stream, flags=flags)
         return cls(h, 3 * g.n + 1, replicas, m3_n=g.n)
 
     @classmethod
@@ -307,6 +318,9 @@ class Instance:
 
     def info(self):
         return pamc_get_info(self.h)
+
+    def reset(self, seed):
+        pamc_reset_population(self.h, seed)
 
     def anneal(self, sched):
         return pamc_anneal(self.h, sched)

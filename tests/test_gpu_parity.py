@@ -50,14 +50,18 @@ GRAPHS = {
 }
 
 
+FIELDS = ["push", "pull"]
+
+
 @pytest.mark.parametrize("gname", list(GRAPHS))
 @pytest.mark.parametrize("rule", [0, 1])
 @pytest.mark.parametrize("R", [64, 512])
-def test_init_and_sweeps(pamc, gname, rule, R):
+@pytest.mark.parametrize("fields", FIELDS)
+def test_init_and_sweeps(pamc, gname, rule, R, fields):
     g = GRAPHS[gname]()
     seed = 1234 + R
-    say(f"case init/sweeps graph={gname} n={g.n} R={R} rule={rule}")
-    inst = pamc.Instance.csr(g, replicas=R, seed=seed, rule=rule)
+    say(f"case init/sweeps graph={gname} n={g.n} R={R} rule={rule} fields={fields}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=seed, rule=rule, fields=fields)
     o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, seed, rule=rule)
     same_state(inst, o, "init")
     for beta, k in [(0.0, 1), (0.3, 2), (1.7, 3), (5.0, 1)]:
@@ -82,11 +86,12 @@ def test_objective_and_fixed_order(pamc, objective):
 
 
 @pytest.mark.parametrize("delta", [0.0, 0.05, -0.03, 2.0])
-def test_resample(pamc, delta):
+@pytest.mark.parametrize("fields", FIELDS)
+def test_resample(pamc, delta, fields):
     g = synth.random_graph(240, 1500, 6)
     R = 512
-    say(f"case resample delta={delta}")
-    inst = pamc.Instance.csr(g, replicas=R, seed=77)
+    say(f"case resample delta={delta} fields={fields}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=77, fields=fields)
     o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 77)
     inst.sweep(0.7, 2)
     o.sweep(0.7, 2)
@@ -102,11 +107,12 @@ def test_resample(pamc, delta):
 
 
 @pytest.mark.parametrize("n_top,trials", [(1, 1), (8, 4), (64, 3)])
-def test_cluster_move(pamc, n_top, trials):
+@pytest.mark.parametrize("fields", FIELDS)
+def test_cluster_move(pamc, n_top, trials, fields):
     g = synth.torus(20, 16, 9)
     R = 128
-    say(f"case cluster n_top={n_top} trials={trials}")
-    inst = pamc.Instance.csr(g, replicas=R, seed=3)
+    say(f"case cluster n_top={n_top} trials={trials} fields={fields}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=3, fields=fields)
     o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 3)
     inst.sweep(2.0, 6)
     o.sweep(2.0, 6)
@@ -157,21 +163,23 @@ def compare_anneal(pamc, inst, o, sched_kw):
 
 
 @pytest.mark.parametrize("rule", [0, 1])
-def test_plain_anneal_c1_full(pamc, rule):
+@pytest.mark.parametrize("fields", FIELDS)
+def test_plain_anneal_c1_full(pamc, rule, fields):
     """Plain PAMC on the full sparse Max-Cut configuration: n = 800, 19,176
     edges, R = 256, 50 steps linear 0.1 -> 3.0, 5 sweeps per step."""
     g = synth.config_c1_graph()
-    say(f"case c1 full rule={rule}")
-    inst = pamc.Instance.csr(g, replicas=256, seed=2024, rule=rule)
+    say(f"case c1 full rule={rule} fields={fields}")
+    inst = pamc.Instance.csr(g, replicas=256, seed=2024, rule=rule, fields=fields)
     o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 256, 2024, rule=rule)
     compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=2.9 / 49, steps=50, sweeps=5))
     inst.close()
 
 
-def test_augmented_anneal_torus(pamc):
+@pytest.mark.parametrize("fields", FIELDS)
+def test_augmented_anneal_torus(pamc, fields):
     g = synth.torus(24, 20, 5)
-    say("case augmented torus")
-    inst = pamc.Instance.csr(g, replicas=256, seed=99)
+    say(f"case augmented torus fields={fields}")
+    inst = pamc.Instance.csr(g, replicas=256, seed=99, fields=fields)
     o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 256, 99)
     res, ores = compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.02, steps=260, sweeps=3, augmented=1,
                                                    z_rst=120, n_top=8, mis_trials=4, tau=25))
@@ -202,11 +210,12 @@ def test_sa_mode_no_resampling(pamc):
     inst.close()
 
 
-def test_max3cut_anneal_and_decode(pamc):
+@pytest.mark.parametrize("fields", FIELDS)
+def test_max3cut_anneal_and_decode(pamc, fields):
     g = synth.random_graph(60, 180, 7)
     R = 128
-    say("case max3cut")
-    inst = pamc.Instance.max3cut(g, replicas=R, seed=21)
+    say(f"case max3cut fields={fields}")
+    inst = pamc.Instance.max3cut(g, replicas=R, seed=21, fields=fields)
     o = oracle.Oracle.max3cut(g.n, g.row_ptr, g.col, g.w, R, 21)
     compare_anneal(pamc, inst, o, dict(beta0=0.05, dbeta=0.03, steps=60, sweeps=4, augmented=1, z_rst=0,
                                        n_top=4))
@@ -246,14 +255,15 @@ def test_invalid_inputs(pamc):
         pamc.pamc_create_instance_csr(g.n, g.row_ptr, col, g.w, replicas=64)
 
 
-def test_c2_full_size_subset_parity_and_invariants(pamc):
+@pytest.mark.parametrize("fields", FIELDS)
+def test_c2_full_size_subset_parity_and_invariants(pamc, fields):
     """Torus 100 x 200 (n = 20,000) at R = 4096: sweeps of replica r depend
     only on (seed, r), so replicas 0..63 must equal an oracle run with
     R = 64.  Then one augmented step with resampling at full size, checked by
     invariants (h = J s, E = -1/2 s.h) on sampled replicas."""
     g = synth.config_c2_graph()
-    say("case c2 full size")
-    inst = pamc.Instance.csr(g, replicas=4096, seed=31)
+    say(f"case c2 full size fields={fields}")
+    inst = pamc.Instance.csr(g, replicas=4096, seed=31, fields=fields)
     o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 64, 31)
     inst.sweep(0.4, 2)
     o.sweep(0.4, 2)
