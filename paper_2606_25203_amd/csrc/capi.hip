@@ -338,6 +338,47 @@ pamc_status read_state(pamc_instance* I, pamc::RunState* out) {
   return PAMC_OK;
 }
 
+// Dense instance buffers (couplings uploaded or generated by the caller of
+// this helper), then the initial population.
+pamc_status build_dense_common(pamc_instance* I, int32_t n) {
+  I->dense = 1;
+  I->n = n;
+  I->dn_pad = (n + 63) & ~63;
+  I->np = I->dn_pad;
+  I->nq = I->dn_pad / 4;
+  I->ncls = 0;
+  I->to_internal.resize(n);
+  I->to_input.resize(n);
+  for (int32_t v = 0; v < n; ++v) I->to_internal[v] = I->to_input[v] = v;
+  const size_t np = (size_t)I->dn_pad;
+  HIP_TRY(dalloc(I, &I->Jd, np * np), "alloc couplings");
+  HIP_TRY(dalloc(I, &I->Sd, (size_t)I->R * np), "alloc population");
+  HIP_TRY(dalloc(I, &I->Sd2, (size_t)I->R * np), "alloc population");
+  for (int b = 0; b < 2; ++b) {
+    HIP_TRY(dalloc(I, &I->pop.E[b], I->R), "alloc population");
+    HIP_TRY(dalloc(I, &I->pop.fam[b], I->R), "alloc population");
+  }
+  HIP_TRY(dalloc(I, &I->best, np), "alloc");
+  HIP_TRY(dalloc(I, &I->st, 1), "alloc");
+  HIP_TRY(dalloc(I, &I->rs_P, I->R), "alloc");
+  HIP_TRY(dalloc(I, &I->rs_parent, I->R), "alloc");
+  HIP_TRY(dalloc(I, &I->flip_ctr, 512), "alloc");
+  HIP_TRY(dalloc(I, &I->Gd, (size_t)pamc::dense_num_partials(I->dn_pad) * 64 * I->R), "alloc fields");
+  I->order_cap = 1;
+  HIP_TRY(dalloc(I, &I->order, 1), "alloc");
+  HIP_TRY(hipMemsetAsync(I->flip_ctr, 0, sizeof(int64_t) * 512, I->stream), "memset");
+  HIP_TRY(hipMemsetAsync(I->st, 0, sizeof(pamc::RunState), I->stream), "memset");
+  HIP_TRY(hipMemsetAsync(I->Sd2, 0, (size_t)I->R * np, I->stream), "memset");
+  return PAMC_OK;
+}
+
+pamc_status finish_dense(pamc_instance* I) {
+  HIP_TRY(dalloc(I, &I->thr, 2 * I->X + 1), "alloc");
+  HIP_TRY(pamc::launch_init_dense(I), "init kernels");
+  HIP_TRY(hipStreamSynchronize(I->stream), "init");
+  return PAMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -443,6 +484,99 @@ pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, cons
         (nnz && hipMemcpy(I->m3_w, w, sizeof(int32_t) * nnz, hipMemcpyHostToDevice)))
       st = fail(PAMC_ERR_OUT_OF_MEMORY, "Max-3-Cut buffers");
   }
+  if (st) {
+    free_instance(I);
+    return st;
+  }
+  *out = I;
+  return PAMC_OK;
+}
+
+pamc_status pamc_create_instance_dense_i8(int32_t n, const int8_t* J, int64_t ld, pamc_mem where,
+                                          int32_t objective, const pamc_config* cfg,
+                                          pamc_instance** out) {
+  if (!out) return fail(PAMC_ERR_INVALID_ARG, "NULL out");
+  *out = nullptr;
+  pamc_status st = check_cfg(cfg);
+  if (st) return st;
+  if (n <= 0 || !J || ld < n) return fail(PAMC_ERR_INVALID_ARG, "bad dense matrix arguments");
+  if (objective != PAMC_OBJ_MAXCUT && objective != PAMC_OBJ_ISING)
+    return fail(PAMC_ERR_INVALID_ARG, "unknown objective");
+  std::vector<int8_t> hj;
+  const int8_t* src = J;
+  if (where == PAMC_MEM_DEVICE) {
+    hj.resize((size_t)n * ld);
+    if (hipMemcpy(hj.data(), J, hj.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(PAMC_ERR_INVALID_ARG, "cannot read device matrix");
+    src = hj.data();
+  } else if (where != PAMC_MEM_HOST) {
+    return fail(PAMC_ERR_INVALID_ARG, "bad memory kind");
+  }
+  int64_t W = 0, X = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (src[(size_t)i * ld + i] != 0) return fail(PAMC_ERR_INVALID_ARG, "nonzero diagonal");
+    int64_t ab = 0;
+    for (int32_t j = 0; j < n; ++j) {
+      const int8_t v = src[(size_t)i * ld + j];
+      if (v == -128) return fail(PAMC_ERR_INVALID_ARG, "entries must lie in [-127, 127]");
+      if (v != src[(size_t)j * ld + i]) return fail(PAMC_ERR_INVALID_ARG, "matrix is not symmetric");
+      ab += v < 0 ? -v : v;
+      if (j > i) W += objective == PAMC_OBJ_MAXCUT ? v : -v;
+    }
+    X = std::max(X, ab);
+  }
+  if (2 * X >= INT32_MAX) return fail(PAMC_ERR_INVALID_ARG, "local field range exceeds int32");
+  pamc_instance* I = new (std::nothrow) pamc_instance();
+  if (!I) return fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
+  st = open_device(I, cfg);
+  if (!st) st = build_dense_common(I, n);
+  if (!st) {
+    I->W = W;
+    I->X = X;
+    const size_t np = (size_t)I->dn_pad;
+    std::vector<int8_t> row(np);
+    hipError_t e = hipMemsetAsync(I->Jd, 0, np * np, I->stream);
+    for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+      std::fill(row.begin(), row.end(), 0);
+      for (int32_t j = 0; j < n; ++j) {
+        const int8_t v = src[(size_t)i * ld + j];
+        row[j] = objective == PAMC_OBJ_MAXCUT ? (int8_t)-v : v;
+      }
+      e = hipMemcpy(I->Jd + (size_t)i * np, row.data(), np, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) st = dev_fail(e, "upload couplings");
+  }
+  if (!st) st = finish_dense(I);
+  if (st) {
+    free_instance(I);
+    return st;
+  }
+  *out = I;
+  return PAMC_OK;
+}
+
+pamc_status pamc_create_instance_dense_random(int32_t n, uint64_t graph_seed, const pamc_config* cfg,
+                                              pamc_instance** out) {
+  if (!out) return fail(PAMC_ERR_INVALID_ARG, "NULL out");
+  *out = nullptr;
+  pamc_status st = check_cfg(cfg);
+  if (st) return st;
+  if (n <= 1) return fail(PAMC_ERR_INVALID_ARG, "n must be at least 2");
+  if (n > 400000) return fail(PAMC_ERR_UNSUPPORTED, "n too large for one device");
+  pamc_instance* I = new (std::nothrow) pamc_instance();
+  if (!I) return fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
+  st = open_device(I, cfg);
+  if (!st) st = build_dense_common(I, n);
+  if (!st) {
+    I->X = n - 1;
+    hipError_t e = pamc::launch_dense_generate(I, graph_seed);
+    int64_t W = 0;
+    if (e == hipSuccess) e = hipStreamSynchronize(I->stream);
+    if (e == hipSuccess) e = hipMemcpy(&W, I->flip_ctr + 400, sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) st = dev_fail(e, "generate couplings");
+    I->W = W;
+  }
+  if (!st) st = finish_dense(I);
   if (st) {
     free_instance(I);
     return st;
@@ -559,12 +693,31 @@ pamc_status pamc_best(pamc_instance* I, int64_t* cut, int64_t* energy, int8_t* s
 pamc_status pamc_get_state(pamc_instance* I, int8_t* spins, int32_t* fields, int64_t* energies,
                            int32_t* family) {
   if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
-  if (I->dense) return fail(PAMC_ERR_UNSUPPORTED, "use the dense state reader");
   hipSetDevice(I->device);
   pamc::RunState s;
   pamc_status r = read_state(I, &s);
   if (r) return r;
   const int b = s.cur;
+  if (I->dense) {
+    const size_t np = (size_t)I->dn_pad;
+    if (spins) {
+      std::vector<int8_t> S((size_t)I->R * np);
+      HIP_TRY(hipMemcpy(S.data(), b ? I->Sd2 : I->Sd, S.size(), hipMemcpyDeviceToHost), "readback");
+      for (int32_t rr = 0; rr < I->R; ++rr) memcpy(spins + (size_t)rr * I->n, &S[(size_t)rr * np], I->n);
+    }
+    if (fields) {
+      if (!I->H_scratch) HIP_TRY(dalloc(I, &I->H_scratch, (size_t)I->R * np), "alloc fields");
+      HIP_TRY(pamc::launch_dense_fields(I, I->H_scratch), "fields");
+      std::vector<int32_t> H((size_t)I->R * np);
+      HIP_TRY(hipStreamSynchronize(I->stream), "fields");
+      HIP_TRY(hipMemcpy(H.data(), I->H_scratch, H.size() * 4, hipMemcpyDeviceToHost), "readback");
+      for (int32_t rr = 0; rr < I->R; ++rr)
+        memcpy(fields + (size_t)rr * I->n, &H[(size_t)rr * np], sizeof(int32_t) * I->n);
+    }
+    if (energies) HIP_TRY(hipMemcpy(energies, I->pop.E[b], sizeof(int64_t) * I->R, hipMemcpyDeviceToHost), "readback");
+    if (family) HIP_TRY(hipMemcpy(family, I->pop.fam[b], sizeof(int32_t) * I->R, hipMemcpyDeviceToHost), "readback");
+    return PAMC_OK;
+  }
   const int n = I->n, R = I->R;
   if (spins) {
     std::vector<uint32_t> S((size_t)I->T * I->nq * 64);
@@ -603,6 +756,8 @@ pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_resul
   if (sched->augmented &&
       (sched->win_long > pamc::kHistCap || sched->win_short > sched->win_long || sched->win_short <= 0))
     return fail(PAMC_ERR_INVALID_ARG, "history windows must satisfy 0 < short <= long <= 64");
+  if (I->dense && sched->augmented)
+    return fail(PAMC_ERR_UNSUPPORTED, "the augmented controller's cluster moves need a sparse instance");
   hipSetDevice(I->device);
   Schedule s = to_sched(sched);
   if (!s.augmented) {

@@ -1,27 +1,407 @@
-// dense.hip -- dense (fully connected) instances: placeholder until the
-// int8 matrix-core field kernels land.
+// dense.hip -- fully connected instances (Sec. "Scalability on a Large-Scale
+// Ising Problem"): int8 couplings J[n][n] in HBM, spins visited in the fixed
+// order 0..n-1.
+//
+// A sweep runs over blocks of kDB = 64 consecutive spins.  For block b the
+// local fields of Eq. 3 against the *current* spins, G = J[blk, :] . S, come
+// from int8 x int8 -> int32 matrix-core products (exact: |h| <= 127 n <
+// 2^31), split over the K (spin) dimension into partial sums.  A sequential
+// kernel (one wavefront per 64 replicas) then visits the block's spins in
+// order: h_k = sum of the partials + sum_{k' < k in block} J_kk' d_k', where
+// d_k' = 2 s_k'(new) if spin k' flipped and 0 otherwise (packed int8, summed
+// four at a time with dot4), applies the same threshold test as the sparse
+// path and updates spins and energies.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
 
 #include "../../include/pamc.h"
 #include "instance.hpp"
+#include "pamc_device.hpp"
 
 namespace pamc {
-hipError_t launch_dense_generate(pamc_instance*, uint64_t) { return hipErrorNotSupported; }
-hipError_t launch_init_dense(pamc_instance*) { return hipErrorNotSupported; }
-hipError_t launch_dense_step(pamc_instance*, const Schedule&, int32_t) { return hipErrorNotSupported; }
-hipError_t launch_dense_prim_sweep(pamc_instance*, double, int32_t) { return hipErrorNotSupported; }
-hipError_t launch_dense_prim_resample(pamc_instance*, double) { return hipErrorNotSupported; }
-hipError_t launch_dense_prim_update_best(pamc_instance*) { return hipErrorNotSupported; }
-}  // namespace pamc
 
-extern "C" {
-pamc_status pamc_create_instance_dense_i8(int32_t, const int8_t*, int64_t, pamc_mem, int32_t,
-                                          const pamc_config*, pamc_instance** out) {
-  if (out) *out = nullptr;
-  return PAMC_ERR_UNSUPPORTED;
+namespace {
+
+constexpr int kDB = 64;          // spins per sequential block
+constexpr int kKSlice = 2048;    // K columns per partial-sum work-group
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// J_ij = J_ji = +-1 from the low bit of Philox(key = seed; (i, j, 0, DENSE))
+// word 0 for i < j; zero diagonal and zero padding.  Also accumulates
+// W = sum_{i<j} (-J_ij).
+__global__ void __launch_bounds__(256) k_dense_generate(int8_t* J, int32_t n, int32_t np, uint32_t k0,
+                                                        uint32_t k1, int64_t* W) {
+  const int64_t total = (int64_t)np * np;
+  int64_t wsum = 0;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / np), j = (int)(idx % np);
+    int8_t v = 0;
+    if (i < n && j < n && i != j) {
+      const int a = i < j ? i : j, b = i < j ? j : i;
+      v = (philox10((uint32_t)a, (uint32_t)b, 0u, kTagDense, k0, k1).a & 1u) ? 1 : -1;
+      if (i < j) wsum -= v;
+    }
+    J[idx] = v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, 64);
+  if ((threadIdx.x & 63) == 0 && wsum)
+    __hip_atomic_fetch_add((unsigned long long*)W, (unsigned long long)wsum, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
-pamc_status pamc_create_instance_dense_random(int32_t, uint64_t, const pamc_config*, pamc_instance** out) {
-  if (out) *out = nullptr;
-  return PAMC_ERR_UNSUPPORTED;
+
+// Spins: +1 iff word (v & 3) of Philox(v >> 2, 0, r, INIT) < 2^31 (the same
+// stream as sparse instances); padding columns are 0.
+__global__ void __launch_bounds__(256) k_dense_init_spins(int8_t* S, int32_t* fam, int32_t n,
+                                                          int32_t np, int32_t R, uint32_t k0,
+                                                          uint32_t k1) {
+  const int64_t total = (int64_t)R * (np / 4);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(i / (np / 4));
+    const int q = (int)(i % (np / 4));
+    const u32x4 w = philox10((uint32_t)q, 0u, (uint32_t)r, kTagInit, k0, k1);
+    uint32_t word = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int v = 4 * q + k;
+      const int8_t s = v < n ? (pick(w, k) < 0x80000000u ? (int8_t)1 : (int8_t)-1) : (int8_t)0;
+      word |= (uint32_t)(uint8_t)s << (8 * k);
+    }
+    reinterpret_cast<uint32_t*>(S)[i] = word;
+    if (q == 0) fam[r] = r;
+  }
 }
+
+// Gpart[p][m][r] = sum_{k in slice p} J[row0 + m][k] S[r][k] for the block's
+// kDB rows and a 64-replica tile.  Work-group = 4 waves; wave w owns rows
+// 16w..16w+15 against the tile's 64 replicas (four 16 x 16 results) with
+// v_mfma_i32_16x16x64_i8.  Operand fragments: lane l supplies 16 consecutive
+// K bytes at 16*(l/16) of row (A) / replica (B) l % 16; the result holds rows
+// 4*(l/16)..+3 of column l % 16.
+__global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J,
+                                                    const int8_t* __restrict__ S0,
+                                                    const int8_t* __restrict__ S1,
+                                                    int32_t* __restrict__ Gpart, const RunState* st,
+                                                    int32_t row0, int32_t np, int32_t R,
+                                                    int32_t use_state) {
+  if (use_state == 1 && !st->active) return;
+  const int8_t* __restrict__ S = (use_state ? st->cur : 0) ? S1 : S0;
+  const int tile = blockIdx.x % (R / 64);
+  const int p = blockIdx.x / (R / 64);
+  const int k_beg = p * kKSlice, k_end = min(np, k_beg + kKSlice);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int8_t* arow = J + (size_t)(row0 + 16 * wave + (lane & 15)) * np + 16 * (lane >> 4);
+  const int8_t* brow = S + (size_t)(tile * 64 + (lane & 15)) * np + 16 * (lane >> 4);
+  v4i acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int k0 = k_beg; k0 < k_end; k0 += 64) {
+    const v4i a = *reinterpret_cast<const v4i*>(arow + k0);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const v4i b = *reinterpret_cast<const v4i*>(brow + (size_t)nt * 16 * np + k0);
+      acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[nt], 0, 0, 0);
+    }
+  }
+  int32_t* out = Gpart + (size_t)p * kDB * R;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      out[(size_t)(16 * wave + 4 * (lane >> 4) + j) * R + tile * 64 + nt * 16 + (lane & 15)] = acc[nt][j];
 }
+
+// Sequential visit of the block's spins for one 64-replica tile (one wave).
+struct SeqArgs {
+  const int8_t* J;
+  int8_t* S0;
+  int8_t* S1;
+  int64_t* E0;
+  int64_t* E1;
+  const int32_t* Gpart;
+  const uint32_t* thr;
+  RunState* st;
+  int32_t row0, n, np, R, P;
+  uint32_t k0, k1;
+  int64_t* flip_ctr;
+};
+
+template <int RULE>
+__global__ void __launch_bounds__(64) k_dense_seq(SeqArgs a, int32_t sweep_idx) {
+  __shared__ uint32_t jd[kDB][kDB / 4];  // J[row0 + k][row0 + 4g .. 4g+3], packed int8
+  RunState* st = a.st;
+  if (!st->active) return;
+  const int cur = st->cur;
+  int8_t* S = cur ? a.S1 : a.S0;
+  int64_t* E = cur ? a.E1 : a.E0;
+  const int lane = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int r = tile * 64 + lane;
+  for (int i = lane; i < kDB * kDB / 4; i += 64) {
+    const int k = i / (kDB / 4), g = i % (kDB / 4);
+    jd[k][g] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(a.row0 + k) * a.np + a.row0 + 4 * g);
+  }
+  __syncthreads();
+  const uint32_t gs = st->gs + (uint32_t)sweep_idx;
+  const int32_t Xt = (int32_t)st->table_x;
+  uint32_t d[kDB / 4];  // packed int8 d_k' of this lane's replica
+#pragma unroll
+  for (int g = 0; g < kDB / 4; ++g) d[g] = 0;
+  uint32_t* srow = reinterpret_cast<uint32_t*>(S + (size_t)r * a.np + a.row0);
+  int64_t dE = 0;
+  int32_t nflip = 0;
+#pragma unroll
+  for (int g = 0; g < kDB / 4; ++g) {
+    const int vq = a.row0 + 4 * g;
+    if (vq >= a.n) break;
+    const u32x4 rnd = philox10((uint32_t)(vq >> 2), gs, (uint32_t)r, kTagSweep, a.k0, a.k1);
+    uint32_t sw = srow[g];
+    uint32_t dg = 0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * g + kk;
+      const int v = a.row0 + k;
+      if (v >= a.n) break;
+      int32_t h = 0;
+      for (int p = 0; p < a.P; ++p) h += a.Gpart[((size_t)p * kDB + k) * a.R + r];
+#pragma unroll
+      for (int g2 = 0; g2 < g; ++g2) h = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)d[g2], h, false);
+      h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, h, false);
+      const int32_t s = (int32_t)(int8_t)(sw >> (8 * kk));
+      const int32_t x = s * h;
+      const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
+      const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, kk) < a.thr[xi + Xt]);
+      if (flip) {
+        dE += 2 * (int64_t)x;
+        sw ^= (0xFEu << (8 * kk));
+        dg |= (uint32_t)(uint8_t)(int8_t)(-2 * s) << (8 * kk);
+        ++nflip;
+      }
+    }
+    d[g] = dg;
+    srow[g] = sw;
+  }
+  if (dE != 0)
+    __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)dE, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  if (a.flip_ctr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nflip += __shfl_xor(nflip, o, 64);
+    if (lane == 0)
+      __hip_atomic_fetch_add((unsigned long long*)&a.flip_ctr[blockIdx.x & 255],
+                             (unsigned long long)nflip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Energy of the population from block fields: E_r += sum_k s_rk G_rk (the
+// caller negates and halves at the end).
+__global__ void __launch_bounds__(64) k_dense_energy_block(const int8_t* S, const int32_t* Gpart,
+                                                           int64_t* E, int32_t row0, int32_t n,
+                                                           int32_t np, int32_t R, int32_t P) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  int64_t acc = 0;
+  for (int k = 0; k < kDB && row0 + k < n; ++k) {
+    int32_t h = 0;
+    for (int p = 0; p < P; ++p) h += Gpart[((size_t)p * kDB + k) * R + r];
+    acc += (int64_t)h * S[(size_t)r * np + row0 + k];
+  }
+  if (acc) __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)acc, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_dense_init_finish(int64_t* E, int32_t R, RunState* st, int8_t* best, int32_t np) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < R) E[i] = -(E[i] / 2);
+  for (int v = i; v < np; v += gridDim.x * blockDim.x) best[v] = 1;
+  if (i == 0) {
+    st->mstar = 0;
+    st->cur = 0;
+    st->gs = st->g_rs = st->g_cl = 0;
+    st->stopped = 0;
+    st->active = 0;
+  }
+}
+
+// Resampling gather for the replica-major layout.
+__global__ void __launch_bounds__(256) k_dense_gather(const RunState* st, int8_t* S0, int8_t* S1,
+                                                      int64_t* E0, int64_t* E1, int32_t* F0, int32_t* F1,
+                                                      const int32_t* parent, int32_t np, int32_t R) {
+  if (!st->active || !st->do_resample) return;
+  const int cur = st->cur;
+  const uint32_t* Ss = reinterpret_cast<const uint32_t*>(cur ? S1 : S0);
+  uint32_t* Sd = reinterpret_cast<uint32_t*>(cur ? S0 : S1);
+  const int c = blockIdx.y;
+  const int p = parent[c];
+  const int words = np / 4;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
+    Sd[(size_t)c * words + i] = Ss[(size_t)p * words + i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    (cur ? E0 : E1)[c] = (cur ? E1 : E0)[p];
+    (cur ? F0 : F1)[c] = (cur ? F1 : F0)[p];
+  }
+}
+
+int32_t num_partials(int32_t np) { return (np + kKSlice - 1) / kKSlice; }
+
+// H[r][row0 + k] = sum of the block's partial fields (snapshots only).
+__global__ void __launch_bounds__(64) k_dense_collect(const int32_t* Gpart, int32_t* H, int32_t row0,
+                                                      int32_t n, int32_t np, int32_t R, int32_t P) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  for (int k = 0; k < kDB && row0 + k < n; ++k) {
+    int32_t h = 0;
+    for (int p = 0; p < P; ++p) h += Gpart[((size_t)p * kDB + k) * R + r];
+    H[(size_t)r * np + row0 + k] = h;
+  }
+}
+
+}  // namespace
+
+int32_t dense_num_partials(int32_t np) { return num_partials(np); }
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline uint32_t key0(const pamc_instance* I) { return (uint32_t)I->seed; }
+static inline uint32_t key1(const pamc_instance* I) { return (uint32_t)(I->seed >> 32); }
+
+hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed) {
+  int64_t* W = I->flip_ctr + 400;
+  hipMemsetAsync(W, 0, sizeof(int64_t), I->stream);
+  const int64_t total = (int64_t)I->dn_pad * I->dn_pad;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 1 << 16);
+  k_dense_generate<<<grid, 256, 0, I->stream>>>(I->Jd, I->n, I->dn_pad, (uint32_t)graph_seed,
+                                                (uint32_t)(graph_seed >> 32), W);
+  return hipGetLastError();
+}
+
+static hipError_t dense_full_energy(pamc_instance* I, int buf) {
+  const int P = num_partials(I->dn_pad);
+  const int T = I->R / 64;
+  hipMemsetAsync(I->pop.E[buf], 0, sizeof(int64_t) * I->R, I->stream);
+  for (int row0 = 0; row0 < I->n; row0 += kDB) {
+    k_dense_gemm<<<T * P, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, I->dn_pad,
+                                               I->R, 0);
+    k_dense_energy_block<<<T, 64, 0, I->stream>>>(buf ? I->Sd2 : I->Sd, I->Gd, I->pop.E[buf], row0,
+                                                  I->n, I->dn_pad, I->R, P);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_dense(pamc_instance* I) {
+  const int64_t total = (int64_t)I->R * (I->dn_pad / 4);
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65535);
+  k_dense_init_spins<<<grid, 256, 0, I->stream>>>(I->Sd, I->pop.fam[0], I->n, I->dn_pad, I->R, key0(I),
+                                                  key1(I));
+  dense_full_energy(I, 0);
+  k_dense_init_finish<<<(std::max(I->R, I->dn_pad) + 255) / 256, 256, 0, I->stream>>>(
+      I->pop.E[0], I->R, I->st, I->best, I->dn_pad);
+  return hipGetLastError();
+}
+
+static hipError_t dense_sweeps(pamc_instance* I, int32_t nsweeps) {
+  const int P = num_partials(I->dn_pad);
+  const int T = I->R / 64;
+  SeqArgs a;
+  a.J = I->Jd;
+  a.S0 = I->Sd;
+  a.S1 = I->Sd2;
+  a.E0 = I->pop.E[0];
+  a.E1 = I->pop.E[1];
+  a.Gpart = I->Gd;
+  a.thr = I->thr;
+  a.st = I->st;
+  a.n = I->n;
+  a.np = I->dn_pad;
+  a.R = I->R;
+  a.P = P;
+  a.k0 = key0(I);
+  a.k1 = key1(I);
+  a.flip_ctr = I->prof ? I->flip_ctr : nullptr;
+  ctl_thresholds(I);
+  for (int s = 0; s < nsweeps; ++s) {
+    for (int row0 = 0; row0 < I->n; row0 += kDB) {
+      hipEvent_t e0 = nullptr;
+      if (I->prof) {
+        e0 = ctl_event(I);
+        hipEventRecord(e0, I->stream);
+      }
+      k_dense_gemm<<<T * P, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, I->dn_pad,
+                                                 I->R, 1);
+      if (I->prof) {
+        hipEvent_t e1 = ctl_event(I);
+        hipEventRecord(e1, I->stream);
+        I->prof_launches += 1;
+      }
+      a.row0 = row0;
+      if (I->rule == 1)
+        k_dense_seq<1><<<T, 64, 0, I->stream>>>(a, s);
+      else
+        k_dense_seq<0><<<T, 64, 0, I->stream>>>(a, s);
+    }
+    if (I->prof) I->prof_attempts += (int64_t)I->n * I->R;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_step(pamc_instance* I, const Schedule& s, int32_t step) {
+  ctl_step_begin(I, step);
+  if (s.resample) {
+    ctl_resample_select(I);
+    k_dense_gather<<<dim3(std::max(1, std::min(64, I->dn_pad / 1024)), I->R), 256, 0, I->stream>>>(
+        I->st, I->Sd, I->Sd2, I->pop.E[0], I->pop.E[1], I->pop.fam[0], I->pop.fam[1], I->rs_parent,
+        I->dn_pad, I->R);
+  }
+  ctl_commit(I, 1);
+  hipError_t e = dense_sweeps(I, s.sweeps);
+  if (e != hipSuccess) return e;
+  ctl_step_end(I, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_prim_sweep(pamc_instance* I, double beta, int32_t nsweeps) {
+  ctl_prim_set(I, 0, beta);
+  hipError_t e = dense_sweeps(I, nsweeps);
+  if (e != hipSuccess) return e;
+  ctl_advance(I, nsweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_prim_resample(pamc_instance* I, double delta) {
+  ctl_prim_set(I, 1, delta);
+  ctl_resample_select(I);
+  k_dense_gather<<<dim3(std::max(1, std::min(64, I->dn_pad / 1024)), I->R), 256, 0, I->stream>>>(
+      I->st, I->Sd, I->Sd2, I->pop.E[0], I->pop.E[1], I->pop.fam[0], I->pop.fam[1], I->rs_parent,
+      I->dn_pad, I->R);
+  ctl_commit(I, 0);
+  ctl_deactivate(I);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_prim_update_best(pamc_instance* I) {
+  ctl_prim_set(I, 0, 0.0);
+  ctl_step_end(I, 0);
+  ctl_deactivate(I);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor) {
+  // fields H[r][v] (replica-major) of the current population, for snapshots
+  const int P = num_partials(I->dn_pad);
+  const int T = I->R / 64;
+  for (int row0 = 0; row0 < I->n; row0 += kDB) {
+    k_dense_gemm<<<T * P, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, I->dn_pad,
+                                               I->R, 2);
+    k_dense_collect<<<T, 64, 0, I->stream>>>(I->Gd, H_rmajor, row0, I->n, I->dn_pad, I->R, P);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pamc

@@ -122,7 +122,20 @@ hipError_t launch_fields(pamc_instance* I, int32_t* H);
 int32_t cluster_max_n();
 hipError_t prepare_cluster_lds();
 
+// controller pieces (sparse.hip) shared with the dense path
+hipError_t ctl_step_begin(pamc_instance* I, int32_t step);
+hipError_t ctl_resample_select(pamc_instance* I);
+hipError_t ctl_commit(pamc_instance* I, int32_t in_run);
+hipError_t ctl_thresholds(pamc_instance* I);
+hipError_t ctl_step_end(pamc_instance* I, int32_t in_run);
+hipError_t ctl_prim_set(pamc_instance* I, int32_t kind, double value);
+hipError_t ctl_advance(pamc_instance* I, int32_t nsweeps);
+hipError_t ctl_deactivate(pamc_instance* I);
+hipEvent_t ctl_event(pamc_instance* I);
+
 // dense path launchers (dense.hip)
+int32_t dense_num_partials(int32_t np);
+hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor);
 hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed);
 hipError_t launch_init_dense(pamc_instance* I);
 hipError_t launch_dense_step(pamc_instance* I, const Schedule& s, int32_t step);

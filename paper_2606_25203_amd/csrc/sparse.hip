@@ -579,6 +579,9 @@ struct StepEndArgs {
   uint64_t* tr_time;
   int32_t tr_cap;
   int32_t ev_bits_extra;
+  const int8_t* D0;  // dense instances: replica-major spins [R][np]
+  const int8_t* D1;
+  int32_t dense;
 };
 
 __device__ int32_t distinct_tail(const int64_t* h, int len, int w) {
@@ -626,10 +629,15 @@ __global__ void __launch_bounds__(1024) k_step_end(StepEndArgs a, int32_t in_run
   if (threadIdx.x == 0) improved = m > st->mstar;
   __syncthreads();
   if (improved) {
-    const int tile = slot >> 6, lane = slot & 63;
-    for (int v = threadIdx.x; v < a.np; v += blockDim.x) {
-      const uint32_t w = S[((size_t)tile * a.nq + (v >> 2)) * kLanes + lane];
-      a.best[v] = (int8_t)(w >> (8 * (v & 3)));
+    if (a.dense) {
+      const int8_t* D = (cur ? a.D1 : a.D0) + (size_t)slot * a.np;
+      for (int v = threadIdx.x; v < a.np; v += blockDim.x) a.best[v] = D[v];
+    } else {
+      const int tile = slot >> 6, lane = slot & 63;
+      for (int v = threadIdx.x; v < a.np; v += blockDim.x) {
+        const uint32_t w = S[((size_t)tile * a.nq + (v >> 2)) * kLanes + lane];
+        a.best[v] = (int8_t)(w >> (8 * (v & 3)));
+      }
     }
   }
   if (threadIdx.x != 0) return;
@@ -1312,6 +1320,9 @@ static StepEndArgs step_end_args(pamc_instance* I) {
   e.tr_time = I->tr_time;
   e.tr_cap = I->tr_cap;
   e.ev_bits_extra = 0;
+  e.D0 = I->Sd;
+  e.D1 = I->Sd2;
+  e.dense = I->dense;
   return e;
 }
 
@@ -1375,6 +1386,50 @@ hipError_t launch_pair_distance(pamc_instance* I, double* out_dev) {
                                                out_dev);
   return hipGetLastError();
 }
+
+// Controller pieces shared with the dense path.
+hipError_t ctl_step_begin(pamc_instance* I, int32_t step) {
+  k_step_begin<<<1, 1, 0, I->stream>>>(I->st, step, I->X);
+  return hipGetLastError();
+}
+hipError_t ctl_resample_select(pamc_instance* I) {
+  RsArgs r;
+  r.st = I->st;
+  r.E0 = I->pop.E[0];
+  r.E1 = I->pop.E[1];
+  r.P = I->rs_P;
+  r.parent = I->rs_parent;
+  r.R = I->R;
+  r.k0 = key0(I);
+  r.k1 = key1(I);
+  k_rs_select<<<1, 1024, 0, I->stream>>>(r);
+  return hipGetLastError();
+}
+hipError_t ctl_commit(pamc_instance* I, int32_t in_run) {
+  k_commit<<<1, 1, 0, I->stream>>>(I->st, in_run, I->tr_lnq, in_run ? I->tr_cap : 0);
+  return hipGetLastError();
+}
+hipError_t ctl_thresholds(pamc_instance* I) {
+  k_thresholds<<<64, 256, 0, I->stream>>>(I->st, I->thr, I->rule, I->order, 0, 0, 0, key0(I), key1(I));
+  return hipGetLastError();
+}
+hipError_t ctl_step_end(pamc_instance* I, int32_t in_run) {
+  k_step_end<<<1, 1024, 0, I->stream>>>(step_end_args(I), in_run);
+  return hipGetLastError();
+}
+hipError_t ctl_prim_set(pamc_instance* I, int32_t kind, double value) {
+  k_prim_set<<<1, 1, 0, I->stream>>>(I->st, kind, value, 0, 0, I->X);
+  return hipGetLastError();
+}
+hipError_t ctl_advance(pamc_instance* I, int32_t nsweeps) {
+  k_advance_sweeps<<<1, 1, 0, I->stream>>>(I->st, nsweeps);
+  return hipGetLastError();
+}
+hipError_t ctl_deactivate(pamc_instance* I) {
+  k_deactivate<<<1, 1, 0, I->stream>>>(I->st);
+  return hipGetLastError();
+}
+hipEvent_t ctl_event(pamc_instance* I) { return next_event(I); }
 
 hipError_t prepare_cluster_lds() {
   return hipFuncSetAttribute((const void*)k_cl_mis, hipFuncAttributeMaxDynamicSharedMemorySize,
