@@ -1,24 +1,30 @@
 #!/usr/bin/env python3
 """Throughput of the augmented PAMC hot path on one MI355X.
 
-Workload: augmented PAMC (adaptive reheat + cluster moves) on a 100 x 200
-toroidal grid with +-1 weights (n = 20,000, degree 4), R = 4096 replicas,
-500 beta steps of 10 sweeps (beta0 = 0.1, dbeta = 0.02, restart every 400
-steps, n_top = 128, 4 independent-set trials, cooldown 25).  One bench step is
-one complete run on the resident instance: population initialisation from a
-fresh seed, then the 500 steps (resampling, cluster moves, threshold tables,
-sweeps, best-cut reduction, controller), all on the device.
+Default workload (the one the JSON line is quoted on): augmented PAMC
+(adaptive reheat + cluster moves) on a 100 x 200 toroidal grid with +-1
+weights (n = 20,000, degree 4), R = 4096 replicas, 500 beta steps of 10
+sweeps (beta0 = 0.1, dbeta = 0.02, restart every 400 steps, n_top = 128, 4
+independent-set trials, cooldown 25).  One bench step is one complete run on
+the resident instance: population initialisation from a fresh seed, then the
+500 steps (resampling, cluster moves, threshold tables, sweeps, best-cut
+reduction, controller), all on the device.
+
+Other workloads (--workload): c1 = plain PAMC on the n = 800 random graph;
+c3 = plain PAMC on the dense n = 100,000 +-1 instance; c4 = augmented PAMC on
+the Max-3-Cut embedding of a 7,000-vertex graph.
 
 Printed (one JSON line): flip attempts per second over the timed runs,
 time-to-target p50/p99 (target = median final best cut of the timed runs),
-the sweep kernel's roofline position measured with HIP events around every
-sweep launch, and the CPU oracle timed on a bounded sample.
+the dominant kernel's roofline position measured with HIP events around
+every launch of it, and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -26,15 +32,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-N_SIDE = (100, 200)
-R = 4096
-STEPS = 500
-SWEEPS = 10
-SCHED = dict(beta0=0.1, dbeta=0.02, steps=STEPS, sweeps=SWEEPS, augmented=1, z_rst=400, n_top=128,
-             mis_trials=4, tau=25)
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "sweep_torus100x200_R4096_counters.json")
-SWEEP_SRC = os.path.join(ROOT, "paper_2606_25203_amd", "csrc", "sparse.hip")
+MFMA_I8_PEAK_TOPS = 5000.0
+CSRC = os.path.join(ROOT, "paper_2606_25203_amd", "csrc")
 
 
 def log(*a):
@@ -51,7 +51,7 @@ def percentile(xs, q):
 
 
 def sweep_bytes_per_attempt(p_flip: float, degree: float, pull: bool) -> float:
-    """Algorithmic HBM bytes of one (replica, vertex) visit of the sweep.
+    """Algorithmic HBM bytes of one (replica, vertex) visit of the sparse sweep.
     Incremental fields (push): read the spin (1 B) and the field (4 B); on a
     flip (probability p) write the spin (1 B) and read-modify-write every
     neighbour field (8 B each).  Gathered fields (pull): read the spin (1 B)
@@ -64,13 +64,14 @@ def sweep_bytes_per_attempt(p_flip: float, degree: float, pull: bool) -> float:
     return 5.0 + p_flip * (1.0 + 8.0 * degree) + csr
 
 
-def counters_traffic():
-    """Bytes per sweep launch from the committed rocprofv3 FETCH/WRITE pass,
-    or None if the sweep source changed since the counters were taken."""
+def counters_traffic(name: str, src: str):
+    """HBM bytes per launch from a committed rocprofv3 FETCH/WRITE pass, or
+    None if the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{name}_counters.json")
     try:
-        with open(COUNTERS) as f:
+        with open(path) as f:
             c = json.load(f)
-        sha = hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()
+        sha = hashlib.sha256(open(os.path.join(CSRC, src), "rb").read()).hexdigest()
         if c.get("source_sha256") != sha:
             return None
         return c["hbm_bytes_per_launch"]
@@ -78,21 +79,62 @@ def counters_traffic():
         return None
 
 
-def cpu_baseline(seconds_budget: float):
-    import oracle
+# ----------------------------------------------------------------- workloads
+def workload(name):
     import synth
-    g = synth.torus(*N_SIDE, seed=1)
-    rr = 64
-    steps = max(1, int(round(seconds_budget / 1.2)))
-    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, rr, 0)
-    kw = dict(SCHED)
-    kw.update(steps=steps, n_top=2)
+    if name == "c2":
+        g = synth.torus(100, 200, seed=1)
+        return dict(kind="csr", graph=g, R=4096, steps=500, sweeps=10,
+                    sched=dict(beta0=0.1, dbeta=0.02, steps=500, sweeps=10, augmented=1, z_rst=400, n_top=128,
+                               mis_trials=4, tau=25),
+                    desc="augmented PAMC, 100x200 torus +-1 weights (n=20000, degree 4), R=4096, "
+                         "500 beta steps x 10 sweeps",
+                    counters="sweep_torus100x200_R4096", cpu=dict(R=64, step_s=1.2))
+    if name == "c1":
+        g = synth.random_graph(800, 19176, seed=1)
+        return dict(kind="csr", graph=g, R=256, steps=50, sweeps=5,
+                    sched=dict(beta0=0.1, dbeta=2.9 / 49, steps=50, sweeps=5),
+                    desc="plain PAMC, random graph n=800 m=19176 w=+1, R=256, 50 beta steps 0.1->3.0 x 5 sweeps",
+                    counters="sweep_gnm800_R256", cpu=dict(R=256, step_s=0.3))
+    if name == "c3":
+        n = 100_000
+        return dict(kind="dense", n=n, R=256, steps=200, sweeps=1,
+                    sched=dict(beta0=0.1 / math.sqrt(n), dbeta=2.9 / math.sqrt(n) / 199, steps=200, sweeps=1),
+                    desc="plain PAMC, dense +-1 Ising n=100000 (int8 J, 10 GB), R=256, "
+                         "200 beta steps 0.1/sqrt(n)->3.0/sqrt(n) x 1 sweep",
+                    counters="dense_gemm_n100000_R256", cpu=None)
+    if name == "c4":
+        g = synth.random_graph(7000, 21000, seed=1)
+        return dict(kind="max3cut", graph=g, R=2048, steps=300, sweeps=10,
+                    sched=dict(beta0=0.1, dbeta=0.02, steps=300, sweeps=10, augmented=1, z_rst=400, n_top=64,
+                               mis_trials=4, tau=25),
+                    desc="augmented PAMC, Max-3-Cut one-hot embedding of G(7000, 21000) (n=21001), R=2048, "
+                         "300 beta steps x 10 sweeps",
+                    counters="sweep_max3cut7000_R2048", cpu=dict(R=64, step_s=1.5))
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, seconds_budget: float):
+    import oracle
+    if w["cpu"] is None:
+        return None
+    rr = w["cpu"]["R"]
+    g = w["graph"]
+    if w["kind"] == "max3cut":
+        o = oracle.Oracle.max3cut(g.n, g.row_ptr, g.col, g.w, rr, 0)
+        n = 3 * g.n + 1
+    else:
+        o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, rr, 0)
+        n = g.n
+    steps = max(1, min(w["steps"], int(round(seconds_budget / w["cpu"]["step_s"]))))
+    kw = dict(w["sched"])
+    kw.update(steps=steps, n_top=max(1, min(kw.get("n_top", 1), rr // 32)))
     t0 = time.perf_counter()
     o.anneal(oracle.default_schedule(**kw))
     dt = time.perf_counter() - t0
-    att = steps * SWEEPS * g.n * rr
+    att = steps * w["sweeps"] * n * rr
     return {"value": att / dt, "unit": "flip attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"same torus, R={rr} replicas, first {steps} augmented beta steps x {SWEEPS} sweeps "
+            "sample": f"same instance, R={rr} replicas, first {steps} beta steps x {w['sweeps']} sweeps "
                       f"({att:.3g} attempts in {dt:.1f} s, single thread)"}
 
 
@@ -101,6 +143,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fields", choices=["auto", "push", "pull"], default="auto")
@@ -111,19 +154,24 @@ def main():
         sys.exit(2)
 
     import torch
-    import synth
     from paper_2606_25203_amd import pamc
 
-    g = synth.torus(*N_SIDE, seed=1)
-    degree = g.nnz / g.n
-    inst = pamc.Instance.csr(g, replicas=R, seed=0, fields=None if args.fields == "auto" else args.fields)
-    pull = bool(inst.info().pull)
-    sched = pamc.schedule(**SCHED)
+    w = workload(args.workload)
+    fields = None if args.fields == "auto" else args.fields
+    if w["kind"] == "csr":
+        inst = pamc.Instance.csr(w["graph"], replicas=w["R"], seed=0, fields=fields)
+    elif w["kind"] == "max3cut":
+        inst = pamc.Instance.max3cut(w["graph"], replicas=w["R"], seed=0, fields=fields)
+    else:
+        inst = pamc.Instance.dense_random(w["n"], 1, replicas=w["R"], seed=0)
+    info = inst.info()
+    n = info.n
+    sched = pamc.schedule(**w["sched"])
     pamc.pamc_profile_enable(inst.h, True)   # warm-up also fills the event pool
-    for w in range(args.warmup):
-        inst.reset(10_000 + w)
+    for k in range(args.warmup):
+        inst.reset(10_000 + k)
         inst.anneal(sched)
-        log(f"warmup {w} done")
+        log(f"warmup {k} done")
     pamc.pamc_profile_enable(inst.h, True)   # zero the counters, keep the pool
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -131,7 +179,7 @@ def main():
     for k in range(args.steps):
         inst.reset(k)
         res = inst.anneal(sched)
-        tr = inst.trace(STEPS)
+        tr = inst.trace(w["steps"])
         runs.append((res, tr))
         log(f"run {k}: best cut {res.best_cut}, device time {res.seconds_total:.3f} s")
     inst.synchronize()
@@ -139,8 +187,7 @@ def main():
     wall = time.perf_counter() - t0
     prof = pamc.pamc_profile_read(inst.h)
 
-    attempts = sum(r.steps_run for r, _ in runs) * SWEEPS * g.n * R
-    value = attempts / wall
+    attempts = sum(r.steps_run for r, _ in runs) * w["sweeps"] * n * w["R"]
     finals = [r.best_cut for r, _ in runs]
     target = int(percentile(finals, 0.5))
     ttt = []
@@ -148,15 +195,32 @@ def main():
         hit = [t for m, t in zip(tr["mstar"], tr["seconds"]) if m >= target]
         if hit:
             ttt.append(float(hit[0]))
-    p_flip = prof["flips"] / max(prof["attempts"], 1)
     launch_ms = prof["ms"] / max(prof["launches"], 1)
-    attempts_per_launch = prof["attempts"] / max(prof["launches"], 1)
-    bpa = sweep_bytes_per_attempt(p_flip, degree, pull)
-    bytes_per_launch = bpa * attempts_per_launch
-    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    p_flip = prof["flips"] / max(prof["attempts"], 1)
+    if w["kind"] == "dense":
+        # matrix-core partial fields of one 64-row block: 2 * 64 * n_pad * R ops
+        npad = (n + 63) // 64 * 64
+        ops = 2.0 * 64 * npad * w["R"]
+        achieved = ops / (launch_ms * 1e-3) / 1e12
+        roof = {"kernel": "k_dense_gemm", "bound": "mfma", "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS,
+                "unit": "TOP/s (int8)", "frac": achieved / MFMA_I8_PEAK_TOPS,
+                "traffic": counters_traffic(w["counters"], "dense.hip"), "launch_ms": launch_ms,
+                "launches": prof["launches"], "ops_per_launch": ops, "flip_rate": p_flip}
+    else:
+        degree = info.nnz / n
+        pull = bool(info.pull)
+        bpa = sweep_bytes_per_attempt(p_flip, degree, pull)
+        apl = prof["attempts"] / max(prof["launches"], 1)
+        achieved = bpa * apl / (launch_ms * 1e-3) / 1e9
+        roof = {"kernel": "k_sweep_pull" if pull else "k_sweep", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": counters_traffic(w["counters"], "sparse.hip"), "launch_ms": launch_ms,
+                "launches": prof["launches"], "attempts_per_launch": apl, "flip_rate": p_flip,
+                "algorithmic_bytes_per_attempt": bpa, "fields": "pull" if pull else "push",
+                "attempts_per_s_in_kernel": apl / (launch_ms * 1e-3)}
     out = {
         "metric": "spin-flip attempts/s + time-to-target-cut (plain vs batched/served), p50/p99",
-        "value": value,
+        "value": attempts / wall,
         "unit": "flip attempts/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -167,22 +231,18 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "augmented PAMC, 100x200 torus +-1 weights (n=20000, degree 4), "
-                               "R=4096, 500 beta steps x 10 sweeps",
-                   "n": g.n, "replicas": R, "beta_steps": STEPS, "sweeps": SWEEPS,
-                   "mode": "plain (one instance per launch sequence)", "parallelism": "1 GPU"},
+        "config": {"workload": w["desc"], "n": n, "replicas": w["R"], "beta_steps": w["steps"],
+                   "sweeps": w["sweeps"], "mode": "plain (one instance per launch sequence)",
+                   "parallelism": "1 GPU"},
         "time_to_target": {"target_cut": target, "p50_s": percentile(ttt, 0.5), "p99_s": percentile(ttt, 0.99),
                            "success_fraction": len(ttt) / len(runs), "final_cuts": finals},
-        "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counters_traffic(),
-                     "launch_ms": launch_ms, "launches": prof["launches"],
-                     "attempts_per_launch": attempts_per_launch, "flip_rate": p_flip,
-                     "algorithmic_bytes_per_attempt": bpa,
-                     "fields": "pull" if pull else "push"},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        cb = cpu_baseline(w, args.cpu_seconds)
+        if cb is not None:
+            out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

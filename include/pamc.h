@@ -68,7 +68,8 @@ typedef enum { PAMC_MEM_HOST = 0, PAMC_MEM_DEVICE = 1 } pamc_mem;
  * in an int32 array updated by each flip; PULL keeps no field array and sums
  * the neighbours' spins when a spin is visited.  The integer fields, hence
  * every decision and the trajectory, are the same; the default picks PULL
- * when the average degree is at most 16. */
+ * when the average degree is at most 16 and no vertex has more than 64
+ * neighbours. */
 #define PAMC_FLAG_FIELDS_PUSH 2u
 #define PAMC_FLAG_FIELDS_PULL 4u
 

@@ -200,7 +200,13 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
   else if (I->flags & PAMC_FLAG_FIELDS_PULL)
     I->pull = 1;
   else
-    I->pull = (I->nnz <= 16 * (int64_t)n) ? 1 : 0;
+  {
+    int64_t maxdeg = 0;
+    for (int32_t v = 0; v < n; ++v) maxdeg = std::max<int64_t>(maxdeg, rp[v + 1] - rp[v]);
+    // gathering a hub's field serialises one wavefront per tile over all of
+    // its neighbours; incremental fields spread that work over the flips
+    I->pull = (I->nnz <= 16 * (int64_t)n && maxdeg <= 64) ? 1 : 0;
+  }
   // Tiles per wavefront: share the per-vertex scalar work among up to 4
   // tiles while keeping enough work-groups to fill the chip.
   {
@@ -363,7 +369,8 @@ pamc_status build_dense_common(pamc_instance* I, int32_t n) {
   HIP_TRY(dalloc(I, &I->rs_P, I->R), "alloc");
   HIP_TRY(dalloc(I, &I->rs_parent, I->R), "alloc");
   HIP_TRY(dalloc(I, &I->flip_ctr, 512), "alloc");
-  HIP_TRY(dalloc(I, &I->Gd, (size_t)pamc::dense_num_partials(I->dn_pad) * 64 * I->R), "alloc fields");
+  HIP_TRY(dalloc(I, &I->Gd, (size_t)64 * I->R), "alloc fields");
+  HIP_TRY(hipMemsetAsync(I->Gd, 0, sizeof(int32_t) * 64 * I->R, I->stream), "memset");
   I->order_cap = 1;
   HIP_TRY(dalloc(I, &I->order, 1), "alloc");
   HIP_TRY(hipMemsetAsync(I->flip_ctr, 0, sizeof(int64_t) * 512, I->stream), "memset");

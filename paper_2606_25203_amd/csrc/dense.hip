@@ -5,9 +5,9 @@
 // A sweep runs over blocks of kDB = 64 consecutive spins.  For block b the
 // local fields of Eq. 3 against the *current* spins, G = J[blk, :] . S, come
 // from int8 x int8 -> int32 matrix-core products (exact: |h| <= 127 n <
-// 2^31), split over the K (spin) dimension into partial sums.  A sequential
+// 2^31), split over the K (spin) dimension and summed atomically.  A sequential
 // kernel (one wavefront per 64 replicas) then visits the block's spins in
-// order: h_k = sum of the partials + sum_{k' < k in block} J_kk' d_k', where
+// order: h_k = G_k + sum_{k' < k in block} J_kk' d_k', where
 // d_k' = 2 s_k'(new) if spin k' flipped and 0 otherwise (packed int8, summed
 // four at a time with dot4), applies the same threshold test as the sparse
 // path and updates spins and energies.
@@ -81,8 +81,9 @@ __global__ void __launch_bounds__(256) k_dense_init_spins(int8_t* S, int32_t* fa
   }
 }
 
-// Gpart[p][m][r] = sum_{k in slice p} J[row0 + m][k] S[r][k] for the block's
-// kDB rows and a 64-replica tile.  Work-group = 4 waves; wave w owns rows
+// G[m][r] += sum_{k in slice p} J[row0 + m][k] S[r][k] for the block's kDB
+// rows and a 64-replica tile (the K slices meet by atomic addition in G).
+// Work-group = 4 waves; wave w owns rows
 // 16w..16w+15 against the tile's 64 replicas (four 16 x 16 results) with
 // v_mfma_i32_16x16x64_i8.  Operand fragments: lane l supplies 16 consecutive
 // K bytes at 16*(l/16) of row (A) / replica (B) l % 16; the result holds rows
@@ -103,20 +104,37 @@ __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J
   const int8_t* arow = J + (size_t)(row0 + 16 * wave + (lane & 15)) * np + 16 * (lane >> 4);
   const int8_t* brow = S + (size_t)(tile * 64 + (lane & 15)) * np + 16 * (lane >> 4);
   v4i acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll 4
   for (int k0 = k_beg; k0 < k_end; k0 += 64) {
     const v4i a = *reinterpret_cast<const v4i*>(arow + k0);
+    v4i b[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const v4i b = *reinterpret_cast<const v4i*>(brow + (size_t)nt * 16 * np + k0);
-      acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[nt], 0, 0, 0);
-    }
+    for (int nt = 0; nt < 4; ++nt) b[nt] = *reinterpret_cast<const v4i*>(brow + (size_t)nt * 16 * np + k0);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[nt], acc[nt], 0, 0, 0);
   }
-  int32_t* out = Gpart + (size_t)p * kDB * R;
+  // K-split partials meet in G[kDB][R] (zeroed by its reader)
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      out[(size_t)(16 * wave + 4 * (lane >> 4) + j) * R + tile * 64 + nt * 16 + (lane & 15)] = acc[nt][j];
+    for (int j = 0; j < 4; ++j) {
+      const int32_t v = acc[nt][j];
+      if (v != 0)
+        __hip_atomic_fetch_add(&Gpart[(size_t)(16 * wave + 4 * (lane >> 4) + j) * R + tile * 64 + nt * 16 + (lane & 15)],
+                               v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Moves the block fields of one 64-replica tile from G[kDB][R] into LDS and
+// clears them in G for the next block's K-split accumulation.
+__device__ __forceinline__ void take_fields(int32_t* __restrict__ G, int32_t R, int tile,
+                                            int32_t (*g)[64]) {
+  for (int i = threadIdx.x; i < kDB * 64; i += blockDim.x) {
+    const int k = i >> 6, l = i & 63;
+    int32_t* src = G + (size_t)k * R + tile * 64 + l;
+    g[k][l] = *src;
+    *src = 0;
+  }
 }
 
 // Sequential visit of the block's spins for one 64-replica tile (one wave).
@@ -126,7 +144,7 @@ struct SeqArgs {
   int8_t* S1;
   int64_t* E0;
   int64_t* E1;
-  const int32_t* Gpart;
+  int32_t* Gpart;
   const uint32_t* thr;
   RunState* st;
   int32_t row0, n, np, R, P;
@@ -135,21 +153,24 @@ struct SeqArgs {
 };
 
 template <int RULE>
-__global__ void __launch_bounds__(64) k_dense_seq(SeqArgs a, int32_t sweep_idx) {
+__global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx) {
   __shared__ uint32_t jd[kDB][kDB / 4];  // J[row0 + k][row0 + 4g .. 4g+3], packed int8
+  __shared__ int32_t gsum[kDB][64];      // block fields of this tile before the block's flips
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
   int8_t* S = cur ? a.S1 : a.S0;
   int64_t* E = cur ? a.E1 : a.E0;
-  const int lane = threadIdx.x;
   const int tile = blockIdx.x;
-  const int r = tile * 64 + lane;
-  for (int i = lane; i < kDB * kDB / 4; i += 64) {
+  for (int i = threadIdx.x; i < kDB * kDB / 4; i += blockDim.x) {
     const int k = i / (kDB / 4), g = i % (kDB / 4);
     jd[k][g] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(a.row0 + k) * a.np + a.row0 + 4 * g);
   }
+  take_fields(a.Gpart, a.R, tile, gsum);
   __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const int r = tile * 64 + lane;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
   const int32_t Xt = (int32_t)st->table_x;
   uint32_t d[kDB / 4];  // packed int8 d_k' of this lane's replica
@@ -170,8 +191,7 @@ __global__ void __launch_bounds__(64) k_dense_seq(SeqArgs a, int32_t sweep_idx) 
       const int k = 4 * g + kk;
       const int v = a.row0 + k;
       if (v >= a.n) break;
-      int32_t h = 0;
-      for (int p = 0; p < a.P; ++p) h += a.Gpart[((size_t)p * kDB + k) * a.R + r];
+      int32_t h = gsum[k][lane];
 #pragma unroll
       for (int g2 = 0; g2 < g; ++g2) h = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)d[g2], h, false);
       h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, h, false);
@@ -203,18 +223,21 @@ __global__ void __launch_bounds__(64) k_dense_seq(SeqArgs a, int32_t sweep_idx) 
 
 // Energy of the population from block fields: E_r += sum_k s_rk G_rk (the
 // caller negates and halves at the end).
-__global__ void __launch_bounds__(64) k_dense_energy_block(const int8_t* S, const int32_t* Gpart,
-                                                           int64_t* E, int32_t row0, int32_t n,
-                                                           int32_t np, int32_t R, int32_t P) {
-  const int r = blockIdx.x * 64 + threadIdx.x;
+__global__ void __launch_bounds__(256) k_dense_energy_block(const int8_t* S, int32_t* Gpart,
+                                                            int64_t* E, int32_t row0, int32_t n,
+                                                            int32_t np, int32_t R, int32_t P) {
+  __shared__ int32_t gsum[kDB][64];
+  const int tile = blockIdx.x;
+  take_fields(Gpart, R, tile, gsum);
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int r = tile * 64 + threadIdx.x;
   int64_t acc = 0;
-  for (int k = 0; k < kDB && row0 + k < n; ++k) {
-    int32_t h = 0;
-    for (int p = 0; p < P; ++p) h += Gpart[((size_t)p * kDB + k) * R + r];
-    acc += (int64_t)h * S[(size_t)r * np + row0 + k];
-  }
-  if (acc) __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)acc, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
+  for (int k = 0; k < kDB && row0 + k < n; ++k)
+    acc += (int64_t)gsum[k][threadIdx.x] * S[(size_t)r * np + row0 + k];
+  if (acc)
+    __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)acc, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_dense_init_finish(int64_t* E, int32_t R, RunState* st, int8_t* best, int32_t np) {
@@ -252,14 +275,15 @@ __global__ void __launch_bounds__(256) k_dense_gather(const RunState* st, int8_t
 int32_t num_partials(int32_t np) { return (np + kKSlice - 1) / kKSlice; }
 
 // H[r][row0 + k] = sum of the block's partial fields (snapshots only).
-__global__ void __launch_bounds__(64) k_dense_collect(const int32_t* Gpart, int32_t* H, int32_t row0,
-                                                      int32_t n, int32_t np, int32_t R, int32_t P) {
-  const int r = blockIdx.x * 64 + threadIdx.x;
-  for (int k = 0; k < kDB && row0 + k < n; ++k) {
-    int32_t h = 0;
-    for (int p = 0; p < P; ++p) h += Gpart[((size_t)p * kDB + k) * R + r];
-    H[(size_t)r * np + row0 + k] = h;
-  }
+__global__ void __launch_bounds__(256) k_dense_collect(int32_t* Gpart, int32_t* H, int32_t row0,
+                                                       int32_t n, int32_t np, int32_t R, int32_t P) {
+  __shared__ int32_t gsum[kDB][64];
+  const int tile = blockIdx.x;
+  take_fields(Gpart, R, tile, gsum);
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int r = tile * 64 + threadIdx.x;
+  for (int k = 0; k < kDB && row0 + k < n; ++k) H[(size_t)r * np + row0 + k] = gsum[k][threadIdx.x];
 }
 
 }  // namespace
@@ -289,7 +313,7 @@ static hipError_t dense_full_energy(pamc_instance* I, int buf) {
   for (int row0 = 0; row0 < I->n; row0 += kDB) {
     k_dense_gemm<<<T * P, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, I->dn_pad,
                                                I->R, 0);
-    k_dense_energy_block<<<T, 64, 0, I->stream>>>(buf ? I->Sd2 : I->Sd, I->Gd, I->pop.E[buf], row0,
+    k_dense_energy_block<<<T, 256, 0, I->stream>>>(buf ? I->Sd2 : I->Sd, I->Gd, I->pop.E[buf], row0,
                                                   I->n, I->dn_pad, I->R, P);
   }
   return hipGetLastError();
@@ -342,9 +366,9 @@ static hipError_t dense_sweeps(pamc_instance* I, int32_t nsweeps) {
       }
       a.row0 = row0;
       if (I->rule == 1)
-        k_dense_seq<1><<<T, 64, 0, I->stream>>>(a, s);
+        k_dense_seq<1><<<T, 256, 0, I->stream>>>(a, s);
       else
-        k_dense_seq<0><<<T, 64, 0, I->stream>>>(a, s);
+        k_dense_seq<0><<<T, 256, 0, I->stream>>>(a, s);
     }
     if (I->prof) I->prof_attempts += (int64_t)I->n * I->R;
   }
@@ -399,7 +423,7 @@ hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor) {
   for (int row0 = 0; row0 < I->n; row0 += kDB) {
     k_dense_gemm<<<T * P, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, I->dn_pad,
                                                I->R, 2);
-    k_dense_collect<<<T, 64, 0, I->stream>>>(I->Gd, H_rmajor, row0, I->n, I->dn_pad, I->R, P);
+    k_dense_collect<<<T, 256, 0, I->stream>>>(I->Gd, H_rmajor, row0, I->n, I->dn_pad, I->R, P);
   }
   return hipGetLastError();
 }
