@@ -147,7 +147,20 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fields", choices=["auto", "push", "pull"], default="auto")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run an elementwise copy of this many MiB (int32 in, int32 out) five "
+                         "times; used to scale the HBM byte counters of rocprofv3")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        x = torch.arange(n, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "kernel": "neg (elementwise)"}))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU replica sharding is design-only "
               "(see DESIGN.md). Use --gpus 1.", file=sys.stderr)
