@@ -219,6 +219,67 @@ pamc_status pamc_profile_read(pamc_instance* inst, double* ms, int64_t* launches
 
 pamc_status pamc_synchronize(pamc_instance* inst);
 
+/* ---------------------------------------------------------------------------
+ * Batched and served runs.  Many independent runs share every kernel launch:
+ * each kernel reads a per-instance descriptor and a block-to-instance map,
+ * so instances of different sizes, schedules and seeds advance together.
+ * A run's result does not depend on what it is batched with: the cut, the
+ * trace and the final population are bit-identical to pamc_anneal on the
+ * same instance.
+ * ------------------------------------------------------------------------- */
+
+/* Runs Algorithm 1 on count sparse instances of one device at once, each
+ * with its own schedule, and waits.  Instances must be distinct; each
+ * instance's queued work is finished first, and the batch runs on the first
+ * instance's stream.  out: count results. */
+pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* scheds, int32_t count,
+                              pamc_result* out);
+
+typedef struct pamc_server pamc_server;
+
+/* Continuous-batching server on cfg->device: requests (a graph, a seed and a
+ * schedule) wait in a FIFO queue; a request is admitted when fewer than
+ * max_slots run and its device memory fits in hbm_budget_bytes next to the
+ * running ones.  Each tick advances every running request by the same number
+ * of beta steps in shared launches, then retires the finished ones and frees
+ * their memory.  cfg gives replicas, rule, flags and stream (the seed comes
+ * with each request).  One thread at a time per server. */
+pamc_status pamc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, const pamc_config* cfg,
+                               pamc_server** out);
+
+/* Queues a Max-Cut (objective PAMC_OBJ_MAXCUT) or Ising request on a host CSR
+ * graph (validated and copied now; the caller keeps its arrays).  Returns
+ * PAMC_ERR_OUT_OF_MEMORY if the request alone exceeds the budget.  *ticket
+ * identifies the request. */
+pamc_status pamc_server_submit(pamc_server* srv, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                               const int32_t* w, int32_t objective, uint64_t seed,
+                               const pamc_schedule* sched, uint64_t* ticket);
+
+/* Admits what fits, advances the running requests by min(max_steps, steps
+ * left of the nearest one) beta steps (max_steps <= 0: no cap), waits, and
+ * retires finished requests.  n_active / n_queued (may be NULL) receive the
+ * counts after the tick.  A request whose instance cannot be built is
+ * dropped and its error returned. */
+pamc_status pamc_server_tick(pamc_server* srv, int32_t max_steps, int32_t* n_active, int32_t* n_queued);
+
+/* Ticks until nothing is queued or running. */
+pamc_status pamc_server_drain(pamc_server* srv);
+
+/* *done = 1 and the result (and best spins, n entries, may be NULL) once
+ * the request has finished, else *done = 0. */
+pamc_status pamc_server_poll(pamc_server* srv, uint64_t ticket, int32_t* done, pamc_result* out,
+                             int8_t* spins);
+
+/* Host wall-clock seconds from submission to admission and to retirement. */
+pamc_status pamc_server_latency(pamc_server* srv, uint64_t ticket, double* queued_seconds,
+                                double* total_seconds);
+
+/* Drops a finished request's stored result. */
+pamc_status pamc_server_forget(pamc_server* srv, uint64_t ticket);
+
+/* Frees the server and every request still queued or running. */
+void pamc_server_destroy(pamc_server* srv);
+
 const char* pamc_last_error(void);
 
 #ifdef __cplusplus

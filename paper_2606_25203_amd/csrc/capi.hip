@@ -7,8 +7,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
 #include <new>
+#include <unordered_map>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -50,6 +53,9 @@ void free_instance(pamc_instance* I) {
   if (!I) return;
   if (I->device >= 0) hipSetDevice(I->device);
   if (I->stream) hipStreamSynchronize(I->stream);
+  delete I->self;
+  I->self = nullptr;
+  if (I->d_sched) hipFree(I->d_sched);
   void* ptrs[] = {I->g.row_ptr, I->g.col, I->g.J, I->g.class_ptr, I->pop.S[0], I->pop.S[1],
                   I->pop.H[0], I->pop.H[1], I->pop.E[0], I->pop.E[1], I->pop.fam[0],
                   I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order, I->rs_P,
@@ -130,6 +136,28 @@ pamc_status open_device(pamc_instance* I, const pamc_config* cfg) {
   I->flags = cfg->flags;
   return PAMC_OK;
 }
+
+// The instance as a batch of one, rebuilt after any change of the buffers or
+// keys its descriptor names.
+pamc::Batch* self_batch(pamc_instance* I, hipError_t* err) {
+  *err = hipSuccess;
+  if (!I->self) I->self = new (std::nothrow) pamc::Batch();
+  if (!I->self) {
+    *err = hipErrorOutOfMemory;
+    return nullptr;
+  }
+  if (I->self_dirty) {
+    *err = pamc::batch_build(*I->self, std::vector<pamc_instance*>{I}, nullptr);
+    if (*err != hipSuccess) return nullptr;
+    I->self_dirty = false;
+  }
+  return I->self;
+}
+
+#define SELF_BATCH(I, var)                                  \
+  hipError_t var##_err;                                     \
+  pamc::Batch* var = self_batch(I, &var##_err);             \
+  if (!var) return dev_fail(var##_err, "batch descriptors")
 
 // Sparse graph (already validated, couplings J in caller ids) -> colouring,
 // relabelling and device buffers, then the initial population.
@@ -252,7 +280,8 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
   HIP_TRY(hipMemcpyAsync(I->g.class_ptr, I->class_ptr.data(), sizeof(int32_t) * (ncls + 1), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->to_internal_dev, I->to_internal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::prepare_cluster_lds(), "hipFuncSetAttribute");
-  HIP_TRY(pamc::launch_init_sparse(I), "init kernels");
+  SELF_BATCH(I, b);
+  HIP_TRY(pamc::batch_init(*b), "init kernels");
   HIP_TRY(hipStreamSynchronize(I->stream), "init");
   return PAMC_OK;
 }
@@ -299,6 +328,7 @@ pamc_status ensure_cluster_scratch(pamc_instance* I, int32_t n_top, int32_t tria
   HIP_TRY(dalloc(I, &I->cl_targets, I->cl_cap_top), "alloc cluster");
   HIP_TRY(dalloc(I, &I->cl_sel, (size_t)I->cl_cap_top * I->cl_cap_trials * I->np), "alloc cluster");
   HIP_TRY(dalloc(I, &I->cl_sizes, (size_t)I->cl_cap_top * I->cl_cap_trials), "alloc cluster");
+  I->self_dirty = true;
   return PAMC_OK;
 }
 
@@ -314,6 +344,7 @@ pamc_status ensure_trace(pamc_instance* I, int32_t steps) {
   HIP_TRY(dalloc(I, &I->tr_lnq, steps), "alloc trace");
   HIP_TRY(dalloc(I, &I->tr_events, steps), "alloc trace");
   HIP_TRY(dalloc(I, &I->tr_time, steps), "alloc trace");
+  I->self_dirty = true;
   return PAMC_OK;
 }
 
@@ -324,6 +355,7 @@ pamc_status ensure_order(pamc_instance* I, int32_t sweeps) {
   I->order = nullptr;
   I->order_cap = sweeps;
   HIP_TRY(dalloc(I, &I->order, (size_t)sweeps * I->ncls), "alloc order");
+  I->self_dirty = true;
   return PAMC_OK;
 }
 
@@ -381,9 +413,49 @@ pamc_status build_dense_common(pamc_instance* I, int32_t n) {
 
 pamc_status finish_dense(pamc_instance* I) {
   HIP_TRY(dalloc(I, &I->thr, 2 * I->X + 1), "alloc");
+  I->self_dirty = true;
   HIP_TRY(pamc::launch_init_dense(I), "init kernels");
   HIP_TRY(hipStreamSynchronize(I->stream), "init");
   return PAMC_OK;
+}
+
+pamc_status check_schedule(const pamc_instance* I, const pamc_schedule* sched) {
+  if (sched->steps < 0 || sched->sweeps < 0 || !std::isfinite(sched->beta0) || !std::isfinite(sched->dbeta))
+    return fail(PAMC_ERR_INVALID_ARG, "bad schedule");
+  if (sched->augmented &&
+      (sched->win_long > pamc::kHistCap || sched->win_short > sched->win_long || sched->win_short <= 0))
+    return fail(PAMC_ERR_INVALID_ARG, "history windows must satisfy 0 < short <= long <= 64");
+  if (I->dense && sched->augmented)
+    return fail(PAMC_ERR_UNSUPPORTED, "the augmented controller's cluster moves need a sparse instance");
+  return PAMC_OK;
+}
+
+int32_t cluster_possible(const Schedule& s) {
+  return (s.augmented && s.resample && s.n_top > 0 && s.mis_trials > 0) ? 1 : 0;
+}
+
+// Normalises the schedule and sizes the per-run buffers of one instance.
+pamc_status prepare_run(pamc_instance* I, Schedule& s) {
+  if (!s.augmented) s.win_long = std::min(std::max(s.win_long, 1), pamc::kHistCap);
+  pamc_status st = ensure_trace(I, std::max(s.steps, 1));
+  if (!st) st = ensure_order(I, std::max(s.sweeps, 1));
+  if (!st && cluster_possible(s)) st = ensure_cluster_scratch(I, s.n_top, s.mis_trials);
+  return st;
+}
+
+void fill_result(const pamc_instance* I, const pamc::RunState& r, pamc_result* out) {
+  memset(out, 0, sizeof *out);
+  out->best_cut = r.mstar;
+  out->best_energy = I->W - 2 * r.mstar;
+  out->steps_run = r.steps_run;
+  out->step_reached = r.step_reached;
+  out->sum_lnq = r.sum_lnq;
+  out->n_cluster_moves = r.n_cluster_moves;
+  out->n_reheats = r.n_reheats;
+  out->n_reversals = r.n_reversals;
+  out->n_restarts = r.n_restarts;
+  out->seconds_total = r.steps_run > 0 ? (double)(r.t_last - r.t_start) / I->clock_hz : 0.0;
+  out->seconds_to_target = r.step_reached >= 0 ? (double)(r.t_reached - r.t_start) / I->clock_hz : -1.0;
 }
 
 }  // namespace
@@ -598,10 +670,12 @@ pamc_status pamc_reset_population(pamc_instance* I, uint64_t seed) {
   if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
   hipSetDevice(I->device);
   I->seed = seed;
+  I->self_dirty = true;  // the descriptor carries the key
+  SELF_BATCH(I, b);
   if (I->dense) {
     HIP_TRY(pamc::launch_init_dense(I), "init kernels");
   } else {
-    HIP_TRY(pamc::launch_init_sparse(I), "init kernels");
+    HIP_TRY(pamc::batch_init(*b), "init kernels");
   }
   return PAMC_OK;
 }
@@ -625,11 +699,12 @@ pamc_status pamc_sweep(pamc_instance* I, double beta, int32_t nsweeps) {
   if (nsweeps < 0 || !std::isfinite(beta)) return fail(PAMC_ERR_INVALID_ARG, "bad sweep arguments");
   if (nsweeps == 0) return PAMC_OK;
   hipSetDevice(I->device);
+  SELF_BATCH(I, b);
   if (I->dense) {
-    HIP_TRY(pamc::launch_dense_prim_sweep(I, beta, nsweeps), "dense sweep");
+    HIP_TRY(pamc::launch_dense_prim_sweep(*b, beta, nsweeps), "dense sweep");
     return PAMC_OK;
   }
-  HIP_TRY(pamc::launch_prim_sweep(I, beta, nsweeps), "sweep");
+  HIP_TRY(pamc::prim_sweep(*b, beta, nsweeps), "sweep");
   return PAMC_OK;
 }
 
@@ -637,10 +712,11 @@ pamc_status pamc_resample(pamc_instance* I, double delta, double* log_q) {
   if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
   if (!std::isfinite(delta)) return fail(PAMC_ERR_INVALID_ARG, "delta must be finite");
   hipSetDevice(I->device);
+  SELF_BATCH(I, b);
   if (I->dense) {
-    HIP_TRY(pamc::launch_dense_prim_resample(I, delta), "dense resample");
+    HIP_TRY(pamc::launch_dense_prim_resample(*b, delta), "dense resample");
   } else {
-    HIP_TRY(pamc::launch_prim_resample(I, delta), "resample");
+    HIP_TRY(pamc::prim_resample(*b, delta), "resample");
   }
   if (log_q) {
     pamc::RunState s;
@@ -659,8 +735,9 @@ pamc_status pamc_cluster_move(pamc_instance* I, int32_t n_top, int32_t mis_trial
   pamc_status st = ensure_cluster_scratch(I, n_top, mis_trials);
   if (st) return st;
   int64_t* ctr = I->flip_ctr + 256;
+  SELF_BATCH(I, b);
   HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(int64_t), I->stream), "memset");
-  HIP_TRY(pamc::launch_prim_cluster(I, n_top, mis_trials), "cluster move");
+  HIP_TRY(pamc::prim_cluster(*b, n_top, mis_trials), "cluster move");
   if (flipped) {
     int64_t f = 0;
     HIP_TRY(hipStreamSynchronize(I->stream), "cluster move");
@@ -673,10 +750,11 @@ pamc_status pamc_cluster_move(pamc_instance* I, int32_t n_top, int32_t mis_trial
 pamc_status pamc_update_best(pamc_instance* I) {
   if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
   hipSetDevice(I->device);
+  SELF_BATCH(I, b);
   if (I->dense) {
-    HIP_TRY(pamc::launch_dense_prim_update_best(I), "best");
+    HIP_TRY(pamc::launch_dense_prim_update_best(*b), "best");
   } else {
-    HIP_TRY(pamc::launch_prim_update_best(I), "best");
+    HIP_TRY(pamc::prim_update_best(*b), "best");
   }
   return PAMC_OK;
 }
@@ -741,8 +819,8 @@ pamc_status pamc_get_state(pamc_instance* I, int8_t* spins, int32_t* fields, int
     const int32_t* src = I->pop.H[b];
     if (I->pull) {
       if (!I->H_scratch) HIP_TRY(dalloc(I, &I->H_scratch, H.size()), "alloc fields");
-      I->host_cur = b;
-      HIP_TRY(pamc::launch_fields(I, I->H_scratch), "fields");
+      SELF_BATCH(I, sb);
+      HIP_TRY(pamc::launch_fields(*sb, b, I->H_scratch), "fields");
       HIP_TRY(hipStreamSynchronize(I->stream), "fields");
       src = I->H_scratch;
     }
@@ -758,28 +836,23 @@ pamc_status pamc_get_state(pamc_instance* I, int8_t* spins, int32_t* fields, int
 
 pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_result* out) {
   if (!I || !sched || !out) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
-  if (sched->steps < 0 || sched->sweeps < 0 || !std::isfinite(sched->beta0) || !std::isfinite(sched->dbeta))
-    return fail(PAMC_ERR_INVALID_ARG, "bad schedule");
-  if (sched->augmented &&
-      (sched->win_long > pamc::kHistCap || sched->win_short > sched->win_long || sched->win_short <= 0))
-    return fail(PAMC_ERR_INVALID_ARG, "history windows must satisfy 0 < short <= long <= 64");
-  if (I->dense && sched->augmented)
-    return fail(PAMC_ERR_UNSUPPORTED, "the augmented controller's cluster moves need a sparse instance");
+  pamc_status st = check_schedule(I, sched);
+  if (st) return st;
   hipSetDevice(I->device);
   Schedule s = to_sched(sched);
-  if (!s.augmented) {
-    s.win_long = std::min(std::max(s.win_long, 1), pamc::kHistCap);
-  }
-  pamc_status st = ensure_trace(I, std::max(s.steps, 1));
-  if (!st) st = ensure_order(I, std::max(s.sweeps, 1));
-  if (!st && s.augmented && s.resample) st = ensure_cluster_scratch(I, s.n_top, s.mis_trials);
+  st = prepare_run(I, s);
   if (st) return st;
-  HIP_TRY(pamc::launch_anneal_setup(I, s), "anneal setup");
+  SELF_BATCH(I, b);
+  b->max_sweeps = std::max(s.sweeps, 1);
+  b->any_cluster = cluster_possible(s);
+  if (!I->d_sched) HIP_TRY(hipMalloc(&I->d_sched, sizeof(Schedule)), "alloc");
+  HIP_TRY(hipMemcpyAsync(I->d_sched, &s, sizeof(Schedule), hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(pamc::batch_anneal_setup(*b, (const Schedule*)I->d_sched, nullptr, 1), "anneal setup");
   for (int32_t step = 0; step < s.steps; ++step) {
     if (I->dense) {
-      HIP_TRY(pamc::launch_dense_step(I, s, step), "dense step");
+      HIP_TRY(pamc::launch_dense_step(*b, s.sweeps, s.resample), "dense step");
     } else {
-      HIP_TRY(pamc::launch_step(I, s, step), "step");
+      HIP_TRY(pamc::batch_step(*b), "step");
     }
     if (s.stop_at_target && (step % 16) == 15) {
       HIP_TRY(hipMemcpyAsync(I->pinned, &I->st->stopped, sizeof(int32_t), hipMemcpyDeviceToHost, I->stream), "poll");
@@ -791,23 +864,66 @@ pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_resul
   st = read_state(I, &r);
   if (!st && I->prof) st = resolve_events(I);
   if (st) return st;
-  memset(out, 0, sizeof *out);
-  out->best_cut = r.mstar;
-  out->best_energy = I->W - 2 * r.mstar;
-  out->steps_run = r.steps_run;
-  out->step_reached = r.step_reached;
-  out->sum_lnq = r.sum_lnq;
-  out->n_cluster_moves = r.n_cluster_moves;
-  out->n_reheats = r.n_reheats;
-  out->n_reversals = r.n_reversals;
-  out->n_restarts = r.n_restarts;
-  out->seconds_total = 0.0;
-  if (r.steps_run > 0) {
-    uint64_t t_last = 0;
-    HIP_TRY(hipMemcpy(&t_last, I->tr_time + (r.steps_run - 1), sizeof(uint64_t), hipMemcpyDeviceToHost), "readback");
-    out->seconds_total = (double)(t_last - r.t_start) / I->clock_hz;
+  fill_result(I, r, out);
+  return PAMC_OK;
+}
+
+pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* scheds, int32_t count,
+                              pamc_result* out) {
+  if (count < 0 || (count > 0 && (!insts || !scheds || !out))) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  if (count == 0) return PAMC_OK;
+  std::vector<pamc_instance*> v(insts, insts + count);
+  for (int32_t i = 0; i < count; ++i) {
+    if (!v[i]) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+    if (v[i]->dense) return fail(PAMC_ERR_UNSUPPORTED, "batched runs take sparse instances");
+    if (v[i]->device != v[0]->device) return fail(PAMC_ERR_INVALID_ARG, "instances on different devices");
+    for (int32_t j = 0; j < i; ++j)
+      if (v[j] == v[i]) return fail(PAMC_ERR_INVALID_ARG, "an instance appears twice");
+    pamc_status st = check_schedule(v[i], &scheds[i]);
+    if (st) return st;
   }
-  out->seconds_to_target = r.step_reached >= 0 ? (double)(r.t_reached - r.t_start) / I->clock_hz : -1.0;
+  hipSetDevice(v[0]->device);
+  std::vector<Schedule> s(count);
+  int32_t max_steps = 0, any_stop = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    s[i] = to_sched(&scheds[i]);
+    pamc_status st = prepare_run(v[i], s[i]);
+    if (st) return st;
+    max_steps = std::max(max_steps, s[i].steps);
+    any_stop |= s[i].stop_at_target;
+  }
+  // every instance's queued work is finished before the batch takes over
+  for (pamc_instance* I : v) HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  pamc::Batch b;
+  HIP_TRY(pamc::batch_build(b, v, &s), "batch descriptors");
+  Schedule* d_sched = nullptr;
+  int32_t* d_status = nullptr;
+  hipError_t e = hipMalloc((void**)&d_sched, sizeof(Schedule) * count);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_status, sizeof(int32_t) * count);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_sched, s.data(), sizeof(Schedule) * count, hipMemcpyHostToDevice, b.stream);
+  if (e == hipSuccess) e = pamc::batch_anneal_setup(b, d_sched, nullptr, count);
+  std::vector<int32_t> status(count);
+  for (int32_t step = 0; step < max_steps && e == hipSuccess; ++step) {
+    e = pamc::batch_step(b);
+    if (e == hipSuccess && any_stop && (step % 16) == 15) {
+      e = pamc::batch_status(b, d_status);
+      if (e == hipSuccess) e = hipMemcpyAsync(status.data(), d_status, sizeof(int32_t) * count, hipMemcpyDeviceToHost, b.stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+      bool all = true;
+      for (int32_t x : status) all = all && (x & 1);
+      if (all) break;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+  if (d_sched) hipFree(d_sched);
+  if (d_status) hipFree(d_status);
+  if (e != hipSuccess) return dev_fail(e, "batched run");
+  for (int32_t i = 0; i < count; ++i) {
+    pamc::RunState r;
+    pamc_status st = read_state(v[i], &r);
+    if (st) return st;
+    fill_result(v[i], r, &out[i]);
+  }
   return PAMC_OK;
 }
 
@@ -878,6 +994,7 @@ pamc_status pamc_profile_enable(pamc_instance* I, int32_t on) {
   I->prof_launches = 0;
   I->prof_attempts = 0;
   HIP_TRY(hipMemset(I->flip_ctr, 0, sizeof(int64_t) * 256), "memset");
+  I->self_dirty = true;  // the descriptor carries the flip counters iff profiling
   return PAMC_OK;
 }
 
@@ -906,6 +1023,313 @@ pamc_status pamc_synchronize(pamc_instance* I) {
   hipSetDevice(I->device);
   HIP_TRY(hipStreamSynchronize(I->stream), "kernel execution");
   return PAMC_OK;
+}
+
+
+// ===========================================================================
+// Continuous-batching server
+// ===========================================================================
+}  // extern "C"
+
+struct pamc_server {
+  struct Req {
+    uint64_t ticket;
+    int32_t n, objective;
+    std::vector<int32_t> rp, col, w;
+    uint64_t seed;
+    pamc_schedule sched;
+    int64_t est;
+    double t_submit;
+  };
+  struct Act {
+    uint64_t ticket;
+    pamc_instance* I;
+    Schedule s;
+    int32_t launched;
+    int32_t fresh;  // controller not yet set up
+    double t_submit, t_admit;
+  };
+  struct Fin {
+    pamc_result res;
+    std::vector<int8_t> spins;
+    double t_submit, t_admit, t_done;
+  };
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t budget = 0, in_use = 0;
+  int32_t max_slots = 0;
+  pamc_config cfg{};
+  uint64_t next_ticket = 1;
+  std::deque<Req> queue;
+  std::vector<Act> active;
+  std::unordered_map<uint64_t, Fin> done;
+  std::unordered_map<uint64_t, int> pending;  // ticket -> 0 queued, 1 active
+  pamc::Batch batch;
+  bool dirty = true;
+  Schedule* d_sched = nullptr;
+  int32_t* d_idx = nullptr;
+  int32_t* d_status = nullptr;
+  int32_t cap = 0;
+};
+
+namespace {
+
+double now_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device bytes a sparse instance of this graph will hold (the allocation
+// plan of build_sparse plus the per-run buffers), for admission.
+int64_t estimate_bytes(int32_t n, const int32_t* rp, const pamc_config& cfg, const pamc_schedule& sc) {
+  const int64_t R = cfg.replicas, np = (n + 3) & ~3, nnz = rp[n];
+  int64_t maxdeg = 0;
+  for (int32_t v = 0; v < n; ++v) maxdeg = std::max<int64_t>(maxdeg, rp[v + 1] - rp[v]);
+  bool pull = nnz <= 16 * (int64_t)n && maxdeg <= 64;
+  if (cfg.flags & PAMC_FLAG_FIELDS_PUSH) pull = false;
+  if (cfg.flags & PAMC_FLAG_FIELDS_PULL) pull = true;
+  int64_t b = 2 * R * np + (pull ? 0 : 8 * R * np);      // spins (+ fields), two buffers
+  b += 2 * 12 * R + 12 * R;                               // energies, lineage, resampling scratch
+  b += 8 * (nnz + 16) + 4 * (int64_t)(n + 1) + 5 * np;    // CSR, best, relabelling
+  b += 4 * (2 * (maxdeg * 127 + 1) + 1);                  // threshold table (|J| <= 127 assumed)
+  b += 4 * (int64_t)std::max(64, sc.sweeps) * (maxdeg + 1);  // class orders
+  b += 36 * (int64_t)std::max(sc.steps, 1) + 8192;        // trace, run state, counters
+  if (sc.augmented && sc.resample && sc.n_top > 0 && sc.mis_trials > 0) {
+    const int64_t t = std::min<int64_t>(sc.n_top, R);
+    b += t * sc.mis_trials * (np + 4) + 4 * t;
+  }
+  return b + 16 * 64;  // allocation granularity
+}
+
+pamc_status server_admit(pamc_server* S) {
+  while (!S->queue.empty() && (int32_t)S->active.size() < S->max_slots &&
+         S->in_use + S->queue.front().est <= S->budget) {
+    pamc_server::Req q = std::move(S->queue.front());
+    S->queue.pop_front();
+    pamc_config c = S->cfg;
+    c.seed = q.seed;
+    c.stream = S->stream;
+    pamc_instance* I = nullptr;
+    pamc_status st = pamc_create_instance_csr(q.n, q.rp.data(), q.col.data(), q.w.data(), PAMC_MEM_HOST,
+                                              q.objective, &c, &I);
+    Schedule s = to_sched(&q.sched);
+    if (!st) st = prepare_run(I, s);
+    if (st) {
+      if (I) free_instance(I);
+      S->pending.erase(q.ticket);
+      return st;
+    }
+    S->in_use += I->device_bytes;
+    S->active.push_back({q.ticket, I, s, 0, 1, q.t_submit, now_seconds()});
+    S->pending[q.ticket] = 1;
+    S->dirty = true;
+  }
+  return PAMC_OK;
+}
+
+pamc_status server_retire(pamc_server* S, const std::vector<int32_t>& status) {
+  std::vector<pamc_server::Act> keep;
+  keep.reserve(S->active.size());
+  for (size_t i = 0; i < S->active.size(); ++i) {
+    pamc_server::Act& a = S->active[i];
+    if (!(status[i] & 1)) {
+      keep.push_back(a);
+      continue;
+    }
+    pamc::RunState r;
+    pamc_status st = read_state(a.I, &r);
+    if (st) return st;
+    pamc_server::Fin f;
+    fill_result(a.I, r, &f.res);
+    f.spins.resize(a.I->n);
+    st = pamc_best(a.I, nullptr, nullptr, f.spins.data());
+    if (st) return st;
+    f.t_submit = a.t_submit;
+    f.t_admit = a.t_admit;
+    f.t_done = now_seconds();
+    S->in_use -= a.I->device_bytes;
+    free_instance(a.I);
+    S->pending.erase(a.ticket);
+    S->done.emplace(a.ticket, std::move(f));
+    S->dirty = true;
+  }
+  S->active.swap(keep);
+  return PAMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pamc_status pamc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, const pamc_config* cfg,
+                               pamc_server** out) {
+  if (!out) return fail(PAMC_ERR_INVALID_ARG, "NULL out");
+  *out = nullptr;
+  pamc_status st = check_cfg(cfg);
+  if (st) return st;
+  if (hbm_budget_bytes <= 0 || max_slots <= 0) return fail(PAMC_ERR_INVALID_ARG, "budget and slots must be positive");
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count), "hipGetDeviceCount");
+  if (cfg->device < 0 || cfg->device >= count) return fail(PAMC_ERR_INVALID_ARG, "bad device");
+  pamc_server* S = new (std::nothrow) pamc_server();
+  if (!S) return fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
+  S->device = cfg->device;
+  S->budget = hbm_budget_bytes;
+  S->max_slots = max_slots;
+  S->cfg = *cfg;
+  hipSetDevice(S->device);
+  if (cfg->stream) {
+    S->stream = (hipStream_t)cfg->stream;
+  } else if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess) {
+    S->own_stream = true;
+  } else {
+    delete S;
+    return fail(PAMC_ERR_DEVICE, "hipStreamCreate");
+  }
+  *out = S;
+  return PAMC_OK;
+}
+
+pamc_status pamc_server_submit(pamc_server* S, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                               const int32_t* w, int32_t objective, uint64_t seed,
+                               const pamc_schedule* sched, uint64_t* ticket) {
+  if (!S || !sched || !ticket) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  if (objective != PAMC_OBJ_MAXCUT && objective != PAMC_OBJ_ISING)
+    return fail(PAMC_ERR_INVALID_ARG, "unknown objective");
+  pamc_status st = validate_csr(n, row_ptr, col, w, false);
+  if (st) return st;
+  pamc_instance probe;  // schedule checks only look at the kind of instance
+  st = check_schedule(&probe, sched);
+  if (st) return st;
+  pamc_server::Req q;
+  q.est = estimate_bytes(n, row_ptr, S->cfg, *sched);
+  if (q.est > S->budget) return fail(PAMC_ERR_OUT_OF_MEMORY, "request larger than the server's memory budget");
+  q.ticket = S->next_ticket++;
+  q.n = n;
+  q.objective = objective;
+  q.rp.assign(row_ptr, row_ptr + n + 1);
+  q.col.assign(col, col + std::max(row_ptr[n], 1));
+  q.w.assign(w, w + std::max(row_ptr[n], 1));
+  if (row_ptr[n] == 0) q.col[0] = q.w[0] = 0;
+  q.seed = seed;
+  q.sched = *sched;
+  q.t_submit = now_seconds();
+  S->pending[q.ticket] = 0;
+  *ticket = q.ticket;
+  S->queue.push_back(std::move(q));
+  return PAMC_OK;
+}
+
+pamc_status pamc_server_tick(pamc_server* S, int32_t max_steps, int32_t* n_active, int32_t* n_queued) {
+  if (!S) return fail(PAMC_ERR_INVALID_ARG, "NULL server");
+  hipSetDevice(S->device);
+  pamc_status st = server_admit(S);
+  if (st) return st;
+  if (!S->active.empty()) {
+    const int32_t na = (int32_t)S->active.size();
+    if (S->dirty) {
+      std::vector<pamc_instance*> v;
+      std::vector<Schedule> sc;
+      for (auto& a : S->active) {
+        v.push_back(a.I);
+        sc.push_back(a.s);
+      }
+      HIP_TRY(pamc::batch_build(S->batch, v, &sc), "batch descriptors");
+      S->dirty = false;
+      if (na > S->cap) {
+        if (S->d_sched) hipFree(S->d_sched);
+        if (S->d_idx) hipFree(S->d_idx);
+        if (S->d_status) hipFree(S->d_status);
+        S->d_sched = nullptr;
+        S->d_idx = S->d_status = nullptr;
+        S->cap = std::max(na, 2 * S->cap);
+        HIP_TRY(hipMalloc((void**)&S->d_sched, sizeof(Schedule) * S->cap), "alloc");
+        HIP_TRY(hipMalloc((void**)&S->d_idx, sizeof(int32_t) * S->cap), "alloc");
+        HIP_TRY(hipMalloc((void**)&S->d_status, sizeof(int32_t) * S->cap), "alloc");
+      }
+    }
+    // controllers of the newly admitted requests (they sit at the end)
+    std::vector<Schedule> ns;
+    std::vector<int32_t> idx;
+    for (int32_t i = 0; i < na; ++i)
+      if (S->active[i].fresh) {
+        ns.push_back(S->active[i].s);
+        idx.push_back(i);
+        S->active[i].fresh = 0;
+      }
+    if (!idx.empty()) {
+      HIP_TRY(hipMemcpy(S->d_sched, ns.data(), sizeof(Schedule) * ns.size(), hipMemcpyHostToDevice), "upload");
+      HIP_TRY(hipMemcpy(S->d_idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice), "upload");
+      HIP_TRY(pamc::batch_anneal_setup(S->batch, S->d_sched, S->d_idx, (int32_t)idx.size()), "anneal setup");
+    }
+    // run until the first request can finish (or max_steps)
+    int32_t k = INT32_MAX;
+    for (auto& a : S->active) k = std::min(k, std::max(a.s.steps - a.launched, 1));
+    if (max_steps > 0) k = std::min(k, max_steps);
+    for (int32_t i = 0; i < k; ++i) HIP_TRY(pamc::batch_step(S->batch), "step");
+    for (auto& a : S->active) a.launched += k;
+    HIP_TRY(pamc::batch_status(S->batch, S->d_status), "status");
+    std::vector<int32_t> status(na);
+    HIP_TRY(hipMemcpyAsync(status.data(), S->d_status, sizeof(int32_t) * na, hipMemcpyDeviceToHost, S->stream), "readback");
+    HIP_TRY(hipStreamSynchronize(S->stream), "batched steps");
+    st = server_retire(S, status);
+    if (st) return st;
+  }
+  if (n_active) *n_active = (int32_t)S->active.size();
+  if (n_queued) *n_queued = (int32_t)S->queue.size();
+  return PAMC_OK;
+}
+
+pamc_status pamc_server_drain(pamc_server* S) {
+  if (!S) return fail(PAMC_ERR_INVALID_ARG, "NULL server");
+  while (!S->active.empty() || !S->queue.empty()) {
+    pamc_status st = pamc_server_tick(S, 0, nullptr, nullptr);
+    if (st) return st;
+  }
+  return PAMC_OK;
+}
+
+pamc_status pamc_server_poll(pamc_server* S, uint64_t ticket, int32_t* done, pamc_result* out, int8_t* spins) {
+  if (!S || !done) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  auto it = S->done.find(ticket);
+  if (it == S->done.end()) {
+    if (!S->pending.count(ticket)) return fail(PAMC_ERR_INVALID_ARG, "unknown ticket");
+    *done = 0;
+    return PAMC_OK;
+  }
+  *done = 1;
+  if (out) *out = it->second.res;
+  if (spins) memcpy(spins, it->second.spins.data(), it->second.spins.size());
+  return PAMC_OK;
+}
+
+pamc_status pamc_server_latency(pamc_server* S, uint64_t ticket, double* queued_seconds, double* total_seconds) {
+  if (!S) return fail(PAMC_ERR_INVALID_ARG, "NULL server");
+  auto it = S->done.find(ticket);
+  if (it == S->done.end()) return fail(PAMC_ERR_STATE, "request not finished");
+  if (queued_seconds) *queued_seconds = it->second.t_admit - it->second.t_submit;
+  if (total_seconds) *total_seconds = it->second.t_done - it->second.t_submit;
+  return PAMC_OK;
+}
+
+pamc_status pamc_server_forget(pamc_server* S, uint64_t ticket) {
+  if (!S) return fail(PAMC_ERR_INVALID_ARG, "NULL server");
+  if (!S->done.erase(ticket)) return fail(PAMC_ERR_STATE, "request not finished");
+  return PAMC_OK;
+}
+
+void pamc_server_destroy(pamc_server* S) {
+  if (!S) return;
+  hipSetDevice(S->device);
+  hipStreamSynchronize(S->stream);
+  for (auto& a : S->active) free_instance(a.I);
+  S->active.clear();
+  S->batch.free_device();
+  if (S->d_sched) hipFree(S->d_sched);
+  if (S->d_idx) hipFree(S->d_idx);
+  if (S->d_status) hipFree(S->d_status);
+  if (S->own_stream) hipStreamDestroy(S->stream);
+  delete S;
 }
 
 }  // extern "C"

@@ -250,6 +250,7 @@ __global__ void k_dense_init_finish(int64_t* E, int32_t R, RunState* st, int8_t*
     st->gs = st->g_rs = st->g_cl = 0;
     st->stopped = 0;
     st->active = 0;
+    st->steps_run = 0;
   }
 }
 
@@ -330,7 +331,8 @@ hipError_t launch_init_dense(pamc_instance* I) {
   return hipGetLastError();
 }
 
-static hipError_t dense_sweeps(pamc_instance* I, int32_t nsweeps) {
+static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
+  pamc_instance* I = b.I[0];
   const int P = num_partials(I->dn_pad);
   const int T = I->R / 64;
   SeqArgs a;
@@ -349,7 +351,7 @@ static hipError_t dense_sweeps(pamc_instance* I, int32_t nsweeps) {
   a.k0 = key0(I);
   a.k1 = key1(I);
   a.flip_ctr = I->prof ? I->flip_ctr : nullptr;
-  ctl_thresholds(I);
+  ctl_thresholds(b);
   for (int s = 0; s < nsweeps; ++s) {
     for (int row0 = 0; row0 < I->n; row0 += kDB) {
       hipEvent_t e0 = nullptr;
@@ -375,44 +377,47 @@ static hipError_t dense_sweeps(pamc_instance* I, int32_t nsweeps) {
   return hipGetLastError();
 }
 
-hipError_t launch_dense_step(pamc_instance* I, const Schedule& s, int32_t step) {
-  ctl_step_begin(I, step);
-  if (s.resample) {
-    ctl_resample_select(I);
-    k_dense_gather<<<dim3(std::max(1, std::min(64, I->dn_pad / 1024)), I->R), 256, 0, I->stream>>>(
-        I->st, I->Sd, I->Sd2, I->pop.E[0], I->pop.E[1], I->pop.fam[0], I->pop.fam[1], I->rs_parent,
-        I->dn_pad, I->R);
-  }
-  ctl_commit(I, 1);
-  hipError_t e = dense_sweeps(I, s.sweeps);
-  if (e != hipSuccess) return e;
-  ctl_step_end(I, 1);
-  return hipGetLastError();
-}
-
-hipError_t launch_dense_prim_sweep(pamc_instance* I, double beta, int32_t nsweeps) {
-  ctl_prim_set(I, 0, beta);
-  hipError_t e = dense_sweeps(I, nsweeps);
-  if (e != hipSuccess) return e;
-  ctl_advance(I, nsweeps);
-  return hipGetLastError();
-}
-
-hipError_t launch_dense_prim_resample(pamc_instance* I, double delta) {
-  ctl_prim_set(I, 1, delta);
-  ctl_resample_select(I);
+static void dense_gather(pamc_instance* I) {
   k_dense_gather<<<dim3(std::max(1, std::min(64, I->dn_pad / 1024)), I->R), 256, 0, I->stream>>>(
       I->st, I->Sd, I->Sd2, I->pop.E[0], I->pop.E[1], I->pop.fam[0], I->pop.fam[1], I->rs_parent,
       I->dn_pad, I->R);
-  ctl_commit(I, 0);
-  ctl_deactivate(I);
+}
+
+hipError_t launch_dense_step(Batch& b, int32_t sweeps, int32_t resample) {
+  pamc_instance* I = b.I[0];
+  ctl_step_begin(b);
+  if (resample) {
+    ctl_resample_select(b);
+    dense_gather(I);
+  }
+  ctl_commit(b, 1);
+  hipError_t e = dense_sweeps(b, sweeps);
+  if (e != hipSuccess) return e;
+  ctl_step_end(b, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_dense_prim_update_best(pamc_instance* I) {
-  ctl_prim_set(I, 0, 0.0);
-  ctl_step_end(I, 0);
-  ctl_deactivate(I);
+hipError_t launch_dense_prim_sweep(Batch& b, double beta, int32_t nsweeps) {
+  ctl_prim_set(b, 0, beta, nsweeps);
+  hipError_t e = dense_sweeps(b, nsweeps);
+  if (e != hipSuccess) return e;
+  ctl_advance(b, nsweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_prim_resample(Batch& b, double delta) {
+  ctl_prim_set(b, 1, delta, 0);
+  ctl_resample_select(b);
+  dense_gather(b.I[0]);
+  ctl_commit(b, 0);
+  ctl_deactivate(b);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_prim_update_best(Batch& b) {
+  ctl_prim_set(b, 0, 0.0, 0);
+  ctl_step_end(b, 0);
+  ctl_deactivate(b);
   return hipGetLastError();
 }
 

@@ -12,6 +12,8 @@
 
 namespace pamc {
 
+struct Batch;
+
 // Population layout.  Replicas are grouped in tiles of 64 (one wavefront, one
 // replica per lane).  Spins are quad-interleaved: the 32-bit word
 // S[(t*nq + q)*64 + l] holds the spins of vertices 4q..4q+3 of replica
@@ -96,6 +98,10 @@ struct pamc_instance {
   int64_t* flip_ctr = nullptr; // [256]
   // scratch for small readbacks
   void* pinned = nullptr;
+  // the instance as a batch of one (rebuilt when a buffer it names changes)
+  pamc::Batch* self = nullptr;
+  bool self_dirty = true;
+  void* d_sched = nullptr;  // device copy of the run's schedule
 };
 
 namespace pamc {
@@ -108,39 +114,103 @@ struct Schedule {
   int32_t stop_at_target, literal_break;
 };
 
-// sparse path launchers (sparse.hip); each returns a hipError_t
-hipError_t launch_init_sparse(pamc_instance* I);
-hipError_t launch_anneal_setup(pamc_instance* I, const Schedule& s);
-hipError_t launch_step(pamc_instance* I, const Schedule& s, int32_t step);
-hipError_t launch_prim_sweep(pamc_instance* I, double beta, int32_t nsweeps);
-hipError_t launch_prim_resample(pamc_instance* I, double delta);
-hipError_t launch_prim_cluster(pamc_instance* I, int32_t n_top, int32_t trials);
-hipError_t launch_prim_update_best(pamc_instance* I);
+// Per-instance descriptor read by every batched kernel: the device pointers
+// and sizes of one instance (copied to the device once per batch).
+struct Desc {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const int32_t* J;
+  const int32_t* class_ptr;
+  int32_t* order;
+  uint32_t* thr;
+  uint32_t *S0, *S1;
+  int32_t *H0, *H1;
+  int64_t *E0, *E1;
+  int32_t *F0, *F1;
+  int8_t* best;
+  RunState* st;
+  uint64_t* rs_P;
+  int32_t* rs_parent;
+  int32_t* cl_targets;
+  uint8_t* cl_sel;
+  int32_t* cl_sizes;
+  int64_t* cl_flipped;
+  int64_t* tr_mstar;
+  double* tr_beta;
+  double* tr_lnq;
+  int32_t* tr_events;
+  uint64_t* tr_time;
+  int64_t* flip_ctr;      // null unless profiling
+  const int8_t *D0, *D1;  // dense instances: replica-major spins [R][np]
+  int64_t W, X;
+  int32_t n, np, nq, R, T, ncls, rule, pull, dense, shuffle, tr_cap, order_cap;
+  uint32_t k0, k1;
+};
+
+// A set of instances advanced by the same launches.  Grid kernels read a map
+// of (instance << 32 | local block) words; one map per launch kind.
+struct Batch {
+  static constexpr int kGroups = 12;  // sweep kernel variants
+  static int group_of(const pamc_instance* I);
+  struct Launch {
+    uint64_t* map = nullptr;
+    int32_t grid = 0;
+  };
+  Launch init_spins, init_fields, thr, thr_dense, gather, cl_mis, cl_apply;
+  Launch sweep[kGroups];
+  Desc* d_desc = nullptr;
+  int32_t n = 0;
+  hipStream_t stream = nullptr;
+  std::vector<pamc_instance*> I;
+  int32_t max_ncls = 0, max_sweeps = 1, any_cluster = 0;
+  int64_t max_lds = 0;
+  void free_device();
+  Batch() = default;
+  Batch(const Batch&) = delete;
+  Batch& operator=(const Batch&) = delete;
+  ~Batch() { free_device(); }
+};
+
+Desc make_desc(const pamc_instance* I);
+// (Re)builds the batch's descriptors and maps; scheds (optional) give the
+// sweeps per step and whether cluster moves can occur.  Synchronises the
+// stream.
+hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const std::vector<Schedule>* scheds);
+hipError_t batch_init(Batch& b);                               // sparse instances
+// Loads schedules and clears the controller of the listed instances (all if
+// idx is null): instance idx[i] (or i) gets d_sched[i].
+hipError_t batch_anneal_setup(Batch& b, const Schedule* d_sched, const int32_t* d_idx, int32_t count);
+hipError_t batch_step(Batch& b);                               // one beta step of every live instance
+hipError_t batch_status(Batch& b, int32_t* d_out);             // (steps_run << 1) | stopped
+hipError_t prim_sweep(Batch& b, double beta, int32_t nsweeps);
+hipError_t prim_resample(Batch& b, double delta);
+hipError_t prim_cluster(Batch& b, int32_t n_top, int32_t trials);
+hipError_t prim_update_best(Batch& b);
+hipError_t launch_fields(Batch& b, int32_t buf, int32_t* H);
 hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
 hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
-hipError_t launch_fields(pamc_instance* I, int32_t* H);
 int32_t cluster_max_n();
 hipError_t prepare_cluster_lds();
 
 // controller pieces (sparse.hip) shared with the dense path
-hipError_t ctl_step_begin(pamc_instance* I, int32_t step);
-hipError_t ctl_resample_select(pamc_instance* I);
-hipError_t ctl_commit(pamc_instance* I, int32_t in_run);
-hipError_t ctl_thresholds(pamc_instance* I);
-hipError_t ctl_step_end(pamc_instance* I, int32_t in_run);
-hipError_t ctl_prim_set(pamc_instance* I, int32_t kind, double value);
-hipError_t ctl_advance(pamc_instance* I, int32_t nsweeps);
-hipError_t ctl_deactivate(pamc_instance* I);
+hipError_t ctl_step_begin(Batch& b);
+hipError_t ctl_resample_select(Batch& b);
+hipError_t ctl_commit(Batch& b, int32_t in_run);
+hipError_t ctl_thresholds(Batch& b);
+hipError_t ctl_step_end(Batch& b, int32_t in_run);
+hipError_t ctl_prim_set(Batch& b, int32_t kind, double value, int32_t nsweeps);
+hipError_t ctl_advance(Batch& b, int32_t nsweeps);
+hipError_t ctl_deactivate(Batch& b);
 hipEvent_t ctl_event(pamc_instance* I);
 
-// dense path launchers (dense.hip)
+// dense path launchers (dense.hip); b is the instance's batch of one
 int32_t dense_num_partials(int32_t np);
 hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor);
 hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed);
 hipError_t launch_init_dense(pamc_instance* I);
-hipError_t launch_dense_step(pamc_instance* I, const Schedule& s, int32_t step);
-hipError_t launch_dense_prim_sweep(pamc_instance* I, double beta, int32_t nsweeps);
-hipError_t launch_dense_prim_resample(pamc_instance* I, double delta);
-hipError_t launch_dense_prim_update_best(pamc_instance* I);
+hipError_t launch_dense_step(Batch& b, int32_t sweeps, int32_t resample);
+hipError_t launch_dense_prim_sweep(Batch& b, double beta, int32_t nsweeps);
+hipError_t launch_dense_prim_resample(Batch& b, double delta);
+hipError_t launch_dense_prim_update_best(Batch& b);
 
 }  // namespace pamc

@@ -12,6 +12,16 @@ namespace pamc {
 enum : uint32_t { kTagInit = 0, kTagSweep = 1, kTagResample = 2, kTagCluster = 3,
                   kTagOrder = 4, kTagDense = 5 };
 
+// Pointers in the global address space.  Device pointers read from a
+// descriptor table are generic to the compiler; casting them back lets it
+// emit global (and, for uniform read-only data, scalar) loads instead of
+// flat ones.
+#define PAMC_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ PAMC_GLOBAL T* gmem(T* p) {
+  return (PAMC_GLOBAL T*)p;
+}
+
 constexpr int kLanes = 64;      // replicas per tile = wavefront width
 constexpr int kHistCap = 64;    // controller history capacity (>= win_long)
 
@@ -132,6 +142,7 @@ struct RunState {
   int32_t step, active, do_resample, do_cluster, cur, best_slot;
   double rs_delta, sweep_beta;
   int32_t cl_n_top, cl_trials;
+  int32_t nsweeps_now, pad1;  // sweeps of the current step / primitive call
   int64_t table_x;   // half-width of the current threshold table
   // counters of the random streams
   uint32_t gs, g_rs, g_cl, pad0;
@@ -142,7 +153,7 @@ struct RunState {
   double sum_lnq, last_lnq;
   int32_t n_cluster_moves, n_reheats, n_reversals, n_restarts;
   int64_t flips, attempts, cl_flipped;
-  uint64_t t_start, t_reached;
+  uint64_t t_start, t_reached, t_last;  // device wall clock (100 MHz)
 };
 
 }  // namespace pamc

@@ -1,15 +1,23 @@
 // sparse.hip -- gfx950 kernels of the sparse PAMC path and of the
-// device-side controller (Algorithm 1), with their host launchers.
+// device-side controller (Algorithm 1), with their batch launchers.
 //
-// One β step of Algorithm 1 is a fixed sequence of launches whose behaviour
-// is decided on the device from RunState, so the host never waits inside a
-// run:
+// Every kernel works on a batch of instances: it reads the instance's
+// descriptor (Desc) and its device-resident run state, and grid kernels map
+// blockIdx through a per-batch table to (instance, local block).  A single
+// instance is a batch of one, so one code path serves the plain, batched and
+// served modes.  One beta step of Algorithm 1 is a fixed launch sequence
+// whose behaviour is decided on the device from RunState, so the host never
+// waits inside a run:
 //   step_begin -> rs_select -> rs_gather -> cl_select -> cl_mis -> cl_apply
 //   -> commit -> thresholds -> S x K sweep phases -> step_end
-// Kernels that have nothing to do in a step return at once.
+// Kernels with nothing to do for an instance return at once.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "instance.hpp"
 #include "pamc_device.hpp"
@@ -24,6 +32,20 @@ constexpr int kQuadsPerBlock = kSweepWaves * kQuadsPerWave;
 constexpr int kGatherQuadsPerBlock = 64;
 constexpr int kClusterMaxN = 26000;        // LDS: 5 bytes per vertex
 constexpr int kRsMaxR = 16384;
+constexpr int kThrLds = 2048;              // threshold entries staged in LDS when they fit
+constexpr int kThrBlocks = 16;             // threshold work-groups per instance
+constexpr int kInitBlocks = 64;            // spin-init work-groups per instance
+constexpr int kApplyChunks = 16;           // cluster-apply work-groups per target
+constexpr int kFieldBlocks = 1024;         // max field-init work-groups per instance
+constexpr uint32_t kIdle = 0xFFFFFFFFu;    // padding block: returns at once
+
+// Map word: instance index in the high half, local block in the low half.
+__device__ __forceinline__ bool resolve(const uint64_t* __restrict__ map, int& inst, int& lb) {
+  const uint64_t m = map[blockIdx.x];
+  inst = (int)(m >> 32);
+  lb = (int)(uint32_t)m;
+  return (uint32_t)m != kIdle;
+}
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
@@ -36,199 +58,35 @@ __device__ __forceinline__ int32_t spin_at(const uint32_t* S, int nq, int tile, 
   return (int32_t)(int8_t)(w >> (8 * (v & 3)));
 }
 
-// blockIdx -> (tile, chunk).  Work-groups are dealt round-robin to the eight
-// XCDs, so tile t is kept on XCD t % 8 when T is a multiple of 8: all field
-// atomics of a tile then meet in one L2.
-__device__ __forceinline__ void tile_chunk(int T, int& tile, int& chunk) {
-  const int b = blockIdx.x;
-  if ((T & 7) == 0) {
-    const int xcd = b & 7, j = b >> 3, tp = T >> 3;
-    tile = (j % tp) * 8 + xcd;
-    chunk = j / tp;
+// local block -> (tile group, chunk).  Work-groups are dealt round-robin to
+// the eight XCDs in launch order; an instance's blocks start at a multiple of
+// 8 in its map, so keeping a group's blocks 8 apart keeps group g on one XCD
+// when the group count is a multiple of 8.  Otherwise a plain split.
+__device__ __forceinline__ void group_chunk(int G, int lb, int& group, int& chunk) {
+  if ((G & 7) == 0) {
+    const int xcd = lb & 7, j = lb >> 3, gp = G >> 3;
+    group = (j % gp) * 8 + xcd;
+    chunk = j / gp;
   } else {
-    tile = b % T;
-    chunk = b / T;
-  }
-}
-
-
-// Field of Eq. 3 for vertex v of replica lane `lane` of a tile, gathered
-// from the neighbours' spin words.  Neighbours are taken four at a time with
-// unconditional loads (the CSR arrays carry kCsrPad trailing entries, and an
-// entry past the row is a valid vertex id), and the couplings of entries past
-// the row are masked to zero, so the loop body has no per-entry branches.
-// Srow points at the tile's spin words + lane.
-constexpr int kCsrPad = 8;
-template <bool SMALLJ>
-__device__ __forceinline__ int32_t gather_field(const int32_t* __restrict__ col,
-                                                const int32_t* __restrict__ J, int e0, int e1,
-                                                const uint32_t* __restrict__ Srow) {
-  int32_t h = 0;
-  for (int e = e0; e < e1; e += 4) {
-    const int cnt = e1 - e;
-    int j[4];
-    int32_t c[4];
-    uint32_t w[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      j[u] = col[e + u];
-      c[u] = J[e + u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) w[u] = Srow[(uint32_t)(j[u] >> 2) * (uint32_t)kLanes];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int32_t cu = u < cnt ? c[u] : 0;
-      const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[u], 8u * (uint32_t)(j[u] & 3), 8u);
-      // couplings below 2^23 in magnitude use the full-rate 24-bit multiply
-      h += SMALLJ ? __mul24(cu, sv) : cu * sv;
-    }
-  }
-  return h;
-}
-
-constexpr int kThrLds = 2048;  // threshold entries staged in LDS when they fit
-
-struct SweepArgs {
-  const int32_t* row_ptr;
-  const int32_t* col;
-  const int32_t* J;
-  const int32_t* class_ptr;
-  const int32_t* order;
-  uint32_t* S0;
-  uint32_t* S1;
-  int32_t* H0;
-  int32_t* H1;
-  int64_t* E0;
-  int64_t* E1;
-  const uint32_t* thr;
-  RunState* st;
-  int64_t* flip_ctr;
-  int32_t nq, np, T, ncls;
-  uint32_t k0, k1;
-};
-
-// ---------------------------------------------------------------------------
-// One colour class of one sweep (Eqs. 3-4).  Work-group = (replica tile,
-// chunk of the class's vertex quads); wave = up to 4 quads; lane = replica.
-// For each vertex: x = s*h, u = Philox word (quad, sweep, replica), flip iff
-// u < T[x] (Metropolis also for x <= 0); on a flip E += 2x and every
-// neighbour field gets 2 J s_new by a coalesced no-return atomic.  Vertices of
-// a class are mutually uncoupled, so no field read here is written here.
-// ---------------------------------------------------------------------------
-template <int RULE>
-__global__ void __launch_bounds__(256) k_sweep(const int32_t* __restrict__ row_ptr,
-                                                  const int32_t* __restrict__ col,
-                                                  const int32_t* __restrict__ Jc,
-                                                  const int32_t* __restrict__ class_ptr,
-                                                  const int32_t* __restrict__ order,
-                                                  const uint32_t* __restrict__ thr_g, SweepArgs a,
-                                                  int sweep_idx, int phase) {
-  __shared__ int64_t red[kSweepWaves][kLanes];
-  __shared__ int32_t fred[kSweepWaves];
-  __shared__ uint32_t thr_s[kThrLds];
-  RunState* st = a.st;
-  if (!st->active) return;
-  const int cur = st->cur;
-  uint32_t* __restrict__ S = cur ? a.S1 : a.S0;
-  int32_t* __restrict__ H = cur ? a.H1 : a.H0;
-  int64_t* __restrict__ E = cur ? a.E1 : a.E0;
-  const int cls = order[sweep_idx * a.ncls + phase];
-  const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
-  const int q0 = v0 >> 2;
-  const int nqc = ((v1 + 3) >> 2) - q0;
-  int tile, chunk;
-  tile_chunk(a.T, tile, chunk);
-  if (chunk * kQuadsPerBlock >= nqc) return;
-  const uint32_t gs = st->gs + (uint32_t)sweep_idx;
-  const int32_t Xt = (int32_t)st->table_x;
-  const bool thr_lds = 2 * Xt + 1 <= kThrLds;
-  if (thr_lds)
-    for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
-  __syncthreads();
-  const uint32_t* __restrict__ thr = thr_lds ? thr_s : a.thr;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t r = (uint32_t)(tile * kLanes + lane);
-  const size_t hbase = (size_t)tile * a.np;
-  int64_t dE = 0;
-  int32_t nflip = 0;
-  for (int i = 0; i < kQuadsPerWave; ++i) {
-    const int qi = chunk * kQuadsPerBlock + i * kSweepWaves + wave;
-    if (qi >= nqc) break;
-    const int q = q0 + qi;
-    const size_t sidx = ((size_t)tile * a.nq + q) * kLanes + lane;
-    uint32_t sw = S[sidx];
-    const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, a.k0, a.k1);
-    bool dirty = false;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int v = 4 * q + k;
-      if (v < v0 || v >= v1) continue;
-      const int32_t h = H[(hbase + v) * kLanes + lane];
-      const int32_t s = (int32_t)(int8_t)(sw >> (8 * k));
-      const int32_t x = s * h;
-      const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
-      const uint32_t T = thr[xi + Xt];
-      const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, k) < T);
-      const int32_t snew = -s;
-      if (flip) {
-        dE += 2 * (int64_t)x;
-        sw = (sw & ~(0xFFu << (8 * k))) | ((uint32_t)(uint8_t)(int8_t)snew << (8 * k));
-        dirty = true;
-        ++nflip;
-      }
-      if (__ballot(flip)) {
-        const int e0 = row_ptr[v], e1 = row_ptr[v + 1];
-        const int32_t d = 2 * snew;
-        for (int e = e0; e < e1; ++e) {
-          const int j = col[e];
-          const int32_t add = Jc[e] * d;
-          if (flip)
-            __hip_atomic_fetch_add(&H[(hbase + j) * kLanes + lane], add, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-    }
-    if (dirty) S[sidx] = sw;
-  }
-  red[wave][lane] = dE;
-  int32_t wf = 0;
-  if (a.flip_ctr) {
-    wf = nflip;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wf += __shfl_xor(wf, o, 64);
-    if (lane == 0) fred[wave] = wf;
-  }
-  __syncthreads();
-  if (wave == 0) {
-    int64_t t = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-    if (t != 0)
-      __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)t, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    if (a.flip_ctr && lane == 0) {
-      int64_t f = (int64_t)fred[0] + fred[1] + fred[2] + fred[3];
-      __hip_atomic_fetch_add((unsigned long long*)&a.flip_ctr[blockIdx.x & 255],
-                             (unsigned long long)f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    group = lb % G;
+    chunk = lb / G;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Same class phase with the local field of Eq. 3 gathered at visit time from
-// the neighbours' spins instead of being kept in a field array.  The integer
-// h and hence every decision are identical to the incremental form; what
-// changes is the memory traffic: no field array and no atomics, only spin
-// words (one byte per replica and vertex), which suits low-degree graphs.
+// Field of Eq. 3 for TPW tiles at once, gathered from the neighbours' spin
+// words.  The scalar work (CSR entries, neighbour offsets, coupling masks) is
+// shared by the tiles; the spin loads and arithmetic are per tile.
+// Neighbours are taken four at a time with unconditional loads (the CSR
+// arrays carry trailing padding, and an entry past the row is a valid vertex
+// id), and the couplings of entries past the row are masked to zero, so the
+// loop body has no per-entry branches.  Srow0 points at the first tile's
+// spin words + lane; tiles are tstride words apart.
 // ---------------------------------------------------------------------------
-// Fields of one vertex for TPW tiles at once: the scalar work (CSR entries,
-// neighbour offsets, coupling masks) is shared by the tiles, the spin loads
-// and arithmetic are per tile.  Srow0 points at the first tile's spin words
-// + lane; tiles are tstride words apart.
 template <bool SMALLJ, int TPW>
-__device__ __forceinline__ void gather_fields(const int32_t* __restrict__ col,
-                                              const int32_t* __restrict__ J, int e0, int e1,
-                                              const uint32_t* __restrict__ Srow0, uint32_t tstride,
+__device__ __forceinline__ void gather_fields(const PAMC_GLOBAL int32_t* __restrict__ col,
+                                              const PAMC_GLOBAL int32_t* __restrict__ J, int e0, int e1,
+                                              const PAMC_GLOBAL uint32_t* __restrict__ Srow0, uint32_t tstride,
                                               int32_t (&h)[TPW]) {
 #pragma unroll
   for (int t = 0; t < TPW; ++t) h[t] = 0;
@@ -252,46 +110,81 @@ __device__ __forceinline__ void gather_fields(const int32_t* __restrict__ col,
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[t][u], 8u * (uint32_t)(j[u] & 3), 8u);
+        // couplings below 2^23 in magnitude use the full-rate 24-bit multiply
         h[t] += SMALLJ ? __mul24(c[u], sv) : c[u] * sv;
       }
   }
 }
 
-template <int RULE, bool SMALLJ, int TPW>
-__global__ void __launch_bounds__(256) k_sweep_pull(const int32_t* __restrict__ row_ptr,
-                                                  const int32_t* __restrict__ col,
-                                                  const int32_t* __restrict__ Jc,
-                                                  const int32_t* __restrict__ class_ptr,
-                                                  const int32_t* __restrict__ order,
-                                                  const uint32_t* __restrict__ thr_g, SweepArgs a,
-                                                  int sweep_idx, int phase) {
-  __shared__ int64_t red[kSweepWaves][TPW][kLanes];
+__device__ __forceinline__ void reduce_energy_and_flips(int64_t (*red)[kLanes], int32_t* fred, int wave,
+                                                        int lane, int ntiles, int tile0,
+                                                        PAMC_GLOBAL int64_t* E, int32_t nflip,
+                                                        PAMC_GLOBAL int64_t* flip_ctr) {
+  if (flip_ctr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nflip += __shfl_xor(nflip, o, 64);
+    if (lane == 0) fred[wave] = nflip;
+  }
+  __syncthreads();
+  if (wave < ntiles) {
+    const int t = wave;
+    int64_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < kSweepWaves; ++w) sum += red[w * ntiles + t][lane];
+    if (sum != 0)
+      __hip_atomic_fetch_add((unsigned long long*)&E[(tile0 + t) * kLanes + lane], (unsigned long long)sum,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (flip_ctr && threadIdx.x == 0) {
+    const int64_t f = (int64_t)fred[0] + fred[1] + fred[2] + fred[3];
+    __hip_atomic_fetch_add((unsigned long long*)&flip_ctr[blockIdx.x & 255], (unsigned long long)f,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One colour class of one sweep with fields gathered at visit time (Eqs.
+// 3-4).  Work-group = (group of TPW replica tiles, chunk of the class's
+// vertex quads); wave = up to 4 quads; lane = replica.  For each vertex:
+// x = s*h, u = Philox word (quad, sweep, replica), flip iff u < T[x]
+// (Metropolis also for x <= 0).  Vertices of a class are mutually
+// uncoupled, so no spin read here as a neighbour is written here.
+// ---------------------------------------------------------------------------
+template <bool SMALLJ, int TPW>
+__device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __restrict__ row_ptr,
+                                                const PAMC_GLOBAL int32_t* __restrict__ col,
+                                                const PAMC_GLOBAL int32_t* __restrict__ Jc,
+                                                const PAMC_GLOBAL int32_t* __restrict__ class_ptr,
+                                                const PAMC_GLOBAL int32_t* __restrict__ order,
+                                                const PAMC_GLOBAL uint32_t* __restrict__ thr_g, const Desc& d,
+                                                int lb, int sweep_idx, int phase) {
+  __shared__ int64_t red[kSweepWaves * TPW][kLanes];
   __shared__ int32_t fred[kSweepWaves];
   __shared__ uint32_t thr_s[kThrLds];
-  RunState* st = a.st;
-  if (!st->active) return;
+  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
   const int cur = st->cur;
-  uint32_t* __restrict__ S = cur ? a.S1 : a.S0;
-  int64_t* __restrict__ E = cur ? a.E1 : a.E0;
-  const int cls = order[sweep_idx * a.ncls + phase];
+  PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0);
+  PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
+  const int cls = order[sweep_idx * d.ncls + phase];
   const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
   const int q0 = v0 >> 2;
   const int nqc = ((v1 + 3) >> 2) - q0;
   int group, chunk;
-  tile_chunk(a.T / TPW, group, chunk);
+  group_chunk(d.T / TPW, lb, group, chunk);
   if (chunk * kQuadsPerBlock >= nqc) return;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
+  const int rule = d.rule;
   const int32_t Xt = (int32_t)st->table_x;
   const bool thr_lds = 2 * Xt + 1 <= kThrLds;
   if (thr_lds)
     for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
   __syncthreads();
-  const uint32_t* __restrict__ thr = thr_lds ? thr_s : thr_g;
+  const uint32_t* __restrict__ thr = thr_lds ? thr_s : (const uint32_t*)thr_g;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile0 = group * TPW;
-  const uint32_t tstride = (uint32_t)a.nq * kLanes;
-  uint32_t* __restrict__ Srow0 = S + (size_t)tile0 * tstride + lane;
+  const uint32_t tstride = (uint32_t)d.nq * kLanes;
+  PAMC_GLOBAL uint32_t* __restrict__ Srow0 = S + (size_t)tile0 * tstride + lane;
   int64_t dE[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) dE[t] = 0;
@@ -317,7 +210,7 @@ __global__ void __launch_bounds__(256) k_sweep_pull(const int32_t* __restrict__ 
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const uint32_t r = (uint32_t)((tile0 + t) * kLanes + lane);
-      const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, a.k0, a.k1);
+      const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
       bool dirty = false;
       uint32_t swt = sw[t];
 #pragma unroll
@@ -328,7 +221,7 @@ __global__ void __launch_bounds__(256) k_sweep_pull(const int32_t* __restrict__ 
         const int32_t x = s * h[k][t];
         const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
         const uint32_t T = thr[xi + Xt];
-        const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, k) < T);
+        const bool flip = (rule == 1 && x <= 0) || (pick(rnd, k) < T);
         if (flip) {
           dE[t] += 2 * (int64_t)x;
           swt ^= (0xFEu << (8 * k));  // +1 (0x01) <-> -1 (0xFF)
@@ -340,26 +233,118 @@ __global__ void __launch_bounds__(256) k_sweep_pull(const int32_t* __restrict__ 
     }
   }
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) red[wave][t][lane] = dE[t];
-  if (a.flip_ctr) {
-    int32_t wf = nflip;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wf += __shfl_xor(wf, o, 64);
-    if (lane == 0) fred[wave] = wf;
-  }
+  for (int t = 0; t < TPW; ++t) red[wave * TPW + t][lane] = dE[t];
+  reduce_energy_and_flips(red, fred, wave, lane, TPW, tile0, E, nflip, gmem(d.flip_ctr));
+}
+
+template <bool SMALLJ, int TPW>
+__global__ void __launch_bounds__(256) k_sweep_pull(const Desc* __restrict__ D,
+                                                  const uint64_t* __restrict__ map, int sweep_idx,
+                                                  int phase) {
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& d = D[inst];
+  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
+  if (!st->active || sweep_idx >= st->nsweeps_now || phase >= d.ncls) return;
+  sweep_pull_body<SMALLJ, TPW>(gmem(d.row_ptr), gmem(d.col), gmem(d.J), gmem(d.class_ptr), gmem((const int32_t*)d.order),
+                               gmem((const uint32_t*)d.thr), d, lb, sweep_idx, phase);
+}
+
+// ---------------------------------------------------------------------------
+// The same class phase with incremental fields: x = s*h from the field
+// array; on a flip E += 2x and every neighbour field gets 2 J s_new by a
+// coalesced no-return atomic.  Used where gathering is dearer (high degree,
+// hub vertices).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __restrict__ row_ptr,
+                                                const PAMC_GLOBAL int32_t* __restrict__ col,
+                                                const PAMC_GLOBAL int32_t* __restrict__ Jc,
+                                                const PAMC_GLOBAL int32_t* __restrict__ class_ptr,
+                                                const PAMC_GLOBAL int32_t* __restrict__ order,
+                                                const PAMC_GLOBAL uint32_t* __restrict__ thr_g, const Desc& d,
+                                                int lb, int sweep_idx, int phase) {
+  __shared__ int64_t red[kSweepWaves][kLanes];
+  __shared__ int32_t fred[kSweepWaves];
+  __shared__ uint32_t thr_s[kThrLds];
+  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
+  const int cur = st->cur;
+  PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0);
+  PAMC_GLOBAL int32_t* H = gmem(cur ? d.H1 : d.H0);
+  PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
+  const int cls = order[sweep_idx * d.ncls + phase];
+  const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
+  const int q0 = v0 >> 2;
+  const int nqc = ((v1 + 3) >> 2) - q0;
+  int tile, chunk;
+  group_chunk(d.T, lb, tile, chunk);
+  if (chunk * kQuadsPerBlock >= nqc) return;
+  const uint32_t gs = st->gs + (uint32_t)sweep_idx;
+  const int rule = d.rule;
+  const int32_t Xt = (int32_t)st->table_x;
+  const bool thr_lds = 2 * Xt + 1 <= kThrLds;
+  if (thr_lds)
+    for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
   __syncthreads();
-  if (wave < TPW) {
-    const int t = wave;
-    const int64_t sum = red[0][t][lane] + red[1][t][lane] + red[2][t][lane] + red[3][t][lane];
-    if (sum != 0)
-      __hip_atomic_fetch_add((unsigned long long*)&E[(tile0 + t) * kLanes + lane],
-                             (unsigned long long)sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t* __restrict__ thr = thr_lds ? thr_s : (const uint32_t*)thr_g;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t r = (uint32_t)(tile * kLanes + lane);
+  const size_t hbase = (size_t)tile * d.np;
+  int64_t dE = 0;
+  int32_t nflip = 0;
+  for (int i = 0; i < kQuadsPerWave; ++i) {
+    const int qi = chunk * kQuadsPerBlock + i * kSweepWaves + wave;
+    if (qi >= nqc) break;
+    const int q = q0 + qi;
+    const size_t sidx = ((size_t)tile * d.nq + q) * kLanes + lane;
+    uint32_t sw = S[sidx];
+    const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
+    bool dirty = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int v = 4 * q + k;
+      if (v < v0 || v >= v1) continue;
+      const int32_t h = H[(hbase + v) * kLanes + lane];
+      const int32_t s = (int32_t)(int8_t)(sw >> (8 * k));
+      const int32_t x = s * h;
+      const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
+      const uint32_t T = thr[xi + Xt];
+      const bool flip = (rule == 1 && x <= 0) || (pick(rnd, k) < T);
+      const int32_t snew = -s;
+      if (flip) {
+        dE += 2 * (int64_t)x;
+        sw ^= (0xFEu << (8 * k));
+        dirty = true;
+        ++nflip;
+      }
+      if (__ballot(flip)) {
+        const int e0 = row_ptr[v], e1 = row_ptr[v + 1];
+        const int32_t dd = 2 * snew;
+        for (int e = e0; e < e1; ++e) {
+          const int j = col[e];
+          const int32_t add = Jc[e] * dd;
+          if (flip)
+            __hip_atomic_fetch_add(&H[(hbase + j) * kLanes + lane], add, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    if (dirty) S[sidx] = sw;
   }
-  if (a.flip_ctr && threadIdx.x == 0) {
-    const int64_t f = (int64_t)fred[0] + fred[1] + fred[2] + fred[3];
-    __hip_atomic_fetch_add((unsigned long long*)&a.flip_ctr[blockIdx.x & 255], (unsigned long long)f,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  red[wave][lane] = dE;
+  reduce_energy_and_flips(red, fred, wave, lane, 1, tile, E, nflip, gmem(d.flip_ctr));
+}
+
+__global__ void __launch_bounds__(256) k_sweep_push(const Desc* __restrict__ D,
+                                                  const uint64_t* __restrict__ map, int sweep_idx,
+                                                  int phase) {
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& d = D[inst];
+  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
+  if (!st->active || sweep_idx >= st->nsweeps_now || phase >= d.ncls) return;
+  sweep_push_body(gmem(d.row_ptr), gmem(d.col), gmem(d.J), gmem(d.class_ptr), gmem((const int32_t*)d.order),
+                  gmem((const uint32_t*)d.thr), d, lb, sweep_idx, phase);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,75 +352,99 @@ __global__ void __launch_bounds__(256) k_sweep_pull(const int32_t* __restrict__ 
 // Philox(quad, 0, replica, INIT) (spin +1 iff the word < 2^31); then local
 // fields by Eq. 3 and energies H = -1/2 sum s h.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_init_spins(uint32_t* S, int32_t* fam, int32_t n, int32_t nq,
-                                                    int32_t T, uint32_t k0, uint32_t k1) {
-  const size_t total = (size_t)T * nq * kLanes;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-       i += (size_t)gridDim.x * blockDim.x) {
+__global__ void __launch_bounds__(256) k_init_spins(const Desc* __restrict__ D,
+                                                    const uint64_t* __restrict__ map) {
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& d = D[inst];
+  const size_t total = (size_t)d.T * d.nq * kLanes;
+  for (size_t i = (size_t)lb * blockDim.x + threadIdx.x; i < total; i += (size_t)kInitBlocks * blockDim.x) {
     const int lane = (int)(i & 63);
     const size_t tq = i >> 6;
-    const int q = (int)(tq % nq);
-    const int tile = (int)(tq / nq);
+    const int q = (int)(tq % d.nq);
+    const int tile = (int)(tq / d.nq);
     const uint32_t r = (uint32_t)(tile * kLanes + lane);
-    const u32x4 w = philox10((uint32_t)q, 0u, r, kTagInit, k0, k1);
+    const u32x4 w = philox10((uint32_t)q, 0u, r, kTagInit, d.k0, d.k1);
     uint32_t sw = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
       int8_t s = 0;
-      if (v < n) s = pick(w, k) < 0x80000000u ? (int8_t)1 : (int8_t)-1;
+      if (v < d.n) s = pick(w, k) < 0x80000000u ? (int8_t)1 : (int8_t)-1;
       sw |= (uint32_t)(uint8_t)s << (8 * k);
     }
-    S[i] = sw;
-    if (q == 0) fam[r] = (int32_t)r;
+    d.S0[i] = sw;
+    if (q == 0) d.F0[r] = (int32_t)r;
   }
 }
 
-// h = J s per (tile, vertex) row; accumulates -s h / 2 into E.
-__global__ void __launch_bounds__(256) k_init_fields(const int32_t* row_ptr, const int32_t* col,
-                                                     const int32_t* J, const uint32_t* S, int32_t* H,
-                                                     int64_t* E, int32_t n, int32_t np, int32_t nq,
-                                                     int32_t T) {
+// h = J s per (tile, vertex) row of buffer `buf` (-1: the current one);
+// writes H (Hout if given, else the instance's field array if it has one)
+// and, if asked, accumulates sum s h into E.  Work item = (64-vertex chunk,
+// tile), dealt to the instance's min(items, kFieldBlocks) work-groups.
+__global__ void __launch_bounds__(256) k_init_fields(const Desc* __restrict__ D,
+                                                     const uint64_t* __restrict__ map, int32_t buf,
+                                                     int32_t* Hout, int32_t accumulate_energy) {
   __shared__ int64_t red[4][kLanes];
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& d = D[inst];
+  const int b = buf < 0 ? d.st->cur : buf;
+  const uint32_t* S = b ? d.S1 : d.S0;
+  int32_t* H = Hout ? Hout : (b ? d.H1 : d.H0);
+  int64_t* E = accumulate_energy ? (b ? d.E1 : d.E0) : nullptr;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tile = blockIdx.x % T;
-  const int vchunk = blockIdx.x / T;
-  int64_t acc = 0;
-  for (int v = vchunk * 64 + wave; v < n && v < (vchunk + 1) * 64; v += 4) {
-    int64_t h = 0;
-    for (int e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
-      h += (int64_t)J[e] * spin_at(S, nq, tile, col[e], lane);
-    if (H) H[((size_t)tile * np + v) * kLanes + lane] = (int32_t)h;
-    acc += h * spin_at(S, nq, tile, v, lane);
-  }
-  red[wave][lane] = acc;
-  __syncthreads();
-  if (wave == 0 && E) {
-    const int64_t t = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-    if (t != 0)
-      __hip_atomic_fetch_add((unsigned long long*)&E[tile * kLanes + lane],
-                             (unsigned long long)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int64_t items = (int64_t)d.T * ((d.n + 63) / 64);
+  const int64_t nblocks = items < kFieldBlocks ? items : kFieldBlocks;
+  for (int64_t it = lb; it < items; it += nblocks) {
+    const int tile = (int)(it % d.T);
+    const int vchunk = (int)(it / d.T);
+    int64_t acc = 0;
+    for (int v = vchunk * 64 + wave; v < d.n && v < (vchunk + 1) * 64; v += 4) {
+      int64_t h = 0;
+      for (int e = d.row_ptr[v]; e < d.row_ptr[v + 1]; ++e)
+        h += (int64_t)d.J[e] * spin_at(S, d.nq, tile, d.col[e], lane);
+      if (H) H[((size_t)tile * d.np + v) * kLanes + lane] = (int32_t)h;
+      acc += h * spin_at(S, d.nq, tile, v, lane);
+    }
+    __syncthreads();
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && E) {
+      const int64_t t = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+      if (t != 0)
+        __hip_atomic_fetch_add((unsigned long long*)&E[tile * kLanes + lane], (unsigned long long)t,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
-// E currently holds sum_v s_v h_v (= 2 sum_{i<j} J s s); H = -that / 2.
-__global__ void k_init_finish(int64_t* E, int32_t R, RunState* st, int8_t* best, int32_t np) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < R) E[i] = -(E[i] / 2);
-  for (int v = i; v < np; v += gridDim.x * blockDim.x) best[v] = 1;
-  if (i == 0) {
+// E currently holds sum_v s_v h_v (= 2 sum_{i<j} J s s); H = -that / 2.  One
+// work-group per instance.
+__global__ void __launch_bounds__(256) k_init_finish(const Desc* __restrict__ D) {
+  const Desc& d = D[blockIdx.x];
+  for (int i = threadIdx.x; i < d.R; i += blockDim.x) d.E0[i] = -(d.E0[i] / 2);
+  for (int v = threadIdx.x; v < d.np; v += blockDim.x) d.best[v] = 1;
+  if (threadIdx.x == 0) {
+    RunState* st = d.st;
     st->mstar = 0;
     st->cur = 0;
     st->gs = st->g_rs = st->g_cl = 0;
     st->stopped = 0;
     st->active = 0;
+    st->steps_run = 0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Controller kernels (single thread): Algorithm 1's per-step decisions.
+// Controller kernels (one thread per instance): Algorithm 1's decisions.
 // ---------------------------------------------------------------------------
-__global__ void k_anneal_setup(RunState* st, Schedule s) {
+__global__ void k_anneal_setup(const Desc* __restrict__ D, const Schedule* __restrict__ sched,
+                               const int32_t* __restrict__ idx, int32_t count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  RunState* st = D[idx ? idx[i] : i].st;
+  const Schedule s = sched[i];
   st->beta0 = s.beta0;
   st->dbeta = s.dbeta;
   st->reheat = s.reheat;
@@ -470,54 +479,67 @@ __global__ void k_anneal_setup(RunState* st, Schedule s) {
   st->n_cluster_moves = st->n_reheats = st->n_reversals = st->n_restarts = 0;
   st->t_start = wall_clock64();
   st->t_reached = 0;
+  st->t_last = st->t_start;
 }
 
-__global__ void k_step_begin(RunState* st, int32_t step, int64_t X) {
-  if (st->stopped || (st->stop_at_target && st->mstar >= st->target)) {
+__global__ void k_step_begin(const Desc* __restrict__ D, int32_t ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  RunState* st = D[i].st;
+  if (st->stopped || st->steps_run >= st->steps || (st->stop_at_target && st->mstar >= st->target)) {
     st->stopped = 1;
     st->active = 0;
     return;
   }
   st->active = 1;
-  st->step = step;
+  st->step = st->steps_run;
   st->do_resample = (st->z > 1 && st->resample) ? 1 : 0;
   st->do_cluster = (st->do_resample && st->augmented && st->enable && st->cooldown == 0) ? 1 : 0;
   st->rs_delta = st->delta;
   st->sweep_beta = st->beta;
+  st->nsweeps_now = st->sweeps;
   st->cl_n_top = st->n_top;
   st->cl_trials = st->mis_trials;
-  st->table_x = table_halfwidth(st->beta, X);
+  st->table_x = table_halfwidth(st->beta, D[i].X);
   st->last_lnq = 0.0;
 }
 
 // Primitive calls: one data-parallel action outside a run.
-__global__ void k_prim_set(RunState* st, int32_t kind, double value, int32_t n_top, int32_t trials,
-                           int64_t X) {
+__global__ void k_prim_set(const Desc* __restrict__ D, int32_t ninst, int32_t kind, double value,
+                           int32_t n_top, int32_t trials, int32_t nsweeps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  RunState* st = D[i].st;
   st->active = 1;
   st->do_resample = kind == 1;
   st->do_cluster = kind == 2;
   st->rs_delta = value;
   st->sweep_beta = value;
+  st->nsweeps_now = nsweeps;
   st->cl_n_top = n_top;
   st->cl_trials = trials;
-  st->table_x = table_halfwidth(value, X);
+  st->table_x = table_halfwidth(value, D[i].X);
   st->last_lnq = 0.0;
 }
 
 // After resampling / cluster move: switch population buffers and advance the
 // stream counters; in a run also apply Algorithm 1's "enable <- false;
 // cooldown <- tau" after a cluster move.
-__global__ void k_commit(RunState* st, int32_t in_run, double* tr_lnq, int32_t tr_cap) {
+__global__ void k_commit(const Desc* __restrict__ D, int32_t ninst, int32_t in_run) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  const Desc& d = D[i];
+  RunState* st = d.st;
   if (!st->active) return;
   if (st->do_resample) {
     st->cur ^= 1;
     st->g_rs += 1;
     if (in_run) {
       st->sum_lnq += st->last_lnq;
-      if (st->step < tr_cap) tr_lnq[st->step] = st->last_lnq;
+      if (st->step < d.tr_cap) d.tr_lnq[st->step] = st->last_lnq;
     }
-  } else if (in_run && st->step < tr_cap) {
-    tr_lnq[st->step] = 0.0;
+  } else if (in_run && st->step < d.tr_cap) {
+    d.tr_lnq[st->step] = 0.0;
   }
   if (st->do_cluster) {
     st->g_cl += 1;
@@ -532,23 +554,26 @@ __global__ void k_commit(RunState* st, int32_t in_run, double* tr_lnq, int32_t t
 // Threshold table for the step's beta (entries x = -Xt..Xt) and the class
 // order of each of the step's sweeps: a Fisher-Yates shuffle driven by
 // Philox(i, sweep, 0, ORDER), j = floor(u (i+1) / 2^32).
-__global__ void __launch_bounds__(256) k_thresholds(RunState* st, uint32_t* thr, int32_t rule,
-                                                    int32_t* order, int32_t ncls, int32_t nsweeps,
-                                                    int32_t shuffle, uint32_t k0, uint32_t k1) {
+__global__ void __launch_bounds__(256) k_thresholds(const Desc* __restrict__ D,
+                                                    const uint64_t* __restrict__ map) {
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& d = D[inst];
+  const RunState* st = d.st;
   if (!st->active) return;
   const int64_t Xt = st->table_x;
   const double beta = st->sweep_beta;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= 2 * Xt;
-       i += (int64_t)gridDim.x * blockDim.x)
-    thr[i] = flip_threshold(beta, rule, i - Xt);
-  if (blockIdx.x == 0) {
-    for (int s = threadIdx.x; s < nsweeps; s += blockDim.x) {
-      int32_t* o = order + (size_t)s * ncls;
-      for (int k = 0; k < ncls; ++k) o[k] = k;
-      if (shuffle) {
+  for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i <= 2 * Xt; i += (int64_t)kThrBlocks * blockDim.x)
+    d.thr[i] = flip_threshold(beta, d.rule, i - Xt);
+  if (lb == 0 && d.ncls > 0) {
+    const int nsw = min(st->nsweeps_now, d.order_cap);
+    for (int s = threadIdx.x; s < nsw; s += blockDim.x) {
+      int32_t* o = d.order + (size_t)s * d.ncls;
+      for (int k = 0; k < d.ncls; ++k) o[k] = k;
+      if (d.shuffle) {
         const uint32_t gs = st->gs + (uint32_t)s;
-        for (int i = ncls - 1; i >= 1; --i) {
-          const u32x4 w = philox10((uint32_t)i, gs, 0u, kTagOrder, k0, k1);
+        for (int i = d.ncls - 1; i >= 1; --i) {
+          const u32x4 w = philox10((uint32_t)i, gs, 0u, kTagOrder, d.k0, d.k1);
           const int j = (int)(((uint64_t)w.a * (uint64_t)(i + 1)) >> 32);
           const int32_t t = o[i];
           o[i] = o[j];
@@ -562,48 +587,28 @@ __global__ void __launch_bounds__(256) k_thresholds(RunState* st, uint32_t* thr,
 // ---------------------------------------------------------------------------
 // Best cut (Algorithm 1: M* <- max(M*, max Cut(P)), lowest slot on ties),
 // then, in a run, the recent-progress history, the adaptive temperature rule
-// and the schedule advance.
+// and the schedule advance.  One work-group per instance.
 // ---------------------------------------------------------------------------
-struct StepEndArgs {
-  RunState* st;
-  int64_t* E0;
-  int64_t* E1;
-  const uint32_t* S0;
-  const uint32_t* S1;
-  int8_t* best;
-  int64_t W;
-  int32_t R, nq, np;
-  int64_t* tr_mstar;
-  double* tr_beta;
-  int32_t* tr_events;
-  uint64_t* tr_time;
-  int32_t tr_cap;
-  int32_t ev_bits_extra;
-  const int8_t* D0;  // dense instances: replica-major spins [R][np]
-  const int8_t* D1;
-  int32_t dense;
-};
-
 __device__ int32_t distinct_tail(const int64_t* h, int len, int w) {
-  int d = 0;
+  int dcount = 0;
   for (int i = len - w; i < len; ++i) {
     bool dup = false;
     for (int j = len - w; j < i; ++j)
       if (h[j] == h[i]) { dup = true; break; }
-    if (!dup) ++d;
+    if (!dup) ++dcount;
   }
-  return d;
+  return dcount;
 }
 
-__global__ void __launch_bounds__(1024) k_step_end(StepEndArgs a, int32_t in_run) {
+__global__ void __launch_bounds__(1024) k_step_end(const Desc* __restrict__ D, int32_t in_run) {
   __shared__ int64_t bc[1024];
   __shared__ int32_t bs[1024];
   __shared__ int improved;
+  const Desc& a = D[blockIdx.x];
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
   const int64_t* E = cur ? a.E1 : a.E0;
-  const uint32_t* S = cur ? a.S1 : a.S0;
   int64_t c = INT64_MIN;
   int32_t cs = 0x7FFFFFFF;
   for (int r = threadIdx.x; r < a.R; r += blockDim.x) {
@@ -630,9 +635,10 @@ __global__ void __launch_bounds__(1024) k_step_end(StepEndArgs a, int32_t in_run
   __syncthreads();
   if (improved) {
     if (a.dense) {
-      const int8_t* D = (cur ? a.D1 : a.D0) + (size_t)slot * a.np;
-      for (int v = threadIdx.x; v < a.np; v += blockDim.x) a.best[v] = D[v];
+      const int8_t* Dsp = (cur ? a.D1 : a.D0) + (size_t)slot * a.np;
+      for (int v = threadIdx.x; v < a.np; v += blockDim.x) a.best[v] = Dsp[v];
     } else {
+      const uint32_t* S = cur ? a.S1 : a.S0;
       const int tile = slot >> 6, lane = slot & 63;
       for (int v = threadIdx.x; v < a.np; v += blockDim.x) {
         const uint32_t w = S[((size_t)tile * a.nq + (v >> 2)) * kLanes + lane];
@@ -699,6 +705,7 @@ __global__ void __launch_bounds__(1024) k_step_end(StepEndArgs a, int32_t in_run
   }
   st->gs += (uint32_t)st->sweeps;
   st->steps_run = st->step + 1;
+  st->t_last = now;
   if (st->step < a.tr_cap) {
     a.tr_mstar[st->step] = ms;
     a.tr_beta[st->step] = st->sweep_beta;
@@ -706,22 +713,34 @@ __global__ void __launch_bounds__(1024) k_step_end(StepEndArgs a, int32_t in_run
     a.tr_time[st->step] = now;
   }
   if (st->stop_at_target && ms >= st->target) st->stopped = 1;
+  if (st->steps_run >= st->steps) st->stopped = 1;
 }
 
-__global__ void k_advance_sweeps(RunState* st, int32_t nsweeps) {
-  st->gs += (uint32_t)nsweeps;
-  st->active = 0;
+__global__ void k_advance_sweeps(const Desc* __restrict__ D, int32_t ninst, int32_t nsweeps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  D[i].st->gs += (uint32_t)nsweeps;
+  D[i].st->active = 0;
 }
 
-__global__ void k_deactivate(RunState* st) { st->active = 0; }
+__global__ void k_deactivate(const Desc* __restrict__ D, int32_t ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) D[i].st->active = 0;
+}
+
+// Per-instance status words for the host: bit 0 stopped, bits 1.. steps run.
+__global__ void k_status(const Desc* __restrict__ D, int32_t ninst, int32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) out[i] = (D[i].st->steps_run << 1) | (D[i].st->stopped ? 1 : 0);
+}
 
 // ---------------------------------------------------------------------------
-// Resampling (Eqs. 1-2), one work-group.  Weights relative to the extreme
-// energy, w_r = e^{-Delta (E_r - E_ref)} in binary64; ln Q = -Delta E_ref +
-// ln sum w - ln R.  Selection is exact integer arithmetic: q_r =
-// floor(w_r 2^48), inclusive prefix P, child k draws a 64-bit Philox word u,
-// y = floor(u Q / 2^64), parent = least j with P_j > y; children are then
-// laid out by parent (counting sort).
+// Resampling (Eqs. 1-2), one work-group per instance.  Weights relative to
+// the extreme energy, w_r = e^{-Delta (E_r - E_ref)} in binary64; ln Q =
+// -Delta E_ref + ln sum w - ln R.  Selection is exact integer arithmetic:
+// q_r = floor(w_r 2^48), inclusive prefix P, child k draws a 64-bit Philox
+// word u, y = floor(u Q / 2^64), parent = least j with P_j > y; children are
+// then laid out by parent (counting sort).
 // ---------------------------------------------------------------------------
 template <typename V>
 __device__ V block_scan_incl(V x, V* tmp) {  // 1024 threads, Hillis-Steele
@@ -738,21 +757,12 @@ __device__ V block_scan_incl(V x, V* tmp) {  // 1024 threads, Hillis-Steele
   return r;
 }
 
-struct RsArgs {
-  RunState* st;
-  int64_t* E0;
-  int64_t* E1;
-  uint64_t* P;
-  int32_t* parent;
-  int32_t R;
-  uint32_t k0, k1;
-};
-
-__global__ void __launch_bounds__(1024) k_rs_select(RsArgs a) {
+__global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D) {
   __shared__ int32_t cnt[kRsMaxR];
   __shared__ uint64_t tmp64[1024];
   __shared__ double tmpd[1024];
   __shared__ int64_t eref_s;
+  const Desc& a = D[blockIdx.x];
   RunState* st = a.st;
   if (!st->active || !st->do_resample) return;
   const int64_t* E = st->cur ? a.E1 : a.E0;
@@ -788,10 +798,10 @@ __global__ void __launch_bounds__(1024) k_rs_select(RsArgs a) {
     const double w = exp_cw(-(delta * (double)(E[r] - eref)));
     wsum += w;
     run += (uint64_t)floor(w * 281474976710656.0);
-    a.P[r] = run;  // local inclusive prefix
+    a.rs_P[r] = run;  // local inclusive prefix
   }
   const uint64_t off = block_scan_incl<uint64_t>(run, tmp64) - run;
-  for (int r = r0; r < r1; ++r) a.P[r] += off;
+  for (int r = r0; r < r1; ++r) a.rs_P[r] += off;
   tmpd[tid] = wsum;
   for (int r = tid; r < R; r += 1024) cnt[r] = 0;
   __syncthreads();
@@ -802,7 +812,7 @@ __global__ void __launch_bounds__(1024) k_rs_select(RsArgs a) {
   const double wtot = tmpd[0];
   __threadfence_block();
   __syncthreads();
-  const uint64_t Q = a.P[R - 1];
+  const uint64_t Q = a.rs_P[R - 1];
   const uint32_t g = st->g_rs;
   for (int k = tid; k < R; k += 1024) {
     const u32x4 w = philox10((uint32_t)(k >> 1), g, 0u, kTagResample, a.k0, a.k1);
@@ -812,7 +822,7 @@ __global__ void __launch_bounds__(1024) k_rs_select(RsArgs a) {
     int lo = 0, hi = R - 1;  // least j with P[j] > y; P[R-1] = Q > y
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (a.P[mid] > y) hi = mid; else lo = mid + 1;
+      if (a.rs_P[mid] > y) hi = mid; else lo = mid + 1;
     }
     atomicAdd(&cnt[lo], 1);
   }
@@ -823,39 +833,29 @@ __global__ void __launch_bounds__(1024) k_rs_select(RsArgs a) {
   const int start = (int)block_scan_incl<uint64_t>((uint64_t)local, tmp64) - local;
   int pos = start;
   for (int r = r0; r < r1; ++r)
-    for (int c = 0; c < cnt[r]; ++c) a.parent[pos++] = r;
+    for (int c = 0; c < cnt[r]; ++c) a.rs_parent[pos++] = r;
   if (tid == 0) st->last_lnq = -delta * (double)eref + log(wtot) - log((double)R);
 }
 
-struct GatherArgs {
-  RunState* st;
-  uint32_t* S0;
-  uint32_t* S1;
-  int32_t* H0;
-  int32_t* H1;
-  int64_t* E0;
-  int64_t* E1;
-  int32_t* F0;
-  int32_t* F1;
-  const int32_t* parent;
-  int32_t nq, np, T;
-};
-
 // Copies every child's spins, fields, energy and lineage from its parent into
-// the other population buffer.
-__global__ void __launch_bounds__(256) k_rs_gather(GatherArgs a) {
+// the other population buffer.  Local block = (tile, quad chunk).
+__global__ void __launch_bounds__(256) k_rs_gather(const Desc* __restrict__ D,
+                                                   const uint64_t* __restrict__ map) {
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& a = D[inst];
   RunState* st = a.st;
   if (!st->active || !st->do_resample) return;
   const int cur = st->cur;
-  const uint32_t* Ss = cur ? a.S1 : a.S0;
-  uint32_t* Sd = cur ? a.S0 : a.S1;
-  const int32_t* Hs = cur ? a.H1 : a.H0;
-  int32_t* Hd = cur ? a.H0 : a.H1;
+  const PAMC_GLOBAL uint32_t* __restrict__ Ss = gmem((const uint32_t*)(cur ? a.S1 : a.S0));
+  PAMC_GLOBAL uint32_t* __restrict__ Sd = gmem(cur ? a.S0 : a.S1);
+  const PAMC_GLOBAL int32_t* __restrict__ Hs = gmem((const int32_t*)(cur ? a.H1 : a.H0));
+  PAMC_GLOBAL int32_t* __restrict__ Hd = gmem(cur ? a.H0 : a.H1);
   int tile, chunk;
-  tile_chunk(a.T, tile, chunk);
+  group_chunk(a.T, lb, tile, chunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = tile * kLanes + lane;
-  const int p = a.parent[c];
+  const int p = gmem(a.rs_parent)[c];
   const int pt = p >> 6, pl = p & 63;
   if (chunk == 0 && wave == 0) {
     (cur ? a.E0 : a.E1)[c] = (cur ? a.E1 : a.E0)[p];
@@ -887,13 +887,17 @@ __global__ void __launch_bounds__(256) k_rs_gather(GatherArgs a) {
 //   neighbours change, the energy does not (every flipped spin has h = 0 and
 //   no two are coupled).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_cl_select(RunState* st, int64_t* E0, int64_t* E1,
-                                                    int32_t R, int32_t* targets) {
+__global__ void __launch_bounds__(1024) k_cl_select(const Desc* __restrict__ D) {
   __shared__ int64_t es[4096];
+  const Desc& d = D[blockIdx.x];
+  RunState* st = d.st;
   if (!st->active || !st->do_cluster) return;
   const int buf = st->cur ^ st->do_resample;
-  const int64_t* E = buf ? E1 : E0;
-  const int n_top = min(st->cl_n_top, R);
+  const int64_t* E = buf ? d.E1 : d.E0;
+  const int R = d.R;
+  // no targets without scratch (a move with no trials flips nothing)
+  const int n_top = (d.cl_targets && st->cl_trials > 0) ? min(st->cl_n_top, R) : 0;
+  if (n_top <= 0) return;
   constexpr int kPer = kRsMaxR / 1024;
   int64_t mine[kPer];
   int rank[kPer];
@@ -923,41 +927,31 @@ __global__ void __launch_bounds__(1024) k_cl_select(RunState* st, int64_t* E0, i
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     const int r = threadIdx.x + i * 1024;
-    if (r < R && rank[i] < n_top) targets[rank[i]] = r;
+    if (r < R && rank[i] < n_top) d.cl_targets[rank[i]] = r;
   }
 }
 
-struct ClArgs {
-  RunState* st;
-  const int32_t* row_ptr;
-  const int32_t* col;
-  const int32_t* J;
-  uint32_t* S0;
-  uint32_t* S1;
-  int32_t* H0;
-  int32_t* H1;
-  const int32_t* targets;
-  uint8_t* sel;
-  int32_t* sizes;
-  int32_t n, np, nq, trials;
-  uint32_t k0, k1;
-};
-
 enum : uint8_t { kOut = 0, kUnd = 1, kCand = 2, kIn = 3 };
 
-__global__ void __launch_bounds__(1024) k_cl_mis(ClArgs a) {
+// Local block = target * trials + trial.
+__global__ void __launch_bounds__(1024) k_cl_mis(const Desc* __restrict__ D, const uint64_t* __restrict__ map) {
   extern __shared__ uint8_t lds[];
   __shared__ int32_t cnt_s;
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& a = D[inst];
   RunState* st = a.st;
   if (!st->active || !st->do_cluster) return;
-  const int i = blockIdx.x / a.trials, t = blockIdx.x % a.trials;
-  if (i >= min(st->cl_n_top, (int)(gridDim.x / a.trials))) return;
+  const int trials = st->cl_trials;
+  if (trials <= 0) return;
+  const int i = lb / trials, t = lb % trials;
+  if (i >= min(st->cl_n_top, a.R)) return;
   const int buf = st->cur ^ st->do_resample;
   const int32_t* H = buf ? a.H1 : a.H0;
   const uint32_t* S = buf ? a.S1 : a.S0;
   uint32_t* key = (uint32_t*)lds;
   uint8_t* state = lds + sizeof(uint32_t) * (size_t)a.np;
-  const int r = a.targets[i];
+  const int r = a.cl_targets[i];
   const int tile = r >> 6, lane = r & 63;
   const uint32_t g = st->g_cl;
   for (int v = threadIdx.x; v < a.np; v += blockDim.x) {
@@ -1010,7 +1004,7 @@ __global__ void __launch_bounds__(1024) k_cl_mis(ClArgs a) {
   if (threadIdx.x == 0) cnt_s = 0;
   __syncthreads();
   int mine = 0;
-  uint8_t* out = a.sel + (size_t)blockIdx.x * a.np;
+  uint8_t* out = a.cl_sel + (size_t)lb * a.np;
   for (int v = threadIdx.x; v < a.np; v += blockDim.x) {
     const uint8_t in = state[v] == kIn;
     out[v] = in;
@@ -1018,49 +1012,53 @@ __global__ void __launch_bounds__(1024) k_cl_mis(ClArgs a) {
   }
   atomicAdd(&cnt_s, mine);
   __syncthreads();
-  if (threadIdx.x == 0) a.sizes[blockIdx.x] = cnt_s;
+  if (threadIdx.x == 0) a.cl_sizes[lb] = cnt_s;
 }
 
-__global__ void __launch_bounds__(256) k_cl_apply(ClArgs a, int64_t* flipped) {
+// Local block = target * kApplyChunks + chunk.
+__global__ void __launch_bounds__(256) k_cl_apply(const Desc* __restrict__ D, const uint64_t* __restrict__ map) {
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& a = D[inst];
   RunState* st = a.st;
   if (!st->active || !st->do_cluster) return;
-  const int i = blockIdx.y;
-  if (i >= st->cl_n_top) return;
+  const int i = lb / kApplyChunks, chunk = lb % kApplyChunks;
+  if (i >= min(st->cl_n_top, a.R)) return;
+  const int trials = st->cl_trials;
+  if (trials <= 0) return;
   const int buf = st->cur ^ st->do_resample;
   uint32_t* S = buf ? a.S1 : a.S0;
   int32_t* H = buf ? a.H1 : a.H0;
   int tb = 0, best = -1;
-  for (int t = 0; t < a.trials; ++t) {
-    const int s = a.sizes[i * a.trials + t];
+  for (int t = 0; t < trials; ++t) {
+    const int s = a.cl_sizes[i * trials + t];
     if (s > best) { best = s; tb = t; }
   }
-  const uint8_t* sel = a.sel + (size_t)(i * a.trials + tb) * a.np;
-  const int r = a.targets[i];
+  const uint8_t* sel = a.cl_sel + (size_t)(i * trials + tb) * a.np;
+  const int r = a.cl_targets[i];
   const int tile = r >> 6, lane = r & 63;
   int mine = 0;
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
+  for (int v = chunk * blockDim.x + threadIdx.x; v < a.n; v += kApplyChunks * blockDim.x) {
     if (!sel[v]) continue;
     int8_t* sb = (int8_t*)&S[((size_t)tile * a.nq + (v >> 2)) * kLanes + lane] + (v & 3);
     const int32_t snew = -(int32_t)*sb;
     *sb = (int8_t)snew;
     if (H)
       for (int e = a.row_ptr[v]; e < a.row_ptr[v + 1]; ++e)
-      __hip_atomic_fetch_add(&H[((size_t)tile * a.np + a.col[e]) * kLanes + lane], 2 * a.J[e] * snew,
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&H[((size_t)tile * a.np + a.col[e]) * kLanes + lane], 2 * a.J[e] * snew,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ++mine;
   }
   if (mine)
-    __hip_atomic_fetch_add((unsigned long long*)flipped, (unsigned long long)mine, __ATOMIC_RELAXED,
+    __hip_atomic_fetch_add((unsigned long long*)a.cl_flipped, (unsigned long long)mine, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
 // Max-3-Cut decode (see pamc.h) and the pairwise Hamming diagnostic.
 // ---------------------------------------------------------------------------
-__global__ void k_m3_decode(const int8_t* spins_internal, const int32_t* to_internal_emb,
-                            int32_t n3, const int32_t* row_ptr, const int32_t* col, const int32_t* w,
-                            int32_t* labels, int64_t* cut) {
-  // pass 1 (all threads): labels
+__global__ void k_m3_decode(const int8_t* spins_internal, const int32_t* to_internal_emb, int32_t n3,
+                            int32_t* labels) {
   const int anc = to_internal_emb[3 * n3];
   const int g = spins_internal[anc] < 0 ? -1 : 1;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += gridDim.x * blockDim.x) {
@@ -1092,16 +1090,16 @@ __global__ void __launch_bounds__(256) k_pair_distance(const uint32_t* S0, const
   const int a = blockIdx.x;
   double acc = 0.0;
   for (int b = a + 1 + threadIdx.x; b < R; b += blockDim.x) {
-    int d = 0;
+    int dd = 0;
     for (int q = 0; q < nq; ++q) {
       const uint32_t x = S[((size_t)(a >> 6) * nq + q) * kLanes + (a & 63)];
       const uint32_t y = S[((size_t)(b >> 6) * nq + q) * kLanes + (b & 63)];
       uint32_t diff = x ^ y;  // spins are 0x01 / 0xFF bytes: a byte differs iff nonzero
       diff = (diff | (diff >> 1) | (diff >> 2) | (diff >> 3) | (diff >> 4) | (diff >> 5) |
               (diff >> 6) | (diff >> 7)) & 0x01010101u;
-      d += __popc(diff);
+      dd += __popc(diff);
     }
-    const double f = (double)d / n;
+    const double f = (double)dd / n;
     acc += f < 1.0 - f ? f : 1.0 - f;
   }
   atomicAdd(out, acc);
@@ -1110,36 +1108,188 @@ __global__ void __launch_bounds__(256) k_pair_distance(const uint32_t* S0, const
 }  // namespace
 
 // ===========================================================================
-// Host launchers
+// Batches and their launchers
 // ===========================================================================
-static inline uint32_t key0(const pamc_instance* I) { return (uint32_t)I->seed; }
-static inline uint32_t key1(const pamc_instance* I) { return (uint32_t)(I->seed >> 32); }
-
 int32_t cluster_max_n() { return kClusterMaxN; }
 
-static SweepArgs sweep_args(pamc_instance* I) {
-  SweepArgs a;
-  a.row_ptr = I->g.row_ptr;
-  a.col = I->g.col;
-  a.J = I->g.J;
-  a.class_ptr = I->g.class_ptr;
-  a.order = I->order;
-  a.S0 = I->pop.S[0];
-  a.S1 = I->pop.S[1];
-  a.H0 = I->pop.H[0];
-  a.H1 = I->pop.H[1];
-  a.E0 = I->pop.E[0];
-  a.E1 = I->pop.E[1];
-  a.thr = I->thr;
-  a.st = I->st;
-  a.flip_ctr = I->prof ? I->flip_ctr : nullptr;
-  a.nq = I->nq;
-  a.np = I->np;
-  a.T = I->T;
-  a.ncls = I->ncls;
-  a.k0 = key0(I);
-  a.k1 = key1(I);
-  return a;
+hipError_t prepare_cluster_lds() {
+  return hipFuncSetAttribute((const void*)k_cl_mis, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             kClusterMaxN * 5 + 64);
+}
+
+Desc make_desc(const pamc_instance* I) {
+  Desc d;
+  memset(&d, 0, sizeof d);
+  d.row_ptr = I->g.row_ptr;
+  d.col = I->g.col;
+  d.J = I->g.J;
+  d.class_ptr = I->g.class_ptr;
+  d.order = I->order;
+  d.thr = I->thr;
+  d.S0 = I->pop.S[0];
+  d.S1 = I->pop.S[1];
+  d.H0 = I->pop.H[0];
+  d.H1 = I->pop.H[1];
+  d.E0 = I->pop.E[0];
+  d.E1 = I->pop.E[1];
+  d.F0 = I->pop.fam[0];
+  d.F1 = I->pop.fam[1];
+  d.best = I->best;
+  d.st = I->st;
+  d.rs_P = I->rs_P;
+  d.rs_parent = I->rs_parent;
+  d.cl_targets = I->cl_targets;
+  d.cl_sel = I->cl_sel;
+  d.cl_sizes = I->cl_sizes;
+  d.cl_flipped = I->flip_ctr ? I->flip_ctr + 256 : nullptr;
+  d.tr_mstar = I->tr_mstar;
+  d.tr_beta = I->tr_beta;
+  d.tr_lnq = I->tr_lnq;
+  d.tr_events = I->tr_events;
+  d.tr_time = I->tr_time;
+  d.flip_ctr = I->prof ? I->flip_ctr : nullptr;
+  d.D0 = I->Sd;
+  d.D1 = I->Sd2;
+  d.W = I->W;
+  d.X = I->X;
+  d.n = I->n;
+  d.np = I->np;
+  d.nq = I->nq;
+  d.R = I->R;
+  d.T = I->T;
+  d.ncls = I->ncls;
+  d.rule = I->rule;
+  d.pull = I->pull;
+  d.dense = I->dense;
+  d.shuffle = (I->flags & 1u) ? 0 : 1;
+  d.tr_cap = I->tr_cap;
+  d.order_cap = I->order_cap;
+  d.k0 = (uint32_t)I->seed;
+  d.k1 = (uint32_t)(I->seed >> 32);
+  return d;
+}
+
+int Batch::group_of(const pamc_instance* I) {
+  if (!I->pull) return 0;
+  const int ti = I->tpw == 4 ? 2 : (I->tpw == 2 ? 1 : 0);
+  return 6 + (I->small_j ? 3 : 0) + ti;
+}
+
+void Batch::free_device() {
+  if (d_desc) hipFree(d_desc);
+  d_desc = nullptr;
+  Launch* all[] = {&init_spins, &init_fields, &thr, &thr_dense, &gather, &cl_mis, &cl_apply};
+  for (Launch* l : all) {
+    if (l->map) hipFree(l->map);
+    l->map = nullptr;
+    l->grid = 0;
+  }
+  for (Launch& l : sweep) {
+    if (l.map) hipFree(l.map);
+    l.map = nullptr;
+    l.grid = 0;
+  }
+
+}
+
+static int64_t sweep_chunks(const pamc_instance* I) {
+  return (I->max_class_quads + kQuadsPerBlock - 1) / kQuadsPerBlock;
+}
+
+// Appends an instance's local blocks to a map.  With align8 the instance's
+// first block is placed at a multiple of 8 (idle blocks fill the gap), so
+// that its XCD placement does not depend on the instances before it.
+static void add_blocks(std::vector<uint64_t>& map, int inst, int64_t count, bool align8) {
+  if (count <= 0) return;
+  const uint64_t hi = (uint64_t)(uint32_t)inst << 32;
+  if (align8)
+    while (map.size() % 8) map.push_back(hi | kIdle);
+  for (int64_t b = 0; b < count; ++b) map.push_back(hi | (uint64_t)b);
+}
+
+static int64_t field_blocks(const pamc_instance* I) {
+  return std::min<int64_t>((int64_t)I->T * ((I->n + 63) / 64), kFieldBlocks);
+}
+
+hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const std::vector<Schedule>* scheds) {
+  // the old maps may still be read by queued kernels
+  if (b.stream && b.n > 0) {
+    const hipError_t e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) return e;
+  }
+  b.free_device();
+  b.I = insts;
+  b.n = (int32_t)insts.size();
+  if (b.n == 0) return hipSuccess;
+  b.stream = insts[0]->stream;
+  std::vector<Desc> desc(b.n);
+  for (int i = 0; i < b.n; ++i) desc[i] = make_desc(insts[i]);
+  std::vector<uint64_t> m_init, m_fields, m_thr, m_gather, m_mis, m_apply;
+  std::vector<std::vector<uint64_t>> m_sweep(Batch::kGroups);
+  b.max_ncls = 0;
+  b.max_sweeps = 1;
+  b.any_cluster = 0;
+  b.max_lds = 0;
+  for (int i = 0; i < b.n; ++i) {
+    pamc_instance* I = insts[i];
+    if (I->dense) continue;
+    add_blocks(m_init, i, kInitBlocks, false);
+    add_blocks(m_fields, i, field_blocks(I), false);
+    add_blocks(m_thr, i, kThrBlocks, false);
+    add_blocks(m_gather, i, (int64_t)I->T * ((I->nq + kGatherQuadsPerBlock - 1) / kGatherQuadsPerBlock), true);
+    add_blocks(m_sweep[Batch::group_of(I)], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_chunks(I), true);
+    b.max_ncls = std::max(b.max_ncls, I->ncls);
+    const int nt = std::min(I->cl_cap_top, I->R);
+    if (nt > 0 && I->cl_cap_trials > 0) {
+      add_blocks(m_mis, i, (int64_t)nt * I->cl_cap_trials, false);
+      add_blocks(m_apply, i, (int64_t)nt * kApplyChunks, false);
+      b.max_lds = std::max<int64_t>(b.max_lds, (int64_t)I->np * 5);
+    }
+  }
+  if (scheds) {
+    for (int i = 0; i < b.n; ++i) {
+      const Schedule& s = (*scheds)[i];
+      b.max_sweeps = std::max(b.max_sweeps, s.sweeps);
+      if (s.augmented && s.resample && s.n_top > 0 && s.mis_trials > 0) b.any_cluster = 1;
+    }
+  }
+  hipError_t e = hipMalloc((void**)&b.d_desc, sizeof(Desc) * b.n);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(b.d_desc, desc.data(), sizeof(Desc) * b.n, hipMemcpyHostToDevice, b.stream);
+  if (e != hipSuccess) return e;
+  auto up = [&](std::vector<uint64_t>& m, Batch::Launch& l) -> hipError_t {
+    if (m.size() > (size_t)INT32_MAX) return hipErrorInvalidValue;
+    l.grid = (int32_t)m.size();
+    if (m.empty()) return hipSuccess;
+    hipError_t err = hipMalloc((void**)&l.map, sizeof(uint64_t) * m.size());
+    if (err != hipSuccess) return err;
+    return hipMemcpyAsync(l.map, m.data(), sizeof(uint64_t) * m.size(), hipMemcpyHostToDevice, b.stream);
+  };
+  if ((e = up(m_init, b.init_spins)) != hipSuccess) return e;
+  if ((e = up(m_fields, b.init_fields)) != hipSuccess) return e;
+  if ((e = up(m_thr, b.thr)) != hipSuccess) return e;
+  if ((e = up(m_gather, b.gather)) != hipSuccess) return e;
+  if ((e = up(m_mis, b.cl_mis)) != hipSuccess) return e;
+  if ((e = up(m_apply, b.cl_apply)) != hipSuccess) return e;
+  for (int g = 0; g < Batch::kGroups; ++g)
+    if ((e = up(m_sweep[g], b.sweep[g])) != hipSuccess) return e;
+  // the staging vectors are local: wait for the copies before they go
+  return hipStreamSynchronize(b.stream);
+}
+
+using SweepKernel = void (*)(const Desc*, const uint64_t*, int, int);
+
+static SweepKernel sweep_kernel_of_group(int g) {
+  // group = 0 (incremental fields) or 6 + 3 * small_j + tiles-per-wave index
+  switch (g) {
+    case 6: return k_sweep_pull<false, 1>;
+    case 7: return k_sweep_pull<false, 2>;
+    case 8: return k_sweep_pull<false, 4>;
+    case 9: return k_sweep_pull<true, 1>;
+    case 10: return k_sweep_pull<true, 2>;
+    case 11: return k_sweep_pull<true, 4>;
+    default: return k_sweep_push;
+  }
 }
 
 static hipEvent_t next_event(pamc_instance* I) {
@@ -1151,230 +1301,121 @@ static hipEvent_t next_event(pamc_instance* I) {
   return I->ev_pool[I->ev_used++];
 }
 
-using PullKernel = void (*)(const int32_t*, const int32_t*, const int32_t*, const int32_t*,
-                           const int32_t*, const uint32_t*, SweepArgs, int, int);
+static inline int tgrid(int n) { return (n + 63) / 64; }
 
-template <int RULE, bool SMALLJ>
-static PullKernel pull_kernel_t(int tpw) {
-  return tpw == 4 ? k_sweep_pull<RULE, SMALLJ, 4>
-                  : (tpw == 2 ? k_sweep_pull<RULE, SMALLJ, 2> : k_sweep_pull<RULE, SMALLJ, 1>);
-}
-
-static PullKernel pull_kernel(const pamc_instance* I) {
-  if (I->rule == 1) return I->small_j ? pull_kernel_t<1, true>(I->tpw) : pull_kernel_t<1, false>(I->tpw);
-  return I->small_j ? pull_kernel_t<0, true>(I->tpw) : pull_kernel_t<0, false>(I->tpw);
-}
-
-// Sweeps of one step (or primitive): thresholds + class orders, then
-// nsweeps x ncls phase launches.
-static hipError_t launch_sweeps(pamc_instance* I, int32_t nsweeps) {
-  const int shuffle = (I->flags & 1u) ? 0 : 1;
-  int done = 0;
-  while (done < nsweeps) {
-    const int batch = std::min(nsweeps - done, I->order_cap);
-    // thresholds are recomputed per batch; class orders use gs + done + s
-    k_thresholds<<<64, 256, 0, I->stream>>>(I->st, I->thr, I->rule, I->order, I->ncls, batch,
-                                            shuffle, key0(I), key1(I));
-    SweepArgs a = sweep_args(I);
-    const int chunks = (I->max_class_quads + kQuadsPerBlock - 1) / kQuadsPerBlock;
-    const int grid = I->T * chunks;
-    for (int s = 0; s < batch; ++s) {
-      for (int p = 0; p < I->ncls; ++p) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (I->prof) {
-          e0 = next_event(I);
-          hipEventRecord(e0, I->stream);
-        }
-        if (I->pull) {
-          pull_kernel(I)<<<grid / I->tpw, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J,
-                                                               I->g.class_ptr, I->order, I->thr, a,
-                                                               s, p);
-        } else if (I->rule == 1) {
-          k_sweep<1><<<grid, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J, I->g.class_ptr, I->order, I->thr, a, s, p);
-        } else {
-          k_sweep<0><<<grid, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J, I->g.class_ptr, I->order, I->thr, a, s, p);
-        }
-        if (I->prof) {
-          e1 = next_event(I);
-          hipEventRecord(e1, I->stream);
-          I->prof_launches += 1;
+// thresholds + class orders, then nsweeps x max_ncls phase launches
+static hipError_t batch_sweeps(Batch& b, int32_t nsweeps) {
+  pamc_instance* P = b.I[0];
+  const bool prof = P->prof;
+  if (b.thr.grid) k_thresholds<<<b.thr.grid, 256, 0, b.stream>>>(b.d_desc, b.thr.map);
+  for (int s = 0; s < nsweeps; ++s) {
+    for (int p = 0; p < b.max_ncls; ++p) {
+      for (int g = 0; g < Batch::kGroups; ++g) {
+        if (!b.sweep[g].grid) continue;
+        if (prof) hipEventRecord(next_event(P), b.stream);
+        sweep_kernel_of_group(g)<<<b.sweep[g].grid, 256, 0, b.stream>>>(b.d_desc, b.sweep[g].map, s, p);
+        if (prof) {
+          hipEventRecord(next_event(P), b.stream);
+          P->prof_launches += 1;
         }
       }
     }
-    if (I->prof) I->prof_attempts += (int64_t)batch * I->n * I->R;
-    done += batch;
-    if (done < nsweeps) {
-      // advance the sweep counter between batches (only the primitive path
-      // can exceed order_cap; a run's step has sweeps <= order_cap)
-      k_advance_sweeps<<<1, 1, 0, I->stream>>>(I->st, batch);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
+  }
+  if (prof)
+    for (pamc_instance* I : b.I) P->prof_attempts += (int64_t)nsweeps * I->n * I->R;
+  return hipGetLastError();
+}
+
+hipError_t batch_init(Batch& b) {
+  if (b.init_spins.grid) k_init_spins<<<b.init_spins.grid, 256, 0, b.stream>>>(b.d_desc, b.init_spins.map);
+  for (pamc_instance* I : b.I) hipMemsetAsync(I->pop.E[0], 0, sizeof(int64_t) * I->R, b.stream);
+  if (b.init_fields.grid)
+    k_init_fields<<<b.init_fields.grid, 256, 0, b.stream>>>(b.d_desc, b.init_fields.map, 0, nullptr, 1);
+  k_init_finish<<<b.n, 256, 0, b.stream>>>(b.d_desc);
+  return hipGetLastError();
+}
+
+hipError_t batch_anneal_setup(Batch& b, const Schedule* d_sched, const int32_t* d_idx, int32_t count) {
+  if (count <= 0) return hipSuccess;
+  k_anneal_setup<<<tgrid(count), 64, 0, b.stream>>>(b.d_desc, d_sched, d_idx, count);
+  return hipGetLastError();
+}
+
+static hipError_t batch_resample(Batch& b) {
+  k_rs_select<<<b.n, 1024, 0, b.stream>>>(b.d_desc);
+  if (b.gather.grid) k_rs_gather<<<b.gather.grid, 256, 0, b.stream>>>(b.d_desc, b.gather.map);
+  return hipGetLastError();
+}
+
+static hipError_t batch_cluster(Batch& b) {
+  k_cl_select<<<b.n, 1024, 0, b.stream>>>(b.d_desc);
+  if (b.cl_mis.grid) k_cl_mis<<<b.cl_mis.grid, 1024, b.max_lds, b.stream>>>(b.d_desc, b.cl_mis.map);
+  if (b.cl_apply.grid) k_cl_apply<<<b.cl_apply.grid, 256, 0, b.stream>>>(b.d_desc, b.cl_apply.map);
+  return hipGetLastError();
+}
+
+hipError_t batch_step(Batch& b) {
+  k_step_begin<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
+  batch_resample(b);
+  if (b.any_cluster) batch_cluster(b);
+  k_commit<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 1);
+  hipError_t e = batch_sweeps(b, b.max_sweeps);
+  if (e != hipSuccess) return e;
+  k_step_end<<<b.n, 1024, 0, b.stream>>>(b.d_desc, 1);
+  return hipGetLastError();
+}
+
+hipError_t batch_status(Batch& b, int32_t* d_out) {
+  k_status<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, d_out);
+  return hipGetLastError();
+}
+
+hipError_t prim_sweep(Batch& b, double beta, int32_t nsweeps) {
+  pamc_instance* I = b.I[0];
+  int done = 0;
+  while (done < nsweeps) {
+    const int chunk = std::min(nsweeps - done, I->order_cap);
+    k_prim_set<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 0, beta, 0, 0, chunk);
+    hipError_t e = batch_sweeps(b, chunk);
+    if (e != hipSuccess) return e;
+    k_advance_sweeps<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, chunk);
+    done += chunk;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_init_sparse(pamc_instance* I) {
-  const size_t words = (size_t)I->T * I->nq * kLanes;
-  int grid = (int)std::min<size_t>((words + 255) / 256, 65535);
-  k_init_spins<<<grid, 256, 0, I->stream>>>(I->pop.S[0], I->pop.fam[0], I->n, I->nq, I->T, key0(I),
-                                            key1(I));
-  hipMemsetAsync(I->pop.E[0], 0, sizeof(int64_t) * I->R, I->stream);
-  const int vchunks = (I->n + 63) / 64;
-  k_init_fields<<<I->T * vchunks, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J, I->pop.S[0],
-                                                       I->pop.H[0], I->pop.E[0], I->n, I->np, I->nq,
-                                                       I->T);
-  k_init_finish<<<(std::max(I->R, I->np) + 255) / 256, 256, 0, I->stream>>>(I->pop.E[0], I->R,
-                                                                             I->st, I->best, I->np);
+hipError_t prim_resample(Batch& b, double delta) {
+  k_prim_set<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 1, delta, 0, 0, 0);
+  batch_resample(b);
+  k_commit<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 0);
+  k_deactivate<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
   return hipGetLastError();
 }
 
-hipError_t launch_fields(pamc_instance* I, int32_t* H) {
-  const int vchunks = (I->n + 63) / 64;
-  // current buffer index is read by the host before this call
-  k_init_fields<<<I->T * vchunks, 256, 0, I->stream>>>(I->g.row_ptr, I->g.col, I->g.J,
-                                                       I->pop.S[I->host_cur], H, nullptr, I->n,
-                                                       I->np, I->nq, I->T);
+hipError_t prim_cluster(Batch& b, int32_t n_top, int32_t trials) {
+  k_prim_set<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 2, 0.0, n_top, trials, 0);
+  batch_cluster(b);
+  k_commit<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 0);
+  k_deactivate<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
   return hipGetLastError();
 }
 
-hipError_t launch_anneal_setup(pamc_instance* I, const Schedule& s) {
-  k_anneal_setup<<<1, 1, 0, I->stream>>>(I->st, s);
+hipError_t prim_update_best(Batch& b) {
+  k_prim_set<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 0, 0.0, 0, 0, 0);
+  k_step_end<<<b.n, 1024, 0, b.stream>>>(b.d_desc, 0);
+  k_deactivate<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
   return hipGetLastError();
 }
 
-static hipError_t launch_resample_kernels(pamc_instance* I) {
-  RsArgs r;
-  r.st = I->st;
-  r.E0 = I->pop.E[0];
-  r.E1 = I->pop.E[1];
-  r.P = I->rs_P;
-  r.parent = I->rs_parent;
-  r.R = I->R;
-  r.k0 = key0(I);
-  r.k1 = key1(I);
-  k_rs_select<<<1, 1024, 0, I->stream>>>(r);
-  GatherArgs g;
-  g.st = I->st;
-  g.S0 = I->pop.S[0];
-  g.S1 = I->pop.S[1];
-  g.H0 = I->pop.H[0];
-  g.H1 = I->pop.H[1];
-  g.E0 = I->pop.E[0];
-  g.E1 = I->pop.E[1];
-  g.F0 = I->pop.fam[0];
-  g.F1 = I->pop.fam[1];
-  g.parent = I->rs_parent;
-  g.nq = I->nq;
-  g.np = I->np;
-  g.T = I->T;
-  const int chunks = (I->nq + kGatherQuadsPerBlock - 1) / kGatherQuadsPerBlock;
-  k_rs_gather<<<I->T * chunks, 256, 0, I->stream>>>(g);
-  return hipGetLastError();
-}
-
-static hipError_t launch_cluster_kernels(pamc_instance* I, int32_t n_top, int32_t trials) {
-  if (n_top <= 0 || trials <= 0) return hipSuccess;
-  n_top = std::min(n_top, I->R);
-  k_cl_select<<<1, 1024, 0, I->stream>>>(I->st, I->pop.E[0], I->pop.E[1], I->R, I->cl_targets);
-  ClArgs c;
-  c.st = I->st;
-  c.row_ptr = I->g.row_ptr;
-  c.col = I->g.col;
-  c.J = I->g.J;
-  c.S0 = I->pop.S[0];
-  c.S1 = I->pop.S[1];
-  c.H0 = I->pop.H[0];
-  c.H1 = I->pop.H[1];
-  c.targets = I->cl_targets;
-  c.sel = I->cl_sel;
-  c.sizes = I->cl_sizes;
-  c.n = I->n;
-  c.np = I->np;
-  c.nq = I->nq;
-  c.trials = trials;
-  c.k0 = key0(I);
-  c.k1 = key1(I);
-  const size_t lds = (size_t)I->np * 5;
-  k_cl_mis<<<n_top * trials, 1024, lds, I->stream>>>(c);
-  const int chunks = std::max(1, std::min(64, (I->n + 255) / 256));
-  k_cl_apply<<<dim3(chunks, n_top), 256, 0, I->stream>>>(c, &((int64_t*)I->flip_ctr)[256]);
-  return hipGetLastError();
-}
-
-static StepEndArgs step_end_args(pamc_instance* I) {
-  StepEndArgs e;
-  e.st = I->st;
-  e.E0 = I->pop.E[0];
-  e.E1 = I->pop.E[1];
-  e.S0 = I->pop.S[0];
-  e.S1 = I->pop.S[1];
-  e.best = I->best;
-  e.W = I->W;
-  e.R = I->R;
-  e.nq = I->nq;
-  e.np = I->np;
-  e.tr_mstar = I->tr_mstar;
-  e.tr_beta = I->tr_beta;
-  e.tr_events = I->tr_events;
-  e.tr_time = I->tr_time;
-  e.tr_cap = I->tr_cap;
-  e.ev_bits_extra = 0;
-  e.D0 = I->Sd;
-  e.D1 = I->Sd2;
-  e.dense = I->dense;
-  return e;
-}
-
-hipError_t launch_step(pamc_instance* I, const Schedule& s, int32_t step) {
-  k_step_begin<<<1, 1, 0, I->stream>>>(I->st, step, I->X);
-  if (s.resample) launch_resample_kernels(I);
-  if (s.augmented && s.resample) launch_cluster_kernels(I, std::min(s.n_top, I->R), s.mis_trials);
-  k_commit<<<1, 1, 0, I->stream>>>(I->st, 1, I->tr_lnq, I->tr_cap);
-  hipError_t e = launch_sweeps(I, s.sweeps);
-  if (e != hipSuccess) return e;
-  k_step_end<<<1, 1024, 0, I->stream>>>(step_end_args(I), 1);
-  return hipGetLastError();
-}
-
-hipError_t launch_prim_sweep(pamc_instance* I, double beta, int32_t nsweeps) {
-  k_prim_set<<<1, 1, 0, I->stream>>>(I->st, 0, beta, 0, 0, I->X);
-  hipError_t e = launch_sweeps(I, nsweeps);
-  if (e != hipSuccess) return e;
-  const int last = nsweeps - ((nsweeps - 1) / I->order_cap) * I->order_cap;
-  k_advance_sweeps<<<1, 1, 0, I->stream>>>(I->st, last);
-  return hipGetLastError();
-}
-
-hipError_t launch_prim_resample(pamc_instance* I, double delta) {
-  k_prim_set<<<1, 1, 0, I->stream>>>(I->st, 1, delta, 0, 0, I->X);
-  launch_resample_kernels(I);
-  k_commit<<<1, 1, 0, I->stream>>>(I->st, 0, I->tr_lnq, 0);
-  k_deactivate<<<1, 1, 0, I->stream>>>(I->st);
-  return hipGetLastError();
-}
-
-hipError_t launch_prim_cluster(pamc_instance* I, int32_t n_top, int32_t trials) {
-  k_prim_set<<<1, 1, 0, I->stream>>>(I->st, 2, 0.0, n_top, trials, I->X);
-  launch_cluster_kernels(I, n_top, trials);
-  k_commit<<<1, 1, 0, I->stream>>>(I->st, 0, I->tr_lnq, 0);
-  k_deactivate<<<1, 1, 0, I->stream>>>(I->st);
-  return hipGetLastError();
-}
-
-hipError_t launch_prim_update_best(pamc_instance* I) {
-  k_prim_set<<<1, 1, 0, I->stream>>>(I->st, 0, 0.0, 0, 0, I->X);
-  k_step_end<<<1, 1024, 0, I->stream>>>(step_end_args(I), 0);
-  k_deactivate<<<1, 1, 0, I->stream>>>(I->st);
+hipError_t launch_fields(Batch& b, int32_t buf, int32_t* H) {
+  k_init_fields<<<b.init_fields.grid, 256, 0, b.stream>>>(b.d_desc, b.init_fields.map, buf, H, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev) {
   hipMemsetAsync(I->m3_cut, 0, sizeof(int64_t), I->stream);
   const int grid = (I->m3_n + 255) / 256;
-  k_m3_decode<<<grid, 256, 0, I->stream>>>(spins_internal_dev, I->to_internal_dev, I->m3_n,
-                                           I->m3_row_ptr, I->m3_col, I->m3_w, I->m3_labels,
-                                           I->m3_cut);
+  k_m3_decode<<<grid, 256, 0, I->stream>>>(spins_internal_dev, I->to_internal_dev, I->m3_n, I->m3_labels);
   k_m3_cut<<<grid, 256, 0, I->stream>>>(I->m3_labels, I->m3_n, I->m3_row_ptr, I->m3_col, I->m3_w,
                                         I->m3_cut);
   return hipGetLastError();
@@ -1387,53 +1428,51 @@ hipError_t launch_pair_distance(pamc_instance* I, double* out_dev) {
   return hipGetLastError();
 }
 
-// Controller pieces shared with the dense path.
-hipError_t ctl_step_begin(pamc_instance* I, int32_t step) {
-  k_step_begin<<<1, 1, 0, I->stream>>>(I->st, step, I->X);
+// ---------------------------------------------------------------------------
+// Controller pieces used by the dense path (single instance via its batch).
+// ---------------------------------------------------------------------------
+hipError_t ctl_step_begin(Batch& b) {
+  k_step_begin<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
   return hipGetLastError();
 }
-hipError_t ctl_resample_select(pamc_instance* I) {
-  RsArgs r;
-  r.st = I->st;
-  r.E0 = I->pop.E[0];
-  r.E1 = I->pop.E[1];
-  r.P = I->rs_P;
-  r.parent = I->rs_parent;
-  r.R = I->R;
-  r.k0 = key0(I);
-  r.k1 = key1(I);
-  k_rs_select<<<1, 1024, 0, I->stream>>>(r);
+hipError_t ctl_resample_select(Batch& b) {
+  k_rs_select<<<b.n, 1024, 0, b.stream>>>(b.d_desc);
   return hipGetLastError();
 }
-hipError_t ctl_commit(pamc_instance* I, int32_t in_run) {
-  k_commit<<<1, 1, 0, I->stream>>>(I->st, in_run, I->tr_lnq, in_run ? I->tr_cap : 0);
+hipError_t ctl_commit(Batch& b, int32_t in_run) {
+  k_commit<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, in_run);
   return hipGetLastError();
 }
-hipError_t ctl_thresholds(pamc_instance* I) {
-  k_thresholds<<<64, 256, 0, I->stream>>>(I->st, I->thr, I->rule, I->order, 0, 0, 0, key0(I), key1(I));
+hipError_t ctl_thresholds(Batch& b) {
+  // dense instances have no classes: only the table is computed
+  if (!b.thr_dense.grid) {
+    std::vector<uint64_t> m;
+    for (int i = 0; i < b.n; ++i) add_blocks(m, i, kThrBlocks, false);
+    b.thr_dense.grid = (int32_t)m.size();
+    hipError_t e = hipMalloc((void**)&b.thr_dense.map, sizeof(uint64_t) * m.size());
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(b.thr_dense.map, m.data(), sizeof(uint64_t) * m.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  k_thresholds<<<b.thr_dense.grid, 256, 0, b.stream>>>(b.d_desc, b.thr_dense.map);
   return hipGetLastError();
 }
-hipError_t ctl_step_end(pamc_instance* I, int32_t in_run) {
-  k_step_end<<<1, 1024, 0, I->stream>>>(step_end_args(I), in_run);
+hipError_t ctl_step_end(Batch& b, int32_t in_run) {
+  k_step_end<<<b.n, 1024, 0, b.stream>>>(b.d_desc, in_run);
   return hipGetLastError();
 }
-hipError_t ctl_prim_set(pamc_instance* I, int32_t kind, double value) {
-  k_prim_set<<<1, 1, 0, I->stream>>>(I->st, kind, value, 0, 0, I->X);
+hipError_t ctl_prim_set(Batch& b, int32_t kind, double value, int32_t nsweeps) {
+  k_prim_set<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, kind, value, 0, 0, nsweeps);
   return hipGetLastError();
 }
-hipError_t ctl_advance(pamc_instance* I, int32_t nsweeps) {
-  k_advance_sweeps<<<1, 1, 0, I->stream>>>(I->st, nsweeps);
+hipError_t ctl_advance(Batch& b, int32_t nsweeps) {
+  k_advance_sweeps<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, nsweeps);
   return hipGetLastError();
 }
-hipError_t ctl_deactivate(pamc_instance* I) {
-  k_deactivate<<<1, 1, 0, I->stream>>>(I->st);
+hipError_t ctl_deactivate(Batch& b) {
+  k_deactivate<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
   return hipGetLastError();
 }
 hipEvent_t ctl_event(pamc_instance* I) { return next_event(I); }
-
-hipError_t prepare_cluster_lds() {
-  return hipFuncSetAttribute((const void*)k_cl_mis, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             kClusterMaxN * 5 + 64);
-}
 
 }  // namespace pamc

@@ -30,6 +30,9 @@ EXPORTED = [
     "pamc_sweep", "pamc_resample", "pamc_cluster_move", "pamc_update_best", "pamc_best",
     "pamc_get_state", "pamc_get_trace", "pamc_max3cut_decode", "pamc_pair_distance",
     "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
+    "pamc_anneal_batch", "pamc_server_create", "pamc_server_submit", "pamc_server_tick",
+    "pamc_server_drain", "pamc_server_poll", "pamc_server_latency", "pamc_server_forget",
+    "pamc_server_destroy",
 ]
 
 
@@ -108,6 +111,15 @@ def _load():
         "pamc_profile_enable": [P, C.c_int32],
         "pamc_profile_read": [P, P, P, P, P],
         "pamc_synchronize": [P],
+        "pamc_anneal_batch": [P, P, C.c_int32, P],
+        "pamc_server_create": [C.c_int64, C.c_int32, C.POINTER(pamc_config), PP],
+        "pamc_server_submit": [P, C.c_int32, P, P, P, C.c_int32, C.c_uint64, C.POINTER(pamc_schedule),
+                               C.POINTER(C.c_uint64)],
+        "pamc_server_tick": [P, C.c_int32, P, P],
+        "pamc_server_drain": [P],
+        "pamc_server_poll": [P, C.c_uint64, P, P, P],
+        "pamc_server_latency": [P, C.c_uint64, P, P],
+        "pamc_server_forget": [P, C.c_uint64],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -115,6 +127,8 @@ def _load():
         f.restype = st
     L.pamc_destroy_instance.argtypes = [P]
     L.pamc_destroy_instance.restype = None
+    L.pamc_server_destroy.argtypes = [P]
+    L.pamc_server_destroy.restype = None
     return L
 
 
@@ -268,6 +282,70 @@ def pamc_synchronize(h):
     _check(lib.pamc_synchronize(h))
 
 
+def pamc_anneal_batch(handles, scheds):
+    """One batched run over several instances (one schedule each)."""
+    k = len(handles)
+    if len(scheds) != k:
+        raise ValueError("one schedule per instance")
+    hs = (C.c_void_p * k)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    ss = (pamc_schedule * k)(*scheds)
+    rs = (pamc_result * k)()
+    _check(lib.pamc_anneal_batch(C.cast(hs, C.c_void_p), C.cast(ss, C.c_void_p), k, C.cast(rs, C.c_void_p)))
+    return list(rs)
+
+
+def pamc_server_create(hbm_budget_bytes, max_slots, *, replicas=64, rule=HEATBATH, device=0, stream=None,
+                       flags=0):
+    cfg = pamc_config(0, replicas, rule, device, stream, flags)
+    h = C.c_void_p()
+    _check(lib.pamc_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(cfg), C.byref(h)))
+    return h
+
+
+def pamc_server_submit(srv, n, row_ptr, col, w, objective, seed, sched):
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    cl = np.ascontiguousarray(col, np.int32)
+    ww = np.ascontiguousarray(w, np.int32)
+    t = C.c_uint64()
+    _check(lib.pamc_server_submit(srv, int(n), _ptr(rp), _ptr(cl), _ptr(ww), int(objective), int(seed),
+                                  C.byref(sched), C.byref(t)))
+    return t.value
+
+
+def pamc_server_tick(srv, max_steps=0):
+    a, q = C.c_int32(), C.c_int32()
+    _check(lib.pamc_server_tick(srv, int(max_steps), C.byref(a), C.byref(q)))
+    return a.value, q.value
+
+
+def pamc_server_drain(srv):
+    _check(lib.pamc_server_drain(srv))
+
+
+def pamc_server_poll(srv, ticket, n=None):
+    d = C.c_int32()
+    res = pamc_result()
+    spins = np.zeros(n, np.int8) if n is not None else None
+    _check(lib.pamc_server_poll(srv, int(ticket), C.byref(d), C.byref(res), _ptr(spins)))
+    if not d.value:
+        return None
+    return (res, spins) if n is not None else res
+
+
+def pamc_server_latency(srv, ticket):
+    q, t = C.c_double(), C.c_double()
+    _check(lib.pamc_server_latency(srv, int(ticket), C.byref(q), C.byref(t)))
+    return q.value, t.value
+
+
+def pamc_server_forget(srv, ticket):
+    _check(lib.pamc_server_forget(srv, int(ticket)))
+
+
+def pamc_server_destroy(srv):
+    lib.pamc_server_destroy(srv)
+
+
 # ---------------------------------------------------------------- owner object
 class Instance:
     """Owns one ``pamc_instance*``; methods forward to the C functions."""
@@ -354,3 +432,50 @@ class Instance:
 
     def synchronize(self):
         pamc_synchronize(self.h)
+
+
+def anneal_batch(instances, scheds):
+    """Batched run of several ``Instance`` objects; returns their results."""
+    return pamc_anneal_batch([i.h for i in instances], scheds)
+
+
+class Server:
+    """Owns one ``pamc_server*`` (continuous batching of annealing requests)."""
+
+    def __init__(self, hbm_budget_bytes, max_slots, *, replicas, rule=HEATBATH, device=0, stream=None,
+                 fields=None):
+        flags = {None: 0, "push": FLAG_FIELDS_PUSH, "pull": FLAG_FIELDS_PULL}[fields]
+        self.h = pamc_server_create(hbm_budget_bytes, max_slots, replicas=replicas, rule=rule, device=device,
+                                    stream=stream, flags=flags)
+        self.sizes = {}
+
+    def submit(self, g, seed, sched, objective=MAXCUT):
+        t = pamc_server_submit(self.h, g.n, g.row_ptr, g.col, g.w, objective, seed, sched)
+        self.sizes[t] = g.n
+        return t
+
+    def tick(self, max_steps=0):
+        return pamc_server_tick(self.h, max_steps)
+
+    def drain(self):
+        pamc_server_drain(self.h)
+
+    def poll(self, ticket, spins=False):
+        return pamc_server_poll(self.h, ticket, self.sizes[ticket] if spins else None)
+
+    def latency(self, ticket):
+        return pamc_server_latency(self.h, ticket)
+
+    def forget(self, ticket):
+        pamc_server_forget(self.h, ticket)
+
+    def close(self):
+        if self.h:
+            pamc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,175 @@
+"""Batched and served runs: every run's result must be bit-identical to the
+same run made alone through pamc_anneal (and hence to the oracle, which the
+single-instance path matches in the parity suite).  One direct oracle check
+ties the batched path to the oracle itself."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pamc():
+    from paper_2606_25203_amd import pamc as p
+    return p
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def same_result(a, b, tag):
+    for f in ("best_cut", "best_energy", "steps_run", "step_reached", "n_cluster_moves", "n_reheats",
+              "n_reversals", "n_restarts"):
+        assert getattr(a, f) == getattr(b, f), f"{tag}: {f} {getattr(a, f)} != {getattr(b, f)}"
+    # the same device kernels sum ln Q in the same order: exact
+    assert a.sum_lnq == b.sum_lnq, f"{tag}: sum ln Q differs"
+
+
+def plain_run(pamc, g, R, seed, sched, fields=None, rule=0):
+    inst = pamc.Instance.csr(g, replicas=R, seed=seed, rule=rule, fields=fields)
+    res = inst.anneal(sched)
+    out = (res, inst.best()[2], inst.state(), inst.trace(sched.steps))
+    inst.close()
+    return out
+
+
+def mixed_cases(pamc):
+    aug = dict(beta0=0.1, dbeta=0.05, augmented=1, z_rst=60, n_top=8, mis_trials=3, win_short=5,
+               win_long=8, tau=4)
+    return [
+        ("random300_plain", synth.random_graph(301, 2500, 3), 128, 11, pamc.schedule(steps=30, sweeps=3), None),
+        ("torus_aug", synth.torus(14, 10, 2), 64, 12, pamc.schedule(steps=70, sweeps=2, **aug), None),
+        ("torus_aug_push", synth.torus(16, 12, 5), 192, 13, pamc.schedule(steps=45, sweeps=1, **aug), "push"),
+        ("dense_ish_pull", synth.random_graph(90, 2000, 4, weights="pm1"), 64, 14,
+         pamc.schedule(steps=25, sweeps=4), "pull"),
+        ("random_push", synth.random_graph(500, 9000, 9), 256, 15, pamc.schedule(steps=12, sweeps=2), "push"),
+    ]
+
+
+def test_batch_equals_plain(pamc):
+    cases = mixed_cases(pamc)
+    say("case batch of", len(cases), "mixed instances")
+    insts = [pamc.Instance.csr(g, replicas=R, seed=seed, fields=f) for _, g, R, seed, _, f in cases]
+    res = pamc.anneal_batch(insts, [c[4] for c in cases])
+    for (name, g, R, seed, sched, f), inst, r in zip(cases, insts, res):
+        say("  compare", name)
+        pr, pbest, pstate, ptrace = plain_run(pamc, g, R, seed, sched, f)
+        same_result(r, pr, name)
+        assert np.array_equal(inst.best()[2], pbest), name
+        for a, b in zip(inst.state(), pstate):
+            assert np.array_equal(a, b), name
+        tr = inst.trace(sched.steps)
+        for k in ("mstar", "beta", "events"):
+            assert np.array_equal(tr[k], ptrace[k]), f"{name}: trace {k}"
+        inst.close()
+
+
+def test_batch_matches_oracle(pamc):
+    g = synth.torus(14, 10, 2)
+    kw = dict(beta0=0.1, dbeta=0.05, steps=70, sweeps=2, augmented=1, z_rst=60, n_top=8, mis_trials=3,
+              win_short=5, win_long=8, tau=4)
+    say("case batch vs oracle")
+    insts = [pamc.Instance.csr(g, replicas=64, seed=s) for s in (21, 22, 23)]
+    res = pamc.anneal_batch(insts, [pamc.schedule(**kw)] * 3)
+    for s, inst, r in zip((21, 22, 23), insts, res):
+        o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 64, s)
+        ores, otr = o.anneal(oracle.default_schedule(**kw), trace=True)
+        assert r.best_cut == ores.best_cut and r.steps_run == ores.steps_run
+        assert r.n_cluster_moves == ores.n_cluster_moves and r.n_restarts == ores.n_restarts
+        assert abs(r.sum_lnq - ores.sum_lnq) <= 1e-12 * max(1.0, abs(ores.sum_lnq))
+        assert np.array_equal(inst.trace(kw["steps"])["mstar"], otr["mstar"])
+        inst.close()
+
+
+def test_batch_many_seeds_one_graph(pamc):
+    """The small-graph case batching is for: one graph, many seeds."""
+    g = synth.random_graph(200, 4000, 6)
+    sched = pamc.schedule(beta0=0.1, dbeta=2.9 / 19, steps=20, sweeps=5)
+    seeds = list(range(100, 132))
+    say("case 32 seeds")
+    insts = [pamc.Instance.csr(g, replicas=64, seed=s) for s in seeds]
+    res = pamc.anneal_batch(insts, [sched] * len(seeds))
+    for s, r in zip(seeds[::7], res[::7]):
+        pr = plain_run(pamc, g, 64, s, sched)[0]
+        same_result(r, pr, f"seed {s}")
+    for i in insts:
+        i.close()
+
+
+def test_batch_stop_at_target(pamc):
+    g = synth.torus(10, 10, 3)
+    say("case batch stop at target")
+    base = pamc.Instance.csr(g, replicas=64, seed=3)
+    full = base.anneal(pamc.schedule(steps=80, sweeps=2))
+    base.close()
+    target = full.best_cut - 2
+    scheds = [pamc.schedule(steps=80, sweeps=2, target=target, stop_at_target=1), pamc.schedule(steps=40, sweeps=1)]
+    insts = [pamc.Instance.csr(g, replicas=64, seed=3), pamc.Instance.csr(g, replicas=64, seed=4)]
+    res = pamc.anneal_batch(insts, scheds)
+    alone = plain_run(pamc, g, 64, 3, scheds[0])[0]
+    same_result(res[0], alone, "stopped run")
+    assert res[0].best_cut >= target and res[0].steps_run <= 80
+    same_result(res[1], plain_run(pamc, g, 64, 4, scheds[1])[0], "full run")
+    for i in insts:
+        i.close()
+
+
+def test_batch_rejects_bad_input(pamc):
+    g = synth.torus(8, 8, 1)
+    a = pamc.Instance.csr(g, replicas=64, seed=1)
+    with pytest.raises(pamc.PamcError):
+        pamc.anneal_batch([a, a], [pamc.schedule(steps=2)] * 2)
+    d = pamc.Instance.dense_random(100, 1, replicas=64, seed=1)
+    with pytest.raises(pamc.PamcError):
+        pamc.anneal_batch([a, d], [pamc.schedule(steps=2)] * 2)
+    a.close()
+    d.close()
+
+
+@pytest.mark.parametrize("slots,budget", [(64, 16 << 30), (2, 16 << 30), (64, 4 << 20)])
+def test_server_alone_vs_mix(pamc, slots, budget):
+    """Requests served in a mix (continuous batching, admissions and
+    retirements between ticks) give the results they give alone."""
+    reqs = synth.request_stream(8, 0.0, seed=7, n_min=60, n_max=1500)
+    R = 128
+    sched = pamc.schedule(beta0=0.1, dbeta=2.9 / 19, steps=20, sweeps=2)
+    scheds = [pamc.schedule(beta0=0.1, dbeta=2.9 / (9 + 5 * (i % 3)), steps=10 + 5 * (i % 3), sweeps=1 + i % 2)
+              for i in range(len(reqs))]
+    say(f"case server slots={slots} budget={budget} requests={len(reqs)}")
+    srv = pamc.Server(budget, slots, replicas=R)
+    tickets = []
+    for q, sc in zip(reqs[:4], scheds):
+        tickets.append(srv.submit(q.graph, q.seed, sc))
+    # a few ticks, then more arrivals while the first ones run
+    srv.tick(3)
+    srv.tick(3)
+    for q, sc in zip(reqs[4:], scheds[4:]):
+        tickets.append(srv.submit(q.graph, q.seed, sc))
+    srv.drain()
+    for t, q, sc in zip(tickets, reqs, scheds):
+        got = srv.poll(t, spins=True)
+        assert got is not None
+        r, spins = got
+        pr, pbest, _, _ = plain_run(pamc, q.graph, R, q.seed, sc)
+        same_result(r, pr, f"request {q.index} n={q.graph.n}")
+        assert np.array_equal(spins, pbest)
+        qs, ts = srv.latency(t)
+        assert 0 <= qs <= ts
+    srv.close()
+
+
+def test_server_rejects_oversize(pamc):
+    srv = pamc.Server(1 << 20, 4, replicas=512)
+    g = synth.torus(100, 100, 1)
+    with pytest.raises(pamc.PamcError):
+        srv.submit(g, 1, pamc.schedule(steps=5))
+    with pytest.raises(pamc.PamcError):
+        srv.poll(12345)
+    srv.close()
