@@ -138,6 +138,141 @@ def cpu_baseline(w, seconds_budget: float):
                       f"({att:.3g} attempts in {dt:.1f} s, single thread)"}
 
 
+# ------------------------------------------------------ batched and served
+BATCH_SEEDS = {"c1": 256, "c2": 8, "c4": 16}
+
+
+def make_instance(pamc, w, seed, fields=None):
+    if w["kind"] == "csr":
+        return pamc.Instance.csr(w["graph"], replicas=w["R"], seed=seed, fields=fields)
+    if w["kind"] == "max3cut":
+        return pamc.Instance.max3cut(w["graph"], replicas=w["R"], seed=seed, fields=fields)
+    raise SystemExit("batched runs take sparse workloads")
+
+
+def bench_batched(pamc, torch, name, count=None):
+    """The same set of runs (one instance, count seeds) made one after the
+    other through pamc_anneal and together through pamc_anneal_batch;
+    instances are built and initialised before the clock starts in both."""
+    w = workload(name)
+    count = count or BATCH_SEEDS[name]
+    sched = pamc.schedule(**w["sched"])
+    seeds = list(range(1000, 1000 + count))
+    insts = [make_instance(pamc, w, s) for s in seeds]
+    n = insts[0].info().n
+    # warm-up of both paths on the first instance
+    insts[0].anneal(sched)
+    pamc.anneal_batch(insts[:2], [sched] * 2)
+    for i, s in zip(insts, seeds):
+        i.reset(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [i.anneal(sched) for i in insts]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for i, s in zip(insts, seeds):
+        i.reset(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batched = pamc.anneal_batch(insts, [sched] * count)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    for i in insts:
+        i.close()
+    att = sum(r.steps_run for r in plain) * w["sweeps"] * n * w["R"]
+    same = all(a.best_cut == b.best_cut and a.sum_lnq == b.sum_lnq and a.steps_run == b.steps_run
+               for a, b in zip(plain, batched))
+    return {"workload": w["desc"], "runs": count, "plain_attempts_per_s": att / t_plain,
+            "batched_attempts_per_s": att / t_batch, "speedup": t_plain / t_batch,
+            "plain_s": t_plain, "batched_s": t_batch, "identical_results": same,
+            "cuts": sorted(r.best_cut for r in batched)[count // 2]}
+
+
+C5_SCHED = dict(beta0=0.1, dbeta=2.9 / 199, steps=200, sweeps=5)
+
+
+def bench_served(pamc, torch, count, budget_gb=16.0, slots=256, tick_steps=8, seed=5):
+    """A prefix of the request stream (n log-uniform in [800, 20000], half
+    random graphs of average degree 4-50, half +-1 tori; R = 512, 200 beta
+    steps x 5 sweeps each): plain = one request after the other through
+    instance creation + pamc_anneal; served = the server, with every
+    request arriving at t = 0, then with Poisson arrivals at 0.8 x and
+    2.5 x the plain path's measured request rate.  Wall time includes
+    building each instance in every mode.  The plain path's latencies under
+    the same arrivals follow from its measured per-request times (one
+    request at a time, in arrival order)."""
+    import synth
+    R = 512
+    sched = pamc.schedule(**C5_SCHED)
+    reqs = synth.request_stream(count, 1.0, seed)
+    # warm-up
+    wi = pamc.Instance.csr(reqs[0].graph, replicas=R, seed=1)
+    wi.anneal(pamc.schedule(**dict(C5_SCHED, steps=3)))
+    wi.close()
+    torch.cuda.synchronize()
+    attempts = sum(q.graph.n for q in reqs) * R * C5_SCHED["steps"] * C5_SCHED["sweeps"]
+    t0 = time.perf_counter()
+    plain, service = {}, []
+    for q in reqs:
+        t1 = time.perf_counter()
+        inst = pamc.Instance.csr(q.graph, replicas=R, seed=q.seed)
+        plain[q.index] = inst.anneal(sched).best_cut
+        inst.close()
+        service.append(time.perf_counter() - t1)
+    t_plain = time.perf_counter() - t0
+    log(f"served bench: plain {count} requests in {t_plain:.2f} s")
+    out = {"requests": count, "replicas": R, "beta_steps": C5_SCHED["steps"], "sweeps": C5_SCHED["sweeps"],
+           "mean_n": sum(q.graph.n for q in reqs) / count, "hbm_budget_gb": budget_gb, "max_slots": slots,
+           "plain_attempts_per_s": attempts / t_plain, "plain_requests_per_s": count / t_plain}
+    def plain_latencies(arrivals):
+        # the plain path is one request at a time in arrival order
+        done, lat = 0.0, []
+        for a, sv in zip(arrivals, service):
+            done = max(done, a) + sv
+            lat.append(done - a)
+        return lat
+
+    for mode, load in (("burst", None), ("poisson", 0.8), ("poisson_overload", 2.5)):
+        rate = load * count / t_plain if load else None
+        arrivals = [0.0] * count if load is None else [q.arrival_s / rate for q in reqs]
+        srv = pamc.Server(int(budget_gb * (1 << 30)), slots, replicas=R)
+        tickets = {}
+        t0 = time.perf_counter()
+        nxt = 0
+        while True:
+            now = time.perf_counter() - t0
+            while nxt < count and arrivals[nxt] <= now:
+                q = reqs[nxt]
+                tickets[srv.submit(q.graph, q.seed, sched)] = q.index
+                nxt += 1
+            active, queued = srv.tick(tick_steps)
+            if nxt >= count and active == 0 and queued == 0:
+                break
+            if active == 0 and queued == 0 and nxt < count:
+                time.sleep(max(0.0, min(0.05, arrivals[nxt] - (time.perf_counter() - t0))))
+        wall = time.perf_counter() - t0
+        sstats = srv.stats()
+        lat, same = [], True
+        for t, idx in tickets.items():
+            res = srv.poll(t)
+            same = same and res.best_cut == plain[idx]
+            lat.append(srv.latency(t)[1])
+        srv.close()
+        pl = plain_latencies(arrivals)
+        out[mode] = {"attempts_per_s": attempts / wall, "wall_s": wall, "speedup_vs_plain": t_plain / wall,
+                     "latency_p50_s": percentile(lat, 0.5), "latency_p99_s": percentile(lat, 0.99),
+                     "plain_latency_p50_s": percentile(pl, 0.5), "plain_latency_p99_s": percentile(pl, 0.99),
+                     "identical_results": same,
+                     "server": {k: sstats[k] for k in ("ticks", "steps", "request_steps", "prep_seconds",
+                                                        "admit_seconds", "step_seconds", "peak_active",
+                                                        "peak_bytes")}}
+        if rate:
+            out[mode]["arrival_rate_per_s"] = rate
+            out[mode]["load_vs_plain_capacity"] = load
+        log(f"served bench: {mode} {wall:.2f} s, p50 {out[mode]['latency_p50_s']:.3f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +282,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fields", choices=["auto", "push", "pull"], default="auto")
+    ap.add_argument("--batched", default="c1",
+                    help="comma-separated workloads for the plain-vs-batched comparison ('' to skip)")
+    ap.add_argument("--batch-count", type=int, default=0, help="runs per batched comparison (0: default)")
+    ap.add_argument("--served", type=int, default=64,
+                    help="requests of the stream for the plain-vs-served comparison (0 to skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run an elementwise copy of this many MiB (int32 in, int32 out) five "
                          "times; used to scale the HBM byte counters of rocprofv3")
@@ -230,6 +370,8 @@ def main():
                 "traffic": counters_traffic(w["counters"], "sparse.hip"), "launch_ms": launch_ms,
                 "launches": prof["launches"], "attempts_per_launch": apl, "flip_rate": p_flip,
                 "algorithmic_bytes_per_attempt": bpa, "fields": "pull" if pull else "push",
+                "kernel_shape": {"tiles_per_wave": info.tiles_per_wave, "quads_per_wave": info.quads_per_wave,
+                                 "coupling_mode": info.coupling_mode},
                 "attempts_per_s_in_kernel": apl / (launch_ms * 1e-3)}
     out = {
         "metric": "spin-flip attempts/s + time-to-target-cut (plain vs batched/served), p50/p99",
@@ -251,6 +393,15 @@ def main():
                            "success_fraction": len(ttt) / len(runs), "final_cuts": finals},
         "roofline": roof,
     }
+    inst.close()
+    if args.batched:
+        out["batched"] = []
+        for name in args.batched.split(","):
+            log(f"batched comparison on {name} ...")
+            out["batched"].append(bench_batched(pamc, torch, name, args.batch_count or None))
+    if args.served:
+        log("served comparison ...")
+        out["served"] = bench_served(pamc, torch, args.served)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         cb = cpu_baseline(w, args.cpu_seconds)

@@ -126,10 +126,16 @@ void pamc_destroy_instance(pamc_instance* inst);
  * resets the RNG counters, keeping the instance's graph and buffers. */
 pamc_status pamc_reset_population(pamc_instance* inst, uint64_t seed);
 
+/* Instance facts.  pull: fields gathered at visit time (1) or kept
+ * incrementally (0).  The sweep kernel's shape for sparse instances:
+ * tiles_per_wave replica tiles of 64 per wavefront, quads_per_wave vertex
+ * quads per wavefront in a work-group, coupling_mode 0 (32-bit products),
+ * 1 (24-bit) or 2 (int8 couplings with 4-way dot products). */
 typedef struct {
   int32_t n, replicas, num_classes, dense, pull;
   int64_t nnz, W, X; /* X = max_v sum_j |J_vj| */
   int64_t device_bytes;
+  int32_t tiles_per_wave, quads_per_wave, coupling_mode, reserved;
 } pamc_info;
 pamc_status pamc_get_info(const pamc_instance* inst, pamc_info* out);
 
@@ -248,31 +254,48 @@ pamc_status pamc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, cons
                                pamc_server** out);
 
 /* Queues a Max-Cut (objective PAMC_OBJ_MAXCUT) or Ising request on a host CSR
- * graph (validated and copied now; the caller keeps its arrays).  Returns
- * PAMC_ERR_OUT_OF_MEMORY if the request alone exceeds the budget.  *ticket
- * identifies the request. */
+ * graph (copied now; the caller keeps its arrays).  The graph is validated,
+ * coloured and relabelled on one of the server's host threads (8, or
+ * PAMC_SERVER_THREADS) while the device runs other requests; a request that
+ * fails there finishes with that error (pamc_server_poll returns it).
+ * Returns PAMC_ERR_OUT_OF_MEMORY if the request alone exceeds the budget.
+ * *ticket identifies the request. */
 pamc_status pamc_server_submit(pamc_server* srv, int32_t n, const int32_t* row_ptr, const int32_t* col,
                                const int32_t* w, int32_t objective, uint64_t seed,
                                const pamc_schedule* sched, uint64_t* ticket);
 
-/* Admits what fits, advances the running requests by min(max_steps, steps
- * left of the nearest one) beta steps (max_steps <= 0: no cap), waits, and
- * retires finished requests.  n_active / n_queued (may be NULL) receive the
- * counts after the tick.  A request whose instance cannot be built is
- * dropped and its error returned. */
+/* Admits what fits (in submission order; a request still being prepared
+ * holds back the ones after it, and is waited for only when nothing runs),
+ * advances the running requests by min(max_steps, steps left of the nearest
+ * one) beta steps (max_steps <= 0: no cap), waits, and retires finished
+ * requests.  n_active / n_queued (may be NULL) receive the counts after the
+ * tick. */
 pamc_status pamc_server_tick(pamc_server* srv, int32_t max_steps, int32_t* n_active, int32_t* n_queued);
 
 /* Ticks until nothing is queued or running. */
 pamc_status pamc_server_drain(pamc_server* srv);
 
 /* *done = 1 and the result (and best spins, n entries, may be NULL) once
- * the request has finished, else *done = 0. */
+ * the request has finished, else *done = 0.  A request that failed (invalid
+ * graph, out of memory) has *done = 1 and its error as the return value. */
 pamc_status pamc_server_poll(pamc_server* srv, uint64_t ticket, int32_t* done, pamc_result* out,
                              int8_t* spins);
 
 /* Host wall-clock seconds from submission to admission and to retirement. */
 pamc_status pamc_server_latency(pamc_server* srv, uint64_t ticket, double* queued_seconds,
                                 double* total_seconds);
+
+/* Server counters: requests submitted / finished / failed, ticks, beta
+ * steps (per tick, and summed over running requests), host seconds spent
+ * preparing requests on the worker threads (colouring, relabelling),
+ * admitting them (device buffers, upload, initial population) and
+ * stepping, peak running requests and device bytes, and the current state. */
+typedef struct {
+  int64_t submitted, finished, failed, ticks, steps, request_steps;
+  double prep_seconds, admit_seconds, step_seconds;
+  int64_t peak_active, peak_bytes, in_use_bytes, active, queued;
+} pamc_server_stats;
+pamc_status pamc_server_get_stats(pamc_server* srv, pamc_server_stats* out);
 
 /* Drops a finished request's stored result. */
 pamc_status pamc_server_forget(pamc_server* srv, uint64_t ticket);

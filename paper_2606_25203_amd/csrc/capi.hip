@@ -9,8 +9,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <deque>
+#include <functional>
+#include <memory>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <unordered_map>
 #include <string>
 #include <tuple>
@@ -56,7 +61,7 @@ void free_instance(pamc_instance* I) {
   delete I->self;
   I->self = nullptr;
   if (I->d_sched) hipFree(I->d_sched);
-  void* ptrs[] = {I->g.row_ptr, I->g.col, I->g.J, I->g.class_ptr, I->pop.S[0], I->pop.S[1],
+  void* ptrs[] = {I->g.row_ptr, I->g.col, I->g.J, I->g.Jp, I->g.class_ptr, I->pop.S[0], I->pop.S[1],
                   I->pop.H[0], I->pop.H[1], I->pop.E[0], I->pop.E[1], I->pop.fam[0],
                   I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order, I->rs_P,
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
@@ -159,14 +164,23 @@ pamc::Batch* self_batch(pamc_instance* I, hipError_t* err) {
   pamc::Batch* var = self_batch(I, &var##_err);             \
   if (!var) return dev_fail(var##_err, "batch descriptors")
 
-// Sparse graph (already validated, couplings J in caller ids) -> colouring,
-// relabelling and device buffers, then the initial population.
-pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const int32_t* col,
-                         const std::vector<int32_t>& Jin) {
-  I->n = n;
-  I->np = (n + 3) & ~3;
-  I->nq = I->np / 4;
-  I->nnz = rp[n];
+// Host half of building a sparse instance (no device calls, safe on any
+// thread): first-fit colouring, class-major relabelling, the relabelled and
+// padded CSR, W, X and the choice of sweep kernel.  Jin: couplings J in
+// caller ids (already validated).  T: replica tiles.
+struct HostSparse {
+  int32_t n = 0, np = 0, nq = 0, ncls = 0, max_class_quads = 0;
+  int32_t small_j = 0, jmode = 0, pull = 0, tpw = 1, qpw = 1;
+  int64_t nnz = 0, W = 0, X = 0;
+  std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, Jp2;
+};
+
+pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const int32_t* col,
+                           const std::vector<int32_t>& Jin, uint32_t flags, int32_t T) {
+  h.n = n;
+  h.np = (n + 3) & ~3;
+  h.nq = h.np / 4;
+  h.nnz = rp[n];
   // first-fit colouring in id order: least colour unused by earlier neighbours
   std::vector<int32_t> colour(n, -1), stamp(n + 1, -1);
   int32_t ncls = 0;
@@ -178,80 +192,133 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
     colour[v] = c;
     ncls = std::max(ncls, c + 1);
   }
-  I->ncls = ncls;
-  I->class_ptr.assign(ncls + 1, 0);
-  for (int32_t v = 0; v < n; ++v) I->class_ptr[colour[v] + 1]++;
-  for (int32_t c = 0; c < ncls; ++c) I->class_ptr[c + 1] += I->class_ptr[c];
-  I->to_internal.resize(n);
-  I->to_input.resize(n);
+  h.ncls = ncls;
+  h.class_ptr.assign(ncls + 1, 0);
+  for (int32_t v = 0; v < n; ++v) h.class_ptr[colour[v] + 1]++;
+  for (int32_t c = 0; c < ncls; ++c) h.class_ptr[c + 1] += h.class_ptr[c];
+  h.to_internal.resize(n);
+  h.to_input.resize(n);
   {
-    std::vector<int32_t> next(I->class_ptr.begin(), I->class_ptr.end() - 1);
+    std::vector<int32_t> next(h.class_ptr.begin(), h.class_ptr.end() - 1);
     for (int32_t v = 0; v < n; ++v) {
       const int32_t iv = next[colour[v]]++;
-      I->to_internal[v] = iv;
-      I->to_input[iv] = v;
+      h.to_internal[v] = iv;
+      h.to_input[iv] = v;
     }
   }
-  I->max_class_quads = 0;
+  h.max_class_quads = 0;
   for (int32_t c = 0; c < ncls; ++c) {
-    const int32_t a = I->class_ptr[c], b = I->class_ptr[c + 1];
-    I->max_class_quads = std::max(I->max_class_quads, ((b + 3) >> 2) - (a >> 2));
+    const int32_t a = h.class_ptr[c], b = h.class_ptr[c + 1];
+    h.max_class_quads = std::max(h.max_class_quads, ((b + 3) >> 2) - (a >> 2));
   }
-  // relabelled CSR
-  // CSR arrays carry trailing padding (vertex 0, coupling 0) so that the
-  // sweep kernels may read a few entries past the last row.
-  std::vector<int32_t> rp2(n + 1, 0), col2(I->nnz + 16, 0), J2(I->nnz + 16, 0);
-  int64_t W = 0, X = 0;
+  // relabelled CSR; the arrays carry trailing padding (vertex 0, coupling
+  // 0) so that the sweep kernels may read a few entries past the last row
+  const size_t nnzp = (size_t)h.nnz + 16;
+  h.rp2.assign(n + 1, 0);
+  h.col2.assign(nnzp, 0);
+  h.J2.assign(nnzp, 0);
+  int64_t W = 0, X = 0, maxdeg = 0;
   for (int32_t iv = 0; iv < n; ++iv) {
-    const int32_t v = I->to_input[iv];
-    int32_t p = rp2[iv];
+    const int32_t v = h.to_input[iv];
+    int32_t p = h.rp2[iv];
     int64_t ab = 0;
     for (int32_t e = rp[v]; e < rp[v + 1]; ++e, ++p) {
-      col2[p] = I->to_internal[col[e]];
-      J2[p] = Jin[e];
+      h.col2[p] = h.to_internal[col[e]];
+      h.J2[p] = Jin[e];
       ab += std::llabs((long long)Jin[e]);
       if (col[e] > v) W -= Jin[e];
     }
-    rp2[iv + 1] = p;
+    h.rp2[iv + 1] = p;
     X = std::max(X, ab);
+    maxdeg = std::max<int64_t>(maxdeg, rp[v + 1] - rp[v]);
   }
   if (2 * X >= INT32_MAX) return fail(PAMC_ERR_INVALID_ARG, "local field range exceeds int32");
-  I->W = W;
-  I->X = X;
-  I->small_j = 1;
-  for (int32_t e = 0; e < rp[n]; ++e)
-    if (std::llabs((long long)Jin[e]) >= (1 << 23)) I->small_j = 0;
+  h.W = W;
+  h.X = X;
+  h.small_j = 1;
+  bool int8_j = true;
+  for (int32_t e = 0; e < rp[n]; ++e) {
+    const long long a = std::llabs((long long)Jin[e]);
+    if (a >= (1 << 23)) h.small_j = 0;
+    if (a > 127) int8_j = false;
+  }
+  // packed int8 couplings when they fit a byte and a work-group's energy
+  // change per replica fits 32 bits
+  h.jmode = (int8_j && X < (1 << 26)) ? 2 : (h.small_j ? 1 : 0);
+  if (const char* e = getenv("PAMC_JMODE")) {
+    const int m = atoi(e);
+    if (m == 0 || (m == 1 && h.small_j) || (m == 2 && h.jmode == 2)) h.jmode = m;
+  }
+  if (h.jmode == 2) {
+    h.Jp2.assign(nnzp, 0);
+    for (int64_t e = 0; e < h.nnz; ++e)
+      h.Jp2[e] = (int32_t)((uint32_t)(uint8_t)(int8_t)h.J2[e] << (8 * (h.col2[e] & 3)));
+  }
   // Field storage: kept incrementally (push) or gathered at visit time
   // (pull); both give the same integer fields and the same trajectory.
-  if (I->flags & PAMC_FLAG_FIELDS_PUSH)
-    I->pull = 0;
-  else if (I->flags & PAMC_FLAG_FIELDS_PULL)
-    I->pull = 1;
+  // Gathering a hub's field serialises one wavefront per tile over all of
+  // its neighbours; incremental fields spread that work over the flips.
+  if (flags & PAMC_FLAG_FIELDS_PUSH)
+    h.pull = 0;
+  else if (flags & PAMC_FLAG_FIELDS_PULL)
+    h.pull = 1;
   else
-  {
-    int64_t maxdeg = 0;
-    for (int32_t v = 0; v < n; ++v) maxdeg = std::max<int64_t>(maxdeg, rp[v + 1] - rp[v]);
-    // gathering a hub's field serialises one wavefront per tile over all of
-    // its neighbours; incremental fields spread that work over the flips
-    I->pull = (I->nnz <= 16 * (int64_t)n && maxdeg <= 64) ? 1 : 0;
-  }
+    h.pull = (h.nnz <= 16 * (int64_t)n && maxdeg <= 64) ? 1 : 0;
   // Tiles per wavefront: share the per-vertex scalar work among up to 4
-  // tiles while keeping enough work-groups to fill the chip.
-  {
-    const int64_t chunks = (I->max_class_quads + 15) / 16;
-    I->tpw = 1;
+  // tiles while keeping enough work-groups (one quad per wave) to fill the
+  // chip.  Then quads per wave: the most (fewer partial energy sums) that
+  // still leave about 16 work-groups per compute unit.
+  const int64_t W4 = pamc::sweep_waves();
+  const int64_t q1 = (h.max_class_quads + W4 - 1) / W4;
+  h.tpw = 1;
+  if (h.pull)
     for (int t : {4, 2})
-      if (I->T % t == 0 && (I->T / t) * chunks >= 1024) { I->tpw = t; break; }
-    if (const char* e = getenv("PAMC_TPW")) {
-      const int t = atoi(e);
-      if ((t == 1 || t == 2 || t == 4) && I->T % t == 0) I->tpw = t;
-    }
+      if (T % t == 0 && (T / t) * q1 >= 1024) {
+        h.tpw = t;
+        break;
+      }
+  if (const char* e = getenv("PAMC_TPW")) {
+    const int t = atoi(e);
+    if ((t == 1 || t == 2 || t == 4) && T % t == 0) h.tpw = t;
   }
+  h.qpw = 1;
+  for (int q : {4, 2})
+    if ((T / h.tpw) * ((h.max_class_quads + W4 * q - 1) / (W4 * q)) >= 4096) {
+      h.qpw = q;
+      break;
+    }
+  if (const char* e = getenv("PAMC_QPW")) {
+    const int q = atoi(e);
+    if (q == 1 || q == 2 || q == 4) h.qpw = q;
+  }
+  return PAMC_OK;
+}
+
+// Device half: buffers, upload and the initial population (waits).
+pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
+  const int32_t n = h.n, ncls = h.ncls;
+  I->n = n;
+  I->np = h.np;
+  I->nq = h.nq;
+  I->nnz = h.nnz;
+  I->ncls = ncls;
+  I->W = h.W;
+  I->X = h.X;
+  I->small_j = h.small_j;
+  I->jmode = h.jmode;
+  I->pull = h.pull;
+  I->tpw = h.tpw;
+  I->qpw = h.qpw;
+  I->max_class_quads = h.max_class_quads;
+  I->class_ptr = std::move(h.class_ptr);
+  I->to_internal = std::move(h.to_internal);
+  I->to_input = std::move(h.to_input);
   const size_t nnz = (size_t)I->nnz + 16;
   const size_t words = (size_t)I->T * I->nq * 64, hs = (size_t)I->T * I->np * 64;
   HIP_TRY(dalloc(I, &I->g.row_ptr, n + 1), "alloc");
   HIP_TRY(dalloc(I, &I->g.col, nnz), "alloc");
   HIP_TRY(dalloc(I, &I->g.J, nnz), "alloc");
+  if (I->jmode == 2) HIP_TRY(dalloc(I, &I->g.Jp, nnz), "alloc");
   HIP_TRY(dalloc(I, &I->g.class_ptr, ncls + 1), "alloc");
   for (int b = 0; b < 2; ++b) {
     HIP_TRY(dalloc(I, &I->pop.S[b], words), "alloc population");
@@ -262,7 +329,7 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
   HIP_TRY(dalloc(I, &I->best, I->np), "alloc");
   HIP_TRY(dalloc(I, &I->to_internal_dev, n), "alloc");
   HIP_TRY(dalloc(I, &I->st, 1), "alloc");
-  HIP_TRY(dalloc(I, &I->thr, 2 * X + 1), "alloc");
+  HIP_TRY(dalloc(I, &I->thr, 2 * I->X + 1), "alloc");
   I->order_cap = 64;
   HIP_TRY(dalloc(I, &I->order, (size_t)I->order_cap * ncls), "alloc");
   HIP_TRY(dalloc(I, &I->rs_P, I->R), "alloc");
@@ -274,16 +341,27 @@ pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const i
     HIP_TRY(hipMemsetAsync(I->pop.H[0], 0, sizeof(int32_t) * hs, I->stream), "memset");
     HIP_TRY(hipMemsetAsync(I->pop.H[1], 0, sizeof(int32_t) * hs, I->stream), "memset");
   }
-  HIP_TRY(hipMemcpyAsync(I->g.row_ptr, rp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, I->stream), "upload");
-  HIP_TRY(hipMemcpyAsync(I->g.col, col2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
-  HIP_TRY(hipMemcpyAsync(I->g.J, J2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(hipMemcpyAsync(I->g.row_ptr, h.rp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(hipMemcpyAsync(I->g.col, h.col2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
+  HIP_TRY(hipMemcpyAsync(I->g.J, h.J2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
+  if (I->g.Jp)
+    HIP_TRY(hipMemcpyAsync(I->g.Jp, h.Jp2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->g.class_ptr, I->class_ptr.data(), sizeof(int32_t) * (ncls + 1), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->to_internal_dev, I->to_internal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::prepare_cluster_lds(), "hipFuncSetAttribute");
   SELF_BATCH(I, b);
   HIP_TRY(pamc::batch_init(*b), "init kernels");
+  // the host arrays are read by the queued copies: wait before they go
   HIP_TRY(hipStreamSynchronize(I->stream), "init");
   return PAMC_OK;
+}
+
+pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const int32_t* col,
+                         const std::vector<int32_t>& Jin) {
+  HostSparse h;
+  pamc_status st = prepare_sparse(h, n, rp, col, Jin, I->flags, I->T);
+  if (st) return st;
+  return upload_sparse(I, h);
 }
 
 Schedule to_sched(const pamc_schedule* s) {
@@ -691,6 +769,10 @@ pamc_status pamc_get_info(const pamc_instance* I, pamc_info* out) {
   out->W = I->W;
   out->X = I->X;
   out->device_bytes = I->device_bytes;
+  out->tiles_per_wave = I->tpw;
+  out->quads_per_wave = I->qpw;
+  out->coupling_mode = I->jmode;
+  out->reserved = 0;
   return PAMC_OK;
 }
 
@@ -1031,11 +1113,67 @@ pamc_status pamc_synchronize(pamc_instance* I) {
 // ===========================================================================
 }  // extern "C"
 
+// Host preparation of one request (validation, colouring, relabelled CSR),
+// done on a worker thread while the device runs other requests.
+struct ServerPrep {
+  int32_t n = 0, objective = 0;
+  std::vector<int32_t> rp, col, w;
+  HostSparse h;
+  pamc_status status = PAMC_OK;
+  std::string error;
+  double seconds = 0.0;
+  std::mutex m;
+  std::condition_variable cv;
+  bool ready = false;
+};
+
+// Fixed pool of host threads for request preparation.
+class ServerWorkers {
+ public:
+  void start(int n) {
+    for (int i = 0; i < n; ++i) th_.emplace_back([this] { loop(); });
+  }
+  void push(std::function<void()> f) {
+    {
+      std::lock_guard<std::mutex> g(m_);
+      q_.push_back(std::move(f));
+    }
+    cv_.notify_one();
+  }
+  ~ServerWorkers() {
+    {
+      std::lock_guard<std::mutex> g(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+
+ private:
+  void loop() {
+    for (;;) {
+      std::function<void()> f;
+      {
+        std::unique_lock<std::mutex> g(m_);
+        cv_.wait(g, [this] { return stop_ || !q_.empty(); });
+        if (q_.empty()) return;  // stopping
+        f = std::move(q_.front());
+        q_.pop_front();
+      }
+      f();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex m_;
+  std::condition_variable cv_;
+  std::deque<std::function<void()>> q_;
+  bool stop_ = false;
+};
+
 struct pamc_server {
   struct Req {
     uint64_t ticket;
-    int32_t n, objective;
-    std::vector<int32_t> rp, col, w;
+    std::shared_ptr<ServerPrep> prep;
     uint64_t seed;
     pamc_schedule sched;
     int64_t est;
@@ -1050,9 +1188,11 @@ struct pamc_server {
     double t_submit, t_admit;
   };
   struct Fin {
-    pamc_result res;
+    pamc_status status = PAMC_OK;
+    std::string error;
+    pamc_result res{};
     std::vector<int8_t> spins;
-    double t_submit, t_admit, t_done;
+    double t_submit = 0, t_admit = 0, t_done = 0;
   };
   int device = 0;
   hipStream_t stream = nullptr;
@@ -1071,6 +1211,8 @@ struct pamc_server {
   int32_t* d_idx = nullptr;
   int32_t* d_status = nullptr;
   int32_t cap = 0;
+  pamc_server_stats stats{};
+  std::unique_ptr<ServerWorkers> workers;  // declared last: joined first
 };
 
 namespace {
@@ -1101,28 +1243,79 @@ int64_t estimate_bytes(int32_t n, const int32_t* rp, const pamc_config& cfg, con
   return b + 16 * 64;  // allocation granularity
 }
 
+void server_prepare(ServerPrep& p, uint32_t flags, int32_t T) {
+  const double t0 = now_seconds();
+  pamc_status st = validate_csr(p.n, p.rp.data(), p.col.data(), p.w.data(), false);
+  if (!st) {
+    std::vector<int32_t> J(std::max(p.rp[p.n], 1));
+    for (int32_t e = 0; e < p.rp[p.n]; ++e) J[e] = p.objective == PAMC_OBJ_MAXCUT ? -p.w[e] : p.w[e];
+    st = prepare_sparse(p.h, p.n, p.rp.data(), p.col.data(), J, flags, T);
+  }
+  std::lock_guard<std::mutex> g(p.m);
+  p.status = st;
+  if (st) p.error = g_err;  // this worker's message
+  p.rp = std::vector<int32_t>();
+  p.col = std::vector<int32_t>();
+  p.w = std::vector<int32_t>();
+  p.seconds = now_seconds() - t0;
+  p.ready = true;
+  p.cv.notify_all();
+}
+
+// Admits queued requests in order while slots and memory allow.  A request
+// whose host preparation is still running stops admission, unless nothing
+// runs, in which case it is waited for.
 pamc_status server_admit(pamc_server* S) {
   while (!S->queue.empty() && (int32_t)S->active.size() < S->max_slots &&
          S->in_use + S->queue.front().est <= S->budget) {
-    pamc_server::Req q = std::move(S->queue.front());
+    pamc_server::Req& front = S->queue.front();
+    ServerPrep& p = *front.prep;
+    {
+      std::unique_lock<std::mutex> g(p.m);
+      if (!p.ready) {
+        if (!S->active.empty()) break;
+        p.cv.wait(g, [&p] { return p.ready; });
+      }
+    }
+    pamc_server::Req q = std::move(front);
     S->queue.pop_front();
-    pamc_config c = S->cfg;
-    c.seed = q.seed;
-    c.stream = S->stream;
+    const double t0 = now_seconds();
+    S->stats.prep_seconds += p.seconds;
+    pamc_status st = p.status;
+    std::string err = p.error;
     pamc_instance* I = nullptr;
-    pamc_status st = pamc_create_instance_csr(q.n, q.rp.data(), q.col.data(), q.w.data(), PAMC_MEM_HOST,
-                                              q.objective, &c, &I);
     Schedule s = to_sched(&q.sched);
-    if (!st) st = prepare_run(I, s);
+    if (!st) {
+      I = new (std::nothrow) pamc_instance();
+      if (!I) st = fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
+      pamc_config c = S->cfg;
+      c.seed = q.seed;
+      c.stream = S->stream;
+      if (!st) st = open_device(I, &c);
+      if (!st) st = upload_sparse(I, p.h);
+      if (!st) st = prepare_run(I, s);
+      if (st) err = g_err;
+    }
+    q.prep.reset();
     if (st) {
       if (I) free_instance(I);
       S->pending.erase(q.ticket);
-      return st;
+      pamc_server::Fin f;
+      f.status = st;
+      f.error = err;
+      f.t_submit = f.t_admit = q.t_submit;
+      f.t_done = now_seconds();
+      S->done.emplace(q.ticket, std::move(f));
+      S->stats.failed += 1;
+      continue;
     }
     S->in_use += I->device_bytes;
+    S->stats.peak_bytes = std::max(S->stats.peak_bytes, S->in_use);
     S->active.push_back({q.ticket, I, s, 0, 1, q.t_submit, now_seconds()});
+    S->stats.peak_active = std::max<int64_t>(S->stats.peak_active, (int64_t)S->active.size());
     S->pending[q.ticket] = 1;
     S->dirty = true;
+    S->stats.admit_seconds += now_seconds() - t0;
   }
   return PAMC_OK;
 }
@@ -1152,6 +1345,7 @@ pamc_status server_retire(pamc_server* S, const std::vector<int32_t>& status) {
     S->pending.erase(a.ticket);
     S->done.emplace(a.ticket, std::move(f));
     S->dirty = true;
+    S->stats.finished += 1;
   }
   S->active.swap(keep);
   return PAMC_OK;
@@ -1177,6 +1371,10 @@ pamc_status pamc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, cons
   S->budget = hbm_budget_bytes;
   S->max_slots = max_slots;
   S->cfg = *cfg;
+  int nthreads = 8;
+  if (const char* e = getenv("PAMC_SERVER_THREADS")) nthreads = std::max(1, std::min(64, atoi(e)));
+  S->workers.reset(new ServerWorkers());
+  S->workers->start(nthreads);
   hipSetDevice(S->device);
   if (cfg->stream) {
     S->stream = (hipStream_t)cfg->stream;
@@ -1193,30 +1391,38 @@ pamc_status pamc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, cons
 pamc_status pamc_server_submit(pamc_server* S, int32_t n, const int32_t* row_ptr, const int32_t* col,
                                const int32_t* w, int32_t objective, uint64_t seed,
                                const pamc_schedule* sched, uint64_t* ticket) {
-  if (!S || !sched || !ticket) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  if (!S || !sched || !ticket || !row_ptr) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
   if (objective != PAMC_OBJ_MAXCUT && objective != PAMC_OBJ_ISING)
     return fail(PAMC_ERR_INVALID_ARG, "unknown objective");
-  pamc_status st = validate_csr(n, row_ptr, col, w, false);
-  if (st) return st;
+  if (n <= 0) return fail(PAMC_ERR_INVALID_ARG, "n must be positive");
+  if (row_ptr[0] != 0) return fail(PAMC_ERR_INVALID_ARG, "row_ptr[0] must be 0");
+  for (int32_t v = 0; v < n; ++v)
+    if (row_ptr[v + 1] < row_ptr[v]) return fail(PAMC_ERR_INVALID_ARG, "row_ptr must be non-decreasing");
+  if (row_ptr[n] > 0 && (!col || !w)) return fail(PAMC_ERR_INVALID_ARG, "NULL CSR array");
   pamc_instance probe;  // schedule checks only look at the kind of instance
-  st = check_schedule(&probe, sched);
+  pamc_status st = check_schedule(&probe, sched);
   if (st) return st;
   pamc_server::Req q;
   q.est = estimate_bytes(n, row_ptr, S->cfg, *sched);
   if (q.est > S->budget) return fail(PAMC_ERR_OUT_OF_MEMORY, "request larger than the server's memory budget");
+  auto prep = std::make_shared<ServerPrep>();
+  prep->n = n;
+  prep->objective = objective;
+  prep->rp.assign(row_ptr, row_ptr + n + 1);
+  prep->col.assign(col ? col : row_ptr, (col ? col : row_ptr) + row_ptr[n]);
+  prep->w.assign(w ? w : row_ptr, (w ? w : row_ptr) + row_ptr[n]);
+  q.prep = prep;
   q.ticket = S->next_ticket++;
-  q.n = n;
-  q.objective = objective;
-  q.rp.assign(row_ptr, row_ptr + n + 1);
-  q.col.assign(col, col + std::max(row_ptr[n], 1));
-  q.w.assign(w, w + std::max(row_ptr[n], 1));
-  if (row_ptr[n] == 0) q.col[0] = q.w[0] = 0;
   q.seed = seed;
   q.sched = *sched;
   q.t_submit = now_seconds();
+  const uint32_t flags = S->cfg.flags;
+  const int32_t T = S->cfg.replicas / 64;
+  S->workers->push([prep, flags, T] { server_prepare(*prep, flags, T); });
   S->pending[q.ticket] = 0;
   *ticket = q.ticket;
   S->queue.push_back(std::move(q));
+  S->stats.submitted += 1;
   return PAMC_OK;
 }
 
@@ -1266,12 +1472,17 @@ pamc_status pamc_server_tick(pamc_server* S, int32_t max_steps, int32_t* n_activ
     int32_t k = INT32_MAX;
     for (auto& a : S->active) k = std::min(k, std::max(a.s.steps - a.launched, 1));
     if (max_steps > 0) k = std::min(k, max_steps);
+    const double t_step = now_seconds();
     for (int32_t i = 0; i < k; ++i) HIP_TRY(pamc::batch_step(S->batch), "step");
     for (auto& a : S->active) a.launched += k;
     HIP_TRY(pamc::batch_status(S->batch, S->d_status), "status");
     std::vector<int32_t> status(na);
     HIP_TRY(hipMemcpyAsync(status.data(), S->d_status, sizeof(int32_t) * na, hipMemcpyDeviceToHost, S->stream), "readback");
     HIP_TRY(hipStreamSynchronize(S->stream), "batched steps");
+    S->stats.step_seconds += now_seconds() - t_step;
+    S->stats.ticks += 1;
+    S->stats.steps += k;
+    S->stats.request_steps += (int64_t)k * na;
     st = server_retire(S, status);
     if (st) return st;
   }
@@ -1298,8 +1509,18 @@ pamc_status pamc_server_poll(pamc_server* S, uint64_t ticket, int32_t* done, pam
     return PAMC_OK;
   }
   *done = 1;
+  if (it->second.status) return fail(it->second.status, it->second.error);
   if (out) *out = it->second.res;
   if (spins) memcpy(spins, it->second.spins.data(), it->second.spins.size());
+  return PAMC_OK;
+}
+
+pamc_status pamc_server_get_stats(pamc_server* S, pamc_server_stats* out) {
+  if (!S || !out) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  *out = S->stats;
+  out->in_use_bytes = S->in_use;
+  out->active = (int64_t)S->active.size();
+  out->queued = (int64_t)S->queue.size();
   return PAMC_OK;
 }
 
@@ -1320,6 +1541,7 @@ pamc_status pamc_server_forget(pamc_server* S, uint64_t ticket) {
 
 void pamc_server_destroy(pamc_server* S) {
   if (!S) return;
+  S->workers.reset();  // finishes the preparations in flight
   hipSetDevice(S->device);
   hipStreamSynchronize(S->stream);
   for (auto& a : S->active) free_instance(a.I);

@@ -31,6 +31,7 @@ struct GraphDev {
   int32_t* row_ptr = nullptr;
   int32_t* col = nullptr;
   int32_t* J = nullptr;
+  int32_t* Jp = nullptr;  // int8 couplings shifted to the neighbour's spin byte (coupling mode 2)
   int32_t* class_ptr = nullptr;
 };
 
@@ -49,7 +50,9 @@ struct pamc_instance {
   int32_t max_class_quads = 0;
   int32_t pull = 0;       // 1: fields gathered at visit time (no field array)
   int32_t tpw = 1;        // replica tiles per wavefront in the gathered-field sweep
+  int32_t qpw = 1;        // vertex quads per wavefront in a sweep work-group (1, 2, 4)
   int32_t small_j = 0;    // 1: every |J| < 2^23 (24-bit multiplies are exact)
+  int32_t jmode = 0;      // gathered-field coupling mode: 0 32-bit, 1 24-bit, 2 packed int8
   int32_t host_cur = 0;   // population buffer index last read back
   int32_t* H_scratch = nullptr;  // fields for snapshots in pull mode
   pamc::GraphDev g;
@@ -120,6 +123,7 @@ struct Desc {
   const int32_t* row_ptr;
   const int32_t* col;
   const int32_t* J;
+  const int32_t* Jp;
   const int32_t* class_ptr;
   int32_t* order;
   uint32_t* thr;
@@ -143,14 +147,14 @@ struct Desc {
   int64_t* flip_ctr;      // null unless profiling
   const int8_t *D0, *D1;  // dense instances: replica-major spins [R][np]
   int64_t W, X;
-  int32_t n, np, nq, R, T, ncls, rule, pull, dense, shuffle, tr_cap, order_cap;
+  int32_t n, np, nq, R, T, ncls, rule, pull, dense, shuffle, tr_cap, order_cap, qpw;
   uint32_t k0, k1;
 };
 
 // A set of instances advanced by the same launches.  Grid kernels read a map
 // of (instance << 32 | local block) words; one map per launch kind.
 struct Batch {
-  static constexpr int kGroups = 12;  // sweep kernel variants
+  static constexpr int kGroups = 19;  // sweep kernel variants
   static int group_of(const pamc_instance* I);
   struct Launch {
     uint64_t* map = nullptr;
@@ -163,6 +167,7 @@ struct Batch {
   hipStream_t stream = nullptr;
   std::vector<pamc_instance*> I;
   int32_t max_ncls = 0, max_sweeps = 1, any_cluster = 0;
+  int32_t group_ncls[kGroups] = {};  // most colour classes of an instance in each sweep group
   int64_t max_lds = 0;
   void free_device();
   Batch() = default;
@@ -190,6 +195,7 @@ hipError_t launch_fields(Batch& b, int32_t buf, int32_t* H);
 hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
 hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
 int32_t cluster_max_n();
+int32_t sweep_waves();  // wavefronts per sweep work-group
 hipError_t prepare_cluster_lds();
 
 // controller pieces (sparse.hip) shared with the dense path

@@ -33,14 +33,27 @@ constexpr int kHistCap = 64;    // controller history capacity (>= win_long)
 // ---------------------------------------------------------------------------
 struct u32x4 { uint32_t a, b, c, d; };
 
-__host__ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
-                                                   uint32_t c3, uint32_t k0, uint32_t k1) {
+// a ^ b ^ c in one three-input bitwise instruction (truth table 0x96).  Only
+// worth it when at most one operand is wave-uniform: two scalar operands
+// would need a copy to a vector register first.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// The counters used here always hold some uniform words (quad, sweep, tag
+// or the like), so the first rounds mix uniform and per-lane values: those
+// keep plain xors (uniform pairs are combined on the scalar unit); from the
+// fourth round on every word is per-lane and the three-input form halves
+// the xor count.
+__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
     const uint64_t m0 = (uint64_t)c0 * 0xD2511F53u;
     const uint64_t m1 = (uint64_t)c2 * 0xCD9E8D57u;
-    const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+    const uint32_t h0 = (uint32_t)(m0 >> 32), h1 = (uint32_t)(m1 >> 32);
+    const uint32_t n0 = i < 3 ? (h1 ^ (c1 ^ k0)) : xor3(h1, c1, k0);
+    const uint32_t n2 = i < 2 ? (h0 ^ (c3 ^ k1)) : xor3(h0, c3, k1);
     c1 = (uint32_t)m1;
     c3 = (uint32_t)m0;
     c0 = n0;

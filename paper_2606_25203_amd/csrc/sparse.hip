@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "instance.hpp"
@@ -27,8 +28,7 @@ namespace pamc {
 namespace {
 
 constexpr int kSweepWaves = 4;             // waves per sweep workgroup
-constexpr int kQuadsPerWave = 4;           // quads per wave per workgroup
-constexpr int kQuadsPerBlock = kSweepWaves * kQuadsPerWave;
+constexpr int kMaxQuadsPerWave = 4;        // quads per wave per sweep work-group: 1, 2 or 4 (Desc::qpw)
 constexpr int kGatherQuadsPerBlock = 64;
 constexpr int kClusterMaxN = 26000;        // LDS: 5 bytes per vertex
 constexpr int kRsMaxR = 16384;
@@ -38,6 +38,7 @@ constexpr int kInitBlocks = 64;            // spin-init work-groups per instance
 constexpr int kApplyChunks = 16;           // cluster-apply work-groups per target
 constexpr int kFieldBlocks = 1024;         // max field-init work-groups per instance
 constexpr uint32_t kIdle = 0xFFFFFFFFu;    // padding block: returns at once
+constexpr int kBufferWord3 = 0x00020000;   // buffer resource word 3: 32-bit raw data
 
 // Map word: instance index in the high half, local block in the low half.
 __device__ __forceinline__ bool resolve(const uint64_t* __restrict__ map, int& inst, int& lb) {
@@ -80,13 +81,17 @@ __device__ __forceinline__ void group_chunk(int G, int lb, int& group, int& chun
 // Neighbours are taken four at a time with unconditional loads (the CSR
 // arrays carry trailing padding, and an entry past the row is a valid vertex
 // id), and the couplings of entries past the row are masked to zero, so the
-// loop body has no per-entry branches.  Srow0 points at the first tile's
-// spin words + lane; tiles are tstride words apart.
+// loop body has no per-entry branches.  Spin words are read with buffer
+// loads: one resource per tile, the neighbour quad as the scalar offset and
+// the lane as the vector offset, so address arithmetic stays on the scalar
+// unit.  Coupling modes (JM): 0 full 32-bit products, 1 24-bit
+// products (|J| < 2^23), 2 int8 couplings pre-shifted to the neighbour's byte
+// of its spin word, so one 4 x int8 dot product adds J s_j.
 // ---------------------------------------------------------------------------
-template <bool SMALLJ, int TPW>
+template <int JM, int TPW>
 __device__ __forceinline__ void gather_fields(const PAMC_GLOBAL int32_t* __restrict__ col,
                                               const PAMC_GLOBAL int32_t* __restrict__ J, int e0, int e1,
-                                              const PAMC_GLOBAL uint32_t* __restrict__ Srow0, uint32_t tstride,
+                                              const __amdgpu_buffer_rsrc_t (&Stile)[TPW], int lane_bytes,
                                               int32_t (&h)[TPW]) {
 #pragma unroll
   for (int t = 0; t < TPW; ++t) h[t] = 0;
@@ -96,35 +101,38 @@ __device__ __forceinline__ void gather_fields(const PAMC_GLOBAL int32_t* __restr
     int32_t c[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      j[u] = col[e + u];
-      c[u] = u < cnt ? J[e + u] : 0;
+      // uniform by construction; stated so that a vector load of them can
+      // never turn the buffer offsets below into per-lane values
+      j[u] = __builtin_amdgcn_readfirstlane(col[e + u]);
+      c[u] = u < cnt ? __builtin_amdgcn_readfirstlane(J[e + u]) : 0;
     }
     uint32_t w[TPW][4];
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        w[t][u] = Srow0[(uint32_t)t * tstride + (uint32_t)(j[u] >> 2) * (uint32_t)kLanes];
+        w[t][u] = __builtin_amdgcn_raw_buffer_load_b32(Stile[t], lane_bytes, (j[u] >> 2) * (kLanes * 4), 0);
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[t][u], 8u * (uint32_t)(j[u] & 3), 8u);
-        // couplings below 2^23 in magnitude use the full-rate 24-bit multiply
-        h[t] += SMALLJ ? __mul24(c[u], sv) : c[u] * sv;
+        if (JM == 2) {
+          h[t] = __builtin_amdgcn_sdot4((int)w[t][u], c[u], h[t], false);
+        } else {
+          const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[t][u], 8u * (uint32_t)(j[u] & 3), 8u);
+          h[t] += JM == 1 ? __mul24(c[u], sv) : c[u] * sv;
+        }
       }
   }
 }
 
+// Work-group totals: energy changes per replica (red[wave * ntiles + t][lane])
+// into E, flip counts per wave (fred, filled by lane 0 of each wave) into
+// the profiling counters.
 __device__ __forceinline__ void reduce_energy_and_flips(int64_t (*red)[kLanes], int32_t* fred, int wave,
                                                         int lane, int ntiles, int tile0,
-                                                        PAMC_GLOBAL int64_t* E, int32_t nflip,
+                                                        PAMC_GLOBAL int64_t* E,
                                                         PAMC_GLOBAL int64_t* flip_ctr) {
-  if (flip_ctr) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) nflip += __shfl_xor(nflip, o, 64);
-    if (lane == 0) fred[wave] = nflip;
-  }
   __syncthreads();
   if (wave < ntiles) {
     const int t = wave;
@@ -149,59 +157,53 @@ __device__ __forceinline__ void reduce_energy_and_flips(int64_t (*red)[kLanes], 
 // x = s*h, u = Philox word (quad, sweep, replica), flip iff u < T[x]
 // (Metropolis also for x <= 0).  Vertices of a class are mutually
 // uncoupled, so no spin read here as a neighbour is written here.
+// The threshold table is read from LDS (THR_LDS) or from global memory.
+// With int8 couplings (JM 2) the energy change of a lane over one
+// work-group stays below 2^31 (|x| <= X < 2^26, at most 4 kMaxQuadsPerWave
+// vertices), so it is summed in 32 bits.
 // ---------------------------------------------------------------------------
-template <bool SMALLJ, int TPW>
+template <int JM, int TPW, bool THR_LDS>
 __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __restrict__ row_ptr,
                                                 const PAMC_GLOBAL int32_t* __restrict__ col,
                                                 const PAMC_GLOBAL int32_t* __restrict__ Jc,
-                                                const PAMC_GLOBAL int32_t* __restrict__ class_ptr,
-                                                const PAMC_GLOBAL int32_t* __restrict__ order,
-                                                const PAMC_GLOBAL uint32_t* __restrict__ thr_g, const Desc& d,
-                                                int lb, int sweep_idx, int phase) {
+                                                const PAMC_GLOBAL uint32_t* __restrict__ thr_g,
+                                                uint32_t* thr_s, PAMC_GLOBAL uint32_t* __restrict__ S,
+                                                PAMC_GLOBAL int64_t* __restrict__ E, const Desc& d,
+                                                int group, int chunk, int v0, int v1, uint32_t gs,
+                                                int32_t Xt) {
+  using acc_t = typename std::conditional<JM == 2, int32_t, int64_t>::type;
   __shared__ int64_t red[kSweepWaves * TPW][kLanes];
   __shared__ int32_t fred[kSweepWaves];
-  __shared__ uint32_t thr_s[kThrLds];
-  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
-  const int cur = st->cur;
-  PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0);
-  PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
-  const int cls = order[sweep_idx * d.ncls + phase];
-  const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
   const int q0 = v0 >> 2;
   const int nqc = ((v1 + 3) >> 2) - q0;
-  int group, chunk;
-  group_chunk(d.T / TPW, lb, group, chunk);
-  if (chunk * kQuadsPerBlock >= nqc) return;
-  const uint32_t gs = st->gs + (uint32_t)sweep_idx;
-  const int rule = d.rule;
-  const int32_t Xt = (int32_t)st->table_x;
-  const bool thr_lds = 2 * Xt + 1 <= kThrLds;
-  if (thr_lds)
-    for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
-  __syncthreads();
-  const uint32_t* __restrict__ thr = thr_lds ? thr_s : (const uint32_t*)thr_g;
+  const bool metropolis = d.rule == 1;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile0 = group * TPW;
   const uint32_t tstride = (uint32_t)d.nq * kLanes;
-  PAMC_GLOBAL uint32_t* __restrict__ Srow0 = S + (size_t)tile0 * tstride + lane;
-  int64_t dE[TPW];
+  __amdgpu_buffer_rsrc_t Stile[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+    Stile[t] = __builtin_amdgcn_make_buffer_rsrc((void*)(S + (size_t)(tile0 + t) * tstride), (short)0,
+                                                 (int)(tstride * 4), kBufferWord3);
+  const int lane_bytes = lane * 4;
+  acc_t dE[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) dE[t] = 0;
   int32_t nflip = 0;
-  for (int i = 0; i < kQuadsPerWave; ++i) {
-    const int qi = chunk * kQuadsPerBlock + i * kSweepWaves + wave;
+  for (int i = 0; i < d.qpw; ++i) {
+    const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
     if (qi >= nqc) break;
     const int q = q0 + qi;
     uint32_t sw[TPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) sw[t] = Srow0[(uint32_t)t * tstride + (uint32_t)q * kLanes];
+    for (int t = 0; t < TPW; ++t) sw[t] = __builtin_amdgcn_raw_buffer_load_b32(Stile[t], lane_bytes, q * (kLanes * 4), 0);
     int32_t h[4][TPW];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
       if (v >= v0 && v < v1) {
-        gather_fields<SMALLJ, TPW>(col, Jc, row_ptr[v], row_ptr[v + 1], Srow0, tstride, h[k]);
+        gather_fields<JM, TPW>(col, Jc, row_ptr[v], row_ptr[v + 1], Stile, lane_bytes, h[k]);
       } else {
 #pragma unroll
         for (int t = 0; t < TPW; ++t) h[k][t] = 0;
@@ -211,43 +213,64 @@ __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __res
     for (int t = 0; t < TPW; ++t) {
       const uint32_t r = (uint32_t)((tile0 + t) * kLanes + lane);
       const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
-      bool dirty = false;
-      uint32_t swt = sw[t];
+      const uint32_t swt = sw[t];
+      uint32_t flipmask = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int v = 4 * q + k;
         if (v < v0 || v >= v1) continue;
-        const int32_t s = (int32_t)(int8_t)(swt >> (8 * k));
-        const int32_t x = s * h[k][t];
-        const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
-        const uint32_t T = thr[xi + Xt];
-        const bool flip = (rule == 1 && x <= 0) || (pick(rnd, k) < T);
-        if (flip) {
-          dE[t] += 2 * (int64_t)x;
-          swt ^= (0xFEu << (8 * k));  // +1 (0x01) <-> -1 (0xFF)
-          dirty = true;
-          ++nflip;
-        }
+        const int32_t s = __builtin_amdgcn_sbfe((int32_t)swt, 8u * k, 8u);
+        const int32_t x = __mul24(s, h[k][t]);
+        const int32_t xi = min(max(x, -Xt), Xt) + Xt;
+        const uint32_t T = THR_LDS ? thr_s[xi] : thr_g[xi];
+        const bool flip = (pick(rnd, k) < T) || (metropolis && x <= 0);
+        dE[t] += flip ? (acc_t)x : (acc_t)0;
+        flipmask |= flip ? (0xFEu << (8 * k)) : 0u;  // +1 (0x01) <-> -1 (0xFF)
+        nflip += __popcll(__ballot(flip));
       }
-      if (dirty) Srow0[(uint32_t)t * tstride + (uint32_t)q * kLanes] = swt;
+      if (flipmask) __builtin_amdgcn_raw_buffer_store_b32(swt ^ flipmask, Stile[t], lane_bytes, q * (kLanes * 4), 0);
     }
   }
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) red[wave * TPW + t][lane] = dE[t];
-  reduce_energy_and_flips(red, fred, wave, lane, TPW, tile0, E, nflip, gmem(d.flip_ctr));
+  for (int t = 0; t < TPW; ++t) red[wave * TPW + t][lane] = 2 * (int64_t)dE[t];
+  if (lane == 0) fred[wave] = nflip;
+  reduce_energy_and_flips(red, fred, wave, lane, TPW, tile0, E, gmem(d.flip_ctr));
 }
 
-template <bool SMALLJ, int TPW>
+// WIDE: the instance's threshold table (2X + 1 entries) may exceed the LDS
+// copy, so every lookup goes to global memory.  The host picks the variant
+// from X; one loop body per kernel keeps the code small.
+template <int JM, int TPW, bool WIDE>
 __global__ void __launch_bounds__(256) k_sweep_pull(const Desc* __restrict__ D,
                                                   const uint64_t* __restrict__ map, int sweep_idx,
                                                   int phase) {
+  __shared__ uint32_t thr_s[WIDE ? 1 : kThrLds];
   int inst, lb;
   if (!resolve(map, inst, lb)) return;
   const Desc& d = D[inst];
   const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
   if (!st->active || sweep_idx >= st->nsweeps_now || phase >= d.ncls) return;
-  sweep_pull_body<SMALLJ, TPW>(gmem(d.row_ptr), gmem(d.col), gmem(d.J), gmem(d.class_ptr), gmem((const int32_t*)d.order),
-                               gmem((const uint32_t*)d.thr), d, lb, sweep_idx, phase);
+  const int cur = st->cur;
+  const PAMC_GLOBAL int32_t* __restrict__ order = gmem((const int32_t*)d.order);
+  const PAMC_GLOBAL int32_t* __restrict__ class_ptr = gmem(d.class_ptr);
+  const int cls = order[sweep_idx * d.ncls + phase];
+  const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
+  const int nqc = ((v1 + 3) >> 2) - (v0 >> 2);
+  int group, chunk;
+  group_chunk(d.T / TPW, lb, group, chunk);
+  if (chunk * (kSweepWaves * d.qpw) >= nqc) return;
+  const uint32_t gs = st->gs + (uint32_t)sweep_idx;
+  const int32_t Xt = (int32_t)st->table_x;
+  const PAMC_GLOBAL uint32_t* __restrict__ thr_g = gmem((const uint32_t*)d.thr);
+  PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0);
+  PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
+  const PAMC_GLOBAL int32_t* __restrict__ Jc = gmem(JM == 2 ? d.Jp : d.J);
+  if (!WIDE) {
+    for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
+    __syncthreads();
+  }
+  sweep_pull_body<JM, TPW, !WIDE>(gmem(d.row_ptr), gmem(d.col), Jc, thr_g, thr_s, S, E, d, group, chunk, v0, v1, gs,
+                                  Xt);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,7 +300,7 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
   const int nqc = ((v1 + 3) >> 2) - q0;
   int tile, chunk;
   group_chunk(d.T, lb, tile, chunk);
-  if (chunk * kQuadsPerBlock >= nqc) return;
+  if (chunk * (kSweepWaves * d.qpw) >= nqc) return;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
   const int rule = d.rule;
   const int32_t Xt = (int32_t)st->table_x;
@@ -292,8 +315,8 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
   const size_t hbase = (size_t)tile * d.np;
   int64_t dE = 0;
   int32_t nflip = 0;
-  for (int i = 0; i < kQuadsPerWave; ++i) {
-    const int qi = chunk * kQuadsPerBlock + i * kSweepWaves + wave;
+  for (int i = 0; i < d.qpw; ++i) {
+    const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
     if (qi >= nqc) break;
     const int q = q0 + qi;
     const size_t sidx = ((size_t)tile * d.nq + q) * kLanes + lane;
@@ -332,7 +355,12 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
     if (dirty) S[sidx] = sw;
   }
   red[wave][lane] = dE;
-  reduce_energy_and_flips(red, fred, wave, lane, 1, tile, E, nflip, gmem(d.flip_ctr));
+  if (d.flip_ctr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nflip += __shfl_xor(nflip, o, 64);
+    if (lane == 0) fred[wave] = nflip;
+  }
+  reduce_energy_and_flips(red, fred, wave, lane, 1, tile, E, gmem(d.flip_ctr));
 }
 
 __global__ void __launch_bounds__(256) k_sweep_push(const Desc* __restrict__ D,
@@ -1111,6 +1139,7 @@ __global__ void __launch_bounds__(256) k_pair_distance(const uint32_t* S0, const
 // Batches and their launchers
 // ===========================================================================
 int32_t cluster_max_n() { return kClusterMaxN; }
+int32_t sweep_waves() { return kSweepWaves; }
 
 hipError_t prepare_cluster_lds() {
   return hipFuncSetAttribute((const void*)k_cl_mis, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1123,6 +1152,7 @@ Desc make_desc(const pamc_instance* I) {
   d.row_ptr = I->g.row_ptr;
   d.col = I->g.col;
   d.J = I->g.J;
+  d.Jp = I->g.Jp;
   d.class_ptr = I->g.class_ptr;
   d.order = I->order;
   d.thr = I->thr;
@@ -1163,6 +1193,7 @@ Desc make_desc(const pamc_instance* I) {
   d.dense = I->dense;
   d.shuffle = (I->flags & 1u) ? 0 : 1;
   d.tr_cap = I->tr_cap;
+  d.qpw = I->qpw;
   d.order_cap = I->order_cap;
   d.k0 = (uint32_t)I->seed;
   d.k1 = (uint32_t)(I->seed >> 32);
@@ -1172,7 +1203,8 @@ Desc make_desc(const pamc_instance* I) {
 int Batch::group_of(const pamc_instance* I) {
   if (!I->pull) return 0;
   const int ti = I->tpw == 4 ? 2 : (I->tpw == 2 ? 1 : 0);
-  return 6 + (I->small_j ? 3 : 0) + ti;
+  const int wide = 2 * I->X + 1 > kThrLds ? 1 : 0;
+  return 1 + 9 * wide + 3 * I->jmode + ti;
 }
 
 void Batch::free_device() {
@@ -1193,7 +1225,8 @@ void Batch::free_device() {
 }
 
 static int64_t sweep_chunks(const pamc_instance* I) {
-  return (I->max_class_quads + kQuadsPerBlock - 1) / kQuadsPerBlock;
+  const int qpb = kSweepWaves * I->qpw;
+  return (I->max_class_quads + qpb - 1) / qpb;
 }
 
 // Appends an instance's local blocks to a map.  With align8 the instance's
@@ -1227,6 +1260,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
   std::vector<uint64_t> m_init, m_fields, m_thr, m_gather, m_mis, m_apply;
   std::vector<std::vector<uint64_t>> m_sweep(Batch::kGroups);
   b.max_ncls = 0;
+  for (int g = 0; g < Batch::kGroups; ++g) b.group_ncls[g] = 0;
   b.max_sweeps = 1;
   b.any_cluster = 0;
   b.max_lds = 0;
@@ -1237,8 +1271,10 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     add_blocks(m_fields, i, field_blocks(I), false);
     add_blocks(m_thr, i, kThrBlocks, false);
     add_blocks(m_gather, i, (int64_t)I->T * ((I->nq + kGatherQuadsPerBlock - 1) / kGatherQuadsPerBlock), true);
-    add_blocks(m_sweep[Batch::group_of(I)], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_chunks(I), true);
+    const int grp = Batch::group_of(I);
+    add_blocks(m_sweep[grp], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_chunks(I), true);
     b.max_ncls = std::max(b.max_ncls, I->ncls);
+    b.group_ncls[grp] = std::max(b.group_ncls[grp], I->ncls);
     const int nt = std::min(I->cl_cap_top, I->R);
     if (nt > 0 && I->cl_cap_trials > 0) {
       add_blocks(m_mis, i, (int64_t)nt * I->cl_cap_trials, false);
@@ -1279,17 +1315,20 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
 
 using SweepKernel = void (*)(const Desc*, const uint64_t*, int, int);
 
+template <bool WIDE>
+static SweepKernel pull_kernel(int jm, int ti) {
+  static const SweepKernel k[3][3] = {
+      {k_sweep_pull<0, 1, WIDE>, k_sweep_pull<0, 2, WIDE>, k_sweep_pull<0, 4, WIDE>},
+      {k_sweep_pull<1, 1, WIDE>, k_sweep_pull<1, 2, WIDE>, k_sweep_pull<1, 4, WIDE>},
+      {k_sweep_pull<2, 1, WIDE>, k_sweep_pull<2, 2, WIDE>, k_sweep_pull<2, 4, WIDE>}};
+  return k[jm][ti];
+}
+
 static SweepKernel sweep_kernel_of_group(int g) {
-  // group = 0 (incremental fields) or 6 + 3 * small_j + tiles-per-wave index
-  switch (g) {
-    case 6: return k_sweep_pull<false, 1>;
-    case 7: return k_sweep_pull<false, 2>;
-    case 8: return k_sweep_pull<false, 4>;
-    case 9: return k_sweep_pull<true, 1>;
-    case 10: return k_sweep_pull<true, 2>;
-    case 11: return k_sweep_pull<true, 4>;
-    default: return k_sweep_push;
-  }
+  // group = 0 (incremental fields) or 1 + 9 * wide table + 3 * coupling mode + tiles-per-wave index
+  if (g == 0) return k_sweep_push;
+  const int x = g - 1;
+  return x >= 9 ? pull_kernel<true>((x - 9) / 3, (x - 9) % 3) : pull_kernel<false>(x / 3, x % 3);
 }
 
 static hipEvent_t next_event(pamc_instance* I) {
@@ -1311,7 +1350,7 @@ static hipError_t batch_sweeps(Batch& b, int32_t nsweeps) {
   for (int s = 0; s < nsweeps; ++s) {
     for (int p = 0; p < b.max_ncls; ++p) {
       for (int g = 0; g < Batch::kGroups; ++g) {
-        if (!b.sweep[g].grid) continue;
+        if (!b.sweep[g].grid || p >= b.group_ncls[g]) continue;  // no instance of the group has class p
         if (prof) hipEventRecord(next_event(P), b.stream);
         sweep_kernel_of_group(g)<<<b.sweep[g].grid, 256, 0, b.stream>>>(b.d_desc, b.sweep[g].map, s, p);
         if (prof) {

@@ -32,7 +32,7 @@ EXPORTED = [
     "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
     "pamc_anneal_batch", "pamc_server_create", "pamc_server_submit", "pamc_server_tick",
     "pamc_server_drain", "pamc_server_poll", "pamc_server_latency", "pamc_server_forget",
-    "pamc_server_destroy",
+    "pamc_server_destroy", "pamc_server_get_stats",
 ]
 
 
@@ -50,7 +50,8 @@ class pamc_config(C.Structure):
 class pamc_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("replicas", C.c_int32), ("num_classes", C.c_int32),
                 ("dense", C.c_int32), ("pull", C.c_int32), ("nnz", C.c_int64), ("W", C.c_int64), ("X", C.c_int64),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("tiles_per_wave", C.c_int32), ("quads_per_wave", C.c_int32),
+                ("coupling_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 class pamc_schedule(C.Structure):
@@ -69,6 +70,17 @@ class pamc_result(C.Structure):
                 ("n_cluster_moves", C.c_int32), ("n_reheats", C.c_int32),
                 ("n_reversals", C.c_int32), ("n_restarts", C.c_int32),
                 ("seconds_total", C.c_double), ("seconds_to_target", C.c_double)]
+
+
+class pamc_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("finished", C.c_int64), ("failed", C.c_int64), ("ticks", C.c_int64),
+                ("steps", C.c_int64), ("request_steps", C.c_int64), ("prep_seconds", C.c_double),
+                ("admit_seconds", C.c_double), ("step_seconds", C.c_double), ("peak_active", C.c_int64),
+                ("peak_bytes", C.c_int64), ("in_use_bytes", C.c_int64), ("active", C.c_int64),
+                ("queued", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def schedule(**kw) -> pamc_schedule:
@@ -120,6 +132,7 @@ def _load():
         "pamc_server_poll": [P, C.c_uint64, P, P, P],
         "pamc_server_latency": [P, C.c_uint64, P, P],
         "pamc_server_forget": [P, C.c_uint64],
+        "pamc_server_get_stats": [P, C.POINTER(pamc_server_stats)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -342,6 +355,12 @@ def pamc_server_forget(srv, ticket):
     _check(lib.pamc_server_forget(srv, int(ticket)))
 
 
+def pamc_server_get_stats(srv):
+    st = pamc_server_stats()
+    _check(lib.pamc_server_get_stats(srv, C.byref(st)))
+    return st.as_dict()
+
+
 def pamc_server_destroy(srv):
     lib.pamc_server_destroy(srv)
 
@@ -468,6 +487,9 @@ class Server:
 
     def forget(self, ticket):
         pamc_server_forget(self.h, ticket)
+
+    def stats(self):
+        return pamc_server_get_stats(self.h)
 
     def close(self):
         if self.h:

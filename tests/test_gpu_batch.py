@@ -173,3 +173,23 @@ def test_server_rejects_oversize(pamc):
     with pytest.raises(pamc.PamcError):
         srv.poll(12345)
     srv.close()
+
+
+def test_server_reports_bad_request(pamc):
+    """A request that fails host preparation finishes with its error and
+    does not disturb the others."""
+    g = synth.torus(8, 8, 1)
+    bad = synth.Graph(g.n, g.row_ptr, g.col, g.w.copy())
+    bad.w[0] = 5  # no longer symmetric
+    say("case server bad request")
+    srv = pamc.Server(1 << 30, 4, replicas=64)
+    t_bad = srv.submit(bad, 1, pamc.schedule(steps=3))
+    t_ok = srv.submit(g, 2, pamc.schedule(steps=3))
+    srv.drain()
+    with pytest.raises(pamc.PamcError):
+        srv.poll(t_bad)
+    r = srv.poll(t_ok)
+    assert r is not None and r.steps_run == 3
+    st = srv.stats()
+    assert st["failed"] == 1 and st["finished"] == 1 and st["submitted"] == 2
+    srv.close()

@@ -282,3 +282,56 @@ def test_c2_full_size_subset_parity_and_invariants(pamc, fields):
         assert np.array_equal(hr, h[r])
         assert E[r] == -(sr * hr).sum() // 2
     inst.close()
+
+
+def weighted_int8_graph(n, m, seed):
+    g = synth.random_graph(n, m, seed)
+    rng = np.random.default_rng(seed + 1)
+    # symmetric weights in [-127, 127] \ {0}: draw per undirected edge
+    w = np.zeros_like(g.w)
+    for v in range(n):
+        for e in range(g.row_ptr[v], g.row_ptr[v + 1]):
+            u = g.col[e]
+            if u > v:
+                x = int(rng.integers(1, 128)) * (1 if rng.integers(0, 2) else -1)
+                w[e] = x
+                f = g.row_ptr[u] + int(np.searchsorted(g.col[g.row_ptr[u]:g.row_ptr[u + 1]], v))
+                w[f] = x
+    return synth.Graph(g.n, g.row_ptr, g.col, w)
+
+
+@pytest.mark.parametrize("jmode", [0, 1, 2])
+@pytest.mark.parametrize("tpw", [1, 2, 4])
+@pytest.mark.parametrize("rule", [0, 1])
+def test_gathered_field_variants(pamc, monkeypatch, jmode, tpw, rule):
+    """Every gathered-field kernel variant (coupling mode x tiles per wave)
+    on int8 weights, where all three coupling modes apply."""
+    g = weighted_int8_graph(203, 1400, 17)
+    monkeypatch.setenv("PAMC_JMODE", str(jmode))
+    monkeypatch.setenv("PAMC_TPW", str(tpw))
+    say(f"case variant jmode={jmode} tpw={tpw} rule={rule}")
+    inst = pamc.Instance.csr(g, replicas=256, seed=77, rule=rule, fields="pull")
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 256, 77, rule=rule)
+    for beta, k in [(0.01, 1), (0.05, 2), (0.4, 1)]:
+        inst.sweep(beta, k)
+        o.sweep(beta, k)
+        same_state(inst, o, f"beta={beta}")
+    inst.close()
+
+
+@pytest.mark.parametrize("qpw", [1, 2, 4])
+@pytest.mark.parametrize("fields", FIELDS)
+def test_quads_per_wave(pamc, monkeypatch, qpw, fields):
+    """Work-group shapes with 1, 2 and 4 vertex quads per wavefront over
+    classes spanning many work-groups with a ragged last one (n = 1,599)."""
+    g = synth.random_graph(1599, 5000, 23, weights="pm1")
+    monkeypatch.setenv("PAMC_QPW", str(qpw))
+    say(f"case qpw={qpw} fields={fields}")
+    inst = pamc.Instance.csr(g, replicas=128, seed=31, fields=fields)
+    assert inst.info().quads_per_wave == qpw
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 128, 31)
+    for beta, k in [(0.1, 1), (0.7, 2)]:
+        inst.sweep(beta, k)
+        o.sweep(beta, k)
+        same_state(inst, o, f"beta={beta}")
+    inst.close()
