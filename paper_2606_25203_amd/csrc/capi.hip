@@ -930,13 +930,17 @@ pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_resul
   if (!I->d_sched) HIP_TRY(hipMalloc(&I->d_sched, sizeof(Schedule)), "alloc");
   HIP_TRY(hipMemcpyAsync(I->d_sched, &s, sizeof(Schedule), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::batch_anneal_setup(*b, (const Schedule*)I->d_sched, nullptr, 1), "anneal setup");
-  for (int32_t step = 0; step < s.steps; ++step) {
+  // steps in chunks of 16 between polls of the stop flag when stopping at
+  // the target, else all at once
+  const int32_t chunk = s.stop_at_target ? 16 : std::max(s.steps, 1);
+  for (int32_t done = 0; done < s.steps; done += chunk) {
+    const int32_t k = std::min(chunk, s.steps - done);
     if (I->dense) {
-      HIP_TRY(pamc::launch_dense_step(*b, s.sweeps, s.resample), "dense step");
+      for (int32_t i = 0; i < k; ++i) HIP_TRY(pamc::launch_dense_step(*b, s.sweeps, s.resample), "dense step");
     } else {
-      HIP_TRY(pamc::batch_step(*b), "step");
+      HIP_TRY(pamc::batch_run_steps(*b, k), "step");
     }
-    if (s.stop_at_target && (step % 16) == 15) {
+    if (s.stop_at_target && done + k < s.steps) {
       HIP_TRY(hipMemcpyAsync(I->pinned, &I->st->stopped, sizeof(int32_t), hipMemcpyDeviceToHost, I->stream), "poll");
       HIP_TRY(hipStreamSynchronize(I->stream), "poll");
       if (*(volatile int32_t*)I->pinned) break;
@@ -985,9 +989,10 @@ pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* 
   if (e == hipSuccess) e = hipMemcpyAsync(d_sched, s.data(), sizeof(Schedule) * count, hipMemcpyHostToDevice, b.stream);
   if (e == hipSuccess) e = pamc::batch_anneal_setup(b, d_sched, nullptr, count);
   std::vector<int32_t> status(count);
-  for (int32_t step = 0; step < max_steps && e == hipSuccess; ++step) {
-    e = pamc::batch_step(b);
-    if (e == hipSuccess && any_stop && (step % 16) == 15) {
+  const int32_t chunk = any_stop ? 16 : std::max(max_steps, 1);
+  for (int32_t done = 0; done < max_steps && e == hipSuccess; done += chunk) {
+    e = pamc::batch_run_steps(b, std::min(chunk, max_steps - done));
+    if (e == hipSuccess && any_stop && done + chunk < max_steps) {
       e = pamc::batch_status(b, d_status);
       if (e == hipSuccess) e = hipMemcpyAsync(status.data(), d_status, sizeof(int32_t) * count, hipMemcpyDeviceToHost, b.stream);
       if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
@@ -1473,7 +1478,7 @@ pamc_status pamc_server_tick(pamc_server* S, int32_t max_steps, int32_t* n_activ
     for (auto& a : S->active) k = std::min(k, std::max(a.s.steps - a.launched, 1));
     if (max_steps > 0) k = std::min(k, max_steps);
     const double t_step = now_seconds();
-    for (int32_t i = 0; i < k; ++i) HIP_TRY(pamc::batch_step(S->batch), "step");
+    HIP_TRY(pamc::batch_run_steps(S->batch, k), "step");
     for (auto& a : S->active) a.launched += k;
     HIP_TRY(pamc::batch_status(S->batch, S->d_status), "status");
     std::vector<int32_t> status(na);

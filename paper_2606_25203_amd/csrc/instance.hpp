@@ -169,6 +169,9 @@ struct Batch {
   int32_t max_ncls = 0, max_sweeps = 1, any_cluster = 0;
   int32_t group_ncls[kGroups] = {};  // most colour classes of an instance in each sweep group
   int64_t max_lds = 0;
+  hipGraphExec_t step_graph = nullptr;  // one captured beta step (batch_run_steps)
+  int64_t graph_key = -1;
+  bool graph_failed = false;
   void free_device();
   Batch() = default;
   Batch(const Batch&) = delete;
@@ -186,6 +189,7 @@ hipError_t batch_init(Batch& b);                               // sparse instanc
 // idx is null): instance idx[i] (or i) gets d_sched[i].
 hipError_t batch_anneal_setup(Batch& b, const Schedule* d_sched, const int32_t* d_idx, int32_t count);
 hipError_t batch_step(Batch& b);                               // one beta step of every live instance
+hipError_t batch_run_steps(Batch& b, int32_t k);               // k steps, replaying a captured step graph
 hipError_t batch_status(Batch& b, int32_t* d_out);             // (steps_run << 1) | stopped
 hipError_t prim_sweep(Batch& b, double beta, int32_t nsweeps);
 hipError_t prim_resample(Batch& b, double delta);

@@ -1221,7 +1221,9 @@ void Batch::free_device() {
     l.map = nullptr;
     l.grid = 0;
   }
-
+  if (step_graph) hipGraphExecDestroy(step_graph);
+  step_graph = nullptr;
+  graph_key = -1;
 }
 
 static int64_t sweep_chunks(const pamc_instance* I) {
@@ -1401,6 +1403,43 @@ hipError_t batch_step(Batch& b) {
   hipError_t e = batch_sweeps(b, b.max_sweeps);
   if (e != hipSuccess) return e;
   k_step_end<<<b.n, 1024, 0, b.stream>>>(b.d_desc, 1);
+  return hipGetLastError();
+}
+
+// k beta steps.  Without profiling, one step is captured once as a HIP graph
+// (kernels only: the launch sequence of a step is fixed and every decision
+// is read from device state) and replayed; if the stream cannot be captured
+// the steps are launched one by one.  PAMC_NO_GRAPH=1 forces the latter.
+hipError_t batch_run_steps(Batch& b, int32_t k) {
+  const char* ng = getenv("PAMC_NO_GRAPH");
+  const bool no_graph = ng && atoi(ng) != 0;
+  const int64_t key = ((int64_t)b.max_sweeps << 1) | (b.any_cluster ? 1 : 0);
+  bool use_graph = !no_graph && !b.I[0]->prof && !b.graph_failed && k > 1;
+  if (use_graph && (!b.step_graph || b.graph_key != key)) {
+    if (b.step_graph) hipGraphExecDestroy(b.step_graph);
+    b.step_graph = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t es = batch_step(b);
+      e = hipStreamEndCapture(b.stream, &g);
+      if (es != hipSuccess) e = es;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b.step_graph, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();  // clear the capture error; launch eagerly from now on
+      b.step_graph = nullptr;
+      b.graph_failed = true;
+      use_graph = false;
+    } else {
+      b.graph_key = key;
+    }
+  }
+  for (int32_t i = 0; i < k; ++i) {
+    const hipError_t e = use_graph ? hipGraphLaunch(b.step_graph, b.stream) : batch_step(b);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -193,3 +193,36 @@ def test_server_reports_bad_request(pamc):
     st = srv.stats()
     assert st["failed"] == 1 and st["finished"] == 1 and st["submitted"] == 2
     srv.close()
+
+
+def test_step_graph_replays_match_eager(pamc, monkeypatch):
+    """Captured beta steps replayed many times, with eager work and waits
+    between replays (stop-flag polls every 16 steps, state reads, a second
+    run on the same instance), against the same calls launched eagerly:
+    every step's trace entry and the final populations must agree."""
+    g = synth.torus(20, 20, 4)
+    kw = dict(beta0=0.1, dbeta=0.05, steps=70, sweeps=2, augmented=1, z_rst=50, n_top=4, mis_trials=2,
+              win_short=5, win_long=8, tau=3, target=10**9, stop_at_target=1)
+
+    def run():
+        inst = pamc.Instance.csr(g, replicas=128, seed=8)
+        r1 = inst.anneal(pamc.schedule(**kw))
+        t1 = inst.trace(kw["steps"])
+        s1 = inst.state()
+        r2 = inst.anneal(pamc.schedule(**dict(kw, beta0=0.3)))
+        t2 = inst.trace(kw["steps"])
+        s2 = inst.state()
+        inst.close()
+        return (r1, t1, s1), (r2, t2, s2)
+
+    say("case graph vs eager")
+    monkeypatch.setenv("PAMC_NO_GRAPH", "1")
+    eager = run()
+    monkeypatch.delenv("PAMC_NO_GRAPH")
+    graph = run()
+    for (re_, te, se), (rg, tg, sg) in zip(eager, graph):
+        same_result(rg, re_, "graph run")
+        for k in ("mstar", "beta", "lnq", "events"):
+            assert np.array_equal(tg[k], te[k]), f"trace {k}"
+        for a, b in zip(sg, se):
+            assert np.array_equal(a, b)
