@@ -2,15 +2,17 @@
 // Ising Problem"): int8 couplings J[n][n] in HBM, spins visited in the fixed
 // order 0..n-1.
 //
-// A sweep runs over blocks of kDB = 64 consecutive spins.  For block b the
-// local fields of Eq. 3 against the *current* spins, G = J[blk, :] . S, come
-// from int8 x int8 -> int32 matrix-core products (exact: |h| <= 127 n <
-// 2^31), split over the K (spin) dimension and summed atomically.  A sequential
-// kernel (one wavefront per 64 replicas) then visits the block's spins in
-// order: h_k = G_k + sum_{k' < k in block} J_kk' d_k', where
-// d_k' = 2 s_k'(new) if spin k' flipped and 0 otherwise (packed int8, summed
-// four at a time with dot4), applies the same threshold test as the sparse
-// path and updates spins and energies.
+// A sweep runs over super-blocks of kSB = 1024 consecutive spins.  For each,
+// one matrix-core launch computes the local fields of Eq. 3 of all its rows
+// against the spins as they stand, G = J[sb, :] . S (int8 x int8 -> int32,
+// exact since |h| <= 127 n < 2^31; split over the K dimension and summed
+// atomically).  A sequential launch (one work-group per 64 replicas) then
+// walks the super-block in blocks of kDB = 64 spins: the couplings to spins
+// already flipped in earlier blocks of the super-block are added with a
+// small matrix-core product over the recorded changes dS, and the block's
+// spins are decided in order with h_k = G_k + C_k + sum_{k' < k in block}
+// J_kk' d_k' (d = 2 s_new for flipped spins, packed int8, dot4), the same
+// threshold test as the sparse path.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -30,7 +32,8 @@ namespace pamc {
 namespace {
 
 constexpr int kDB = 64;          // spins per sequential block
-constexpr int kKSlice = 2048;    // K columns per partial-sum work-group
+constexpr int kSB = 1024;        // rows per super-block: one field product, one sequential launch
+constexpr int kKSlice = 4096;    // K columns per partial-sum work-group
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // J_ij = J_ji = +-1 from the low bit of Philox(key = seed; (i, j, 0, DENSE))
@@ -81,27 +84,32 @@ __global__ void __launch_bounds__(256) k_dense_init_spins(int8_t* S, int32_t* fa
   }
 }
 
-// G[m][r] += sum_{k in slice p} J[row0 + m][k] S[r][k] for the block's kDB
-// rows and a 64-replica tile (the K slices meet by atomic addition in G).
-// Work-group = 4 waves; wave w owns rows
-// 16w..16w+15 against the tile's 64 replicas (four 16 x 16 results) with
+// G[m][r] += sum_{k in slice p} J[row0 + m][k] S[r][k] for the super-block's
+// rows m < rows (a multiple of 64) and every replica r (the K slices meet by
+// atomic addition in G, which its reader clears).  Work-group = (64-replica
+// tile, 64-row block, K slice) with 4 waves; wave w owns rows 16w..16w+15
+// against the tile's 64 replicas (four 16 x 16 results) with
 // v_mfma_i32_16x16x64_i8.  Operand fragments: lane l supplies 16 consecutive
 // K bytes at 16*(l/16) of row (A) / replica (B) l % 16; the result holds rows
 // 4*(l/16)..+3 of column l % 16.
 __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J,
                                                     const int8_t* __restrict__ S0,
                                                     const int8_t* __restrict__ S1,
-                                                    int32_t* __restrict__ Gpart, const RunState* st,
-                                                    int32_t row0, int32_t np, int32_t R,
+                                                    int32_t* __restrict__ G, const RunState* st,
+                                                    int32_t row0, int32_t rows, int32_t np, int32_t R,
                                                     int32_t use_state) {
   if (use_state == 1 && !st->active) return;
   const int8_t* __restrict__ S = (use_state ? st->cur : 0) ? S1 : S0;
-  const int tile = blockIdx.x % (R / 64);
-  const int p = blockIdx.x / (R / 64);
+  const int T = R / 64, RB = rows / 64;
+  int g = blockIdx.x;
+  const int tile = g % T;
+  g /= T;
+  const int rb = g % RB;
+  const int p = g / RB;
   const int k_beg = p * kKSlice, k_end = min(np, k_beg + kKSlice);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int8_t* arow = J + (size_t)(row0 + 16 * wave + (lane & 15)) * np + 16 * (lane >> 4);
+  const int8_t* arow = J + (size_t)(row0 + 64 * rb + 16 * wave + (lane & 15)) * np + 16 * (lane >> 4);
   const int8_t* brow = S + (size_t)(tile * 64 + (lane & 15)) * np + 16 * (lane >> 4);
   v4i acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll 4
@@ -113,102 +121,132 @@ __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[nt], acc[nt], 0, 0, 0);
   }
-  // K-split partials meet in G[kDB][R] (zeroed by its reader)
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int32_t v = acc[nt][j];
       if (v != 0)
-        __hip_atomic_fetch_add(&Gpart[(size_t)(16 * wave + 4 * (lane >> 4) + j) * R + tile * 64 + nt * 16 + (lane & 15)],
-                               v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(
+            &G[(size_t)(64 * rb + 16 * wave + 4 * (lane >> 4) + j) * R + tile * 64 + nt * 16 + (lane & 15)], v,
+            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// Moves the block fields of one 64-replica tile from G[kDB][R] into LDS and
-// clears them in G for the next block's K-split accumulation.
-__device__ __forceinline__ void take_fields(int32_t* __restrict__ G, int32_t R, int tile,
-                                            int32_t (*g)[64]) {
-  for (int i = threadIdx.x; i < kDB * 64; i += blockDim.x) {
-    const int k = i >> 6, l = i & 63;
-    int32_t* src = G + (size_t)k * R + tile * 64 + l;
-    g[k][l] = *src;
-    *src = 0;
-  }
-}
-
-// Sequential visit of the block's spins for one 64-replica tile (one wave).
+// Sequential visit of one super-block's spins for one 64-replica tile.
 struct SeqArgs {
   const int8_t* J;
   int8_t* S0;
   int8_t* S1;
+  int8_t* dS;   // [R][np]: 2 s_new where a spin flipped in this super-block, else 0
   int64_t* E0;
   int64_t* E1;
-  int32_t* Gpart;
+  int32_t* G;   // [kSB][R] fields of the super-block rows against its starting spins
   const uint32_t* thr;
   RunState* st;
-  int32_t row0, n, np, R, P;
+  int32_t n, np, R;
   uint32_t k0, k1;
   int64_t* flip_ctr;
 };
 
+// One work-group per tile walks the super-block's 64-spin blocks in order.
+// For block b, the four waves first add to G the couplings to the spins that
+// flipped in the earlier blocks of the super-block, C = J[blk, row0 ..
+// row0 + 64b) . dS (matrix cores; dS read past the L1 with coherent buffer
+// loads, since this work-group wrote it), then wave 0 (lane = replica)
+// decides the block's spins in order with the in-block corrections
+// h_k = G_k + C_k + sum_{k' < k in block} J_kk' d_k' (d packed int8, dot4),
+// and records d in dS.
 template <int RULE>
-__global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx) {
-  __shared__ uint32_t jd[kDB][kDB / 4];  // J[row0 + k][row0 + 4g .. 4g+3], packed int8
-  __shared__ int32_t gsum[kDB][64];      // block fields of this tile before the block's flips
+__global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
+  __shared__ uint32_t jd[kDB][kDB / 4];  // J[rb0 + k][rb0 + 4g .. 4g+3], packed int8
+  __shared__ int32_t gsum[kDB][64];      // fields of this tile before the block's own flips
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
   int8_t* S = cur ? a.S1 : a.S0;
   int64_t* E = cur ? a.E1 : a.E0;
   const int tile = blockIdx.x;
-  for (int i = threadIdx.x; i < kDB * kDB / 4; i += blockDim.x) {
-    const int k = i / (kDB / 4), g = i % (kDB / 4);
-    jd[k][g] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(a.row0 + k) * a.np + a.row0 + 4 * g);
-  }
-  take_fields(a.Gpart, a.R, tile, gsum);
-  __syncthreads();
-  if (threadIdx.x >= 64) return;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = tile * 64 + lane;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
   const int32_t Xt = (int32_t)st->table_x;
-  uint32_t d[kDB / 4];  // packed int8 d_k' of this lane's replica
-#pragma unroll
-  for (int g = 0; g < kDB / 4; ++g) d[g] = 0;
-  uint32_t* srow = reinterpret_cast<uint32_t*>(S + (size_t)r * a.np + a.row0);
+  const __amdgpu_buffer_rsrc_t dsr =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(a.dS + (size_t)tile * 64 * a.np), (short)0, 64 * a.np, 0x00020000);
   int64_t dE = 0;
   int32_t nflip = 0;
+  for (int b = 0; b * kDB < rows; ++b) {
+    const int rb0 = row0 + b * kDB;
+    if (rb0 >= a.n) break;
+    // corrections from the earlier blocks of the super-block
+    v4i acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    const int8_t* arow = a.J + (size_t)(rb0 + 16 * wave + (lane & 15)) * a.np + row0 + 16 * (lane >> 4);
+    const int boff = (lane & 15) * a.np + row0 + 16 * (lane >> 4);
+    for (int k0 = 0; k0 < b * kDB; k0 += 64) {
+      const v4i av = *reinterpret_cast<const v4i*>(arow + k0);
+      v4i bv[4];
 #pragma unroll
-  for (int g = 0; g < kDB / 4; ++g) {
-    const int vq = a.row0 + 4 * g;
-    if (vq >= a.n) break;
-    const u32x4 rnd = philox10((uint32_t)(vq >> 2), gs, (uint32_t)r, kTagSweep, a.k0, a.k1);
-    uint32_t sw = srow[g];
-    uint32_t dg = 0;
+      for (int nt = 0; nt < 4; ++nt)
+        bv[nt] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(dsr, boff + nt * 16 * a.np + k0, 0, 1));
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * g + kk;
-      const int v = a.row0 + k;
-      if (v >= a.n) break;
-      int32_t h = gsum[k][lane];
-#pragma unroll
-      for (int g2 = 0; g2 < g; ++g2) h = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)d[g2], h, false);
-      h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, h, false);
-      const int32_t s = (int32_t)(int8_t)(sw >> (8 * kk));
-      const int32_t x = s * h;
-      const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
-      const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, kk) < a.thr[xi + Xt]);
-      if (flip) {
-        dE += 2 * (int64_t)x;
-        sw ^= (0xFEu << (8 * kk));
-        dg |= (uint32_t)(uint8_t)(int8_t)(-2 * s) << (8 * kk);
-        ++nflip;
-      }
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv[nt], acc[nt], 0, 0, 0);
     }
-    d[g] = dg;
-    srow[g] = sw;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = 16 * wave + 4 * (lane >> 4) + j, c = nt * 16 + (lane & 15);
+        int32_t* gp = a.G + (size_t)(b * kDB + m) * a.R + tile * 64 + c;
+        gsum[m][c] = acc[nt][j] + *gp;
+        *gp = 0;  // cleared for the next super-block's accumulation
+      }
+    for (int i = threadIdx.x; i < kDB * kDB / 4; i += blockDim.x) {
+      const int k = i / (kDB / 4), g = i % (kDB / 4);
+      jd[k][g] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 4 * g);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      uint32_t d[kDB / 4];  // packed int8 d_k' of this lane's replica
+#pragma unroll
+      for (int g = 0; g < kDB / 4; ++g) d[g] = 0;
+      uint32_t* srow = reinterpret_cast<uint32_t*>(S + (size_t)r * a.np + rb0);
+#pragma unroll
+      for (int g = 0; g < kDB / 4; ++g) {
+        const int vq = rb0 + 4 * g;
+        if (vq >= a.n) break;
+        const u32x4 rnd = philox10((uint32_t)(vq >> 2), gs, (uint32_t)r, kTagSweep, a.k0, a.k1);
+        uint32_t sw = srow[g];
+        uint32_t dg = 0;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * g + kk;
+          if (rb0 + k >= a.n) break;
+          int32_t h = gsum[k][lane];
+#pragma unroll
+          for (int g2 = 0; g2 < g; ++g2) h = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)d[g2], h, false);
+          h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, h, false);
+          const int32_t s = (int32_t)(int8_t)(sw >> (8 * kk));
+          const int32_t x = s * h;
+          const int32_t xi = min(max(x, -Xt), Xt);
+          const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, kk) < a.thr[xi + Xt]);
+          if (flip) {
+            dE += 2 * (int64_t)x;
+            sw ^= (0xFEu << (8 * kk));
+            dg |= (uint32_t)(uint8_t)(int8_t)(-2 * s) << (8 * kk);
+            ++nflip;
+          }
+        }
+        d[g] = dg;
+        srow[g] = sw;
+      }
+      uint32_t* drow = reinterpret_cast<uint32_t*>(a.dS + (size_t)r * a.np + rb0);
+#pragma unroll
+      for (int g = 0; g < kDB / 4; ++g) drow[g] = d[g];
+    }
+    __syncthreads();  // dS of this block is read by the next block's corrections
   }
+  if (wave != 0) return;
   if (dE != 0)
     __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)dE, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -221,20 +259,20 @@ __global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx)
   }
 }
 
-// Energy of the population from block fields: E_r += sum_k s_rk G_rk (the
-// caller negates and halves at the end).
-__global__ void __launch_bounds__(256) k_dense_energy_block(const int8_t* S, int32_t* Gpart,
-                                                            int64_t* E, int32_t row0, int32_t n,
-                                                            int32_t np, int32_t R, int32_t P) {
-  __shared__ int32_t gsum[kDB][64];
-  const int tile = blockIdx.x;
-  take_fields(Gpart, R, tile, gsum);
-  __syncthreads();
-  if (threadIdx.x >= 64) return;
+// Energy of the population from super-block fields: E_r += sum_k s_rk G_kr
+// (the caller negates and halves at the end); clears G.  Work-group =
+// (tile, 64-row block), wave 0 lanes = replicas.
+__global__ void __launch_bounds__(64) k_dense_energy_sb(const int8_t* S, int32_t* G, int64_t* E, int32_t row0,
+                                                        int32_t rows, int32_t n, int32_t np, int32_t R) {
+  const int T = R / 64;
+  const int tile = blockIdx.x % T, rb = blockIdx.x / T;
   const int r = tile * 64 + threadIdx.x;
   int64_t acc = 0;
-  for (int k = 0; k < kDB && row0 + k < n; ++k)
-    acc += (int64_t)gsum[k][threadIdx.x] * S[(size_t)r * np + row0 + k];
+  for (int k = 64 * rb; k < 64 * rb + 64 && row0 + k < n; ++k) {
+    int32_t* gp = G + (size_t)k * R + r;
+    acc += (int64_t)*gp * S[(size_t)r * np + row0 + k];
+    *gp = 0;
+  }
   if (acc)
     __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)acc, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -275,16 +313,15 @@ __global__ void __launch_bounds__(256) k_dense_gather(const RunState* st, int8_t
 
 int32_t num_partials(int32_t np) { return (np + kKSlice - 1) / kKSlice; }
 
-// H[r][row0 + k] = sum of the block's partial fields (snapshots only).
-__global__ void __launch_bounds__(256) k_dense_collect(int32_t* Gpart, int32_t* H, int32_t row0,
-                                                       int32_t n, int32_t np, int32_t R, int32_t P) {
-  __shared__ int32_t gsum[kDB][64];
-  const int tile = blockIdx.x;
-  take_fields(Gpart, R, tile, gsum);
-  __syncthreads();
-  if (threadIdx.x >= 64) return;
-  const int r = tile * 64 + threadIdx.x;
-  for (int k = 0; k < kDB && row0 + k < n; ++k) H[(size_t)r * np + row0 + k] = gsum[k][threadIdx.x];
+// H[r][row0 + k] = G[k][r] for the super-block's rows (snapshots); clears G.
+__global__ void __launch_bounds__(256) k_dense_collect_sb(int32_t* G, int32_t* H, int32_t row0, int32_t rows,
+                                                          int32_t n, int32_t np, int32_t R) {
+  const int64_t total = (int64_t)rows * R;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / R), r = (int)(i % R);
+    if (row0 + k < n) H[(size_t)r * np + row0 + k] = G[i];
+    G[i] = 0;
+  }
 }
 
 }  // namespace
@@ -307,15 +344,22 @@ hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed) {
   return hipGetLastError();
 }
 
+// rows of the super-block starting at row0 (a multiple of 64)
+static inline int sb_rows(const pamc_instance* I, int row0) { return std::min(kSB, I->dn_pad - row0); }
+
+static inline int gemm_grid(const pamc_instance* I, int rows) {
+  return (I->R / 64) * (rows / 64) * num_partials(I->dn_pad);
+}
+
 static hipError_t dense_full_energy(pamc_instance* I, int buf) {
-  const int P = num_partials(I->dn_pad);
   const int T = I->R / 64;
   hipMemsetAsync(I->pop.E[buf], 0, sizeof(int64_t) * I->R, I->stream);
-  for (int row0 = 0; row0 < I->n; row0 += kDB) {
-    k_dense_gemm<<<T * P, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, I->dn_pad,
-                                               I->R, 0);
-    k_dense_energy_block<<<T, 256, 0, I->stream>>>(buf ? I->Sd2 : I->Sd, I->Gd, I->pop.E[buf], row0,
-                                                  I->n, I->dn_pad, I->R, P);
+  for (int row0 = 0; row0 < I->n; row0 += kSB) {
+    const int rows = sb_rows(I, row0);
+    k_dense_gemm<<<gemm_grid(I, rows), 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows,
+                                                            I->dn_pad, I->R, 0);
+    k_dense_energy_sb<<<T * (rows / 64), 64, 0, I->stream>>>(buf ? I->Sd2 : I->Sd, I->Gd, I->pop.E[buf], row0,
+                                                             rows, I->n, I->dn_pad, I->R);
   }
   return hipGetLastError();
 }
@@ -333,44 +377,43 @@ hipError_t launch_init_dense(pamc_instance* I) {
 
 static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
   pamc_instance* I = b.I[0];
-  const int P = num_partials(I->dn_pad);
   const int T = I->R / 64;
   SeqArgs a;
   a.J = I->Jd;
   a.S0 = I->Sd;
   a.S1 = I->Sd2;
+  a.dS = I->Dd;
   a.E0 = I->pop.E[0];
   a.E1 = I->pop.E[1];
-  a.Gpart = I->Gd;
+  a.G = I->Gd;
   a.thr = I->thr;
   a.st = I->st;
   a.n = I->n;
   a.np = I->dn_pad;
   a.R = I->R;
-  a.P = P;
   a.k0 = key0(I);
   a.k1 = key1(I);
   a.flip_ctr = I->prof ? I->flip_ctr : nullptr;
   ctl_thresholds(b);
   for (int s = 0; s < nsweeps; ++s) {
-    for (int row0 = 0; row0 < I->n; row0 += kDB) {
+    for (int row0 = 0; row0 < I->n; row0 += kSB) {
+      const int rows = sb_rows(I, row0);
       hipEvent_t e0 = nullptr;
       if (I->prof) {
         e0 = ctl_event(I);
         hipEventRecord(e0, I->stream);
       }
-      k_dense_gemm<<<T * P, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, I->dn_pad,
-                                                 I->R, 1);
+      k_dense_gemm<<<gemm_grid(I, rows), 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows,
+                                                              I->dn_pad, I->R, 1);
       if (I->prof) {
         hipEvent_t e1 = ctl_event(I);
         hipEventRecord(e1, I->stream);
         I->prof_launches += 1;
       }
-      a.row0 = row0;
       if (I->rule == 1)
-        k_dense_seq<1><<<T, 256, 0, I->stream>>>(a, s);
+        k_dense_seq<1><<<T, 256, 0, I->stream>>>(a, s, row0, rows);
       else
-        k_dense_seq<0><<<T, 256, 0, I->stream>>>(a, s);
+        k_dense_seq<0><<<T, 256, 0, I->stream>>>(a, s, row0, rows);
     }
     if (I->prof) I->prof_attempts += (int64_t)I->n * I->R;
   }
@@ -423,14 +466,16 @@ hipError_t launch_dense_prim_update_best(Batch& b) {
 
 hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor) {
   // fields H[r][v] (replica-major) of the current population, for snapshots
-  const int P = num_partials(I->dn_pad);
-  const int T = I->R / 64;
-  for (int row0 = 0; row0 < I->n; row0 += kDB) {
-    k_dense_gemm<<<T * P, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, I->dn_pad,
-                                               I->R, 2);
-    k_dense_collect<<<T, 256, 0, I->stream>>>(I->Gd, H_rmajor, row0, I->n, I->dn_pad, I->R, P);
+  for (int row0 = 0; row0 < I->n; row0 += kSB) {
+    const int rows = sb_rows(I, row0);
+    k_dense_gemm<<<gemm_grid(I, rows), 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows,
+                                                            I->dn_pad, I->R, 2);
+    k_dense_collect_sb<<<std::min(1024, (rows * I->R + 255) / 256), 256, 0, I->stream>>>(
+        I->Gd, H_rmajor, row0, rows, I->n, I->dn_pad, I->R);
   }
   return hipGetLastError();
 }
+
+int32_t dense_superblock_rows() { return kSB; }
 
 }  // namespace pamc

@@ -90,7 +90,8 @@ struct pamc_instance {
   int32_t dn_pad = 0;    // padded dimension of the dense matrix
   int8_t* Sd = nullptr;  // [R][dn_pad] replica-major spins (dense)
   int8_t* Sd2 = nullptr; // resampling buffer
-  int32_t* Gd = nullptr; // block field scratch
+  int32_t* Gd = nullptr; // super-block field scratch [rows][R]
+  int8_t* Dd = nullptr;  // [R][dn_pad] 2 s_new of spins flipped in the current super-block
   int64_t* Ed[2] = {nullptr, nullptr};
   // profiling
   bool prof = false;
@@ -215,6 +216,7 @@ hipEvent_t ctl_event(pamc_instance* I);
 
 // dense path launchers (dense.hip); b is the instance's batch of one
 int32_t dense_num_partials(int32_t np);
+int32_t dense_superblock_rows();
 hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor);
 hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed);
 hipError_t launch_init_dense(pamc_instance* I);
