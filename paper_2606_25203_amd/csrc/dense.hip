@@ -32,8 +32,10 @@ namespace pamc {
 namespace {
 
 constexpr int kDB = 64;          // spins per sequential block
-constexpr int kSB = 1024;        // rows per super-block: one field product, one sequential launch
-constexpr int kKSlice = 4096;    // K columns per partial-sum work-group
+constexpr int kSB = 2048;        // rows per super-block: one field product, one sequential launch
+constexpr int kGM = 128, kGN = 128, kGK = 64;  // field-product tile: rows x replicas x K stage
+constexpr int kLdsRow = kGK + 16;              // bytes per staged row (padded)
+constexpr int kThrL = 4095;      // half-width of the LDS copy of the threshold table
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // J_ij = J_ji = +-1 from the low bit of Philox(key = seed; (i, j, 0, DENSE))
@@ -85,52 +87,108 @@ __global__ void __launch_bounds__(256) k_dense_init_spins(int8_t* S, int32_t* fa
 }
 
 // G[m][r] += sum_{k in slice p} J[row0 + m][k] S[r][k] for the super-block's
-// rows m < rows (a multiple of 64) and every replica r (the K slices meet by
-// atomic addition in G, which its reader clears).  Work-group = (64-replica
-// tile, 64-row block, K slice) with 4 waves; wave w owns rows 16w..16w+15
-// against the tile's 64 replicas (four 16 x 16 results) with
-// v_mfma_i32_16x16x64_i8.  Operand fragments: lane l supplies 16 consecutive
-// K bytes at 16*(l/16) of row (A) / replica (B) l % 16; the result holds rows
-// 4*(l/16)..+3 of column l % 16.
+// rows m < rows and every replica r (the K slices meet by atomic addition in
+// G, which its reader clears).  Work-group = (128-row tile, 128-replica
+// tile, K slice); each 64-column K stage of both operands is staged through
+// LDS (double-buffered, rows padded by 16 bytes against bank conflicts) and
+// the four waves (2 x 2) each compute a 64 x 64 block as 4 x 4
+// v_mfma_i32_16x16x64_i8 tiles.  Operand fragments: lane l supplies 16
+// consecutive K bytes at 16*(l/16) of row (A) / replica (B) l % 16; the
+// result holds rows 4*(l/16)..+3 of column l % 16.
 __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J,
                                                     const int8_t* __restrict__ S0,
                                                     const int8_t* __restrict__ S1,
                                                     int32_t* __restrict__ G, const RunState* st,
                                                     int32_t row0, int32_t rows, int32_t np, int32_t R,
-                                                    int32_t use_state) {
+                                                    int32_t use_state, int32_t kslice) {
+  __shared__ __attribute__((aligned(16))) int8_t As[2][kGM * kLdsRow];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[2][kGN * kLdsRow];
   if (use_state == 1 && !st->active) return;
   const int8_t* __restrict__ S = (use_state ? st->cur : 0) ? S1 : S0;
-  const int T = R / 64, RB = rows / 64;
+  const int MT = (rows + kGM - 1) / kGM, NT = (R + kGN - 1) / kGN;
   int g = blockIdx.x;
-  const int tile = g % T;
-  g /= T;
-  const int rb = g % RB;
-  const int p = g / RB;
-  const int k_beg = p * kKSlice, k_end = min(np, k_beg + kKSlice);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int8_t* arow = J + (size_t)(row0 + 64 * rb + 16 * wave + (lane & 15)) * np + 16 * (lane >> 4);
-  const int8_t* brow = S + (size_t)(tile * 64 + (lane & 15)) * np + 16 * (lane >> 4);
-  v4i acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-#pragma unroll 4
-  for (int k0 = k_beg; k0 < k_end; k0 += 64) {
-    const v4i a = *reinterpret_cast<const v4i*>(arow + k0);
-    v4i b[4];
+  const int mt = g % MT;
+  g /= MT;
+  const int ntile = g % NT;
+  const int p = g / NT;
+  const int k_beg = p * kslice, k_end = min(np, k_beg + kslice);
+  if (k_beg >= k_end) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wm = wave & 1, wn = wave >> 1;
+  // staging: 512 chunks of 16 bytes per operand tile, chunks t and t + 256
+  // per thread; chunk c = (row c / 4, bytes 16 (c % 4) ..).  Rows past the
+  // super-block or replicas past R re-read the last valid one; their results
+  // are dropped below.
+  const v4i zero = {0, 0, 0, 0};
+  const int8_t* ag[2];
+  const int8_t* bg[2];
+  int lofs[2];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) b[nt] = *reinterpret_cast<const v4i*>(brow + (size_t)nt * 16 * np + k0);
+  for (int i = 0; i < 2; ++i) {
+    const int c = t + 256 * i, row = c >> 2, col = (c & 3) * 16;
+    const int m = min(mt * kGM + row, rows - 1), n = min(ntile * kGN + row, R - 1);
+    ag[i] = J + (size_t)(row0 + m) * np + col;
+    bg[i] = S + (size_t)n * np + col;
+    lofs[i] = row * kLdsRow + col;
+  }
+  v4i ra[2], rb[2];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[nt], acc[nt], 0, 0, 0);
+  for (int i = 0; i < 2; ++i) {
+    ra[i] = *reinterpret_cast<const v4i*>(ag[i] + k_beg);
+    rb[i] = *reinterpret_cast<const v4i*>(bg[i] + k_beg);
+    *reinterpret_cast<v4i*>(As[0] + lofs[i]) = ra[i];
+    *reinterpret_cast<v4i*>(Bs[0] + lofs[i]) = rb[i];
+  }
+  __syncthreads();
+  v4i acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = zero;
+  const int frag = (lane & 15) * kLdsRow + 16 * (lane >> 4);
+  int buf = 0;
+  for (int k0 = k_beg; k0 < k_end; k0 += kGK) {
+    const bool more = k0 + kGK < k_end;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ra[i] = *reinterpret_cast<const v4i*>(ag[i] + k0 + kGK);
+        rb[i] = *reinterpret_cast<const v4i*>(bg[i] + k0 + kGK);
+      }
+    }
+    v4i af[4], bf[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      af[i] = *reinterpret_cast<const v4i*>(As[buf] + (wm * 64 + 16 * i) * kLdsRow + frag);
+      bf[i] = *reinterpret_cast<const v4i*>(Bs[buf] + (wn * 64 + 16 * i) * kLdsRow + frag);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[i][j], 0, 0, 0);
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        *reinterpret_cast<v4i*>(As[buf ^ 1] + lofs[i]) = ra[i];
+        *reinterpret_cast<v4i*>(Bs[buf ^ 1] + lofs[i]) = rb[i];
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int32_t v = acc[nt][j];
-      if (v != 0)
-        __hip_atomic_fetch_add(
-            &G[(size_t)(64 * rb + 16 * wave + 4 * (lane >> 4) + j) * R + tile * 64 + nt * 16 + (lane & 15)], v,
-            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = mt * kGM + wm * 64 + 16 * i + 4 * (lane >> 4) + e;
+        const int n = ntile * kGN + wn * 64 + 16 * j + (lane & 15);
+        const int32_t v = acc[i][j][e];
+        if (v != 0 && m < rows && n < R)
+          __hip_atomic_fetch_add(&G[(size_t)m * R + n], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
 }
 
 // Sequential visit of one super-block's spins for one 64-replica tile.
@@ -161,6 +219,7 @@ template <int RULE>
 __global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
   __shared__ uint32_t jd[kDB][kDB / 4];  // J[rb0 + k][rb0 + 4g .. 4g+3], packed int8
   __shared__ int32_t gsum[kDB][64];      // fields of this tile before the block's own flips
+  __shared__ uint32_t thr_s[2 * kThrL + 1];  // thresholds for |x| <= Xl
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
@@ -172,6 +231,11 @@ __global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx,
   const int r = tile * 64 + lane;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
   const int32_t Xt = (int32_t)st->table_x;
+  // The decision chain waits for every threshold read, so the central part
+  // of the table lives in LDS; |x| > Xl (beyond about 13 standard deviations
+  // of the field at n = 100,000) reads global memory.
+  const int32_t Xl = min(Xt, kThrL);
+  for (int i = threadIdx.x; i <= 2 * Xl; i += blockDim.x) thr_s[i] = a.thr[Xt - Xl + i];
   const __amdgpu_buffer_rsrc_t dsr =
       __builtin_amdgcn_make_buffer_rsrc((void*)(a.dS + (size_t)tile * 64 * a.np), (short)0, 64 * a.np, 0x00020000);
   int64_t dE = 0;
@@ -228,8 +292,10 @@ __global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx,
           h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, h, false);
           const int32_t s = (int32_t)(int8_t)(sw >> (8 * kk));
           const int32_t x = s * h;
-          const int32_t xi = min(max(x, -Xt), Xt);
-          const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, kk) < a.thr[xi + Xt]);
+          const int32_t xl = min(max(x, -Xl), Xl);
+          uint32_t T = thr_s[xl + Xl];
+          if (x != xl && Xl < Xt) T = a.thr[min(max(x, -Xt), Xt) + Xt];
+          const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, kk) < T);
           if (flip) {
             dE += 2 * (int64_t)x;
             sw ^= (0xFEu << (8 * kk));
@@ -311,7 +377,7 @@ __global__ void __launch_bounds__(256) k_dense_gather(const RunState* st, int8_t
   }
 }
 
-int32_t num_partials(int32_t np) { return (np + kKSlice - 1) / kKSlice; }
+
 
 // H[r][row0 + k] = G[k][r] for the super-block's rows (snapshots); clears G.
 __global__ void __launch_bounds__(256) k_dense_collect_sb(int32_t* G, int32_t* H, int32_t row0, int32_t rows,
@@ -326,7 +392,6 @@ __global__ void __launch_bounds__(256) k_dense_collect_sb(int32_t* G, int32_t* H
 
 }  // namespace
 
-int32_t dense_num_partials(int32_t np) { return num_partials(np); }
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -347,8 +412,17 @@ hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed) {
 // rows of the super-block starting at row0 (a multiple of 64)
 static inline int sb_rows(const pamc_instance* I, int row0) { return std::min(kSB, I->dn_pad - row0); }
 
-static inline int gemm_grid(const pamc_instance* I, int rows) {
-  return (I->R / 64) * (rows / 64) * num_partials(I->dn_pad);
+// K slices of the field product: enough work-groups for two per compute
+// unit, each slice a multiple of the 64-column stage.
+struct GemmShape {
+  int grid, kslice;
+};
+static inline GemmShape gemm_shape(const pamc_instance* I, int rows) {
+  const int tiles = ((rows + kGM - 1) / kGM) * ((I->R + kGN - 1) / kGN);
+  const int stages = I->dn_pad / kGK;
+  const int P = std::max(1, std::min(stages, (512 + tiles - 1) / tiles));
+  const int kslice = ((stages + P - 1) / P) * kGK;
+  return {tiles * ((I->dn_pad + kslice - 1) / kslice), kslice};
 }
 
 static hipError_t dense_full_energy(pamc_instance* I, int buf) {
@@ -356,8 +430,9 @@ static hipError_t dense_full_energy(pamc_instance* I, int buf) {
   hipMemsetAsync(I->pop.E[buf], 0, sizeof(int64_t) * I->R, I->stream);
   for (int row0 = 0; row0 < I->n; row0 += kSB) {
     const int rows = sb_rows(I, row0);
-    k_dense_gemm<<<gemm_grid(I, rows), 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows,
-                                                            I->dn_pad, I->R, 0);
+    const GemmShape gsh = gemm_shape(I, rows);
+    k_dense_gemm<<<gsh.grid, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows, I->dn_pad, I->R,
+                                                  0, gsh.kslice);
     k_dense_energy_sb<<<T * (rows / 64), 64, 0, I->stream>>>(buf ? I->Sd2 : I->Sd, I->Gd, I->pop.E[buf], row0,
                                                              rows, I->n, I->dn_pad, I->R);
   }
@@ -403,8 +478,9 @@ static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
         e0 = ctl_event(I);
         hipEventRecord(e0, I->stream);
       }
-      k_dense_gemm<<<gemm_grid(I, rows), 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows,
-                                                              I->dn_pad, I->R, 1);
+      const GemmShape gsh = gemm_shape(I, rows);
+      k_dense_gemm<<<gsh.grid, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows, I->dn_pad,
+                                                    I->R, 1, gsh.kslice);
       if (I->prof) {
         hipEvent_t e1 = ctl_event(I);
         hipEventRecord(e1, I->stream);
@@ -468,8 +544,9 @@ hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor) {
   // fields H[r][v] (replica-major) of the current population, for snapshots
   for (int row0 = 0; row0 < I->n; row0 += kSB) {
     const int rows = sb_rows(I, row0);
-    k_dense_gemm<<<gemm_grid(I, rows), 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows,
-                                                            I->dn_pad, I->R, 2);
+    const GemmShape gsh = gemm_shape(I, rows);
+    k_dense_gemm<<<gsh.grid, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows, I->dn_pad, I->R,
+                                                  2, gsh.kslice);
     k_dense_collect_sb<<<std::min(1024, (rows * I->R + 255) / 256), 256, 0, I->stream>>>(
         I->Gd, H_rmajor, row0, rows, I->n, I->dn_pad, I->R);
   }

@@ -215,7 +215,6 @@ hipError_t ctl_deactivate(Batch& b);
 hipEvent_t ctl_event(pamc_instance* I);
 
 // dense path launchers (dense.hip); b is the instance's batch of one
-int32_t dense_num_partials(int32_t np);
 int32_t dense_superblock_rows();
 hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor);
 hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed);
