@@ -61,7 +61,7 @@ void free_instance(pamc_instance* I) {
   delete I->self;
   I->self = nullptr;
   if (I->d_sched) hipFree(I->d_sched);
-  void* ptrs[] = {I->g.row_ptr, I->g.col, I->g.J, I->g.Jp, I->g.class_ptr, I->pop.S[0], I->pop.S[1],
+  void* ptrs[] = {I->g.row_ptr, I->g.col, I->g.J, I->g.grow, I->g.gcol, I->g.gJ, I->g.class_ptr, I->pop.S[0], I->pop.S[1],
                   I->pop.H[0], I->pop.H[1], I->pop.E[0], I->pop.E[1], I->pop.fam[0],
                   I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order, I->rs_P,
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
@@ -172,7 +172,7 @@ struct HostSparse {
   int32_t n = 0, np = 0, nq = 0, ncls = 0, max_class_quads = 0;
   int32_t small_j = 0, jmode = 0, pull = 0, tpw = 1, qpw = 1;
   int64_t nnz = 0, W = 0, X = 0;
-  std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, Jp2;
+  std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, grow, gcol, gJ;
 };
 
 pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const int32_t* col,
@@ -249,11 +249,6 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
     const int m = atoi(e);
     if (m == 0 || (m == 1 && h.small_j) || (m == 2 && h.jmode == 2)) h.jmode = m;
   }
-  if (h.jmode == 2) {
-    h.Jp2.assign(nnzp, 0);
-    for (int64_t e = 0; e < h.nnz; ++e)
-      h.Jp2[e] = (int32_t)((uint32_t)(uint8_t)(int8_t)h.J2[e] << (8 * (h.col2[e] & 3)));
-  }
   // Field storage: kept incrementally (push) or gathered at visit time
   // (pull); both give the same integer fields and the same trajectory.
   // Gathering a hub's field serialises one wavefront per tile over all of
@@ -264,6 +259,23 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
     h.pull = 1;
   else
     h.pull = (h.nnz <= 16 * (int64_t)n && maxdeg <= 64) ? 1 : 0;
+  // Gathered-field CSR: rows padded to multiples of 4 entries; columns as
+  // byte offsets of the neighbour's spin word in a tile (plus its byte index
+  // in modes 0 and 1), couplings in the kernel's mode (mode 2: the int8
+  // coupling in the neighbour's byte).
+  if (h.pull) {
+    h.grow.assign(n + 1, 0);
+    for (int32_t iv = 0; iv < n; ++iv) h.grow[iv + 1] = h.grow[iv] + ((h.rp2[iv + 1] - h.rp2[iv] + 3) & ~3);
+    h.gcol.assign(std::max(h.grow[n], 4), 0);
+    h.gJ.assign(std::max(h.grow[n], 4), 0);
+    for (int32_t iv = 0; iv < n; ++iv) {
+      int32_t p = h.grow[iv];
+      for (int32_t e = h.rp2[iv]; e < h.rp2[iv + 1]; ++e, ++p) {
+        h.gcol[p] = (h.col2[e] >> 2) * 256 + (h.jmode == 2 ? 0 : (h.col2[e] & 3));
+        h.gJ[p] = h.jmode == 2 ? (int32_t)((uint32_t)(uint8_t)(int8_t)h.J2[e] << (8 * (h.col2[e] & 3))) : h.J2[e];
+      }
+    }
+  }
   // Tiles per wavefront: share the per-vertex scalar work among up to 4
   // tiles while keeping enough work-groups (one quad per wave) to fill the
   // chip.  Then quads per wave: the most (fewer partial energy sums) that
@@ -318,7 +330,11 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(dalloc(I, &I->g.row_ptr, n + 1), "alloc");
   HIP_TRY(dalloc(I, &I->g.col, nnz), "alloc");
   HIP_TRY(dalloc(I, &I->g.J, nnz), "alloc");
-  if (I->jmode == 2) HIP_TRY(dalloc(I, &I->g.Jp, nnz), "alloc");
+  if (I->pull) {
+    HIP_TRY(dalloc(I, &I->g.grow, n + 1), "alloc");
+    HIP_TRY(dalloc(I, &I->g.gcol, h.gcol.size()), "alloc");
+    HIP_TRY(dalloc(I, &I->g.gJ, h.gJ.size()), "alloc");
+  }
   HIP_TRY(dalloc(I, &I->g.class_ptr, ncls + 1), "alloc");
   for (int b = 0; b < 2; ++b) {
     HIP_TRY(dalloc(I, &I->pop.S[b], words), "alloc population");
@@ -344,8 +360,11 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(hipMemcpyAsync(I->g.row_ptr, h.rp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->g.col, h.col2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->g.J, h.J2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
-  if (I->g.Jp)
-    HIP_TRY(hipMemcpyAsync(I->g.Jp, h.Jp2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
+  if (I->pull) {
+    HIP_TRY(hipMemcpyAsync(I->g.grow, h.grow.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, I->stream), "upload");
+    HIP_TRY(hipMemcpyAsync(I->g.gcol, h.gcol.data(), sizeof(int32_t) * h.gcol.size(), hipMemcpyHostToDevice, I->stream), "upload");
+    HIP_TRY(hipMemcpyAsync(I->g.gJ, h.gJ.data(), sizeof(int32_t) * h.gJ.size(), hipMemcpyHostToDevice, I->stream), "upload");
+  }
   HIP_TRY(hipMemcpyAsync(I->g.class_ptr, I->class_ptr.data(), sizeof(int32_t) * (ncls + 1), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->to_internal_dev, I->to_internal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::prepare_cluster_lds(), "hipFuncSetAttribute");

@@ -31,7 +31,13 @@ struct GraphDev {
   int32_t* row_ptr = nullptr;
   int32_t* col = nullptr;
   int32_t* J = nullptr;
-  int32_t* Jp = nullptr;  // int8 couplings shifted to the neighbour's spin byte (coupling mode 2)
+  // gathered-field copy of the CSR: rows padded to multiples of 4 entries
+  // (vertex 0, coupling 0); columns as spin-word byte offsets 256 (v >> 2)
+  // (+ (v & 3) in coupling modes 0 and 1); couplings as the sweep kernel's
+  // coupling mode wants them (mode 2: int8 shifted to the neighbour's byte)
+  int32_t* grow = nullptr;
+  int32_t* gcol = nullptr;
+  int32_t* gJ = nullptr;
   int32_t* class_ptr = nullptr;
 };
 
@@ -124,7 +130,9 @@ struct Desc {
   const int32_t* row_ptr;
   const int32_t* col;
   const int32_t* J;
-  const int32_t* Jp;
+  const int32_t* grow;
+  const int32_t* gcol;
+  const int32_t* gJ;
   const int32_t* class_ptr;
   int32_t* order;
   uint32_t* thr;

@@ -38,6 +38,7 @@ constexpr int kInitBlocks = 64;            // spin-init work-groups per instance
 constexpr int kApplyChunks = 16;           // cluster-apply work-groups per target
 constexpr int kFieldBlocks = 1024;         // max field-init work-groups per instance
 constexpr uint32_t kIdle = 0xFFFFFFFFu;    // padding block: returns at once
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBufferWord3 = 0x00020000;   // buffer resource word 3: 32-bit raw data
 
 // Map word: instance index in the high half, local block in the low half.
@@ -78,40 +79,39 @@ __device__ __forceinline__ void group_chunk(int G, int lb, int& group, int& chun
 // Field of Eq. 3 for TPW tiles at once, gathered from the neighbours' spin
 // words.  The scalar work (CSR entries, neighbour offsets, coupling masks) is
 // shared by the tiles; the spin loads and arithmetic are per tile.
-// Neighbours are taken four at a time with unconditional loads (the CSR
-// arrays carry trailing padding, and an entry past the row is a valid vertex
-// id), and the couplings of entries past the row are masked to zero, so the
-// loop body has no per-entry branches.  Spin words are read with buffer
-// loads: one resource per tile, the neighbour quad as the scalar offset and
-// the lane as the vector offset, so address arithmetic stays on the scalar
-// unit.  Coupling modes (JM): 0 full 32-bit products, 1 24-bit
+// Neighbours are taken four at a time from a copy of the CSR whose rows are
+// padded to multiples of 4 entries (padding: vertex 0, coupling 0), so the
+// loop body has no per-entry branches or masks.  Its column entries hold the
+// byte offset of the neighbour's spin word within a tile, 256 (v >> 2), plus
+// (v & 3) in coupling modes 0 and 1.  Spin words are read with
+// buffer loads: the neighbour quad as the scalar offset, tile and lane as the
+// vector offset, so address arithmetic stays on the scalar unit.  Coupling modes (JM): 0 full 32-bit products, 1 24-bit
 // products (|J| < 2^23), 2 int8 couplings pre-shifted to the neighbour's byte
 // of its spin word, so one 4 x int8 dot product adds J s_j.
 // ---------------------------------------------------------------------------
 template <int JM, int TPW>
-__device__ __forceinline__ void gather_fields(const PAMC_GLOBAL int32_t* __restrict__ col,
-                                              const PAMC_GLOBAL int32_t* __restrict__ J, int e0, int e1,
-                                              const __amdgpu_buffer_rsrc_t (&Stile)[TPW], int lane_bytes,
+__device__ __forceinline__ void gather_fields(const PAMC_GLOBAL int32_t* __restrict__ gcol,
+                                              const PAMC_GLOBAL int32_t* __restrict__ gJ, int e0, int e1,
+                                              __amdgpu_buffer_rsrc_t Sr, const int (&voff)[TPW],
                                               int32_t (&h)[TPW]) {
 #pragma unroll
   for (int t = 0; t < TPW; ++t) h[t] = 0;
   for (int e = e0; e < e1; e += 4) {
-    const int cnt = e1 - e;
-    int j[4];
-    int32_t c[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      // uniform by construction; stated so that a vector load of them can
-      // never turn the buffer offsets below into per-lane values
-      j[u] = __builtin_amdgcn_readfirstlane(col[e + u]);
-      c[u] = u < cnt ? __builtin_amdgcn_readfirstlane(J[e + u]) : 0;
-    }
+    // rows start at multiples of 4 entries: one 16-byte scalar load each
+    const i32x4 cj = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(gcol + e);
+    const i32x4 cJ = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(gJ + e);
+    // uniform by construction; stated so that a vector load of them can
+    // never turn the buffer offsets below into per-lane values
+    const int j[4] = {__builtin_amdgcn_readfirstlane(cj.x), __builtin_amdgcn_readfirstlane(cj.y),
+                      __builtin_amdgcn_readfirstlane(cj.z), __builtin_amdgcn_readfirstlane(cj.w)};
+    const int32_t c[4] = {__builtin_amdgcn_readfirstlane(cJ.x), __builtin_amdgcn_readfirstlane(cJ.y),
+                          __builtin_amdgcn_readfirstlane(cJ.z), __builtin_amdgcn_readfirstlane(cJ.w)};
     uint32_t w[TPW][4];
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        w[t][u] = __builtin_amdgcn_raw_buffer_load_b32(Stile[t], lane_bytes, (j[u] >> 2) * (kLanes * 4), 0);
+        w[t][u] = __builtin_amdgcn_raw_buffer_load_b32(Sr, voff[t], JM == 2 ? j[u] : (j[u] & ~3), 0);
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
@@ -119,7 +119,7 @@ __device__ __forceinline__ void gather_fields(const PAMC_GLOBAL int32_t* __restr
         if (JM == 2) {
           h[t] = __builtin_amdgcn_sdot4((int)w[t][u], c[u], h[t], false);
         } else {
-          const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[t][u], 8u * (uint32_t)(j[u] & 3), 8u);
+          const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[t][u], 8u * (uint32_t)(j[u] & 3), 8u);  // byte of the spin
           h[t] += JM == 1 ? __mul24(c[u], sv) : c[u] * sv;
         }
       }
@@ -181,12 +181,11 @@ __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __res
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile0 = group * TPW;
   const uint32_t tstride = (uint32_t)d.nq * kLanes;
-  __amdgpu_buffer_rsrc_t Stile[TPW];
+  const __amdgpu_buffer_rsrc_t Sr = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(S + (size_t)tile0 * tstride), (short)0, (int)(TPW * tstride * 4), kBufferWord3);
+  int voff[TPW];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t)
-    Stile[t] = __builtin_amdgcn_make_buffer_rsrc((void*)(S + (size_t)(tile0 + t) * tstride), (short)0,
-                                                 (int)(tstride * 4), kBufferWord3);
-  const int lane_bytes = lane * 4;
+  for (int t = 0; t < TPW; ++t) voff[t] = (int)(t * tstride * 4) + lane * 4;
   acc_t dE[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) dE[t] = 0;
@@ -197,13 +196,13 @@ __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __res
     const int q = q0 + qi;
     uint32_t sw[TPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) sw[t] = __builtin_amdgcn_raw_buffer_load_b32(Stile[t], lane_bytes, q * (kLanes * 4), 0);
+    for (int t = 0; t < TPW; ++t) sw[t] = __builtin_amdgcn_raw_buffer_load_b32(Sr, voff[t], q * (kLanes * 4), 0);
     int32_t h[4][TPW];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
       if (v >= v0 && v < v1) {
-        gather_fields<JM, TPW>(col, Jc, row_ptr[v], row_ptr[v + 1], Stile, lane_bytes, h[k]);
+        gather_fields<JM, TPW>(col, Jc, row_ptr[v], row_ptr[v + 1], Sr, voff, h[k]);
       } else {
 #pragma unroll
         for (int t = 0; t < TPW; ++t) h[k][t] = 0;
@@ -228,7 +227,7 @@ __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __res
         flipmask |= flip ? (0xFEu << (8 * k)) : 0u;  // +1 (0x01) <-> -1 (0xFF)
         nflip += __popcll(__ballot(flip));
       }
-      if (flipmask) __builtin_amdgcn_raw_buffer_store_b32(swt ^ flipmask, Stile[t], lane_bytes, q * (kLanes * 4), 0);
+      if (flipmask) __builtin_amdgcn_raw_buffer_store_b32(swt ^ flipmask, Sr, voff[t], q * (kLanes * 4), 0);
     }
   }
 #pragma unroll
@@ -264,12 +263,12 @@ __global__ void __launch_bounds__(256) k_sweep_pull(const Desc* __restrict__ D,
   const PAMC_GLOBAL uint32_t* __restrict__ thr_g = gmem((const uint32_t*)d.thr);
   PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0);
   PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
-  const PAMC_GLOBAL int32_t* __restrict__ Jc = gmem(JM == 2 ? d.Jp : d.J);
+  const PAMC_GLOBAL int32_t* __restrict__ Jc = gmem(d.gJ);
   if (!WIDE) {
     for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
     __syncthreads();
   }
-  sweep_pull_body<JM, TPW, !WIDE>(gmem(d.row_ptr), gmem(d.col), Jc, thr_g, thr_s, S, E, d, group, chunk, v0, v1, gs,
+  sweep_pull_body<JM, TPW, !WIDE>(gmem(d.grow), gmem(d.gcol), Jc, thr_g, thr_s, S, E, d, group, chunk, v0, v1, gs,
                                   Xt);
 }
 
@@ -1152,7 +1151,9 @@ Desc make_desc(const pamc_instance* I) {
   d.row_ptr = I->g.row_ptr;
   d.col = I->g.col;
   d.J = I->g.J;
-  d.Jp = I->g.Jp;
+  d.grow = I->g.grow;
+  d.gcol = I->g.gcol;
+  d.gJ = I->g.gJ;
   d.class_ptr = I->g.class_ptr;
   d.order = I->order;
   d.thr = I->thr;
