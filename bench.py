@@ -64,6 +64,22 @@ def sweep_bytes_per_attempt(p_flip: float, degree: float, pull: bool) -> float:
     return 5.0 + p_flip * (1.0 + 8.0 * degree) + csr
 
 
+VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12   # 39.3 T int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+
+def alu_slots_per_attempt(degree: float, coupling_mode: int) -> float:
+    """Vector-ALU issue slots (lane-ops, a 32x32->64 product counting 4 as it
+    issues at quarter rate) of one (replica, vertex) visit of the
+    gathered-field sweep.  Philox4x32-10: one 4-word block per 4 attempts,
+    10 rounds of two 32x32->64 products and two three-input xors, i.e.
+    (10 x (2 x 4 + 2)) / 4 = 25 slots.  Field: one int8 dot product per
+    neighbour (coupling mode 2), else byte extract + multiply + add.
+    Decision: spin extract, s*h, clamp (2), table address, compare, spin
+    flip select, energy select + add: 9 slots."""
+    per_neighbour = 1.0 if coupling_mode == 2 else 3.0
+    return 25.0 + per_neighbour * degree + 9.0
+
+
 def counters_traffic(name: str, src: str):
     """HBM bytes per launch from a committed rocprofv3 FETCH/WRITE pass, or
     None if the kernel source changed since the counters were taken."""
@@ -353,7 +369,9 @@ def main():
     if w["kind"] == "dense":
         # matrix-core partial fields of one 64-row block: 2 * 64 * n_pad * R ops
         npad = (n + 63) // 64 * 64
-        ops = 2.0 * 64 * npad * w["R"]
+        # matrix-core field products: 2 npad^2 R int8 ops per sweep
+        sweeps_done = prof["attempts"] / (n * w["R"])
+        ops = 2.0 * npad * npad * w["R"] * sweeps_done / max(prof["launches"], 1)
         achieved = ops / (launch_ms * 1e-3) / 1e12
         roof = {"kernel": "k_dense_gemm", "bound": "mfma", "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS,
                 "unit": "TOP/s (int8)", "frac": achieved / MFMA_I8_PEAK_TOPS,
@@ -364,15 +382,25 @@ def main():
         pull = bool(info.pull)
         bpa = sweep_bytes_per_attempt(p_flip, degree, pull)
         apl = prof["attempts"] / max(prof["launches"], 1)
-        achieved = bpa * apl / (launch_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_sweep_pull" if pull else "k_sweep", "bound": "hbm", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": counters_traffic(w["counters"], "sparse.hip"), "launch_ms": launch_ms,
-                "launches": prof["launches"], "attempts_per_launch": apl, "flip_rate": p_flip,
-                "algorithmic_bytes_per_attempt": bpa, "fields": "pull" if pull else "push",
-                "kernel_shape": {"tiles_per_wave": info.tiles_per_wave, "quads_per_wave": info.quads_per_wave,
-                                 "coupling_mode": info.coupling_mode},
-                "attempts_per_s_in_kernel": apl / (launch_ms * 1e-3)}
+        rate = apl / (launch_ms * 1e-3)
+        hbm = bpa * rate / 1e9
+        shape = {"tiles_per_wave": info.tiles_per_wave, "quads_per_wave": info.quads_per_wave,
+                 "coupling_mode": info.coupling_mode}
+        if pull:
+            # issue-bound: vector ALU slots per attempt (see alu_slots_per_attempt)
+            slots = alu_slots_per_attempt(degree, info.coupling_mode)
+            achieved = slots * rate / 1e12
+            roof = {"kernel": "k_sweep_pull", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
+                    "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
+                    "alu_slots_per_attempt": slots, "hbm_algorithmic_gbs": hbm,
+                    "hbm_algorithmic_frac": hbm / HBM_PEAK_GBS}
+        else:
+            roof = {"kernel": "k_sweep_push", "bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS}
+        roof.update({"traffic": counters_traffic(w["counters"], "sparse.hip"), "launch_ms": launch_ms,
+                     "launches": prof["launches"], "attempts_per_launch": apl, "flip_rate": p_flip,
+                     "algorithmic_bytes_per_attempt": bpa, "fields": "pull" if pull else "push",
+                     "kernel_shape": shape, "attempts_per_s_in_kernel": rate})
     out = {
         "metric": "spin-flip attempts/s + time-to-target-cut (plain vs batched/served), p50/p99",
         "value": attempts / wall,
