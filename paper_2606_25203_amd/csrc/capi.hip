@@ -66,7 +66,7 @@ void free_instance(pamc_instance* I) {
                   I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order, I->rs_P,
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
                   I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
-                  I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Dd, I->Ed[0], I->Ed[1],
+                  I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Ed[0], I->Ed[1],
                   I->flip_ctr, I->H_scratch};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -501,7 +501,6 @@ pamc_status build_dense_common(pamc_instance* I, int32_t n) {
   const size_t gsz = (size_t)pamc::dense_superblock_rows() * I->R;
   HIP_TRY(dalloc(I, &I->Gd, gsz), "alloc fields");
   HIP_TRY(hipMemsetAsync(I->Gd, 0, sizeof(int32_t) * gsz, I->stream), "memset");
-  HIP_TRY(dalloc(I, &I->Dd, (size_t)I->R * np), "alloc flips");
   I->order_cap = 1;
   HIP_TRY(dalloc(I, &I->order, 1), "alloc");
   HIP_TRY(hipMemsetAsync(I->flip_ctr, 0, sizeof(int64_t) * 512, I->stream), "memset");
@@ -704,6 +703,8 @@ pamc_status pamc_create_instance_dense_i8(int32_t n, const int8_t* J, int64_t ld
     X = std::max(X, ab);
   }
   if (2 * X >= INT32_MAX) return fail(PAMC_ERR_INVALID_ARG, "local field range exceeds int32");
+  // the dense sweep sums a block's 64 energy changes in 32 bits
+  if (X >= (1 << 25)) return fail(PAMC_ERR_UNSUPPORTED, "dense couplings with max_v sum_j |J_vj| >= 2^25");
   pamc_instance* I = new (std::nothrow) pamc_instance();
   if (!I) return fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
   st = open_device(I, cfg);

@@ -32,10 +32,10 @@ namespace pamc {
 namespace {
 
 constexpr int kDB = 64;          // spins per sequential block
-constexpr int kSB = 2048;        // rows per super-block: one field product, one sequential launch
+constexpr int kSB = 1024;        // rows per super-block: one field product, one sequential launch
 constexpr int kGM = 128, kGN = 128, kGK = 64;  // field-product tile: rows x replicas x K stage
 constexpr int kLdsRow = kGK + 16;              // bytes per staged row (padded)
-constexpr int kThrL = 4095;      // half-width of the LDS copy of the threshold table
+constexpr int kThrL = 2047;      // half-width of the LDS copy of the threshold table
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // J_ij = J_ji = +-1 from the low bit of Philox(key = seed; (i, j, 0, DENSE))
@@ -196,7 +196,6 @@ struct SeqArgs {
   const int8_t* J;
   int8_t* S0;
   int8_t* S1;
-  int8_t* dS;   // [R][np]: 2 s_new where a spin flipped in this super-block, else 0
   int64_t* E0;
   int64_t* E1;
   int32_t* G;   // [kSB][R] fields of the super-block rows against its starting spins
@@ -207,19 +206,93 @@ struct SeqArgs {
   int64_t* flip_ctr;
 };
 
-// One work-group per tile walks the super-block's 64-spin blocks in order.
-// For block b, the four waves first add to G the couplings to the spins that
-// flipped in the earlier blocks of the super-block, C = J[blk, row0 ..
-// row0 + 64b) . dS (matrix cores; dS read past the L1 with coherent buffer
-// loads, since this work-group wrote it), then wave 0 (lane = replica)
-// decides the block's spins in order with the in-block corrections
-// h_k = G_k + C_k + sum_{k' < k in block} J_kk' d_k' (d packed int8, dot4),
-// and records d in dS.
+// Out of line: only reached for fields beyond the LDS copy of the table.
+__device__ __noinline__ uint32_t threshold_far(double beta, int rule, int32_t x) {
+  return flip_threshold(beta, rule, x);
+}
+
+// Decides the 64 spins of one block for one replica per lane (wave 0):
+// h_k = gsum_k + sum_{k' < k in block} J_kk' d_k' (d = 2 s_new of flipped
+// spins, packed int8, dot4), x = s h, flip iff u < T[x] (Metropolis also for
+// x <= 0).  sw: the block's 16 spin words (updated in place); d: the
+// block's d words.
 template <int RULE>
-__global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
-  __shared__ uint32_t jd[kDB][kDB / 4];  // J[rb0 + k][rb0 + 4g .. 4g+3], packed int8
-  __shared__ int32_t gsum[kDB][64];      // fields of this tile before the block's own flips
+__device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
+                                             const uint32_t* thr_s, double beta, int32_t Xl, int32_t Xt,
+                                             uint32_t (&sw)[kDB / 4], int rb0, int n, uint32_t gs, uint32_t r,
+                                             uint32_t k0, uint32_t k1, int lane, uint32_t (&d)[kDB / 4], int64_t& dE,
+                                             int32_t& nflip) {
+  int32_t dE32 = 0;  // at most 64 |x| <= 64 X < 2^31 (X < 2^25)
+#pragma unroll
+  for (int g = 0; g < kDB / 4; ++g) d[g] = 0;
+#pragma unroll
+  for (int g = 0; g < kDB / 4; ++g) {
+    const int vq = rb0 + 4 * g;
+    if (vq >= n) break;
+    const u32x4 rnd = philox10((uint32_t)(vq >> 2), gs, r, kTagSweep, k0, k1);
+    // couplings to the flips of the earlier groups of the block: four
+    // independent chains, two partial sums each, off the decision chain
+    int32_t base[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * g + kk;
+      int32_t p0 = gsum[k][lane], p1 = 0;
+#pragma unroll
+      for (int g2 = 0; g2 + 1 < g; g2 += 2) {
+        p0 = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)d[g2], p0, false);
+        p1 = __builtin_amdgcn_sdot4((int)jd[k][g2 + 1], (int)d[g2 + 1], p1, false);
+      }
+      if (g & 1) p0 = __builtin_amdgcn_sdot4((int)jd[k][g - 1], (int)d[g - 1], p0, false);
+      base[kk] = p0 + p1;
+    }
+    uint32_t w = sw[g];
+    uint32_t dg = 0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * g + kk;
+      if (vq + kk >= n) break;
+      const int32_t h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, base[kk], false);
+      const int32_t sm = __builtin_amdgcn_sbfe((int32_t)w, 8u * kk + 7u, 1u);  // 0 for s = +1, -1 for s = -1
+      const int32_t x = (h ^ sm) - sm;                                         // s h
+      const int32_t xl = min(max(x, -Xl), Xl);
+      const uint32_t u = pick(rnd, kk);
+      bool flip = u < thr_s[xl + Xl];
+      // |x| beyond the LDS table (rare): the threshold is recomputed by the
+      // function that fills the table, so the decision chain never waits
+      // for global memory
+      if (__builtin_amdgcn_ballot_w64(x != xl) && Xl < Xt) {
+        if (x != xl) flip = u < threshold_far(beta, RULE, min(max(x, -Xt), Xt));
+      }
+      if (RULE == 1) flip = flip || x <= 0;
+      // branch-free update: spin byte 0x01 <-> 0xFF, d = 2 s_new = -2 s
+      dE32 += flip ? x : 0;
+      w ^= flip ? (0xFEu << (8 * kk)) : 0u;
+      dg |= flip ? (uint32_t)(uint8_t)(int8_t)(sm == 0 ? -2 : 2) << (8 * kk) : 0u;
+      nflip += flip ? 1 : 0;
+    }
+    d[g] = dg;
+    sw[g] = w;
+  }
+  dE += 2 * (int64_t)dE32;
+}
+
+// One work-group per tile walks the super-block's 64-spin blocks in order,
+// pipelined: while wave 0 decides block b, waves 1-3 prepare block b + 1 --
+// its fields G (taken from the field product, which is cleared for the next
+// super-block), plus the couplings to the spins flipped in blocks 0..b-1 of
+// the super-block, C = J[blk b+1, blocks 0..b-1] . dS (matrix cores; the
+// spin changes dS of the super-block are kept in LDS, replica-major), and
+// its diagonal block of J.  After wave 0 is done, the four waves add block
+// b's own contribution to block b + 1 (one 64-column matrix-core step, its J
+// fragments loaded before the decisions).
+template <int RULE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
+  __shared__ uint32_t jd[2][kDB][kDB / 4];   // J[rb0 + k][rb0 + 4g .. 4g+3], packed int8
+  __shared__ int32_t gsum[2][kDB][64];       // fields of this tile before the block's own flips
   __shared__ uint32_t thr_s[2 * kThrL + 1];  // thresholds for |x| <= Xl
+  __shared__ __attribute__((aligned(16))) int8_t dsl[64][kSB + 16];  // spin changes d, [replica][row - row0]
+  __shared__ uint32_t swl[2][64][kDB / 4 + 1];  // the block's spin words, [replica][word]
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
@@ -231,86 +304,129 @@ __global__ void __launch_bounds__(256) k_dense_seq(SeqArgs a, int32_t sweep_idx,
   const int r = tile * 64 + lane;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
   const int32_t Xt = (int32_t)st->table_x;
+  const double beta = st->sweep_beta;
   // The decision chain waits for every threshold read, so the central part
-  // of the table lives in LDS; |x| > Xl (beyond about 13 standard deviations
-  // of the field at n = 100,000) reads global memory.
+  // of the table lives in LDS; for |x| > Xl it is recomputed.
   const int32_t Xl = min(Xt, kThrL);
   for (int i = threadIdx.x; i <= 2 * Xl; i += blockDim.x) thr_s[i] = a.thr[Xt - Xl + i];
-  const __amdgpu_buffer_rsrc_t dsr =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(a.dS + (size_t)tile * 64 * a.np), (short)0, 64 * a.np, 0x00020000);
-  int64_t dE = 0;
-  int32_t nflip = 0;
-  for (int b = 0; b * kDB < rows; ++b) {
-    const int rb0 = row0 + b * kDB;
-    if (rb0 >= a.n) break;
-    // corrections from the earlier blocks of the super-block
-    v4i acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    const int8_t* arow = a.J + (size_t)(rb0 + 16 * wave + (lane & 15)) * a.np + row0 + 16 * (lane >> 4);
-    const int boff = (lane & 15) * a.np + row0 + 16 * (lane >> 4);
-    for (int k0 = 0; k0 < b * kDB; k0 += 64) {
-      const v4i av = *reinterpret_cast<const v4i*>(arow + k0);
-      v4i bv[4];
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-        bv[nt] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(dsr, boff + nt * 16 * a.np + k0, 0, 1));
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv[nt], acc[nt], 0, 0, 0);
+  const int nb = min(rows, a.n - row0 + kDB - 1) / kDB;  // blocks holding real spins
+  // fields of block bb (rows row0 + 64 bb ..) from G, cleared behind for
+  // the next super-block's product; the diagonal J block
+  auto load_fields = [&](int bb, int buf) {
+    for (int i = threadIdx.x; i < kDB * 64; i += blockDim.x) {
+      const int k = i >> 6, c = i & 63;
+      int32_t* gp = a.G + (size_t)(bb * kDB + k) * a.R + tile * 64 + c;
+      gsum[buf][k][c] = *gp;
+      *gp = 0;
     }
+  };
+  auto load_diag = [&](int bb, int buf, int t, int nt) {
+    const int rb0 = row0 + bb * kDB;
+    for (int i = t; i < kDB * kDB / 4; i += nt) {
+      const int k = i / (kDB / 4), g = i % (kDB / 4);
+      jd[buf][k][g] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 4 * g);
+      // the block's spin words of the tile (replica k, word g)
+      swl[buf][k][g] = *reinterpret_cast<const uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + rb0 + 4 * g);
+    }
+  };
+  // matrix-core product over the first 64 nsteps columns of the super-block
+  // for the 16-row strip sr of block bb: acc += J[strip rows][cols] . dsl[:, cols]
+  // (all of the strip's J fragments are loaded before the first product, so
+  // their latencies overlap)
+  auto strip_product = [&](int bb, int sr, int nsteps, v4i (&acc)[4]) {
+    const int8_t* arow = a.J + (size_t)(row0 + bb * kDB + 16 * sr + (lane & 15)) * a.np + row0 + 16 * (lane >> 4);
+    v4i av[kSB / kDB];
+#pragma unroll
+    for (int k = 0; k < kSB / kDB; ++k)
+      if (k < nsteps) av[k] = *reinterpret_cast<const v4i*>(arow + 64 * k);
+#pragma unroll
+    for (int k = 0; k < kSB / kDB; ++k) {
+      if (k < nsteps) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const v4i bv = *reinterpret_cast<const v4i*>(&dsl[nt * 16 + (lane & 15)][64 * k + 16 * (lane >> 4)]);
+          acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[k], bv, acc[nt], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // result fragment (row 4 (lane / 16) + j of the strip, replica 16 nt +
+  // lane % 16) of strip sr into gsum[buf]; with G, the fields are taken
+  // from the field product (and cleared there) in the same pass
+  auto add_strip = [&](int bb, int buf, int sr, const v4i (&acc)[4], bool with_g) {
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int m = 16 * wave + 4 * (lane >> 4) + j, c = nt * 16 + (lane & 15);
-        int32_t* gp = a.G + (size_t)(b * kDB + m) * a.R + tile * 64 + c;
-        gsum[m][c] = acc[nt][j] + *gp;
-        *gp = 0;  // cleared for the next super-block's accumulation
-      }
-    for (int i = threadIdx.x; i < kDB * kDB / 4; i += blockDim.x) {
-      const int k = i / (kDB / 4), g = i % (kDB / 4);
-      jd[k][g] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 4 * g);
-    }
-    __syncthreads();
-    if (wave == 0) {
-      uint32_t d[kDB / 4];  // packed int8 d_k' of this lane's replica
-#pragma unroll
-      for (int g = 0; g < kDB / 4; ++g) d[g] = 0;
-      uint32_t* srow = reinterpret_cast<uint32_t*>(S + (size_t)r * a.np + rb0);
-#pragma unroll
-      for (int g = 0; g < kDB / 4; ++g) {
-        const int vq = rb0 + 4 * g;
-        if (vq >= a.n) break;
-        const u32x4 rnd = philox10((uint32_t)(vq >> 2), gs, (uint32_t)r, kTagSweep, a.k0, a.k1);
-        uint32_t sw = srow[g];
-        uint32_t dg = 0;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int k = 4 * g + kk;
-          if (rb0 + k >= a.n) break;
-          int32_t h = gsum[k][lane];
-#pragma unroll
-          for (int g2 = 0; g2 < g; ++g2) h = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)d[g2], h, false);
-          h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, h, false);
-          const int32_t s = (int32_t)(int8_t)(sw >> (8 * kk));
-          const int32_t x = s * h;
-          const int32_t xl = min(max(x, -Xl), Xl);
-          uint32_t T = thr_s[xl + Xl];
-          if (x != xl && Xl < Xt) T = a.thr[min(max(x, -Xt), Xt) + Xt];
-          const bool flip = (RULE == 1 && x <= 0) || (pick(rnd, kk) < T);
-          if (flip) {
-            dE += 2 * (int64_t)x;
-            sw ^= (0xFEu << (8 * kk));
-            dg |= (uint32_t)(uint8_t)(int8_t)(-2 * s) << (8 * kk);
-            ++nflip;
-          }
+        const int k = 16 * sr + 4 * (lane >> 4) + j, c = nt * 16 + (lane & 15);
+        if (with_g) {
+          int32_t* gp = a.G + (size_t)(bb * kDB + k) * a.R + tile * 64 + c;
+          gsum[buf][k][c] = *gp + acc[nt][j];
+          *gp = 0;
+        } else {
+          gsum[buf][k][c] += acc[nt][j];
         }
-        d[g] = dg;
-        srow[g] = sw;
       }
-      uint32_t* drow = reinterpret_cast<uint32_t*>(a.dS + (size_t)r * a.np + rb0);
+  };
+  if (nb > 0) {
+    load_fields(0, 0);
+    load_diag(0, 0, threadIdx.x, blockDim.x);
+  }
+  __syncthreads();
+  int64_t dE = 0;
+  int32_t nflip = 0;
+  const v4i zero = {0, 0, 0, 0};
+  for (int b = 0; b < nb; ++b) {
+    const int cb = b & 1;
+    const int rb0 = row0 + b * kDB;
+    const bool next = b + 1 < nb;
+    // J fragment of block b+1, strip `wave`, against block b's columns
+    v4i a_next = zero;
+    if (next)
+      a_next = *reinterpret_cast<const v4i*>(a.J + (size_t)(rb0 + kDB + 16 * wave + (lane & 15)) * a.np + rb0 +
+                                             16 * (lane >> 4));
+    if (wave == 0) {
+      uint32_t sw[kDB / 4], d[kDB / 4];
+#pragma unroll
+      for (int g = 0; g < kDB / 4; ++g) sw[g] = swl[cb][lane][g];
+      decide_block<RULE>(jd[cb], gsum[cb], thr_s, beta, Xl, Xt, sw, rb0, a.n, gs, (uint32_t)r, a.k0, a.k1, lane, d,
+                         dE, nflip);
+      // the spins themselves are written back once, at the end
+      uint32_t* drow = reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]);
 #pragma unroll
       for (int g = 0; g < kDB / 4; ++g) drow[g] = d[g];
+    } else if (next) {
+      // waves 1..3: strips 0..3 of block b+1 (wave 1 also takes strip 3),
+      // then the diagonal J block
+      for (int sr = wave - 1; sr < 4; sr += 3) {
+        v4i acc[4] = {zero, zero, zero, zero};
+        strip_product(b + 1, sr, b, acc);
+        add_strip(b + 1, cb ^ 1, sr, acc, true);
+      }
+      load_diag(b + 1, cb ^ 1, threadIdx.x - 64, 192);
     }
-    __syncthreads();  // dS of this block is read by the next block's corrections
+    __syncthreads();
+    if (next) {
+      // block b's own flips, strip `wave` of block b+1
+      v4i acc[4] = {zero, zero, zero, zero};
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const v4i bv = *reinterpret_cast<const v4i*>(&dsl[nt * 16 + (lane & 15)][b * kDB + 16 * (lane >> 4)]);
+        acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a_next, bv, acc[nt], 0, 0, 0);
+      }
+      add_strip(b + 1, cb ^ 1, wave, acc, false);
+    }
+    __syncthreads();
+  }
+  // write back the super-block's spins, coalesced: a byte of d is 0 (no
+  // flip), 2 or -2, and a flip turns 0x01 <-> 0xFF, i.e. xor 0xFE
+  for (int i = threadIdx.x; i < 64 * nb * (kDB / 4); i += blockDim.x) {
+    const int rep = i / (nb * (kDB / 4)), j = i % (nb * (kDB / 4));
+    const uint32_t dw = *reinterpret_cast<const uint32_t*>(&dsl[rep][4 * j]);
+    if (dw != 0) {
+      uint32_t* sp = reinterpret_cast<uint32_t*>(S + (size_t)(tile * 64 + rep) * a.np + row0) + j;
+      *sp ^= (dw & 0x02020202u) * 0x7Fu;
+    }
   }
   if (wave != 0) return;
   if (dE != 0)
@@ -457,7 +573,6 @@ static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
   a.J = I->Jd;
   a.S0 = I->Sd;
   a.S1 = I->Sd2;
-  a.dS = I->Dd;
   a.E0 = I->pop.E[0];
   a.E1 = I->pop.E[1];
   a.G = I->Gd;

@@ -97,7 +97,6 @@ struct pamc_instance {
   int8_t* Sd = nullptr;  // [R][dn_pad] replica-major spins (dense)
   int8_t* Sd2 = nullptr; // resampling buffer
   int32_t* Gd = nullptr; // super-block field scratch [rows][R]
-  int8_t* Dd = nullptr;  // [R][dn_pad] 2 s_new of spins flipped in the current super-block
   int64_t* Ed[2] = {nullptr, nullptr};
   // profiling
   bool prof = false;
