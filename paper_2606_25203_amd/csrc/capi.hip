@@ -63,7 +63,7 @@ void free_instance(pamc_instance* I) {
   if (I->d_sched) hipFree(I->d_sched);
   void* ptrs[] = {I->g.row_ptr, I->g.col, I->g.J, I->g.grow, I->g.gcol, I->g.gJ, I->g.class_ptr, I->pop.S[0], I->pop.S[1],
                   I->pop.H[0], I->pop.H[1], I->pop.E[0], I->pop.E[1], I->pop.fam[0],
-                  I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order, I->rs_P,
+                  I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order,
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
                   I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
                   I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Ed[0], I->Ed[1],
@@ -348,7 +348,6 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(dalloc(I, &I->thr, 2 * I->X + 1), "alloc");
   I->order_cap = 64;
   HIP_TRY(dalloc(I, &I->order, (size_t)I->order_cap * ncls), "alloc");
-  HIP_TRY(dalloc(I, &I->rs_P, I->R), "alloc");
   HIP_TRY(dalloc(I, &I->rs_parent, I->R), "alloc");
   HIP_TRY(dalloc(I, &I->flip_ctr, 512), "alloc");
   HIP_TRY(hipMemsetAsync(I->flip_ctr, 0, sizeof(int64_t) * 512, I->stream), "memset");
@@ -367,7 +366,7 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   }
   HIP_TRY(hipMemcpyAsync(I->g.class_ptr, I->class_ptr.data(), sizeof(int32_t) * (ncls + 1), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->to_internal_dev, I->to_internal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, I->stream), "upload");
-  HIP_TRY(pamc::prepare_cluster_lds(), "hipFuncSetAttribute");
+  HIP_TRY(pamc::prepare_kernel_lds(), "hipFuncSetAttribute");
   SELF_BATCH(I, b);
   HIP_TRY(pamc::batch_init(*b), "init kernels");
   // the host arrays are read by the queued copies: wait before they go
@@ -495,9 +494,9 @@ pamc_status build_dense_common(pamc_instance* I, int32_t n) {
   }
   HIP_TRY(dalloc(I, &I->best, np), "alloc");
   HIP_TRY(dalloc(I, &I->st, 1), "alloc");
-  HIP_TRY(dalloc(I, &I->rs_P, I->R), "alloc");
   HIP_TRY(dalloc(I, &I->rs_parent, I->R), "alloc");
   HIP_TRY(dalloc(I, &I->flip_ctr, 512), "alloc");
+  HIP_TRY(pamc::prepare_kernel_lds(), "hipFuncSetAttribute");
   const size_t gsz = (size_t)pamc::dense_superblock_rows() * I->R;
   HIP_TRY(dalloc(I, &I->Gd, gsz), "alloc fields");
   HIP_TRY(hipMemsetAsync(I->Gd, 0, sizeof(int32_t) * gsz, I->stream), "memset");

@@ -70,7 +70,6 @@ struct pamc_instance {
   int32_t* order = nullptr; // [order_cap][ncls]
   int32_t order_cap = 0;
   // resampling scratch
-  uint64_t* rs_P = nullptr;
   int32_t* rs_parent = nullptr;
   // cluster scratch
   int32_t* cl_targets = nullptr;
@@ -141,7 +140,6 @@ struct Desc {
   int32_t *F0, *F1;
   int8_t* best;
   RunState* st;
-  uint64_t* rs_P;
   int32_t* rs_parent;
   int32_t* cl_targets;
   uint8_t* cl_sel;
@@ -177,6 +175,7 @@ struct Batch {
   int32_t max_ncls = 0, max_sweeps = 1, any_cluster = 0;
   int32_t group_ncls[kGroups] = {};  // most colour classes of an instance in each sweep group
   int64_t max_lds = 0;
+  int32_t max_R = 0;  // most replicas of an instance (resampling LDS)
   hipGraphExec_t step_graph = nullptr;  // one captured beta step (batch_run_steps)
   int64_t graph_key = -1;
   bool graph_failed = false;
@@ -208,7 +207,7 @@ hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
 hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
 int32_t cluster_max_n();
 int32_t sweep_waves();  // wavefronts per sweep work-group
-hipError_t prepare_cluster_lds();
+hipError_t prepare_kernel_lds();
 
 // controller pieces (sparse.hip) shared with the dense path
 hipError_t ctl_step_begin(Batch& b);

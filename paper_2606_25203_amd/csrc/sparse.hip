@@ -612,89 +612,123 @@ __global__ void __launch_bounds__(256) k_thresholds(const Desc* __restrict__ D,
 }
 
 // ---------------------------------------------------------------------------
-// Best cut (Algorithm 1: M* <- max(M*, max Cut(P)), lowest slot on ties),
-// then, in a run, the recent-progress history, the adaptive temperature rule
-// and the schedule advance.  One work-group per instance.
+// Block-wide helpers for the 1024-thread per-instance kernels: shuffles
+// within each wave, then the 16 wave results through LDS.
 // ---------------------------------------------------------------------------
-__device__ int32_t distinct_tail(const int64_t* h, int len, int w) {
-  int dcount = 0;
-  for (int i = len - w; i < len; ++i) {
-    bool dup = false;
-    for (int j = len - w; j < i; ++j)
-      if (h[j] == h[i]) { dup = true; break; }
-    if (!dup) ++dcount;
+template <typename V>
+__device__ __forceinline__ V block_excl_scan(V x, V* part16) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  V inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const V y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
   }
-  return dcount;
+  if (lane == 63) part16[wv] = inc;
+  __syncthreads();
+  V off = 0;
+  for (int i = 0; i < wv; ++i) off += part16[i];
+  __syncthreads();
+  return off + inc - x;
 }
 
+// ---------------------------------------------------------------------------
+// Best cut (Algorithm 1: M* <- max(M*, max Cut(P)), lowest slot on ties),
+// then, in a run, the recent-progress history, the adaptive temperature rule
+// and the schedule advance.  One work-group per instance; the distinct
+// counts over the two history windows are taken by one thread per entry.
+// ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_step_end(const Desc* __restrict__ D, int32_t in_run) {
-  __shared__ int64_t bc[1024];
-  __shared__ int32_t bs[1024];
-  __shared__ int improved;
+  __shared__ int64_t bc[16];
+  __shared__ int32_t bs[16];
+  __shared__ int64_t hs[kHistCap];
   const Desc& a = D[blockIdx.x];
   RunState* st = a.st;
   if (!st->active) return;
+  // every thread reads the state it needs before the first barrier; thread
+  // 0 writes it only after the last one
   const int cur = st->cur;
+  const int64_t mstar_old = st->mstar;
+  const int L0 = st->hist_len, wl = st->win_long, ws = st->win_short;
+  const bool eval_ok = st->augmented && st->cooldown == 0;
   const int64_t* E = cur ? a.E1 : a.E0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int64_t c = INT64_MIN;
   int32_t cs = 0x7FFFFFFF;
-  for (int r = threadIdx.x; r < a.R; r += blockDim.x) {
+  for (int r = tid; r < a.R; r += blockDim.x) {
     const int64_t cut = (a.W - E[r]) / 2;
-    if (cut > c) { c = cut; cs = r; }
+    if (cut > c) { c = cut; cs = r; }  // r increases: ties keep the lower slot
   }
-  bc[threadIdx.x] = c;
-  bs[threadIdx.x] = cs;
-  __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      const int64_t c2 = bc[threadIdx.x + o];
-      const int32_t s2 = bs[threadIdx.x + o];
-      if (c2 > bc[threadIdx.x] || (c2 == bc[threadIdx.x] && s2 < bs[threadIdx.x])) {
-        bc[threadIdx.x] = c2;
-        bs[threadIdx.x] = s2;
-      }
-    }
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t c2 = __shfl_xor(c, o, 64);
+    const int32_t s2 = __shfl_xor(cs, o, 64);
+    if (c2 > c || (c2 == c && s2 < cs)) { c = c2; cs = s2; }
   }
-  const int64_t m = bc[0];
-  const int32_t slot = bs[0];
-  if (threadIdx.x == 0) improved = m > st->mstar;
+  if (lane == 0) { bc[wv] = c; bs[wv] = cs; }
   __syncthreads();
+  int64_t m = bc[0];
+  int32_t slot = bs[0];
+  for (int i = 1; i < 16; ++i)
+    if (bc[i] > m || (bc[i] == m && bs[i] < slot)) { m = bc[i]; slot = bs[i]; }
+  const bool improved = m > mstar_old;
   if (improved) {
     if (a.dense) {
       const int8_t* Dsp = (cur ? a.D1 : a.D0) + (size_t)slot * a.np;
-      for (int v = threadIdx.x; v < a.np; v += blockDim.x) a.best[v] = Dsp[v];
+      for (int v = tid; v < a.np; v += blockDim.x) a.best[v] = Dsp[v];
     } else {
+      // one spin word (4 spins) per thread and step
       const uint32_t* S = cur ? a.S1 : a.S0;
-      const int tile = slot >> 6, lane = slot & 63;
-      for (int v = threadIdx.x; v < a.np; v += blockDim.x) {
-        const uint32_t w = S[((size_t)tile * a.nq + (v >> 2)) * kLanes + lane];
-        a.best[v] = (int8_t)(w >> (8 * (v & 3)));
-      }
+      const int tile = slot >> 6, sl = slot & 63;
+      for (int q = tid; q < a.nq; q += blockDim.x)
+        reinterpret_cast<uint32_t*>(a.best)[q] = S[((size_t)tile * a.nq + q) * kLanes + sl];
     }
   }
-  if (threadIdx.x != 0) return;
+  if (!in_run) {
+    if (tid == 0 && improved) {
+      st->mstar = m;
+      st->best_slot = slot;
+    }
+    return;
+  }
+  const int64_t ms = improved ? m : mstar_old;
+  // recent-progress history: the oldest value leaves once win_long are
+  // held, then M* is appended
+  const int drop = L0 >= wl ? 1 : 0;
+  const int L = L0 - drop + 1;
+  if (tid < L - 1) hs[tid] = st->hist[tid + drop];
+  if (tid == L - 1) hs[tid] = ms;
+  __syncthreads();
+  if (tid < L) st->hist[tid] = hs[tid];
+  int ds = 0, dl = 0;
+  if (eval_ok && L >= wl) {  // uniform
+    // entry tid counts for a window when no earlier entry of that window
+    // holds the same value
+    bool first_s = tid >= L - ws && tid < L, first_l = tid >= L - wl && tid < L;
+    if (first_l) {
+      const int64_t v = hs[tid];
+      for (int j = L - wl; j < tid; ++j)
+        if (hs[j] == v) {
+          first_l = false;
+          if (j >= L - ws) first_s = false;
+        }
+    }
+    ds = __syncthreads_count(first_s);
+    dl = __syncthreads_count(first_l);
+  }
+  if (tid != 0) return;
   if (improved) {
     st->mstar = m;
     st->best_slot = slot;
   }
-  if (!in_run) return;
-  const int64_t ms = st->mstar;
+  st->hist_len = L;
   int32_t ev = (st->do_resample ? 1 : 0) | (st->do_cluster ? 2 : 0);
   const uint64_t now = wall_clock64();
   if (st->step_reached < 0 && ms >= st->target) {
     st->step_reached = st->step;
     st->t_reached = now;
   }
-  // recent-progress history (only the last win_long values are needed)
-  if (st->hist_len >= st->win_long) {
-    for (int i = 1; i < st->hist_len; ++i) st->hist[i - 1] = st->hist[i];
-    st->hist_len -= 1;
-  }
-  st->hist[st->hist_len++] = ms;
-  if (st->augmented && st->cooldown == 0 && st->hist_len >= st->win_long) {
-    const int ds = distinct_tail(st->hist, st->hist_len, st->win_short);
-    const int dl = distinct_tail(st->hist, st->hist_len, st->win_long);
+  if (eval_ok && L >= wl) {
     if (ds <= st->max_ds && dl <= st->max_dl) {          // strong stagnation
       st->beta = st->reheat * st->beta;
       st->delta = st->dbeta;
@@ -769,96 +803,88 @@ __global__ void k_status(const Desc* __restrict__ D, int32_t ninst, int32_t* out
 // word u, y = floor(u Q / 2^64), parent = least j with P_j > y; children are
 // then laid out by parent (counting sort).
 // ---------------------------------------------------------------------------
-template <typename V>
-__device__ V block_scan_incl(V x, V* tmp) {  // 1024 threads, Hillis-Steele
-  tmp[threadIdx.x] = x;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    V y = (int)threadIdx.x >= o ? tmp[threadIdx.x - o] : (V)0;
-    __syncthreads();
-    tmp[threadIdx.x] += y;
-    __syncthreads();
-  }
-  V r = tmp[threadIdx.x];
-  __syncthreads();
-  return r;
-}
-
 __global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D) {
-  __shared__ int32_t cnt[kRsMaxR];
-  __shared__ uint64_t tmp64[1024];
-  __shared__ double tmpd[1024];
-  __shared__ int64_t eref_s;
+  // the prefix P in LDS for the children's searches, then the same space
+  // holds the number of children of each slot
+  extern __shared__ uint64_t P[];
+  __shared__ int64_t part_m[16];
+  __shared__ uint64_t part_u[16];
+  __shared__ double part_d[16];
+  __shared__ int32_t part_i[16];
   const Desc& a = D[blockIdx.x];
   RunState* st = a.st;
   if (!st->active || !st->do_resample) return;
   const int64_t* E = st->cur ? a.E1 : a.E0;
   const double delta = st->rs_delta;
+  const bool lowest = delta >= 0;  // reference energy: min for delta >= 0, max otherwise
   const int R = a.R;
-  const int tid = threadIdx.x;
-  // extreme energy: min for delta >= 0, max otherwise
-  {
-    int64_t m = E[0];
-    for (int r = tid; r < R; r += 1024) {
-      const int64_t e = E[r];
-      if (delta >= 0 ? e < m : e > m) m = e;
-    }
-    tmp64[tid] = (uint64_t)m;
-    __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-      if (tid < o) {
-        const int64_t x = (int64_t)tmp64[tid], y = (int64_t)tmp64[tid + o];
-        tmp64[tid] = (uint64_t)(delta >= 0 ? (y < x ? y : x) : (y > x ? y : x));
-      }
-      __syncthreads();
-    }
-    if (tid == 0) eref_s = (int64_t)tmp64[0];
-    __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int64_t m = E[0];
+  for (int r = tid; r < R; r += 1024) {
+    const int64_t e = E[r];
+    if (lowest ? e < m : e > m) m = e;
   }
-  const int64_t eref = eref_s;
-  // contiguous chunk per thread
-  const int per = (R + 1023) / 1024;
-  const int r0 = tid * per, r1 = min(R, r0 + per);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(m, o, 64);
+    if (lowest ? y < m : y > m) m = y;
+  }
+  if (lane == 0) part_m[wv] = m;
+  __syncthreads();
+  int64_t eref = part_m[0];
+  for (int i = 1; i < 16; ++i)
+    if (lowest ? part_m[i] < eref : part_m[i] > eref) eref = part_m[i];
+  // weights and their integer prefix, a contiguous chunk of slots per thread
+  const int per = (R + 1023) >> 10;
+  const int r0 = min(R, tid * per), r1 = min(R, r0 + per);
   double wsum = 0.0;
   uint64_t run = 0;
   for (int r = r0; r < r1; ++r) {
     const double w = exp_cw(-(delta * (double)(E[r] - eref)));
     wsum += w;
     run += (uint64_t)floor(w * 281474976710656.0);
-    a.rs_P[r] = run;  // local inclusive prefix
+    P[r] = run;  // local inclusive prefix
   }
-  const uint64_t off = block_scan_incl<uint64_t>(run, tmp64) - run;
-  for (int r = r0; r < r1; ++r) a.rs_P[r] += off;
-  tmpd[tid] = wsum;
+  const uint64_t off = block_excl_scan<uint64_t>(run, part_u);
+  for (int r = r0; r < r1; ++r) P[r] += off;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, 64);
+  if (lane == 0) part_d[wv] = wsum;
+  __syncthreads();
+  double wtot = 0.0;
+  for (int i = 0; i < 16; ++i) wtot += part_d[i];
+  const uint64_t Q = P[R - 1];
+  const uint32_t g = st->g_rs;
+  int par[kRsMaxR / 1024];
+#pragma unroll
+  for (int i = 0; i < kRsMaxR / 1024; ++i) {
+    const int k = tid + 1024 * i;
+    par[i] = -1;
+    if (k < R) {
+      const u32x4 w = philox10((uint32_t)(k >> 1), g, 0u, kTagResample, a.k0, a.k1);
+      const uint64_t u = (k & 1) ? ((uint64_t)w.c | ((uint64_t)w.d << 32))
+                                 : ((uint64_t)w.a | ((uint64_t)w.b << 32));
+      const uint64_t y = __umul64hi(u, Q);
+      int lo = 0, hi = R - 1;  // least j with P[j] > y; P[R-1] = Q > y
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (P[mid] > y) hi = mid; else lo = mid + 1;
+      }
+      par[i] = lo;
+    }
+  }
+  __syncthreads();
+  int32_t* cnt = reinterpret_cast<int32_t*>(P);
   for (int r = tid; r < R; r += 1024) cnt[r] = 0;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if (tid < o) tmpd[tid] += tmpd[tid + o];
-    __syncthreads();
-  }
-  const double wtot = tmpd[0];
-  __threadfence_block();
-  __syncthreads();
-  const uint64_t Q = a.rs_P[R - 1];
-  const uint32_t g = st->g_rs;
-  for (int k = tid; k < R; k += 1024) {
-    const u32x4 w = philox10((uint32_t)(k >> 1), g, 0u, kTagResample, a.k0, a.k1);
-    const uint64_t u = (k & 1) ? ((uint64_t)w.c | ((uint64_t)w.d << 32))
-                               : ((uint64_t)w.a | ((uint64_t)w.b << 32));
-    const uint64_t y = __umul64hi(u, Q);
-    int lo = 0, hi = R - 1;  // least j with P[j] > y; P[R-1] = Q > y
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (a.rs_P[mid] > y) hi = mid; else lo = mid + 1;
-    }
-    atomicAdd(&cnt[lo], 1);
-  }
+#pragma unroll
+  for (int i = 0; i < kRsMaxR / 1024; ++i)
+    if (par[i] >= 0) atomicAdd(&cnt[par[i]], 1);
   __syncthreads();
   // children ordered by parent
   int local = 0;
   for (int r = r0; r < r1; ++r) local += cnt[r];
-  const int start = (int)block_scan_incl<uint64_t>((uint64_t)local, tmp64) - local;
-  int pos = start;
+  int pos = block_excl_scan<int32_t>(local, part_i);
   for (int r = r0; r < r1; ++r)
     for (int c = 0; c < cnt[r]; ++c) a.rs_parent[pos++] = r;
   if (tid == 0) st->last_lnq = -delta * (double)eref + log(wtot) - log((double)R);
@@ -904,7 +930,9 @@ __global__ void __launch_bounds__(256) k_rs_gather(const Desc* __restrict__ D,
 
 // ---------------------------------------------------------------------------
 // Non-local cluster move (Algorithm 1; Sec. "Augmented PAMC").
-// cl_select: the n_top slots with the lowest (E, slot), by rank counting.
+// cl_select: the n_top slots with the lowest (E, slot), by a radix select on
+//   E - min E; targets are listed in slot order (each target's move depends
+//   on its slot only).
 // cl_mis: per (target, trial), the greedy independent set of iso-sites
 //   (h = 0) in the order of Philox keys (v, g_cl, r, CL | t<<8), ties by id.
 //   The sequential greedy is computed with parallel rounds: an undecided
@@ -915,7 +943,11 @@ __global__ void __launch_bounds__(256) k_rs_gather(const Desc* __restrict__ D,
 //   no two are coupled).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_cl_select(const Desc* __restrict__ D) {
-  __shared__ int64_t es[4096];
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t part_u[16];
+  __shared__ int32_t part_i[16];
+  __shared__ uint64_t pick_prefix;
+  __shared__ int32_t pick_want;
   const Desc& d = D[blockIdx.x];
   RunState* st = d.st;
   if (!st->active || !st->do_cluster) return;
@@ -925,37 +957,104 @@ __global__ void __launch_bounds__(1024) k_cl_select(const Desc* __restrict__ D) 
   // no targets without scratch (a move with no trials flips nothing)
   const int n_top = (d.cl_targets && st->cl_trials > 0) ? min(st->cl_n_top, R) : 0;
   if (n_top <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // a contiguous chunk of slots per thread, keys E - min E as unsigned
   constexpr int kPer = kRsMaxR / 1024;
-  int64_t mine[kPer];
-  int rank[kPer];
+  const int per = (R + 1023) >> 10;
+  const int r0 = min(R, tid * per), r1 = min(R, r0 + per);
+  int64_t e[kPer];
+  int64_t emin = INT64_MAX;
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
-    const int r = threadIdx.x + i * 1024;
-    mine[i] = r < R ? E[r] : 0;
-    rank[i] = 0;
+    e[i] = r0 + i < r1 ? E[r0 + i] : INT64_MAX;
+    emin = e[i] < emin ? e[i] : emin;
   }
-  for (int base = 0; base < R; base += 4096) {
-    const int len = min(4096, R - base);
-    __syncthreads();
-    for (int q = threadIdx.x; q < len; q += 1024) es[q] = E[base + q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(emin, o, 64);
+    emin = y < emin ? y : emin;
+  }
+  if (lane == 0) part_u[wv] = (uint64_t)emin;
+  __syncthreads();
+  emin = (int64_t)part_u[0];
+  for (int i = 1; i < 16; ++i) emin = (int64_t)part_u[i] < emin ? (int64_t)part_u[i] : emin;
+  __syncthreads();
+  uint64_t key[kPer], kmax = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    key[i] = (uint64_t)e[i] - (uint64_t)emin;
+    if (r0 + i < r1 && key[i] > kmax) kmax = key[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t y = __shfl_xor(kmax, o, 64);
+    kmax = y > kmax ? y : kmax;
+  }
+  if (lane == 0) part_u[wv] = kmax;
+  __syncthreads();
+  kmax = part_u[0];
+  for (int i = 1; i < 16; ++i) kmax = part_u[i] > kmax ? part_u[i] : kmax;
+  // radix select, 8 bits a pass from the highest used bit: t = the key of
+  // the n_top-th smallest (E, slot); want = how many slots with key t are
+  // taken (the lowest ones)
+  const int nbits = kmax ? 64 - __clzll((long long)kmax) : 0;
+  uint64_t t = 0;
+  int want = n_top;
+  for (int s = ((nbits + 7) / 8) * 8 - 8; s >= 0; s -= 8) {
+    if (tid < 256) hist[tid] = 0;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const int r = threadIdx.x + i * 1024;
-      if (r >= R) continue;
-      int c = 0;
-      for (int q = 0; q < len; ++q) {
-        const int64_t f = es[q];
-        c += (f < mine[i]) || (f == mine[i] && base + q < r);
+    for (int i = 0; i < kPer; ++i)
+      if (r0 + i < r1 && (s + 8 >= 64 || ((key[i] ^ t) >> (s + 8)) == 0))
+        atomicAdd(&hist[(key[i] >> s) & 255u], 1u);
+    __syncthreads();
+    if (wv == 0) {
+      uint32_t h[4], tot = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) { h[j] = hist[4 * lane + j]; tot += h[j]; }
+      uint32_t inc = tot;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
       }
-      rank[i] += c;
+      uint32_t cum = inc - tot;
+      if (cum < (uint32_t)want && (uint32_t)want <= inc) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (cum + h[j] >= (uint32_t)want) {
+            pick_prefix = t | ((uint64_t)(4 * lane + j) << s);
+            pick_want = want - (int)cum;
+            break;
+          }
+          cum += h[j];
+        }
+      }
     }
+    __syncthreads();
+    t = pick_prefix;
+    want = pick_want;
   }
+  // selected: key < t, or key == t among the first `want` such slots
+  int neq = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) neq += (r0 + i < r1 && key[i] == t) ? 1 : 0;
+  int eq_before = block_excl_scan<int32_t>(neq, part_i);
+  bool sel[kPer];
+  int nsel = 0;
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
-    const int r = threadIdx.x + i * 1024;
-    if (r < R && rank[i] < n_top) d.cl_targets[rank[i]] = r;
+    sel[i] = false;
+    if (r0 + i < r1) {
+      if (key[i] < t) sel[i] = true;
+      else if (key[i] == t) sel[i] = eq_before++ < want;
+    }
+    nsel += sel[i] ? 1 : 0;
   }
+  int pos = block_excl_scan<int32_t>(nsel, part_i);
+#pragma unroll
+  for (int i = 0; i < kPer; ++i)
+    if (sel[i]) d.cl_targets[pos++] = r0 + i;
 }
 
 enum : uint8_t { kOut = 0, kUnd = 1, kCand = 2, kIn = 3 };
@@ -1076,8 +1175,15 @@ __global__ void __launch_bounds__(256) k_cl_apply(const Desc* __restrict__ D, co
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ++mine;
   }
-  if (mine)
-    __hip_atomic_fetch_add((unsigned long long*)a.cl_flipped, (unsigned long long)mine, __ATOMIC_RELAXED,
+  // one counter update per work-group
+  __shared__ int32_t part[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  const int total = part[0] + part[1] + part[2] + part[3];
+  if (threadIdx.x == 0 && total)
+    __hip_atomic_fetch_add((unsigned long long*)a.cl_flipped, (unsigned long long)total, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -1140,9 +1246,13 @@ __global__ void __launch_bounds__(256) k_pair_distance(const uint32_t* S0, const
 int32_t cluster_max_n() { return kClusterMaxN; }
 int32_t sweep_waves() { return kSweepWaves; }
 
-hipError_t prepare_cluster_lds() {
-  return hipFuncSetAttribute((const void*)k_cl_mis, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             kClusterMaxN * 5 + 64);
+// Kernels whose dynamic LDS may exceed the default limit.
+hipError_t prepare_kernel_lds() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_cl_mis, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     kClusterMaxN * 5 + 64);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_rs_select, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sizeof(uint64_t) * kRsMaxR);
 }
 
 Desc make_desc(const pamc_instance* I) {
@@ -1167,7 +1277,6 @@ Desc make_desc(const pamc_instance* I) {
   d.F1 = I->pop.fam[1];
   d.best = I->best;
   d.st = I->st;
-  d.rs_P = I->rs_P;
   d.rs_parent = I->rs_parent;
   d.cl_targets = I->cl_targets;
   d.cl_sel = I->cl_sel;
@@ -1267,8 +1376,10 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
   b.max_sweeps = 1;
   b.any_cluster = 0;
   b.max_lds = 0;
+  b.max_R = 0;
   for (int i = 0; i < b.n; ++i) {
     pamc_instance* I = insts[i];
+    b.max_R = std::max(b.max_R, I->R);
     if (I->dense) continue;
     add_blocks(m_init, i, kInitBlocks, false);
     add_blocks(m_fields, i, field_blocks(I), false);
@@ -1384,7 +1495,7 @@ hipError_t batch_anneal_setup(Batch& b, const Schedule* d_sched, const int32_t* 
 }
 
 static hipError_t batch_resample(Batch& b) {
-  k_rs_select<<<b.n, 1024, 0, b.stream>>>(b.d_desc);
+  k_rs_select<<<b.n, 1024, sizeof(uint64_t) * b.max_R, b.stream>>>(b.d_desc);
   if (b.gather.grid) k_rs_gather<<<b.gather.grid, 256, 0, b.stream>>>(b.d_desc, b.gather.map);
   return hipGetLastError();
 }
@@ -1515,7 +1626,7 @@ hipError_t ctl_step_begin(Batch& b) {
   return hipGetLastError();
 }
 hipError_t ctl_resample_select(Batch& b) {
-  k_rs_select<<<b.n, 1024, 0, b.stream>>>(b.d_desc);
+  k_rs_select<<<b.n, 1024, sizeof(uint64_t) * b.max_R, b.stream>>>(b.d_desc);
   return hipGetLastError();
 }
 hipError_t ctl_commit(Batch& b, int32_t in_run) {

@@ -127,6 +127,39 @@ def test_cluster_move(pamc, n_top, trials, fields):
     inst.close()
 
 
+@pytest.mark.parametrize("R,n_top", [(2048, 300), (1216, 1216), (3008, 1)])
+def test_cluster_move_large_population(pamc, R, n_top):
+    # several slots per thread of the selection, every slot a target, and a
+    # population that is not a multiple of the work-group size
+    g = synth.torus(12, 10, 4)
+    say(f"case cluster R={R} n_top={n_top}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=21)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 21)
+    inst.sweep(2.5, 4)
+    o.sweep(2.5, 4)
+    f = inst.cluster_move(n_top, 2)
+    tot, _ = o.cluster(n_top, 2)
+    assert f == tot
+    same_state(inst, o, "after cluster")
+    inst.close()
+
+
+@pytest.mark.parametrize("R", [4096, 16384])
+def test_resample_large_population(pamc, R):
+    g = synth.random_graph(60, 200, 8)
+    say(f"case resample R={R}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=5)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 5)
+    inst.sweep(0.9, 2)
+    o.sweep(0.9, 2)
+    for delta in (0.3, -0.1):
+        lq = inst.resample(delta)
+        olq = o.resample(delta)
+        assert close_lnq(lq, olq), (lq, olq)
+        same_state(inst, o, "after resample")
+    inst.close()
+
+
 def test_update_best(pamc):
     g = synth.random_graph(150, 700, 2)
     inst = pamc.Instance.csr(g, replicas=64, seed=9)
