@@ -215,8 +215,12 @@ pamc_status pamc_max3cut_decode(pamc_instance* inst, const int8_t* spins, int32_
  * replica pairs (Supplement, Hamming distance).  Waits. */
 pamc_status pamc_pair_distance(pamc_instance* inst, double* mean);
 
-/* Kernel timing: when enabled, the library brackets every launch of the
- * sweep kernel with HIP events on the instance stream. */
+/* Kernel timing: when enabled, the library records HIP events on the
+ * instance stream around the sweep kernels: for sparse couplings one pair
+ * around each step's consecutive sweep launches (so the mean launch time
+ * includes the launch boundaries), for dense couplings one pair around each
+ * launch of the field product.  Enabling it also turns on the flip counters
+ * and turns off graph replay of beta steps. */
 pamc_status pamc_profile_enable(pamc_instance* inst, int32_t on);
 /* Sum of event-measured sweep-kernel time (ms), number of launches, and the
  * attempts (replica x vertex visits) they made since enabling.  Waits. */

@@ -509,10 +509,9 @@ __global__ void k_anneal_setup(const Desc* __restrict__ D, const Schedule* __res
   st->t_last = st->t_start;
 }
 
-__global__ void k_step_begin(const Desc* __restrict__ D, int32_t ninst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ninst) return;
-  RunState* st = D[i].st;
+// Decisions of a run's beta step (Algorithm 1), by one thread per instance.
+__device__ __forceinline__ void begin_step(const Desc& d) {
+  RunState* st = d.st;
   if (st->stopped || st->steps_run >= st->steps || (st->stop_at_target && st->mstar >= st->target)) {
     st->stopped = 1;
     st->active = 0;
@@ -527,8 +526,13 @@ __global__ void k_step_begin(const Desc* __restrict__ D, int32_t ninst) {
   st->nsweeps_now = st->sweeps;
   st->cl_n_top = st->n_top;
   st->cl_trials = st->mis_trials;
-  st->table_x = table_halfwidth(st->beta, D[i].X);
+  st->table_x = table_halfwidth(st->beta, d.X);
   st->last_lnq = 0.0;
+}
+
+__global__ void k_step_begin(const Desc* __restrict__ D, int32_t ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) begin_step(D[i]);
 }
 
 // Primitive calls: one data-parallel action outside a run.
@@ -552,10 +556,7 @@ __global__ void k_prim_set(const Desc* __restrict__ D, int32_t ninst, int32_t ki
 // After resampling / cluster move: switch population buffers and advance the
 // stream counters; in a run also apply Algorithm 1's "enable <- false;
 // cooldown <- tau" after a cluster move.
-__global__ void k_commit(const Desc* __restrict__ D, int32_t ninst, int32_t in_run) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ninst) return;
-  const Desc& d = D[i];
+__device__ __forceinline__ void commit_step(const Desc& d, int32_t in_run) {
   RunState* st = d.st;
   if (!st->active) return;
   if (st->do_resample) {
@@ -578,16 +579,24 @@ __global__ void k_commit(const Desc* __restrict__ D, int32_t ninst, int32_t in_r
   }
 }
 
+__global__ void k_commit(const Desc* __restrict__ D, int32_t ninst, int32_t in_run) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) commit_step(D[i], in_run);
+}
+
 // Threshold table for the step's beta (entries x = -Xt..Xt) and the class
 // order of each of the step's sweeps: a Fisher-Yates shuffle driven by
-// Philox(i, sweep, 0, ORDER), j = floor(u (i+1) / 2^32).
+// Philox(i, sweep, 0, ORDER), j = floor(u (i+1) / 2^32).  With commit >= 0
+// the instance's first block also commits the step's resampling / cluster
+// move (commit = in_run); no field read here is changed by that.
 __global__ void __launch_bounds__(256) k_thresholds(const Desc* __restrict__ D,
-                                                    const uint64_t* __restrict__ map) {
+                                                    const uint64_t* __restrict__ map, int32_t commit) {
   int inst, lb;
   if (!resolve(map, inst, lb)) return;
   const Desc& d = D[inst];
   const RunState* st = d.st;
   if (!st->active) return;
+  if (commit >= 0 && lb == 0 && threadIdx.x == 0) commit_step(d, commit);
   const int64_t Xt = st->table_x;
   const double beta = st->sweep_beta;
   for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i <= 2 * Xt; i += (int64_t)kThrBlocks * blockDim.x)
@@ -796,6 +805,136 @@ __global__ void k_status(const Desc* __restrict__ D, int32_t ninst, int32_t* out
 }
 
 // ---------------------------------------------------------------------------
+// Targets of the non-local cluster move: the n_top slots with the lowest
+// (E, slot), by a radix select on E - min E; they are listed in slot order
+// (each target's move depends on its slot only).
+// ---------------------------------------------------------------------------
+// LDS of the target selection (declared by the calling kernel).
+struct SelectLds {
+  uint32_t hist[256];
+  uint64_t part_u[16];
+  int32_t part_i[16];
+  uint64_t pick_prefix;
+  int32_t pick_want;
+};
+
+// Energy of slot r of the population the cluster move acts on: E[r], or,
+// right after the resampling draw, the energy of r's parent.
+__device__ __forceinline__ int64_t target_energy(const int64_t* E, const int32_t* parent, int r) {
+  return E[parent ? parent[r] : r];
+}
+
+// Called by all 1024 threads of the work-group.
+__device__ __forceinline__ void select_cluster_targets(const Desc& d, const RunState* st, const int64_t* E,
+                                       const int32_t* parent, SelectLds& L) {
+  uint32_t* hist = L.hist;
+  uint64_t* part_u = L.part_u;
+  int32_t* part_i = L.part_i;
+  const int R = d.R;
+  // no targets without scratch (a move with no trials flips nothing)
+  const int n_top = (d.cl_targets && st->cl_trials > 0) ? min(st->cl_n_top, R) : 0;
+  if (n_top <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // a contiguous chunk of slots per thread, keys E - min E as unsigned
+  constexpr int kPer = kRsMaxR / 1024;
+  const int per = (R + 1023) >> 10;
+  const int r0 = min(R, tid * per), r1 = min(R, r0 + per);
+  int64_t e[kPer];
+  int64_t emin = INT64_MAX;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    e[i] = r0 + i < r1 ? target_energy(E, parent, r0 + i) : INT64_MAX;
+    emin = e[i] < emin ? e[i] : emin;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(emin, o, 64);
+    emin = y < emin ? y : emin;
+  }
+  if (lane == 0) part_u[wv] = (uint64_t)emin;
+  __syncthreads();
+  emin = (int64_t)part_u[0];
+  for (int i = 1; i < 16; ++i) emin = (int64_t)part_u[i] < emin ? (int64_t)part_u[i] : emin;
+  __syncthreads();
+  uint64_t key[kPer], kmax = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    key[i] = (uint64_t)e[i] - (uint64_t)emin;
+    if (r0 + i < r1 && key[i] > kmax) kmax = key[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t y = __shfl_xor(kmax, o, 64);
+    kmax = y > kmax ? y : kmax;
+  }
+  if (lane == 0) part_u[wv] = kmax;
+  __syncthreads();
+  kmax = part_u[0];
+  for (int i = 1; i < 16; ++i) kmax = part_u[i] > kmax ? part_u[i] : kmax;
+  // radix select, 8 bits a pass from the highest used bit: t = the key of
+  // the n_top-th smallest (E, slot); want = how many slots with key t are
+  // taken (the lowest ones)
+  const int nbits = kmax ? 64 - __clzll((long long)kmax) : 0;
+  uint64_t t = 0;
+  int want = n_top;
+  for (int s = ((nbits + 7) / 8) * 8 - 8; s >= 0; s -= 8) {
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+      if (r0 + i < r1 && (s + 8 >= 64 || ((key[i] ^ t) >> (s + 8)) == 0))
+        atomicAdd(&hist[(key[i] >> s) & 255u], 1u);
+    __syncthreads();
+    if (wv == 0) {
+      uint32_t h[4], tot = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) { h[j] = hist[4 * lane + j]; tot += h[j]; }
+      uint32_t inc = tot;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+      }
+      uint32_t cum = inc - tot;
+      if (cum < (uint32_t)want && (uint32_t)want <= inc) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (cum + h[j] >= (uint32_t)want) {
+            L.pick_prefix = t | ((uint64_t)(4 * lane + j) << s);
+            L.pick_want = want - (int)cum;
+            break;
+          }
+          cum += h[j];
+        }
+      }
+    }
+    __syncthreads();
+    t = L.pick_prefix;
+    want = L.pick_want;
+  }
+  // selected: key < t, or key == t among the first `want` such slots
+  int neq = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) neq += (r0 + i < r1 && key[i] == t) ? 1 : 0;
+  int eq_before = block_excl_scan<int32_t>(neq, part_i);
+  bool sel[kPer];
+  int nsel = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    sel[i] = false;
+    if (r0 + i < r1) {
+      if (key[i] < t) sel[i] = true;
+      else if (key[i] == t) sel[i] = eq_before++ < want;
+    }
+    nsel += sel[i] ? 1 : 0;
+  }
+  int pos = block_excl_scan<int32_t>(nsel, part_i);
+#pragma unroll
+  for (int i = 0; i < kPer; ++i)
+    if (sel[i]) d.cl_targets[pos++] = r0 + i;
+}
+
+// ---------------------------------------------------------------------------
 // Resampling (Eqs. 1-2), one work-group per instance.  Weights relative to
 // the extreme energy, w_r = e^{-Delta (E_r - E_ref)} in binary64; ln Q =
 // -Delta E_ref + ln sum w - ln R.  Selection is exact integer arithmetic:
@@ -803,7 +942,10 @@ __global__ void k_status(const Desc* __restrict__ D, int32_t ninst, int32_t* out
 // word u, y = floor(u Q / 2^64), parent = least j with P_j > y; children are
 // then laid out by parent (counting sort).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D) {
+// In a run (fused = 1) the kernel first takes the step's decisions and,
+// when the step makes a cluster move, ends by selecting its targets from the
+// children's energies.
+__global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D, int32_t fused) {
   // the prefix P in LDS for the children's searches, then the same space
   // holds the number of children of each slot
   extern __shared__ uint64_t P[];
@@ -811,8 +953,13 @@ __global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D) 
   __shared__ uint64_t part_u[16];
   __shared__ double part_d[16];
   __shared__ int32_t part_i[16];
+  __shared__ SelectLds L;
   const Desc& a = D[blockIdx.x];
   RunState* st = a.st;
+  if (fused) {
+    if (threadIdx.x == 0) begin_step(a);
+    __syncthreads();
+  }
   if (!st->active || !st->do_resample) return;
   const int64_t* E = st->cur ? a.E1 : a.E0;
   const double delta = st->rs_delta;
@@ -881,13 +1028,29 @@ __global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D) 
   for (int i = 0; i < kRsMaxR / 1024; ++i)
     if (par[i] >= 0) atomicAdd(&cnt[par[i]], 1);
   __syncthreads();
-  // children ordered by parent
+  // children ordered by parent: cnt becomes the inclusive prefix C, and
+  // child j's parent is the least r with C_r > j
   int local = 0;
-  for (int r = r0; r < r1; ++r) local += cnt[r];
-  int pos = block_excl_scan<int32_t>(local, part_i);
-  for (int r = r0; r < r1; ++r)
-    for (int c = 0; c < cnt[r]; ++c) a.rs_parent[pos++] = r;
+  for (int r = r0; r < r1; ++r) {
+    local += cnt[r];
+    cnt[r] = local;
+  }
+  const int coff = block_excl_scan<int32_t>(local, part_i);
+  for (int r = r0; r < r1; ++r) cnt[r] += coff;
+  __syncthreads();
+  for (int j = tid; j < R; j += 1024) {
+    int lo = 0, hi = R - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cnt[mid] > j) hi = mid; else lo = mid + 1;
+    }
+    a.rs_parent[j] = lo;
+  }
   if (tid == 0) st->last_lnq = -delta * (double)eref + log(wtot) - log((double)R);
+  if (fused && st->do_cluster) {
+    __syncthreads();
+    select_cluster_targets(a, st, E, a.rs_parent, L);
+  }
 }
 
 // Copies every child's spins, fields, energy and lineage from its parent into
@@ -930,9 +1093,8 @@ __global__ void __launch_bounds__(256) k_rs_gather(const Desc* __restrict__ D,
 
 // ---------------------------------------------------------------------------
 // Non-local cluster move (Algorithm 1; Sec. "Augmented PAMC").
-// cl_select: the n_top slots with the lowest (E, slot), by a radix select on
-//   E - min E; targets are listed in slot order (each target's move depends
-//   on its slot only).
+// cl_select: the targets (see select_cluster_targets; in a run this is done
+//   at the end of the resampling selection).
 // cl_mis: per (target, trial), the greedy independent set of iso-sites
 //   (h = 0) in the order of Philox keys (v, g_cl, r, CL | t<<8), ties by id.
 //   The sequential greedy is computed with parallel rounds: an undecided
@@ -943,118 +1105,12 @@ __global__ void __launch_bounds__(256) k_rs_gather(const Desc* __restrict__ D,
 //   no two are coupled).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_cl_select(const Desc* __restrict__ D) {
-  __shared__ uint32_t hist[256];
-  __shared__ uint64_t part_u[16];
-  __shared__ int32_t part_i[16];
-  __shared__ uint64_t pick_prefix;
-  __shared__ int32_t pick_want;
+  __shared__ SelectLds L;
   const Desc& d = D[blockIdx.x];
   RunState* st = d.st;
   if (!st->active || !st->do_cluster) return;
   const int buf = st->cur ^ st->do_resample;
-  const int64_t* E = buf ? d.E1 : d.E0;
-  const int R = d.R;
-  // no targets without scratch (a move with no trials flips nothing)
-  const int n_top = (d.cl_targets && st->cl_trials > 0) ? min(st->cl_n_top, R) : 0;
-  if (n_top <= 0) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // a contiguous chunk of slots per thread, keys E - min E as unsigned
-  constexpr int kPer = kRsMaxR / 1024;
-  const int per = (R + 1023) >> 10;
-  const int r0 = min(R, tid * per), r1 = min(R, r0 + per);
-  int64_t e[kPer];
-  int64_t emin = INT64_MAX;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    e[i] = r0 + i < r1 ? E[r0 + i] : INT64_MAX;
-    emin = e[i] < emin ? e[i] : emin;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const int64_t y = __shfl_xor(emin, o, 64);
-    emin = y < emin ? y : emin;
-  }
-  if (lane == 0) part_u[wv] = (uint64_t)emin;
-  __syncthreads();
-  emin = (int64_t)part_u[0];
-  for (int i = 1; i < 16; ++i) emin = (int64_t)part_u[i] < emin ? (int64_t)part_u[i] : emin;
-  __syncthreads();
-  uint64_t key[kPer], kmax = 0;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    key[i] = (uint64_t)e[i] - (uint64_t)emin;
-    if (r0 + i < r1 && key[i] > kmax) kmax = key[i];
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t y = __shfl_xor(kmax, o, 64);
-    kmax = y > kmax ? y : kmax;
-  }
-  if (lane == 0) part_u[wv] = kmax;
-  __syncthreads();
-  kmax = part_u[0];
-  for (int i = 1; i < 16; ++i) kmax = part_u[i] > kmax ? part_u[i] : kmax;
-  // radix select, 8 bits a pass from the highest used bit: t = the key of
-  // the n_top-th smallest (E, slot); want = how many slots with key t are
-  // taken (the lowest ones)
-  const int nbits = kmax ? 64 - __clzll((long long)kmax) : 0;
-  uint64_t t = 0;
-  int want = n_top;
-  for (int s = ((nbits + 7) / 8) * 8 - 8; s >= 0; s -= 8) {
-    if (tid < 256) hist[tid] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kPer; ++i)
-      if (r0 + i < r1 && (s + 8 >= 64 || ((key[i] ^ t) >> (s + 8)) == 0))
-        atomicAdd(&hist[(key[i] >> s) & 255u], 1u);
-    __syncthreads();
-    if (wv == 0) {
-      uint32_t h[4], tot = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) { h[j] = hist[4 * lane + j]; tot += h[j]; }
-      uint32_t inc = tot;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += y;
-      }
-      uint32_t cum = inc - tot;
-      if (cum < (uint32_t)want && (uint32_t)want <= inc) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (cum + h[j] >= (uint32_t)want) {
-            pick_prefix = t | ((uint64_t)(4 * lane + j) << s);
-            pick_want = want - (int)cum;
-            break;
-          }
-          cum += h[j];
-        }
-      }
-    }
-    __syncthreads();
-    t = pick_prefix;
-    want = pick_want;
-  }
-  // selected: key < t, or key == t among the first `want` such slots
-  int neq = 0;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) neq += (r0 + i < r1 && key[i] == t) ? 1 : 0;
-  int eq_before = block_excl_scan<int32_t>(neq, part_i);
-  bool sel[kPer];
-  int nsel = 0;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    sel[i] = false;
-    if (r0 + i < r1) {
-      if (key[i] < t) sel[i] = true;
-      else if (key[i] == t) sel[i] = eq_before++ < want;
-    }
-    nsel += sel[i] ? 1 : 0;
-  }
-  int pos = block_excl_scan<int32_t>(nsel, part_i);
-#pragma unroll
-  for (int i = 0; i < kPer; ++i)
-    if (sel[i]) d.cl_targets[pos++] = r0 + i;
+  select_cluster_targets(d, st, buf ? d.E1 : d.E0, nullptr, L);
 }
 
 enum : uint8_t { kOut = 0, kUnd = 1, kCand = 2, kIn = 3 };
@@ -1456,26 +1512,32 @@ static hipEvent_t next_event(pamc_instance* I) {
 
 static inline int tgrid(int n) { return (n + 63) / 64; }
 
-// thresholds + class orders, then nsweeps x max_ncls phase launches
-static hipError_t batch_sweeps(Batch& b, int32_t nsweeps) {
+// thresholds + class orders (and, with commit >= 0, the step's commit), then
+// nsweeps x max_ncls phase launches.  When
+// profiling, one event pair brackets the step's back-to-back sweep launches
+// (nothing else runs between them), so the mean launch time includes the
+// launch boundaries and the events cost two markers per step, not two per
+// launch.
+static hipError_t batch_sweeps(Batch& b, int32_t nsweeps, int32_t commit = -1) {
   pamc_instance* P = b.I[0];
   const bool prof = P->prof;
-  if (b.thr.grid) k_thresholds<<<b.thr.grid, 256, 0, b.stream>>>(b.d_desc, b.thr.map);
+  if (b.thr.grid) k_thresholds<<<b.thr.grid, 256, 0, b.stream>>>(b.d_desc, b.thr.map, commit);
+  int64_t launches = 0;
+  if (prof) hipEventRecord(next_event(P), b.stream);
   for (int s = 0; s < nsweeps; ++s) {
     for (int p = 0; p < b.max_ncls; ++p) {
       for (int g = 0; g < Batch::kGroups; ++g) {
         if (!b.sweep[g].grid || p >= b.group_ncls[g]) continue;  // no instance of the group has class p
-        if (prof) hipEventRecord(next_event(P), b.stream);
         sweep_kernel_of_group(g)<<<b.sweep[g].grid, 256, 0, b.stream>>>(b.d_desc, b.sweep[g].map, s, p);
-        if (prof) {
-          hipEventRecord(next_event(P), b.stream);
-          P->prof_launches += 1;
-        }
+        ++launches;
       }
     }
   }
-  if (prof)
+  if (prof) {
+    hipEventRecord(next_event(P), b.stream);
+    P->prof_launches += launches;
     for (pamc_instance* I : b.I) P->prof_attempts += (int64_t)nsweeps * I->n * I->R;
+  }
   return hipGetLastError();
 }
 
@@ -1494,25 +1556,27 @@ hipError_t batch_anneal_setup(Batch& b, const Schedule* d_sched, const int32_t* 
   return hipGetLastError();
 }
 
-static hipError_t batch_resample(Batch& b) {
-  k_rs_select<<<b.n, 1024, sizeof(uint64_t) * b.max_R, b.stream>>>(b.d_desc);
+// fused: the run step's decisions before, the cluster targets after the draw
+static hipError_t batch_resample(Batch& b, int32_t fused) {
+  k_rs_select<<<b.n, 1024, sizeof(uint64_t) * b.max_R, b.stream>>>(b.d_desc, fused);
   if (b.gather.grid) k_rs_gather<<<b.gather.grid, 256, 0, b.stream>>>(b.d_desc, b.gather.map);
   return hipGetLastError();
 }
 
-static hipError_t batch_cluster(Batch& b) {
-  k_cl_select<<<b.n, 1024, 0, b.stream>>>(b.d_desc);
+// select: false when the targets were chosen with the resampling draw
+static hipError_t batch_cluster(Batch& b, bool select) {
+  if (select) k_cl_select<<<b.n, 1024, 0, b.stream>>>(b.d_desc);
   if (b.cl_mis.grid) k_cl_mis<<<b.cl_mis.grid, 1024, b.max_lds, b.stream>>>(b.d_desc, b.cl_mis.map);
   if (b.cl_apply.grid) k_cl_apply<<<b.cl_apply.grid, 256, 0, b.stream>>>(b.d_desc, b.cl_apply.map);
   return hipGetLastError();
 }
 
 hipError_t batch_step(Batch& b) {
-  k_step_begin<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
-  batch_resample(b);
-  if (b.any_cluster) batch_cluster(b);
-  k_commit<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 1);
-  hipError_t e = batch_sweeps(b, b.max_sweeps);
+  // step decisions + resampling draw (+ cluster targets), gather, cluster
+  // move, thresholds + commit, sweeps, step end
+  batch_resample(b, 1);
+  if (b.any_cluster) batch_cluster(b, false);
+  hipError_t e = batch_sweeps(b, b.max_sweeps, 1);
   if (e != hipSuccess) return e;
   k_step_end<<<b.n, 1024, 0, b.stream>>>(b.d_desc, 1);
   return hipGetLastError();
@@ -1576,7 +1640,7 @@ hipError_t prim_sweep(Batch& b, double beta, int32_t nsweeps) {
 
 hipError_t prim_resample(Batch& b, double delta) {
   k_prim_set<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 1, delta, 0, 0, 0);
-  batch_resample(b);
+  batch_resample(b, 0);
   k_commit<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 0);
   k_deactivate<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
   return hipGetLastError();
@@ -1584,7 +1648,7 @@ hipError_t prim_resample(Batch& b, double delta) {
 
 hipError_t prim_cluster(Batch& b, int32_t n_top, int32_t trials) {
   k_prim_set<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 2, 0.0, n_top, trials, 0);
-  batch_cluster(b);
+  batch_cluster(b, true);
   k_commit<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n, 0);
   k_deactivate<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
   return hipGetLastError();
@@ -1626,7 +1690,7 @@ hipError_t ctl_step_begin(Batch& b) {
   return hipGetLastError();
 }
 hipError_t ctl_resample_select(Batch& b) {
-  k_rs_select<<<b.n, 1024, sizeof(uint64_t) * b.max_R, b.stream>>>(b.d_desc);
+  k_rs_select<<<b.n, 1024, sizeof(uint64_t) * b.max_R, b.stream>>>(b.d_desc, 0);
   return hipGetLastError();
 }
 hipError_t ctl_commit(Batch& b, int32_t in_run) {
@@ -1644,7 +1708,7 @@ hipError_t ctl_thresholds(Batch& b) {
     e = hipMemcpy(b.thr_dense.map, m.data(), sizeof(uint64_t) * m.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
   }
-  k_thresholds<<<b.thr_dense.grid, 256, 0, b.stream>>>(b.d_desc, b.thr_dense.map);
+  k_thresholds<<<b.thr_dense.grid, 256, 0, b.stream>>>(b.d_desc, b.thr_dense.map, -1);
   return hipGetLastError();
 }
 hipError_t ctl_step_end(Batch& b, int32_t in_run) {
