@@ -206,33 +206,32 @@ struct SeqArgs {
   int64_t* flip_ctr;
 };
 
-// Out of line: only reached for fields beyond the LDS copy of the table.
-__device__ __noinline__ uint32_t threshold_far(double beta, int rule, int32_t x) {
-  return flip_threshold(beta, rule, x);
-}
 
-// Decides the 64 spins of one block for one replica per lane (wave 0):
+// One pass over the 64 spins of one block for one replica per lane (wave 0):
 // h_k = gsum_k + sum_{k' < k in block} J_kk' d_k' (d = 2 s_new of flipped
 // spins, packed int8, dot4), x = s h, flip iff u < T[x] (Metropolis also for
-// x <= 0).  sw: the block's 16 spin words (updated in place); d: the
-// block's d words.
+// x <= 0), u from the block's Philox words in LDS; every spin of the block
+// is below n.  sw: the block's 16 spin words (updated in place); d: the
+// block's d words.  Thresholds come from the LDS
+// table with x clamped to +-Xl; the pass returns whether any lane met
+// |x| > Xl.  It has no branches, so the compiler can move the independent
+// work (Philox, the couplings to earlier groups, LDS reads) into the
+// latency of the decision chain.
 template <int RULE>
-__device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
-                                             const uint32_t* thr_s, double beta, int32_t Xl, int32_t Xt,
-                                             uint32_t (&sw)[kDB / 4], int rb0, int n, uint32_t gs, uint32_t r,
-                                             uint32_t k0, uint32_t k1, int lane, uint32_t (&d)[kDB / 4], int64_t& dE,
-                                             int32_t& nflip) {
-  int32_t dE32 = 0;  // at most 64 |x| <= 64 X < 2^31 (X < 2^25)
+__device__ __forceinline__ bool decide_pass(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
+                                            const u32x4 (*rnd_s)[64], const uint32_t* thr_s, int32_t Xl,
+                                            uint32_t (&sw)[kDB / 4], int lane, uint32_t (&d)[kDB / 4],
+                                            int32_t& dE32, int32_t& nflip) {
+  bool wide = false;
 #pragma unroll
   for (int g = 0; g < kDB / 4; ++g) d[g] = 0;
 #pragma unroll
   for (int g = 0; g < kDB / 4; ++g) {
-    const int vq = rb0 + 4 * g;
-    if (vq >= n) break;
-    const u32x4 rnd = philox10((uint32_t)(vq >> 2), gs, r, kTagSweep, k0, k1);
+    const u32x4 rnd = rnd_s[g][lane];
     // couplings to the flips of the earlier groups of the block: four
     // independent chains, two partial sums each, off the decision chain
     int32_t base[4];
+    uint32_t jg[4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int k = 4 * g + kk;
@@ -244,25 +243,18 @@ __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], cons
       }
       if (g & 1) p0 = __builtin_amdgcn_sdot4((int)jd[k][g - 1], (int)d[g - 1], p0, false);
       base[kk] = p0 + p1;
+      jg[kk] = jd[k][g];
     }
     uint32_t w = sw[g];
     uint32_t dg = 0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * g + kk;
-      if (vq + kk >= n) break;
-      const int32_t h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, base[kk], false);
+      const int32_t h = __builtin_amdgcn_sdot4((int)jg[kk], (int)dg, base[kk], false);
       const int32_t sm = __builtin_amdgcn_sbfe((int32_t)w, 8u * kk + 7u, 1u);  // 0 for s = +1, -1 for s = -1
       const int32_t x = (h ^ sm) - sm;                                         // s h
       const int32_t xl = min(max(x, -Xl), Xl);
-      const uint32_t u = pick(rnd, kk);
-      bool flip = u < thr_s[xl + Xl];
-      // |x| beyond the LDS table (rare): the threshold is recomputed by the
-      // function that fills the table, so the decision chain never waits
-      // for global memory
-      if (__builtin_amdgcn_ballot_w64(x != xl) && Xl < Xt) {
-        if (x != xl) flip = u < threshold_far(beta, RULE, min(max(x, -Xt), Xt));
-      }
+      wide = wide || x != xl;
+      bool flip = pick(rnd, kk) < thr_s[xl + Xl];
       if (RULE == 1) flip = flip || x <= 0;
       // branch-free update: spin byte 0x01 <-> 0xFF, d = 2 s_new = -2 s
       dE32 += flip ? x : 0;
@@ -273,7 +265,85 @@ __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], cons
     d[g] = dg;
     sw[g] = w;
   }
+  return wide;
+}
+
+struct BlockTally {
+  int32_t dE32, nflip;
+};
+
+// The same decisions with every threshold exact (fields beyond the LDS
+// table recomputed by the function that fills it), from the block's
+// starting spin words sw0 (LDS); the d words go to dout (LDS).  Out of line
+// and unoptimised for speed: only reached when a lane met |x| > Xl.
+template <int RULE>
+__device__ __noinline__ BlockTally decide_block_exact(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
+                                                      const uint32_t* thr_s, double beta, int32_t Xl, int32_t Xt,
+                                                      const uint32_t* sw0, uint32_t* dout, int rb0, int n,
+                                                      uint32_t gs, uint32_t r, uint32_t k0, uint32_t k1, int lane) {
+  BlockTally t = {0, 0};
+  for (int g = 0; g < kDB / 4; ++g) {
+    const int vq = rb0 + 4 * g;
+    const u32x4 rnd = philox10((uint32_t)(vq >> 2), gs, r, kTagSweep, k0, k1);
+    uint32_t w = sw0[g], dg = 0;
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * g + kk;
+      int32_t h = gsum[k][lane];
+      for (int g2 = 0; g2 < g; ++g2) h = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)dout[g2], h, false);
+      h = __builtin_amdgcn_sdot4((int)jd[k][g], (int)dg, h, false);
+      const int32_t sm = -(int32_t)((w >> (8 * kk + 7)) & 1u);
+      const int32_t x = (h ^ sm) - sm;
+      const int32_t xl = min(max(x, -Xl), Xl);
+      const uint32_t thr = x == xl ? thr_s[xl + Xl] : flip_threshold(beta, RULE, min(max(x, -Xt), Xt));
+      const uint32_t u = kk == 0 ? rnd.a : kk == 1 ? rnd.b : kk == 2 ? rnd.c : rnd.d;
+      bool flip = u < thr;
+      if (RULE == 1) flip = flip || x <= 0;
+      flip = flip && vq + kk < n;
+      if (flip) {
+        t.dE32 += x;
+        w ^= 0xFEu << (8 * kk);
+        dg |= (uint32_t)(uint8_t)(int8_t)(sm == 0 ? -2 : 2) << (8 * kk);
+        t.nflip += 1;
+      }
+    }
+    dout[g] = dg;
+  }
+  return t;
+}
+
+// Decides the 64 spins of one block; d words into dout (LDS).  The LDS
+// table covers |x| <= Xl; when it is narrower than the table (Xl < Xt) and
+// some lane met a field beyond it, the block is decided again, exactly,
+// from its starting spins (one uniform branch per block keeps the common
+// pass free of control flow).  The last block of the matrix, which holds
+// spins at or beyond n, takes the exact path directly.
+template <int RULE>
+__device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
+                                             const u32x4 (*rnd_s)[64], const uint32_t* thr_s, double beta,
+                                             int32_t Xl, int32_t Xt, const uint32_t* sw0, uint32_t* dout, int rb0,
+                                             int n, uint32_t gs, uint32_t r, uint32_t k0, uint32_t k1, int lane,
+                                             int64_t& dE, int32_t& nflip) {
+  int32_t dE32 = 0, nf = 0;  // |dE32| <= 64 X < 2^31 (X < 2^25)
+  bool exact = rb0 + kDB > n;
+  if (!exact) {
+    uint32_t sw[kDB / 4], d[kDB / 4];
+#pragma unroll
+    for (int g = 0; g < kDB / 4; ++g) sw[g] = sw0[g];
+    const bool wide = decide_pass<RULE>(jd, gsum, rnd_s, thr_s, Xl, sw, lane, d, dE32, nf);
+    exact = Xl < Xt && __builtin_amdgcn_ballot_w64(wide);
+    if (!exact) {
+#pragma unroll
+      for (int g = 0; g < kDB / 4; ++g) dout[g] = d[g];
+    }
+  }
+  if (exact) {
+    const BlockTally t = decide_block_exact<RULE>(jd, gsum, thr_s, beta, Xl, Xt, sw0, dout, rb0, n, gs, r, k0, k1,
+                                                  lane);
+    dE32 = t.dE32;
+    nf = t.nflip;
+  }
   dE += 2 * (int64_t)dE32;
+  nflip += nf;
 }
 
 // One work-group per tile walks the super-block's 64-spin blocks in order,
@@ -293,6 +363,7 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
   __shared__ uint32_t thr_s[2 * kThrL + 1];  // thresholds for |x| <= Xl
   __shared__ __attribute__((aligned(16))) int8_t dsl[64][kSB + 16];  // spin changes d, [replica][row - row0]
   __shared__ uint32_t swl[2][64][kDB / 4 + 1];  // the block's spin words, [replica][word]
+  __shared__ __attribute__((aligned(16))) u32x4 rnd_s[kDB / 4][64];  // the block's Philox words, [group][replica]
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
@@ -368,9 +439,14 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
         }
       }
   };
+  // Philox words of block bb, group g (four spins), this lane's replica
+  auto philox_group = [&](int bb, int g) {
+    return philox10((uint32_t)(((row0 + bb * kDB) >> 2) + g), gs, (uint32_t)r, kTagSweep, a.k0, a.k1);
+  };
   if (nb > 0) {
     load_fields(0, 0);
     load_diag(0, 0, threadIdx.x, blockDim.x);
+    for (int g = wave; g < kDB / 4; g += 4) rnd_s[g][lane] = philox_group(0, g);
   }
   __syncthreads();
   int64_t dE = 0;
@@ -385,19 +461,24 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
     if (next)
       a_next = *reinterpret_cast<const v4i*>(a.J + (size_t)(rb0 + kDB + 16 * wave + (lane & 15)) * a.np + rb0 +
                                              16 * (lane >> 4));
+    // waves 1..3: the Philox words of block b+1, groups wave-1, wave+2, ..
+    // (held in registers until wave 0 is done with block b's)
+    constexpr int kRndPerHelper = (kDB / 4 + 2) / 3;
+    u32x4 rnd_next[kRndPerHelper];
     if (wave == 0) {
-      uint32_t sw[kDB / 4], d[kDB / 4];
-#pragma unroll
-      for (int g = 0; g < kDB / 4; ++g) sw[g] = swl[cb][lane][g];
-      decide_block<RULE>(jd[cb], gsum[cb], thr_s, beta, Xl, Xt, sw, rb0, a.n, gs, (uint32_t)r, a.k0, a.k1, lane, d,
-                         dE, nflip);
-      // the spins themselves are written back once, at the end
-      uint32_t* drow = reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]);
-#pragma unroll
-      for (int g = 0; g < kDB / 4; ++g) drow[g] = d[g];
+      // the d words go to the super-block's spin changes; the spins
+      // themselves are written back once, at the end
+      decide_block<RULE>(jd[cb], gsum[cb], rnd_s, thr_s, beta, Xl, Xt, swl[cb][lane],
+                         reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]), rb0, a.n, gs, (uint32_t)r, a.k0, a.k1,
+                         lane, dE, nflip);
     } else if (next) {
-      // waves 1..3: strips 0..3 of block b+1 (wave 1 also takes strip 3),
-      // then the diagonal J block
+#pragma unroll
+      for (int i = 0; i < kRndPerHelper; ++i) {
+        const int g = wave - 1 + 3 * i;
+        if (g < kDB / 4) rnd_next[i] = philox_group(b + 1, g);
+      }
+      // strips 0..3 of block b+1 (wave 1 also takes strip 3), then the
+      // diagonal J block
       for (int sr = wave - 1; sr < 4; sr += 3) {
         v4i acc[4] = {zero, zero, zero, zero};
         strip_product(b + 1, sr, b, acc);
@@ -407,6 +488,13 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
     }
     __syncthreads();
     if (next) {
+      if (wave != 0) {
+#pragma unroll
+        for (int i = 0; i < kRndPerHelper; ++i) {
+          const int g = wave - 1 + 3 * i;
+          if (g < kDB / 4) rnd_s[g][lane] = rnd_next[i];
+        }
+      }
       // block b's own flips, strip `wave` of block b+1
       v4i acc[4] = {zero, zero, zero, zero};
 #pragma unroll

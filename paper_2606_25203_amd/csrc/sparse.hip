@@ -1002,22 +1002,34 @@ __global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D, 
   for (int i = 0; i < 16; ++i) wtot += part_d[i];
   const uint64_t Q = P[R - 1];
   const uint32_t g = st->g_rs;
+  // searches with a fixed number of steps (no divergence; the LDS reads of a
+  // thread's searches overlap): least j with P[j] > y, as the count of
+  // entries <= y; P[R-1] = Q > y
+  const int top = 1 << (31 - __clz(R));  // largest power of two <= R
   int par[kRsMaxR / 1024];
 #pragma unroll
-  for (int i = 0; i < kRsMaxR / 1024; ++i) {
-    const int k = tid + 1024 * i;
-    par[i] = -1;
-    if (k < R) {
-      const u32x4 w = philox10((uint32_t)(k >> 1), g, 0u, kTagResample, a.k0, a.k1);
-      const uint64_t u = (k & 1) ? ((uint64_t)w.c | ((uint64_t)w.d << 32))
-                                 : ((uint64_t)w.a | ((uint64_t)w.b << 32));
-      const uint64_t y = __umul64hi(u, Q);
-      int lo = 0, hi = R - 1;  // least j with P[j] > y; P[R-1] = Q > y
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (P[mid] > y) hi = mid; else lo = mid + 1;
+  for (int i0 = 0; i0 < kRsMaxR / 1024; i0 += 4) {  // four searches at a time
+    uint64_t yv[4];
+#pragma unroll
+    for (int i = i0; i < i0 + 4; ++i) {
+      const int k = tid + 1024 * i;
+      par[i] = -1;
+      yv[i - i0] = 0;
+      if (k < R) {
+        const u32x4 w = philox10((uint32_t)(k >> 1), g, 0u, kTagResample, a.k0, a.k1);
+        const uint64_t u = (k & 1) ? ((uint64_t)w.c | ((uint64_t)w.d << 32))
+                                   : ((uint64_t)w.a | ((uint64_t)w.b << 32));
+        yv[i - i0] = __umul64hi(u, Q);
+        par[i] = 0;
       }
-      par[i] = lo;
+    }
+    if (tid + 1024 * i0 >= R) continue;
+    for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+      for (int i = i0; i < i0 + 4; ++i) {
+        const int nx = par[i] + step;  // candidate count: P[nx - 1] <= y
+        if (par[i] >= 0 && nx <= R && P[nx - 1] <= yv[i - i0]) par[i] = nx;
+      }
     }
   }
   __syncthreads();
@@ -1038,13 +1050,20 @@ __global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D, 
   const int coff = block_excl_scan<int32_t>(local, part_i);
   for (int r = r0; r < r1; ++r) cnt[r] += coff;
   __syncthreads();
-  for (int j = tid; j < R; j += 1024) {
-    int lo = 0, hi = R - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (cnt[mid] > j) hi = mid; else lo = mid + 1;
+#pragma unroll
+  for (int i0 = 0; i0 < kRsMaxR / 1024; i0 += 4) {
+    if (tid + 1024 * i0 >= R) break;
+    int pj[4] = {0, 0, 0, 0};
+    for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = tid + 1024 * (i0 + i), nx = pj[i] + step;
+        if (j < R && nx <= R && cnt[nx - 1] <= j) pj[i] = nx;
+      }
     }
-    a.rs_parent[j] = lo;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (tid + 1024 * (i0 + i) < R) a.rs_parent[tid + 1024 * (i0 + i)] = pj[i];
   }
   if (tid == 0) st->last_lnq = -delta * (double)eref + log(wtot) - log((double)R);
   if (fused && st->do_cluster) {
