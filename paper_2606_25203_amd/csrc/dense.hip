@@ -32,6 +32,7 @@ namespace pamc {
 namespace {
 
 constexpr int kDB = 64;          // spins per sequential block
+static_assert(kDB / 4 == 2 + 7 + 7, "the helper waves' share of the Philox groups assumes 16 groups");
 constexpr int kSB = 1024;        // rows per super-block: one field product, one sequential launch
 constexpr int kGM = 128, kGN = 128, kGK = 64;  // field-product tile: rows x replicas x K stage
 constexpr int kLdsRow = kGK + 16;              // bytes per staged row (padded)
@@ -211,8 +212,8 @@ struct SeqArgs {
 // h_k = gsum_k + sum_{k' < k in block} J_kk' d_k' (d = 2 s_new of flipped
 // spins, packed int8, dot4), x = s h, flip iff u < T[x] (Metropolis also for
 // x <= 0), u from the block's Philox words in LDS; every spin of the block
-// is below n.  sw: the block's 16 spin words (updated in place); d: the
-// block's d words.  Thresholds come from the LDS
+// is below n.  sw: the block's 16 starting spin words; d: the block's d
+// words.  Thresholds come from the LDS
 // table with x clamped to +-Xl; the pass returns whether any lane met
 // |x| > Xl.  It has no branches, so the compiler can move the independent
 // work (Philox, the couplings to earlier groups, LDS reads) into the
@@ -220,7 +221,7 @@ struct SeqArgs {
 template <int RULE>
 __device__ __forceinline__ bool decide_pass(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
                                             const u32x4 (*rnd_s)[64], const uint32_t* thr_s, int32_t Xl,
-                                            uint32_t (&sw)[kDB / 4], int lane, uint32_t (&d)[kDB / 4],
+                                            const uint32_t (&sw)[kDB / 4], int lane, uint32_t (&d)[kDB / 4],
                                             int32_t& dE32, int32_t& nflip) {
   bool wide = false;
 #pragma unroll
@@ -229,41 +230,41 @@ __device__ __forceinline__ bool decide_pass(const uint32_t (*jd)[kDB / 4], const
   for (int g = 0; g < kDB / 4; ++g) {
     const u32x4 rnd = rnd_s[g][lane];
     // couplings to the flips of the earlier groups of the block: four
-    // independent chains, two partial sums each, off the decision chain
+    // independent accumulations, in group order, so only the last one
+    // (the previous group's flips) waits for the decision chain
     int32_t base[4];
     uint32_t jg[4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int k = 4 * g + kk;
-      int32_t p0 = gsum[k][lane], p1 = 0;
+      int32_t p = gsum[k][lane];
 #pragma unroll
-      for (int g2 = 0; g2 + 1 < g; g2 += 2) {
-        p0 = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)d[g2], p0, false);
-        p1 = __builtin_amdgcn_sdot4((int)jd[k][g2 + 1], (int)d[g2 + 1], p1, false);
-      }
-      if (g & 1) p0 = __builtin_amdgcn_sdot4((int)jd[k][g - 1], (int)d[g - 1], p0, false);
-      base[kk] = p0 + p1;
+      for (int g2 = 0; g2 < g; ++g2) p = __builtin_amdgcn_sdot4((int)jd[k][g2], (int)d[g2], p, false);
+      base[kk] = p;
       jg[kk] = jd[k][g];
     }
-    uint32_t w = sw[g];
-    uint32_t dg = 0;
+    // x = s h = s base + J . (s d): the group's flips are kept both as d
+    // (dg) and as -d (ndg), so the chain from one decision to the next is
+    // select, dot4, clamp, table read, compare, select
+    const uint32_t w = sw[g];
+    uint32_t dg = 0, ndg = 0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int32_t h = __builtin_amdgcn_sdot4((int)jg[kk], (int)dg, base[kk], false);
-      const int32_t sm = __builtin_amdgcn_sbfe((int32_t)w, 8u * kk + 7u, 1u);  // 0 for s = +1, -1 for s = -1
-      const int32_t x = (h ^ sm) - sm;                                         // s h
+      const bool neg = (w >> (8 * kk + 7)) & 1u;  // s = -1 (its own spin has not changed yet)
+      const int32_t xb = neg ? -base[kk] : base[kk];
+      const int32_t x = __builtin_amdgcn_sdot4((int)jg[kk], (int)(neg ? ndg : dg), xb, false);
       const int32_t xl = min(max(x, -Xl), Xl);
       wide = wide || x != xl;
       bool flip = pick(rnd, kk) < thr_s[xl + Xl];
       if (RULE == 1) flip = flip || x <= 0;
-      // branch-free update: spin byte 0x01 <-> 0xFF, d = 2 s_new = -2 s
+      // d = 2 s_new = -2 s: byte 0xFE for s = +1, 0x02 for s = -1
+      const uint32_t bp = (neg ? 0x02u : 0xFEu) << (8 * kk), bn = (neg ? 0xFEu : 0x02u) << (8 * kk);
+      dg = flip ? dg | bp : dg;
+      ndg = flip ? ndg | bn : ndg;
       dE32 += flip ? x : 0;
-      w ^= flip ? (0xFEu << (8 * kk)) : 0u;
-      dg |= flip ? (uint32_t)(uint8_t)(int8_t)(sm == 0 ? -2 : 2) << (8 * kk) : 0u;
       nflip += flip ? 1 : 0;
     }
     d[g] = dg;
-    sw[g] = w;
   }
   return wide;
 }
@@ -461,9 +462,12 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
     if (next)
       a_next = *reinterpret_cast<const v4i*>(a.J + (size_t)(rb0 + kDB + 16 * wave + (lane & 15)) * a.np + rb0 +
                                              16 * (lane >> 4));
-    // waves 1..3: the Philox words of block b+1, groups wave-1, wave+2, ..
-    // (held in registers until wave 0 is done with block b's)
-    constexpr int kRndPerHelper = (kDB / 4 + 2) / 3;
+    // waves 1..3: the Philox words of block b+1 (held in registers until
+    // wave 0 is done with block b's); wave 1, which also takes a second
+    // strip, computes 2 of the 16 groups, waves 2 and 3 seven each
+    constexpr int kRndPerHelper = 7;
+    const int rnd_g0 = wave == 1 ? 0 : wave == 2 ? 2 : 9;
+    const int rnd_cnt = wave == 1 ? 2 : 7;
     u32x4 rnd_next[kRndPerHelper];
     if (wave == 0) {
       // the d words go to the super-block's spin changes; the spins
@@ -473,10 +477,8 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
                          lane, dE, nflip);
     } else if (next) {
 #pragma unroll
-      for (int i = 0; i < kRndPerHelper; ++i) {
-        const int g = wave - 1 + 3 * i;
-        if (g < kDB / 4) rnd_next[i] = philox_group(b + 1, g);
-      }
+      for (int i = 0; i < kRndPerHelper; ++i)
+        if (i < rnd_cnt) rnd_next[i] = philox_group(b + 1, rnd_g0 + i);
       // strips 0..3 of block b+1 (wave 1 also takes strip 3), then the
       // diagonal J block
       for (int sr = wave - 1; sr < 4; sr += 3) {
@@ -490,10 +492,8 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
     if (next) {
       if (wave != 0) {
 #pragma unroll
-        for (int i = 0; i < kRndPerHelper; ++i) {
-          const int g = wave - 1 + 3 * i;
-          if (g < kDB / 4) rnd_s[g][lane] = rnd_next[i];
-        }
+        for (int i = 0; i < kRndPerHelper; ++i)
+          if (i < rnd_cnt) rnd_s[rnd_g0 + i][lane] = rnd_next[i];
       }
       // block b's own flips, strip `wave` of block b+1
       v4i acc[4] = {zero, zero, zero, zero};
