@@ -36,6 +36,7 @@ static_assert(kDB / 4 == 2 + 7 + 7, "the helper waves' share of the Philox group
 constexpr int kSB = 1024;        // rows per super-block: one field product, one sequential launch
 constexpr int kGM = 128, kGN = 128, kGK = 64;  // field-product tile: rows x replicas x K stage
 constexpr int kLdsRow = kGK + 16;              // bytes per staged row (padded)
+constexpr int kGStages = 3;                    // field-product K stages in flight per thread
 constexpr int kThrL = 2047;      // half-width of the LDS copy of the threshold table
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -106,12 +107,15 @@ __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J
   __shared__ __attribute__((aligned(16))) int8_t Bs[2][kGN * kLdsRow];
   if (use_state == 1 && !st->active) return;
   const int8_t* __restrict__ S = (use_state ? st->cur : 0) ? S1 : S0;
+  // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so
+  // every output tile of K slice p lands on XCD p % 8 and the slice's J
+  // columns and spins are fetched into that XCD's L2 once, not once per
+  // tile row / column
   const int MT = (rows + kGM - 1) / kGM, NT = (R + kGN - 1) / kGN;
-  int g = blockIdx.x;
-  const int mt = g % MT;
-  g /= MT;
-  const int ntile = g % NT;
-  const int p = g / NT;
+  const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int tile = q % (MT * NT);
+  const int p = (q / (MT * NT)) * 8 + xcd;
+  const int mt = tile % MT, ntile = tile / MT;
   const int k_beg = p * kslice, k_end = min(np, k_beg + kslice);
   if (k_beg >= k_end) return;
   const int t = threadIdx.x, lane = t & 63;
@@ -133,31 +137,37 @@ __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J
     bg[i] = S + (size_t)n * np + col;
     lofs[i] = row * kLdsRow + col;
   }
-  v4i ra[2], rb[2];
+  // kGStages K stages in flight in registers: the loads of stage s + D are
+  // issued while stage s is multiplied, so each load has D - 1 stages of
+  // matrix-core work to arrive in; stage s + 1 goes to the other LDS buffer
+  // at the end of stage s.  In the main loop every load and store is
+  // unconditional (a prefetch past the last stage re-reads the last stage
+  // and is never used), so the compiler waits for exactly the stage it
+  // stores, not for everything in flight.
+  constexpr int D = kGStages;
+  const int nst = (k_end - k_beg) / kGK;
+  v4i ra[D][2], rb[D][2];
+  auto load_stage = [&](int slot, int stage) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    ra[i] = *reinterpret_cast<const v4i*>(ag[i] + k_beg);
-    rb[i] = *reinterpret_cast<const v4i*>(bg[i] + k_beg);
-    *reinterpret_cast<v4i*>(As[0] + lofs[i]) = ra[i];
-    *reinterpret_cast<v4i*>(Bs[0] + lofs[i]) = rb[i];
-  }
-  __syncthreads();
+    for (int i = 0; i < 2; ++i) {
+      ra[slot][i] = *reinterpret_cast<const v4i*>(ag[i] + k_beg + stage * kGK);
+      rb[slot][i] = *reinterpret_cast<const v4i*>(bg[i] + k_beg + stage * kGK);
+    }
+  };
+  auto store_stage = [&](int slot, int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      *reinterpret_cast<v4i*>(As[buf] + lofs[i]) = ra[slot][i];
+      *reinterpret_cast<v4i*>(Bs[buf] + lofs[i]) = rb[slot][i];
+    }
+  };
   v4i acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = zero;
   const int frag = (lane & 15) * kLdsRow + 16 * (lane >> 4);
-  int buf = 0;
-  for (int k0 = k_beg; k0 < k_end; k0 += kGK) {
-    const bool more = k0 + kGK < k_end;
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ra[i] = *reinterpret_cast<const v4i*>(ag[i] + k0 + kGK);
-        rb[i] = *reinterpret_cast<const v4i*>(bg[i] + k0 + kGK);
-      }
-    }
+  auto multiply = [&](int buf) {
     v4i af[4], bf[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -167,16 +177,32 @@ __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[i][j], 0, 0, 0);
-    if (more) {
+      for (int jj = 0; jj < 4; ++jj)
+        acc[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[jj], acc[i][jj], 0, 0, 0);
+  };
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        *reinterpret_cast<v4i*>(As[buf ^ 1] + lofs[i]) = ra[i];
-        *reinterpret_cast<v4i*>(Bs[buf ^ 1] + lofs[i]) = rb[i];
-      }
+  for (int d = 0; d < D; ++d) load_stage(d, min(d, nst - 1));
+  store_stage(0, 0);
+  __syncthreads();
+  int s0 = 0;
+  for (; s0 + D <= nst; s0 += D) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int st_ = s0 + j;  // in LDS buffer st_ & 1; register slot j is free
+      load_stage(j, min(st_ + D, nst - 1));
+      multiply(st_ & 1);
+      store_stage((j + 1) % D, (st_ + 1) & 1);
+      __syncthreads();
     }
-    __syncthreads();
-    buf ^= 1;
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) {  // the last nst % D stages
+    const int st_ = s0 + j;
+    if (st_ < nst) {
+      multiply(st_ & 1);
+      if (st_ + 1 < nst) store_stage((j + 1) % D, (st_ + 1) & 1);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -401,6 +427,18 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
       swl[buf][k][g] = *reinterpret_cast<const uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + rb0 + 4 * g);
     }
   };
+  // new spin words of block bb from its starting words and its d words: a
+  // byte of d is 0 (no flip), 2 or -2, and a flip turns 0x01 <-> 0xFF, i.e.
+  // xor 0xFE.  Same (replica, word) per thread as load_diag, so a thread
+  // reads swl[buf] here before its own load_diag overwrites it.
+  auto store_block = [&](int bb, int buf, int t, int nt) {
+    for (int i = t; i < kDB * kDB / 4; i += nt) {
+      const int k = i / (kDB / 4), g = i % (kDB / 4);
+      const uint32_t dw = *reinterpret_cast<const uint32_t*>(&dsl[k][bb * kDB + 4 * g]);
+      *reinterpret_cast<uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + row0 + bb * kDB + 4 * g) =
+          swl[buf][k][g] ^ ((dw & 0x02020202u) * 0x7Fu);
+    }
+  };
   // matrix-core product over the first 64 nsteps columns of the super-block
   // for the 16-row strip sr of block bb: acc += J[strip rows][cols] . dsl[:, cols]
   // (all of the strip's J fragments are loaded before the first product, so
@@ -470,23 +508,28 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
     const int rnd_cnt = wave == 1 ? 2 : 7;
     u32x4 rnd_next[kRndPerHelper];
     if (wave == 0) {
-      // the d words go to the super-block's spin changes; the spins
-      // themselves are written back once, at the end
+      // the d words go to the super-block's spin changes; the helpers
+      // write the block's spins back while the next block is decided
       decide_block<RULE>(jd[cb], gsum[cb], rnd_s, thr_s, beta, Xl, Xt, swl[cb][lane],
                          reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]), rb0, a.n, gs, (uint32_t)r, a.k0, a.k1,
                          lane, dE, nflip);
-    } else if (next) {
+    } else {
+      // the spins of block b-1 go back to memory (its words are in
+      // swl[cb ^ 1] until load_diag below replaces them)
+      if (b > 0) store_block(b - 1, cb ^ 1, threadIdx.x - 64, 192);
+      if (next) {
 #pragma unroll
-      for (int i = 0; i < kRndPerHelper; ++i)
-        if (i < rnd_cnt) rnd_next[i] = philox_group(b + 1, rnd_g0 + i);
-      // strips 0..3 of block b+1 (wave 1 also takes strip 3), then the
-      // diagonal J block
-      for (int sr = wave - 1; sr < 4; sr += 3) {
-        v4i acc[4] = {zero, zero, zero, zero};
-        strip_product(b + 1, sr, b, acc);
-        add_strip(b + 1, cb ^ 1, sr, acc, true);
+        for (int i = 0; i < kRndPerHelper; ++i)
+          if (i < rnd_cnt) rnd_next[i] = philox_group(b + 1, rnd_g0 + i);
+        // strips 0..3 of block b+1 (wave 1 also takes strip 3), then the
+        // diagonal J block
+        for (int sr = wave - 1; sr < 4; sr += 3) {
+          v4i acc[4] = {zero, zero, zero, zero};
+          strip_product(b + 1, sr, b, acc);
+          add_strip(b + 1, cb ^ 1, sr, acc, true);
+        }
+        load_diag(b + 1, cb ^ 1, threadIdx.x - 64, 192);
       }
-      load_diag(b + 1, cb ^ 1, threadIdx.x - 64, 192);
     }
     __syncthreads();
     if (next) {
@@ -506,16 +549,8 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
     }
     __syncthreads();
   }
-  // write back the super-block's spins, coalesced: a byte of d is 0 (no
-  // flip), 2 or -2, and a flip turns 0x01 <-> 0xFF, i.e. xor 0xFE
-  for (int i = threadIdx.x; i < 64 * nb * (kDB / 4); i += blockDim.x) {
-    const int rep = i / (nb * (kDB / 4)), j = i % (nb * (kDB / 4));
-    const uint32_t dw = *reinterpret_cast<const uint32_t*>(&dsl[rep][4 * j]);
-    if (dw != 0) {
-      uint32_t* sp = reinterpret_cast<uint32_t*>(S + (size_t)(tile * 64 + rep) * a.np + row0) + j;
-      *sp ^= (dw & 0x02020202u) * 0x7Fu;
-    }
-  }
+  // the last block's spins (the others went back while the next was decided)
+  if (nb > 0) store_block(nb - 1, (nb - 1) & 1, threadIdx.x, blockDim.x);
   if (wave != 0) return;
   if (dE != 0)
     __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)dE, __ATOMIC_RELAXED,
@@ -621,12 +656,16 @@ static inline int sb_rows(const pamc_instance* I, int row0) { return std::min(kS
 struct GemmShape {
   int grid, kslice;
 };
+// About 512 work-groups: the K range is cut into P slices of whole stages;
+// the grid covers the slices in groups of 8 (one per XCD; work-groups of
+// slices past the end return at once).
 static inline GemmShape gemm_shape(const pamc_instance* I, int rows) {
   const int tiles = ((rows + kGM - 1) / kGM) * ((I->R + kGN - 1) / kGN);
   const int stages = I->dn_pad / kGK;
   const int P = std::max(1, std::min(stages, (512 + tiles - 1) / tiles));
   const int kslice = ((stages + P - 1) / P) * kGK;
-  return {tiles * ((I->dn_pad + kslice - 1) / kslice), kslice};
+  const int slices = (I->dn_pad + kslice - 1) / kslice;
+  return {tiles * ((slices + 7) / 8) * 8, kslice};
 }
 
 static hipError_t dense_full_energy(pamc_instance* I, int buf) {
