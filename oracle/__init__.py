@@ -17,8 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "pamc_oracle.c")
 
-TAG_INIT, TAG_SWEEP, TAG_RS, TAG_CL, TAG_ORDER, TAG_DENSE = range(6)
+TAG_INIT, TAG_SWEEP, TAG_RS, TAG_CL, TAG_ORDER, TAG_DENSE, TAG_POTTS = range(7)
 HEATBATH, METROPOLIS = 0, 1
+POTTS_SOFTMAX, POTTS_CASCADE = 0, 1
 MAXCUT, ISING = 0, 1
 
 
@@ -93,6 +94,14 @@ def lib():
         L.orc_create_max3cut.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_int32, C.c_uint64,
                                          C.c_int32, C.c_int32, C.c_char_p, C.c_int32]
         L.orc_create_max3cut.restype = P
+        L.orc_create_potts.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_int32, C.c_int32, C.c_uint64,
+                                       C.c_int32, C.c_double, C.c_int32, C.c_char_p, C.c_int32]
+        L.orc_create_potts.restype = P
+        L.orc_potts_energy.argtypes = [P, C.c_int32]
+        L.orc_potts_energy.restype = C.c_int64
+        L.orc_potts_choose.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                       np.ctypeslib.ndpointer(np.int64), np.ctypeslib.ndpointer(np.uint32)]
+        L.orc_potts_choose.restype = C.c_int32
         L.orc_destroy.argtypes = [P]
         for f, rt in (("orc_n", C.c_int32), ("orc_replicas", C.c_int32),
                       ("orc_num_classes", C.c_int32), ("orc_W", C.c_int64), ("orc_X", C.c_int64)):
@@ -152,6 +161,15 @@ def dense_random(n: int, seed: int) -> np.ndarray:
     return J
 
 
+def potts_choose(K: int, rule: int, gamma: float, beta: float, syn, u) -> int:
+    """The label one Potts update picks (Eqs. 8-9 or the cascaded sampler)."""
+    sv = np.zeros(4, np.int64)
+    sv[:K] = np.asarray(syn, np.int64)
+    uv = np.zeros(4, np.uint32)
+    uv[:len(u)] = np.asarray(u, np.uint32)
+    return int(lib().orc_potts_choose(int(K), int(rule), float(gamma), float(beta), sv, uv))
+
+
 def default_schedule(**kw) -> Schedule:
     s = Schedule(beta0=0.1, dbeta=0.02, steps=10, sweeps=1, z_rst=0, augmented=0, resample=1,
                  win_short=25, win_long=40, max_distinct_short=3, max_distinct_long=5,
@@ -205,6 +223,21 @@ class Oracle:
         o = cls(h, "max3cut")
         o.m3_n = int(n)
         return o
+
+    @classmethod
+    def potts(cls, n, row_ptr, col, w, K, replicas, seed, rule=POTTS_SOFTMAX, gamma=1.0, shuffle=True):
+        err = C.create_string_buffer(256)
+        h = lib().orc_create_potts(int(n), np.ascontiguousarray(row_ptr, np.int32),
+                                   np.ascontiguousarray(col, np.int32), np.ascontiguousarray(w, np.int32),
+                                   int(K), replicas, seed, int(rule), float(gamma), int(bool(shuffle)), err, 256)
+        if not h:
+            raise ValueError(err.value.decode())
+        o = cls(h, "potts")
+        o.K = int(K)
+        return o
+
+    def potts_energy(self, r):
+        return lib().orc_potts_energy(self._h, int(r))
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -146,6 +146,9 @@ struct orc {
   /* Max-3-Cut embedding: original graph (input ids) */
   int32_t m3_n;
   int32_t *m3_row_ptr, *m3_col, *m3_w;
+  /* Potts labels (potts_K > 0): s holds labels 0..K-1, h is unused */
+  int32_t potts_K, potts_rule;
+  double potts_gamma;
 };
 
 static void set_err(char* err, int32_t errlen, const char* msg) {
@@ -333,6 +336,73 @@ orc* orc_create_sparse(int32_t n, const int32_t* row_ptr, const int32_t* col,
   return o;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Potts Max-K-Cut (Sec. "Max-3-Cut"; Eqs. 6-9; Supplement, cascaded         */
+/* sampler).  Labels start uniform: label = floor(u K / 2^32) with u the     */
+/* initialization word of the vertex.  E = -sum_{i<j} J_ij (2 delta - 1).    */
+/* ------------------------------------------------------------------------ */
+int64_t orc_potts_energy(const orc* o, int32_t r) {
+  const int8_t* lab = o->s + (size_t)r * o->n;
+  int64_t E = 0;
+  for (int32_t v = 0; v < o->n; ++v)
+    for (int32_t e = o->row_ptr[v]; e < o->row_ptr[v + 1]; ++e) {
+      int32_t j = o->col[e];
+      if (j > v) E -= (int64_t)o->J[e] * (lab[v] == lab[j] ? 1 : -1);
+    }
+  return E;
+}
+
+static void init_potts(orc* o) {
+  int32_t n = o->n;
+  for (int32_t r = 0; r < o->R; ++r) {
+    int8_t* lab = o->s + (size_t)r * n;
+    for (int32_t v = 0; v < n; ++v) {
+      uint32_t out[4];
+      philox(o->seed, (uint32_t)(v >> 2), 0u, (uint32_t)r, ORC_TAG_INIT, out);
+      lab[v] = (int8_t)(((uint64_t)out[v & 3] * (uint64_t)o->potts_K) >> 32);
+    }
+    o->E[r] = orc_potts_energy(o, r);
+    o->family[r] = r;
+  }
+  o->mstar = 0;
+  for (int32_t v = 0; v < n; ++v) o->best[v] = 0;  /* all in one part: cut 0 */
+  o->gs = o->g_rs = o->g_cl = 0;
+}
+
+orc* orc_create_potts(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                      const int32_t* w, int32_t K, int32_t replicas, uint64_t seed,
+                      int32_t potts_rule, double gamma, int32_t shuffle_classes,
+                      char* err, int32_t errlen) {
+  if (replicas <= 0) { set_err(err, errlen, "replicas must be positive"); return NULL; }
+  if (K < 2 || K > 4) { set_err(err, errlen, "K must be 2, 3 or 4"); return NULL; }
+  if (potts_rule == ORC_POTTS_CASCADE && K != 3) { set_err(err, errlen, "the cascade is for K = 3"); return NULL; }
+  if (potts_rule != ORC_POTTS_SOFTMAX && potts_rule != ORC_POTTS_CASCADE) { set_err(err, errlen, "bad rule"); return NULL; }
+  if (!validate_csr(n, row_ptr, col, w, err, errlen)) return NULL;
+  int32_t nnz = row_ptr[n];
+  int32_t* Jin = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nnz + 1));
+  int64_t X = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    int64_t a = 0;
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      Jin[e] = -w[e];
+      a += llabs((long long)w[e]);
+    }
+    if (a > X) X = a;
+  }
+  if (2 * X >= 2147483647LL) { free(Jin); set_err(err, errlen, "local field range exceeds int32"); return NULL; }
+  orc* o = alloc_orc(n, replicas);
+  o->seed = seed;
+  o->rule = ORC_RULE_HEATBATH;
+  o->shuffle = shuffle_classes;
+  o->potts_K = K;
+  o->potts_rule = potts_rule;
+  o->potts_gamma = gamma;
+  build_graph(o, row_ptr, col, Jin, 0);
+  free(Jin);
+  init_potts(o);
+  return o;
+}
+
 orc* orc_create_dense(int32_t n, const int8_t* J, int32_t objective,
                       int32_t replicas, uint64_t seed, int32_t rule,
                       char* err, int32_t errlen) {
@@ -498,6 +568,60 @@ static void flip_spin(orc* o, int32_t r, int32_t v) {
     h[o->col[e]] += 2 * o->J[e] * s[v];
 }
 
+/* One Potts label update (Eqs. 7-9, or the Supplement's cascade).
+ * omega_k = e^{beta (syn_k - max syn)}: the numerators of Eq. 8 scaled by a
+ * common factor, so they do not overflow.
+ *   softmax: P_k = omega_k / sum_m omega_m (sum in label order); the new
+ *     label is the k with the largest P_k - gamma U_k, U_k = u_k / 2^32
+ *     (the lowest k on ties).
+ *   cascade (K = 3, labels alpha, beta, gamma = 0, 1, 2): tanh(Delta_1) =
+ *     (w0 - (w1 + w2)) / (w0 + (w1 + w2)) and tanh(Delta_2) = (w1 - w2) /
+ *     (w1 + w2), since tanh(ln(a/b)/2) = (a - b)/(a + b); the p-bits are
+ *     b = [tanh(Delta) > eta] with eta = u / 2^31 - 1 in [-1, 1); b1 = 1
+ *     picks label 0, else b2 picks label 1 (b2 = 1) or 2. */
+int32_t orc_potts_choose(int32_t K, int32_t potts_rule, double gamma, double beta,
+                         const int64_t* syn, const uint32_t* u) {
+  int64_t m = syn[0];
+  for (int32_t k = 1; k < K; ++k)
+    if (syn[k] > m) m = syn[k];
+  double om[4];
+  for (int32_t k = 0; k < K; ++k) om[k] = orc_pexp(beta * (double)(syn[k] - m));
+  if (potts_rule == ORC_POTTS_CASCADE) {
+    double s12 = om[1] + om[2];
+    double t1 = (om[0] - s12) / (om[0] + s12);
+    double eta1 = (double)u[0] * (1.0 / 2147483648.0) - 1.0;
+    if (t1 > eta1) return 0;
+    double t2 = (om[1] - om[2]) / s12;
+    double eta2 = (double)u[1] * (1.0 / 2147483648.0) - 1.0;
+    return t2 > eta2 ? 1 : 2;
+  }
+  double S = 0.0;
+  for (int32_t k = 0; k < K; ++k) S += om[k];
+  int32_t best = 0;
+  double bs = om[0] / S - gamma * ((double)u[0] * (1.0 / 4294967296.0));
+  for (int32_t k = 1; k < K; ++k) {
+    double sc = om[k] / S - gamma * ((double)u[k] * (1.0 / 4294967296.0));
+    if (sc > bs) { bs = sc; best = k; }
+  }
+  return best;
+}
+
+/* Potts update of vertex v in replica r: the K-label field (Eq. 7), the
+ * new label, and the Eq. 6 energy change -2 (syn_new - syn_old). */
+static void potts_visit(orc* o, int32_t r, int32_t v, double beta) {
+  int8_t* lab = o->s + (size_t)r * o->n;
+  int64_t syn[4] = {0, 0, 0, 0};
+  for (int32_t e = o->row_ptr[v]; e < o->row_ptr[v + 1]; ++e) syn[lab[o->col[e]]] += o->J[e];
+  uint32_t u[4];
+  philox(o->seed, (uint32_t)v, o->gs, (uint32_t)r, ORC_TAG_POTTS, u);
+  int32_t old = lab[v];
+  int32_t nw = orc_potts_choose(o->potts_K, o->potts_rule, o->potts_gamma, beta, syn, u);
+  if (nw != old) {
+    o->E[r] += -2 * (syn[nw] - syn[old]);
+    lab[v] = (int8_t)nw;
+  }
+}
+
 void orc_sweep(orc* o, double beta, int32_t nsweeps) {
   int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)o->ncls);
   for (int32_t sw = 0; sw < nsweeps; ++sw) {
@@ -505,6 +629,10 @@ void orc_sweep(orc* o, double beta, int32_t nsweeps) {
     for (int32_t ci = 0; ci < o->ncls; ++ci) {
       int32_t c = order[ci];
       for (int32_t v = o->class_ptr[c]; v < o->class_ptr[c + 1]; ++v) {
+        if (o->potts_K) {
+          for (int32_t r = 0; r < o->R; ++r) potts_visit(o, r, v, beta);
+          continue;
+        }
         for (int32_t r = 0; r < o->R; ++r) {
           int64_t x = (int64_t)o->s[(size_t)r * o->n + v] * o->h[(size_t)r * o->n + v];
           uint32_t out[4];
@@ -530,8 +658,11 @@ void orc_sweep(orc* o, double beta, int32_t nsweeps) {
 /* arithmetic) and quantised to q_j = floor(w_j 2^48) so that the draw is   */
 /* an exact integer computation; children are ordered by parent.            */
 /* ------------------------------------------------------------------------ */
-double orc_resample(orc* o, double delta, int32_t* parents_out) {
+double orc_resample(orc* o, double delta_in, int32_t* parents_out) {
   int32_t R = o->R, n = o->n;
+  /* Potts labels: the update of Eq. 8 at beta leaves e^{-(beta/2) E}
+   * invariant for the Eq. 6 energy, so the weights use Delta/2. */
+  double delta = o->potts_K ? 0.5 * delta_in : delta_in;
   int64_t Eref = o->E[0];
   for (int32_t r = 1; r < R; ++r) {
     if (delta >= 0 ? (o->E[r] < Eref) : (o->E[r] > Eref)) Eref = o->E[r];
@@ -611,6 +742,7 @@ static int cmp_eslot(const void* a, const void* b) {
 }
 
 int32_t orc_cluster(orc* o, int32_t n_top, int32_t mis_trials, int32_t* chosen_sizes) {
+  if (o->potts_K) return 0;  /* defined for Ising spins only */
   int32_t R = o->R, n = o->n;
   if (n_top > R) n_top = R;
   if (n_top < 0) n_top = 0;
@@ -790,7 +922,7 @@ void orc_anneal(orc* o, const orc_schedule* s, orc_result* res, orc_trace* tr) {
       lnq = orc_resample(o, c.delta, NULL);
       res->sum_lnq += lnq;
       ev |= 1;
-      if (s->augmented && c.enable && c.cooldown == 0) {
+      if (s->augmented && c.enable && c.cooldown == 0 && !o->potts_K) {
         orc_cluster(o, s->n_top, s->mis_trials, NULL);
         c.enable = 0;
         c.cooldown = s->tau;

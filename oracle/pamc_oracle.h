@@ -35,7 +35,12 @@ extern "C" {
 
 /* RNG stream tags (fourth Philox counter word). */
 enum { ORC_TAG_INIT = 0, ORC_TAG_SWEEP = 1, ORC_TAG_RS = 2, ORC_TAG_CL = 3,
-       ORC_TAG_ORDER = 4, ORC_TAG_DENSE = 5 };
+       ORC_TAG_ORDER = 4, ORC_TAG_DENSE = 5, ORC_TAG_POTTS = 6 };
+
+/* Potts label updates (Sec. "Max-3-Cut"): softmax probabilities perturbed by
+ * gamma-scaled uniform noise, then argmax (Eqs. 8-9); or the cascade of two
+ * binary p-bits for K = 3 (Supplement, cascaded sampler). */
+enum { ORC_POTTS_SOFTMAX = 0, ORC_POTTS_CASCADE = 1 };
 
 enum { ORC_RULE_HEATBATH = 0, ORC_RULE_METROPOLIS = 1 };
 enum { ORC_OBJ_MAXCUT = 0, ORC_OBJ_ISING = 1 };
@@ -97,6 +102,21 @@ orc* orc_create_max3cut(int32_t n, const int32_t* row_ptr, const int32_t* col,
                         const int32_t* w, int32_t replicas, uint64_t seed,
                         int32_t rule, int32_t shuffle_classes,
                         char* err, int32_t errlen);
+/* Max-K-Cut with K-state Potts labels (Sec. "Max-3-Cut", Eqs. 6-9; the
+ * cascaded K = 3 sampler of the Supplement), 2 <= K <= 4.  J = -w; the
+ * energy is Eq. 6, E = -sum_{edges} J_ij (2 delta(s_i, s_j) - 1), so the
+ * K-cut is (W - E)/2.  A label update draws P(k) from Eq. 8 with the
+ * K-label field syn_k(i) = sum_j J_ij delta(s_j, k) at the step's beta. */
+orc* orc_create_potts(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                      const int32_t* w, int32_t K, int32_t replicas, uint64_t seed,
+                      int32_t potts_rule, double gamma, int32_t shuffle_classes,
+                      char* err, int32_t errlen);
+/* Eq. 6 energy of replica r recomputed from its labels. */
+int64_t orc_potts_energy(const orc* o, int32_t r);
+/* The label a Potts update picks for K-label field syn (length K) and four
+ * uniform words u, at inverse temperature beta. */
+int32_t orc_potts_choose(int32_t K, int32_t potts_rule, double gamma, double beta,
+                         const int64_t* syn, const uint32_t* u);
 void orc_destroy(orc* o);
 
 /* Instance facts. */

@@ -540,3 +540,127 @@ def test_invalid_inputs_rejected(oracle_lib):
     w[0] = 5
     with pytest.raises(ValueError):
         oracle_lib.Oracle.sparse(g.n, g.row_ptr, g.col, w, 64, 1)
+
+
+# ----------------------------------------------------------------- Potts labels
+# Potts Max-K-Cut (Sec. "Max-3-Cut", Eqs. 6-9; Supplement, cascaded sampler).
+def graph_edges(g):
+    return [(i, int(g.col[e]), int(g.w[e])) for i in range(g.n)
+            for e in range(g.row_ptr[i], g.row_ptr[i + 1]) if g.col[e] > i]
+
+
+def k_cut(edges, lab):
+    return sum(w for i, j, w in edges if lab[i] != lab[j])
+
+
+@pytest.mark.parametrize("K,rule", [(2, 0), (3, 0), (4, 0), (3, 1)])
+def test_potts_energy_and_cut_identities(oracle_lib, K, rule):
+    # tracked energy = Eq. 6 recomputed from labels, and (W - E)/2 = the
+    # weight of the edges whose ends carry different labels
+    g = synth.random_graph(40, 90, 3, weights="pm1")
+    o = oracle_lib.Oracle.potts(g.n, g.row_ptr, g.col, g.w, K, 64, 11, rule=rule)
+    edges = graph_edges(g)
+    for beta, k in [(0.0, 1), (0.7, 3), (2.0, 2)]:
+        o.sweep(beta, k)
+        o.resample(0.05)
+        lab, _, E, _ = o.state()
+        assert lab.min() >= 0 and lab.max() < K
+        for r in range(0, 64, 7):
+            assert E[r] == o.potts_energy(r)
+            assert (o.W - E[r]) // 2 == k_cut(edges, lab[r])
+            assert (o.W - E[r]) % 2 == 0
+
+
+def test_potts_cascade_samples_the_gibbs_conditional(oracle_lib):
+    # the cascade's two p-bits reproduce P(k) = e^{beta syn_k} / sum_m
+    # e^{beta syn_m} (the Supplement's claim), checked against that textbook
+    # softmax with independent uniform words
+    rng = np.random.default_rng(5)
+    for syn, beta in [((3, -1, 2), 0.4), ((0, 0, 0), 1.0), ((-5, 4, 4), 0.3), ((7, -7, 0), 0.05)]:
+        p = np.exp(beta * np.array(syn, float))
+        p /= p.sum()
+        N = 60000
+        u = rng.integers(0, 2**32, size=(N, 2), dtype=np.uint64).astype(np.uint32)
+        cnt = np.zeros(3)
+        for i in range(N):
+            cnt[oracle_lib.potts_choose(3, 1, 0.0, beta, syn, u[i])] += 1
+        emp = cnt / N
+        assert np.all(np.abs(emp - p) < 5 * np.sqrt(p * (1 - p) / N) + 1e-9), (syn, emp, p)
+
+
+def test_potts_softmax_argmax_two_labels_closed_form(oracle_lib):
+    # K = 2: label 1 wins iff U0 - U1 > (P0 - P1)/gamma = c, and U0 - U1 has
+    # the triangular density on [-1, 1], so P(1) = (1 - c)^2 / 2 for c >= 0
+    # and 1 - (1 + c)^2 / 2 for c < 0
+    rng = np.random.default_rng(9)
+    for syn, beta, gamma in [((2, -1), 0.3, 1.0), ((-1, 3), 0.2, 0.5), ((0, 0), 1.0, 1.0), ((4, 0), 0.1, 2.0)]:
+        e = np.exp(beta * np.array(syn, float))
+        P = e / e.sum()
+        c = (P[0] - P[1]) / gamma
+        p1 = (1 - c) ** 2 / 2 if c >= 0 else 1 - (1 + c) ** 2 / 2
+        p1 = min(max(p1, 0.0), 1.0)
+        N = 40000
+        u = rng.integers(0, 2**32, size=(N, 2), dtype=np.uint64).astype(np.uint32)
+        ones = sum(oracle_lib.potts_choose(2, 0, gamma, beta, syn, u[i]) for i in range(N))
+        assert abs(ones / N - p1) < 5 * math.sqrt(max(p1 * (1 - p1), 1e-6) / N) + 1e-9, (syn, ones / N, p1)
+    # gamma = 0: the most probable label, the lowest on ties
+    assert oracle_lib.potts_choose(3, 0, 0.0, 1.0, (1, 5, 5), (7, 8, 9)) == 1
+    assert oracle_lib.potts_choose(4, 0, 0.0, 1.0, (2, 2, 2, 2), (9, 1, 5, 3)) == 0
+
+
+def test_potts_cascade_boltzmann_histogram_by_enumeration(oracle_lib):
+    # sweeps of the cascade leave P(labels) ~ e^{beta sum_edges J delta}
+    # = e^{-(beta/2) E} (E of Eq. 6) invariant: compare the replica histogram
+    # with the exact law over all 3^5 labelings
+    g = synth.random_graph(5, 7, 4, weights="pm1")
+    beta = 0.8
+    o = oracle_lib.Oracle.potts(g.n, g.row_ptr, g.col, g.w, 3, 2048, 23, rule=1)
+    o.sweep(beta, 30)
+    edges = graph_edges(g)
+    states = list(itertools.product(range(3), repeat=g.n))
+    index = {s: i for i, s in enumerate(states)}
+    logw = np.array([beta * sum(-w for i, j, w in edges if s[i] == s[j]) for s in states])
+    p_exact = np.exp(logw - logw.max())
+    p_exact /= p_exact.sum()
+    cnt = np.zeros(len(states))
+    for _ in range(60):
+        o.sweep(beta, 1)
+        lab = o.state()[0]
+        for row in lab:
+            cnt[index[tuple(int(x) for x in row)]] += 1
+    p_emp = cnt / cnt.sum()
+    tv = 0.5 * np.abs(p_exact - p_emp).sum()
+    assert tv < 0.03, tv
+
+
+def test_potts_resample_uses_half_delta(oracle_lib):
+    # reading: Eq. 8 at beta samples e^{-(beta/2) E}, so Eq. 2's ln Q uses
+    # Delta/2 with the Eq. 6 energy
+    g = synth.random_graph(20, 40, 2)
+    o = oracle_lib.Oracle.potts(g.n, g.row_ptr, g.col, g.w, 3, 256, 3)
+    o.sweep(1.0, 2)
+    E = o.state()[2].astype(float)
+    for delta in (0.1, -0.04):
+        a = -0.5 * delta * E
+        lnq = a.max() + math.log(np.exp(a - a.max()).sum()) - math.log(len(E))
+        got = o.resample(delta)
+        assert abs(got - lnq) <= 1e-12 * max(1.0, abs(lnq))
+        E = o.state()[2].astype(float)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_potts_anneal_reaches_brute_force_max3cut(oracle_lib, rule):
+    g = synth.random_graph(8, 16, 6)
+    best = brute_max3cut(g)
+    o = oracle_lib.Oracle.potts(g.n, g.row_ptr, g.col, g.w, 3, 128, 5, rule=rule)
+    res = o.anneal(oracle_lib.default_schedule(beta0=0.2, dbeta=0.1, steps=40, sweeps=4))
+    assert res.best_cut == best
+    cut, _, lab = o.best()
+    assert k_cut(graph_edges(g), lab) == best
+
+
+def test_potts_invalid_inputs(oracle_lib):
+    g = synth.random_graph(10, 20, 1)
+    for K, rule in [(1, 0), (5, 0), (2, 1), (4, 1), (3, 2)]:
+        with pytest.raises(ValueError):
+            oracle_lib.Oracle.potts(g.n, g.row_ptr, g.col, g.w, K, 64, 1, rule=rule)
