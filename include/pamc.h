@@ -14,7 +14,8 @@
  *  - Every call returns pamc_status; nothing throws or aborts across the ABI.
  *    On failure pamc_last_error() (thread-local) describes the cause.
  *  - Vertex ids at the ABI are the caller's ids (0..n-1).  Spin arrays are
- *    int8 in {-1,+1}; populations are slot-major [R][n].
+ *    int8 in {-1,+1} (Potts instances: labels 0..K-1); populations are
+ *    slot-major [R][n].
  *  - Input arrays are copied; the caller keeps ownership.  The instance owns
  *    its device memory (hipMalloc on cfg->device) until pamc_destroy_instance.
  *  - One host thread at a time per instance; distinct instances may be used
@@ -119,6 +120,36 @@ pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, cons
                                          const int32_t* w, const pamc_config* cfg,
                                          pamc_instance** out);
 
+/* Max-K-Cut with K-state Potts labels, the paper's own formulation (Sec.
+ * "Max-3-Cut", Eqs. 6-9): one label per vertex, no auxiliary spins.  The
+ * graph is given as for pamc_create_instance_csr (host memory, nonzero
+ * symmetric weights w, J = -w).  Wherever the ABI returns spins
+ * (pamc_best, pamc_get_state) it returns the labels, int8 in 0..K-1; fields
+ * are returned as 0.  The energy is Eq. 6,
+ * E = -sum_{i<j} J_ij (2 delta(s_i, s_j) - 1) = W - 2 cut, so the reported
+ * cut is the weight of the edges whose ends carry different labels.
+ * Visiting vertex i with the K-label field syn_k(i) = sum_j J_ij delta(s_j,
+ * k) (Eq. 7) and omega_k = e^{beta (syn_k - max_m syn_m)} (binary64), the new
+ * label is
+ *   PAMC_POTTS_SOFTMAX: the k with the largest P_k - gamma U_k, P_k =
+ *     omega_k / sum_m omega_m (Eqs. 8-9), U_k = u_k / 2^32, lowest k on ties;
+ *   PAMC_POTTS_CASCADE (K = 3 only): the two binary p-bits of the cascaded
+ *     sampler (Supplement): label 0 if tanh(Delta_1) = (omega_0 - (omega_1 +
+ *     omega_2)) / (omega_0 + (omega_1 + omega_2)) exceeds eta_1 = u_0/2^31 - 1,
+ *     else label 1 if tanh(Delta_2) = (omega_1 - omega_2) / (omega_1 +
+ *     omega_2) exceeds eta_2 = u_1/2^31 - 1, else label 2 (exact Gibbs).
+ * u_0..u_3 are the words of Philox(vertex, sweep, replica, 6).  This update
+ * at beta leaves e^{-(beta/2) E} invariant, so resampling weighs replicas by
+ * e^{-(Delta/2) (E - E_ref)} (ln Q likewise).  Cluster moves and the pair
+ * distance are not defined for labels (PAMC_ERR_UNSUPPORTED; pamc_anneal
+ * makes no moves, its controller still reheats).  cfg->rule is ignored.
+ * Errors: K < 2, an unknown rule, the cascade with K != 3, gamma < 0 or not
+ * finite: PAMC_ERR_INVALID_ARG; K > 4: PAMC_ERR_UNSUPPORTED. */
+typedef enum { PAMC_POTTS_SOFTMAX = 0, PAMC_POTTS_CASCADE = 1 } pamc_potts_rule;
+pamc_status pamc_create_instance_potts(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                       const int32_t* w, int32_t K, int32_t potts_rule, double gamma,
+                                       const pamc_config* cfg, pamc_instance** out);
+
 void pamc_destroy_instance(pamc_instance* inst);
 
 /* Re-draws the population from a new Philox key (Algorithm 1,
@@ -135,7 +166,8 @@ typedef struct {
   int32_t n, replicas, num_classes, dense, pull;
   int64_t nnz, W, X; /* X = max_v sum_j |J_vj| */
   int64_t device_bytes;
-  int32_t tiles_per_wave, quads_per_wave, coupling_mode, reserved;
+  int32_t tiles_per_wave, quads_per_wave, coupling_mode;
+  int32_t potts_K; /* labels per vertex of a Potts instance, else 0 */
 } pamc_info;
 pamc_status pamc_get_info(const pamc_instance* inst, pamc_info* out);
 

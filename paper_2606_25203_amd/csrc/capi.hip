@@ -67,7 +67,7 @@ void free_instance(pamc_instance* I) {
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
                   I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
                   I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Ed[0], I->Ed[1],
-                  I->flip_ctr, I->H_scratch};
+                  I->flip_ctr, I->H_scratch, I->ptab};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (I->pinned) hipHostFree(I->pinned);
@@ -169,6 +169,7 @@ pamc::Batch* self_batch(pamc_instance* I, hipError_t* err) {
 // padded CSR, W, X and the choice of sweep kernel.  Jin: couplings J in
 // caller ids (already validated).  T: replica tiles.
 struct HostSparse {
+  int32_t potts_K = 0;  // set by the caller for Potts labels (no fields, plain CSR only)
   int32_t n = 0, np = 0, nq = 0, ncls = 0, max_class_quads = 0;
   int32_t small_j = 0, jmode = 0, pull = 0, tpw = 1, qpw = 1;
   int64_t nnz = 0, W = 0, X = 0;
@@ -253,7 +254,9 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   // (pull); both give the same integer fields and the same trajectory.
   // Gathering a hub's field serialises one wavefront per tile over all of
   // its neighbours; incremental fields spread that work over the flips.
-  if (flags & PAMC_FLAG_FIELDS_PUSH)
+  if (h.potts_K)
+    h.pull = 1;  // Potts labels: K-label fields gathered at visit time
+  else if (flags & PAMC_FLAG_FIELDS_PUSH)
     h.pull = 0;
   else if (flags & PAMC_FLAG_FIELDS_PULL)
     h.pull = 1;
@@ -263,7 +266,7 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   // byte offsets of the neighbour's spin word in a tile (plus its byte index
   // in modes 0 and 1), couplings in the kernel's mode (mode 2: the int8
   // coupling in the neighbour's byte).
-  if (h.pull) {
+  if (h.pull && !h.potts_K) {
     h.grow.assign(n + 1, 0);
     for (int32_t iv = 0; iv < n; ++iv) h.grow[iv + 1] = h.grow[iv] + ((h.rp2[iv + 1] - h.rp2[iv] + 3) & ~3);
     h.gcol.assign(std::max(h.grow[n], 4), 0);
@@ -283,7 +286,7 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   const int64_t W4 = pamc::sweep_waves();
   const int64_t q1 = (h.max_class_quads + W4 - 1) / W4;
   h.tpw = 1;
-  if (h.pull)
+  if (h.pull && !h.potts_K)
     for (int t : {4, 2})
       if (T % t == 0 && (T / t) * q1 >= 1024) {
         h.tpw = t;
@@ -291,7 +294,7 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
       }
   if (const char* e = getenv("PAMC_TPW")) {
     const int t = atoi(e);
-    if ((t == 1 || t == 2 || t == 4) && T % t == 0) h.tpw = t;
+    if ((t == 1 || t == 2 || t == 4) && T % t == 0 && !h.potts_K) h.tpw = t;
   }
   h.qpw = 1;
   for (int q : {4, 2})
@@ -330,7 +333,8 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(dalloc(I, &I->g.row_ptr, n + 1), "alloc");
   HIP_TRY(dalloc(I, &I->g.col, nnz), "alloc");
   HIP_TRY(dalloc(I, &I->g.J, nnz), "alloc");
-  if (I->pull) {
+  const bool gathered = I->pull && !I->potts_K;
+  if (gathered) {
     HIP_TRY(dalloc(I, &I->g.grow, n + 1), "alloc");
     HIP_TRY(dalloc(I, &I->g.gcol, h.gcol.size()), "alloc");
     HIP_TRY(dalloc(I, &I->g.gJ, h.gJ.size()), "alloc");
@@ -345,7 +349,9 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(dalloc(I, &I->best, I->np), "alloc");
   HIP_TRY(dalloc(I, &I->to_internal_dev, n), "alloc");
   HIP_TRY(dalloc(I, &I->st, 1), "alloc");
-  HIP_TRY(dalloc(I, &I->thr, 2 * I->X + 1), "alloc");
+  if (I->potts_K)
+    HIP_TRY(dalloc(I, &I->ptab, 2 * I->X + 1), "alloc");
+  HIP_TRY(dalloc(I, &I->thr, I->potts_K ? 1 : 2 * I->X + 1), "alloc");
   I->order_cap = 64;
   HIP_TRY(dalloc(I, &I->order, (size_t)I->order_cap * ncls), "alloc");
   HIP_TRY(dalloc(I, &I->rs_parent, I->R), "alloc");
@@ -359,7 +365,7 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(hipMemcpyAsync(I->g.row_ptr, h.rp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->g.col, h.col2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->g.J, h.J2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, I->stream), "upload");
-  if (I->pull) {
+  if (gathered) {
     HIP_TRY(hipMemcpyAsync(I->g.grow, h.grow.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, I->stream), "upload");
     HIP_TRY(hipMemcpyAsync(I->g.gcol, h.gcol.data(), sizeof(int32_t) * h.gcol.size(), hipMemcpyHostToDevice, I->stream), "upload");
     HIP_TRY(hipMemcpyAsync(I->g.gJ, h.gJ.data(), sizeof(int32_t) * h.gJ.size(), hipMemcpyHostToDevice, I->stream), "upload");
@@ -377,6 +383,7 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
 pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const int32_t* col,
                          const std::vector<int32_t>& Jin) {
   HostSparse h;
+  h.potts_K = I->potts_K;
   pamc_status st = prepare_sparse(h, n, rp, col, Jin, I->flags, I->T);
   if (st) return st;
   return upload_sparse(I, h);
@@ -606,6 +613,39 @@ pamc_status pamc_create_instance_csr(int32_t n, const int32_t* row_ptr, const in
   return PAMC_OK;
 }
 
+pamc_status pamc_create_instance_potts(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                       const int32_t* w, int32_t K, int32_t potts_rule, double gamma,
+                                       const pamc_config* cfg, pamc_instance** out) {
+  if (!out) return fail(PAMC_ERR_INVALID_ARG, "NULL out");
+  *out = nullptr;
+  pamc_status st = check_cfg(cfg);
+  if (st) return st;
+  if (K < 2) return fail(PAMC_ERR_INVALID_ARG, "K must be at least 2");
+  if (K > 4) return fail(PAMC_ERR_UNSUPPORTED, "K > 4");
+  if (potts_rule != PAMC_POTTS_SOFTMAX && potts_rule != PAMC_POTTS_CASCADE)
+    return fail(PAMC_ERR_INVALID_ARG, "unknown Potts rule");
+  if (potts_rule == PAMC_POTTS_CASCADE && K != 3) return fail(PAMC_ERR_INVALID_ARG, "the cascade is for K = 3");
+  if (!std::isfinite(gamma) || gamma < 0) return fail(PAMC_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+  if (n <= 0 || !row_ptr) return fail(PAMC_ERR_INVALID_ARG, "n must be positive");
+  st = validate_csr(n, row_ptr, col, w, false);
+  if (st) return st;
+  std::vector<int32_t> J(std::max(row_ptr[n], 1));
+  for (int32_t e = 0; e < row_ptr[n]; ++e) J[e] = -w[e];
+  pamc_instance* I = new (std::nothrow) pamc_instance();
+  if (!I) return fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
+  I->potts_K = K;
+  I->potts_rule = potts_rule;
+  I->potts_gamma = gamma;
+  st = open_device(I, cfg);
+  if (!st) st = build_sparse(I, n, row_ptr, col, J);
+  if (st) {
+    free_instance(I);
+    return st;
+  }
+  *out = I;
+  return PAMC_OK;
+}
+
 pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, const int32_t* col,
                                          const int32_t* w, const pamc_config* cfg,
                                          pamc_instance** out) {
@@ -793,13 +833,14 @@ pamc_status pamc_get_info(const pamc_instance* I, pamc_info* out) {
   out->tiles_per_wave = I->tpw;
   out->quads_per_wave = I->qpw;
   out->coupling_mode = I->jmode;
-  out->reserved = 0;
+  out->potts_K = I->potts_K;
   return PAMC_OK;
 }
 
 pamc_status pamc_sweep(pamc_instance* I, double beta, int32_t nsweeps) {
   if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
   if (nsweeps < 0 || !std::isfinite(beta)) return fail(PAMC_ERR_INVALID_ARG, "bad sweep arguments");
+  if (I->potts_K && beta < 0) return fail(PAMC_ERR_INVALID_ARG, "negative beta on Potts labels");
   if (nsweeps == 0) return PAMC_OK;
   hipSetDevice(I->device);
   SELF_BATCH(I, b);
@@ -834,6 +875,7 @@ pamc_status pamc_cluster_move(pamc_instance* I, int32_t n_top, int32_t mis_trial
   if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
   if (n_top < 0 || mis_trials < 0) return fail(PAMC_ERR_INVALID_ARG, "negative argument");
   if (I->dense) return fail(PAMC_ERR_UNSUPPORTED, "cluster moves on dense instances");
+  if (I->potts_K) return fail(PAMC_ERR_UNSUPPORTED, "cluster moves on Potts labels");
   hipSetDevice(I->device);
   pamc_status st = ensure_cluster_scratch(I, n_top, mis_trials);
   if (st) return st;
@@ -1082,6 +1124,7 @@ pamc_status pamc_max3cut_decode(pamc_instance* I, const int8_t* spins, int32_t* 
 pamc_status pamc_pair_distance(pamc_instance* I, double* mean) {
   if (!I || !mean) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
   if (I->dense) return fail(PAMC_ERR_UNSUPPORTED, "pair distance on dense instances");
+  if (I->potts_K) return fail(PAMC_ERR_UNSUPPORTED, "pair distance on Potts labels");
   hipSetDevice(I->device);
   double* d = (double*)(I->flip_ctr + 300);
   HIP_TRY(pamc::launch_pair_distance(I, d), "pair distance");

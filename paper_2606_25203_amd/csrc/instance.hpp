@@ -67,6 +67,9 @@ struct pamc_instance {
   int32_t* to_internal_dev = nullptr;  // [n] caller id -> internal id
   pamc::RunState* st = nullptr;
   uint32_t* thr = nullptr;  // threshold table, 2X+1 entries
+  int32_t potts_K = 0, potts_rule = 0;  // Potts labels (2 <= K <= 4), else 0
+  double potts_gamma = 0.0;
+  double* ptab = nullptr;   // Potts weight table, 2X+1 entries
   int32_t* order = nullptr; // [order_cap][ncls]
   int32_t order_cap = 0;
   // resampling scratch
@@ -152,6 +155,10 @@ struct Desc {
   uint64_t* tr_time;
   int64_t* flip_ctr;      // null unless profiling
   const int8_t *D0, *D1;  // dense instances: replica-major spins [R][np]
+  double* ptab;           // Potts labels: e^{-beta d}, d = 0..table_x
+  double potts_gamma;     // softmax noise amplitude (Eq. 9)
+  int32_t potts_K;        // 0: Ising spins; 2..4: Potts labels
+  int32_t potts_rule;     // 0 softmax-perturbed argmax, 1 cascaded p-bits (K = 3)
   int64_t W, X;
   int32_t n, np, nq, R, T, ncls, rule, pull, dense, shuffle, tr_cap, order_cap, qpw;
   uint32_t k0, k1;
@@ -160,7 +167,7 @@ struct Desc {
 // A set of instances advanced by the same launches.  Grid kernels read a map
 // of (instance << 32 | local block) words; one map per launch kind.
 struct Batch {
-  static constexpr int kGroups = 19;  // sweep kernel variants
+  static constexpr int kGroups = 22;  // sweep kernel variants (19 spin, 3 Potts label)
   static int group_of(const pamc_instance* I);
   struct Launch {
     uint64_t* map = nullptr;

@@ -10,7 +10,7 @@ namespace pamc {
 
 // Stream tags carried in the fourth Philox counter word.
 enum : uint32_t { kTagInit = 0, kTagSweep = 1, kTagResample = 2, kTagCluster = 3,
-                  kTagOrder = 4, kTagDense = 5 };
+                  kTagOrder = 4, kTagDense = 5, kTagPotts = 6 };
 
 // Pointers in the global address space.  Device pointers read from a
 // descriptor table are generic to the compiler; casting them back lets it
@@ -127,6 +127,16 @@ __device__ inline uint32_t flip_threshold(double beta, int rule, long long x) {
 // Half-width of the threshold table: beyond |x| = ceil(12.5/|beta|) + 1 the
 // heat-bath and Metropolis thresholds are saturated (e^{25} > 2^32), so
 // clamping x into the table is exact.
+// Potts labels: entries d = 0..D of the table e^{-beta d} (d = max syn -
+// syn_k, at most 2X).  Beyond D (only when D < 2X) the value is exactly 0:
+// beta d >= 746 + beta exceeds the point below which the exponential
+// returns 0.
+__host__ __device__ inline int64_t potts_table_last(double beta, int64_t X) {
+  if (!(beta > 0)) return 2 * X;
+  const double lim = 746.0 / beta;
+  return lim >= (double)(2 * X) ? 2 * X : (int64_t)lim + 1;
+}
+
 __host__ __device__ inline int64_t table_halfwidth(double beta, int64_t X) {
   const double b = beta < 0 ? -beta : beta;
   if (b < 1e-300) return X < 1 ? X : 1;

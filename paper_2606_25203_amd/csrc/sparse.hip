@@ -375,6 +375,155 @@ __global__ void __launch_bounds__(256) k_sweep_push(const Desc* __restrict__ D,
 }
 
 // ---------------------------------------------------------------------------
+// Potts labels (Sec. "Max-3-Cut"; Eqs. 6-9; the cascaded K = 3 sampler of the
+// Supplement).  A label word holds the labels (bytes 0..K-1) of the four
+// vertices of a quad, like a spin word.  Visiting vertex v of replica r:
+// the K-label field syn_k = sum_j J_vj [s_j = k] over the CSR row (Eq. 7),
+// omega_k = e^{beta (syn_k - max syn)} from the step's table, then
+//   softmax: the k with the largest omega_k / sum omega - gamma u_k 2^-32
+//     (Eqs. 8-9, lowest k on ties);
+//   cascade: label 0 iff tanh(Delta_1) = (w0 - (w1 + w2)) / (w0 + (w1 + w2))
+//     exceeds eta_1 = u_0 2^-31 - 1, else label 1 iff tanh(Delta_2) =
+//     (w1 - w2) / (w1 + w2) exceeds eta_2 = u_1 2^-31 - 1, else 2;
+// u = Philox(v, sweep, r, POTTS).  Every operation is a correctly rounded
+// binary64 operation in a fixed order (no contraction), so the choice is
+// the same wherever it is computed.  The energy (Eq. 6) changes by
+// -2 (syn_new - syn_old).
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ int32_t syn_of(const int32_t (&syn)[K], int k) {
+  int32_t x = syn[0];
+#pragma unroll
+  for (int i = 1; i < K; ++i) x = k == i ? syn[i] : x;
+  return x;
+}
+
+template <int K>
+__device__ __forceinline__ int potts_choose(const int32_t (&syn)[K], const u32x4& u, const double* __restrict__ tab,
+                                            int32_t last, int rule, double gamma) {
+  int32_t m = syn[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) m = max(m, syn[k]);
+  double om[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int32_t dd = m - syn[k];
+    om[k] = dd <= last ? tab[dd] : 0.0;
+  }
+  if constexpr (K == 3) {
+    if (rule == 1) {
+      const double s12 = om[1] + om[2];
+      const double t1 = (om[0] - s12) / (om[0] + s12);
+      const double eta1 = (double)u.a * (1.0 / 2147483648.0) - 1.0;
+      if (t1 > eta1) return 0;
+      const double t2 = (om[1] - om[2]) / s12;
+      const double eta2 = (double)u.b * (1.0 / 2147483648.0) - 1.0;
+      return t2 > eta2 ? 1 : 2;
+    }
+  }
+  double S = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) S += om[k];
+  int best = 0;
+  double bs = om[0] / S - gamma * ((double)u.a * (1.0 / 4294967296.0));
+#pragma unroll
+  for (int k = 1; k < K; ++k) {
+    const double sc = om[k] / S - gamma * ((double)pick(u, k) * (1.0 / 4294967296.0));
+    if (sc > bs) {
+      bs = sc;
+      best = k;
+    }
+  }
+  return best;
+}
+
+constexpr int kPottsTabLds = 4096;  // doubles of the weight table kept in LDS
+
+template <int K>
+__global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
+                                                   const uint64_t* __restrict__ map, int sweep_idx,
+                                                   int phase) {
+  __shared__ int64_t red[kSweepWaves][kLanes];
+  __shared__ int32_t fred[kSweepWaves];
+  __shared__ double tab_s[kPottsTabLds];
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& d = D[inst];
+  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
+  if (!st->active || sweep_idx >= st->nsweeps_now || phase >= d.ncls) return;
+  const PAMC_GLOBAL int32_t* __restrict__ row_ptr = gmem(d.row_ptr);
+  const PAMC_GLOBAL int32_t* __restrict__ col = gmem(d.col);
+  const PAMC_GLOBAL int32_t* __restrict__ Jc = gmem(d.J);
+  const PAMC_GLOBAL int32_t* __restrict__ class_ptr = gmem(d.class_ptr);
+  const int cur = st->cur;
+  PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0);
+  PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
+  const int cls = gmem((const int32_t*)d.order)[sweep_idx * d.ncls + phase];
+  const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
+  const int q0 = v0 >> 2;
+  const int nqc = ((v1 + 3) >> 2) - q0;
+  int tile, chunk;
+  group_chunk(d.T, lb, tile, chunk);
+  if (chunk * (kSweepWaves * d.qpw) >= nqc) return;
+  const uint32_t gs = st->gs + (uint32_t)sweep_idx;
+  const int32_t last = (int32_t)st->table_x;
+  const bool lds = last < kPottsTabLds;
+  if (lds)
+    for (int i = threadIdx.x; i <= last; i += blockDim.x) tab_s[i] = d.ptab[i];
+  __syncthreads();
+  const double* __restrict__ tab = lds ? tab_s : (const double*)d.ptab;
+  const int rule = d.potts_rule;
+  const double gamma = d.potts_gamma;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t r = (uint32_t)(tile * kLanes + lane);
+  const size_t tbase = (size_t)tile * d.nq;
+  int64_t dE = 0;
+  int32_t nflip = 0;
+  for (int i = 0; i < d.qpw; ++i) {
+    const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
+    if (qi >= nqc) break;
+    const int q = q0 + qi;
+    const size_t sidx = (tbase + q) * kLanes + lane;
+    uint32_t sw = S[sidx];
+    bool dirty = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int v = 4 * q + k;
+      if (v < v0 || v >= v1) continue;
+      int32_t syn[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) syn[c] = 0;
+      const int e1 = row_ptr[v + 1];
+      for (int e = row_ptr[v]; e < e1; ++e) {
+        const int j = col[e];
+        const int32_t Jv = Jc[e];
+        const uint32_t lab = (S[(tbase + (j >> 2)) * kLanes + lane] >> (8 * (j & 3))) & 0xFFu;
+#pragma unroll
+        for (int c = 0; c < K; ++c) syn[c] += lab == (uint32_t)c ? Jv : 0;
+      }
+      const u32x4 u = philox10((uint32_t)v, gs, r, kTagPotts, d.k0, d.k1);
+      const int old = (int)((sw >> (8 * k)) & 0xFFu);
+      const int nw = potts_choose<K>(syn, u, tab, last, rule, gamma);
+      if (nw != old) {
+        dE += -2 * (int64_t)(syn_of<K>(syn, nw) - syn_of<K>(syn, old));
+        sw = (sw & ~(0xFFu << (8 * k))) | ((uint32_t)nw << (8 * k));
+        dirty = true;
+        ++nflip;
+      }
+    }
+    if (dirty) S[sidx] = sw;
+  }
+  red[wave][lane] = dE;
+  if (d.flip_ctr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nflip += __shfl_xor(nflip, o, 64);
+    if (lane == 0) fred[wave] = nflip;
+  }
+  reduce_energy_and_flips(red, fred, wave, lane, 1, tile, E, gmem(d.flip_ctr));
+}
+
+// ---------------------------------------------------------------------------
 // Population initialisation (Algorithm 1, initialization): spins uniform from
 // Philox(quad, 0, replica, INIT) (spin +1 iff the word < 2^31); then local
 // fields by Eq. 3 and energies H = -1/2 sum s h.
@@ -397,7 +546,10 @@ __global__ void __launch_bounds__(256) k_init_spins(const Desc* __restrict__ D,
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
       int8_t s = 0;
-      if (v < d.n) s = pick(w, k) < 0x80000000u ? (int8_t)1 : (int8_t)-1;
+      if (d.potts_K)  // label floor(u K / 2^32)
+        s = v < d.n ? (int8_t)(((uint64_t)pick(w, k) * (uint64_t)d.potts_K) >> 32) : (int8_t)0;
+      else if (v < d.n)
+        s = pick(w, k) < 0x80000000u ? (int8_t)1 : (int8_t)-1;
       sw |= (uint32_t)(uint8_t)s << (8 * k);
     }
     d.S0[i] = sw;
@@ -428,6 +580,14 @@ __global__ void __launch_bounds__(256) k_init_fields(const Desc* __restrict__ D,
     const int vchunk = (int)(it / d.T);
     int64_t acc = 0;
     for (int v = vchunk * 64 + wave; v < d.n && v < (vchunk + 1) * 64; v += 4) {
+      if (d.potts_K) {
+        // Potts labels (Eq. 6): sum_j J_vj (2 delta(s_v, s_j) - 1); no fields
+        const int32_t lv = spin_at(S, d.nq, tile, v, lane);
+        for (int e = d.row_ptr[v]; e < d.row_ptr[v + 1]; ++e)
+          acc += spin_at(S, d.nq, tile, d.col[e], lane) == lv ? d.J[e] : -d.J[e];
+        if (H) H[((size_t)tile * d.np + v) * kLanes + lane] = 0;
+        continue;
+      }
       int64_t h = 0;
       for (int e = d.row_ptr[v]; e < d.row_ptr[v + 1]; ++e)
         h += (int64_t)d.J[e] * spin_at(S, d.nq, tile, d.col[e], lane);
@@ -446,12 +606,13 @@ __global__ void __launch_bounds__(256) k_init_fields(const Desc* __restrict__ D,
   }
 }
 
-// E currently holds sum_v s_v h_v (= 2 sum_{i<j} J s s); H = -that / 2.  One
-// work-group per instance.
+// E currently holds sum_v s_v h_v (= 2 sum_{i<j} J s s; Potts labels: 2
+// sum_{i<j} J (2 delta - 1)); H = -that / 2.  The best configuration starts
+// with cut 0: all spins +1, or all labels 0.  One work-group per instance.
 __global__ void __launch_bounds__(256) k_init_finish(const Desc* __restrict__ D) {
   const Desc& d = D[blockIdx.x];
   for (int i = threadIdx.x; i < d.R; i += blockDim.x) d.E0[i] = -(d.E0[i] / 2);
-  for (int v = threadIdx.x; v < d.np; v += blockDim.x) d.best[v] = 1;
+  for (int v = threadIdx.x; v < d.np; v += blockDim.x) d.best[v] = d.potts_K ? 0 : 1;
   if (threadIdx.x == 0) {
     RunState* st = d.st;
     st->mstar = 0;
@@ -520,13 +681,14 @@ __device__ __forceinline__ void begin_step(const Desc& d) {
   st->active = 1;
   st->step = st->steps_run;
   st->do_resample = (st->z > 1 && st->resample) ? 1 : 0;
-  st->do_cluster = (st->do_resample && st->augmented && st->enable && st->cooldown == 0) ? 1 : 0;
+  // cluster moves are defined for Ising spins only
+  st->do_cluster = (st->do_resample && st->augmented && st->enable && st->cooldown == 0 && !d.potts_K) ? 1 : 0;
   st->rs_delta = st->delta;
   st->sweep_beta = st->beta;
   st->nsweeps_now = st->sweeps;
   st->cl_n_top = st->n_top;
   st->cl_trials = st->mis_trials;
-  st->table_x = table_halfwidth(st->beta, d.X);
+  st->table_x = d.potts_K ? potts_table_last(st->beta, d.X) : table_halfwidth(st->beta, d.X);
   st->last_lnq = 0.0;
 }
 
@@ -549,7 +711,7 @@ __global__ void k_prim_set(const Desc* __restrict__ D, int32_t ninst, int32_t ki
   st->nsweeps_now = nsweeps;
   st->cl_n_top = n_top;
   st->cl_trials = trials;
-  st->table_x = table_halfwidth(value, D[i].X);
+  st->table_x = D[i].potts_K ? potts_table_last(value, D[i].X) : table_halfwidth(value, D[i].X);
   st->last_lnq = 0.0;
 }
 
@@ -599,8 +761,13 @@ __global__ void __launch_bounds__(256) k_thresholds(const Desc* __restrict__ D,
   if (commit >= 0 && lb == 0 && threadIdx.x == 0) commit_step(d, commit);
   const int64_t Xt = st->table_x;
   const double beta = st->sweep_beta;
-  for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i <= 2 * Xt; i += (int64_t)kThrBlocks * blockDim.x)
-    d.thr[i] = flip_threshold(beta, d.rule, i - Xt);
+  if (d.potts_K) {  // e^{beta (syn_k - max syn)} for max syn - syn_k = i
+    for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i <= Xt; i += (int64_t)kThrBlocks * blockDim.x)
+      d.ptab[i] = exp_cw(beta * (double)(-i));
+  } else {
+    for (int64_t i = (int64_t)lb * blockDim.x + threadIdx.x; i <= 2 * Xt; i += (int64_t)kThrBlocks * blockDim.x)
+      d.thr[i] = flip_threshold(beta, d.rule, i - Xt);
+  }
   if (lb == 0 && d.ncls > 0) {
     const int nsw = min(st->nsweeps_now, d.order_cap);
     for (int s = threadIdx.x; s < nsw; s += blockDim.x) {
@@ -962,7 +1129,9 @@ __global__ void __launch_bounds__(1024) k_rs_select(const Desc* __restrict__ D, 
   }
   if (!st->active || !st->do_resample) return;
   const int64_t* E = st->cur ? a.E1 : a.E0;
-  const double delta = st->rs_delta;
+  // Potts labels: the update of Eq. 8 at beta leaves e^{-(beta/2) E}
+  // invariant for the Eq. 6 energy, so the weights use Delta/2
+  const double delta = a.potts_K ? 0.5 * st->rs_delta : st->rs_delta;
   const bool lowest = delta >= 0;  // reference energy: min for delta >= 0, max otherwise
   const int R = a.R;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1376,6 +1545,10 @@ Desc make_desc(const pamc_instance* I) {
   d.rule = I->rule;
   d.pull = I->pull;
   d.dense = I->dense;
+  d.ptab = I->ptab;
+  d.potts_gamma = I->potts_gamma;
+  d.potts_K = I->potts_K;
+  d.potts_rule = I->potts_rule;
   d.shuffle = (I->flags & 1u) ? 0 : 1;
   d.tr_cap = I->tr_cap;
   d.qpw = I->qpw;
@@ -1386,6 +1559,7 @@ Desc make_desc(const pamc_instance* I) {
 }
 
 int Batch::group_of(const pamc_instance* I) {
+  if (I->potts_K) return 19 + (I->potts_K - 2);
   if (!I->pull) return 0;
   const int ti = I->tpw == 4 ? 2 : (I->tpw == 2 ? 1 : 0);
   const int wide = 2 * I->X + 1 > kThrLds ? 1 : 0;
@@ -1516,6 +1690,7 @@ static SweepKernel pull_kernel(int jm, int ti) {
 static SweepKernel sweep_kernel_of_group(int g) {
   // group = 0 (incremental fields) or 1 + 9 * wide table + 3 * coupling mode + tiles-per-wave index
   if (g == 0) return k_sweep_push;
+  if (g >= 19) return g == 19 ? k_sweep_potts<2> : (g == 20 ? k_sweep_potts<3> : k_sweep_potts<4>);
   const int x = g - 1;
   return x >= 9 ? pull_kernel<true>((x - 9) / 3, (x - 9) % 3) : pull_kernel<false>(x / 3, x % 3);
 }

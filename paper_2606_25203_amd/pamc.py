@@ -23,10 +23,11 @@ MEM_HOST, MEM_DEVICE = 0, 1
 FLAG_FIXED_CLASS_ORDER = 1
 FLAG_FIELDS_PUSH = 2
 FLAG_FIELDS_PULL = 4
+POTTS_SOFTMAX, POTTS_CASCADE = 0, 1
 
 EXPORTED = [
     "pamc_create_instance_csr", "pamc_create_instance_dense_i8", "pamc_create_instance_dense_random",
-    "pamc_create_instance_max3cut", "pamc_destroy_instance", "pamc_reset_population", "pamc_get_info", "pamc_anneal",
+    "pamc_create_instance_max3cut", "pamc_create_instance_potts", "pamc_destroy_instance", "pamc_reset_population", "pamc_get_info", "pamc_anneal",
     "pamc_sweep", "pamc_resample", "pamc_cluster_move", "pamc_update_best", "pamc_best",
     "pamc_get_state", "pamc_get_trace", "pamc_max3cut_decode", "pamc_pair_distance",
     "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
@@ -51,7 +52,7 @@ class pamc_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("replicas", C.c_int32), ("num_classes", C.c_int32),
                 ("dense", C.c_int32), ("pull", C.c_int32), ("nnz", C.c_int64), ("W", C.c_int64), ("X", C.c_int64),
                 ("device_bytes", C.c_int64), ("tiles_per_wave", C.c_int32), ("quads_per_wave", C.c_int32),
-                ("coupling_mode", C.c_int32), ("reserved", C.c_int32)]
+                ("coupling_mode", C.c_int32), ("potts_K", C.c_int32)]
 
 
 class pamc_schedule(C.Structure):
@@ -108,6 +109,8 @@ def _load():
         "pamc_create_instance_dense_i8": [C.c_int32, P, C.c_int64, C.c_int, C.c_int32, C.POINTER(pamc_config), PP],
         "pamc_create_instance_dense_random": [C.c_int32, C.c_uint64, C.POINTER(pamc_config), PP],
         "pamc_create_instance_max3cut": [C.c_int32, P, P, P, C.POINTER(pamc_config), PP],
+        "pamc_create_instance_potts": [C.c_int32, P, P, P, C.c_int32, C.c_int32, C.c_double,
+                                       C.POINTER(pamc_config), PP],
         "pamc_get_info": [P, C.POINTER(pamc_info)],
         "pamc_reset_population": [P, C.c_uint64],
         "pamc_anneal": [P, C.POINTER(pamc_schedule), C.POINTER(pamc_result)],
@@ -185,6 +188,18 @@ def pamc_create_instance_dense_random(n, graph_seed, *, seed=0, replicas=64, rul
     cfg = pamc_config(seed, replicas, rule, device, stream, flags)
     h = C.c_void_p()
     _check(lib.pamc_create_instance_dense_random(int(n), int(graph_seed), C.byref(cfg), C.byref(h)))
+    return h
+
+
+def pamc_create_instance_potts(n, row_ptr, col, w, K, potts_rule=POTTS_SOFTMAX, gamma=1.0, *, seed=0,
+                               replicas=64, device=0, stream=None, flags=0):
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    cl = np.ascontiguousarray(col, np.int32)
+    ww = np.ascontiguousarray(w, np.int32)
+    cfg = pamc_config(seed, replicas, HEATBATH, device, stream, flags)
+    h = C.c_void_p()
+    _check(lib.pamc_create_instance_potts(int(n), _ptr(rp), _ptr(cl), _ptr(ww), int(K), int(potts_rule),
+                                          float(gamma), C.byref(cfg), C.byref(h)))
     return h
 
 
@@ -390,6 +405,13 @@ class Instance:
         h = pamc_create_instance_max3cut(g.n, g.row_ptr, g.col, g.w, seed=seed, replicas=replicas, rule=rule,
                                          stream=stream, flags=flags)
         return cls(h, 3 * g.n + 1, replicas, m3_n=g.n)
+
+    @classmethod
+    def potts(cls, g, K, *, replicas, seed, potts_rule=POTTS_SOFTMAX, gamma=1.0, shuffle=True, stream=None):
+        flags = 0 if shuffle else FLAG_FIXED_CLASS_ORDER
+        h = pamc_create_instance_potts(g.n, g.row_ptr, g.col, g.w, K, potts_rule, gamma, seed=seed,
+                                       replicas=replicas, stream=stream, flags=flags)
+        return cls(h, g.n, replicas)
 
     @classmethod
     def dense(cls, J, *, replicas, seed, rule=HEATBATH, objective=ISING, stream=None):
