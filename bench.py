@@ -12,7 +12,9 @@ reduction, controller), all on the device.
 
 Other workloads (--workload): c1 = plain PAMC on the n = 800 random graph;
 c3 = plain PAMC on the dense n = 100,000 +-1 instance; c4 = augmented PAMC on
-the Max-3-Cut embedding of a 7,000-vertex graph.
+the Max-3-Cut embedding of a 7,000-vertex graph (the decoded 3-cuts are
+reported as final_3cuts); c4p / c4c = the same graph with 3-state Potts
+labels (softmax-perturbed argmax / cascaded p-bits).
 
 Printed (one JSON line): flip attempts per second over the timed runs,
 time-to-target p50/p99 (target = median final best cut of the timed runs),
@@ -80,6 +82,17 @@ def alu_slots_per_attempt(degree: float, coupling_mode: int) -> float:
     return 25.0 + per_neighbour * degree + 9.0
 
 
+def potts_slots_per_attempt(degree: float) -> float:
+    """Vector-ALU issue slots (lane-ops, 32x32->64 products counting 4) of
+    one Potts label visit of k_sweep_potts<3>, from the compiled loop: 910
+    slots per quad of 4 vertices x 64 lanes on C4's graph (padded rows of 8
+    entries), i.e. about 155 per visit for Philox4x32-10 (one 4-word block
+    per visit), the binary64 weights and comparisons and the label update,
+    plus 9 per gathered-CSR entry (rows padded to multiples of 4: readfirstlane,
+    byte extract, K compare-select-adds)."""
+    return 155.0 + 9.0 * 4.0 * math.ceil(degree / 4.0)
+
+
 def counters_traffic(name: str, src: str):
     """HBM bytes per launch from a committed rocprofv3 FETCH/WRITE pass, or
     None if the kernel source changed since the counters were taken."""
@@ -127,6 +140,19 @@ def workload(name):
                     desc="augmented PAMC, Max-3-Cut one-hot embedding of G(7000, 21000) (n=21001), R=2048, "
                          "300 beta steps x 10 sweeps",
                     counters="sweep_max3cut7000_R2048", cpu=dict(R=64, step_s=1.5))
+    if name in ("c4p", "c4c"):
+        # the paper's own Max-3-Cut formulation on C4's graph: one 3-state
+        # Potts label per vertex (n = 7000 instead of the embedding's 21001)
+        g = synth.random_graph(7000, 21000, seed=1)
+        cascade = name == "c4c"
+        return dict(kind="potts", graph=g, K=3, potts_rule=1 if cascade else 0, gamma=0.0 if cascade else 1.0,
+                    R=2048, steps=300, sweeps=10,
+                    sched=dict(beta0=0.1, dbeta=0.02, steps=300, sweeps=10, augmented=1, z_rst=400, n_top=64,
+                               mis_trials=4, tau=25),
+                    desc="augmented PAMC, Max-3-Cut with 3-state Potts labels (" +
+                         ("cascaded p-bit sampler" if cascade else "softmax-perturbed argmax, gamma=1") +
+                         ") on G(7000, 21000), R=2048, 300 beta steps x 10 sweeps",
+                    counters="sweep_potts7000_R2048", cpu=dict(R=64, step_s=0.6))
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -139,6 +165,9 @@ def cpu_baseline(w, seconds_budget: float):
     if w["kind"] == "max3cut":
         o = oracle.Oracle.max3cut(g.n, g.row_ptr, g.col, g.w, rr, 0)
         n = 3 * g.n + 1
+    elif w["kind"] == "potts":
+        o = oracle.Oracle.potts(g.n, g.row_ptr, g.col, g.w, w["K"], rr, 0, rule=w["potts_rule"], gamma=w["gamma"])
+        n = g.n
     else:
         o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, rr, 0)
         n = g.n
@@ -294,7 +323,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4p", "c4c"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fields", choices=["auto", "push", "pull"], default="auto")
@@ -331,6 +360,9 @@ def main():
         inst = pamc.Instance.csr(w["graph"], replicas=w["R"], seed=0, fields=fields)
     elif w["kind"] == "max3cut":
         inst = pamc.Instance.max3cut(w["graph"], replicas=w["R"], seed=0, fields=fields)
+    elif w["kind"] == "potts":
+        inst = pamc.Instance.potts(w["graph"], w["K"], replicas=w["R"], seed=0, potts_rule=w["potts_rule"],
+                                   gamma=w["gamma"])
     else:
         inst = pamc.Instance.dense_random(w["n"], 1, replicas=w["R"], seed=0)
     info = inst.info()
@@ -345,11 +377,14 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
+    decoded = []
     for k in range(args.steps):
         inst.reset(k)
         res = inst.anneal(sched)
         tr = inst.trace(w["steps"])
         runs.append((res, tr))
+        if w["kind"] == "max3cut":  # the 3-cut of the run's best configuration
+            decoded.append(int(inst.max3cut_decode()[0]))
         log(f"run {k}: best cut {res.best_cut}, device time {res.seconds_total:.3f} s")
     inst.synchronize()
     torch.cuda.synchronize()
@@ -358,6 +393,7 @@ def main():
 
     attempts = sum(r.steps_run for r, _ in runs) * w["sweeps"] * n * w["R"]
     finals = [r.best_cut for r, _ in runs]
+    finals3 = [c for c in decoded] if decoded else None
     target = int(percentile(finals, 0.5))
     ttt = []
     for res, tr in runs:
@@ -386,7 +422,14 @@ def main():
         hbm = bpa * rate / 1e9
         shape = {"tiles_per_wave": info.tiles_per_wave, "quads_per_wave": info.quads_per_wave,
                  "coupling_mode": info.coupling_mode}
-        if pull:
+        if w["kind"] == "potts":
+            slots = potts_slots_per_attempt(degree)
+            achieved = slots * rate / 1e12
+            roof = {"kernel": "k_sweep_potts<3>", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
+                    "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
+                    "alu_slots_per_attempt": slots, "hbm_algorithmic_gbs": hbm,
+                    "hbm_algorithmic_frac": hbm / HBM_PEAK_GBS}
+        elif pull:
             # issue-bound: vector ALU slots per attempt (see alu_slots_per_attempt)
             slots = alu_slots_per_attempt(degree, info.coupling_mode)
             achieved = slots * rate / 1e12
@@ -419,6 +462,7 @@ def main():
                    "parallelism": "1 GPU"},
         "time_to_target": {"target_cut": target, "p50_s": percentile(ttt, 0.5), "p99_s": percentile(ttt, 0.99),
                            "success_fraction": len(ttt) / len(runs), "final_cuts": finals},
+        **({"final_3cuts": finals3} if finals3 else {}),
         "roofline": roof,
     }
     inst.close()

@@ -132,12 +132,14 @@ pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, cons
  * k) (Eq. 7) and omega_k = e^{beta (syn_k - max_m syn_m)} (binary64), the new
  * label is
  *   PAMC_POTTS_SOFTMAX: the k with the largest P_k - gamma U_k, P_k =
- *     omega_k / sum_m omega_m (Eqs. 8-9), U_k = u_k / 2^32, lowest k on ties;
+ *     omega_k / S, S = sum_m omega_m (Eqs. 8-9), U_k = u_k / 2^32, lowest k
+ *     on ties; compared as omega_k - (gamma U_k) S;
  *   PAMC_POTTS_CASCADE (K = 3 only): the two binary p-bits of the cascaded
- *     sampler (Supplement): label 0 if tanh(Delta_1) = (omega_0 - (omega_1 +
- *     omega_2)) / (omega_0 + (omega_1 + omega_2)) exceeds eta_1 = u_0/2^31 - 1,
- *     else label 1 if tanh(Delta_2) = (omega_1 - omega_2) / (omega_1 +
- *     omega_2) exceeds eta_2 = u_1/2^31 - 1, else label 2 (exact Gibbs).
+ *     sampler (Supplement): label 0 if tanh(Delta_1) = (omega_0 - s12) /
+ *     (omega_0 + s12), s12 = omega_1 + omega_2, exceeds eta_1 = u_0/2^31 - 1,
+ *     else label 1 if tanh(Delta_2) = (omega_1 - omega_2) / s12 exceeds
+ *     eta_2 = u_1/2^31 - 1, else label 2 (exact Gibbs); each compared as
+ *     numerator > eta * denominator.
  * u_0..u_3 are the words of Philox(vertex, sweep, replica, 6).  This update
  * at beta leaves e^{-(beta/2) E} invariant, so resampling weighs replicas by
  * e^{-(Delta/2) (E - E_ref)} (ln Q likewise).  Cluster moves and the pair

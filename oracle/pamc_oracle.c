@@ -570,15 +570,18 @@ static void flip_spin(orc* o, int32_t r, int32_t v) {
 
 /* One Potts label update (Eqs. 7-9, or the Supplement's cascade).
  * omega_k = e^{beta (syn_k - max syn)}: the numerators of Eq. 8 scaled by a
- * common factor, so they do not overflow.
- *   softmax: P_k = omega_k / sum_m omega_m (sum in label order); the new
- *     label is the k with the largest P_k - gamma U_k, U_k = u_k / 2^32
- *     (the lowest k on ties).
+ * common factor, so they do not overflow.  Both rules compare quantities
+ * multiplied through by their positive denominators, which leaves every
+ * comparison of the paper's formulas unchanged and needs no division:
+ *   softmax: with S = sum_m omega_m (summed in label order), P_k - gamma U_k
+ *     is compared as omega_k - (gamma U_k) S, U_k = u_k / 2^32; the largest
+ *     wins, the lowest k on ties (Eq. 9).
  *   cascade (K = 3, labels alpha, beta, gamma = 0, 1, 2): tanh(Delta_1) =
- *     (w0 - (w1 + w2)) / (w0 + (w1 + w2)) and tanh(Delta_2) = (w1 - w2) /
- *     (w1 + w2), since tanh(ln(a/b)/2) = (a - b)/(a + b); the p-bits are
- *     b = [tanh(Delta) > eta] with eta = u / 2^31 - 1 in [-1, 1); b1 = 1
- *     picks label 0, else b2 picks label 1 (b2 = 1) or 2. */
+ *     (w0 - s12) / (w0 + s12) with s12 = w1 + w2 and tanh(Delta_2) =
+ *     (w1 - w2) / s12, since tanh(ln(a/b)/2) = (a - b)/(a + b); the p-bit
+ *     b = [tanh(Delta) > eta], eta = u / 2^31 - 1 in [-1, 1), is taken as
+ *     numerator > eta * denominator.  b1 = 1 picks label 0, else b2 picks
+ *     label 1 (b2 = 1) or 2. */
 int32_t orc_potts_choose(int32_t K, int32_t potts_rule, double gamma, double beta,
                          const int64_t* syn, const uint32_t* u) {
   int64_t m = syn[0];
@@ -588,19 +591,17 @@ int32_t orc_potts_choose(int32_t K, int32_t potts_rule, double gamma, double bet
   for (int32_t k = 0; k < K; ++k) om[k] = orc_pexp(beta * (double)(syn[k] - m));
   if (potts_rule == ORC_POTTS_CASCADE) {
     double s12 = om[1] + om[2];
-    double t1 = (om[0] - s12) / (om[0] + s12);
     double eta1 = (double)u[0] * (1.0 / 2147483648.0) - 1.0;
-    if (t1 > eta1) return 0;
-    double t2 = (om[1] - om[2]) / s12;
+    if (om[0] - s12 > eta1 * (om[0] + s12)) return 0;
     double eta2 = (double)u[1] * (1.0 / 2147483648.0) - 1.0;
-    return t2 > eta2 ? 1 : 2;
+    return om[1] - om[2] > eta2 * s12 ? 1 : 2;
   }
   double S = 0.0;
   for (int32_t k = 0; k < K; ++k) S += om[k];
   int32_t best = 0;
-  double bs = om[0] / S - gamma * ((double)u[0] * (1.0 / 4294967296.0));
+  double bs = om[0] - (gamma * ((double)u[0] * (1.0 / 4294967296.0))) * S;
   for (int32_t k = 1; k < K; ++k) {
-    double sc = om[k] / S - gamma * ((double)u[k] * (1.0 / 4294967296.0));
+    double sc = om[k] - (gamma * ((double)u[k] * (1.0 / 4294967296.0))) * S;
     if (sc > bs) { bs = sc; best = k; }
   }
   return best;

@@ -266,7 +266,9 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   // byte offsets of the neighbour's spin word in a tile (plus its byte index
   // in modes 0 and 1), couplings in the kernel's mode (mode 2: the int8
   // coupling in the neighbour's byte).
-  if (h.pull && !h.potts_K) {
+  // Potts labels are read with a byte index: coupling mode 0 or 1 layout
+  if (h.potts_K && h.jmode == 2) h.jmode = h.small_j ? 1 : 0;
+  if (h.pull) {
     h.grow.assign(n + 1, 0);
     for (int32_t iv = 0; iv < n; ++iv) h.grow[iv + 1] = h.grow[iv] + ((h.rp2[iv + 1] - h.rp2[iv] + 3) & ~3);
     h.gcol.assign(std::max(h.grow[n], 4), 0);
@@ -333,7 +335,7 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(dalloc(I, &I->g.row_ptr, n + 1), "alloc");
   HIP_TRY(dalloc(I, &I->g.col, nnz), "alloc");
   HIP_TRY(dalloc(I, &I->g.J, nnz), "alloc");
-  const bool gathered = I->pull && !I->potts_K;
+  const bool gathered = I->pull;
   if (gathered) {
     HIP_TRY(dalloc(I, &I->g.grow, n + 1), "alloc");
     HIP_TRY(dalloc(I, &I->g.gcol, h.gcol.size()), "alloc");

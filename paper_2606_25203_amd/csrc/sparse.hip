@@ -379,12 +379,14 @@ __global__ void __launch_bounds__(256) k_sweep_push(const Desc* __restrict__ D,
 // Supplement).  A label word holds the labels (bytes 0..K-1) of the four
 // vertices of a quad, like a spin word.  Visiting vertex v of replica r:
 // the K-label field syn_k = sum_j J_vj [s_j = k] over the CSR row (Eq. 7),
-// omega_k = e^{beta (syn_k - max syn)} from the step's table, then
-//   softmax: the k with the largest omega_k / sum omega - gamma u_k 2^-32
-//     (Eqs. 8-9, lowest k on ties);
-//   cascade: label 0 iff tanh(Delta_1) = (w0 - (w1 + w2)) / (w0 + (w1 + w2))
-//     exceeds eta_1 = u_0 2^-31 - 1, else label 1 iff tanh(Delta_2) =
-//     (w1 - w2) / (w1 + w2) exceeds eta_2 = u_1 2^-31 - 1, else 2;
+// omega_k = e^{beta (syn_k - max syn)} from the step's table, then the
+// comparisons of the paper's formulas multiplied through by their positive
+// denominators (no division):
+//   softmax: the k with the largest omega_k - (gamma u_k 2^-32) S, S = sum
+//     omega (Eqs. 8-9: P_k - gamma U_k times S; lowest k on ties);
+//   cascade: label 0 iff w0 - s12 > eta_1 (w0 + s12), s12 = w1 + w2 (the
+//     p-bit tanh(Delta_1) > eta_1), else label 1 iff w1 - w2 > eta_2 s12,
+//     else 2; eta = u 2^-31 - 1;
 // u = Philox(v, sweep, r, POTTS).  Every operation is a correctly rounded
 // binary64 operation in a fixed order (no contraction), so the choice is
 // the same wherever it is computed.  The energy (Eq. 6) changes by
@@ -413,22 +415,20 @@ __device__ __forceinline__ int potts_choose(const int32_t (&syn)[K], const u32x4
   if constexpr (K == 3) {
     if (rule == 1) {
       const double s12 = om[1] + om[2];
-      const double t1 = (om[0] - s12) / (om[0] + s12);
       const double eta1 = (double)u.a * (1.0 / 2147483648.0) - 1.0;
-      if (t1 > eta1) return 0;
-      const double t2 = (om[1] - om[2]) / s12;
+      if (om[0] - s12 > eta1 * (om[0] + s12)) return 0;
       const double eta2 = (double)u.b * (1.0 / 2147483648.0) - 1.0;
-      return t2 > eta2 ? 1 : 2;
+      return om[1] - om[2] > eta2 * s12 ? 1 : 2;
     }
   }
   double S = 0.0;
 #pragma unroll
   for (int k = 0; k < K; ++k) S += om[k];
   int best = 0;
-  double bs = om[0] / S - gamma * ((double)u.a * (1.0 / 4294967296.0));
+  double bs = om[0] - (gamma * ((double)u.a * (1.0 / 4294967296.0))) * S;
 #pragma unroll
   for (int k = 1; k < K; ++k) {
-    const double sc = om[k] / S - gamma * ((double)pick(u, k) * (1.0 / 4294967296.0));
+    const double sc = om[k] - (gamma * ((double)pick(u, k) * (1.0 / 4294967296.0))) * S;
     if (sc > bs) {
       bs = sc;
       best = k;
@@ -437,7 +437,36 @@ __device__ __forceinline__ int potts_choose(const int32_t (&syn)[K], const u32x4
   return best;
 }
 
-constexpr int kPottsTabLds = 4096;  // doubles of the weight table kept in LDS
+constexpr int kPottsTabLds = 1024;  // doubles of the weight table kept in LDS (8 KB: occupancy)
+
+// K-label field of one vertex from the gathered CSR (rows padded to
+// multiples of 4 entries with coupling 0; columns as the byte offset of the
+// neighbour's label word in a tile plus its byte index), four neighbours per
+// step: two 16-byte scalar loads and four buffer loads.
+template <int K>
+__device__ __forceinline__ void gather_labels(const PAMC_GLOBAL int32_t* __restrict__ gcol,
+                                              const PAMC_GLOBAL int32_t* __restrict__ gJ, int e0, int e1,
+                                              __amdgpu_buffer_rsrc_t Sr, int voff, int32_t (&syn)[K]) {
+#pragma unroll
+  for (int c = 0; c < K; ++c) syn[c] = 0;
+  for (int e = e0; e < e1; e += 4) {
+    const i32x4 cj = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(gcol + e);
+    const i32x4 cJ = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(gJ + e);
+    const int j[4] = {__builtin_amdgcn_readfirstlane(cj.x), __builtin_amdgcn_readfirstlane(cj.y),
+                      __builtin_amdgcn_readfirstlane(cj.z), __builtin_amdgcn_readfirstlane(cj.w)};
+    const int32_t c4[4] = {__builtin_amdgcn_readfirstlane(cJ.x), __builtin_amdgcn_readfirstlane(cJ.y),
+                           __builtin_amdgcn_readfirstlane(cJ.z), __builtin_amdgcn_readfirstlane(cJ.w)};
+    uint32_t w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = __builtin_amdgcn_raw_buffer_load_b32(Sr, voff, j[u] & ~3, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t lab = __builtin_amdgcn_ubfe(w[u], 8u * (uint32_t)(j[u] & 3), 8u);
+#pragma unroll
+      for (int c = 0; c < K; ++c) syn[c] += lab == (uint32_t)c ? c4[u] : 0;
+    }
+  }
+}
 
 template <int K>
 __global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
@@ -451,9 +480,9 @@ __global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
   const Desc& d = D[inst];
   const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
   if (!st->active || sweep_idx >= st->nsweeps_now || phase >= d.ncls) return;
-  const PAMC_GLOBAL int32_t* __restrict__ row_ptr = gmem(d.row_ptr);
-  const PAMC_GLOBAL int32_t* __restrict__ col = gmem(d.col);
-  const PAMC_GLOBAL int32_t* __restrict__ Jc = gmem(d.J);
+  const PAMC_GLOBAL int32_t* __restrict__ grow = gmem(d.grow);
+  const PAMC_GLOBAL int32_t* __restrict__ gcol = gmem(d.gcol);
+  const PAMC_GLOBAL int32_t* __restrict__ gJ = gmem(d.gJ);
   const PAMC_GLOBAL int32_t* __restrict__ class_ptr = gmem(d.class_ptr);
   const int cur = st->cur;
   PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0);
@@ -477,42 +506,44 @@ __global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t r = (uint32_t)(tile * kLanes + lane);
-  const size_t tbase = (size_t)tile * d.nq;
+  const uint32_t tstride = (uint32_t)d.nq * kLanes;
+  const __amdgpu_buffer_rsrc_t Sr = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(S + (size_t)tile * tstride), (short)0, (int)(tstride * 4), kBufferWord3);
+  const int voff = lane * 4;
   int64_t dE = 0;
   int32_t nflip = 0;
   for (int i = 0; i < d.qpw; ++i) {
     const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
     if (qi >= nqc) break;
     const int q = q0 + qi;
-    const size_t sidx = (tbase + q) * kLanes + lane;
-    uint32_t sw = S[sidx];
-    bool dirty = false;
+    uint32_t sw = __builtin_amdgcn_raw_buffer_load_b32(Sr, voff, q * (kLanes * 4), 0);
+    const uint32_t sw0 = sw;
+    // the four fields first (the class's vertices do not see each other)
+    int32_t synq[4][K];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
-      if (v < v0 || v >= v1) continue;
-      int32_t syn[K];
+      const bool in = v >= v0 && v < v1;
+      gather_labels<K>(gcol, gJ, in ? grow[v] : 0, in ? grow[v + 1] : 0, Sr, voff, synq[k]);
+    }
 #pragma unroll
-      for (int c = 0; c < K; ++c) syn[c] = 0;
-      const int e1 = row_ptr[v + 1];
-      for (int e = row_ptr[v]; e < e1; ++e) {
-        const int j = col[e];
-        const int32_t Jv = Jc[e];
-        const uint32_t lab = (S[(tbase + (j >> 2)) * kLanes + lane] >> (8 * (j & 3))) & 0xFFu;
+    for (int k = 0; k < 4; ++k) {
+      const int v = 4 * q + k;
+      if (v >= v0 && v < v1) {
+        int32_t syn[K];
 #pragma unroll
-        for (int c = 0; c < K; ++c) syn[c] += lab == (uint32_t)c ? Jv : 0;
-      }
-      const u32x4 u = philox10((uint32_t)v, gs, r, kTagPotts, d.k0, d.k1);
-      const int old = (int)((sw >> (8 * k)) & 0xFFu);
-      const int nw = potts_choose<K>(syn, u, tab, last, rule, gamma);
-      if (nw != old) {
-        dE += -2 * (int64_t)(syn_of<K>(syn, nw) - syn_of<K>(syn, old));
-        sw = (sw & ~(0xFFu << (8 * k))) | ((uint32_t)nw << (8 * k));
-        dirty = true;
-        ++nflip;
+        for (int c = 0; c < K; ++c) syn[c] = synq[k][c];
+        const u32x4 u = philox10((uint32_t)v, gs, r, kTagPotts, d.k0, d.k1);
+        const int old = (int)((sw >> (8 * k)) & 0xFFu);
+        const int nw = potts_choose<K>(syn, u, tab, last, rule, gamma);
+        if (nw != old) {
+          dE += -2 * (int64_t)(syn_of<K>(syn, nw) - syn_of<K>(syn, old));
+          sw = (sw & ~(0xFFu << (8 * k))) | ((uint32_t)nw << (8 * k));
+          ++nflip;
+        }
       }
     }
-    if (dirty) S[sidx] = sw;
+    if (sw != sw0) __builtin_amdgcn_raw_buffer_store_b32(sw, Sr, voff, q * (kLanes * 4), 0);
   }
   red[wave][lane] = dE;
   if (d.flip_ctr) {

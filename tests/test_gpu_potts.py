@@ -89,7 +89,7 @@ def test_potts_resample(pamc, K, rule):
 
 def test_potts_weight_table_beyond_lds(pamc):
     # weights up to 900 on degree ~10: max syn - syn_k reaches past the
-    # 4,096-entry LDS copy of the weight table at small beta
+    # LDS copy of the weight table (1,024 entries) at small beta
     g = synth.random_graph(120, 600, 9)
     rng = np.random.default_rng(1)
     w = np.zeros_like(g.w)
