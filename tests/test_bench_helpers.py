@@ -1,0 +1,33 @@
+"""CPU checks of the benchmark's reporting helpers."""
+import importlib.util
+import math
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_tts99_eq5(bench):
+    # Eq. 5: TTS = T ln(0.01) / ln(1 - P_s), minimised over T
+    assert bench.tts99([], 4) is None
+    assert bench.tts99([0.3, 0.3, 0.4, 0.5], 4) == 0.5          # every run hit by 0.5 s
+    half = 0.5 * math.log(0.01) / math.log(0.5)
+    quarter = 0.4 * math.log(0.01) / math.log(0.75)
+    assert bench.tts99([0.4, 0.5], 4) == pytest.approx(min(half, quarter))
+    # a later T with a higher success fraction can win
+    assert bench.tts99([1.0, 1.1, 1.2], 4) == pytest.approx(1.2 * math.log(0.01) / math.log(0.25))
+
+
+def test_percentile(bench):
+    assert bench.percentile([3, 1, 2], 0.5) == 2
+    assert bench.percentile([], 0.5) is None
+    assert bench.percentile([0.0, 10.0], 0.99) == pytest.approx(9.9)
