@@ -506,7 +506,7 @@ pamc_status build_dense_common(pamc_instance* I, int32_t n) {
   HIP_TRY(dalloc(I, &I->rs_parent, I->R), "alloc");
   HIP_TRY(dalloc(I, &I->flip_ctr, 512), "alloc");
   HIP_TRY(pamc::prepare_kernel_lds(), "hipFuncSetAttribute");
-  const size_t gsz = (size_t)pamc::dense_superblock_rows() * I->R;
+  const size_t gsz = (size_t)pamc::dense_field_buffers() * pamc::dense_superblock_rows() * I->R;
   HIP_TRY(dalloc(I, &I->Gd, gsz), "alloc fields");
   HIP_TRY(hipMemsetAsync(I->Gd, 0, sizeof(int32_t) * gsz, I->stream), "memset");
   I->order_cap = 1;

@@ -97,26 +97,43 @@ __global__ void __launch_bounds__(256) k_dense_init_spins(int8_t* S, int32_t* fa
 // v_mfma_i32_16x16x64_i8 tiles.  Operand fragments: lane l supplies 16
 // consecutive K bytes at 16*(l/16) of row (A) / replica (B) l % 16; the
 // result holds rows 4*(l/16)..+3 of column l % 16.
-__global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J,
-                                                    const int8_t* __restrict__ S0,
-                                                    const int8_t* __restrict__ S1,
-                                                    int32_t* __restrict__ G, const RunState* st,
-                                                    int32_t row0, int32_t rows, int32_t np, int32_t R,
-                                                    int32_t use_state, int32_t kslice) {
-  __shared__ __attribute__((aligned(16))) int8_t As[2][kGM * kLdsRow];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[2][kGN * kLdsRow];
-  if (use_state == 1 && !st->active) return;
-  const int8_t* __restrict__ S = (use_state ? st->cur : 0) ? S1 : S0;
+// The product runs over a K domain given as columns kbase .. kbase + kcount
+// + xlen with the xlen columns from kbase + x0 left out (x0, xlen, kbase and
+// kcount multiples of 64): compacted column k maps to kbase + k, plus xlen
+// once k >= x0.
+struct GemmArgs {
+  const int8_t* J;
+  const int8_t* S0;
+  const int8_t* S1;
+  int32_t* G;
+  const RunState* st;
+  int32_t row0, rows, np, R, use_state, kslice;
+  int32_t kbase, kcount, x0, xlen;
+};
+
+struct GemmLds {
+  __attribute__((aligned(16))) int8_t As[2][kGM * kLdsRow];
+  __attribute__((aligned(16))) int8_t Bs[2][kGN * kLdsRow];
+};
+
+__device__ __forceinline__ void gemm_body(const GemmArgs g, int bid, GemmLds& L) {
+  auto& As = L.As;
+  auto& Bs = L.Bs;
+  const int8_t* __restrict__ J = g.J;
+  int32_t* __restrict__ G = g.G;
+  const int32_t row0 = g.row0, rows = g.rows, np = g.np, R = g.R, kslice = g.kslice;
+  if (g.use_state == 1 && !g.st->active) return;
+  const int8_t* __restrict__ S = (g.use_state ? g.st->cur : 0) ? g.S1 : g.S0;
   // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so
   // every output tile of K slice p lands on XCD p % 8 and the slice's J
   // columns and spins are fetched into that XCD's L2 once, not once per
   // tile row / column
   const int MT = (rows + kGM - 1) / kGM, NT = (R + kGN - 1) / kGN;
-  const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int xcd = bid & 7, q = bid >> 3;
   const int tile = q % (MT * NT);
   const int p = (q / (MT * NT)) * 8 + xcd;
   const int mt = tile % MT, ntile = tile / MT;
-  const int k_beg = p * kslice, k_end = min(np, k_beg + kslice);
+  const int k_beg = p * kslice, k_end = min(g.kcount, k_beg + kslice);
   if (k_beg >= k_end) return;
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -148,10 +165,12 @@ __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J
   const int nst = (k_end - k_beg) / kGK;
   v4i ra[D][2], rb[D][2];
   auto load_stage = [&](int slot, int stage) {
+    const int kc = k_beg + stage * kGK;  // compacted column of the stage
+    const int k = g.kbase + kc + (kc >= g.x0 ? g.xlen : 0);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      ra[slot][i] = *reinterpret_cast<const v4i*>(ag[i] + k_beg + stage * kGK);
-      rb[slot][i] = *reinterpret_cast<const v4i*>(bg[i] + k_beg + stage * kGK);
+      ra[slot][i] = *reinterpret_cast<const v4i*>(ag[i] + k);
+      rb[slot][i] = *reinterpret_cast<const v4i*>(bg[i] + k);
     }
   };
   auto store_stage = [&](int slot, int buf) {
@@ -216,6 +235,11 @@ __global__ void __launch_bounds__(256) k_dense_gemm(const int8_t* __restrict__ J
         if (v != 0 && m < rows && n < R)
           __hip_atomic_fetch_add(&G[(size_t)m * R + n], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+}
+
+__global__ void __launch_bounds__(256) k_dense_gemm(GemmArgs g) {
+  __shared__ GemmLds L;
+  gemm_body(g, blockIdx.x, L);
 }
 
 // Sequential visit of one super-block's spins for one 64-replica tile.
@@ -382,21 +406,29 @@ __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], cons
 // its diagonal block of J.  After wave 0 is done, the four waves add block
 // b's own contribution to block b + 1 (one 64-column matrix-core step, its J
 // fragments loaded before the decisions).
+struct SeqLds {
+  uint32_t jd[2][kDB][kDB / 4];   // J[rb0 + k][rb0 + 4g .. 4g+3], packed int8
+  int32_t gsum[2][kDB][64];       // fields of this tile before the block's own flips
+  uint32_t thr_s[2 * kThrL + 1];  // thresholds for |x| <= Xl
+  __attribute__((aligned(16))) int8_t dsl[64][kSB + 16];  // spin changes d, [replica][row - row0]
+  uint32_t swl[2][64][kDB / 4 + 1];                       // the block's spin words, [replica][word]
+  __attribute__((aligned(16))) u32x4 rnd_s[kDB / 4][64];  // the block's Philox words, [group][replica]
+};
+
 template <int RULE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
-  __shared__ uint32_t jd[2][kDB][kDB / 4];   // J[rb0 + k][rb0 + 4g .. 4g+3], packed int8
-  __shared__ int32_t gsum[2][kDB][64];       // fields of this tile before the block's own flips
-  __shared__ uint32_t thr_s[2 * kThrL + 1];  // thresholds for |x| <= Xl
-  __shared__ __attribute__((aligned(16))) int8_t dsl[64][kSB + 16];  // spin changes d, [replica][row - row0]
-  __shared__ uint32_t swl[2][64][kDB / 4 + 1];  // the block's spin words, [replica][word]
-  __shared__ __attribute__((aligned(16))) u32x4 rnd_s[kDB / 4][64];  // the block's Philox words, [group][replica]
+__device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t sweep_idx, int32_t row0, int32_t rows,
+                                         SeqLds& L) {
+  auto& jd = L.jd;
+  auto& gsum = L.gsum;
+  auto& thr_s = L.thr_s;
+  auto& dsl = L.dsl;
+  auto& swl = L.swl;
+  auto& rnd_s = L.rnd_s;
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
   int8_t* S = cur ? a.S1 : a.S0;
   int64_t* E = cur ? a.E1 : a.E0;
-  const int tile = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = tile * 64 + lane;
@@ -559,9 +591,29 @@ k_dense_seq(SeqArgs a, int32_t sweep_idx, int32_t row0, int32_t rows) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) nflip += __shfl_xor(nflip, o, 64);
     if (lane == 0)
-      __hip_atomic_fetch_add((unsigned long long*)&a.flip_ctr[blockIdx.x & 255],
+      __hip_atomic_fetch_add((unsigned long long*)&a.flip_ctr[tile & 255],
                              (unsigned long long)nflip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// One super-block step: work-groups 0..T-1 run the sequential pass of this
+// super-block (one per replica tile); with gemm_on the others compute the
+// field product of the next super-block over every column except this
+// super-block's own (which the pass is changing), into the other field
+// buffer.  The two parts share no data, so the product runs on the compute
+// units the pass leaves idle; the missing columns are added by a small
+// product once the pass is done.
+template <int RULE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_dense_step(SeqArgs a, GemmArgs g, int32_t sweep_idx, int32_t row0, int32_t rows, int32_t T, int32_t gemm_on) {
+  __shared__ union {
+    SeqLds seq;
+    GemmLds gemm;
+  } L;
+  if ((int)blockIdx.x < T)
+    seq_body<RULE>(a, blockIdx.x, sweep_idx, row0, rows, L.seq);
+  else if (gemm_on)
+    gemm_body(g, blockIdx.x - T, L.gemm);
 }
 
 // Energy of the population from super-block fields: E_r += sum_k s_rk G_kr
@@ -659,13 +711,44 @@ struct GemmShape {
 // About 512 work-groups: the K range is cut into P slices of whole stages;
 // the grid covers the slices in groups of 8 (one per XCD; work-groups of
 // slices past the end return at once).
-static inline GemmShape gemm_shape(const pamc_instance* I, int rows) {
+static inline GemmShape gemm_shape(const pamc_instance* I, int rows, int kcount) {
   const int tiles = ((rows + kGM - 1) / kGM) * ((I->R + kGN - 1) / kGN);
-  const int stages = I->dn_pad / kGK;
+  const int stages = std::max(1, kcount / kGK);
   const int P = std::max(1, std::min(stages, (512 + tiles - 1) / tiles));
   const int kslice = ((stages + P - 1) / P) * kGK;
-  const int slices = (I->dn_pad + kslice - 1) / kslice;
+  const int slices = (kcount + kslice - 1) / kslice;
   return {tiles * ((slices + 7) / 8) * 8, kslice};
+}
+
+// Field product G = J[row0 .. row0 + rows) . S over the K domain (kbase,
+// kcount, x0, xlen; see GemmArgs), and its grid.
+struct GemmLaunch {
+  GemmArgs g;
+  int grid;
+};
+static GemmLaunch gemm_launch(const pamc_instance* I, int32_t row0, int32_t rows, int32_t use_state, int32_t* G,
+                              int32_t kbase, int32_t kcount, int32_t x0, int32_t xlen) {
+  const GemmShape gsh = gemm_shape(I, rows, kcount);
+  GemmArgs g;
+  g.J = I->Jd;
+  g.S0 = I->Sd;
+  g.S1 = I->Sd2;
+  g.G = G;
+  g.st = I->st;
+  g.row0 = row0;
+  g.rows = rows;
+  g.np = I->dn_pad;
+  g.R = I->R;
+  g.use_state = use_state;
+  g.kslice = gsh.kslice;
+  g.kbase = kbase;
+  g.kcount = kcount;
+  g.x0 = x0;
+  g.xlen = xlen;
+  return {g, gsh.grid};
+}
+static GemmLaunch gemm_full(const pamc_instance* I, int32_t row0, int32_t rows, int32_t use_state, int32_t* G) {
+  return gemm_launch(I, row0, rows, use_state, G, 0, I->dn_pad, I->dn_pad, 0);
 }
 
 static hipError_t dense_full_energy(pamc_instance* I, int buf) {
@@ -673,9 +756,8 @@ static hipError_t dense_full_energy(pamc_instance* I, int buf) {
   hipMemsetAsync(I->pop.E[buf], 0, sizeof(int64_t) * I->R, I->stream);
   for (int row0 = 0; row0 < I->n; row0 += kSB) {
     const int rows = sb_rows(I, row0);
-    const GemmShape gsh = gemm_shape(I, rows);
-    k_dense_gemm<<<gsh.grid, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows, I->dn_pad, I->R,
-                                                  0, gsh.kslice);
+    const GemmLaunch gl = gemm_full(I, row0, rows, 0, I->Gd);
+    k_dense_gemm<<<gl.grid, 256, 0, I->stream>>>(gl.g);
     k_dense_energy_sb<<<T * (rows / 64), 64, 0, I->stream>>>(buf ? I->Sd2 : I->Sd, I->Gd, I->pop.E[buf], row0,
                                                              rows, I->n, I->dn_pad, I->R);
   }
@@ -693,6 +775,14 @@ hipError_t launch_init_dense(pamc_instance* I) {
   return hipGetLastError();
 }
 
+// Sweeps of the dense path, super-block by super-block (rows row0_i ..).
+// The field buffer alternates between two halves of Gd.  Super-block 0 of a
+// sweep gets its full product first; then, for each super-block i, the
+// launch that runs its sequential pass also computes the product of i+1
+// over every column except i's, and a small product adds i's (now final)
+// columns to i+1 before its pass.  With profiling, one event pair brackets
+// each super-block step (the completing product and the pass with the
+// overlapped product).
 static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
   pamc_instance* I = b.I[0];
   const int T = I->R / 64;
@@ -702,7 +792,6 @@ static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
   a.S1 = I->Sd2;
   a.E0 = I->pop.E[0];
   a.E1 = I->pop.E[1];
-  a.G = I->Gd;
   a.thr = I->thr;
   a.st = I->st;
   a.n = I->n;
@@ -711,27 +800,43 @@ static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
   a.k0 = key0(I);
   a.k1 = key1(I);
   a.flip_ctr = I->prof ? I->flip_ctr : nullptr;
+  auto gbuf = [&](int i) { return I->Gd + (size_t)(i & 1) * kSB * I->R; };
+  const int nsb = (I->n + kSB - 1) / kSB;
   ctl_thresholds(b);
   for (int s = 0; s < nsweeps; ++s) {
-    for (int row0 = 0; row0 < I->n; row0 += kSB) {
-      const int rows = sb_rows(I, row0);
+    for (int i = 0; i < nsb; ++i) {
+      const int row0 = i * kSB, rows = sb_rows(I, row0);
       hipEvent_t e0 = nullptr;
       if (I->prof) {
         e0 = ctl_event(I);
         hipEventRecord(e0, I->stream);
       }
-      const GemmShape gsh = gemm_shape(I, rows);
-      k_dense_gemm<<<gsh.grid, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows, I->dn_pad,
-                                                    I->R, 1, gsh.kslice);
+      if (i == 0) {
+        const GemmLaunch gl = gemm_full(I, row0, rows, 1, gbuf(0));
+        k_dense_gemm<<<gl.grid, 256, 0, I->stream>>>(gl.g);
+      } else {
+        // the previous super-block's columns, final now
+        const int p0 = row0 - kSB;
+        const GemmLaunch gl = gemm_launch(I, row0, rows, 1, gbuf(i), p0, sb_rows(I, p0), 0, 0);
+        k_dense_gemm<<<gl.grid, 256, 0, I->stream>>>(gl.g);
+      }
+      a.G = gbuf(i);
+      const bool next = i + 1 < nsb;
+      GemmLaunch nx{};
+      if (next) {
+        const int n0 = row0 + kSB;
+        nx = gemm_launch(I, n0, sb_rows(I, n0), 1, gbuf(i + 1), 0, I->dn_pad - rows, row0, rows);
+      }
+      const int grid = T + (next ? nx.grid : 0);
+      if (I->rule == 1)
+        k_dense_step<1><<<grid, 256, 0, I->stream>>>(a, nx.g, s, row0, rows, T, next ? 1 : 0);
+      else
+        k_dense_step<0><<<grid, 256, 0, I->stream>>>(a, nx.g, s, row0, rows, T, next ? 1 : 0);
       if (I->prof) {
         hipEvent_t e1 = ctl_event(I);
         hipEventRecord(e1, I->stream);
         I->prof_launches += 1;
       }
-      if (I->rule == 1)
-        k_dense_seq<1><<<T, 256, 0, I->stream>>>(a, s, row0, rows);
-      else
-        k_dense_seq<0><<<T, 256, 0, I->stream>>>(a, s, row0, rows);
     }
     if (I->prof) I->prof_attempts += (int64_t)I->n * I->R;
   }
@@ -786,9 +891,8 @@ hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor) {
   // fields H[r][v] (replica-major) of the current population, for snapshots
   for (int row0 = 0; row0 < I->n; row0 += kSB) {
     const int rows = sb_rows(I, row0);
-    const GemmShape gsh = gemm_shape(I, rows);
-    k_dense_gemm<<<gsh.grid, 256, 0, I->stream>>>(I->Jd, I->Sd, I->Sd2, I->Gd, I->st, row0, rows, I->dn_pad, I->R,
-                                                  2, gsh.kslice);
+    const GemmLaunch gl = gemm_full(I, row0, rows, 2, I->Gd);
+    k_dense_gemm<<<gl.grid, 256, 0, I->stream>>>(gl.g);
     k_dense_collect_sb<<<std::min(1024, (rows * I->R + 255) / 256), 256, 0, I->stream>>>(
         I->Gd, H_rmajor, row0, rows, I->n, I->dn_pad, I->R);
   }
@@ -796,5 +900,6 @@ hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor) {
 }
 
 int32_t dense_superblock_rows() { return kSB; }
+int32_t dense_field_buffers() { return 2; }
 
 }  // namespace pamc

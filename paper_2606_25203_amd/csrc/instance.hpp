@@ -98,7 +98,7 @@ struct pamc_instance {
   int32_t dn_pad = 0;    // padded dimension of the dense matrix
   int8_t* Sd = nullptr;  // [R][dn_pad] replica-major spins (dense)
   int8_t* Sd2 = nullptr; // resampling buffer
-  int32_t* Gd = nullptr; // super-block field scratch [rows][R]
+  int32_t* Gd = nullptr; // super-block field buffers [2][rows][R]
   int64_t* Ed[2] = {nullptr, nullptr};
   // profiling
   bool prof = false;
@@ -229,6 +229,7 @@ hipEvent_t ctl_event(pamc_instance* I);
 
 // dense path launchers (dense.hip); b is the instance's batch of one
 int32_t dense_superblock_rows();
+int32_t dense_field_buffers();  // super-block field buffers (the next one is filled during a pass)
 hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor);
 hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed);
 hipError_t launch_init_dense(pamc_instance* I);
