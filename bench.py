@@ -416,14 +416,18 @@ def main():
     launch_ms = prof["ms"] / max(prof["launches"], 1)
     p_flip = prof["flips"] / max(prof["attempts"], 1)
     if w["kind"] == "dense":
-        # matrix-core partial fields of one 64-row block: 2 * 64 * n_pad * R ops
+        # One timed unit is a super-block step: the product completing this
+        # super-block's fields, then k_dense_step (its sequential pass with
+        # the next super-block's product on the other compute units).  Its
+        # matrix-core work is one super-block's share of the field products,
+        # 2 npad^2 R int8 ops per sweep; the step lasts as long as the
+        # sequential pass, so this fraction is that of the whole dense sweep.
         npad = (n + 63) // 64 * 64
-        # matrix-core field products: 2 npad^2 R int8 ops per sweep
         sweeps_done = prof["attempts"] / (n * w["R"])
         ops = 2.0 * npad * npad * w["R"] * sweeps_done / max(prof["launches"], 1)
         achieved = ops / (launch_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_dense_gemm", "bound": "mfma", "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS,
-                "unit": "TOP/s (int8)", "frac": achieved / MFMA_I8_PEAK_TOPS,
+        roof = {"kernel": "k_dense_step (+ k_dense_gemm)", "bound": "mfma", "achieved": achieved,
+                "peak": MFMA_I8_PEAK_TOPS, "unit": "TOP/s (int8)", "frac": achieved / MFMA_I8_PEAK_TOPS,
                 "traffic": counters_traffic(w["counters"], "dense.hip"), "launch_ms": launch_ms,
                 "launches": prof["launches"], "ops_per_launch": ops, "flip_rate": p_flip}
     else:
