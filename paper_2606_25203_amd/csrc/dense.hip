@@ -708,13 +708,16 @@ static inline int sb_rows(const pamc_instance* I, int row0) { return std::min(kS
 struct GemmShape {
   int grid, kslice;
 };
-// About 512 work-groups: the K range is cut into P slices of whole stages;
+// About 512 work-groups: the K range is cut into P slices of whole stages
+// (at least 8 per slice);
 // the grid covers the slices in groups of 8 (one per XCD; work-groups of
 // slices past the end return at once).
 static inline GemmShape gemm_shape(const pamc_instance* I, int rows, int kcount) {
   const int tiles = ((rows + kGM - 1) / kGM) * ((I->R + kGN - 1) / kGN);
   const int stages = std::max(1, kcount / kGK);
-  const int P = std::max(1, std::min(stages, (512 + tiles - 1) / tiles));
+  // at least 8 stages per work-group: a short K range (the previous
+  // super-block's columns) is not worth 16 atomic tile updates per stage
+  const int P = std::max(1, std::min(stages / 8, (512 + tiles - 1) / tiles));
   const int kslice = ((stages + P - 1) / P) * kGK;
   const int slices = (kcount + kslice - 1) / kslice;
   return {tiles * ((slices + 7) / 8) * 8, kslice};
