@@ -140,7 +140,10 @@ pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, cons
  *     else label 1 if tanh(Delta_2) = (omega_1 - omega_2) / s12 exceeds
  *     eta_2 = u_1/2^31 - 1, else label 2 (exact Gibbs); each compared as
  *     numerator > eta * denominator.
- * u_0..u_3 are the words of Philox(vertex, sweep, replica, 6).  This update
+ * u_0.. are the visit's W words (W = K, or 2 for the cascade): the four
+ * vertices of a quad (id / 4, internal ids) share the W Philox blocks
+ * (quad, sweep, replica, 6 | b << 8), b = 0..W-1, read as one sequence of 4W
+ * words, vertex id % 4 = k taking words kW .. kW + W - 1.  This update
  * at beta leaves e^{-(beta/2) E} invariant, so resampling weighs replicas by
  * e^{-(Delta/2) (E - E_ref)} (ln Q likewise).  Cluster moves and the pair
  * distance are not defined for labels (PAMC_ERR_UNSUPPORTED; pamc_anneal

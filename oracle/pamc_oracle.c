@@ -607,14 +607,27 @@ int32_t orc_potts_choose(int32_t K, int32_t potts_rule, double gamma, double bet
   return best;
 }
 
+/* Uniform words of a Potts visit: a visit takes W words (W = K for the
+ * softmax, 2 for the cascade); the four vertices of a quad (v >> 2) share W
+ * Philox blocks (quad, sweep, replica, POTTS | b << 8), b = 0..W-1, read as
+ * one sequence of 4W words, of which vertex v takes words (v & 3) W ..
+ * (v & 3) W + W - 1. */
+static void potts_words(const orc* o, int32_t r, int32_t v, uint32_t* u) {
+  int32_t W = o->potts_rule == ORC_POTTS_CASCADE ? 2 : o->potts_K;
+  uint32_t blk[16];
+  for (int32_t b = 0; b < W; ++b)
+    philox(o->seed, (uint32_t)(v >> 2), o->gs, (uint32_t)r, ORC_TAG_POTTS | ((uint32_t)b << 8), blk + 4 * b);
+  for (int32_t k = 0; k < W; ++k) u[k] = blk[(v & 3) * W + k];
+}
+
 /* Potts update of vertex v in replica r: the K-label field (Eq. 7), the
  * new label, and the Eq. 6 energy change -2 (syn_new - syn_old). */
 static void potts_visit(orc* o, int32_t r, int32_t v, double beta) {
   int8_t* lab = o->s + (size_t)r * o->n;
   int64_t syn[4] = {0, 0, 0, 0};
   for (int32_t e = o->row_ptr[v]; e < o->row_ptr[v + 1]; ++e) syn[lab[o->col[e]]] += o->J[e];
-  uint32_t u[4];
-  philox(o->seed, (uint32_t)v, o->gs, (uint32_t)r, ORC_TAG_POTTS, u);
+  uint32_t u[4] = {0, 0, 0, 0};
+  potts_words(o, r, v, u);
   int32_t old = lab[v];
   int32_t nw = orc_potts_choose(o->potts_K, o->potts_rule, o->potts_gamma, beta, syn, u);
   if (nw != old) {

@@ -387,10 +387,10 @@ __global__ void __launch_bounds__(256) k_sweep_push(const Desc* __restrict__ D,
 //   cascade: label 0 iff w0 - s12 > eta_1 (w0 + s12), s12 = w1 + w2 (the
 //     p-bit tanh(Delta_1) > eta_1), else label 1 iff w1 - w2 > eta_2 s12,
 //     else 2; eta = u 2^-31 - 1;
-// u = Philox(v, sweep, r, POTTS).  Every operation is a correctly rounded
-// binary64 operation in a fixed order (no contraction), so the choice is
-// the same wherever it is computed.  The energy (Eq. 6) changes by
-// -2 (syn_new - syn_old).
+// u: the visit's words of its quad's Philox blocks (below).  Every operation
+// is a correctly rounded binary64 operation in a fixed order (no
+// contraction), so the choice is the same wherever it is computed.  The
+// energy (Eq. 6) changes by -2 (syn_new - syn_old).
 // ---------------------------------------------------------------------------
 template <int K>
 __device__ __forceinline__ int32_t syn_of(const int32_t (&syn)[K], int k) {
@@ -401,8 +401,8 @@ __device__ __forceinline__ int32_t syn_of(const int32_t (&syn)[K], int k) {
 }
 
 template <int K>
-__device__ __forceinline__ int potts_choose(const int32_t (&syn)[K], const u32x4& u, const double* __restrict__ tab,
-                                            int32_t last, int rule, double gamma) {
+__device__ __forceinline__ int potts_choose(const int32_t (&syn)[K], const uint32_t (&u)[K],
+                                            const double* __restrict__ tab, int32_t last, int rule, double gamma) {
   int32_t m = syn[0];
 #pragma unroll
   for (int k = 1; k < K; ++k) m = max(m, syn[k]);
@@ -415,9 +415,9 @@ __device__ __forceinline__ int potts_choose(const int32_t (&syn)[K], const u32x4
   if constexpr (K == 3) {
     if (rule == 1) {
       const double s12 = om[1] + om[2];
-      const double eta1 = (double)u.a * (1.0 / 2147483648.0) - 1.0;
+      const double eta1 = (double)u[0] * (1.0 / 2147483648.0) - 1.0;
       if (om[0] - s12 > eta1 * (om[0] + s12)) return 0;
-      const double eta2 = (double)u.b * (1.0 / 2147483648.0) - 1.0;
+      const double eta2 = (double)u[1] * (1.0 / 2147483648.0) - 1.0;
       return om[1] - om[2] > eta2 * s12 ? 1 : 2;
     }
   }
@@ -425,10 +425,10 @@ __device__ __forceinline__ int potts_choose(const int32_t (&syn)[K], const u32x4
 #pragma unroll
   for (int k = 0; k < K; ++k) S += om[k];
   int best = 0;
-  double bs = om[0] - (gamma * ((double)u.a * (1.0 / 4294967296.0))) * S;
+  double bs = om[0] - (gamma * ((double)u[0] * (1.0 / 4294967296.0))) * S;
 #pragma unroll
   for (int k = 1; k < K; ++k) {
-    const double sc = om[k] - (gamma * ((double)pick(u, k) * (1.0 / 4294967296.0))) * S;
+    const double sc = om[k] - (gamma * ((double)u[k] * (1.0 / 4294967296.0))) * S;
     if (sc > bs) {
       bs = sc;
       best = k;
@@ -526,6 +526,21 @@ __global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
       const bool in = v >= v0 && v < v1;
       gather_labels<K>(gcol, gJ, in ? grow[v] : 0, in ? grow[v + 1] : 0, Sr, voff, synq[k]);
     }
+    // uniform words: W per visit (K, or 2 for the cascade); the quad's
+    // visits share W Philox blocks (quad, sweep, replica, POTTS | b << 8),
+    // read as one sequence, vertex k of the quad taking words k W .. k W + W-1
+    uint32_t uw[4 * K];
+    const bool cascade = K == 3 && rule == 1;
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+      if (b < 2 || !cascade) {
+        const u32x4 w = philox10((uint32_t)q, gs, r, kTagPotts | ((uint32_t)b << 8), d.k0, d.k1);
+        uw[4 * b] = w.a;
+        uw[4 * b + 1] = w.b;
+        uw[4 * b + 2] = w.c;
+        uw[4 * b + 3] = w.d;
+      }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
@@ -533,7 +548,9 @@ __global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
         int32_t syn[K];
 #pragma unroll
         for (int c = 0; c < K; ++c) syn[c] = synq[k][c];
-        const u32x4 u = philox10((uint32_t)v, gs, r, kTagPotts, d.k0, d.k1);
+        uint32_t u[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) u[c] = cascade ? (c < 2 ? uw[2 * k + c] : 0u) : uw[K * k + c];
         const int old = (int)((sw >> (8 * k)) & 0xFFu);
         const int nw = potts_choose<K>(syn, u, tab, last, rule, gamma);
         if (nw != old) {
