@@ -66,7 +66,7 @@ void free_instance(pamc_instance* I) {
                   I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order,
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
                   I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
-                  I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Ed[0], I->Ed[1],
+                  I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Cd, I->Ed[0], I->Ed[1],
                   I->flip_ctr, I->H_scratch, I->ptab};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -509,6 +509,7 @@ pamc_status build_dense_common(pamc_instance* I, int32_t n) {
   const size_t gsz = (size_t)pamc::dense_field_buffers() * pamc::dense_superblock_rows() * I->R;
   HIP_TRY(dalloc(I, &I->Gd, gsz), "alloc fields");
   HIP_TRY(hipMemsetAsync(I->Gd, 0, sizeof(int32_t) * gsz, I->stream), "memset");
+  HIP_TRY(dalloc(I, &I->Cd, np * (size_t)I->R), "alloc critical fields");
   I->order_cap = 1;
   HIP_TRY(dalloc(I, &I->order, 1), "alloc");
   HIP_TRY(hipMemsetAsync(I->flip_ctr, 0, sizeof(int64_t) * 512, I->stream), "memset");

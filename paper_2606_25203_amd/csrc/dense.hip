@@ -32,12 +32,13 @@ namespace pamc {
 namespace {
 
 constexpr int kDB = 64;          // spins per sequential block
-static_assert(kDB / 4 == 2 + 7 + 7, "the helper waves' share of the Philox groups assumes 16 groups");
+static_assert(kDB / 4 == 4 + 6 + 6, "the helper waves' share of the critical-field groups assumes 16 groups");
 constexpr int kSB = 1024;        // rows per super-block: one field product, one sequential launch
 constexpr int kGM = 128, kGN = 128, kGK = 64;  // field-product tile: rows x replicas x K stage
 constexpr int kLdsRow = kGK + 16;              // bytes per staged row (padded)
 constexpr int kGStages = 3;                    // field-product K stages in flight per thread
 constexpr int kThrL = 2047;      // half-width of the LDS copy of the threshold table
+constexpr int32_t kCritInf = 1 << 30;  // critical field of a visit that flips (or not) at every x
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // J_ij = J_ji = +-1 from the low bit of Philox(key = seed; (i, j, 0, DENSE))
@@ -251,6 +252,7 @@ struct SeqArgs {
   int64_t* E1;
   int32_t* G;   // [kSB][R] fields of the super-block rows against its starting spins
   const uint32_t* thr;
+  const v4i* C;  // [n_pad / 4][R] critical fields of the sweep (k_dense_crit)
   RunState* st;
   int32_t n, np, R;
   uint32_t k0, k1;
@@ -258,27 +260,82 @@ struct SeqArgs {
 };
 
 
+// Critical fields of one sweep's visits.  The thresholds T[x + Xl] (|x| <=
+// Xl) do not increase with x, so the test u < T[x + Xl] holds exactly for
+// x < c - Xl, c = the number of leading entries of T[0 .. 2Xl] above u.  The
+// stored value is c - Xl, with c = 0 stored as -2^30 and c = 2Xl + 1 as
+// +2^30, so that a field beyond the table (|x| > Xl, when the table is
+// saturated) meets the decision of the clamped lookup (|x| < 2^30 - 2^12);
+// Metropolis then raises it to 1 (x <= 0 always flips).  C[q][r] holds the
+// four spins of quad q for replica r, from the same Philox words (q, sweep,
+// r, SWEEP) as the visits.  The table lives in LDS; the search is a
+// fixed-step binary lifting over it.
+template <int RULE>
+__global__ void __launch_bounds__(256) k_dense_crit(const uint32_t* thr, const RunState* st, v4i* C,
+                                                    int32_t sweep_idx, int32_t nq, int32_t R, uint32_t k0,
+                                                    uint32_t k1) {
+  __shared__ uint32_t thr_s[2 * kThrL + 1];
+  if (!st->active) return;
+  const int32_t Xt = (int32_t)st->table_x, Xl = min(Xt, kThrL), L = 2 * Xl + 1;
+  const uint32_t gs = st->gs + (uint32_t)sweep_idx;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) thr_s[i] = thr[Xt - Xl + i];
+  __syncthreads();
+  const int64_t total = (int64_t)nq * R, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t q = (int32_t)(first / R), r = (int32_t)(first % R);
+  const int32_t dq = (int32_t)(stride / R), dr = (int32_t)(stride % R);
+  for (int64_t it = first; it < total; it += stride) {
+    const u32x4 w = philox10((uint32_t)q, gs, (uint32_t)r, kTagSweep, k0, k1);
+    int32_t pos[4] = {0, 0, 0, 0};
+    // pos + step <= 4096 - step before each step, so every read is inside
+    // the table's 2 kThrL + 1 entries (entries at or past L are never taken)
+#pragma unroll
+    for (int step = 2048; step > 0; step >>= 1)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int32_t p = pos[kk] + step;
+        const uint32_t tv = thr_s[p - 1];
+        pos[kk] = (p <= L && tv > pick(w, kk)) ? p : pos[kk];
+      }
+    v4i c;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      int32_t v = pos[kk] == 0 ? -kCritInf : pos[kk] == L ? kCritInf : pos[kk] - Xl;
+      if (RULE == 1) v = max(v, 1);
+      c[kk] = v;
+    }
+    C[it] = c;
+    q += dq;
+    r += dr;
+    if (r >= R) {
+      r -= R;
+      q += 1;
+    }
+  }
+}
+
 // One pass over the 64 spins of one block for one replica per lane (wave 0):
 // h_k = gsum_k + sum_{k' < k in block} J_kk' d_k' (d = 2 s_new of flipped
-// spins, packed int8, dot4), x = s h, flip iff u < T[x] (Metropolis also for
-// x <= 0), u from the block's Philox words in LDS; every spin of the block
-// is below n.  sw: the block's 16 starting spin words; d: the block's d
-// words.  Thresholds come from the LDS
-// table with x clamped to +-Xl; the pass returns whether any lane met
-// |x| > Xl.  It has no branches, so the compiler can move the independent
-// work (Philox, the couplings to earlier groups, LDS reads) into the
-// latency of the decision chain.
-template <int RULE>
+// spins, packed int8, dot4), x = s h, flip iff x < cc (the visit's critical
+// field, from LDS); every spin of the block is below n.  sw: the block's 16
+// starting spin words; d: the block's d words.  With WIDE the pass also
+// returns whether any lane met |x| > Xl (needed only when the LDS table is
+// narrower than the full one).  The sign is applied as a mask, m = 0 or -1:
+// x < cc is (h ^ m) < cc + m, since h ^ -1 = -h - 1.  The pass has no
+// branches, so the compiler can move the independent work (the couplings to
+// earlier groups, LDS reads) into the latency of the decision chain, which
+// per spin is dot4, xor, compare, select.
+template <int RULE, bool WIDE>
 __device__ __forceinline__ bool decide_pass(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
-                                            const u32x4 (*rnd_s)[64], const uint32_t* thr_s, int32_t Xl,
-                                            const uint32_t (&sw)[kDB / 4], int lane, uint32_t (&d)[kDB / 4],
-                                            int32_t& dE32, int32_t& nflip) {
-  bool wide = false;
+                                            const v4i (*crit)[64], int32_t Xl, const uint32_t (&sw)[kDB / 4],
+                                            int lane, uint32_t (&d)[kDB / 4], int32_t& dE32, int32_t& nflip) {
+  uint32_t wide = 0;
+  int32_t xsum = 0, nf = 0;
 #pragma unroll
   for (int g = 0; g < kDB / 4; ++g) d[g] = 0;
 #pragma unroll
   for (int g = 0; g < kDB / 4; ++g) {
-    const u32x4 rnd = rnd_s[g][lane];
+    const v4i cc = crit[g][lane];
     // couplings to the flips of the earlier groups of the block: four
     // independent accumulations, in group order, so only the last one
     // (the previous group's flips) waits for the decision chain
@@ -293,30 +350,28 @@ __device__ __forceinline__ bool decide_pass(const uint32_t (*jd)[kDB / 4], const
       base[kk] = p;
       jg[kk] = jd[k][g];
     }
-    // x = s h = s base + J . (s d): the group's flips are kept both as d
-    // (dg) and as -d (ndg), so the chain from one decision to the next is
-    // select, dot4, clamp, table read, compare, select
     const uint32_t w = sw[g];
-    uint32_t dg = 0, ndg = 0;
+    // the d byte of a flip, -2 s: 0xFE for s = +1 (0x01), 0x02 for s = -1 (0xFF)
+    const uint32_t bw = 0xFEFEFEFEu ^ (((w >> 7) & 0x01010101u) * 0xFCu);
+    uint32_t dg = 0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const bool neg = (w >> (8 * kk + 7)) & 1u;  // s = -1 (its own spin has not changed yet)
-      const int32_t xb = neg ? -base[kk] : base[kk];
-      const int32_t x = __builtin_amdgcn_sdot4((int)jg[kk], (int)(neg ? ndg : dg), xb, false);
-      const int32_t xl = min(max(x, -Xl), Xl);
-      wide = wide || x != xl;
-      bool flip = pick(rnd, kk) < thr_s[xl + Xl];
-      if (RULE == 1) flip = flip || x <= 0;
-      // d = 2 s_new = -2 s: byte 0xFE for s = +1, 0x02 for s = -1
-      const uint32_t bp = (neg ? 0x02u : 0xFEu) << (8 * kk), bn = (neg ? 0xFEu : 0x02u) << (8 * kk);
-      dg = flip ? dg | bp : dg;
-      ndg = flip ? ndg | bn : ndg;
-      dE32 += flip ? x : 0;
-      nflip += flip ? 1 : 0;
+      const int32_t m = -(int32_t)((w >> (8 * kk + 7)) & 1u);  // its own spin has not changed yet
+      const int32_t h = __builtin_amdgcn_sdot4((int)jg[kk], (int)dg, base[kk], false);
+      const int32_t y = h ^ m;  // x = y - m
+      if (WIDE) wide |= (uint32_t)(h + Xl) > (uint32_t)(2 * Xl);
+      const bool flip = y < cc[kk] + m;
+      dg = flip ? dg | (bw & (0xFFu << (8 * kk))) : dg;
+      xsum += flip ? y - m : 0;
     }
     d[g] = dg;
   }
-  return wide;
+  // a flipped byte is 0xFE or 0x02, both with bit 1 set
+#pragma unroll
+  for (int g = 0; g < kDB / 4; ++g) nf += __builtin_popcount(d[g] & 0x02020202u);
+  dE32 += xsum;
+  nflip += nf;
+  return wide != 0;
 }
 
 struct BlockTally {
@@ -362,26 +417,28 @@ __device__ __noinline__ BlockTally decide_block_exact(const uint32_t (*jd)[kDB /
   return t;
 }
 
-// Decides the 64 spins of one block; d words into dout (LDS).  The LDS
-// table covers |x| <= Xl; when it is narrower than the table (Xl < Xt) and
-// some lane met a field beyond it, the block is decided again, exactly,
-// from its starting spins (one uniform branch per block keeps the common
-// pass free of control flow).  The last block of the matrix, which holds
-// spins at or beyond n, takes the exact path directly.
+// Decides the 64 spins of one block; d words into dout (LDS).  The critical
+// fields cover |x| <= Xl; when the LDS table is narrower than the full one
+// (Xl < Xt) and some lane met a field beyond it, the block is decided
+// again, exactly, from its starting spins (one uniform branch per block
+// keeps the common pass free of control flow).  The last block of the
+// matrix, which holds spins at or beyond n, takes the exact path directly,
+// and so does every block when the table is not monotone (all_exact).
 template <int RULE>
 __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
-                                             const u32x4 (*rnd_s)[64], const uint32_t* thr_s, double beta,
-                                             int32_t Xl, int32_t Xt, const uint32_t* sw0, uint32_t* dout, int rb0,
-                                             int n, uint32_t gs, uint32_t r, uint32_t k0, uint32_t k1, int lane,
-                                             int64_t& dE, int32_t& nflip) {
+                                             const v4i (*crit)[64], const uint32_t* thr_s, double beta,
+                                             int32_t Xl, int32_t Xt, bool all_exact, const uint32_t* sw0,
+                                             uint32_t* dout, int rb0, int n, uint32_t gs, uint32_t r, uint32_t k0,
+                                             uint32_t k1, int lane, int64_t& dE, int32_t& nflip) {
   int32_t dE32 = 0, nf = 0;  // |dE32| <= 64 X < 2^31 (X < 2^25)
-  bool exact = rb0 + kDB > n;
+  bool exact = all_exact || rb0 + kDB > n;
   if (!exact) {
     uint32_t sw[kDB / 4], d[kDB / 4];
 #pragma unroll
     for (int g = 0; g < kDB / 4; ++g) sw[g] = sw0[g];
-    const bool wide = decide_pass<RULE>(jd, gsum, rnd_s, thr_s, Xl, sw, lane, d, dE32, nf);
-    exact = Xl < Xt && __builtin_amdgcn_ballot_w64(wide);
+    const bool wide = Xl < Xt ? decide_pass<RULE, true>(jd, gsum, crit, Xl, sw, lane, d, dE32, nf)
+                              : decide_pass<RULE, false>(jd, gsum, crit, Xl, sw, lane, d, dE32, nf);
+    exact = __builtin_amdgcn_ballot_w64(wide) != 0;
     if (!exact) {
 #pragma unroll
       for (int g = 0; g < kDB / 4; ++g) dout[g] = d[g];
@@ -412,7 +469,7 @@ struct SeqLds {
   uint32_t thr_s[2 * kThrL + 1];  // thresholds for |x| <= Xl
   __attribute__((aligned(16))) int8_t dsl[64][kSB + 16];  // spin changes d, [replica][row - row0]
   uint32_t swl[2][64][kDB / 4 + 1];                       // the block's spin words, [replica][word]
-  __attribute__((aligned(16))) u32x4 rnd_s[kDB / 4][64];  // the block's Philox words, [group][replica]
+  __attribute__((aligned(16))) v4i crit[kDB / 4][64];     // the block's critical fields, [group][replica]
 };
 
 template <int RULE>
@@ -423,7 +480,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
   auto& thr_s = L.thr_s;
   auto& dsl = L.dsl;
   auto& swl = L.swl;
-  auto& rnd_s = L.rnd_s;
+  auto& crit = L.crit;
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
@@ -461,8 +518,9 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
   };
   // new spin words of block bb from its starting words and its d words: a
   // byte of d is 0 (no flip), 2 or -2, and a flip turns 0x01 <-> 0xFF, i.e.
-  // xor 0xFE.  Same (replica, word) per thread as load_diag, so a thread
-  // reads swl[buf] here before its own load_diag overwrites it.
+  // xor 0xFE.  In the loop, thread t of 128 (waves 2 and 3) takes the same
+  // (replica, word) items as put_diag, so it reads swl[buf] here before its
+  // own put_diag overwrites them.
   auto store_block = [&](int bb, int buf, int t, int nt) {
     for (int i = t; i < kDB * kDB / 4; i += nt) {
       const int k = i / (kDB / 4), g = i % (kDB / 4);
@@ -471,16 +529,43 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
           swl[buf][k][g] ^ ((dw & 0x02020202u) * 0x7Fu);
     }
   };
-  // matrix-core product over the first 64 nsteps columns of the super-block
-  // for the 16-row strip sr of block bb: acc += J[strip rows][cols] . dsl[:, cols]
-  // (all of the strip's J fragments are loaded before the first product, so
-  // their latencies overlap)
-  auto strip_product = [&](int bb, int sr, int nsteps, v4i (&acc)[4]) {
+  // the diagonal block of bb into registers (thread t of nt, the same
+  // (replica, word) items as store_block) and from there into LDS
+  constexpr int kDiagPer = kDB * kDB / 4 / 128;
+  auto fetch_diag = [&](int bb, int t, uint32_t (&dj)[kDiagPer], uint32_t (&dsw)[kDiagPer]) {
+    const int rb0 = row0 + bb * kDB;
+#pragma unroll
+    for (int it = 0; it < kDiagPer; ++it) {
+      const int i = t + 128 * it, k = i / (kDB / 4), g = i % (kDB / 4);
+      dj[it] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 4 * g);
+      dsw[it] = *reinterpret_cast<const uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + rb0 + 4 * g);
+    }
+  };
+  auto put_diag = [&](int buf, int t, const uint32_t (&dj)[kDiagPer], const uint32_t (&dsw)[kDiagPer]) {
+#pragma unroll
+    for (int it = 0; it < kDiagPer; ++it) {
+      const int i = t + 128 * it, k = i / (kDB / 4), g = i % (kDB / 4);
+      jd[buf][k][g] = dj[it];
+      swl[buf][k][g] = dsw[it];
+    }
+  };
+  // the 16-row strip sr of block bb against the first 64 nsteps columns of
+  // the super-block: its J fragments, and its fields from G (fragment
+  // layout: row 4 (lane / 16) + j of the strip, replica 16 nt + lane % 16)
+  auto load_strip = [&](int bb, int sr, int nsteps, v4i (&av)[kSB / kDB], int32_t (&gv)[16]) {
     const int8_t* arow = a.J + (size_t)(row0 + bb * kDB + 16 * sr + (lane & 15)) * a.np + row0 + 16 * (lane >> 4);
-    v4i av[kSB / kDB];
 #pragma unroll
     for (int k = 0; k < kSB / kDB; ++k)
       if (k < nsteps) av[k] = *reinterpret_cast<const v4i*>(arow + 64 * k);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        gv[4 * nt + j] = a.G[(size_t)(bb * kDB + 16 * sr + 4 * (lane >> 4) + j) * a.R + tile * 64 + nt * 16 +
+                             (lane & 15)];
+  };
+  // acc += J[strip rows][cols] . dsl[:, cols] on the matrix cores
+  auto strip_product = [&](int nsteps, const v4i (&av)[kSB / kDB], v4i (&acc)[4]) {
 #pragma unroll
     for (int k = 0; k < kSB / kDB; ++k) {
       if (k < nsteps) {
@@ -492,34 +577,36 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       }
     }
   };
-  // result fragment (row 4 (lane / 16) + j of the strip, replica 16 nt +
-  // lane % 16) of strip sr into gsum[buf]; with G, the fields are taken
-  // from the field product (and cleared there) in the same pass
-  auto add_strip = [&](int bb, int buf, int sr, const v4i (&acc)[4], bool with_g) {
+  // result fragment of strip sr into gsum[buf]: with G, the fields gv
+  // taken from the field product plus the product (G is cleared behind for
+  // the next super-block's product), else added to gsum
+  auto add_strip = [&](int bb, int buf, int sr, const v4i (&acc)[4], const int32_t* gv) {
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 16 * sr + 4 * (lane >> 4) + j, c = nt * 16 + (lane & 15);
-        if (with_g) {
-          int32_t* gp = a.G + (size_t)(bb * kDB + k) * a.R + tile * 64 + c;
-          gsum[buf][k][c] = *gp + acc[nt][j];
-          *gp = 0;
+        if (gv) {
+          gsum[buf][k][c] = gv[4 * nt + j] + acc[nt][j];
+          a.G[(size_t)(bb * kDB + k) * a.R + tile * 64 + c] = 0;
         } else {
           gsum[buf][k][c] += acc[nt][j];
         }
       }
   };
-  // Philox words of block bb, group g (four spins), this lane's replica
-  auto philox_group = [&](int bb, int g) {
-    return philox10((uint32_t)(((row0 + bb * kDB) >> 2) + g), gs, (uint32_t)r, kTagSweep, a.k0, a.k1);
-  };
+  // critical fields of block bb, group g (four spins), this lane's replica
+  auto crit_group = [&](int bb, int g) { return a.C[(size_t)(((row0 + bb * kDB) >> 2) + g) * a.R + r]; };
   if (nb > 0) {
     load_fields(0, 0);
     load_diag(0, 0, threadIdx.x, blockDim.x);
-    for (int g = wave; g < kDB / 4; g += 4) rnd_s[g][lane] = philox_group(0, g);
+    for (int g = wave; g < kDB / 4; g += 4) crit[g][lane] = crit_group(0, g);
   }
   __syncthreads();
+  // the critical fields assume thresholds that do not increase with x;
+  // should the table ever break that, every block takes the exact path
+  bool mono = true;
+  for (int i = threadIdx.x; i < 2 * Xl; i += blockDim.x) mono = mono && thr_s[i] >= thr_s[i + 1];
+  const bool all_exact = !__syncthreads_and(mono);
   int64_t dE = 0;
   int32_t nflip = 0;
   const v4i zero = {0, 0, 0, 0};
@@ -532,43 +619,59 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
     if (next)
       a_next = *reinterpret_cast<const v4i*>(a.J + (size_t)(rb0 + kDB + 16 * wave + (lane & 15)) * a.np + rb0 +
                                              16 * (lane >> 4));
-    // waves 1..3: the Philox words of block b+1 (held in registers until
-    // wave 0 is done with block b's); wave 1, which also takes a second
-    // strip, computes 2 of the 16 groups, waves 2 and 3 seven each
-    constexpr int kRndPerHelper = 7;
-    const int rnd_g0 = wave == 1 ? 0 : wave == 2 ? 2 : 9;
-    const int rnd_cnt = wave == 1 ? 2 : 7;
-    u32x4 rnd_next[kRndPerHelper];
+    // waves 1..3: the critical fields of block b+1 (held in registers
+    // until wave 0 is done with block b's); wave 1, which also takes a
+    // second strip, loads 4 of the 16 groups, waves 2 and 3 six each
+    constexpr int kCritPerHelper = 6;
+    const int crit_g0 = wave == 1 ? 0 : wave == 2 ? 4 : 10;
+    const int crit_cnt = wave == 1 ? 4 : 6;
+    v4i crit_next[kCritPerHelper];
     if (wave == 0) {
       // the d words go to the super-block's spin changes; the helpers
       // write the block's spins back while the next block is decided
-      decide_block<RULE>(jd[cb], gsum[cb], rnd_s, thr_s, beta, Xl, Xt, swl[cb][lane],
+      decide_block<RULE>(jd[cb], gsum[cb], crit, thr_s, beta, Xl, Xt, all_exact, swl[cb][lane],
                          reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]), rb0, a.n, gs, (uint32_t)r, a.k0, a.k1,
                          lane, dE, nflip);
     } else {
-      // the spins of block b-1 go back to memory (its words are in
-      // swl[cb ^ 1] until load_diag below replaces them)
-      if (b > 0) store_block(b - 1, cb ^ 1, threadIdx.x - 64, 192);
+      // the global reads for block b+1 are issued before any of them is
+      // used, so that their latencies overlap: its critical fields, this
+      // wave's first strip (wave 1 takes strips 0 and 3, the second once the
+      // first is multiplied, waves 2 and 3 strips 1 and 2) and, for waves 2
+      // and 3, its diagonal J block and spin words
+      const int ns = wave == 1 ? 2 : 1;
+      v4i av[kSB / kDB];
+      int32_t gv[2][16];
+      uint32_t dj[kDiagPer], dsw[kDiagPer];
       if (next) {
 #pragma unroll
-        for (int i = 0; i < kRndPerHelper; ++i)
-          if (i < rnd_cnt) rnd_next[i] = philox_group(b + 1, rnd_g0 + i);
-        // strips 0..3 of block b+1 (wave 1 also takes strip 3), then the
-        // diagonal J block
-        for (int sr = wave - 1; sr < 4; sr += 3) {
-          v4i acc[4] = {zero, zero, zero, zero};
-          strip_product(b + 1, sr, b, acc);
-          add_strip(b + 1, cb ^ 1, sr, acc, true);
+        for (int i = 0; i < kCritPerHelper; ++i)
+          if (i < crit_cnt) crit_next[i] = crit_group(b + 1, crit_g0 + i);
+        load_strip(b + 1, wave - 1, b, av, gv[0]);
+        if (wave >= 2) fetch_diag(b + 1, threadIdx.x - 128, dj, dsw);
+      }
+      // the spins of block b-1 go back to memory (its words are in
+      // swl[cb ^ 1] until put_diag below replaces them, same items per
+      // thread)
+      if (b > 0 && wave >= 2) store_block(b - 1, cb ^ 1, threadIdx.x - 128, 128);
+      if (next) {
+#pragma unroll
+        for (int si = 0; si < 2; ++si) {
+          if (si < ns) {
+            v4i acc[4] = {zero, zero, zero, zero};
+            if (si == 1) load_strip(b + 1, 3, b, av, gv[1]);
+            strip_product(b, av, acc);
+            add_strip(b + 1, cb ^ 1, si == 0 ? wave - 1 : 3, acc, gv[si]);
+          }
         }
-        load_diag(b + 1, cb ^ 1, threadIdx.x - 64, 192);
+        if (wave >= 2) put_diag(cb ^ 1, threadIdx.x - 128, dj, dsw);
       }
     }
     __syncthreads();
     if (next) {
       if (wave != 0) {
 #pragma unroll
-        for (int i = 0; i < kRndPerHelper; ++i)
-          if (i < rnd_cnt) rnd_s[rnd_g0 + i][lane] = rnd_next[i];
+        for (int i = 0; i < kCritPerHelper; ++i)
+          if (i < crit_cnt) crit[crit_g0 + i][lane] = crit_next[i];
       }
       // block b's own flips, strip `wave` of block b+1
       v4i acc[4] = {zero, zero, zero, zero};
@@ -577,7 +680,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
         const v4i bv = *reinterpret_cast<const v4i*>(&dsl[nt * 16 + (lane & 15)][b * kDB + 16 * (lane >> 4)]);
         acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a_next, bv, acc[nt], 0, 0, 0);
       }
-      add_strip(b + 1, cb ^ 1, wave, acc, false);
+      add_strip(b + 1, cb ^ 1, wave, acc, nullptr);
     }
     __syncthreads();
   }
@@ -779,7 +882,8 @@ hipError_t launch_init_dense(pamc_instance* I) {
 }
 
 // Sweeps of the dense path, super-block by super-block (rows row0_i ..).
-// The field buffer alternates between two halves of Gd.  Super-block 0 of a
+// The field buffer alternates between two halves of Gd.  Each sweep starts
+// with its critical fields (every visit's, one launch); super-block 0 of a
 // sweep gets its full product first; then, for each super-block i, the
 // launch that runs its sequential pass also computes the product of i+1
 // over every column except i's, and a small product adds i's (now final)
@@ -796,6 +900,7 @@ static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
   a.E0 = I->pop.E[0];
   a.E1 = I->pop.E[1];
   a.thr = I->thr;
+  a.C = reinterpret_cast<const v4i*>(I->Cd);
   a.st = I->st;
   a.n = I->n;
   a.np = I->dn_pad;
@@ -815,6 +920,14 @@ static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
         hipEventRecord(e0, I->stream);
       }
       if (i == 0) {
+        // the sweep's critical fields, then super-block 0's full product
+        const int64_t items = (int64_t)(I->dn_pad / 4) * I->R;
+        const int cgrid = (int)std::min<int64_t>((items + 255) / 256, 2048);
+        v4i* C = reinterpret_cast<v4i*>(I->Cd);
+        if (I->rule == 1)
+          k_dense_crit<1><<<cgrid, 256, 0, I->stream>>>(I->thr, I->st, C, s, I->dn_pad / 4, I->R, a.k0, a.k1);
+        else
+          k_dense_crit<0><<<cgrid, 256, 0, I->stream>>>(I->thr, I->st, C, s, I->dn_pad / 4, I->R, a.k0, a.k1);
         const GemmLaunch gl = gemm_full(I, row0, rows, 1, gbuf(0));
         k_dense_gemm<<<gl.grid, 256, 0, I->stream>>>(gl.g);
       } else {

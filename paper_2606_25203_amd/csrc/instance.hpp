@@ -99,6 +99,7 @@ struct pamc_instance {
   int8_t* Sd = nullptr;  // [R][dn_pad] replica-major spins (dense)
   int8_t* Sd2 = nullptr; // resampling buffer
   int32_t* Gd = nullptr; // super-block field buffers [2][rows][R]
+  int32_t* Cd = nullptr; // critical fields of a sweep [dn_pad / 4][R][4]
   int64_t* Ed[2] = {nullptr, nullptr};
   // profiling
   bool prof = false;
