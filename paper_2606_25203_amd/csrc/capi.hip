@@ -732,6 +732,7 @@ pamc_status pamc_create_instance_dense_i8(int32_t n, const int8_t* J, int64_t ld
     return fail(PAMC_ERR_INVALID_ARG, "bad memory kind");
   }
   int64_t W = 0, X = 0;
+  int32_t maxabs = 0;
   for (int32_t i = 0; i < n; ++i) {
     if (src[(size_t)i * ld + i] != 0) return fail(PAMC_ERR_INVALID_ARG, "nonzero diagonal");
     int64_t ab = 0;
@@ -739,6 +740,7 @@ pamc_status pamc_create_instance_dense_i8(int32_t n, const int8_t* J, int64_t ld
       const int8_t v = src[(size_t)i * ld + j];
       if (v == -128) return fail(PAMC_ERR_INVALID_ARG, "entries must lie in [-127, 127]");
       if (v != src[(size_t)j * ld + i]) return fail(PAMC_ERR_INVALID_ARG, "matrix is not symmetric");
+      maxabs = std::max(maxabs, (int32_t)(v < 0 ? -v : v));
       ab += v < 0 ? -v : v;
       if (j > i) W += objective == PAMC_OBJ_MAXCUT ? v : -v;
     }
@@ -754,6 +756,7 @@ pamc_status pamc_create_instance_dense_i8(int32_t n, const int8_t* J, int64_t ld
   if (!st) {
     I->W = W;
     I->X = X;
+    I->dense_j4 = maxabs <= 7;  // stored couplings are v or -v
     const size_t np = (size_t)I->dn_pad;
     std::vector<int8_t> row(np);
     hipError_t e = hipMemsetAsync(I->Jd, 0, np * np, I->stream);
@@ -790,6 +793,7 @@ pamc_status pamc_create_instance_dense_random(int32_t n, uint64_t graph_seed, co
   if (!st) st = build_dense_common(I, n);
   if (!st) {
     I->X = n - 1;
+    I->dense_j4 = 1;  // +-1 couplings
     hipError_t e = pamc::launch_dense_generate(I, graph_seed);
     int64_t W = 0;
     if (e == hipSuccess) e = hipStreamSynchronize(I->stream);

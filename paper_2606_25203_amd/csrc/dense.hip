@@ -255,6 +255,7 @@ struct SeqArgs {
   const v4i* C;  // [n_pad / 4][R] critical fields of the sweep (k_dense_crit)
   RunState* st;
   int32_t n, np, R;
+  int32_t j4;  // every coupling in [-8, 7]: the sequential pass uses four-bit dot products
   uint32_t k0, k1;
   int64_t* flip_ctr;
 };
@@ -356,20 +357,88 @@ __device__ __forceinline__ bool decide_pass(const uint32_t (*jd)[kDB / 4], const
     uint32_t dg = 0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int32_t m = -(int32_t)((w >> (8 * kk + 7)) & 1u);  // its own spin has not changed yet
+      // m = -1 for s = -1 (its own spin has not changed yet), else 0
+      const int32_t m = (int32_t)(w << (24 - 8 * kk)) >> 31;
       const int32_t h = __builtin_amdgcn_sdot4((int)jg[kk], (int)dg, base[kk], false);
       const int32_t y = h ^ m;  // x = y - m
       if (WIDE) wide |= (uint32_t)(h + Xl) > (uint32_t)(2 * Xl);
       const bool flip = y < cc[kk] + m;
       dg = flip ? dg | (bw & (0xFFu << (8 * kk))) : dg;
-      xsum += flip ? y - m : 0;
+      xsum += flip ? y : 0;
     }
     d[g] = dg;
   }
-  // a flipped byte is 0xFE or 0x02, both with bit 1 set
+  // a flipped byte is 0xFE (s = +1) or 0x02 (s = -1): bit 1 counts the
+  // flips, bit 2 those of s = +1; sum x = sum y + the flips of s = -1
+  int32_t npos = 0;
 #pragma unroll
-  for (int g = 0; g < kDB / 4; ++g) nf += __builtin_popcount(d[g] & 0x02020202u);
-  dE32 += xsum;
+  for (int g = 0; g < kDB / 4; ++g) {
+    nf += __builtin_popcount(d[g] & 0x02020202u);
+    npos += __builtin_popcount(d[g] & 0x04040404u);
+  }
+  dE32 += xsum + (nf - npos);
+  nflip += nf;
+  return wide != 0;
+}
+
+// The same pass for couplings in [-8, 7], four bits each.  jd8 packs a
+// row's couplings to eight spins of the block per word and the flips are
+// kept in the same layout -- of the eight spins 8G + j, nibble 2j holds
+// spin j < 4 and nibble 2 (j - 4) + 1 spin j >= 4 -- so that one dot8 covers
+// eight couplings; a flip is the nibble 0xE (s = +1) or 0x2 (s = -1).  The
+// d words go out as bytes, unpacked at the end.
+template <int RULE, bool WIDE>
+__device__ __forceinline__ bool decide_pass8(const uint32_t (*jd8)[kDB / 8], const int32_t (*gsum)[64],
+                                             const v4i (*crit)[64], int32_t Xl, const uint32_t (&sw)[kDB / 4],
+                                             int lane, uint32_t (&d)[kDB / 4], int32_t& dE32, int32_t& nflip) {
+  uint32_t wide = 0, d8[kDB / 8];
+  int32_t xsum = 0, nf = 0, npos = 0;
+#pragma unroll
+  for (int G = 0; G < kDB / 8; ++G) d8[G] = 0;
+#pragma unroll
+  for (int G = 0; G < kDB / 8; ++G) {
+    const v4i cc0 = crit[2 * G][lane], cc1 = crit[2 * G + 1][lane];
+    int32_t base[8];
+    uint32_t jg[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * G + j;
+      int32_t p = gsum[k][lane];
+#pragma unroll
+      for (int G2 = 0; G2 < G; ++G2) p = __builtin_amdgcn_sdot8((int)jd8[k][G2], (int)d8[G2], p, false);
+      base[j] = p;
+      jg[j] = jd8[k][G];
+    }
+    const uint32_t w0 = sw[2 * G], w1 = sw[2 * G + 1];
+    // the flip nibbles, 0xE, or 0x2 where the spin is -1
+    const uint32_t negn = ((w0 >> 7) & 0x01010101u) | ((w1 >> 3) & 0x10101010u);
+    const uint32_t bw = 0xEEEEEEEEu ^ (negn * 0xCu);
+    uint32_t dg = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int jb = j & 3, sh = j < 4 ? 8 * jb : 8 * jb + 4;
+      const int32_t m = (int32_t)((j < 4 ? w0 : w1) << (24 - 8 * jb)) >> 31;
+      const int32_t h = __builtin_amdgcn_sdot8((int)jg[j], (int)dg, base[j], false);
+      const int32_t y = h ^ m;  // x = y - m
+      if (WIDE) wide |= (uint32_t)(h + Xl) > (uint32_t)(2 * Xl);
+      const bool flip = y < (j < 4 ? cc0[jb] : cc1[jb]) + m;
+      dg = flip ? dg | (bw & (0xFu << sh)) : dg;
+      xsum += flip ? y : 0;
+    }
+    d8[G] = dg;
+  }
+#pragma unroll
+  for (int G = 0; G < kDB / 8; ++G) {
+    // bit 1 of a flip nibble counts the flips, bit 2 those of s = +1
+    nf += __builtin_popcount(d8[G] & 0x22222222u);
+    npos += __builtin_popcount(d8[G] & 0x44444444u);
+    // nibbles 0, 2, 4, 6 are spins 0..3, nibbles 1, 3, 5, 7 spins 4..7;
+    // 0x0E becomes the byte 0xFE
+    const uint32_t lo = d8[G] & 0x0F0F0F0Fu, hi = (d8[G] >> 4) & 0x0F0F0F0Fu;
+    d[2 * G] = lo | ((lo & 0x08080808u) * 0x1Eu);
+    d[2 * G + 1] = hi | ((hi & 0x08080808u) * 0x1Eu);
+  }
+  dE32 += xsum + (nf - npos);
   nflip += nf;
   return wide != 0;
 }
@@ -424,8 +493,9 @@ __device__ __noinline__ BlockTally decide_block_exact(const uint32_t (*jd)[kDB /
 // keeps the common pass free of control flow).  The last block of the
 // matrix, which holds spins at or beyond n, takes the exact path directly,
 // and so does every block when the table is not monotone (all_exact).
-template <int RULE>
-__device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], const int32_t (*gsum)[64],
+template <int RULE, bool WIDE, bool J4>
+__device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], const uint32_t (*jd8)[kDB / 8],
+                                             const int32_t (*gsum)[64],
                                              const v4i (*crit)[64], const uint32_t* thr_s, double beta,
                                              int32_t Xl, int32_t Xt, bool all_exact, const uint32_t* sw0,
                                              uint32_t* dout, int rb0, int n, uint32_t gs, uint32_t r, uint32_t k0,
@@ -436,9 +506,9 @@ __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], cons
     uint32_t sw[kDB / 4], d[kDB / 4];
 #pragma unroll
     for (int g = 0; g < kDB / 4; ++g) sw[g] = sw0[g];
-    const bool wide = Xl < Xt ? decide_pass<RULE, true>(jd, gsum, crit, Xl, sw, lane, d, dE32, nf)
-                              : decide_pass<RULE, false>(jd, gsum, crit, Xl, sw, lane, d, dE32, nf);
-    exact = __builtin_amdgcn_ballot_w64(wide) != 0;
+    const bool wide = J4 ? decide_pass8<RULE, WIDE>(jd8, gsum, crit, Xl, sw, lane, d, dE32, nf)
+                         : decide_pass<RULE, WIDE>(jd, gsum, crit, Xl, sw, lane, d, dE32, nf);
+    exact = WIDE && __builtin_amdgcn_ballot_w64(wide) != 0;
     if (!exact) {
 #pragma unroll
       for (int g = 0; g < kDB / 4; ++g) dout[g] = d[g];
@@ -454,6 +524,11 @@ __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], cons
   nflip += nf;
 }
 
+template <int N>
+struct IntC {
+  static constexpr int value = N;
+};
+
 // One work-group per tile walks the super-block's 64-spin blocks in order,
 // pipelined: while wave 0 decides block b, waves 1-3 prepare block b + 1 --
 // its fields G (taken from the field product, which is cleared for the next
@@ -465,6 +540,7 @@ __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], cons
 // fragments loaded before the decisions).
 struct SeqLds {
   uint32_t jd[2][kDB][kDB / 4];   // J[rb0 + k][rb0 + 4g .. 4g+3], packed int8
+  uint32_t jd8[2][kDB][kDB / 8];  // the same, eight four-bit couplings per word (order of decide_pass8)
   int32_t gsum[2][kDB][64];       // fields of this tile before the block's own flips
   uint32_t thr_s[2 * kThrL + 1];  // thresholds for |x| <= Xl
   __attribute__((aligned(16))) int8_t dsl[64][kSB + 16];  // spin changes d, [replica][row - row0]
@@ -472,10 +548,11 @@ struct SeqLds {
   __attribute__((aligned(16))) v4i crit[kDB / 4][64];     // the block's critical fields, [group][replica]
 };
 
-template <int RULE>
+template <int RULE, bool WIDE, bool J4>
 __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t sweep_idx, int32_t row0, int32_t rows,
                                          SeqLds& L) {
   auto& jd = L.jd;
+  auto& jd8 = L.jd8;
   auto& gsum = L.gsum;
   auto& thr_s = L.thr_s;
   auto& dsl = L.dsl;
@@ -507,11 +584,23 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       *gp = 0;
     }
   };
+  // words 2 gp and 2 gp + 1 of row k of the diagonal J block, in bytes and
+  // in four-bit couplings (nibble 2 b from the first word's byte b, nibble
+  // 2 b + 1 from the second's)
+  auto put_jd = [&](int buf, int k, int gp, uint32_t lo, uint32_t hi) {
+    jd[buf][k][2 * gp] = lo;
+    jd[buf][k][2 * gp + 1] = hi;
+    jd8[buf][k][gp] = (lo & 0x0F0F0F0Fu) | ((hi & 0x0F0F0F0Fu) << 4);
+  };
   auto load_diag = [&](int bb, int buf, int t, int nt) {
     const int rb0 = row0 + bb * kDB;
+    for (int i = t; i < kDB * kDB / 8; i += nt) {
+      const int k = i / (kDB / 8), gp = i % (kDB / 8);
+      const uint2 w = *reinterpret_cast<const uint2*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 8 * gp);
+      put_jd(buf, k, gp, w.x, w.y);
+    }
     for (int i = t; i < kDB * kDB / 4; i += nt) {
       const int k = i / (kDB / 4), g = i % (kDB / 4);
-      jd[buf][k][g] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 4 * g);
       // the block's spin words of the tile (replica k, word g)
       swl[buf][k][g] = *reinterpret_cast<const uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + rb0 + 4 * g);
     }
@@ -521,9 +610,11 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
   // xor 0xFE.  In the loop, thread t of 128 (waves 2 and 3) takes the same
   // (replica, word) items as put_diag, so it reads swl[buf] here before its
   // own put_diag overwrites them.
-  auto store_block = [&](int bb, int buf, int t, int nt) {
-    for (int i = t; i < kDB * kDB / 4; i += nt) {
-      const int k = i / (kDB / 4), g = i % (kDB / 4);
+  auto store_block = [&](int bb, int buf, int t, auto ntc) {
+    constexpr int NT = decltype(ntc)::value;
+#pragma unroll
+    for (int it = 0; it < kDB * kDB / 4 / NT; ++it) {
+      const int i = t + NT * it, k = i / (kDB / 4), g = i % (kDB / 4);
       const uint32_t dw = *reinterpret_cast<const uint32_t*>(&dsl[k][bb * kDB + 4 * g]);
       *reinterpret_cast<uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + row0 + bb * kDB + 4 * g) =
           swl[buf][k][g] ^ ((dw & 0x02020202u) * 0x7Fu);
@@ -531,21 +622,30 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
   };
   // the diagonal block of bb into registers (thread t of nt, the same
   // (replica, word) items as store_block) and from there into LDS
-  constexpr int kDiagPer = kDB * kDB / 4 / 128;
-  auto fetch_diag = [&](int bb, int t, uint32_t (&dj)[kDiagPer], uint32_t (&dsw)[kDiagPer]) {
+  constexpr int kDiagPer = kDB * kDB / 4 / 128;  // spin words per thread
+  constexpr int kPairPer = kDB * kDB / 8 / 128;  // J word pairs per thread
+  auto fetch_diag = [&](int bb, int t, uint2 (&dj)[kPairPer], uint32_t (&dsw)[kDiagPer]) {
     const int rb0 = row0 + bb * kDB;
+#pragma unroll
+    for (int it = 0; it < kPairPer; ++it) {
+      const int i = t + 128 * it, k = i / (kDB / 8), gp = i % (kDB / 8);
+      dj[it] = *reinterpret_cast<const uint2*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 8 * gp);
+    }
 #pragma unroll
     for (int it = 0; it < kDiagPer; ++it) {
       const int i = t + 128 * it, k = i / (kDB / 4), g = i % (kDB / 4);
-      dj[it] = *reinterpret_cast<const uint32_t*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 4 * g);
       dsw[it] = *reinterpret_cast<const uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + rb0 + 4 * g);
     }
   };
-  auto put_diag = [&](int buf, int t, const uint32_t (&dj)[kDiagPer], const uint32_t (&dsw)[kDiagPer]) {
+  auto put_diag = [&](int buf, int t, const uint2 (&dj)[kPairPer], const uint32_t (&dsw)[kDiagPer]) {
+#pragma unroll
+    for (int it = 0; it < kPairPer; ++it) {
+      const int i = t + 128 * it;
+      put_jd(buf, i / (kDB / 8), i % (kDB / 8), dj[it].x, dj[it].y);
+    }
 #pragma unroll
     for (int it = 0; it < kDiagPer; ++it) {
       const int i = t + 128 * it, k = i / (kDB / 4), g = i % (kDB / 4);
-      jd[buf][k][g] = dj[it];
       swl[buf][k][g] = dsw[it];
     }
   };
@@ -629,7 +729,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
     if (wave == 0) {
       // the d words go to the super-block's spin changes; the helpers
       // write the block's spins back while the next block is decided
-      decide_block<RULE>(jd[cb], gsum[cb], crit, thr_s, beta, Xl, Xt, all_exact, swl[cb][lane],
+      decide_block<RULE, WIDE, J4>(jd[cb], jd8[cb], gsum[cb], crit, thr_s, beta, Xl, Xt, all_exact, swl[cb][lane],
                          reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]), rb0, a.n, gs, (uint32_t)r, a.k0, a.k1,
                          lane, dE, nflip);
     } else {
@@ -641,7 +741,8 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       const int ns = wave == 1 ? 2 : 1;
       v4i av[kSB / kDB];
       int32_t gv[2][16];
-      uint32_t dj[kDiagPer], dsw[kDiagPer];
+      uint2 dj[kPairPer];
+      uint32_t dsw[kDiagPer];
       if (next) {
 #pragma unroll
         for (int i = 0; i < kCritPerHelper; ++i)
@@ -652,7 +753,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       // the spins of block b-1 go back to memory (its words are in
       // swl[cb ^ 1] until put_diag below replaces them, same items per
       // thread)
-      if (b > 0 && wave >= 2) store_block(b - 1, cb ^ 1, threadIdx.x - 128, 128);
+      if (b > 0 && wave >= 2) store_block(b - 1, cb ^ 1, threadIdx.x - 128, IntC<128>{});
       if (next) {
 #pragma unroll
         for (int si = 0; si < 2; ++si) {
@@ -685,7 +786,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
     __syncthreads();
   }
   // the last block's spins (the others went back while the next was decided)
-  if (nb > 0) store_block(nb - 1, (nb - 1) & 1, threadIdx.x, blockDim.x);
+  if (nb > 0) store_block(nb - 1, (nb - 1) & 1, threadIdx.x, IntC<256>{});
   if (wave != 0) return;
   if (dE != 0)
     __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)dE, __ATOMIC_RELAXED,
@@ -713,8 +814,22 @@ k_dense_step(SeqArgs a, GemmArgs g, int32_t sweep_idx, int32_t row0, int32_t row
     SeqLds seq;
     GemmLds gemm;
   } L;
-  if ((int)blockIdx.x < T)
-    seq_body<RULE>(a, blockIdx.x, sweep_idx, row0, rows, L.seq);
+  if ((int)blockIdx.x < T) {
+    // fields beyond the LDS table need checking only when it is narrower
+    // than the full one
+    const int32_t Xt = (int32_t)a.st->table_x;
+    if (a.j4) {
+      if (Xt > kThrL)
+        seq_body<RULE, true, true>(a, blockIdx.x, sweep_idx, row0, rows, L.seq);
+      else
+        seq_body<RULE, false, true>(a, blockIdx.x, sweep_idx, row0, rows, L.seq);
+    } else {
+      if (Xt > kThrL)
+        seq_body<RULE, true, false>(a, blockIdx.x, sweep_idx, row0, rows, L.seq);
+      else
+        seq_body<RULE, false, false>(a, blockIdx.x, sweep_idx, row0, rows, L.seq);
+    }
+  }
   else if (gemm_on)
     gemm_body(g, blockIdx.x - T, L.gemm);
 }
@@ -905,6 +1020,7 @@ static hipError_t dense_sweeps(Batch& b, int32_t nsweeps) {
   a.n = I->n;
   a.np = I->dn_pad;
   a.R = I->R;
+  a.j4 = I->dense_j4;
   a.k0 = key0(I);
   a.k1 = key1(I);
   a.flip_ctr = I->prof ? I->flip_ctr : nullptr;

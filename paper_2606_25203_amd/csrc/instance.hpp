@@ -96,6 +96,7 @@ struct pamc_instance {
   int8_t* Jd = nullptr;  // [np_pad][ld] row-major
   int64_t ldj = 0;
   int32_t dn_pad = 0;    // padded dimension of the dense matrix
+  int32_t dense_j4 = 0;  // every dense coupling in [-8, 7] (four-bit dot products)
   int8_t* Sd = nullptr;  // [R][dn_pad] replica-major spins (dense)
   int8_t* Sd2 = nullptr; // resampling buffer
   int32_t* Gd = nullptr; // super-block field buffers [2][rows][R]

@@ -66,6 +66,29 @@ def test_dense_i8_weighted(pamc, objective, n):
     inst.close()
 
 
+@pytest.mark.parametrize("objective", [0, 1])
+@pytest.mark.parametrize("rule", [0, 1])
+def test_dense_i4_weighted(pamc, objective, rule):
+    # couplings in [-7, 7] take the four-bit sequential pass; n = 1300 spans
+    # two super-blocks and a partial last block, and max_v sum_j |J_vj| is
+    # above the LDS part of the threshold table, so beta = 0.001 also checks
+    # the fields beyond it
+    n = 1300
+    rng = np.random.default_rng(11)
+    A = rng.integers(-7, 8, size=(n, n)).astype(np.int8)
+    J = np.triu(A, 1)
+    J = (J + J.T).astype(np.int8)
+    say(f"case dense i4 objective={objective} rule={rule}")
+    inst = pamc.Instance.dense(J, replicas=128, seed=4, objective=objective, rule=rule)
+    o = oracle.Oracle.dense(J, 128, 4, objective=objective, rule=rule)
+    assert inst.info().W == o.W and o.X > 2047
+    for beta in (0.001, 0.05, 0.5):
+        inst.sweep(beta, 1)
+        o.sweep(beta, 1)
+        same_state(inst, o, f"beta={beta}")
+    inst.close()
+
+
 def test_dense_resample_and_anneal(pamc):
     n, R = 400, 128
     J = synth.dense_pm1(n, 8)
