@@ -32,7 +32,7 @@ namespace pamc {
 namespace {
 
 constexpr int kDB = 64;          // spins per sequential block
-static_assert(kDB / 4 == 4 + 6 + 6, "the helper waves' share of the critical-field groups assumes 16 groups");
+static_assert(kDB / 4 == 6 + 6 + 4, "the helper waves' share of the critical-field groups assumes 16 groups");
 constexpr int kSB = 1024;        // rows per super-block: one field product, one sequential launch
 constexpr int kGM = 128, kGN = 128, kGK = 64;  // field-product tile: rows x replicas x K stage
 constexpr int kLdsRow = kGK + 16;              // bytes per staged row (padded)
@@ -545,6 +545,7 @@ struct SeqLds {
   uint32_t thr_s[2 * kThrL + 1];  // thresholds for |x| <= Xl
   __attribute__((aligned(16))) int8_t dsl[64][kSB + 16];  // spin changes d, [replica][row - row0]
   uint32_t swl[2][64][kDB / 4 + 1];                       // the block's spin words, [replica][word]
+  int32_t part[16][64];  // wave 2's part of strip 3, fragment rows x replicas
   __attribute__((aligned(16))) v4i crit[kDB / 4][64];     // the block's critical fields, [group][replica]
 };
 
@@ -558,6 +559,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
   auto& dsl = L.dsl;
   auto& swl = L.swl;
   auto& crit = L.crit;
+  auto& part = L.part;
   RunState* st = a.st;
   if (!st->active) return;
   const int cur = st->cur;
@@ -607,9 +609,9 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
   };
   // new spin words of block bb from its starting words and its d words: a
   // byte of d is 0 (no flip), 2 or -2, and a flip turns 0x01 <-> 0xFF, i.e.
-  // xor 0xFE.  In the loop, thread t of 128 (waves 2 and 3) takes the same
-  // (replica, word) items as put_diag, so it reads swl[buf] here before its
-  // own put_diag overwrites them.
+  // xor 0xFE.  In the loop, lane t of wave 3 takes the same (replica, word)
+  // items as put_diag, so it reads swl[buf] here before its own put_diag
+  // overwrites them.
   auto store_block = [&](int bb, int buf, int t, auto ntc) {
     constexpr int NT = decltype(ntc)::value;
 #pragma unroll
@@ -620,43 +622,47 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
           swl[buf][k][g] ^ ((dw & 0x02020202u) * 0x7Fu);
     }
   };
-  // the diagonal block of bb into registers (thread t of nt, the same
+  // the diagonal block of bb into registers (thread t of wave 3, the same
   // (replica, word) items as store_block) and from there into LDS
-  constexpr int kDiagPer = kDB * kDB / 4 / 128;  // spin words per thread
-  constexpr int kPairPer = kDB * kDB / 8 / 128;  // J word pairs per thread
+  constexpr int kDiagPer = kDB * kDB / 4 / 64;  // spin words per thread of wave 3
+  constexpr int kPairPer = kDB * kDB / 8 / 64;  // J word pairs per thread of wave 3
   auto fetch_diag = [&](int bb, int t, uint2 (&dj)[kPairPer], uint32_t (&dsw)[kDiagPer]) {
     const int rb0 = row0 + bb * kDB;
 #pragma unroll
     for (int it = 0; it < kPairPer; ++it) {
-      const int i = t + 128 * it, k = i / (kDB / 8), gp = i % (kDB / 8);
+      const int i = t + 64 * it, k = i / (kDB / 8), gp = i % (kDB / 8);
       dj[it] = *reinterpret_cast<const uint2*>(a.J + (size_t)(rb0 + k) * a.np + rb0 + 8 * gp);
     }
 #pragma unroll
     for (int it = 0; it < kDiagPer; ++it) {
-      const int i = t + 128 * it, k = i / (kDB / 4), g = i % (kDB / 4);
+      const int i = t + 64 * it, k = i / (kDB / 4), g = i % (kDB / 4);
       dsw[it] = *reinterpret_cast<const uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + rb0 + 4 * g);
     }
   };
   auto put_diag = [&](int buf, int t, const uint2 (&dj)[kPairPer], const uint32_t (&dsw)[kDiagPer]) {
 #pragma unroll
     for (int it = 0; it < kPairPer; ++it) {
-      const int i = t + 128 * it;
+      const int i = t + 64 * it;
       put_jd(buf, i / (kDB / 8), i % (kDB / 8), dj[it].x, dj[it].y);
     }
 #pragma unroll
     for (int it = 0; it < kDiagPer; ++it) {
-      const int i = t + 128 * it, k = i / (kDB / 4), g = i % (kDB / 4);
+      const int i = t + 64 * it, k = i / (kDB / 4), g = i % (kDB / 4);
       swl[buf][k][g] = dsw[it];
     }
   };
-  // the 16-row strip sr of block bb against the first 64 nsteps columns of
-  // the super-block: its J fragments, and its fields from G (fragment
-  // layout: row 4 (lane / 16) + j of the strip, replica 16 nt + lane % 16)
-  auto load_strip = [&](int bb, int sr, int nsteps, v4i (&av)[kSB / kDB], int32_t (&gv)[16]) {
+  // the 16-row strip sr of block bb against the column steps kbeg .. kend
+  // of the super-block (64 columns each): its J fragments (step kbeg + i in
+  // av[i]), and its fields from G (fragment layout: row 4 (lane / 16) + j
+  // of the strip, replica 16 nt + lane % 16)
+  auto load_frags = [&](int bb, int sr, int kbeg, int kend, auto& av) {
+    constexpr int N = sizeof(av) / sizeof(av[0]);
     const int8_t* arow = a.J + (size_t)(row0 + bb * kDB + 16 * sr + (lane & 15)) * a.np + row0 + 16 * (lane >> 4);
 #pragma unroll
-    for (int k = 0; k < kSB / kDB; ++k)
-      if (k < nsteps) av[k] = *reinterpret_cast<const v4i*>(arow + 64 * k);
+    for (int i = 0; i < N; ++i)
+      av[i] = kbeg + i < kend ? *reinterpret_cast<const v4i*>(arow + 64 * (kbeg + i)) : v4i{0, 0, 0, 0};
+  };
+  auto load_g = [&](int bb, int sr, int32_t (&gv)[16]) {
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -664,15 +670,18 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
         gv[4 * nt + j] = a.G[(size_t)(bb * kDB + 16 * sr + 4 * (lane >> 4) + j) * a.R + tile * 64 + nt * 16 +
                              (lane & 15)];
   };
-  // acc += J[strip rows][cols] . dsl[:, cols] on the matrix cores
-  auto strip_product = [&](int nsteps, const v4i (&av)[kSB / kDB], v4i (&acc)[4]) {
+  // acc += J[strip rows][steps kbeg .. kend) . dsl[:, those columns] on
+  // the matrix cores
+  auto strip_product = [&](int kbeg, int kend, const auto& av, v4i (&acc)[4]) {
+    constexpr int N = sizeof(av) / sizeof(av[0]);
 #pragma unroll
-    for (int k = 0; k < kSB / kDB; ++k) {
-      if (k < nsteps) {
+    for (int i = 0; i < N; ++i) {
+      if (kbeg + i < kend) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-          const v4i bv = *reinterpret_cast<const v4i*>(&dsl[nt * 16 + (lane & 15)][64 * k + 16 * (lane >> 4)]);
-          acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[k], bv, acc[nt], 0, 0, 0);
+          const v4i bv =
+              *reinterpret_cast<const v4i*>(&dsl[nt * 16 + (lane & 15)][64 * (kbeg + i) + 16 * (lane >> 4)]);
+          acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[i], bv, acc[nt], 0, 0, 0);
         }
       }
     }
@@ -720,51 +729,64 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       a_next = *reinterpret_cast<const v4i*>(a.J + (size_t)(rb0 + kDB + 16 * wave + (lane & 15)) * a.np + rb0 +
                                              16 * (lane >> 4));
     // waves 1..3: the critical fields of block b+1 (held in registers
-    // until wave 0 is done with block b's); wave 1, which also takes a
-    // second strip, loads 4 of the 16 groups, waves 2 and 3 six each
+    // until wave 0 is done with block b's); wave 3, which also takes the
+    // diagonal block, loads 4 of the 16 groups, waves 1 and 2 six each
     constexpr int kCritPerHelper = 6;
-    const int crit_g0 = wave == 1 ? 0 : wave == 2 ? 4 : 10;
-    const int crit_cnt = wave == 1 ? 4 : 6;
+    const int crit_g0 = wave == 1 ? 0 : wave == 2 ? 6 : 12;
+    const int crit_cnt = wave == 3 ? 4 : 6;
     v4i crit_next[kCritPerHelper];
     if (wave == 0) {
       // the d words go to the super-block's spin changes; the helpers
       // write the block's spins back while the next block is decided
       decide_block<RULE, WIDE, J4>(jd[cb], jd8[cb], gsum[cb], crit, thr_s, beta, Xl, Xt, all_exact, swl[cb][lane],
-                         reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]), rb0, a.n, gs, (uint32_t)r, a.k0, a.k1,
-                         lane, dE, nflip);
+                                   reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]), rb0, a.n, gs, (uint32_t)r,
+                                   a.k0, a.k1, lane, dE, nflip);
     } else {
-      // the global reads for block b+1 are issued before any of them is
-      // used, so that their latencies overlap: its critical fields, this
-      // wave's first strip (wave 1 takes strips 0 and 3, the second once the
-      // first is multiplied, waves 2 and 3 strips 1 and 2) and, for waves 2
-      // and 3, its diagonal J block and spin words
-      const int ns = wave == 1 ? 2 : 1;
-      v4i av[kSB / kDB];
-      int32_t gv[2][16];
+      // Helper wave w takes strip w - 1 of block b+1 over all b column
+      // steps; strip 3 is split at step h = b / 2, steps [0, h) to wave 1
+      // (with its fields G) and [h, b) to wave 2 (into an LDS partial that
+      // wave 3 adds after the barrier); wave 3 also takes the diagonal
+      // block and writes the spins of block b-1 back (its words are in
+      // swl[cb ^ 1] until put_diag replaces them, same items per lane).
+      // The global reads of a part are issued before any of them is used,
+      // so that their latencies overlap.
+      const int h = b / 2;
+      v4i av[kSB / kDB - 2];  // b <= kSB / kDB - 2 when there is a next block
+      int32_t gv[16];
       uint2 dj[kPairPer];
       uint32_t dsw[kDiagPer];
+      if (wave == 3) {
+        // the diagonal block's reads first: their latency overlaps the
+        // write-back, and their registers are free before the strip's
+        if (next) fetch_diag(b + 1, lane, dj, dsw);
+        if (b > 0) store_block(b - 1, cb ^ 1, lane, IntC<64>{});
+        if (next) put_diag(cb ^ 1, lane, dj, dsw);
+      }
       if (next) {
 #pragma unroll
         for (int i = 0; i < kCritPerHelper; ++i)
           if (i < crit_cnt) crit_next[i] = crit_group(b + 1, crit_g0 + i);
-        load_strip(b + 1, wave - 1, b, av, gv[0]);
-        if (wave >= 2) fetch_diag(b + 1, threadIdx.x - 128, dj, dsw);
-      }
-      // the spins of block b-1 go back to memory (its words are in
-      // swl[cb ^ 1] until put_diag below replaces them, same items per
-      // thread)
-      if (b > 0 && wave >= 2) store_block(b - 1, cb ^ 1, threadIdx.x - 128, IntC<128>{});
-      if (next) {
+        load_frags(b + 1, wave - 1, 0, b, av);
+        load_g(b + 1, wave - 1, gv);
+        v4i acc[4] = {zero, zero, zero, zero};
+        strip_product(0, b, av, acc);
+        add_strip(b + 1, cb ^ 1, wave - 1, acc, gv);
+        if (wave <= 2) {
+          v4i a3[(kSB / kDB - 1) / 2];
+          const int kb = wave == 1 ? 0 : h, ke = wave == 1 ? h : b;
+          load_frags(b + 1, 3, kb, ke, a3);
+          if (wave == 1) load_g(b + 1, 3, gv);
+          v4i acc3[4] = {zero, zero, zero, zero};
+          strip_product(kb, ke, a3, acc3);
+          if (wave == 1) {
+            add_strip(b + 1, cb ^ 1, 3, acc3, gv);
+          } else {
 #pragma unroll
-        for (int si = 0; si < 2; ++si) {
-          if (si < ns) {
-            v4i acc[4] = {zero, zero, zero, zero};
-            if (si == 1) load_strip(b + 1, 3, b, av, gv[1]);
-            strip_product(b, av, acc);
-            add_strip(b + 1, cb ^ 1, si == 0 ? wave - 1 : 3, acc, gv[si]);
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) part[4 * (lane >> 4) + j][nt * 16 + (lane & 15)] = acc3[nt][j];
           }
         }
-        if (wave >= 2) put_diag(cb ^ 1, threadIdx.x - 128, dj, dsw);
       }
     }
     __syncthreads();
@@ -780,6 +802,13 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       for (int nt = 0; nt < 4; ++nt) {
         const v4i bv = *reinterpret_cast<const v4i*>(&dsl[nt * 16 + (lane & 15)][b * kDB + 16 * (lane >> 4)]);
         acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a_next, bv, acc[nt], 0, 0, 0);
+      }
+      if (wave == 3) {
+        // wave 2's part of strip 3
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[nt][j] += part[4 * (lane >> 4) + j][nt * 16 + (lane & 15)];
       }
       add_strip(b + 1, cb ^ 1, wave, acc, nullptr);
     }
