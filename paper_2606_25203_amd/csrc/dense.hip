@@ -524,11 +524,6 @@ __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], cons
   nflip += nf;
 }
 
-template <int N>
-struct IntC {
-  static constexpr int value = N;
-};
-
 // One work-group per tile walks the super-block's 64-spin blocks in order,
 // pipelined: while wave 0 decides block b, waves 1-3 prepare block b + 1 --
 // its fields G (taken from the field product, which is cleared for the next
@@ -607,23 +602,8 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       swl[buf][k][g] = *reinterpret_cast<const uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + rb0 + 4 * g);
     }
   };
-  // new spin words of block bb from its starting words and its d words: a
-  // byte of d is 0 (no flip), 2 or -2, and a flip turns 0x01 <-> 0xFF, i.e.
-  // xor 0xFE.  In the loop, lane t of wave 3 takes the same (replica, word)
-  // items as put_diag, so it reads swl[buf] here before its own put_diag
-  // overwrites them.
-  auto store_block = [&](int bb, int buf, int t, auto ntc) {
-    constexpr int NT = decltype(ntc)::value;
-#pragma unroll
-    for (int it = 0; it < kDB * kDB / 4 / NT; ++it) {
-      const int i = t + NT * it, k = i / (kDB / 4), g = i % (kDB / 4);
-      const uint32_t dw = *reinterpret_cast<const uint32_t*>(&dsl[k][bb * kDB + 4 * g]);
-      *reinterpret_cast<uint32_t*>(S + (size_t)(tile * 64 + k) * a.np + row0 + bb * kDB + 4 * g) =
-          swl[buf][k][g] ^ ((dw & 0x02020202u) * 0x7Fu);
-    }
-  };
-  // the diagonal block of bb into registers (thread t of wave 3, the same
-  // (replica, word) items as store_block) and from there into LDS
+  // the diagonal block of bb into registers (lane t of wave 3) and from
+  // there into LDS
   constexpr int kDiagPer = kDB * kDB / 4 / 64;  // spin words per thread of wave 3
   constexpr int kPairPer = kDB * kDB / 8 / 64;  // J word pairs per thread of wave 3
   auto fetch_diag = [&](int bb, int t, uint2 (&dj)[kPairPer], uint32_t (&dsw)[kDiagPer]) {
@@ -741,26 +721,40 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       decide_block<RULE, WIDE, J4>(jd[cb], jd8[cb], gsum[cb], crit, thr_s, beta, Xl, Xt, all_exact, swl[cb][lane],
                                    reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]), rb0, a.n, gs, (uint32_t)r,
                                    a.k0, a.k1, lane, dE, nflip);
+      // the lane's new spin words of the block go straight back: a byte of
+      // d is 0 (no flip), 2 or -2, and a flip turns 0x01 <-> 0xFF, i.e. xor
+      // 0xFE
+      {
+        const uint32_t* dw = reinterpret_cast<const uint32_t*>(&dsl[lane][b * kDB]);
+        const uint32_t* sw = swl[cb][lane];
+        uint4* dst = reinterpret_cast<uint4*>(S + (size_t)r * a.np + rb0);
+#pragma unroll
+        for (int q = 0; q < kDB / 16; ++q) {
+          uint4 v;
+          v.x = sw[4 * q] ^ ((dw[4 * q] & 0x02020202u) * 0x7Fu);
+          v.y = sw[4 * q + 1] ^ ((dw[4 * q + 1] & 0x02020202u) * 0x7Fu);
+          v.z = sw[4 * q + 2] ^ ((dw[4 * q + 2] & 0x02020202u) * 0x7Fu);
+          v.w = sw[4 * q + 3] ^ ((dw[4 * q + 3] & 0x02020202u) * 0x7Fu);
+          dst[q] = v;
+        }
+      }
     } else {
       // Helper wave w takes strip w - 1 of block b+1 over all b column
       // steps; strip 3 is split at step h = b / 2, steps [0, h) to wave 1
       // (with its fields G) and [h, b) to wave 2 (into an LDS partial that
       // wave 3 adds after the barrier); wave 3 also takes the diagonal
-      // block and writes the spins of block b-1 back (its words are in
-      // swl[cb ^ 1] until put_diag replaces them, same items per lane).
-      // The global reads of a part are issued before any of them is used,
-      // so that their latencies overlap.
+      // block.  The global reads of a part are issued before any of them
+      // is used, so that their latencies overlap.
       const int h = b / 2;
       v4i av[kSB / kDB - 2];  // b <= kSB / kDB - 2 when there is a next block
       int32_t gv[16];
       uint2 dj[kPairPer];
       uint32_t dsw[kDiagPer];
-      if (wave == 3) {
-        // the diagonal block's reads first: their latency overlaps the
-        // write-back, and their registers are free before the strip's
-        if (next) fetch_diag(b + 1, lane, dj, dsw);
-        if (b > 0) store_block(b - 1, cb ^ 1, lane, IntC<64>{});
-        if (next) put_diag(cb ^ 1, lane, dj, dsw);
+      if (wave == 3 && next) {
+        // the diagonal block first, so that its registers are free before
+        // the strip's
+        fetch_diag(b + 1, lane, dj, dsw);
+        put_diag(cb ^ 1, lane, dj, dsw);
       }
       if (next) {
 #pragma unroll
@@ -814,8 +808,6 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
     }
     __syncthreads();
   }
-  // the last block's spins (the others went back while the next was decided)
-  if (nb > 0) store_block(nb - 1, (nb - 1) & 1, threadIdx.x, IntC<256>{});
   if (wave != 0) return;
   if (dE != 0)
     __hip_atomic_fetch_add((unsigned long long*)&E[r], (unsigned long long)dE, __ATOMIC_RELAXED,
