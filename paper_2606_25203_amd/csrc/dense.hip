@@ -6,13 +6,16 @@
 // one matrix-core launch computes the local fields of Eq. 3 of all its rows
 // against the spins as they stand, G = J[sb, :] . S (int8 x int8 -> int32,
 // exact since |h| <= 127 n < 2^31; split over the K dimension and summed
-// atomically).  A sequential launch (one work-group per 64 replicas) then
+// atomically).  A sequential pass (one work-group per 64 replicas) then
 // walks the super-block in blocks of kDB = 64 spins: the couplings to spins
 // already flipped in earlier blocks of the super-block are added with a
 // small matrix-core product over the recorded changes dS, and the block's
 // spins are decided in order with h_k = G_k + C_k + sum_{k' < k in block}
-// J_kk' d_k' (d = 2 s_new for flipped spins, packed int8, dot4), the same
-// threshold test as the sparse path.
+// J_kk' d_k' (d = 2 s_new for flipped spins; packed int8 with dot4, or four
+// bits with dot8 when every coupling fits), by the same threshold test as
+// the sparse path in the form x < c (each visit's critical field c, computed
+// for the whole sweep beforehand).  The pass and the next super-block's
+// product share one launch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -525,13 +528,14 @@ __device__ __forceinline__ void decide_block(const uint32_t (*jd)[kDB / 4], cons
 }
 
 // One work-group per tile walks the super-block's 64-spin blocks in order,
-// pipelined: while wave 0 decides block b, waves 1-3 prepare block b + 1 --
-// its fields G (taken from the field product, which is cleared for the next
-// super-block), plus the couplings to the spins flipped in blocks 0..b-1 of
-// the super-block, C = J[blk b+1, blocks 0..b-1] . dS (matrix cores; the
-// spin changes dS of the super-block are kept in LDS, replica-major), and
-// its diagonal block of J.  After wave 0 is done, the four waves add block
-// b's own contribution to block b + 1 (one 64-column matrix-core step, its J
+// pipelined: while wave 0 decides block b (and writes its replica's new spin
+// words back), waves 1-3 prepare block b + 1 -- its fields G (taken from the
+// field product, which is cleared for the next super-block), plus the
+// couplings to the spins flipped in blocks 0..b-1 of the super-block, C =
+// J[blk b+1, blocks 0..b-1] . dS (matrix cores; the spin changes dS of the
+// super-block are kept in LDS, replica-major), its diagonal block of J and
+// its critical fields.  After wave 0 is done, the four waves add block b's
+// own contribution to block b + 1 (one 64-column matrix-core step, its J
 // fragments loaded before the decisions).
 struct SeqLds {
   uint32_t jd[2][kDB][kDB / 4];   // J[rb0 + k][rb0 + 4g .. 4g+3], packed int8
@@ -566,8 +570,8 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
   const int32_t Xt = (int32_t)st->table_x;
   const double beta = st->sweep_beta;
-  // The decision chain waits for every threshold read, so the central part
-  // of the table lives in LDS; for |x| > Xl it is recomputed.
+  // The central part of the table lives in LDS, for the exact path (which
+  // recomputes it for |x| > Xl) and the monotonicity check below.
   const int32_t Xl = min(Xt, kThrL);
   for (int i = threadIdx.x; i <= 2 * Xl; i += blockDim.x) thr_s[i] = a.thr[Xt - Xl + i];
   const int nb = min(rows, a.n - row0 + kDB - 1) / kDB;  // blocks holding real spins
