@@ -95,9 +95,14 @@ pamc_status pamc_create_instance_csr(int32_t n, const int32_t* row_ptr, const in
                                      const pamc_config* cfg, pamc_instance** out);
 
 /* Dense instance from an int8 coupling matrix J[n][ld] (row-major,
- * symmetric, zero diagonal).  Spins are visited in the fixed order 0..n-1;
- * local fields are recomputed exactly with int8 x int8 -> int32 matrix-core
- * products (Scalability section: fully connected instance). */
+ * symmetric, zero diagonal, entries in [-127, 127]).  Spins are visited in
+ * the fixed order 0..n-1; local fields are recomputed exactly with int8 x
+ * int8 -> int32 matrix-core products (Scalability section: fully connected
+ * instance).  Device memory: the padded matrix (n_pad^2 bytes, n_pad = n
+ * rounded up to 64), two populations (2 n_pad R bytes), and per sweep each
+ * visit's precomputed critical field (4 n_pad R bytes).  Instances whose
+ * couplings all lie in [-7, 7] use four-bit products inside a block (same
+ * results). */
 pamc_status pamc_create_instance_dense_i8(int32_t n, const int8_t* J, int64_t ld, pamc_mem where,
                                           int32_t objective, const pamc_config* cfg,
                                           pamc_instance** out);
