@@ -95,15 +95,18 @@ def alu_slots_per_attempt(degree: float, coupling_mode: int) -> float:
     return 25.0 + per_neighbour * degree + 9.0
 
 
-def potts_slots_per_attempt(degree: float) -> float:
-    """Vector-ALU issue slots (lane-ops, 32x32->64 products counting 4) of
-    one Potts label visit of k_sweep_potts<3>, from the compiled loop: 910
-    slots per quad of 4 vertices x 64 lanes on C4's graph (padded rows of 8
-    entries), i.e. about 155 per visit for Philox4x32-10 (one 4-word block
-    per visit), the binary64 weights and comparisons and the label update,
-    plus 9 per gathered-CSR entry (rows padded to multiples of 4: readfirstlane,
-    byte extract, K compare-select-adds)."""
-    return 155.0 + 9.0 * 4.0 * math.ceil(degree / 4.0)
+def potts_slots_per_attempt(degree: float, K: int, X: int) -> float:
+    """Vector-ALU issue slots (lane-ops, 32x32->64 products counting 4,
+    binary64 operations 2) of one Potts label visit of k_sweep_potts<3>, from
+    the compiled loop: 506 slots per quad of 4 vertices outside the gather
+    loops (Philox4x32-10 blocks shared by the quad, the binary64 weights and
+    comparisons, the label updates; both rules' code counted, so an upper
+    bound), i.e. 126.5 per visit, plus per gathered-CSR entry (rows padded to
+    multiples of 4) 23/4 slots when the K label sums fit 32/K-bit fields of
+    one integer (X < 2^(32/K - 1): byte extract, shift, add) and 47/4
+    otherwise (K compare-select-adds)."""
+    per_entry = 23.0 / 4.0 if X < (1 << (32 // K - 1)) else 47.0 / 4.0
+    return 126.5 + per_entry * 4.0 * math.ceil(degree / 4.0)
 
 
 def counters_traffic(name: str, src: str):
@@ -440,7 +443,7 @@ def main():
         shape = {"tiles_per_wave": info.tiles_per_wave, "quads_per_wave": info.quads_per_wave,
                  "coupling_mode": info.coupling_mode}
         if w["kind"] == "potts":
-            slots = potts_slots_per_attempt(degree)
+            slots = potts_slots_per_attempt(degree, info.potts_K, info.X)
             achieved = slots * rate / 1e12
             roof = {"kernel": "k_sweep_potts<3>", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
                     "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,

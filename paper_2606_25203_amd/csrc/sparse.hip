@@ -468,6 +468,46 @@ __device__ __forceinline__ void gather_labels(const PAMC_GLOBAL int32_t* __restr
   }
 }
 
+// The same field when every |syn_k| fits W = 32 / K bits less one (X <
+// 2^(W-1)): the K sums are kept as W-bit fields of one 32-bit integer, sum_j
+// J_vj 2^(W label_j), so a neighbour costs a shift and an add instead of K
+// compare-select-adds; the fields are taken apart at the end, each as the
+// sign-extended low W bits of what remains (exact: the integer is
+// sum_k syn_k 2^(W k) with every |syn_k| < 2^(W-1), which fits 32 bits).
+template <int K>
+__device__ __forceinline__ void gather_labels_packed(const PAMC_GLOBAL int32_t* __restrict__ gcol,
+                                                     const PAMC_GLOBAL int32_t* __restrict__ gJ, int e0, int e1,
+                                                     __amdgpu_buffer_rsrc_t Sr, int voff, int32_t (&syn)[K]) {
+  constexpr int W = 32 / K;
+  uint32_t acc = 0;
+  for (int e = e0; e < e1; e += 4) {
+    const i32x4 cj = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(gcol + e);
+    const i32x4 cJ = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(gJ + e);
+    const int j[4] = {__builtin_amdgcn_readfirstlane(cj.x), __builtin_amdgcn_readfirstlane(cj.y),
+                      __builtin_amdgcn_readfirstlane(cj.z), __builtin_amdgcn_readfirstlane(cj.w)};
+    const uint32_t c4[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(cJ.x),
+                            (uint32_t)__builtin_amdgcn_readfirstlane(cJ.y),
+                            (uint32_t)__builtin_amdgcn_readfirstlane(cJ.z),
+                            (uint32_t)__builtin_amdgcn_readfirstlane(cJ.w)};
+    uint32_t w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = __builtin_amdgcn_raw_buffer_load_b32(Sr, voff, j[u] & ~3, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t lab = __builtin_amdgcn_ubfe(w[u], 8u * (uint32_t)(j[u] & 3), 8u);
+      acc += c4[u] << (W * lab);
+    }
+  }
+  int32_t rest = (int32_t)acc;
+#pragma unroll
+  for (int k = 0; k < K - 1; ++k) {
+    const int32_t f = (int32_t)((uint32_t)rest << (32 - W)) >> (32 - W);
+    syn[k] = f;
+    rest = (rest - f) >> W;
+  }
+  syn[K - 1] = rest;
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
                                                    const uint64_t* __restrict__ map, int sweep_idx,
@@ -503,6 +543,7 @@ __global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
   const double* __restrict__ tab = lds ? tab_s : (const double*)d.ptab;
   const int rule = d.potts_rule;
   const double gamma = d.potts_gamma;
+  const bool packed = d.X < (1 << (32 / K - 1));
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t r = (uint32_t)(tile * kLanes + lane);
@@ -524,7 +565,10 @@ __global__ void __launch_bounds__(256) k_sweep_potts(const Desc* __restrict__ D,
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
       const bool in = v >= v0 && v < v1;
-      gather_labels<K>(gcol, gJ, in ? grow[v] : 0, in ? grow[v + 1] : 0, Sr, voff, synq[k]);
+      if (packed)
+        gather_labels_packed<K>(gcol, gJ, in ? grow[v] : 0, in ? grow[v + 1] : 0, Sr, voff, synq[k]);
+      else
+        gather_labels<K>(gcol, gJ, in ? grow[v] : 0, in ? grow[v + 1] : 0, Sr, voff, synq[k]);
     }
     // uniform words: W per visit (K, or 2 for the cascade); the quad's
     // visits share W Philox blocks (quad, sweep, replica, POTTS | b << 8),

@@ -115,6 +115,41 @@ def test_potts_weight_table_beyond_lds(pamc):
     inst.close()
 
 
+def weighted_graph(g, wmax, seed):
+    """g with symmetric integer weights drawn from [1, wmax]."""
+    rng = np.random.default_rng(seed)
+    w = np.zeros_like(g.w)
+    for i in range(g.n):
+        for e in range(g.row_ptr[i], g.row_ptr[i + 1]):
+            j = g.col[e]
+            if j > i:
+                x = int(rng.integers(1, wmax + 1))
+                w[e] = x
+                for f in range(g.row_ptr[j], g.row_ptr[j + 1]):
+                    if g.col[f] == i:
+                        w[f] = x
+    return synth.Graph(g.n, g.row_ptr, g.col, w.astype(np.int32))
+
+
+@pytest.mark.parametrize("K,rule,wmax,packed", [(2, 0, 1500, True), (2, 0, 9000, False), (3, 0, 20, True),
+                                                (3, 1, 120, False), (4, 0, 5, True), (4, 0, 40, False)])
+def test_potts_weighted_label_sums(pamc, K, rule, wmax, packed):
+    # the sweep keeps the K label sums of a vertex as 32/K-bit fields of one
+    # integer when max_v sum_j |J_vj| < 2^(32/K - 1), as K integers otherwise;
+    # the weights put each case on the side it names
+    g = weighted_graph(synth.random_graph(200, 1000, 5), wmax, K)
+    say(f"case potts weighted K={K} rule={rule} wmax={wmax}")
+    inst = pamc.Instance.potts(g, K, replicas=128, seed=6, potts_rule=rule, gamma=1.0)
+    o = oracle.Oracle.potts(g.n, g.row_ptr, g.col, g.w, K, 128, 6, rule=rule, gamma=1.0)
+    assert (o.X < (1 << (32 // K - 1))) == packed
+    same_state(inst, o, "init")
+    for beta in (0.001, 0.02, 0.3):
+        inst.sweep(beta, 2)
+        o.sweep(beta, 2)
+        same_state(inst, o, f"beta={beta}")
+    inst.close()
+
+
 @pytest.mark.parametrize("K,rule,gamma", [(3, 0, 1.0), (3, 1, 0.0), (2, 0, 0.5)])
 def test_potts_anneal(pamc, K, rule, gamma):
     g = synth.random_graph(400, 1200, 12)
