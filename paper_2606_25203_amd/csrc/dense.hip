@@ -720,8 +720,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
     const int crit_cnt = wave == 3 ? 4 : 6;
     v4i crit_next[kCritPerHelper];
     if (wave == 0) {
-      // the d words go to the super-block's spin changes; the helpers
-      // write the block's spins back while the next block is decided
+      // the d words go to the super-block's spin changes (dsl)
       decide_block<RULE, WIDE, J4>(jd[cb], jd8[cb], gsum[cb], crit, thr_s, beta, Xl, Xt, all_exact, swl[cb][lane],
                                    reinterpret_cast<uint32_t*>(&dsl[lane][b * kDB]), rb0, a.n, gs, (uint32_t)r,
                                    a.k0, a.k1, lane, dE, nflip);
