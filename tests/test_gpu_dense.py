@@ -46,18 +46,18 @@ def test_dense_random_init_and_sweeps(pamc, n, R, rule):
     inst.close()
 
 
-@pytest.mark.parametrize("objective", [0, 1])
+@pytest.mark.parametrize("objective,rule", [(0, 0), (1, 0), (1, 1)])
 @pytest.mark.parametrize("n", [200, 1000])
-def test_dense_i8_weighted(pamc, objective, n):
+def test_dense_i8_weighted(pamc, objective, rule, n):
     # weights up to 127: at small beta many fields lie beyond the LDS part of
     # the threshold table, so blocks take the exact re-decision path
     rng = np.random.default_rng(3)
     A = rng.integers(-127, 128, size=(n, n)).astype(np.int8)
     J = np.triu(A, 1)
     J = (J + J.T).astype(np.int8)
-    say(f"case dense i8 objective={objective} n={n}")
-    inst = pamc.Instance.dense(J, replicas=64, seed=9, objective=objective)
-    o = oracle.Oracle.dense(J, 64, 9, objective=objective)
+    say(f"case dense i8 objective={objective} rule={rule} n={n}")
+    inst = pamc.Instance.dense(J, replicas=64, seed=9, objective=objective, rule=rule)
+    o = oracle.Oracle.dense(J, 64, 9, objective=objective, rule=rule)
     assert inst.info().W == o.W
     for beta in (0.001, 0.01, 0.05):
         inst.sweep(beta, 1)
