@@ -363,8 +363,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "kernel": "neg (elementwise)"}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU replica sharding is design-only "
-              "(see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU; sharding the population across GPUs is not "
+              "implemented. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
