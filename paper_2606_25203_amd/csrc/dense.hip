@@ -957,9 +957,10 @@ struct GemmShape {
 static inline GemmShape gemm_shape(const pamc_instance* I, int rows, int kcount) {
   const int tiles = ((rows + kGM - 1) / kGM) * ((I->R + kGN - 1) / kGN);
   const int stages = std::max(1, kcount / kGK);
-  // at least 8 stages per work-group: a short K range (the previous
-  // super-block's columns) is not worth 16 atomic tile updates per stage
-  const int P = std::max(1, std::min(stages / 8, (512 + tiles - 1) / tiles));
+  // at least 4 stages per work-group: a short K range (the previous
+  // super-block's columns, 16 stages) splits in 4 slices (timed against
+  // 1, 2, 8 and 16 stages per work-group)
+  const int P = std::max(1, std::min(stages / 4, (512 + tiles - 1) / tiles));
   const int kslice = ((stages + P - 1) / P) * kGK;
   const int slices = (kcount + kslice - 1) / kslice;
   return {tiles * ((slices + 7) / 8) * 8, kslice};
