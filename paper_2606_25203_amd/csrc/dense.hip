@@ -945,22 +945,23 @@ hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed) {
 // rows of the super-block starting at row0 (a multiple of 64)
 static inline int sb_rows(const pamc_instance* I, int row0) { return std::min(kSB, I->dn_pad - row0); }
 
-// K slices of the field product: enough work-groups for two per compute
-// unit, each slice a multiple of the 64-column stage.
+// K slices of the field product, each a multiple of the 64-column stage.
 struct GemmShape {
   int grid, kslice;
 };
-// About 512 work-groups: the K range is cut into P slices of whole stages
-// (at least 8 per slice);
-// the grid covers the slices in groups of 8 (one per XCD; work-groups of
-// slices past the end return at once).
+// About 192 working work-groups: the K range is cut into P slices of whole
+// stages; the grid covers the slices in groups of 8 (one per XCD;
+// work-groups of slices past the end return at once).  The product shares
+// the device with the sequential pass, and fewer, longer work-groups leave
+// it more of the memory system: C3 sweeps timed at 128, 192, 256, 384, 512,
+// 768 and 1,024 were fastest at 192.
 static inline GemmShape gemm_shape(const pamc_instance* I, int rows, int kcount) {
   const int tiles = ((rows + kGM - 1) / kGM) * ((I->R + kGN - 1) / kGN);
   const int stages = std::max(1, kcount / kGK);
   // at least 4 stages per work-group: a short K range (the previous
   // super-block's columns, 16 stages) splits in 4 slices (timed against
   // 1, 2, 8 and 16 stages per work-group)
-  const int P = std::max(1, std::min(stages / 4, (512 + tiles - 1) / tiles));
+  const int P = std::max(1, std::min(stages / 4, (192 + tiles - 1) / tiles));
   const int kslice = ((stages + P - 1) / P) * kGK;
   const int slices = (kcount + kslice - 1) / kslice;
   return {tiles * ((slices + 7) / 8) * 8, kslice};
