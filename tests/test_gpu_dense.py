@@ -31,7 +31,7 @@ def same_state(inst, o, tag=""):
     assert np.array_equal(f, of), f"{tag}: lineage differs"
 
 
-@pytest.mark.parametrize("n,R", [(300, 64), (1000, 128), (130, 64)])
+@pytest.mark.parametrize("n,R", [(300, 64), (1000, 128), (130, 64), (1100, 320)])
 @pytest.mark.parametrize("rule", [0, 1])
 def test_dense_random_init_and_sweeps(pamc, n, R, rule):
     say(f"case dense random n={n} R={R} rule={rule}")
