@@ -1358,11 +1358,24 @@ __global__ void __launch_bounds__(256) k_rs_gather(const Desc* __restrict__ D,
     (cur ? a.F0 : a.F1)[c] = (cur ? a.F1 : a.F0)[p];
   }
   const int qb = chunk * kGatherQuadsPerBlock;
+  // the wave's spin words: every read issued before the first write, so
+  // that they are in flight together
+  constexpr int kPer = kGatherQuadsPerBlock / 4;
+  uint32_t w[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int q = qb + wave + 4 * i;
+    if (q < a.nq) w[i] = Ss[((size_t)pt * a.nq + q) * kLanes + pl];
+  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int q = qb + wave + 4 * i;
+    if (q < a.nq) Sd[((size_t)tile * a.nq + q) * kLanes + lane] = w[i];
+  }
+  if (!Hs) return;
   for (int qi = wave; qi < kGatherQuadsPerBlock; qi += 4) {
     const int q = qb + qi;
     if (q >= a.nq) break;
-    Sd[((size_t)tile * a.nq + q) * kLanes + lane] = Ss[((size_t)pt * a.nq + q) * kLanes + pl];
-    if (!Hs) continue;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
