@@ -1373,13 +1373,24 @@ __global__ void __launch_bounds__(256) k_rs_gather(const Desc* __restrict__ D,
     if (q < a.nq) Sd[((size_t)tile * a.nq + q) * kLanes + lane] = w[i];
   }
   if (!Hs) return;
-  for (int qi = wave; qi < kGatherQuadsPerBlock; qi += 4) {
-    const int q = qb + qi;
-    if (q >= a.nq) break;
+  // the fields (incremental mode), four quads (16 words) in flight at a time
+  for (int i0 = 0; i0 < kPer; i0 += 4) {
+    int32_t hv[4][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int v = 4 * q + k;
-      Hd[((size_t)tile * a.np + v) * kLanes + lane] = Hs[((size_t)pt * a.np + v) * kLanes + pl];
+    for (int i = 0; i < 4; ++i) {
+      const int q = qb + wave + 4 * (i0 + i);
+      if (q < a.nq) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hv[i][k] = Hs[((size_t)pt * a.np + 4 * q + k) * kLanes + pl];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = qb + wave + 4 * (i0 + i);
+      if (q < a.nq) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Hd[((size_t)tile * a.np + 4 * q + k) * kLanes + lane] = hv[i][k];
+      }
     }
   }
 }
