@@ -321,12 +321,17 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
     const size_t sidx = ((size_t)tile * d.nq + q) * kLanes + lane;
     uint32_t sw = S[sidx];
     const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
+    // the quad's four fields up front: vertices of one class are not
+    // neighbours, so no flip of this phase changes them (v < np always)
+    int32_t hq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hq[k] = H[(hbase + 4 * q + k) * kLanes + lane];
     bool dirty = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
       if (v < v0 || v >= v1) continue;
-      const int32_t h = H[(hbase + v) * kLanes + lane];
+      const int32_t h = hq[k];
       const int32_t s = (int32_t)(int8_t)(sw >> (8 * k));
       const int32_t x = s * h;
       const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
