@@ -314,18 +314,32 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
   const size_t hbase = (size_t)tile * d.np;
   int64_t dE = 0;
   int32_t nflip = 0;
-  for (int i = 0; i < d.qpw; ++i) {
+  // the spin words and fields of all of the wave's quads up front: the
+  // vertices of one class are not neighbours, so no flip of this phase
+  // changes them (v < np always)
+  constexpr int kMaxQpw = 4;
+  uint32_t swq[kMaxQpw];
+  int32_t hqq[kMaxQpw][4];
+#pragma unroll
+  for (int i = 0; i < kMaxQpw; ++i) {
+    const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
+    if (i < d.qpw && qi < nqc) {
+      const int q = q0 + qi;
+      swq[i] = S[((size_t)tile * d.nq + q) * kLanes + lane];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hqq[i][k] = H[(hbase + 4 * q + k) * kLanes + lane];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxQpw; ++i) {
+    if (i >= d.qpw) break;
     const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
     if (qi >= nqc) break;
     const int q = q0 + qi;
     const size_t sidx = ((size_t)tile * d.nq + q) * kLanes + lane;
-    uint32_t sw = S[sidx];
+    uint32_t sw = swq[i];
     const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
-    // the quad's four fields up front: vertices of one class are not
-    // neighbours, so no flip of this phase changes them (v < np always)
-    int32_t hq[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) hq[k] = H[(hbase + 4 * q + k) * kLanes + lane];
+    const int32_t (&hq)[4] = hqq[i];
     bool dirty = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
