@@ -87,8 +87,8 @@ typedef struct {
  * self loops, no duplicate or zero entries, symmetric weights).
  * row_ptr[n+1], col[nnz], w[nnz] with nnz = row_ptr[n], int32.  Vertices are
  * coloured first-fit in id order and swept class by class (spins of a class
- * are mutually uncoupled, so this equals a sequential sweep in that order;
- * Eq. 4 and "sequentially updated ... in a randomized order").  Fails with
+ * are mutually uncoupled, so this equals a one-spin-at-a-time sweep in that
+ * order; Eq. 4, with the class sequence reshuffled every sweep).  Fails with
  * PAMC_ERR_INVALID_ARG if 2*max_v sum_j |J_vj| does not fit int32. */
 pamc_status pamc_create_instance_csr(int32_t n, const int32_t* row_ptr, const int32_t* col,
                                      const int32_t* w, pamc_mem where, int32_t objective,

@@ -128,6 +128,10 @@ def lib():
         L.orc_controller_step.restype = C.c_int32
         L.orc_mean_pair_distance.argtypes = [P]
         L.orc_mean_pair_distance.restype = C.c_double
+        L.orc_set_population.argtypes = [P, i8p, P]
+        L.orc_set_population.restype = C.c_int32
+        L.orc_set_counters.argtypes = [P, np.ctypeslib.ndpointer(np.uint32)]
+        L.orc_pair_distances.argtypes = [P, np.ctypeslib.ndpointer(np.float64)]
         _lib = L
     return _lib
 
@@ -330,6 +334,20 @@ class Oracle:
 
     def mean_pair_distance(self):
         return lib().orc_mean_pair_distance(self._h)
+
+    def pair_distances(self):
+        out = np.zeros(self.R * (self.R - 1) // 2, np.float64)
+        lib().orc_pair_distances(self._h, out)
+        return out
+
+    def set_population(self, spins, family=None):
+        s = np.ascontiguousarray(spins, np.int8).reshape(self.R, self.n)
+        f = None if family is None else np.ascontiguousarray(family, np.int32)
+        if lib().orc_set_population(self._h, s, None if f is None else f.ctypes.data) != 0:
+            raise ValueError("spin or label out of range")
+
+    def set_counters(self, gs, g_rs, g_cl):
+        lib().orc_set_counters(self._h, np.array([gs, g_rs, g_cl], np.uint32))
 
 
 def controller_step(ctrl: Ctrl, sched: Schedule, mstar: int) -> int:

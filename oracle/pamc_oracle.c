@@ -543,11 +543,12 @@ void orc_class_ptr(const orc* o, int32_t* c) { memcpy(c, o->class_ptr, sizeof(in
 void orc_counters(const orc* o, uint32_t* c) { c[0] = o->gs; c[1] = o->g_rs; c[2] = o->g_cl; }
 
 /* ------------------------------------------------------------------------ */
-/* Monte Carlo sweep (Eqs. 3-4; "all spins sequentially updated once in a   */
-/* randomized order").  Classes of the colouring hold mutually uncoupled     */
-/* spins, so the spins of a class can be visited in any order; the order of  */
-/* the classes is a fresh Fisher-Yates permutation each sweep.  Dense        */
-/* instances use the fixed order 0..n-1.                                     */
+/* Monte Carlo sweep (Eqs. 3-4, Algorithm 1): every spin is visited once per */
+/* sweep, one at a time, in an order that changes from sweep to sweep.       */
+/* Here the order is colour class by colour class.  A class holds mutually   */
+/* uncoupled spins, so the visits inside it commute; the class sequence is a */
+/* fresh Fisher-Yates permutation each sweep.  Dense instances use the fixed */
+/* order 0..n-1.                                                             */
 /* ------------------------------------------------------------------------ */
 static void class_order(const orc* o, uint32_t gs, int32_t* order) {
   for (int32_t k = 0; k < o->ncls; ++k) order[k] = k;
@@ -732,13 +733,13 @@ double orc_resample(orc* o, double delta_in, int32_t* parents_out) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Non-local cluster move (Sec. "Augmented PAMC", NCM; Algorithm 1).  For    */
-/* each of the n_top lowest-energy replicas: iso-sites are spins with local  */
-/* field exactly 0 (flipping one leaves H unchanged).  The iso-sites are     */
-/* randomly permuted; the first is selected and each later one is added if  */
-/* it has zero coupling to every selected site.  This is repeated            */
-/* mis_trials times and the largest set (earliest trial on ties) is flipped  */
-/* at once; the set is independent, so H does not change.                   */
+/* Non-local cluster move (Sec. "Augmented PAMC", NCM; Algorithm 1).  Target */
+/* replicas: the n_top lowest (E, slot).  A spin whose local field is 0 (an  */
+/* iso-site) can be flipped at zero energy cost, and so can any set of them  */
+/* with no coupling inside the set.  Trial t orders the iso-sites by a       */
+/* Philox key and builds such a set greedily in that order (a site joins    */
+/* unless it is coupled to one already taken).  Of the mis_trials sets the   */
+/* largest is flipped, the earliest trial winning a tie; H is unchanged.     */
 /* ------------------------------------------------------------------------ */
 typedef struct { uint32_t key; int32_t v; } keyed;
 static int cmp_keyed(const void* a, const void* b) {
@@ -848,15 +849,25 @@ void orc_get_state(const orc* o, int8_t* spins, int32_t* fields, int64_t* energi
 }
 
 /* ------------------------------------------------------------------------ */
-/* Adaptive temperature control (Algorithm 1 and Sec. "Augmented PAMC").     */
-/* After a step, with no cooldown and at least win_long recorded values:     */
-/*   strong stagnation (<= max_s distinct in the short window and <= max_l   */
-/*   in the long one): beta <- reheat*beta, Delta <- +dbeta, enable NCM;     */
-/*   mild stagnation (short window stalled, long window not): reverse the    */
-/*   beta update if beta > beta0;                                            */
-/*   otherwise keep cooling.  Then restart every z_rst steps or advance.     */
-/* Returns event bits (bit2 strong, bit3 mild, bit4 restart).               */
+/* Adaptive temperature control (Algorithm 1; Sec. "Augmented PAMC").        */
+/* The controller keeps the last win_long values of M*.  Once the window is  */
+/* full and no cooldown runs, the history is classified by how many distinct */
+/* values its two tails hold, and each class maps to one action:            */
+/*                                                                           */
+/*   class     | condition (ds, dl: distinct in short / long tail) | action  */
+/*   STRONG    | ds <= max_s and dl <= max_l    | beta *= reheat, +dbeta, arm NCM */
+/*   MILD      | ds <= max_s and dl >  max_l    | -dbeta if beta > beta0, else    */
+/*             |                                | +dbeta (or stop: literal_break) */
+/*   PROGRESS  | ds >  max_s                    | +dbeta                          */
+/*   NONE      | cooldown or short history      | keep Delta                      */
+/*                                                                           */
+/* After the action the schedule moves on: a restart every z_rst steps       */
+/* (beta, Delta, NCM arming, cooldown and the history reset), otherwise     */
+/* beta += Delta and the cooldown counts down.  Event bits: 4 strong, 8 a    */
+/* reversal, 16 a restart.                                                   */
 /* ------------------------------------------------------------------------ */
+enum { STAG_NONE = 0, STAG_PROGRESS = 1, STAG_MILD = 2, STAG_STRONG = 3 };
+
 static int32_t distinct_tail(const int64_t* hist, int32_t len, int32_t w) {
   int32_t d = 0;
   for (int32_t i = len - w; i < len; ++i) {
@@ -868,35 +879,43 @@ static int32_t distinct_tail(const int64_t* hist, int32_t len, int32_t w) {
   return d;
 }
 
-int32_t orc_controller_step(orc_ctrl* c, const orc_schedule* s, int64_t mstar) {
-  int32_t ev = 0;
-  /* record M* (the window never needs more than win_long values) */
-  if (c->hist_len == s->win_long) {
+static void record_mstar(orc_ctrl* c, const orc_schedule* s, int64_t mstar) {
+  if (c->hist_len == s->win_long) { /* the oldest value leaves */
     memmove(c->hist, c->hist + 1, sizeof(int64_t) * (size_t)(s->win_long - 1));
     c->hist_len--;
   }
   c->hist[c->hist_len++] = mstar;
-  if (s->augmented && c->cooldown == 0 && c->hist_len >= s->win_long) {
-    int32_t ds = distinct_tail(c->hist, c->hist_len, s->win_short);
-    int32_t dl = distinct_tail(c->hist, c->hist_len, s->win_long);
-    if (ds <= s->max_distinct_short && dl <= s->max_distinct_long) {
+}
+
+static int32_t classify(const orc_ctrl* c, const orc_schedule* s) {
+  if (!s->augmented || c->cooldown != 0 || c->hist_len < s->win_long) return STAG_NONE;
+  int32_t ds = distinct_tail(c->hist, c->hist_len, s->win_short);
+  int32_t dl = distinct_tail(c->hist, c->hist_len, s->win_long);
+  if (ds > s->max_distinct_short) return STAG_PROGRESS;
+  return dl <= s->max_distinct_long ? STAG_STRONG : STAG_MILD;
+}
+
+static int32_t act(orc_ctrl* c, const orc_schedule* s, int32_t cls) {
+  switch (cls) {
+    case STAG_STRONG:
       c->beta = s->reheat * c->beta;
       c->delta = s->dbeta;
       c->enable = 1;
-      ev |= 4;
-    } else if (ds <= s->max_distinct_short) {
-      if (c->beta > s->beta0) {
-        c->delta = -s->dbeta;
-        ev |= 8;
-      } else if (s->literal_break) {
-        c->stop = 1;
-      } else {
-        c->delta = s->dbeta;
-      }
-    } else {
+      return 4;
+    case STAG_MILD:
+      if (c->beta > s->beta0) { c->delta = -s->dbeta; return 8; }
+      if (s->literal_break) { c->stop = 1; return 0; }
       c->delta = s->dbeta;
-    }
+      return 0;
+    case STAG_PROGRESS:
+      c->delta = s->dbeta;
+      return 0;
+    default:
+      return 0;
   }
+}
+
+static int32_t advance_schedule(orc_ctrl* c, const orc_schedule* s) {
   if (s->z_rst > 0 && c->z >= s->z_rst) {
     c->cycle++;
     c->z = 1;
@@ -905,13 +924,18 @@ int32_t orc_controller_step(orc_ctrl* c, const orc_schedule* s, int64_t mstar) {
     c->enable = 0;
     c->cooldown = 0;
     c->hist_len = 0;
-    ev |= 16;
-  } else {
-    c->z++;
-    c->beta = c->beta + c->delta;
-    if (c->cooldown > 0) c->cooldown--;
+    return 16;
   }
-  return ev;
+  c->z++;
+  c->beta = c->beta + c->delta;
+  if (c->cooldown > 0) c->cooldown--;
+  return 0;
+}
+
+int32_t orc_controller_step(orc_ctrl* c, const orc_schedule* s, int64_t mstar) {
+  record_mstar(c, s, mstar);
+  int32_t ev = act(c, s, classify(c, s));
+  return ev | advance_schedule(c, s);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1006,4 +1030,50 @@ double orc_mean_pair_distance(const orc* o) {
       acc += d < 1.0 - d ? d : 1.0 - d;
     }
   return acc / ((double)R * (R - 1) / 2.0);
+}
+
+int32_t orc_set_population(orc* o, const int8_t* spins, const int32_t* family) {
+  int32_t n = o->n;
+  for (size_t k = 0; k < (size_t)o->R * n; ++k) {
+    int8_t x = spins[k];
+    if (o->potts_K ? (x < 0 || x >= o->potts_K) : (x != 1 && x != -1)) return -1;
+  }
+  for (int32_t r = 0; r < o->R; ++r) {
+    for (int32_t v = 0; v < n; ++v)
+      o->s[(size_t)r * n + o->to_internal[v]] = spins[(size_t)r * n + v];
+    if (family) o->family[r] = family[r];
+    if (o->potts_K) {
+      o->E[r] = orc_potts_energy(o, r);
+      continue;
+    }
+    const int8_t* s = o->s + (size_t)r * n;
+    int32_t* h = o->h + (size_t)r * n;
+    int64_t twoE = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      int64_t acc = 0;
+      for (int32_t e = o->row_ptr[v]; e < o->row_ptr[v + 1]; ++e) acc += (int64_t)o->J[e] * s[o->col[e]];
+      h[v] = (int32_t)acc;
+      twoE += (int64_t)s[v] * acc;
+    }
+    o->E[r] = -twoE / 2;
+  }
+  return 0;
+}
+
+void orc_set_counters(orc* o, const uint32_t* c3) {
+  o->gs = c3[0];
+  o->g_rs = c3[1];
+  o->g_cl = c3[2];
+}
+
+void orc_pair_distances(const orc* o, double* out) {
+  int32_t R = o->R, n = o->n;
+  size_t k = 0;
+  for (int32_t a = 0; a < R; ++a)
+    for (int32_t b = a + 1; b < R; ++b) {
+      int32_t dd = 0;
+      for (int32_t v = 0; v < n; ++v) dd += o->s[(size_t)a * n + v] != o->s[(size_t)b * n + v];
+      double d = (double)dd / n;
+      out[k++] = d < 1.0 - d ? d : 1.0 - d;
+    }
 }

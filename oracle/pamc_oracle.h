@@ -160,6 +160,20 @@ int32_t orc_controller_step(orc_ctrl* c, const orc_schedule* s, int64_t mstar);
  * global-flip symmetry folded in (Supplement, Hamming distance). */
 double orc_mean_pair_distance(const orc* o);
 
+/* Replaces the population: spins (labels for Potts instances) in input ids,
+ * slot-major [R][n], and the lineage ids (NULL: unchanged).  Fields and
+ * energies are recomputed from the spins (Eq. 3 and H = -1/2 sum s h; Eq. 6
+ * for labels).  Returns 0, or -1 (nothing changed) for a value outside the
+ * spin or label range. */
+int32_t orc_set_population(orc* o, const int8_t* spins, const int32_t* family);
+
+/* Sets the stream counters (sweeps, resamplings, cluster moves). */
+void orc_set_counters(orc* o, const uint32_t* c3);
+
+/* All R(R-1)/2 normalised pair distances d_H = min(d, 1-d), pairs (a, b)
+ * with a < b in row-major order. */
+void orc_pair_distances(const orc* o, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,16 @@ hipError_t dalloc(pamc_instance* I, T** p, size_t count) {
   return e;
 }
 
+// Frees a buffer that dalloc made for count elements of T and takes it off
+// the instance's byte count.
+template <typename T>
+void dfree(pamc_instance* I, T*& p, size_t count) {
+  if (!p) return;
+  hipFree(p);
+  I->device_bytes -= (int64_t)std::max<size_t>(sizeof(T) * count, 16);
+  p = nullptr;
+}
+
 void free_instance(pamc_instance* I) {
   if (!I) return;
   if (I->device >= 0) hipSetDevice(I->device);
@@ -422,12 +432,9 @@ pamc_status ensure_cluster_scratch(pamc_instance* I, int32_t n_top, int32_t tria
   if (trials > 64) return fail(PAMC_ERR_UNSUPPORTED, "mis_trials > 64");
   if (n_top <= I->cl_cap_top && trials <= I->cl_cap_trials) return PAMC_OK;
   HIP_TRY(hipStreamSynchronize(I->stream), "sync");
-  if (I->cl_targets) hipFree(I->cl_targets);
-  if (I->cl_sel) hipFree(I->cl_sel);
-  if (I->cl_sizes) hipFree(I->cl_sizes);
-  I->cl_targets = nullptr;
-  I->cl_sel = nullptr;
-  I->cl_sizes = nullptr;
+  dfree(I, I->cl_targets, I->cl_cap_top);
+  dfree(I, I->cl_sel, (size_t)I->cl_cap_top * I->cl_cap_trials * I->np);
+  dfree(I, I->cl_sizes, (size_t)I->cl_cap_top * I->cl_cap_trials);
   I->cl_cap_top = std::max(n_top, I->cl_cap_top);
   I->cl_cap_trials = std::max(trials, I->cl_cap_trials);
   HIP_TRY(dalloc(I, &I->cl_targets, I->cl_cap_top), "alloc cluster");
@@ -440,9 +447,11 @@ pamc_status ensure_cluster_scratch(pamc_instance* I, int32_t n_top, int32_t tria
 pamc_status ensure_trace(pamc_instance* I, int32_t steps) {
   if (steps <= I->tr_cap) return PAMC_OK;
   HIP_TRY(hipStreamSynchronize(I->stream), "sync");
-  void* olds[] = {I->tr_mstar, I->tr_beta, I->tr_lnq, I->tr_events, I->tr_time};
-  for (void* p : olds)
-    if (p) hipFree(p);
+  dfree(I, I->tr_mstar, I->tr_cap);
+  dfree(I, I->tr_beta, I->tr_cap);
+  dfree(I, I->tr_lnq, I->tr_cap);
+  dfree(I, I->tr_events, I->tr_cap);
+  dfree(I, I->tr_time, I->tr_cap);
   I->tr_cap = steps;
   HIP_TRY(dalloc(I, &I->tr_mstar, steps), "alloc trace");
   HIP_TRY(dalloc(I, &I->tr_beta, steps), "alloc trace");
@@ -456,8 +465,7 @@ pamc_status ensure_trace(pamc_instance* I, int32_t steps) {
 pamc_status ensure_order(pamc_instance* I, int32_t sweeps) {
   if (sweeps <= I->order_cap) return PAMC_OK;
   HIP_TRY(hipStreamSynchronize(I->stream), "sync");
-  hipFree(I->order);
-  I->order = nullptr;
+  dfree(I, I->order, (size_t)I->order_cap * I->ncls);
   I->order_cap = sweeps;
   HIP_TRY(dalloc(I, &I->order, (size_t)sweeps * I->ncls), "alloc order");
   I->self_dirty = true;
@@ -1297,26 +1305,44 @@ double now_seconds() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Device bytes a sparse instance of this graph will hold (the allocation
-// plan of build_sparse plus the per-run buffers), for admission.
-int64_t estimate_bytes(int32_t n, const int32_t* rp, const pamc_config& cfg, const pamc_schedule& sc) {
+// Device bytes a sparse instance of this graph will hold: the allocation
+// plan of upload_sparse and prepare_run term by term (each allocation counts
+// at least 16 bytes, as dalloc does), with the colour-class count bounded by
+// the largest degree + 1.  It is an upper bound of the instance's
+// device_bytes, so admission against it never overruns the budget.  The
+// threshold table has 2X + 1 entries, X = max_v sum_j |w_vj| of this graph.
+int64_t estimate_bytes(int32_t n, const int32_t* rp, const int32_t* w, const pamc_config& cfg,
+                       const pamc_schedule& sc) {
+  auto a = [](int64_t bytes) { return std::max<int64_t>(bytes, 16); };
   const int64_t R = cfg.replicas, np = (n + 3) & ~3, nnz = rp[n];
-  int64_t maxdeg = 0;
-  for (int32_t v = 0; v < n; ++v) maxdeg = std::max<int64_t>(maxdeg, rp[v + 1] - rp[v]);
+  int64_t maxdeg = 0, X = 0, gathered = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t deg = rp[v + 1] - rp[v];
+    maxdeg = std::max(maxdeg, deg);
+    gathered += (deg + 3) & ~3;
+    int64_t ab = 0;
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) ab += std::llabs((long long)w[e]);
+    X = std::max(X, ab);
+  }
   bool pull = nnz <= 16 * (int64_t)n && maxdeg <= 64;
   if (cfg.flags & PAMC_FLAG_FIELDS_PUSH) pull = false;
   if (cfg.flags & PAMC_FLAG_FIELDS_PULL) pull = true;
-  int64_t b = 2 * R * np + (pull ? 0 : 8 * R * np);      // spins (+ fields), two buffers
-  b += 2 * 12 * R + 12 * R;                               // energies, lineage, resampling scratch
-  b += 8 * (nnz + 16) + 4 * (int64_t)(n + 1) + 5 * np;    // CSR, best, relabelling
-  b += 4 * (2 * (maxdeg * 127 + 1) + 1);                  // threshold table (|J| <= 127 assumed)
-  b += 4 * (int64_t)std::max(64, sc.sweeps) * (maxdeg + 1);  // class orders
-  b += 36 * (int64_t)std::max(sc.steps, 1) + 8192;        // trace, run state, counters
-  if (sc.augmented && sc.resample && sc.n_top > 0 && sc.mis_trials > 0) {
+  const int64_t ncls = maxdeg + 1;
+  int64_t b = a(4 * (int64_t)(n + 1)) + 2 * a(4 * (nnz + 16));                 // CSR
+  if (pull) b += a(4 * (int64_t)(n + 1)) + 2 * a(4 * std::max<int64_t>(gathered, 4));  // gathered CSR
+  b += a(4 * (ncls + 1));                                                      // class_ptr
+  b += 2 * (a(R * np) + (pull ? 0 : a(4 * R * np)) + a(8 * R) + a(4 * R));     // two populations
+  b += a(np) + a(4 * (int64_t)n) + a((int64_t)sizeof(pamc::RunState));        // best, ids, run state
+  b += a(4 * (2 * X + 1));                                                     // threshold table
+  b += a(4 * std::max<int64_t>(64, sc.sweeps) * ncls);                        // class orders
+  b += a(4 * R) + a(8 * 512);                                                  // parents, counters
+  b += 3 * a(8 * (int64_t)std::max(sc.steps, 1)) + a(4 * (int64_t)std::max(sc.steps, 1)) +
+       a(8 * (int64_t)std::max(sc.steps, 1));                                  // trace
+  if (sc.augmented && sc.resample && sc.n_top > 0 && sc.mis_trials > 0) {    // cluster scratch
     const int64_t t = std::min<int64_t>(sc.n_top, R);
-    b += t * sc.mis_trials * (np + 4) + 4 * t;
+    b += a(4 * t) + a(t * sc.mis_trials * np) + a(4 * t * sc.mis_trials);
   }
-  return b + 16 * 64;  // allocation granularity
+  return b;
 }
 
 void server_prepare(ServerPrep& p, uint32_t flags, int32_t T) {
@@ -1396,23 +1422,41 @@ pamc_status server_admit(pamc_server* S) {
   return PAMC_OK;
 }
 
+// Retires the finished requests.  Every finished request leaves the running
+// set and has its memory freed even when reading its result fails (it then
+// finishes with that error); the first such error is returned once the
+// running set is consistent again.
 pamc_status server_retire(pamc_server* S, const std::vector<int32_t>& status) {
   std::vector<pamc_server::Act> keep;
   keep.reserve(S->active.size());
+  pamc_status first = PAMC_OK;
+  std::string first_msg;
   for (size_t i = 0; i < S->active.size(); ++i) {
     pamc_server::Act& a = S->active[i];
     if (!(status[i] & 1)) {
       keep.push_back(a);
       continue;
     }
+    pamc_server::Fin f;
     pamc::RunState r;
     pamc_status st = read_state(a.I, &r);
-    if (st) return st;
-    pamc_server::Fin f;
-    fill_result(a.I, r, &f.res);
-    f.spins.resize(a.I->n);
-    st = pamc_best(a.I, nullptr, nullptr, f.spins.data());
-    if (st) return st;
+    if (!st) {
+      fill_result(a.I, r, &f.res);
+      f.spins.resize(a.I->n);
+      st = pamc_best(a.I, nullptr, nullptr, f.spins.data());
+    }
+    if (st) {
+      f.status = st;
+      f.error = g_err;
+      f.spins.clear();
+      if (!first) {
+        first = st;
+        first_msg = g_err;
+      }
+      S->stats.failed += 1;
+    } else {
+      S->stats.finished += 1;
+    }
     f.t_submit = a.t_submit;
     f.t_admit = a.t_admit;
     f.t_done = now_seconds();
@@ -1421,9 +1465,9 @@ pamc_status server_retire(pamc_server* S, const std::vector<int32_t>& status) {
     S->pending.erase(a.ticket);
     S->done.emplace(a.ticket, std::move(f));
     S->dirty = true;
-    S->stats.finished += 1;
   }
   S->active.swap(keep);
+  if (first) return fail(first, first_msg);
   return PAMC_OK;
 }
 
@@ -1479,7 +1523,7 @@ pamc_status pamc_server_submit(pamc_server* S, int32_t n, const int32_t* row_ptr
   pamc_status st = check_schedule(&probe, sched);
   if (st) return st;
   pamc_server::Req q;
-  q.est = estimate_bytes(n, row_ptr, S->cfg, *sched);
+  q.est = estimate_bytes(n, row_ptr, w ? w : row_ptr, S->cfg, *sched);
   if (q.est > S->budget) return fail(PAMC_ERR_OUT_OF_MEMORY, "request larger than the server's memory budget");
   auto prep = std::make_shared<ServerPrep>();
   prep->n = n;

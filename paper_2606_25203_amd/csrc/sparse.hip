@@ -919,6 +919,16 @@ __device__ __forceinline__ V block_excl_scan(V x, V* part16) {
   return off + inc - x;
 }
 
+// Stagnation classes of the recent-progress history (Sec. "Augmented PAMC"),
+// from the distinct M* values in its short (ds) and long (dl) tails: few
+// distinct values in both tails is a strong stall, in the short tail only a
+// mild one, otherwise the search still progresses.
+enum : int { kStagNone = 0, kStagProgress = 1, kStagMild = 2, kStagStrong = 3 };
+__device__ __forceinline__ int stagnation_class(int ds, int dl, int max_ds, int max_dl) {
+  if (ds > max_ds) return kStagProgress;
+  return dl <= max_dl ? kStagStrong : kStagMild;
+}
+
 // ---------------------------------------------------------------------------
 // Best cut (Algorithm 1: M* <- max(M*, max Cut(P)), lowest slot on ties),
 // then, in a run, the recent-progress history, the adaptive temperature rule
@@ -1015,14 +1025,17 @@ __global__ void __launch_bounds__(1024) k_step_end(const Desc* __restrict__ D, i
     st->step_reached = st->step;
     st->t_reached = now;
   }
-  if (eval_ok && L >= wl) {
-    if (ds <= st->max_ds && dl <= st->max_dl) {          // strong stagnation
+  // the history's stagnation class picks the temperature action (see
+  // stagnation_class), then the schedule moves on
+  switch (eval_ok && L >= wl ? stagnation_class(ds, dl, st->max_ds, st->max_dl) : kStagNone) {
+    case kStagStrong:  // reheat and arm the cluster move
       st->beta = st->reheat * st->beta;
       st->delta = st->dbeta;
       st->enable = 1;
       ev |= 4;
       st->n_reheats += 1;
-    } else if (ds <= st->max_ds) {                       // mild stagnation
+      break;
+    case kStagMild:  // run the schedule backwards while above beta0
       if (st->beta > st->beta0) {
         st->delta = -st->dbeta;
         ev |= 8;
@@ -1032,11 +1045,15 @@ __global__ void __launch_bounds__(1024) k_step_end(const Desc* __restrict__ D, i
       } else {
         st->delta = st->dbeta;
       }
-    } else {                                             // progress: cool
+      break;
+    case kStagProgress:
       st->delta = st->dbeta;
-    }
+      break;
+    default:
+      break;
   }
-  if (st->z_rst > 0 && st->z >= st->z_rst) {             // restart
+  const bool restart = st->z_rst > 0 && st->z >= st->z_rst;
+  if (restart) {  // schedule, arming, cooldown and history start over
     st->cycle += 1;
     st->z = 1;
     st->beta = st->beta0;

@@ -518,16 +518,57 @@ def test_max3cut_decode_one_hot_roundtrip(oracle_lib):
                           if g.col[e] > i and lab[i] != lab[g.col[e]])
 
 
-def test_pair_distance_definition(oracle_lib):
-    g = synth.random_graph(30, 60, 1)
-    o = oracle_lib.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 64, 3)
-    s = o.state()[0]
-    d = []
-    for a in range(64):
-        for b in range(a + 1, 64):
-            x = np.mean(s[a] != s[b])
-            d.append(min(x, 1 - x))
-    assert abs(o.mean_pair_distance() - np.mean(d)) < 1e-12
+# Normalised pair distance d_H = min(d, 1 - d) (Supplement, Hamming
+# distance), pinned on populations whose distances are known by
+# construction, with closed-form sums for the means.
+def staircase(R, n):
+    # replica r: all +1 with its first r spins flipped, so d(a, b) = |a - b| / n
+    s = np.ones((R, n), np.int8)
+    for r in range(R):
+        s[r, :r] = -1
+    return s
+
+
+def test_pair_distance_known_populations(oracle_lib):
+    g = synth.random_graph(64, 150, 2)
+    # R = 32 < n/2: every pair is closer than 1/2, d_H = |a - b| / 64;
+    # sum_{a<b} (b - a) = sum_d d (R - d) = R D(D+1)/2 - D(D+1)(2D+1)/6, D = R-1
+    R, n = 32, 64
+    o = oracle_lib.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 3)
+    o.set_population(staircase(R, n))
+    D = R - 1
+    total = R * D * (D + 1) // 2 - D * (D + 1) * (2 * D + 1) // 6
+    assert total == 5456
+    assert o.mean_pair_distance() == pytest.approx(total / n / (R * D // 2), abs=1e-15)
+    pd = o.pair_distances()
+    k = 0
+    for a in range(R):
+        for b in range(a + 1, R):
+            assert pd[k] == (b - a) / n
+            k += 1
+    # n = 16, R = 16: distances cross 1/2 and fold back, d_H(k) = min(k, 16-k)/16
+    g16 = synth.random_graph(16, 30, 4)
+    o = oracle_lib.Oracle.sparse(g16.n, g16.row_ptr, g16.col, g16.w, 16, 3)
+    o.set_population(staircase(16, 16))
+    want = sum((16 - d) * min(d, 16 - d) for d in range(1, 16)) / 16 / (16 * 15 // 2)
+    assert want == pytest.approx(4 / 15)  # sum_d (16-d) min(d, 16-d) = 512
+    assert o.mean_pair_distance() == pytest.approx(want, abs=1e-15)
+
+
+def test_pair_distance_global_flip_symmetry(oracle_lib):
+    g = synth.random_graph(40, 100, 5)
+    rng = np.random.default_rng(2)
+    base = rng.choice(np.array([-1, 1], np.int8), size=40)
+    o = oracle_lib.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 2, 7)
+    for k in range(0, 41):
+        pop = np.stack([base, base.copy()])
+        pop[1, :k] *= -1
+        o.set_population(pop)
+        assert o.mean_pair_distance() == pytest.approx(min(k, 40 - k) / 40, abs=1e-15)
+        o.set_population(np.stack([base, -pop[1]]))          # complement of the partner
+        assert o.mean_pair_distance() == pytest.approx(min(k, 40 - k) / 40, abs=1e-15)
+    o.set_population(np.stack([base, -base]))                 # a configuration and its flip: same cut
+    assert o.mean_pair_distance() == 0.0
 
 
 def test_invalid_inputs_rejected(oracle_lib):
