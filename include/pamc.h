@@ -287,6 +287,23 @@ pamc_status pamc_synchronize(pamc_instance* inst);
 pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* scheds, int32_t count,
                               pamc_result* out);
 
+/* The same batched run for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It calls no hipMalloc, hipFree or other allocating routine:
+ * the batch's descriptors, launch maps and schedules, each instance's class
+ * orders and its cluster-move scratch (n_top x mis_trials x n bytes) are
+ * carved from a fixed 16 MiB device array that every GPU the library runs
+ * on holds until the process ends.  A batch that needs more returns
+ * PAMC_ERR_UNSUPPORTED (pamc_last_error() states the bytes needed) before
+ * any device work.  Results and final populations equal pamc_anneal_batch's
+ * bit for bit; no per-step trace is recorded (pamc_get_trace then reports
+ * 0 steps), beta steps are launched one by one (no graph), and profiling is
+ * off.  All calls on one GPU share the array, so calls that overlap on one
+ * GPU (other threads) race; a call returns only after its device work is
+ * done. */
+pamc_status pamc_anneal_batch_noalloc(pamc_instance* const* insts, const pamc_schedule* scheds,
+                                      int32_t count, pamc_result* out);
+
 typedef struct pamc_server pamc_server;
 
 /* Continuous-batching server on cfg->device: requests (a graph, a seed and a

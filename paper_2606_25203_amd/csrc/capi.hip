@@ -1028,6 +1028,7 @@ pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_resul
   st = read_state(I, &r);
   if (!st && I->prof) st = resolve_events(I);
   if (st) return st;
+  I->trace_ok = true;
   fill_result(I, r, out);
   return PAMC_OK;
 }
@@ -1087,6 +1088,79 @@ pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* 
     pamc::RunState r;
     pamc_status st = read_state(v[i], &r);
     if (st) return st;
+    v[i]->trace_ok = true;
+    fill_result(v[i], r, &out[i]);
+  }
+  return PAMC_OK;
+}
+
+pamc_status pamc_anneal_batch_noalloc(pamc_instance* const* insts, const pamc_schedule* scheds, int32_t count,
+                                      pamc_result* out) {
+  if (count < 0 || (count > 0 && (!insts || !scheds || !out))) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  if (count == 0) return PAMC_OK;
+  std::vector<pamc_instance*> v(insts, insts + count);
+  for (int32_t i = 0; i < count; ++i) {
+    if (!v[i]) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
+    if (v[i]->dense) return fail(PAMC_ERR_UNSUPPORTED, "batched runs take sparse instances");
+    if (v[i]->device != v[0]->device) return fail(PAMC_ERR_INVALID_ARG, "instances on different devices");
+    for (int32_t j = 0; j < i; ++j)
+      if (v[j] == v[i]) return fail(PAMC_ERR_INVALID_ARG, "an instance appears twice");
+    pamc_status st = check_schedule(v[i], &scheds[i]);
+    if (st) return st;
+  }
+  hipSetDevice(v[0]->device);
+  std::vector<Schedule> s(count);
+  int32_t max_steps = 0, any_stop = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    s[i] = to_sched(&scheds[i]);
+    if (!s[i].augmented) s[i].win_long = std::min(std::max(s[i].win_long, 1), pamc::kHistCap);
+    if (cluster_possible(s[i]) && !v[i]->potts_K) {
+      if (v[i]->n > pamc::cluster_max_n()) return fail(PAMC_ERR_UNSUPPORTED, "cluster moves need n <= 26000");
+      if (s[i].mis_trials > 64) return fail(PAMC_ERR_UNSUPPORTED, "mis_trials > 64");
+    }
+    max_steps = std::max(max_steps, s[i].steps);
+    any_stop |= s[i].stop_at_target;
+  }
+  void* scratch = nullptr;
+  size_t cap = 0;
+  HIP_TRY(pamc::fixed_scratch(&scratch, &cap), "hipGetSymbolAddress");
+  for (pamc_instance* I : v) HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  pamc::Batch b;
+  b.arena = (char*)scratch;
+  b.arena_cap = cap;
+  hipError_t e = pamc::batch_build(b, v, &s);
+  pamc::Schedule* d_sched = nullptr;
+  int32_t* d_status = nullptr;
+  if (e == hipSuccess) e = pamc::batch_alloc(b, (void**)&d_sched, sizeof(Schedule) * count);
+  if (e == hipSuccess) e = pamc::batch_alloc(b, (void**)&d_status, sizeof(int32_t) * count);
+  if (e == hipErrorOutOfMemory)
+    return fail(PAMC_ERR_UNSUPPORTED, "this batch needs " + std::to_string(b.arena_need) +
+                                          " bytes of device scratch; the fixed scratch holds " +
+                                          std::to_string(cap));
+  if (e != hipSuccess) return dev_fail(e, "batch descriptors");
+  e = hipMemcpyAsync(d_sched, s.data(), sizeof(Schedule) * count, hipMemcpyHostToDevice, b.stream);
+  if (e == hipSuccess) e = pamc::batch_anneal_setup(b, d_sched, nullptr, count);
+  std::vector<int32_t> status(count);
+  const int32_t chunk = any_stop ? 16 : std::max(max_steps, 1);
+  for (int32_t done = 0; done < max_steps && e == hipSuccess; done += chunk) {
+    e = pamc::batch_run_steps(b, std::min(chunk, max_steps - done));
+    if (e == hipSuccess && any_stop && done + chunk < max_steps) {
+      e = pamc::batch_status(b, d_status);
+      if (e == hipSuccess) e = hipMemcpyAsync(status.data(), d_status, sizeof(int32_t) * count, hipMemcpyDeviceToHost, b.stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+      bool all = true;
+      for (int32_t x : status) all = all && (x & 1);
+      if (all) break;
+    }
+  }
+  // the scratch is reused by the next call: nothing may still read it
+  if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+  if (e != hipSuccess) return dev_fail(e, "batched run");
+  for (int32_t i = 0; i < count; ++i) {
+    pamc::RunState r;
+    pamc_status st = read_state(v[i], &r);
+    if (st) return st;
+    v[i]->trace_ok = false;  // no trace was recorded
     fill_result(v[i], r, &out[i]);
   }
   return PAMC_OK;
@@ -1099,7 +1173,7 @@ pamc_status pamc_get_trace(pamc_instance* I, int32_t capacity, int64_t* mstar, d
   pamc::RunState r;
   pamc_status st = read_state(I, &r);
   if (st) return st;
-  const int32_t k = std::min(std::min(capacity, r.steps_run), I->tr_cap);
+  const int32_t k = I->trace_ok ? std::min(std::min(capacity, r.steps_run), I->tr_cap) : 0;
   if (steps) *steps = k;
   if (k <= 0) return PAMC_OK;
   if (mstar) HIP_TRY(hipMemcpy(mstar, I->tr_mstar, sizeof(int64_t) * k, hipMemcpyDeviceToHost), "readback");

@@ -86,6 +86,7 @@ struct pamc_instance {
   int32_t* tr_events = nullptr;
   uint64_t* tr_time = nullptr;
   int32_t tr_cap = 0;
+  bool trace_ok = false;  // the trace describes the last run (not one without a trace)
   double clock_hz = 100e6;
   // Max-3-Cut source graph (host and device)
   int32_t m3_n = 0;
@@ -188,6 +189,13 @@ struct Batch {
   hipGraphExec_t step_graph = nullptr;  // one captured beta step (batch_run_steps)
   int64_t graph_key = -1;
   bool graph_failed = false;
+  // Arena mode (arena != nullptr): the descriptors, maps and per-run scratch
+  // of batch_build are carved from [arena, arena + arena_cap) instead of
+  // hipMalloc, never freed by the batch, and the batch launches eagerly
+  // (no graph capture, no profiling events).  arena_need: bytes the last
+  // build asked for (set also when it did not fit).
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0, arena_need = 0;
   void free_device();
   Batch() = default;
   Batch(const Batch&) = delete;
@@ -196,9 +204,18 @@ struct Batch {
 };
 
 Desc make_desc(const pamc_instance* I);
+// Device memory of the batch: hipMalloc, or in arena mode the next 256-byte
+// aligned piece of the arena (hipErrorOutOfMemory once it is full).
+hipError_t batch_alloc(Batch& b, void** p, size_t bytes);
+// The library's fixed device scratch on the current device (a file-scope
+// __device__ array; its address is looked up once per device).
+hipError_t fixed_scratch(void** ptr, size_t* bytes);
 // (Re)builds the batch's descriptors and maps; scheds (optional) give the
 // sweeps per step and whether cluster moves can occur.  Synchronises the
-// stream.
+// stream.  In arena mode scheds are required and each instance's class
+// orders and cluster-move scratch come from the arena too, sized for its
+// schedule (the instance's own buffers of those kinds are not used, and no
+// per-step trace is recorded).
 hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const std::vector<Schedule>* scheds);
 hipError_t batch_init(Batch& b);                               // sparse instances
 // Loads schedules and clears the controller of the listed instances (all if

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1719,22 +1720,64 @@ int Batch::group_of(const pamc_instance* I) {
 }
 
 void Batch::free_device() {
-  if (d_desc) hipFree(d_desc);
+  const bool own = arena == nullptr;  // arena pieces are not the batch's to free
+  if (d_desc && own) hipFree(d_desc);
   d_desc = nullptr;
   Launch* all[] = {&init_spins, &init_fields, &thr, &thr_dense, &gather, &cl_mis, &cl_apply};
   for (Launch* l : all) {
-    if (l->map) hipFree(l->map);
+    if (l->map && own) hipFree(l->map);
     l->map = nullptr;
     l->grid = 0;
   }
   for (Launch& l : sweep) {
-    if (l.map) hipFree(l.map);
+    if (l.map && own) hipFree(l.map);
     l.map = nullptr;
     l.grid = 0;
   }
+  arena_used = 0;
   if (step_graph) hipGraphExecDestroy(step_graph);
   step_graph = nullptr;
   graph_key = -1;
+}
+
+hipError_t batch_alloc(Batch& b, void** p, size_t bytes) {
+  if (!b.arena) return hipMalloc(p, bytes);
+  const size_t at = (b.arena_used + 255) & ~(size_t)255;
+  b.arena_need = at + bytes;
+  if (bytes > b.arena_cap || at > b.arena_cap - bytes) return hipErrorOutOfMemory;
+  *p = b.arena + at;
+  b.arena_used = at + bytes;
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch for callers that cannot allocate device memory
+// (pamc_anneal_batch_noalloc).  Every GPU the library runs on holds its own
+// copy of this array until the process ends.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t kFixedScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+hipError_t fixed_scratch(void** ptr, size_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex m;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(m);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kFixedScratchBytes;
+  return hipSuccess;
 }
 
 static int64_t sweep_chunks(const pamc_instance* I) {
@@ -1770,6 +1813,37 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
   b.stream = insts[0]->stream;
   std::vector<Desc> desc(b.n);
   for (int i = 0; i < b.n; ++i) desc[i] = make_desc(insts[i]);
+  // arena mode: per-run scratch sized for each instance's schedule
+  std::vector<int32_t> cl_top(b.n), cl_trials(b.n);
+  for (int i = 0; i < b.n; ++i) {
+    cl_top[i] = std::min(insts[i]->cl_cap_top, insts[i]->R);
+    cl_trials[i] = insts[i]->cl_cap_trials;
+  }
+  if (b.arena) {
+    if (!scheds) return hipErrorInvalidValue;
+    for (int i = 0; i < b.n; ++i) {
+      const pamc_instance* I = insts[i];
+      const Schedule& s = (*scheds)[i];
+      Desc& d = desc[i];
+      d.flip_ctr = nullptr;
+      d.tr_cap = 0;
+      d.order_cap = std::max(s.sweeps, 1);
+      hipError_t e = batch_alloc(b, (void**)&d.order, sizeof(int32_t) * (size_t)d.order_cap * std::max(I->ncls, 1));
+      if (e != hipSuccess) return e;
+      const bool cl = s.augmented && s.resample && s.n_top > 0 && s.mis_trials > 0 && !I->potts_K && !I->dense;
+      cl_top[i] = cl ? std::min(s.n_top, I->R) : 0;
+      cl_trials[i] = cl ? s.mis_trials : 0;
+      d.cl_targets = nullptr;
+      d.cl_sel = nullptr;
+      d.cl_sizes = nullptr;
+      if (cl) {
+        if ((e = batch_alloc(b, (void**)&d.cl_targets, sizeof(int32_t) * cl_top[i])) != hipSuccess) return e;
+        if ((e = batch_alloc(b, (void**)&d.cl_sizes, sizeof(int32_t) * (size_t)cl_top[i] * cl_trials[i])) != hipSuccess)
+          return e;
+        if ((e = batch_alloc(b, (void**)&d.cl_sel, (size_t)cl_top[i] * cl_trials[i] * I->np)) != hipSuccess) return e;
+      }
+    }
+  }
   std::vector<uint64_t> m_init, m_fields, m_thr, m_gather, m_mis, m_apply;
   std::vector<std::vector<uint64_t>> m_sweep(Batch::kGroups);
   b.max_ncls = 0;
@@ -1790,9 +1864,9 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     add_blocks(m_sweep[grp], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_chunks(I), true);
     b.max_ncls = std::max(b.max_ncls, I->ncls);
     b.group_ncls[grp] = std::max(b.group_ncls[grp], I->ncls);
-    const int nt = std::min(I->cl_cap_top, I->R);
-    if (nt > 0 && I->cl_cap_trials > 0) {
-      add_blocks(m_mis, i, (int64_t)nt * I->cl_cap_trials, false);
+    const int nt = cl_top[i];
+    if (nt > 0 && cl_trials[i] > 0) {
+      add_blocks(m_mis, i, (int64_t)nt * cl_trials[i], false);
       add_blocks(m_apply, i, (int64_t)nt * kApplyChunks, false);
       b.max_lds = std::max<int64_t>(b.max_lds, (int64_t)I->np * 5);
     }
@@ -1804,7 +1878,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
       if (s.augmented && s.resample && s.n_top > 0 && s.mis_trials > 0) b.any_cluster = 1;
     }
   }
-  hipError_t e = hipMalloc((void**)&b.d_desc, sizeof(Desc) * b.n);
+  hipError_t e = batch_alloc(b, (void**)&b.d_desc, sizeof(Desc) * b.n);
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(b.d_desc, desc.data(), sizeof(Desc) * b.n, hipMemcpyHostToDevice, b.stream);
   if (e != hipSuccess) return e;
@@ -1812,7 +1886,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     if (m.size() > (size_t)INT32_MAX) return hipErrorInvalidValue;
     l.grid = (int32_t)m.size();
     if (m.empty()) return hipSuccess;
-    hipError_t err = hipMalloc((void**)&l.map, sizeof(uint64_t) * m.size());
+    hipError_t err = batch_alloc(b, (void**)&l.map, sizeof(uint64_t) * m.size());
     if (err != hipSuccess) return err;
     return hipMemcpyAsync(l.map, m.data(), sizeof(uint64_t) * m.size(), hipMemcpyHostToDevice, b.stream);
   };
@@ -1866,7 +1940,7 @@ static inline int tgrid(int n) { return (n + 63) / 64; }
 // launch.
 static hipError_t batch_sweeps(Batch& b, int32_t nsweeps, int32_t commit = -1) {
   pamc_instance* P = b.I[0];
-  const bool prof = P->prof;
+  const bool prof = P->prof && !b.arena;
   if (b.thr.grid) k_thresholds<<<b.thr.grid, 256, 0, b.stream>>>(b.d_desc, b.thr.map, commit);
   int64_t launches = 0;
   if (prof) hipEventRecord(next_event(P), b.stream);
@@ -1936,7 +2010,7 @@ hipError_t batch_run_steps(Batch& b, int32_t k) {
   const char* ng = getenv("PAMC_NO_GRAPH");
   const bool no_graph = ng && atoi(ng) != 0;
   const int64_t key = ((int64_t)b.max_sweeps << 1) | (b.any_cluster ? 1 : 0);
-  bool use_graph = !no_graph && !b.I[0]->prof && !b.graph_failed && k > 1;
+  bool use_graph = !no_graph && !b.arena && !b.I[0]->prof && !b.graph_failed && k > 1;
   if (use_graph && (!b.step_graph || b.graph_key != key)) {
     if (b.step_graph) hipGraphExecDestroy(b.step_graph);
     b.step_graph = nullptr;

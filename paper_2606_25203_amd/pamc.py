@@ -31,7 +31,8 @@ EXPORTED = [
     "pamc_sweep", "pamc_resample", "pamc_cluster_move", "pamc_update_best", "pamc_best",
     "pamc_get_state", "pamc_get_trace", "pamc_max3cut_decode", "pamc_pair_distance",
     "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
-    "pamc_anneal_batch", "pamc_server_create", "pamc_server_submit", "pamc_server_tick",
+    "pamc_anneal_batch", "pamc_anneal_batch_noalloc", "pamc_server_create", "pamc_server_submit",
+    "pamc_server_tick",
     "pamc_server_drain", "pamc_server_poll", "pamc_server_latency", "pamc_server_forget",
     "pamc_server_destroy", "pamc_server_get_stats",
 ]
@@ -127,6 +128,7 @@ def _load():
         "pamc_profile_read": [P, P, P, P, P],
         "pamc_synchronize": [P],
         "pamc_anneal_batch": [P, P, C.c_int32, P],
+        "pamc_anneal_batch_noalloc": [P, P, C.c_int32, P],
         "pamc_server_create": [C.c_int64, C.c_int32, C.POINTER(pamc_config), PP],
         "pamc_server_submit": [P, C.c_int32, P, P, P, C.c_int32, C.c_uint64, C.POINTER(pamc_schedule),
                                C.POINTER(C.c_uint64)],
@@ -322,6 +324,19 @@ def pamc_anneal_batch(handles, scheds):
     return list(rs)
 
 
+def pamc_anneal_batch_noalloc(handles, scheds):
+    """pamc_anneal_batch without device allocation (fixed device scratch)."""
+    k = len(handles)
+    if len(scheds) != k:
+        raise ValueError("one schedule per instance")
+    hs = (C.c_void_p * k)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    ss = (pamc_schedule * k)(*scheds)
+    rs = (pamc_result * k)()
+    _check(lib.pamc_anneal_batch_noalloc(C.cast(hs, C.c_void_p), C.cast(ss, C.c_void_p), k,
+                                         C.cast(rs, C.c_void_p)))
+    return list(rs)
+
+
 def pamc_server_create(hbm_budget_bytes, max_slots, *, replicas=64, rule=HEATBATH, device=0, stream=None,
                        flags=0):
     cfg = pamc_config(0, replicas, rule, device, stream, flags)
@@ -478,6 +493,11 @@ class Instance:
 def anneal_batch(instances, scheds):
     """Batched run of several ``Instance`` objects; returns their results."""
     return pamc_anneal_batch([i.h for i in instances], scheds)
+
+
+def anneal_batch_noalloc(instances, scheds):
+    """``anneal_batch`` through the entry point that allocates no device memory."""
+    return pamc_anneal_batch_noalloc([i.h for i in instances], scheds)
 
 
 class Server:
