@@ -226,3 +226,52 @@ def test_step_graph_replays_match_eager(pamc, monkeypatch):
             assert np.array_equal(tg[k], te[k]), f"trace {k}"
         for a, b in zip(sg, se):
             assert np.array_equal(a, b)
+
+
+def test_server_budget_with_large_weights(pamc):
+    """Admission by device footprint with weighted requests: the threshold
+    table has 2X + 1 entries (X = max_v sum_j |w_vj|), so large weights make
+    a request large.  The budget is never exceeded, results equal plain runs,
+    and a request larger than the whole budget is refused at submission."""
+    R = 64
+    sched = pamc.schedule(beta0=1e-6, dbeta=2e-6, steps=12, sweeps=2)
+    reqs = []
+    for i in range(6):
+        g = synth.random_graph(200 + 37 * i, 900, 40 + i)
+        g.w[:] = 0
+        rng = np.random.default_rng(i)
+        # symmetric weights up to 2e5: X of a few 1e6, tables of tens of MB
+        wmap = {}
+        for v in range(g.n):
+            for e in range(g.row_ptr[v], g.row_ptr[v + 1]):
+                a, b = min(v, g.col[e]), max(v, g.col[e])
+                if (a, b) not in wmap:
+                    wmap[(a, b)] = int(rng.integers(1, 200_000))
+                g.w[e] = wmap[(a, b)]
+        reqs.append((g, 500 + i))
+    budget = 100 << 20
+    srv = pamc.Server(budget, 8, replicas=R)
+    say("case server with large weights, budget 100 MiB")
+    tickets = [srv.submit(g, seed, sched) for g, seed in reqs]
+    peak = 0
+    while True:
+        active, queued = srv.tick(3)
+        st = srv.stats()
+        peak = max(peak, st["in_use_bytes"], st["peak_bytes"])
+        assert st["in_use_bytes"] <= budget
+        if active == 0 and queued == 0:
+            break
+    assert peak <= budget
+    for t, (g, seed) in zip(tickets, reqs):
+        res = srv.poll(t)
+        inst = pamc.Instance.csr(g, replicas=R, seed=seed)
+        pr = inst.anneal(sched)
+        same_result(res, pr, f"weighted request {seed}")
+        inst.close()
+    # one request whose table alone exceeds the budget
+    g = synth.random_graph(100, 400, 3)
+    g.w[:] = 300_000_000 // 20
+    with pytest.raises(pamc.PamcError) as ex:
+        srv.submit(g, 1, sched)
+    assert ex.value.status == pamc.PAMC_ERR_OUT_OF_MEMORY
+    srv.close()

@@ -368,3 +368,28 @@ def test_quads_per_wave(pamc, monkeypatch, qpw, fields):
         o.sweep(beta, k)
         same_state(inst, o, f"beta={beta}")
     inst.close()
+
+
+@pytest.mark.parametrize("fields", FIELDS)
+def test_pair_distance_matches_oracle(pamc, fields):
+    """Mean normalised pair distance d_H = min(d, 1 - d) (Supplement, Hamming
+    distance) of the library against the oracle on the same population:
+    after initialisation, sweeps and a resampling (which makes copies, so
+    many pairs are at distance 0).  Both sides sum R(R-1)/2 binary64 terms
+    in different orders: 1e-12 relative."""
+    g = synth.random_graph(301, 2500, 3)
+    R = 192
+    say(f"case pair distance fields={fields}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=8, fields=fields)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 8)
+    assert close_lnq(inst.pair_distance(), o.mean_pair_distance())
+    inst.sweep(0.8, 3)
+    o.sweep(0.8, 3)
+    inst.resample(0.3)
+    o.resample(0.3)
+    inst.sweep(1.2, 2)
+    o.sweep(1.2, 2)
+    same_state(inst, o, "pair distance")
+    a, b = inst.pair_distance(), o.mean_pair_distance()
+    assert close_lnq(a, b), (a, b)
+    inst.close()
