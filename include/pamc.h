@@ -17,7 +17,8 @@
  *    int8 in {-1,+1} (Potts instances: labels 0..K-1); populations are
  *    slot-major [R][n].
  *  - Input arrays are copied; the caller keeps ownership.  The instance owns
- *    its device memory (hipMalloc on cfg->device) until pamc_destroy_instance.
+ *    its device memory (from cfg->alloc, else hipMalloc on cfg->device)
+ *    until pamc_destroy_instance.
  *  - One host thread at a time per instance; distinct instances may be used
  *    concurrently.  Device work is enqueued on the instance's stream
  *    (cfg->stream, or a stream the library creates).  pamc_sweep,
@@ -74,6 +75,18 @@ typedef enum { PAMC_MEM_HOST = 0, PAMC_MEM_DEVICE = 1 } pamc_mem;
 #define PAMC_FLAG_FIELDS_PUSH 2u
 #define PAMC_FLAG_FIELDS_PULL 4u
 
+/* Device memory provider.  alloc returns device memory of at least bytes
+ * bytes for use on stream (NULL on failure, which the library reports as
+ * PAMC_ERR_OUT_OF_MEMORY after returning everything it already holds);
+ * free gives a block back after the library has waited for the stream.
+ * ctx is passed through.  The Python binding can hand torch's caching
+ * allocator here, so that the library's buffers come from torch's pool. */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+} pamc_allocator;
+
 typedef struct {
   uint64_t seed;     /* Philox key */
   int32_t replicas;  /* R, a positive multiple of 64 */
@@ -81,6 +94,10 @@ typedef struct {
   int32_t device;    /* HIP device ordinal */
   void* stream;      /* hipStream_t or NULL (library-owned stream) */
   uint32_t flags;
+  /* NULL: hipMalloc / hipFree.  Otherwise every device buffer the instance
+   * (or server) holds comes from it; the struct is copied, its functions and
+   * ctx must stay valid until the instance (server) is destroyed. */
+  const pamc_allocator* alloc;
 } pamc_config;
 
 /* Sparse instance from a symmetric CSR graph (both directions stored, no
@@ -197,6 +214,13 @@ typedef struct {
   int64_t target;         /* MC* */
   int32_t stop_at_target; /* 1: loop "while M* < MC*" */
   int32_t literal_break;  /* 1: end the run where Algorithm 1 prints "break" */
+  /* 1: continue the run the instance holds (restored by pamc_set_checkpoint,
+   * or left by a pamc_anneal that ended at its step count) instead of
+   * starting Algorithm 1 afresh: the controller, M*, its configuration, the
+   * history, the counts and the steps run are kept, and the run goes on
+   * until the steps run reach steps (or M* reaches the target).  The trace
+   * holds this call's steps at their absolute step indices. */
+  int32_t resume;
 } pamc_schedule;
 
 typedef struct {
@@ -256,6 +280,57 @@ pamc_status pamc_max3cut_decode(pamc_instance* inst, const int8_t* spins, int32_
 /* Mean normalised pairwise Hamming distance d_H = min(d, 1-d) over all
  * replica pairs (Supplement, Hamming distance).  Waits. */
 pamc_status pamc_pair_distance(pamc_instance* inst, double* mean);
+
+/* ---------------------------------------------------------------------------
+ * Checkpoint and resume.  A run of Algorithm 1 is a function of the
+ * population, the controller variables and the stream counters, so a run
+ * stopped after any beta step continues bit for bit from them, on the same
+ * instance or on a new one built from the same graph.
+ * ------------------------------------------------------------------------- */
+
+/* Replaces the population: spins [R][n] in caller ids (labels 0..K-1 for
+ * Potts instances), lineage ids [R] (NULL: 0..R-1) and the stream counters
+ * {sweeps, resamplings, cluster moves} (NULL: unchanged).  Local fields and
+ * energies are recomputed from the spins (Eq. 3 and H = -1/2 sum s h; Eq. 6
+ * for labels).  M*, its configuration and the controller are not changed.
+ * A spin outside {-1, +1} (a label outside 0..K-1): PAMC_ERR_INVALID_ARG,
+ * nothing changed.  Waits. */
+pamc_status pamc_set_state(pamc_instance* inst, const int8_t* spins, const int32_t* family,
+                           const uint32_t* counters);
+
+/* Checkpoint byte format, version 1: little-endian, fields packed in this
+ * order at these offsets.
+ *     0  char[8]  "PAMCCKP1"
+ *     8  uint32   version = 1
+ *    12  uint32   kind: 0 Ising spins on a CSR graph (also Max-3-Cut
+ *                 embeddings), 1 Potts labels, 2 dense couplings
+ *    16  int32    n              20  int32  R
+ *    24  uint64   seed (the Philox key)
+ *    32  uint32   sweeps, resamplings, cluster moves made (stream counters),
+ *                 then a zero word
+ *    48  int64    M*
+ *    56  double   beta           64  double Delta   (controller, Algorithm 1)
+ *    72  int32    z, cycle, cooldown, cluster move armed (0/1), history
+ *                 length, steps run, first step with M* >= target (-1:
+ *                 never), cluster moves, reheats, reversals, restarts, 0
+ *   120  double   sum of ln Q
+ *   128  int64    history[64]: the last (history length) values of M*,
+ *                 oldest first, then zeros
+ *   640  int8     spins [R][n], caller ids (labels for Potts instances)
+ *   640 + R n         int32  lineage [R]
+ *   640 + R n + 4 R   int8   configuration of M* [n], caller ids
+ * Size: 640 + R n + 4 R + n bytes. */
+#define PAMC_CHECKPOINT_HEADER_BYTES 640
+pamc_status pamc_checkpoint_size(const pamc_instance* inst, int64_t* bytes);
+/* Writes the instance's checkpoint into buf (bytes >= the size).  Waits. */
+pamc_status pamc_get_checkpoint(pamc_instance* inst, void* buf, int64_t bytes);
+/* Loads a checkpoint into an instance of the same kind, n and R (its graph
+ * must be the one the checkpoint was taken on): the seed, the population
+ * (fields and energies recomputed), the lineage, M* and its configuration,
+ * the controller and the stream counters.  pamc_anneal with resume = 1 then
+ * continues the run.  A malformed or mismatched buffer:
+ * PAMC_ERR_INVALID_ARG, nothing changed.  Waits. */
+pamc_status pamc_set_checkpoint(pamc_instance* inst, const void* buf, int64_t bytes);
 
 /* Kernel timing: when enabled, the library records HIP events on the
  * instance stream around the sweep kernels: for sparse couplings one pair

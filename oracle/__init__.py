@@ -42,7 +42,7 @@ class Schedule(C.Structure):
                 ("max_distinct_short", C.c_int32), ("max_distinct_long", C.c_int32),
                 ("reheat", C.c_double), ("tau", C.c_int32), ("n_top", C.c_int32),
                 ("mis_trials", C.c_int32), ("target", C.c_int64),
-                ("stop_at_target", C.c_int32), ("literal_break", C.c_int32)]
+                ("stop_at_target", C.c_int32), ("literal_break", C.c_int32), ("resume", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -132,6 +132,11 @@ def lib():
         L.orc_set_population.restype = C.c_int32
         L.orc_set_counters.argtypes = [P, np.ctypeslib.ndpointer(np.uint32)]
         L.orc_pair_distances.argtypes = [P, np.ctypeslib.ndpointer(np.float64)]
+        L.orc_checkpoint_size.argtypes = [P]
+        L.orc_checkpoint_size.restype = C.c_int64
+        L.orc_get_checkpoint.argtypes = [P, np.ctypeslib.ndpointer(np.uint8)]
+        L.orc_set_checkpoint.argtypes = [P, np.ctypeslib.ndpointer(np.uint8), C.c_int64]
+        L.orc_set_checkpoint.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -178,7 +183,7 @@ def default_schedule(**kw) -> Schedule:
     s = Schedule(beta0=0.1, dbeta=0.02, steps=10, sweeps=1, z_rst=0, augmented=0, resample=1,
                  win_short=25, win_long=40, max_distinct_short=3, max_distinct_long=5,
                  reheat=0.8, tau=25, n_top=1, mis_trials=4, target=2**62,
-                 stop_at_target=0, literal_break=0)
+                 stop_at_target=0, literal_break=0, resume=0)
     for k, v in kw.items():
         setattr(s, k, v)
     return s
@@ -345,6 +350,16 @@ class Oracle:
         f = None if family is None else np.ascontiguousarray(family, np.int32)
         if lib().orc_set_population(self._h, s, None if f is None else f.ctypes.data) != 0:
             raise ValueError("spin or label out of range")
+
+    def checkpoint(self) -> bytes:
+        buf = np.zeros(lib().orc_checkpoint_size(self._h), np.uint8)
+        lib().orc_get_checkpoint(self._h, buf)
+        return buf.tobytes()
+
+    def restore(self, blob: bytes):
+        buf = np.frombuffer(blob, np.uint8).copy()
+        if lib().orc_set_checkpoint(self._h, buf, buf.size) != 0:
+            raise ValueError("not a checkpoint of this instance")
 
     def set_counters(self, gs, g_rs, g_cl):
         lib().orc_set_counters(self._h, np.array([gs, g_rs, g_cl], np.uint32))

@@ -149,6 +149,10 @@ struct orc {
   /* Potts labels (potts_K > 0): s holds labels 0..K-1, h is unused */
   int32_t potts_K, potts_rule;
   double potts_gamma;
+  /* Algorithm 1's controller and the run's counts, kept between calls so
+   * that a run can be resumed */
+  orc_ctrl ctrl;
+  orc_result run;
 };
 
 static void set_err(char* err, int32_t errlen, const char* msg) {
@@ -944,49 +948,142 @@ int32_t orc_controller_step(orc_ctrl* c, const orc_schedule* s, int64_t mstar) {
 /* independent chains (SA).                                                  */
 /* ------------------------------------------------------------------------ */
 void orc_anneal(orc* o, const orc_schedule* s, orc_result* res, orc_trace* tr) {
-  orc_ctrl c;
-  memset(&c, 0, sizeof c);
-  c.z = 1;
-  c.beta = s->beta0;
-  c.delta = s->dbeta;
-  memset(res, 0, sizeof *res);
-  res->step_reached = -1;
+  orc_ctrl* c = &o->ctrl;
+  orc_result* run = &o->run;
+  if (!s->resume) { /* a fresh run: Algorithm 1's initial controller */
+    memset(c, 0, sizeof *c);
+    c->z = 1;
+    c->beta = s->beta0;
+    c->delta = s->dbeta;
+    memset(run, 0, sizeof *run);
+    run->step_reached = -1;
+  }
+  c->stop = 0;
   int32_t step;
-  for (step = 0; step < s->steps; ++step) {
+  for (step = run->steps_run; step < s->steps; ++step) {
     if (s->stop_at_target && o->mstar >= s->target) break;
     int32_t ev = 0;
     double lnq = 0.0;
-    if (c.z > 1 && s->resample) {
-      lnq = orc_resample(o, c.delta, NULL);
-      res->sum_lnq += lnq;
+    if (c->z > 1 && s->resample) {
+      lnq = orc_resample(o, c->delta, NULL);
+      run->sum_lnq += lnq;
       ev |= 1;
-      if (s->augmented && c.enable && c.cooldown == 0 && !o->potts_K) {
+      if (s->augmented && c->enable && c->cooldown == 0 && !o->potts_K) {
         orc_cluster(o, s->n_top, s->mis_trials, NULL);
-        c.enable = 0;
-        c.cooldown = s->tau;
+        c->enable = 0;
+        c->cooldown = s->tau;
         ev |= 2;
-        res->n_cluster_moves++;
+        run->n_cluster_moves++;
       }
     }
-    double beta_used = c.beta;
-    orc_sweep(o, c.beta, s->sweeps);
+    double beta_used = c->beta;
+    orc_sweep(o, c->beta, s->sweeps);
     int64_t m = orc_update_best(o);
-    if (res->step_reached < 0 && m >= s->target) res->step_reached = step;
-    ev |= orc_controller_step(&c, s, m);
-    if (ev & 4) res->n_reheats++;
-    if (ev & 8) res->n_reversals++;
-    if (ev & 16) res->n_restarts++;
+    if (run->step_reached < 0 && m >= s->target) run->step_reached = step;
+    ev |= orc_controller_step(c, s, m);
+    if (ev & 4) run->n_reheats++;
+    if (ev & 8) run->n_reversals++;
+    if (ev & 16) run->n_restarts++;
     if (tr) {
       if (tr->mstar) tr->mstar[step] = m;
       if (tr->beta) tr->beta[step] = beta_used;
       if (tr->lnq) tr->lnq[step] = lnq;
       if (tr->events) tr->events[step] = ev;
     }
-    if (c.stop) { ++step; break; }
+    if (c->stop) { ++step; break; }
   }
-  res->steps_run = step;
-  res->best_cut = o->mstar;
-  res->best_energy = o->W - 2 * o->mstar;
+  run->steps_run = step;
+  run->best_cut = o->mstar;
+  run->best_energy = o->W - 2 * o->mstar;
+  *res = *run;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Checkpoints (the library's byte layout, version 1; see the header).      */
+/* ------------------------------------------------------------------------ */
+static int32_t ckp_kind(const orc* o) { return o->dense ? 2 : (o->potts_K ? 1 : 0); }
+
+int64_t orc_checkpoint_size(const orc* o) {
+  return 640 + (int64_t)o->R * o->n + 4 * (int64_t)o->R + o->n;
+}
+
+static void wr(uint8_t* b, size_t at, const void* v, size_t len) { memcpy(b + at, v, len); }
+static void rd(const uint8_t* b, size_t at, void* v, size_t len) { memcpy(v, b + at, len); }
+
+void orc_get_checkpoint(const orc* o, uint8_t* b) {
+  int32_t n = o->n, R = o->R;
+  memset(b, 0, 640);
+  memcpy(b, "PAMCCKP1", 8);
+  uint32_t u32[4] = {1u, (uint32_t)ckp_kind(o), 0u, 0u};
+  wr(b, 8, u32, 8);
+  wr(b, 16, &n, 4);
+  wr(b, 20, &R, 4);
+  wr(b, 24, &o->seed, 8);
+  uint32_t ctr[4] = {o->gs, o->g_rs, o->g_cl, 0u};
+  wr(b, 32, ctr, 16);
+  wr(b, 48, &o->mstar, 8);
+  wr(b, 56, &o->ctrl.beta, 8);
+  wr(b, 64, &o->ctrl.delta, 8);
+  int32_t f[12] = {o->ctrl.z, o->ctrl.cycle, o->ctrl.cooldown, o->ctrl.enable ? 1 : 0, o->ctrl.hist_len,
+                   o->run.steps_run, o->run.step_reached, o->run.n_cluster_moves, o->run.n_reheats,
+                   o->run.n_reversals, o->run.n_restarts, 0};
+  wr(b, 72, f, sizeof f);
+  wr(b, 120, &o->run.sum_lnq, 8);
+  for (int32_t i = 0; i < o->ctrl.hist_len && i < 64; ++i) wr(b, 128 + 8 * (size_t)i, &o->ctrl.hist[i], 8);
+  size_t at = 640;
+  for (int32_t r = 0; r < R; ++r)
+    for (int32_t v = 0; v < n; ++v) b[at + (size_t)r * n + v] = (uint8_t)o->s[(size_t)r * n + o->to_internal[v]];
+  at += (size_t)R * n;
+  wr(b, at, o->family, 4 * (size_t)R);
+  at += 4 * (size_t)R;
+  for (int32_t v = 0; v < n; ++v) b[at + v] = (uint8_t)o->best[o->to_internal[v]];
+}
+
+int32_t orc_set_checkpoint(orc* o, const uint8_t* b, int64_t bytes) {
+  int32_t n = o->n, R = o->R;
+  if (bytes < orc_checkpoint_size(o) || memcmp(b, "PAMCCKP1", 8) != 0) return -1;
+  uint32_t ver, kind;
+  int32_t cn, cR;
+  rd(b, 8, &ver, 4);
+  rd(b, 12, &kind, 4);
+  rd(b, 16, &cn, 4);
+  rd(b, 20, &cR, 4);
+  if (ver != 1u || kind != (uint32_t)ckp_kind(o) || cn != n || cR != R) return -1;
+  int32_t f[12];
+  rd(b, 72, f, sizeof f);
+  if (f[4] < 0 || f[4] > 64) return -1;
+  const int8_t* spins = (const int8_t*)b + 640;
+  int32_t* fam = (int32_t*)malloc(sizeof(int32_t) * (size_t)R);
+  rd(b, 640 + (size_t)R * n, fam, 4 * (size_t)R);
+  if (orc_set_population(o, spins, fam) != 0) { free(fam); return -1; }
+  free(fam);
+  const int8_t* best = spins + (size_t)R * n + 4 * (size_t)R;
+  for (int32_t v = 0; v < n; ++v) o->best[o->to_internal[v]] = best[v];
+  rd(b, 24, &o->seed, 8);
+  uint32_t ctr[3];
+  rd(b, 32, ctr, 12);
+  o->gs = ctr[0];
+  o->g_rs = ctr[1];
+  o->g_cl = ctr[2];
+  rd(b, 48, &o->mstar, 8);
+  memset(&o->ctrl, 0, sizeof o->ctrl);
+  rd(b, 56, &o->ctrl.beta, 8);
+  rd(b, 64, &o->ctrl.delta, 8);
+  o->ctrl.z = f[0];
+  o->ctrl.cycle = f[1];
+  o->ctrl.cooldown = f[2];
+  o->ctrl.enable = f[3];
+  o->ctrl.hist_len = f[4];
+  for (int32_t i = 0; i < f[4]; ++i) rd(b, 128 + 8 * (size_t)i, &o->ctrl.hist[i], 8);
+  memset(&o->run, 0, sizeof o->run);
+  o->run.steps_run = f[5];
+  o->run.step_reached = f[6];
+  o->run.n_cluster_moves = f[7];
+  o->run.n_reheats = f[8];
+  o->run.n_reversals = f[9];
+  o->run.n_restarts = f[10];
+  rd(b, 120, &o->run.sum_lnq, 8);
+  return 0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -59,6 +59,8 @@ typedef struct {
   int64_t target;         /* target cut MC* */
   int32_t stop_at_target; /* 1: loop "while M* < MC*" */
   int32_t literal_break;  /* 1: end the run where Algorithm 1 prints "break" */
+  int32_t resume;         /* 1: continue the run the instance holds (controller,
+                             M*, history, counts and steps run kept) */
 } orc_schedule;
 
 typedef struct {
@@ -166,6 +168,17 @@ double orc_mean_pair_distance(const orc* o);
  * for labels).  Returns 0, or -1 (nothing changed) for a value outside the
  * spin or label range. */
 int32_t orc_set_population(orc* o, const int8_t* spins, const int32_t* family);
+
+/* Checkpoints in the library's documented byte layout (version 1): header
+ * of 640 bytes (magic "PAMCCKP1", version, kind, n, R, seed, the three stream
+ * counters, M*, beta, Delta, twelve int32 controller and count fields, the
+ * sum of ln Q, history[64]), then spins [R][n] in input ids, lineage [R]
+ * (int32) and the configuration of M* [n].  orc_set_checkpoint returns 0, or
+ * -1 (nothing changed) for a buffer that is not a checkpoint of an instance
+ * of this kind, n and R. */
+int64_t orc_checkpoint_size(const orc* o);
+void orc_get_checkpoint(const orc* o, uint8_t* buf);
+int32_t orc_set_checkpoint(orc* o, const uint8_t* buf, int64_t bytes);
 
 /* Sets the stream counters (sweeps, resamplings, cluster moves). */
 void orc_set_counters(orc* o, const uint32_t* c3);

@@ -46,11 +46,33 @@ pamc_status dev_fail(hipError_t e, const char* where) {
     if (_e != hipSuccess) return dev_fail(_e, where); \
   } while (0)
 
+// Device memory of an instance: from its allocator when it has one, else
+// hipMalloc.
+hipError_t dev_alloc(pamc_instance* I, void** p, size_t bytes) {
+  if (I->use_al) {
+    *p = I->al.alloc(I->al.ctx, bytes, (void*)I->stream);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+void dev_free(pamc_instance* I, void* p) {
+  if (!p) return;
+  if (I->use_al)
+    I->al.free(I->al.ctx, p, (void*)I->stream);
+  else
+    hipFree(p);
+}
+
 template <typename T>
 hipError_t dalloc(pamc_instance* I, T** p, size_t count) {
   const size_t bytes = std::max<size_t>(sizeof(T) * count, 16);
-  hipError_t e = hipMalloc((void**)p, bytes);
-  if (e == hipSuccess) I->device_bytes += (int64_t)bytes;
+  void* q = nullptr;
+  hipError_t e = dev_alloc(I, &q, bytes);
+  if (e == hipSuccess) {
+    *p = (T*)q;
+    I->device_bytes += (int64_t)bytes;
+  }
   return e;
 }
 
@@ -59,7 +81,7 @@ hipError_t dalloc(pamc_instance* I, T** p, size_t count) {
 template <typename T>
 void dfree(pamc_instance* I, T*& p, size_t count) {
   if (!p) return;
-  hipFree(p);
+  dev_free(I, p);
   I->device_bytes -= (int64_t)std::max<size_t>(sizeof(T) * count, 16);
   p = nullptr;
 }
@@ -70,7 +92,7 @@ void free_instance(pamc_instance* I) {
   if (I->stream) hipStreamSynchronize(I->stream);
   delete I->self;
   I->self = nullptr;
-  if (I->d_sched) hipFree(I->d_sched);
+  dev_free(I, I->d_sched);
   void* ptrs[] = {I->g.row_ptr, I->g.col, I->g.J, I->g.grow, I->g.gcol, I->g.gJ, I->g.class_ptr, I->pop.S[0], I->pop.S[1],
                   I->pop.H[0], I->pop.H[1], I->pop.E[0], I->pop.E[1], I->pop.fam[0],
                   I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order,
@@ -78,8 +100,7 @@ void free_instance(pamc_instance* I) {
                   I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
                   I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Cd, I->Ed[0], I->Ed[1],
                   I->flip_ctr, I->H_scratch, I->ptab};
-  for (void* p : ptrs)
-    if (p) hipFree(p);
+  for (void* p : ptrs) dev_free(I, p);
   if (I->pinned) hipHostFree(I->pinned);
   for (hipEvent_t e : I->ev_pool) hipEventDestroy(e);
   if (I->own_stream && I->stream) hipStreamDestroy(I->stream);
@@ -133,6 +154,11 @@ pamc_status open_device(pamc_instance* I, const pamc_config* cfg) {
   HIP_TRY(hipGetDeviceCount(&count), "hipGetDeviceCount");
   if (cfg->device < 0 || cfg->device >= count) return fail(PAMC_ERR_INVALID_ARG, "bad device");
   I->device = cfg->device;
+  if (cfg->alloc) {
+    if (!cfg->alloc->alloc || !cfg->alloc->free) return fail(PAMC_ERR_INVALID_ARG, "allocator without functions");
+    I->al = *cfg->alloc;
+    I->use_al = true;
+  }
   HIP_TRY(hipSetDevice(I->device), "hipSetDevice");
   if (cfg->stream) {
     I->stream = (hipStream_t)cfg->stream;
@@ -156,7 +182,10 @@ pamc_status open_device(pamc_instance* I, const pamc_config* cfg) {
 // keys its descriptor names.
 pamc::Batch* self_batch(pamc_instance* I, hipError_t* err) {
   *err = hipSuccess;
-  if (!I->self) I->self = new (std::nothrow) pamc::Batch();
+  if (!I->self) {
+    I->self = new (std::nothrow) pamc::Batch();
+    if (I->self && I->use_al) I->self->al = &I->al;
+  }
   if (!I->self) {
     *err = hipErrorOutOfMemory;
     return nullptr;
@@ -421,9 +450,15 @@ Schedule to_sched(const pamc_schedule* s) {
   d.mis_trials = s->mis_trials;
   d.stop_at_target = s->stop_at_target;
   d.literal_break = s->literal_break;
+  d.resume = s->resume ? 1 : 0;
+  d.pad = 0;
   return d;
 }
 
+// The ensure_* helpers grow per-run buffers.  The old buffers go first (the
+// stream is drained), and a size is recorded only once all of its buffers
+// exist: after a failed allocation the instance holds none of that kind and
+// a size of 0, so no kernel is ever handed a missing buffer.
 pamc_status ensure_cluster_scratch(pamc_instance* I, int32_t n_top, int32_t trials) {
   n_top = std::min(n_top, I->R);
   if (n_top <= 0 || trials <= 0) return PAMC_OK;
@@ -432,15 +467,23 @@ pamc_status ensure_cluster_scratch(pamc_instance* I, int32_t n_top, int32_t tria
   if (trials > 64) return fail(PAMC_ERR_UNSUPPORTED, "mis_trials > 64");
   if (n_top <= I->cl_cap_top && trials <= I->cl_cap_trials) return PAMC_OK;
   HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  const int32_t top = std::max(n_top, I->cl_cap_top), tr = std::max(trials, I->cl_cap_trials);
   dfree(I, I->cl_targets, I->cl_cap_top);
   dfree(I, I->cl_sel, (size_t)I->cl_cap_top * I->cl_cap_trials * I->np);
   dfree(I, I->cl_sizes, (size_t)I->cl_cap_top * I->cl_cap_trials);
-  I->cl_cap_top = std::max(n_top, I->cl_cap_top);
-  I->cl_cap_trials = std::max(trials, I->cl_cap_trials);
-  HIP_TRY(dalloc(I, &I->cl_targets, I->cl_cap_top), "alloc cluster");
-  HIP_TRY(dalloc(I, &I->cl_sel, (size_t)I->cl_cap_top * I->cl_cap_trials * I->np), "alloc cluster");
-  HIP_TRY(dalloc(I, &I->cl_sizes, (size_t)I->cl_cap_top * I->cl_cap_trials), "alloc cluster");
+  I->cl_cap_top = I->cl_cap_trials = 0;
   I->self_dirty = true;
+  hipError_t e = dalloc(I, &I->cl_targets, top);
+  if (e == hipSuccess) e = dalloc(I, &I->cl_sel, (size_t)top * tr * I->np);
+  if (e == hipSuccess) e = dalloc(I, &I->cl_sizes, (size_t)top * tr);
+  if (e != hipSuccess) {
+    dfree(I, I->cl_targets, top);
+    dfree(I, I->cl_sel, (size_t)top * tr * I->np);
+    dfree(I, I->cl_sizes, (size_t)top * tr);
+    return dev_fail(e, "alloc cluster");
+  }
+  I->cl_cap_top = top;
+  I->cl_cap_trials = tr;
   return PAMC_OK;
 }
 
@@ -452,22 +495,33 @@ pamc_status ensure_trace(pamc_instance* I, int32_t steps) {
   dfree(I, I->tr_lnq, I->tr_cap);
   dfree(I, I->tr_events, I->tr_cap);
   dfree(I, I->tr_time, I->tr_cap);
-  I->tr_cap = steps;
-  HIP_TRY(dalloc(I, &I->tr_mstar, steps), "alloc trace");
-  HIP_TRY(dalloc(I, &I->tr_beta, steps), "alloc trace");
-  HIP_TRY(dalloc(I, &I->tr_lnq, steps), "alloc trace");
-  HIP_TRY(dalloc(I, &I->tr_events, steps), "alloc trace");
-  HIP_TRY(dalloc(I, &I->tr_time, steps), "alloc trace");
+  I->tr_cap = 0;
   I->self_dirty = true;
+  hipError_t e = dalloc(I, &I->tr_mstar, steps);
+  if (e == hipSuccess) e = dalloc(I, &I->tr_beta, steps);
+  if (e == hipSuccess) e = dalloc(I, &I->tr_lnq, steps);
+  if (e == hipSuccess) e = dalloc(I, &I->tr_events, steps);
+  if (e == hipSuccess) e = dalloc(I, &I->tr_time, steps);
+  if (e != hipSuccess) {
+    dfree(I, I->tr_mstar, steps);
+    dfree(I, I->tr_beta, steps);
+    dfree(I, I->tr_lnq, steps);
+    dfree(I, I->tr_events, steps);
+    dfree(I, I->tr_time, steps);
+    return dev_fail(e, "alloc trace");
+  }
+  I->tr_cap = steps;
   return PAMC_OK;
 }
 
 pamc_status ensure_order(pamc_instance* I, int32_t sweeps) {
   if (sweeps <= I->order_cap) return PAMC_OK;
   HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  int32_t* fresh = nullptr;
+  HIP_TRY(dalloc(I, &fresh, (size_t)sweeps * I->ncls), "alloc order");  // the old orders stay on failure
   dfree(I, I->order, (size_t)I->order_cap * I->ncls);
+  I->order = fresh;
   I->order_cap = sweeps;
-  HIP_TRY(dalloc(I, &I->order, (size_t)sweeps * I->ncls), "alloc order");
   I->self_dirty = true;
   return PAMC_OK;
 }
@@ -1005,7 +1059,7 @@ pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_resul
   SELF_BATCH(I, b);
   b->max_sweeps = std::max(s.sweeps, 1);
   b->any_cluster = cluster_possible(s);
-  if (!I->d_sched) HIP_TRY(hipMalloc(&I->d_sched, sizeof(Schedule)), "alloc");
+  if (!I->d_sched) HIP_TRY(dev_alloc(I, &I->d_sched, sizeof(Schedule)), "alloc");
   HIP_TRY(hipMemcpyAsync(I->d_sched, &s, sizeof(Schedule), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::batch_anneal_setup(*b, (const Schedule*)I->d_sched, nullptr, 1), "anneal setup");
   // steps in chunks of 16 between polls of the stop flag when stopping at
@@ -1060,11 +1114,12 @@ pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* 
   // every instance's queued work is finished before the batch takes over
   for (pamc_instance* I : v) HIP_TRY(hipStreamSynchronize(I->stream), "sync");
   pamc::Batch b;
+  if (v[0]->use_al) b.al = &v[0]->al;  // the batch's memory from the first instance's provider
   HIP_TRY(pamc::batch_build(b, v, &s), "batch descriptors");
   Schedule* d_sched = nullptr;
   int32_t* d_status = nullptr;
-  hipError_t e = hipMalloc((void**)&d_sched, sizeof(Schedule) * count);
-  if (e == hipSuccess) e = hipMalloc((void**)&d_status, sizeof(int32_t) * count);
+  hipError_t e = pamc::batch_alloc(b, (void**)&d_sched, sizeof(Schedule) * count);
+  if (e == hipSuccess) e = pamc::batch_alloc(b, (void**)&d_status, sizeof(int32_t) * count);
   if (e == hipSuccess) e = hipMemcpyAsync(d_sched, s.data(), sizeof(Schedule) * count, hipMemcpyHostToDevice, b.stream);
   if (e == hipSuccess) e = pamc::batch_anneal_setup(b, d_sched, nullptr, count);
   std::vector<int32_t> status(count);
@@ -1081,8 +1136,13 @@ pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* 
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
-  if (d_sched) hipFree(d_sched);
-  if (d_status) hipFree(d_status);
+  for (void* p : {(void*)d_sched, (void*)d_status}) {
+    if (!p) continue;
+    if (b.al)
+      b.al->free(b.al->ctx, p, (void*)b.stream);
+    else
+      hipFree(p);
+  }
   if (e != hipSuccess) return dev_fail(e, "batched run");
   for (int32_t i = 0; i < count; ++i) {
     pamc::RunState r;
@@ -1197,7 +1257,7 @@ pamc_status pamc_max3cut_decode(pamc_instance* I, const int8_t* spins, int32_t* 
   if (spins) {
     std::vector<int8_t> internal(I->np, 1);
     for (int32_t v = 0; v < I->n; ++v) internal[I->to_internal[v]] = spins[v];
-    HIP_TRY(hipMalloc((void**)&tmp, I->np), "alloc");
+    HIP_TRY(dev_alloc(I, (void**)&tmp, I->np), "alloc");
     HIP_TRY(hipMemcpyAsync(tmp, internal.data(), I->np, hipMemcpyHostToDevice, I->stream), "upload");
     src = tmp;
   }
@@ -1205,7 +1265,7 @@ pamc_status pamc_max3cut_decode(pamc_instance* I, const int8_t* spins, int32_t* 
   if (e == hipSuccess) e = hipStreamSynchronize(I->stream);
   if (e == hipSuccess && labels) e = hipMemcpy(labels, I->m3_labels, sizeof(int32_t) * I->m3_n, hipMemcpyDeviceToHost);
   if (e == hipSuccess && cut3) e = hipMemcpy(cut3, I->m3_cut, sizeof(int64_t), hipMemcpyDeviceToHost);
-  if (tmp) hipFree(tmp);
+  dev_free(I, tmp);
   if (e != hipSuccess) return dev_fail(e, "max3cut decode");
   return PAMC_OK;
 }
@@ -1222,6 +1282,190 @@ pamc_status pamc_pair_distance(pamc_instance* I, double* mean) {
   HIP_TRY(hipMemcpy(&v, d, sizeof(double), hipMemcpyDeviceToHost), "readback");
   *mean = I->R > 1 ? v / ((double)I->R * (I->R - 1) / 2.0) : 0.0;
   return PAMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Population from the host (spins [R][n] in caller ids, lineage [R]) into
+// buffer 0, fields and energies recomputed on the device; waits.
+pamc_status load_population(pamc_instance* I, const int8_t* spins, const int32_t* family) {
+  const int32_t n = I->n, R = I->R;
+  for (size_t k = 0; k < (size_t)R * n; ++k) {
+    const int8_t x = spins[k];
+    if (I->potts_K ? (x < 0 || x >= I->potts_K) : (x != 1 && x != -1))
+      return fail(PAMC_ERR_INVALID_ARG, I->potts_K ? "label out of range" : "spins must be -1 or +1");
+  }
+  std::vector<int32_t> fam(R);
+  for (int32_t r = 0; r < R; ++r) fam[r] = family ? family[r] : r;
+  HIP_TRY(hipStreamSynchronize(I->stream), "sync");
+  if (I->dense) {
+    const size_t np = (size_t)I->dn_pad;
+    std::vector<int8_t> S((size_t)R * np, 0);
+    for (int32_t r = 0; r < R; ++r) memcpy(&S[(size_t)r * np], spins + (size_t)r * n, n);
+    HIP_TRY(hipMemcpy(I->Sd, S.data(), S.size(), hipMemcpyHostToDevice), "upload");
+    HIP_TRY(hipMemcpy(I->pop.fam[0], fam.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice), "upload");
+    HIP_TRY(pamc::launch_dense_load(I), "energies");
+  } else {
+    std::vector<uint32_t> S((size_t)I->T * I->nq * 64, 0u);
+    for (int32_t r = 0; r < R; ++r)
+      for (int32_t v = 0; v < n; ++v) {
+        const int32_t iv = I->to_internal[v];
+        uint32_t& w = S[((size_t)(r >> 6) * I->nq + (iv >> 2)) * 64 + (r & 63)];
+        w |= (uint32_t)(uint8_t)spins[(size_t)r * n + v] << (8 * (iv & 3));
+      }
+    HIP_TRY(hipMemcpy(I->pop.S[0], S.data(), S.size() * 4, hipMemcpyHostToDevice), "upload");
+    HIP_TRY(hipMemcpy(I->pop.fam[0], fam.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice), "upload");
+    SELF_BATCH(I, b);
+    HIP_TRY(pamc::launch_load_population(*b), "fields and energies");
+  }
+  HIP_TRY(hipStreamSynchronize(I->stream), "fields and energies");
+  return PAMC_OK;
+}
+
+pamc_status write_state(pamc_instance* I, const pamc::RunState& r) {
+  HIP_TRY(hipMemcpy(I->st, &r, sizeof(pamc::RunState), hipMemcpyHostToDevice), "upload");
+  return PAMC_OK;
+}
+
+int64_t checkpoint_bytes(const pamc_instance* I) {
+  return PAMC_CHECKPOINT_HEADER_BYTES + (int64_t)I->R * I->n + 4 * (int64_t)I->R + I->n;
+}
+
+uint32_t checkpoint_kind(const pamc_instance* I) { return I->dense ? 2u : (I->potts_K ? 1u : 0u); }
+
+template <typename T>
+void put(uint8_t* buf, size_t off, T v) {
+  memcpy(buf + off, &v, sizeof(T));
+}
+template <typename T>
+T get(const uint8_t* buf, size_t off) {
+  T v;
+  memcpy(&v, buf + off, sizeof(T));
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+pamc_status pamc_set_state(pamc_instance* I, const int8_t* spins, const int32_t* family, const uint32_t* counters) {
+  if (!I || !spins) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  hipSetDevice(I->device);
+  pamc_status st = load_population(I, spins, family);
+  if (st) return st;
+  pamc::RunState r;
+  st = read_state(I, &r);
+  if (st) return st;
+  if (counters) {
+    r.gs = counters[0];
+    r.g_rs = counters[1];
+    r.g_cl = counters[2];
+  }
+  r.cur = 0;
+  return write_state(I, r);
+}
+
+pamc_status pamc_checkpoint_size(const pamc_instance* I, int64_t* bytes) {
+  if (!I || !bytes) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  *bytes = checkpoint_bytes(I);
+  return PAMC_OK;
+}
+
+pamc_status pamc_get_checkpoint(pamc_instance* I, void* buf, int64_t bytes) {
+  if (!I || !buf) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  const int64_t need = checkpoint_bytes(I);
+  if (bytes < need) return fail(PAMC_ERR_INVALID_ARG, "checkpoint buffer too small");
+  hipSetDevice(I->device);
+  pamc::RunState r;
+  pamc_status st = read_state(I, &r);
+  if (st) return st;
+  const int32_t n = I->n, R = I->R;
+  uint8_t* b = (uint8_t*)buf;
+  memset(b, 0, PAMC_CHECKPOINT_HEADER_BYTES);
+  memcpy(b, "PAMCCKP1", 8);
+  put<uint32_t>(b, 8, 1u);
+  put<uint32_t>(b, 12, checkpoint_kind(I));
+  put<int32_t>(b, 16, n);
+  put<int32_t>(b, 20, R);
+  put<uint64_t>(b, 24, I->seed);
+  put<uint32_t>(b, 32, r.gs);
+  put<uint32_t>(b, 36, r.g_rs);
+  put<uint32_t>(b, 40, r.g_cl);
+  put<int64_t>(b, 48, r.mstar);
+  put<double>(b, 56, r.beta);
+  put<double>(b, 64, r.delta);
+  const int32_t ints[12] = {r.z, r.cycle, r.cooldown, r.enable ? 1 : 0, r.hist_len, r.steps_run, r.step_reached,
+                            r.n_cluster_moves, r.n_reheats, r.n_reversals, r.n_restarts, 0};
+  memcpy(b + 72, ints, sizeof ints);
+  put<double>(b, 120, r.sum_lnq);
+  for (int i = 0; i < pamc::kHistCap; ++i) put<int64_t>(b, 128 + 8 * (size_t)i, i < r.hist_len ? r.hist[i] : 0);
+  std::vector<int32_t> fam(R);
+  st = pamc_get_state(I, (int8_t*)b + PAMC_CHECKPOINT_HEADER_BYTES, nullptr, nullptr, fam.data());
+  if (st) return st;
+  memcpy(b + PAMC_CHECKPOINT_HEADER_BYTES + (size_t)R * n, fam.data(), 4 * (size_t)R);
+  return pamc_best(I, nullptr, nullptr, (int8_t*)b + PAMC_CHECKPOINT_HEADER_BYTES + (size_t)R * n + 4 * (size_t)R);
+}
+
+pamc_status pamc_set_checkpoint(pamc_instance* I, const void* buf, int64_t bytes) {
+  if (!I || !buf) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  const uint8_t* b = (const uint8_t*)buf;
+  if (bytes < PAMC_CHECKPOINT_HEADER_BYTES || memcmp(b, "PAMCCKP1", 8) != 0 || get<uint32_t>(b, 8) != 1u)
+    return fail(PAMC_ERR_INVALID_ARG, "not a version 1 checkpoint");
+  if (get<uint32_t>(b, 12) != checkpoint_kind(I) || get<int32_t>(b, 16) != I->n || get<int32_t>(b, 20) != I->R)
+    return fail(PAMC_ERR_INVALID_ARG, "checkpoint of another kind of instance, n or R");
+  if (bytes < checkpoint_bytes(I)) return fail(PAMC_ERR_INVALID_ARG, "checkpoint truncated");
+  int32_t ints[12];
+  memcpy(ints, b + 72, sizeof ints);
+  if (ints[4] < 0 || ints[4] > pamc::kHistCap || ints[0] < 1 || ints[5] < 0)
+    return fail(PAMC_ERR_INVALID_ARG, "checkpoint controller out of range");
+  const int32_t n = I->n, R = I->R;
+  const int8_t* spins = (const int8_t*)b + PAMC_CHECKPOINT_HEADER_BYTES;
+  std::vector<int32_t> fam(R);
+  memcpy(fam.data(), b + PAMC_CHECKPOINT_HEADER_BYTES + (size_t)R * n, 4 * (size_t)R);
+  const int8_t* best = spins + (size_t)R * n + 4 * (size_t)R;
+  for (int32_t v = 0; v < n; ++v)
+    if (I->potts_K ? (best[v] < 0 || best[v] >= I->potts_K) : (best[v] != 1 && best[v] != -1))
+      return fail(PAMC_ERR_INVALID_ARG, "checkpoint configuration out of range");
+  hipSetDevice(I->device);
+  const uint64_t seed = get<uint64_t>(b, 24);
+  if (seed != I->seed) {
+    I->seed = seed;
+    I->self_dirty = true;  // the descriptor carries the key
+  }
+  pamc_status st = load_population(I, spins, fam.data());
+  if (st) return st;
+  std::vector<int8_t> bi(I->np, I->potts_K ? 0 : 1);
+  for (int32_t v = 0; v < n; ++v) bi[I->dense ? v : I->to_internal[v]] = best[v];
+  HIP_TRY(hipMemcpy(I->best, bi.data(), I->np, hipMemcpyHostToDevice), "upload");
+  pamc::RunState r;
+  st = read_state(I, &r);
+  if (st) return st;
+  r.gs = get<uint32_t>(b, 32);
+  r.g_rs = get<uint32_t>(b, 36);
+  r.g_cl = get<uint32_t>(b, 40);
+  r.mstar = get<int64_t>(b, 48);
+  r.beta = get<double>(b, 56);
+  r.delta = get<double>(b, 64);
+  r.z = ints[0];
+  r.cycle = ints[1];
+  r.cooldown = ints[2];
+  r.enable = ints[3] ? 1 : 0;
+  r.hist_len = ints[4];
+  r.steps_run = ints[5];
+  r.step_reached = ints[6];
+  r.n_cluster_moves = ints[7];
+  r.n_reheats = ints[8];
+  r.n_reversals = ints[9];
+  r.n_restarts = ints[10];
+  r.sum_lnq = get<double>(b, 120);
+  for (int i = 0; i < pamc::kHistCap; ++i) r.hist[i] = get<int64_t>(b, 128 + 8 * (size_t)i);
+  r.cur = 0;
+  r.stopped = 0;
+  r.active = 0;
+  I->trace_ok = false;
+  return write_state(I, r);
 }
 
 pamc_status pamc_profile_enable(pamc_instance* I, int32_t on) {
@@ -1370,6 +1614,20 @@ struct pamc_server {
   int32_t* d_status = nullptr;
   int32_t cap = 0;
   pamc_server_stats stats{};
+  pamc_allocator al{};  // the caller's provider (copied), if any
+  bool use_al = false;
+  void* dmalloc(size_t bytes) {
+    if (use_al) return al.alloc(al.ctx, bytes, (void*)stream);
+    void* p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+  }
+  void dmfree(void* p) {
+    if (!p) return;
+    if (use_al)
+      al.free(al.ctx, p, (void*)stream);
+    else
+      hipFree(p);
+  }
   std::unique_ptr<ServerWorkers> workers;  // declared last: joined first
 };
 
@@ -1565,6 +1823,16 @@ pamc_status pamc_server_create(int64_t hbm_budget_bytes, int32_t max_slots, cons
   S->budget = hbm_budget_bytes;
   S->max_slots = max_slots;
   S->cfg = *cfg;
+  if (cfg->alloc) {
+    if (!cfg->alloc->alloc || !cfg->alloc->free) {
+      delete S;
+      return fail(PAMC_ERR_INVALID_ARG, "allocator without functions");
+    }
+    S->al = *cfg->alloc;
+    S->use_al = true;
+    S->cfg.alloc = &S->al;  // requests copy it from here
+    S->batch.al = &S->al;
+  }
   int nthreads = 8;
   if (const char* e = getenv("PAMC_SERVER_THREADS")) nthreads = std::max(1, std::min(64, atoi(e)));
   S->workers.reset(new ServerWorkers());
@@ -1637,15 +1905,18 @@ pamc_status pamc_server_tick(pamc_server* S, int32_t max_steps, int32_t* n_activ
       HIP_TRY(pamc::batch_build(S->batch, v, &sc), "batch descriptors");
       S->dirty = false;
       if (na > S->cap) {
-        if (S->d_sched) hipFree(S->d_sched);
-        if (S->d_idx) hipFree(S->d_idx);
-        if (S->d_status) hipFree(S->d_status);
+        const int32_t cap = std::max(na, 2 * S->cap);
+        S->dmfree(S->d_sched);
+        S->dmfree(S->d_idx);
+        S->dmfree(S->d_status);
         S->d_sched = nullptr;
         S->d_idx = S->d_status = nullptr;
-        S->cap = std::max(na, 2 * S->cap);
-        HIP_TRY(hipMalloc((void**)&S->d_sched, sizeof(Schedule) * S->cap), "alloc");
-        HIP_TRY(hipMalloc((void**)&S->d_idx, sizeof(int32_t) * S->cap), "alloc");
-        HIP_TRY(hipMalloc((void**)&S->d_status, sizeof(int32_t) * S->cap), "alloc");
+        S->cap = 0;
+        S->d_sched = (Schedule*)S->dmalloc(sizeof(Schedule) * cap);
+        S->d_idx = (int32_t*)S->dmalloc(sizeof(int32_t) * cap);
+        S->d_status = (int32_t*)S->dmalloc(sizeof(int32_t) * cap);
+        if (!S->d_sched || !S->d_idx || !S->d_status) return fail(PAMC_ERR_OUT_OF_MEMORY, "server buffers");
+        S->cap = cap;
       }
     }
     // controllers of the newly admitted requests (they sit at the end)
@@ -1741,9 +2012,9 @@ void pamc_server_destroy(pamc_server* S) {
   for (auto& a : S->active) free_instance(a.I);
   S->active.clear();
   S->batch.free_device();
-  if (S->d_sched) hipFree(S->d_sched);
-  if (S->d_idx) hipFree(S->d_idx);
-  if (S->d_status) hipFree(S->d_status);
+  S->dmfree(S->d_sched);
+  S->dmfree(S->d_idx);
+  S->dmfree(S->d_status);
   if (S->own_stream) hipStreamDestroy(S->stream);
   delete S;
 }

@@ -891,6 +891,14 @@ __global__ void k_dense_init_finish(int64_t* E, int32_t R, RunState* st, int8_t*
   }
 }
 
+// Energies of a population the host loaded into buffer 0: E = -E / 2 and
+// buffer 0 becomes the current one.
+__global__ void k_dense_load_finish(int64_t* E, int32_t R, RunState* st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < R) E[i] = -(E[i] / 2);
+  if (i == 0) st->cur = 0;
+}
+
 // Resampling gather for the replica-major layout.
 __global__ void __launch_bounds__(256) k_dense_gather(const RunState* st, int8_t* S0, int8_t* S1,
                                                       int64_t* E0, int64_t* E1, int32_t* F0, int32_t* F1,
@@ -1019,6 +1027,12 @@ hipError_t launch_init_dense(pamc_instance* I) {
   dense_full_energy(I, 0);
   k_dense_init_finish<<<(std::max(I->R, I->dn_pad) + 255) / 256, 256, 0, I->stream>>>(
       I->pop.E[0], I->R, I->st, I->best, I->dn_pad);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_load(pamc_instance* I) {
+  dense_full_energy(I, 0);
+  k_dense_load_finish<<<(I->R + 255) / 256, 256, 0, I->stream>>>(I->pop.E[0], I->R, I->st);
   return hipGetLastError();
 }
 

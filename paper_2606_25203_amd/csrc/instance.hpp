@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/pamc.h"
 #include "pamc_device.hpp"
 
 namespace pamc {
@@ -44,6 +45,8 @@ struct GraphDev {
 }  // namespace pamc
 
 struct pamc_instance {
+  pamc_allocator al{};  // device memory provider (use_al), else hipMalloc
+  bool use_al = false;
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -126,6 +129,7 @@ struct Schedule {
   int32_t steps, sweeps, z_rst, augmented, resample;
   int32_t win_short, win_long, max_ds, max_dl, tau, n_top, mis_trials;
   int32_t stop_at_target, literal_break;
+  int32_t resume, pad;
 };
 
 // Per-instance descriptor read by every batched kernel: the device pointers
@@ -196,6 +200,9 @@ struct Batch {
   // build asked for (set also when it did not fit).
   char* arena = nullptr;
   size_t arena_cap = 0, arena_used = 0, arena_need = 0;
+  // outside arena mode: the provider of the batch's device memory (null:
+  // hipMalloc); it must outlive the batch
+  const pamc_allocator* al = nullptr;
   void free_device();
   Batch() = default;
   Batch(const Batch&) = delete;
@@ -229,6 +236,9 @@ hipError_t prim_resample(Batch& b, double delta);
 hipError_t prim_cluster(Batch& b, int32_t n_top, int32_t trials);
 hipError_t prim_update_best(Batch& b);
 hipError_t launch_fields(Batch& b, int32_t buf, int32_t* H);
+// Fields and energies of population buffer 0 recomputed from its spins
+// (spins uploaded by the host); the current buffer becomes 0.
+hipError_t launch_load_population(Batch& b);
 hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
 hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
 int32_t cluster_max_n();
@@ -252,6 +262,7 @@ int32_t dense_field_buffers();  // super-block field buffers (the next one is fi
 hipError_t launch_dense_fields(pamc_instance* I, int32_t* H_rmajor);
 hipError_t launch_dense_generate(pamc_instance* I, uint64_t graph_seed);
 hipError_t launch_init_dense(pamc_instance* I);
+hipError_t launch_dense_load(pamc_instance* I);  // energies of uploaded spins (buffer 0)
 hipError_t launch_dense_step(Batch& b, int32_t sweeps, int32_t resample);
 hipError_t launch_dense_prim_sweep(Batch& b, double beta, int32_t nsweeps);
 hipError_t launch_dense_prim_resample(Batch& b, double delta);

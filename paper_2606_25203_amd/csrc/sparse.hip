@@ -736,6 +736,15 @@ __global__ void __launch_bounds__(256) k_init_finish(const Desc* __restrict__ D)
   }
 }
 
+// Population loaded by the host into buffer 0: E holds sum_v s_v h_v (Potts
+// labels: 2 sum_{i<j} J (2 delta - 1)); H = -that / 2, and buffer 0 becomes
+// the current one.  One work-group per instance.
+__global__ void __launch_bounds__(256) k_load_finish(const Desc* __restrict__ D) {
+  const Desc& d = D[blockIdx.x];
+  for (int i = threadIdx.x; i < d.R; i += blockDim.x) d.E0[i] = -(d.E0[i] / 2);
+  if (threadIdx.x == 0) d.st->cur = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Controller kernels (one thread per instance): Algorithm 1's decisions.
 // ---------------------------------------------------------------------------
@@ -763,6 +772,14 @@ __global__ void k_anneal_setup(const Desc* __restrict__ D, const Schedule* __res
   st->mis_trials = s.mis_trials;
   st->stop_at_target = s.stop_at_target;
   st->literal_break = s.literal_break;
+  st->stopped = 0;
+  st->active = 0;
+  st->t_start = wall_clock64();
+  st->t_last = st->t_start;
+  if (s.resume) {  // the run goes on from the controller it holds
+    st->t_reached = st->step_reached >= 0 ? st->t_start : 0;
+    return;
+  }
   st->z = 1;
   st->cycle = 0;
   st->beta = s.beta0;
@@ -770,16 +787,12 @@ __global__ void k_anneal_setup(const Desc* __restrict__ D, const Schedule* __res
   st->enable = 0;
   st->cooldown = 0;
   st->hist_len = 0;
-  st->stopped = 0;
-  st->active = 0;
   st->step_reached = -1;
   st->steps_run = 0;
   st->sum_lnq = 0.0;
   st->last_lnq = 0.0;
   st->n_cluster_moves = st->n_reheats = st->n_reversals = st->n_restarts = 0;
-  st->t_start = wall_clock64();
   st->t_reached = 0;
-  st->t_last = st->t_start;
 }
 
 // Decisions of a run's beta step (Algorithm 1), by one thread per instance.
@@ -1721,16 +1734,23 @@ int Batch::group_of(const pamc_instance* I) {
 
 void Batch::free_device() {
   const bool own = arena == nullptr;  // arena pieces are not the batch's to free
-  if (d_desc && own) hipFree(d_desc);
+  auto release = [&](void* p) {
+    if (!p || !own) return;
+    if (al)
+      al->free(al->ctx, p, (void*)stream);
+    else
+      hipFree(p);
+  };
+  release(d_desc);
   d_desc = nullptr;
   Launch* all[] = {&init_spins, &init_fields, &thr, &thr_dense, &gather, &cl_mis, &cl_apply};
   for (Launch* l : all) {
-    if (l->map && own) hipFree(l->map);
+    release(l->map);
     l->map = nullptr;
     l->grid = 0;
   }
   for (Launch& l : sweep) {
-    if (l.map && own) hipFree(l.map);
+    release(l.map);
     l.map = nullptr;
     l.grid = 0;
   }
@@ -1741,6 +1761,10 @@ void Batch::free_device() {
 }
 
 hipError_t batch_alloc(Batch& b, void** p, size_t bytes) {
+  if (!b.arena && b.al) {
+    *p = b.al->alloc(b.al->ctx, bytes, (void*)b.stream);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
   if (!b.arena) return hipMalloc(p, bytes);
   const size_t at = (b.arena_used + 255) & ~(size_t)255;
   b.arena_need = at + bytes;
@@ -2086,6 +2110,14 @@ hipError_t launch_fields(Batch& b, int32_t buf, int32_t* H) {
   return hipGetLastError();
 }
 
+hipError_t launch_load_population(Batch& b) {
+  for (pamc_instance* I : b.I) hipMemsetAsync(I->pop.E[0], 0, sizeof(int64_t) * I->R, b.stream);
+  if (b.init_fields.grid)
+    k_init_fields<<<b.init_fields.grid, 256, 0, b.stream>>>(b.d_desc, b.init_fields.map, 0, nullptr, 1);
+  k_load_finish<<<b.n, 256, 0, b.stream>>>(b.d_desc);
+  return hipGetLastError();
+}
+
 hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev) {
   hipMemsetAsync(I->m3_cut, 0, sizeof(int64_t), I->stream);
   const int grid = (I->m3_n + 255) / 256;
@@ -2123,7 +2155,7 @@ hipError_t ctl_thresholds(Batch& b) {
     std::vector<uint64_t> m;
     for (int i = 0; i < b.n; ++i) add_blocks(m, i, kThrBlocks, false);
     b.thr_dense.grid = (int32_t)m.size();
-    hipError_t e = hipMalloc((void**)&b.thr_dense.map, sizeof(uint64_t) * m.size());
+    hipError_t e = batch_alloc(b, (void**)&b.thr_dense.map, sizeof(uint64_t) * m.size());
     if (e != hipSuccess) return e;
     e = hipMemcpy(b.thr_dense.map, m.data(), sizeof(uint64_t) * m.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;

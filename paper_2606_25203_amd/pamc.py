@@ -31,6 +31,7 @@ EXPORTED = [
     "pamc_sweep", "pamc_resample", "pamc_cluster_move", "pamc_update_best", "pamc_best",
     "pamc_get_state", "pamc_get_trace", "pamc_max3cut_decode", "pamc_pair_distance",
     "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
+    "pamc_set_state", "pamc_checkpoint_size", "pamc_get_checkpoint", "pamc_set_checkpoint",
     "pamc_anneal_batch", "pamc_anneal_batch_noalloc", "pamc_server_create", "pamc_server_submit",
     "pamc_server_tick",
     "pamc_server_drain", "pamc_server_poll", "pamc_server_latency", "pamc_server_forget",
@@ -44,9 +45,54 @@ class PamcError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class pamc_allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
 class pamc_config(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("replicas", C.c_int32), ("rule", C.c_int32),
-                ("device", C.c_int32), ("stream", C.c_void_p), ("flags", C.c_uint32)]
+                ("device", C.c_int32), ("stream", C.c_void_p), ("flags", C.c_uint32),
+                ("alloc", C.c_void_p)]
+
+
+class Allocator:
+    """A pamc_allocator made of two Python callables: alloc(nbytes, stream)
+    returning a device pointer as an int (0 or an exception: failure) and
+    free(ptr, stream).  It must outlive every instance or server made with
+    it (the Instance and Server wrappers keep a reference)."""
+
+    def __init__(self, alloc, free):
+        def _alloc(ctx, nbytes, stream):
+            try:
+                return alloc(int(nbytes), int(stream or 0)) or None
+            except Exception:
+                return None
+
+        def _free(ctx, ptr, stream):
+            free(int(ptr), int(stream or 0))
+
+        self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+        self.struct = pamc_allocator(None, self._cb[0], self._cb[1])
+
+    @property
+    def ptr(self):
+        return C.cast(C.pointer(self.struct), C.c_void_p)
+
+
+def torch_allocator(device=0):
+    """Device memory from torch's caching allocator, on the stream the
+    library names for each block."""
+    import torch
+    return Allocator(lambda n, s: torch.cuda.caching_allocator_alloc(n, device, s),
+                     lambda p, s: torch.cuda.caching_allocator_delete(p))
+
+
+def _alloc_ptr(allocator):
+    return allocator.ptr if allocator is not None else None
 
 
 class pamc_info(C.Structure):
@@ -63,7 +109,7 @@ class pamc_schedule(C.Structure):
                 ("max_distinct_short", C.c_int32), ("max_distinct_long", C.c_int32),
                 ("reheat", C.c_double), ("tau", C.c_int32), ("n_top", C.c_int32),
                 ("mis_trials", C.c_int32), ("target", C.c_int64), ("stop_at_target", C.c_int32),
-                ("literal_break", C.c_int32)]
+                ("literal_break", C.c_int32), ("resume", C.c_int32)]
 
 
 class pamc_result(C.Structure):
@@ -91,13 +137,20 @@ def schedule(**kw) -> pamc_schedule:
     s = pamc_schedule(beta0=0.1, dbeta=0.02, steps=10, sweeps=1, z_rst=0, augmented=0, resample=1,
                       win_short=25, win_long=40, max_distinct_short=3, max_distinct_long=5,
                       reheat=0.8, tau=25, n_top=1, mis_trials=4, target=2**62, stop_at_target=0,
-                      literal_break=0)
+                      literal_break=0, resume=0)
     for k, v in kw.items():
         setattr(s, k, v)
     return s
 
 
 def _load():
+    # torch first, when it is installed: it ships its own HIP runtime, and
+    # loaded first that runtime also serves this library, so the process has
+    # one runtime and torch's memory and streams are usable by the library
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
     L = C.CDLL(LIB_PATH)
@@ -127,6 +180,10 @@ def _load():
         "pamc_profile_enable": [P, C.c_int32],
         "pamc_profile_read": [P, P, P, P, P],
         "pamc_synchronize": [P],
+        "pamc_set_state": [P, P, P, P],
+        "pamc_checkpoint_size": [P, C.POINTER(C.c_int64)],
+        "pamc_get_checkpoint": [P, P, C.c_int64],
+        "pamc_set_checkpoint": [P, P, C.c_int64],
         "pamc_anneal_batch": [P, P, C.c_int32, P],
         "pamc_anneal_batch_noalloc": [P, P, C.c_int32, P],
         "pamc_server_create": [C.c_int64, C.c_int32, C.POINTER(pamc_config), PP],
@@ -164,11 +221,11 @@ def _ptr(a):
 
 # ---------------------------------------------------------------- C names
 def pamc_create_instance_csr(n, row_ptr, col, w, objective=MAXCUT, *, seed=0, replicas=64,
-                             rule=HEATBATH, device=0, stream=None, flags=0):
+                             rule=HEATBATH, device=0, stream=None, flags=0, allocator=None):
     rp = np.ascontiguousarray(row_ptr, np.int32)
     cl = np.ascontiguousarray(col, np.int32)
     ww = np.ascontiguousarray(w, np.int32)
-    cfg = pamc_config(seed, replicas, rule, device, stream, flags)
+    cfg = pamc_config(seed, replicas, rule, device, stream, flags, _alloc_ptr(allocator))
     h = C.c_void_p()
     _check(lib.pamc_create_instance_csr(int(n), _ptr(rp), _ptr(cl), _ptr(ww), MEM_HOST, objective,
                                         C.byref(cfg), C.byref(h)))
@@ -176,9 +233,9 @@ def pamc_create_instance_csr(n, row_ptr, col, w, objective=MAXCUT, *, seed=0, re
 
 
 def pamc_create_instance_dense_i8(J, objective=ISING, *, seed=0, replicas=64, rule=HEATBATH,
-                                  device=0, stream=None, flags=0):
+                                  device=0, stream=None, flags=0, allocator=None):
     J = np.ascontiguousarray(J, np.int8)
-    cfg = pamc_config(seed, replicas, rule, device, stream, flags)
+    cfg = pamc_config(seed, replicas, rule, device, stream, flags, _alloc_ptr(allocator))
     h = C.c_void_p()
     _check(lib.pamc_create_instance_dense_i8(int(J.shape[0]), _ptr(J), int(J.shape[1]), MEM_HOST,
                                              objective, C.byref(cfg), C.byref(h)))
@@ -186,19 +243,19 @@ def pamc_create_instance_dense_i8(J, objective=ISING, *, seed=0, replicas=64, ru
 
 
 def pamc_create_instance_dense_random(n, graph_seed, *, seed=0, replicas=64, rule=HEATBATH,
-                                      device=0, stream=None, flags=0):
-    cfg = pamc_config(seed, replicas, rule, device, stream, flags)
+                                      device=0, stream=None, flags=0, allocator=None):
+    cfg = pamc_config(seed, replicas, rule, device, stream, flags, _alloc_ptr(allocator))
     h = C.c_void_p()
     _check(lib.pamc_create_instance_dense_random(int(n), int(graph_seed), C.byref(cfg), C.byref(h)))
     return h
 
 
 def pamc_create_instance_potts(n, row_ptr, col, w, K, potts_rule=POTTS_SOFTMAX, gamma=1.0, *, seed=0,
-                               replicas=64, device=0, stream=None, flags=0):
+                               replicas=64, device=0, stream=None, flags=0, allocator=None):
     rp = np.ascontiguousarray(row_ptr, np.int32)
     cl = np.ascontiguousarray(col, np.int32)
     ww = np.ascontiguousarray(w, np.int32)
-    cfg = pamc_config(seed, replicas, HEATBATH, device, stream, flags)
+    cfg = pamc_config(seed, replicas, HEATBATH, device, stream, flags, _alloc_ptr(allocator))
     h = C.c_void_p()
     _check(lib.pamc_create_instance_potts(int(n), _ptr(rp), _ptr(cl), _ptr(ww), int(K), int(potts_rule),
                                           float(gamma), C.byref(cfg), C.byref(h)))
@@ -206,11 +263,11 @@ def pamc_create_instance_potts(n, row_ptr, col, w, K, potts_rule=POTTS_SOFTMAX, 
 
 
 def pamc_create_instance_max3cut(n, row_ptr, col, w, *, seed=0, replicas=64, rule=HEATBATH,
-                                 device=0, stream=None, flags=0):
+                                 device=0, stream=None, flags=0, allocator=None):
     rp = np.ascontiguousarray(row_ptr, np.int32)
     cl = np.ascontiguousarray(col, np.int32)
     ww = np.ascontiguousarray(w, np.int32)
-    cfg = pamc_config(seed, replicas, rule, device, stream, flags)
+    cfg = pamc_config(seed, replicas, rule, device, stream, flags, _alloc_ptr(allocator))
     h = C.c_void_p()
     _check(lib.pamc_create_instance_max3cut(int(n), _ptr(rp), _ptr(cl), _ptr(ww), C.byref(cfg), C.byref(h)))
     return h
@@ -312,6 +369,26 @@ def pamc_synchronize(h):
     _check(lib.pamc_synchronize(h))
 
 
+def pamc_set_state(h, spins, family=None, counters=None):
+    sp = np.ascontiguousarray(spins, np.int8)
+    fa = None if family is None else np.ascontiguousarray(family, np.int32)
+    co = None if counters is None else np.ascontiguousarray(counters, np.uint32)
+    _check(lib.pamc_set_state(h, _ptr(sp), _ptr(fa), _ptr(co)))
+
+
+def pamc_get_checkpoint(h) -> bytes:
+    size = C.c_int64()
+    _check(lib.pamc_checkpoint_size(h, C.byref(size)))
+    buf = np.zeros(size.value, np.uint8)
+    _check(lib.pamc_get_checkpoint(h, _ptr(buf), size.value))
+    return buf.tobytes()
+
+
+def pamc_set_checkpoint(h, blob: bytes):
+    buf = np.frombuffer(blob, np.uint8).copy()
+    _check(lib.pamc_set_checkpoint(h, _ptr(buf), buf.size))
+
+
 def pamc_anneal_batch(handles, scheds):
     """One batched run over several instances (one schedule each)."""
     k = len(handles)
@@ -338,8 +415,8 @@ def pamc_anneal_batch_noalloc(handles, scheds):
 
 
 def pamc_server_create(hbm_budget_bytes, max_slots, *, replicas=64, rule=HEATBATH, device=0, stream=None,
-                       flags=0):
-    cfg = pamc_config(0, replicas, rule, device, stream, flags)
+                       flags=0, allocator=None):
+    cfg = pamc_config(0, replicas, rule, device, stream, flags, _alloc_ptr(allocator))
     h = C.c_void_p()
     _check(lib.pamc_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(cfg), C.byref(h)))
     return h
@@ -399,19 +476,21 @@ def pamc_server_destroy(srv):
 class Instance:
     """Owns one ``pamc_instance*``; methods forward to the C functions."""
 
-    def __init__(self, handle, n, replicas, m3_n=0):
+    def __init__(self, handle, n, replicas, m3_n=0, allocator=None):
         self.h = handle
         self.n = int(n)
         self.R = int(replicas)
         self.m3_n = m3_n
+        self.allocator = allocator  # kept alive while the instance exists
 
     @classmethod
-    def csr(cls, g, *, replicas, seed, rule=HEATBATH, objective=MAXCUT, shuffle=True, stream=None, fields=None):
+    def csr(cls, g, *, replicas, seed, rule=HEATBATH, objective=MAXCUT, shuffle=True, stream=None, fields=None,
+            allocator=None):
         flags = 0 if shuffle else FLAG_FIXED_CLASS_ORDER
         flags |= {None: 0, "push": FLAG_FIELDS_PUSH, "pull": FLAG_FIELDS_PULL}[fields]
         h = pamc_create_instance_csr(g.n, g.row_ptr, g.col, g.w, objective, seed=seed, replicas=replicas,
-                                     rule=rule, stream=stream, flags=flags)
-        return cls(h, g.n, replicas)
+                                     rule=rule, stream=stream, flags=flags, allocator=allocator)
+        return cls(h, g.n, replicas, allocator=allocator)
 
     @classmethod
     def max3cut(cls, g, *, replicas, seed, rule=HEATBATH, shuffle=True, stream=None, fields=None):
@@ -434,10 +513,10 @@ class Instance:
         return cls(h, J.shape[0], replicas)
 
     @classmethod
-    def dense_random(cls, n, graph_seed, *, replicas, seed, rule=HEATBATH, stream=None):
+    def dense_random(cls, n, graph_seed, *, replicas, seed, rule=HEATBATH, stream=None, allocator=None):
         h = pamc_create_instance_dense_random(n, graph_seed, seed=seed, replicas=replicas, rule=rule,
-                                              stream=stream)
-        return cls(h, n, replicas)
+                                              stream=stream, allocator=allocator)
+        return cls(h, n, replicas, allocator=allocator)
 
     def close(self):
         if self.h:
@@ -486,6 +565,15 @@ class Instance:
     def pair_distance(self):
         return pamc_pair_distance(self.h)
 
+    def set_state(self, spins, family=None, counters=None):
+        pamc_set_state(self.h, spins, family, counters)
+
+    def checkpoint(self) -> bytes:
+        return pamc_get_checkpoint(self.h)
+
+    def restore(self, blob: bytes):
+        pamc_set_checkpoint(self.h, blob)
+
     def synchronize(self):
         pamc_synchronize(self.h)
 
@@ -504,10 +592,11 @@ class Server:
     """Owns one ``pamc_server*`` (continuous batching of annealing requests)."""
 
     def __init__(self, hbm_budget_bytes, max_slots, *, replicas, rule=HEATBATH, device=0, stream=None,
-                 fields=None):
+                 fields=None, allocator=None):
         flags = {None: 0, "push": FLAG_FIELDS_PUSH, "pull": FLAG_FIELDS_PULL}[fields]
+        self.allocator = allocator
         self.h = pamc_server_create(hbm_budget_bytes, max_slots, replicas=replicas, rule=rule, device=device,
-                                    stream=stream, flags=flags)
+                                    stream=stream, flags=flags, allocator=allocator)
         self.sizes = {}
 
     def submit(self, g, seed, sched, objective=MAXCUT):
