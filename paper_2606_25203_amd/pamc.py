@@ -147,10 +147,13 @@ def _load():
     # torch first, when it is installed: it ships its own HIP runtime, and
     # loaded first that runtime also serves this library, so the process has
     # one runtime and torch's memory and streams are usable by the library
-    try:
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    # (PAMC_NO_TORCH=1 skips this: the library then uses the HIP runtime it
+    # was built against, for tools that must not load a second one)
+    if os.environ.get("PAMC_NO_TORCH", "0") != "1":
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
     L = C.CDLL(LIB_PATH)
