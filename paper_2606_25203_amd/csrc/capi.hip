@@ -99,7 +99,7 @@ void free_instance(pamc_instance* I) {
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
                   I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
                   I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Cd, I->Ed[0], I->Ed[1],
-                  I->flip_ctr, I->H_scratch, I->ptab};
+                  I->flip_ctr, I->H_scratch, I->ptab, I->g.hubJ, I->pop.HF[0], I->pop.HF[1]};
   for (void* p : ptrs) dev_free(I, p);
   if (I->pinned) hipHostFree(I->pinned);
   for (hipEvent_t e : I->ev_pool) hipEventDestroy(e);
@@ -211,9 +211,42 @@ struct HostSparse {
   int32_t potts_K = 0;  // set by the caller for Potts labels (no fields, plain CSR only)
   int32_t n = 0, np = 0, nq = 0, ncls = 0, max_class_quads = 0;
   int32_t small_j = 0, jmode = 0, pull = 0, tpw = 1, qpw = 1;
+  int32_t nhub = 0, hub_v[pamc::kMaxHubs] = {-1, -1};  // internal ids of the hubs (pull mode)
   int64_t nnz = 0, W = 0, X = 0;
-  std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, grow, gcol, gJ;
+  std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, grow, gcol, gJ, hubJ;
 };
+
+// Field storage of a sparse graph: gathered at visit time (pull) or kept
+// incrementally (push); both give the same integer fields and trajectory.
+// Gathering a vertex's field costs its degree at every visit; keeping it
+// costs one device-scope atomic per neighbour of every flip.  Pull is the
+// default when every row is short: at most 16 entries per vertex on average
+// and 64 at most.  With PAMC_FLAG_FIELDS_PULL, up to kMaxHubs hub rows
+// (more than 64 entries) are allowed too: their fields are kept (the
+// updates of a work-group summed in LDS before one atomic per replica),
+// since gathering a hub serialises one wavefront per tile over all of its
+// neighbours.  On the Max-3-Cut embedding of G(7000, 21000) that mode takes
+// about 25 us per class phase at any temperature, incremental fields 17 us
+// at a flip rate of 0.16% but 170 us at 10%; the benchmark's runs average
+// 1%, where incremental fields are faster, so graphs with hubs default to
+// them.  Returns pull; hubs receives the hubs' caller ids.
+bool choose_fields(int32_t n, const int32_t* rp, uint32_t flags, bool potts, std::vector<int32_t>* hubs) {
+  hubs->clear();
+  if (potts) return true;  // Potts labels: K-label fields gathered at visit time
+  if (flags & PAMC_FLAG_FIELDS_PUSH) return false;
+  int64_t hub_entries = 0;
+  std::vector<int32_t> h;
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] - rp[v] > 64) {
+      h.push_back(v);
+      hub_entries += rp[v + 1] - rp[v];
+    }
+  if (flags & PAMC_FLAG_FIELDS_PULL) {
+    if ((int)h.size() <= pamc::kMaxHubs) *hubs = h;  // more hubs than that: gathered like any row
+    return true;
+  }
+  return h.empty() && (int64_t)rp[n] <= 16 * (int64_t)n;
+}
 
 pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const int32_t* col,
                            const std::vector<int32_t>& Jin, uint32_t flags, int32_t T) {
@@ -289,18 +322,17 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
     const int m = atoi(e);
     if (m == 0 || (m == 1 && h.small_j) || (m == 2 && h.jmode == 2)) h.jmode = m;
   }
-  // Field storage: kept incrementally (push) or gathered at visit time
-  // (pull); both give the same integer fields and the same trajectory.
-  // Gathering a hub's field serialises one wavefront per tile over all of
-  // its neighbours; incremental fields spread that work over the flips.
-  if (h.potts_K)
-    h.pull = 1;  // Potts labels: K-label fields gathered at visit time
-  else if (flags & PAMC_FLAG_FIELDS_PUSH)
-    h.pull = 0;
-  else if (flags & PAMC_FLAG_FIELDS_PULL)
-    h.pull = 1;
-  else
-    h.pull = (h.nnz <= 16 * (int64_t)n && maxdeg <= 64) ? 1 : 0;
+  std::vector<int32_t> hubs;
+  h.pull = choose_fields(n, rp, flags, h.potts_K != 0, &hubs) ? 1 : 0;
+  h.nhub = h.pull ? (int32_t)hubs.size() : 0;
+  for (int32_t k = 0; k < h.nhub; ++k) h.hub_v[k] = h.to_internal[hubs[k]];
+  if (h.nhub) {  // couplings of every vertex to each hub
+    h.hubJ.assign((size_t)h.np * pamc::kMaxHubs, 0);
+    for (int32_t iv = 0; iv < n; ++iv)
+      for (int32_t e = h.rp2[iv]; e < h.rp2[iv + 1]; ++e)
+        for (int32_t k = 0; k < h.nhub; ++k)
+          if (h.col2[e] == h.hub_v[k]) h.hubJ[(size_t)iv * pamc::kMaxHubs + k] = h.J2[e];
+  }
   // Gathered-field CSR: rows padded to multiples of 4 entries; columns as
   // byte offsets of the neighbour's spin word in a tile (plus its byte index
   // in modes 0 and 1), couplings in the kernel's mode (mode 2: the int8
@@ -308,11 +340,15 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   // Potts labels are read with a byte index: coupling mode 0 or 1 layout
   if (h.potts_K && h.jmode == 2) h.jmode = h.small_j ? 1 : 0;
   if (h.pull) {
+    // a hub's row is not gathered (its field is kept), so it stays empty here
+    auto is_hub = [&](int32_t iv) { return h.nhub && (iv == h.hub_v[0] || iv == h.hub_v[1]); };
     h.grow.assign(n + 1, 0);
-    for (int32_t iv = 0; iv < n; ++iv) h.grow[iv + 1] = h.grow[iv] + ((h.rp2[iv + 1] - h.rp2[iv] + 3) & ~3);
+    for (int32_t iv = 0; iv < n; ++iv)
+      h.grow[iv + 1] = h.grow[iv] + (is_hub(iv) ? 0 : ((h.rp2[iv + 1] - h.rp2[iv] + 3) & ~3));
     h.gcol.assign(std::max(h.grow[n], 4), 0);
     h.gJ.assign(std::max(h.grow[n], 4), 0);
     for (int32_t iv = 0; iv < n; ++iv) {
+      if (is_hub(iv)) continue;
       int32_t p = h.grow[iv];
       for (int32_t e = h.rp2[iv]; e < h.rp2[iv + 1]; ++e, ++p) {
         h.gcol[p] = (h.col2[e] >> 2) * 256 + (h.jmode == 2 ? 0 : (h.col2[e] & 3));
@@ -333,13 +369,15 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
         h.tpw = t;
         break;
       }
+  if (h.nhub)  // the measured best shape of the kept-hub mode on the Max-3-Cut embedding: 4 x 1
+    h.tpw = (T % 4 == 0) ? 4 : ((T % 2 == 0) ? 2 : 1);
   if (const char* e = getenv("PAMC_TPW")) {
     const int t = atoi(e);
     if ((t == 1 || t == 2 || t == 4) && T % t == 0 && !h.potts_K) h.tpw = t;
   }
   h.qpw = 1;
   for (int q : {4, 2})
-    if ((T / h.tpw) * ((h.max_class_quads + W4 * q - 1) / (W4 * q)) >= 4096) {
+    if (!h.nhub && (T / h.tpw) * ((h.max_class_quads + W4 * q - 1) / (W4 * q)) >= 4096) {
       h.qpw = q;
       break;
     }
@@ -363,6 +401,8 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   I->small_j = h.small_j;
   I->jmode = h.jmode;
   I->pull = h.pull;
+  I->nhub = h.nhub;
+  for (int k = 0; k < pamc::kMaxHubs; ++k) I->hub_v[k] = h.hub_v[k];
   I->tpw = h.tpw;
   I->qpw = h.qpw;
   I->max_class_quads = h.max_class_quads;
@@ -381,9 +421,11 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
     HIP_TRY(dalloc(I, &I->g.gJ, h.gJ.size()), "alloc");
   }
   HIP_TRY(dalloc(I, &I->g.class_ptr, ncls + 1), "alloc");
+  if (I->nhub) HIP_TRY(dalloc(I, &I->g.hubJ, h.hubJ.size()), "alloc");
   for (int b = 0; b < 2; ++b) {
     HIP_TRY(dalloc(I, &I->pop.S[b], words), "alloc population");
     if (!I->pull) HIP_TRY(dalloc(I, &I->pop.H[b], hs), "alloc population");
+    if (I->nhub) HIP_TRY(dalloc(I, &I->pop.HF[b], (size_t)pamc::kMaxHubs * I->R), "alloc population");
     HIP_TRY(dalloc(I, &I->pop.E[b], I->R), "alloc population");
     HIP_TRY(dalloc(I, &I->pop.fam[b], I->R), "alloc population");
   }
@@ -412,6 +454,8 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
     HIP_TRY(hipMemcpyAsync(I->g.gJ, h.gJ.data(), sizeof(int32_t) * h.gJ.size(), hipMemcpyHostToDevice, I->stream), "upload");
   }
   HIP_TRY(hipMemcpyAsync(I->g.class_ptr, I->class_ptr.data(), sizeof(int32_t) * (ncls + 1), hipMemcpyHostToDevice, I->stream), "upload");
+  if (I->nhub)
+    HIP_TRY(hipMemcpyAsync(I->g.hubJ, h.hubJ.data(), sizeof(int32_t) * h.hubJ.size(), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->to_internal_dev, I->to_internal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::prepare_kernel_lds(), "hipFuncSetAttribute");
   SELF_BATCH(I, b);
@@ -1656,12 +1700,12 @@ int64_t estimate_bytes(int32_t n, const int32_t* rp, const int32_t* w, const pam
     for (int32_t e = rp[v]; e < rp[v + 1]; ++e) ab += std::llabs((long long)w[e]);
     X = std::max(X, ab);
   }
-  bool pull = nnz <= 16 * (int64_t)n && maxdeg <= 64;
-  if (cfg.flags & PAMC_FLAG_FIELDS_PUSH) pull = false;
-  if (cfg.flags & PAMC_FLAG_FIELDS_PULL) pull = true;
+  std::vector<int32_t> hubs;
+  const bool pull = choose_fields(n, rp, cfg.flags, false, &hubs);
   const int64_t ncls = maxdeg + 1;
   int64_t b = a(4 * (int64_t)(n + 1)) + 2 * a(4 * (nnz + 16));                 // CSR
   if (pull) b += a(4 * (int64_t)(n + 1)) + 2 * a(4 * std::max<int64_t>(gathered, 4));  // gathered CSR
+  if (pull && !hubs.empty()) b += a(4 * np * pamc::kMaxHubs) + 2 * a(4 * pamc::kMaxHubs * R);  // hubs
   b += a(4 * (ncls + 1));                                                      // class_ptr
   b += 2 * (a(R * np) + (pull ? 0 : a(4 * R * np)) + a(8 * R) + a(4 * R));     // two populations
   b += a(np) + a(4 * (int64_t)n) + a((int64_t)sizeof(pamc::RunState));        // best, ids, run state

@@ -24,6 +24,7 @@ struct Batch;
 struct Pop {
   uint32_t* S[2] = {nullptr, nullptr};
   int32_t* H[2] = {nullptr, nullptr};
+  int32_t* HF[2] = {nullptr, nullptr};  // hub fields [kMaxHubs][R] (gathered-field mode with hubs)
   int64_t* E[2] = {nullptr, nullptr};
   int32_t* fam[2] = {nullptr, nullptr};
 };
@@ -40,6 +41,9 @@ struct GraphDev {
   int32_t* gcol = nullptr;
   int32_t* gJ = nullptr;
   int32_t* class_ptr = nullptr;
+  // hubs of the gathered-field mode: J between each vertex and each hub
+  // [np][kMaxHubs] (0 where not adjacent)
+  int32_t* hubJ = nullptr;
 };
 
 }  // namespace pamc
@@ -58,6 +62,8 @@ struct pamc_instance {
   std::vector<int32_t> to_internal, to_input, class_ptr;
   int32_t max_class_quads = 0;
   int32_t pull = 0;       // 1: fields gathered at visit time (no field array)
+  int32_t nhub = 0;       // hubs (pull mode): vertices whose fields are kept incrementally
+  int32_t hub_v[pamc::kMaxHubs] = {-1, -1};  // their internal ids
   int32_t tpw = 1;        // replica tiles per wavefront in the gathered-field sweep
   int32_t qpw = 1;        // vertex quads per wavefront in a sweep work-group (1, 2, 4)
   int32_t small_j = 0;    // 1: every |J| < 2^23 (24-bit multiplies are exact)
@@ -142,6 +148,9 @@ struct Desc {
   const int32_t* gcol;
   const int32_t* gJ;
   const int32_t* class_ptr;
+  const int32_t* hubJ;    // [np][kMaxHubs] couplings to the hubs (gathered-field mode)
+  int32_t *HF0, *HF1;     // hub fields [kMaxHubs][R], one per population buffer
+  int32_t nhub, hub_v0, hub_v1;
   int32_t* order;
   uint32_t* thr;
   uint32_t *S0, *S1;
@@ -174,7 +183,7 @@ struct Desc {
 // A set of instances advanced by the same launches.  Grid kernels read a map
 // of (instance << 32 | local block) words; one map per launch kind.
 struct Batch {
-  static constexpr int kGroups = 22;  // sweep kernel variants (19 spin, 3 Potts label)
+  static constexpr int kGroups = 40;  // sweep kernel variants (37 spin, 3 Potts label)
   static int group_of(const pamc_instance* I);
   struct Launch {
     uint64_t* map = nullptr;

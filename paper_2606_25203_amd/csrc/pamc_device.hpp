@@ -23,6 +23,7 @@ __device__ __forceinline__ PAMC_GLOBAL T* gmem(T* p) {
 }
 
 constexpr int kLanes = 64;      // replicas per tile = wavefront width
+constexpr int kMaxHubs = 2;     // hub vertices with incrementally kept fields in the gathered-field mode
 constexpr int kHistCap = 64;    // controller history capacity (>= win_long)
 
 // ---------------------------------------------------------------------------

@@ -127,6 +127,11 @@ __device__ __forceinline__ void gather_fields(const PAMC_GLOBAL int32_t* __restr
   }
 }
 
+// Hub fields of the current population buffer (null without hubs).
+__device__ __forceinline__ int32_t* st_cur_hub(const Desc& d) {
+  return d.nhub ? (gmem((const RunState*)d.st)->cur ? d.HF1 : d.HF0) : nullptr;
+}
+
 // Work-group totals: energy changes per replica (red[wave * ntiles + t][lane])
 // into E, flip counts per wave (fred, filled by lane 0 of each wave) into
 // the profiling counters.
@@ -163,7 +168,7 @@ __device__ __forceinline__ void reduce_energy_and_flips(int64_t (*red)[kLanes], 
 // work-group stays below 2^31 (|x| <= X < 2^26, at most 4 kMaxQuadsPerWave
 // vertices), so it is summed in 32 bits.
 // ---------------------------------------------------------------------------
-template <int JM, int TPW, bool THR_LDS>
+template <int JM, int TPW, bool THR_LDS, bool HUB>
 __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __restrict__ row_ptr,
                                                 const PAMC_GLOBAL int32_t* __restrict__ col,
                                                 const PAMC_GLOBAL int32_t* __restrict__ Jc,
@@ -191,6 +196,16 @@ __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __res
 #pragma unroll
   for (int t = 0; t < TPW; ++t) dE[t] = 0;
   int32_t nflip = 0;
+  // hubs (rows too long to gather): their fields come from HF, and each
+  // flip's change to them (2 J s_new) is summed per lane in registers, then
+  // over the work-group's waves, before one atomic per lane and hub
+  const int nhub = HUB ? d.nhub : 0;
+  PAMC_GLOBAL int32_t* HF = gmem(HUB ? st_cur_hub(d) : nullptr);
+  int32_t hacc[kMaxHubs][TPW];
+#pragma unroll
+  for (int hk = 0; hk < kMaxHubs; ++hk)
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) hacc[hk][t] = 0;
   for (int i = 0; i < d.qpw; ++i) {
     const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
     if (qi >= nqc) break;
@@ -199,10 +214,18 @@ __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __res
 #pragma unroll
     for (int t = 0; t < TPW; ++t) sw[t] = __builtin_amdgcn_raw_buffer_load_b32(Sr, voff[t], q * (kLanes * 4), 0);
     int32_t h[4][TPW];
+    int32_t hj[4][kMaxHubs];  // couplings of the quad's vertices to the hubs (uniform)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int v = 4 * q + k;
-      if (v >= v0 && v < v1) {
+      const bool in = v >= v0 && v < v1;
+#pragma unroll
+      for (int hk = 0; hk < kMaxHubs; ++hk) hj[k][hk] = (HUB && in) ? gmem(d.hubJ)[v * kMaxHubs + hk] : 0;
+      if (HUB && in && (v == d.hub_v0 || v == d.hub_v1)) {
+        const int hk = v == d.hub_v0 ? 0 : 1;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) h[k][t] = HF[hk * d.R + (tile0 + t) * kLanes + lane];
+      } else if (in) {
         gather_fields<JM, TPW>(col, Jc, row_ptr[v], row_ptr[v + 1], Sr, voff, h[k]);
       } else {
 #pragma unroll
@@ -227,6 +250,10 @@ __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __res
         dE[t] += flip ? (acc_t)x : (acc_t)0;
         flipmask |= flip ? (0xFEu << (8 * k)) : 0u;  // +1 (0x01) <-> -1 (0xFF)
         nflip += __popcll(__ballot(flip));
+        if constexpr (HUB) {
+#pragma unroll
+          for (int hk = 0; hk < kMaxHubs; ++hk) hacc[hk][t] += flip ? -2 * s * hj[k][hk] : 0;
+        }
       }
       if (flipmask) __builtin_amdgcn_raw_buffer_store_b32(swt ^ flipmask, Sr, voff[t], q * (kLanes * 4), 0);
     }
@@ -235,16 +262,39 @@ __device__ __forceinline__ void sweep_pull_body(const PAMC_GLOBAL int32_t* __res
   for (int t = 0; t < TPW; ++t) red[wave * TPW + t][lane] = 2 * (int64_t)dE[t];
   if (lane == 0) fred[wave] = nflip;
   reduce_energy_and_flips(red, fred, wave, lane, TPW, tile0, E, gmem(d.flip_ctr));
+  if constexpr (HUB) {
+    // the energy sums are done with red: it now holds the waves' hub sums
+    // (kSweepWaves x kMaxHubs x TPW x 64 int32, the same 2048 TPW bytes)
+    int32_t* hred = reinterpret_cast<int32_t*>(&red[0][0]);
+    __syncthreads();
+#pragma unroll
+    for (int hk = 0; hk < kMaxHubs; ++hk)
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) hred[((wave * kMaxHubs + hk) * TPW + t) * kLanes + lane] = hacc[hk][t];
+    __syncthreads();
+    if (wave < TPW) {
+      const int t = wave;
+      for (int hk = 0; hk < nhub; ++hk) {
+        int32_t sum = 0;
+#pragma unroll
+        for (int w = 0; w < kSweepWaves; ++w) sum += hred[((w * kMaxHubs + hk) * TPW + t) * kLanes + lane];
+        if (sum != 0)
+          __hip_atomic_fetch_add(&HF[hk * d.R + (tile0 + t) * kLanes + lane], sum, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
 }
 
 // WIDE: the instance's threshold table (2X + 1 entries) may exceed the LDS
-// copy, so every lookup goes to global memory.  The host picks the variant
-// from X; one loop body per kernel keeps the code small.
-template <int JM, int TPW, bool WIDE>
+// copy; a step whose table does not fit reads it from global memory.  The
+// host picks the variant from X, so instances whose table always fits get
+// one loop body.  HUB: the instance keeps the fields of its hub vertices.
+template <int JM, int TPW, bool WIDE, bool HUB>
 __global__ void __launch_bounds__(256) k_sweep_pull(const Desc* __restrict__ D,
                                                   const uint64_t* __restrict__ map, int sweep_idx,
                                                   int phase) {
-  __shared__ uint32_t thr_s[WIDE ? 1 : kThrLds];
+  __shared__ uint32_t thr_s[kThrLds];
   int inst, lb;
   if (!resolve(map, inst, lb)) return;
   const Desc& d = D[inst];
@@ -265,12 +315,17 @@ __global__ void __launch_bounds__(256) k_sweep_pull(const Desc* __restrict__ D,
   PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0);
   PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
   const PAMC_GLOBAL int32_t* __restrict__ Jc = gmem(d.gJ);
-  if (!WIDE) {
+  // the step's table (2 Xt + 1 entries) goes to LDS whenever it fits, also
+  // for instances whose full range (WIDE: 2X + 1) would not
+  if (!WIDE || 2 * Xt + 1 <= kThrLds) {
     for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
     __syncthreads();
+    sweep_pull_body<JM, TPW, true, HUB>(gmem(d.grow), gmem(d.gcol), Jc, thr_g, thr_s, S, E, d, group, chunk, v0,
+                                        v1, gs, Xt);
+  } else {
+    sweep_pull_body<JM, TPW, false, HUB>(gmem(d.grow), gmem(d.gcol), Jc, thr_g, thr_s, S, E, d, group, chunk, v0,
+                                         v1, gs, Xt);
   }
-  sweep_pull_body<JM, TPW, !WIDE>(gmem(d.grow), gmem(d.gcol), Jc, thr_g, thr_s, S, E, d, group, chunk, v0, v1, gs,
-                                  Xt);
 }
 
 // ---------------------------------------------------------------------------
@@ -704,6 +759,8 @@ __global__ void __launch_bounds__(256) k_init_fields(const Desc* __restrict__ D,
       for (int e = d.row_ptr[v]; e < d.row_ptr[v + 1]; ++e)
         h += (int64_t)d.J[e] * spin_at(S, d.nq, tile, d.col[e], lane);
       if (H) H[((size_t)tile * d.np + v) * kLanes + lane] = (int32_t)h;
+      if (!Hout && d.nhub && (v == d.hub_v0 || v == d.hub_v1))  // the kept hub fields
+        (b ? d.HF1 : d.HF0)[(v == d.hub_v0 ? 0 : 1) * d.R + tile * kLanes + lane] = (int32_t)h;
       acc += h * spin_at(S, d.nq, tile, v, lane);
     }
     __syncthreads();
@@ -1406,6 +1463,7 @@ __global__ void __launch_bounds__(256) k_rs_gather(const Desc* __restrict__ D,
   if (chunk == 0 && wave == 0) {
     (cur ? a.E0 : a.E1)[c] = (cur ? a.E1 : a.E0)[p];
     (cur ? a.F0 : a.F1)[c] = (cur ? a.F1 : a.F0)[p];
+    for (int hk = 0; hk < a.nhub; ++hk) (cur ? a.HF0 : a.HF1)[hk * a.R + c] = (cur ? a.HF1 : a.HF0)[hk * a.R + p];
   }
   const int qb = chunk * kGatherQuadsPerBlock;
   // the wave's spin words: every read issued before the first write, so
@@ -1496,6 +1554,8 @@ __global__ void __launch_bounds__(1024) k_cl_mis(const Desc* __restrict__ D, con
     if (v < a.n) {
       if (H) {
         h = H[((size_t)tile * a.np + v) * kLanes + lane];
+      } else if (a.nhub && (v == a.hub_v0 || v == a.hub_v1)) {
+        h = (buf ? a.HF1 : a.HF0)[(v == a.hub_v0 ? 0 : 1) * a.R + r];
       } else {
         h = 0;
         for (int e = a.row_ptr[v]; e < a.row_ptr[v + 1]; ++e) h += a.J[e] * spin_at(S, a.nq, tile, a.col[e], lane);
@@ -1583,6 +1643,13 @@ __global__ void __launch_bounds__(256) k_cl_apply(const Desc* __restrict__ D, co
       for (int e = a.row_ptr[v]; e < a.row_ptr[v + 1]; ++e)
         __hip_atomic_fetch_add(&H[((size_t)tile * a.np + a.col[e]) * kLanes + lane], 2 * a.J[e] * snew,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      for (int hk = 0; hk < a.nhub; ++hk) {  // gathered fields: only the kept hub fields change
+        const int32_t hj = a.hubJ[v * kMaxHubs + hk];
+        if (hj)
+          __hip_atomic_fetch_add(&(buf ? a.HF1 : a.HF0)[hk * a.R + r], 2 * hj * snew, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
     ++mine;
   }
   // one counter update per work-group
@@ -1675,6 +1742,12 @@ Desc make_desc(const pamc_instance* I) {
   d.gcol = I->g.gcol;
   d.gJ = I->g.gJ;
   d.class_ptr = I->g.class_ptr;
+  d.hubJ = I->g.hubJ;
+  d.HF0 = I->pop.HF[0];
+  d.HF1 = I->pop.HF[1];
+  d.nhub = I->nhub;
+  d.hub_v0 = I->hub_v[0];
+  d.hub_v1 = I->hub_v[1];
   d.order = I->order;
   d.thr = I->thr;
   d.S0 = I->pop.S[0];
@@ -1725,11 +1798,11 @@ Desc make_desc(const pamc_instance* I) {
 }
 
 int Batch::group_of(const pamc_instance* I) {
-  if (I->potts_K) return 19 + (I->potts_K - 2);
+  if (I->potts_K) return 37 + (I->potts_K - 2);
   if (!I->pull) return 0;
   const int ti = I->tpw == 4 ? 2 : (I->tpw == 2 ? 1 : 0);
   const int wide = 2 * I->X + 1 > kThrLds ? 1 : 0;
-  return 1 + 9 * wide + 3 * I->jmode + ti;
+  return 1 + 18 * (I->nhub ? 1 : 0) + 9 * wide + 3 * I->jmode + ti;
 }
 
 void Batch::free_device() {
@@ -1928,21 +2001,27 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
 
 using SweepKernel = void (*)(const Desc*, const uint64_t*, int, int);
 
-template <bool WIDE>
+template <bool WIDE, bool HUB>
 static SweepKernel pull_kernel(int jm, int ti) {
   static const SweepKernel k[3][3] = {
-      {k_sweep_pull<0, 1, WIDE>, k_sweep_pull<0, 2, WIDE>, k_sweep_pull<0, 4, WIDE>},
-      {k_sweep_pull<1, 1, WIDE>, k_sweep_pull<1, 2, WIDE>, k_sweep_pull<1, 4, WIDE>},
-      {k_sweep_pull<2, 1, WIDE>, k_sweep_pull<2, 2, WIDE>, k_sweep_pull<2, 4, WIDE>}};
+      {k_sweep_pull<0, 1, WIDE, HUB>, k_sweep_pull<0, 2, WIDE, HUB>, k_sweep_pull<0, 4, WIDE, HUB>},
+      {k_sweep_pull<1, 1, WIDE, HUB>, k_sweep_pull<1, 2, WIDE, HUB>, k_sweep_pull<1, 4, WIDE, HUB>},
+      {k_sweep_pull<2, 1, WIDE, HUB>, k_sweep_pull<2, 2, WIDE, HUB>, k_sweep_pull<2, 4, WIDE, HUB>}};
   return k[jm][ti];
 }
 
 static SweepKernel sweep_kernel_of_group(int g) {
-  // group = 0 (incremental fields) or 1 + 9 * wide table + 3 * coupling mode + tiles-per-wave index
+  // group = 0 (incremental fields), 1 + 18 * hubs + 9 * wide table + 3 * coupling mode +
+  // tiles-per-wave index (gathered fields), 37 + K - 2 (Potts labels)
   if (g == 0) return k_sweep_push;
-  if (g >= 19) return g == 19 ? k_sweep_potts<2> : (g == 20 ? k_sweep_potts<3> : k_sweep_potts<4>);
-  const int x = g - 1;
-  return x >= 9 ? pull_kernel<true>((x - 9) / 3, (x - 9) % 3) : pull_kernel<false>(x / 3, x % 3);
+  if (g >= 37) return g == 37 ? k_sweep_potts<2> : (g == 38 ? k_sweep_potts<3> : k_sweep_potts<4>);
+  int x = g - 1;
+  const bool hub = x >= 18;
+  x %= 18;
+  const bool wide = x >= 9;
+  x %= 9;
+  if (hub) return wide ? pull_kernel<true, true>(x / 3, x % 3) : pull_kernel<false, true>(x / 3, x % 3);
+  return wide ? pull_kernel<true, false>(x / 3, x % 3) : pull_kernel<false, false>(x / 3, x % 3);
 }
 
 static hipEvent_t next_event(pamc_instance* I) {

@@ -9,8 +9,9 @@ are compared after whole runs, not only on sampled replicas.
     move over all 20,000 spins (about 100 KB of LDS per work-group) and a
     restart.
   C4 graph: the full Max-3-Cut embedding of G(7000, 21000) (n = 21,001 with
-    the degree-21,000 ancilla, incremental fields), R = 64, 30 steps of 10
-    sweeps with the same forcing.
+    the degree-21,000 ancilla), R = 64, 30 steps of 10 sweeps with the same
+    forcing, with incremental fields (the default) and with gathered fields
+    where the ancilla's field is kept.
   C3 shape: a dense +-1 instance generated on the device with n = 8192 (eight
     1024-row super-blocks), R = 256 (four sequential-pass work-groups and the
     overlapped field product), three plain steps.
@@ -86,12 +87,13 @@ def test_c2_graph_augmented_full_size(pamc, monkeypatch):
     inst.close()
 
 
-def test_c4_embedding_augmented_full_size(pamc):
+@pytest.mark.parametrize("fields", [None, "pull"])
+def test_c4_embedding_augmented_full_size(pamc, fields):
     g = synth.config_c4_graph()
     R, seed = 64, 78
-    say("case c4 embedding n=21001 R=64 augmented, incremental fields")
-    inst = pamc.Instance.max3cut(g, replicas=R, seed=seed)
-    assert inst.info().n == 21001 and inst.info().pull == 0
+    say(f"case c4 embedding n=21001 R=64 augmented, fields={fields or 'incremental'}")
+    inst = pamc.Instance.max3cut(g, replicas=R, seed=seed, fields=fields)
+    assert inst.info().n == 21001 and inst.info().pull == (1 if fields == "pull" else 0)
     o = oracle.Oracle.max3cut(g.n, g.row_ptr, g.col, g.w, R, seed)
     kw = dict(beta0=0.1, dbeta=0.1, steps=30, sweeps=10, augmented=1, z_rst=25, n_top=2, **FORCE)
     res, ores = compare_run(pamc, inst, o, kw)

@@ -393,3 +393,52 @@ def test_pair_distance_matches_oracle(pamc, fields):
     a, b = inst.pair_distance(), o.mean_pair_distance()
     assert close_lnq(a, b), (a, b)
     inst.close()
+
+
+def hub_graph(n, m, hubs, seed, wmax):
+    """A random graph plus `hubs` vertices joined to most others (rows far
+    longer than a gathered row may be), symmetric weights in [-wmax, wmax]."""
+    rng = np.random.default_rng(seed)
+    base = synth.random_graph(n, m, seed)
+    us, vs = [], []
+    for v in range(n):
+        for e in range(base.row_ptr[v], base.row_ptr[v + 1]):
+            if base.col[e] > v:
+                us.append(v)
+                vs.append(int(base.col[e]))
+    for k in range(hubs):
+        h = n + k
+        for v in range(n):
+            if rng.random() < 0.7:
+                us.append(v)
+                vs.append(h)
+    if hubs == 2:
+        us.append(n)
+        vs.append(n + 1)
+    w = rng.integers(1, wmax + 1, size=len(us)) * rng.choice([-1, 1], size=len(us))
+    return synth.csr_from_edges(n + hubs, np.array(us), np.array(vs), w.astype(np.int32))
+
+
+@pytest.mark.parametrize("hubs", [1, 2])
+@pytest.mark.parametrize("wmax,jmode", [(1, 2), (100, 2), (5000, 1), (5000, 0)])
+@pytest.mark.parametrize("tpw", [1, 4])
+def test_kept_hub_fields(pamc, monkeypatch, hubs, wmax, jmode, tpw):
+    """Gathered fields with the hubs' fields kept incrementally (summed per
+    work-group before one atomic per replica): sweeps, resampling (hub fields
+    gathered with the population), cluster moves (hub fields updated by the
+    flipped iso-sites) and the controller, against the oracle."""
+    g = hub_graph(300, 700, hubs, 40 + hubs + tpw, wmax)
+    monkeypatch.setenv("PAMC_JMODE", str(jmode))
+    monkeypatch.setenv("PAMC_TPW", str(tpw))
+    R = 256
+    say(f"case kept hub fields hubs={hubs} wmax={wmax} jmode={jmode} tpw={tpw}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=5, objective=pamc.ISING, fields="pull")
+    info = inst.info()
+    assert info.pull == 1 and info.tiles_per_wave == tpw
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 5, objective=oracle.ISING)
+    same_state(inst, o, "init")
+    scale = 1.0 / wmax
+    compare_anneal(pamc, inst, o, dict(beta0=0.1 * scale, dbeta=0.05 * scale, steps=60, sweeps=2, augmented=1,
+                                       z_rst=45, n_top=16, mis_trials=3, win_short=4, win_long=6,
+                                       max_distinct_short=2, max_distinct_long=3, tau=3))
+    inst.close()
