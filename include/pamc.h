@@ -188,13 +188,17 @@ pamc_status pamc_reset_population(pamc_instance* inst, uint64_t seed);
  * incrementally (0).  The sweep kernel's shape for sparse instances:
  * tiles_per_wave replica tiles of 64 per wavefront, quads_per_wave vertex
  * quads per wavefront in a work-group, coupling_mode 0 (32-bit products),
- * 1 (24-bit) or 2 (int8 couplings with 4-way dot products). */
+ * 1 (24-bit) or 2 (int8 couplings with 4-way dot products); tile_sweeps 1:
+ * small instance whose step's sweeps run in one launch, one work-group per
+ * replica tile holding the tile's spins in LDS; hubs: vertices whose fields
+ * are kept while the others are gathered. */
 typedef struct {
   int32_t n, replicas, num_classes, dense, pull;
   int64_t nnz, W, X; /* X = max_v sum_j |J_vj| */
   int64_t device_bytes;
   int32_t tiles_per_wave, quads_per_wave, coupling_mode;
   int32_t potts_K; /* labels per vertex of a Potts instance, else 0 */
+  int32_t tile_sweeps, hubs;
 } pamc_info;
 pamc_status pamc_get_info(const pamc_instance* inst, pamc_info* out);
 

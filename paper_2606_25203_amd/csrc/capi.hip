@@ -212,6 +212,8 @@ struct HostSparse {
   int32_t n = 0, np = 0, nq = 0, ncls = 0, max_class_quads = 0;
   int32_t small_j = 0, jmode = 0, pull = 0, tpw = 1, qpw = 1;
   int32_t nhub = 0, hub_v[pamc::kMaxHubs] = {-1, -1};  // internal ids of the hubs (pull mode)
+  int32_t tile = 0;  // a step's sweeps of a replica tile in one work-group
+  int32_t tile_rows = 0;  // gathered-CSR entries of the largest colour class
   int64_t nnz = 0, W = 0, X = 0;
   std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, grow, gcol, gJ, hubJ;
 };
@@ -230,17 +232,20 @@ struct HostSparse {
 // at a flip rate of 0.16% but 170 us at 10%; the benchmark's runs average
 // 1%, where incremental fields are faster, so graphs with hubs default to
 // them.  Returns pull; hubs receives the hubs' caller ids.
+// Small instances (at most tile_max_quads vertex quads, a threshold table
+// that fits LDS) sweep tile-resident: one work-group per replica tile holds
+// the tile's spins in LDS and makes all of a step's sweeps in one launch,
+// where per-class launches would each carry microseconds of launch latency
+// for a few dozen vertices.
+bool tile_fits(int64_t nq, int64_t X) { return nq <= pamc::tile_max_quads() && 2 * X + 1 <= 2048; }
+
 bool choose_fields(int32_t n, const int32_t* rp, uint32_t flags, bool potts, std::vector<int32_t>* hubs) {
   hubs->clear();
   if (potts) return true;  // Potts labels: K-label fields gathered at visit time
   if (flags & PAMC_FLAG_FIELDS_PUSH) return false;
-  int64_t hub_entries = 0;
   std::vector<int32_t> h;
   for (int32_t v = 0; v < n; ++v)
-    if (rp[v + 1] - rp[v] > 64) {
-      h.push_back(v);
-      hub_entries += rp[v + 1] - rp[v];
-    }
+    if (rp[v + 1] - rp[v] > 64) h.push_back(v);
   if (flags & PAMC_FLAG_FIELDS_PULL) {
     if ((int)h.size() <= pamc::kMaxHubs) *hubs = h;  // more hubs than that: gathered like any row
     return true;
@@ -324,6 +329,14 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   }
   std::vector<int32_t> hubs;
   h.pull = choose_fields(n, rp, flags, h.potts_K != 0, &hubs) ? 1 : 0;
+  // Small instances sweep tile-resident (see below): the spins sit in LDS,
+  // so gathering is cheap whatever the degree, and no field array is kept.
+  h.tile = (!h.potts_K && !(flags & PAMC_FLAG_FIELDS_PUSH) && tile_fits(h.nq, X)) ? 1 : 0;
+  if (const char* e = getenv("PAMC_TILE")) h.tile = h.tile && atoi(e) != 0 ? 1 : 0;
+  if (h.tile) {
+    h.pull = 1;
+    hubs.clear();
+  }
   h.nhub = h.pull ? (int32_t)hubs.size() : 0;
   for (int32_t k = 0; k < h.nhub; ++k) h.hub_v[k] = h.to_internal[hubs[k]];
   if (h.nhub) {  // couplings of every vertex to each hub
@@ -353,6 +366,21 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
       for (int32_t e = h.rp2[iv]; e < h.rp2[iv + 1]; ++e, ++p) {
         h.gcol[p] = (h.col2[e] >> 2) * 256 + (h.jmode == 2 ? 0 : (h.col2[e] & 3));
         h.gJ[p] = h.jmode == 2 ? (int32_t)((uint32_t)(uint8_t)(int8_t)h.J2[e] << (8 * (h.col2[e] & 3))) : h.J2[e];
+      }
+    }
+  }
+  if (h.tile) {  // a class's gathered rows are staged in LDS next to the spins
+    for (int32_t c = 0; c < h.ncls; ++c)
+      h.tile_rows = std::max(h.tile_rows, h.grow[h.class_ptr[c + 1]] - h.grow[h.class_ptr[c]]);
+    h.tile_rows = (h.tile_rows + 3) & ~3;
+    if (pamc::tile_lds_bytes(h.nq, h.tile_rows) > pamc::tile_lds_limit()) {
+      h.tile = 0;
+      h.tile_rows = 0;
+      if (!choose_fields(n, rp, flags, false, &hubs)) {  // back to the field storage it would have had
+        h.pull = 0;
+        h.grow.clear();
+        h.gcol.clear();
+        h.gJ.clear();
       }
     }
   }
@@ -401,6 +429,8 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   I->small_j = h.small_j;
   I->jmode = h.jmode;
   I->pull = h.pull;
+  I->tile = h.tile;
+  I->tile_rows = h.tile_rows;
   I->nhub = h.nhub;
   for (int k = 0; k < pamc::kMaxHubs; ++k) I->hub_v[k] = h.hub_v[k];
   I->tpw = h.tpw;
@@ -947,6 +977,8 @@ pamc_status pamc_get_info(const pamc_instance* I, pamc_info* out) {
   out->quads_per_wave = I->qpw;
   out->coupling_mode = I->jmode;
   out->potts_K = I->potts_K;
+  out->tile_sweeps = I->tile;
+  out->hubs = I->nhub;
   return PAMC_OK;
 }
 
@@ -1701,10 +1733,11 @@ int64_t estimate_bytes(int32_t n, const int32_t* rp, const int32_t* w, const pam
     X = std::max(X, ab);
   }
   std::vector<int32_t> hubs;
-  const bool pull = choose_fields(n, rp, cfg.flags, false, &hubs);
+  bool pull = choose_fields(n, rp, cfg.flags, false, &hubs);
+  const bool tile = !(cfg.flags & PAMC_FLAG_FIELDS_PUSH) && tile_fits(np / 4, X);
   const int64_t ncls = maxdeg + 1;
   int64_t b = a(4 * (int64_t)(n + 1)) + 2 * a(4 * (nnz + 16));                 // CSR
-  if (pull) b += a(4 * (int64_t)(n + 1)) + 2 * a(4 * std::max<int64_t>(gathered, 4));  // gathered CSR
+  if (pull || tile) b += a(4 * (int64_t)(n + 1)) + 2 * a(4 * std::max<int64_t>(gathered, 4));  // gathered CSR
   if (pull && !hubs.empty()) b += a(4 * np * pamc::kMaxHubs) + 2 * a(4 * pamc::kMaxHubs * R);  // hubs
   b += a(4 * (ncls + 1));                                                      // class_ptr
   b += 2 * (a(R * np) + (pull ? 0 : a(4 * R * np)) + a(8 * R) + a(4 * R));     // two populations

@@ -62,6 +62,8 @@ struct pamc_instance {
   std::vector<int32_t> to_internal, to_input, class_ptr;
   int32_t max_class_quads = 0;
   int32_t pull = 0;       // 1: fields gathered at visit time (no field array)
+  int32_t tile = 0;       // 1: a step's sweeps of a replica tile in one work-group (small pull instances)
+  int32_t tile_rows = 0;  // gathered-CSR entries of the largest colour class (staged in LDS by tile sweeps)
   int32_t nhub = 0;       // hubs (pull mode): vertices whose fields are kept incrementally
   int32_t hub_v[pamc::kMaxHubs] = {-1, -1};  // their internal ids
   int32_t tpw = 1;        // replica tiles per wavefront in the gathered-field sweep
@@ -151,6 +153,7 @@ struct Desc {
   const int32_t* hubJ;    // [np][kMaxHubs] couplings to the hubs (gathered-field mode)
   int32_t *HF0, *HF1;     // hub fields [kMaxHubs][R], one per population buffer
   int32_t nhub, hub_v0, hub_v1;
+  int32_t tile_rows;      // tile sweeps: gathered-CSR entries of the largest class
   int32_t* order;
   uint32_t* thr;
   uint32_t *S0, *S1;
@@ -191,6 +194,8 @@ struct Batch {
   };
   Launch init_spins, init_fields, thr, thr_dense, gather, cl_mis, cl_apply;
   Launch sweep[kGroups];
+  Launch tile[3];          // tile-resident sweeps, per coupling mode
+  int64_t tile_lds = 0;    // their dynamic LDS bytes
   Desc* d_desc = nullptr;
   int32_t n = 0;
   hipStream_t stream = nullptr;
@@ -252,6 +257,9 @@ hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
 hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
 int32_t cluster_max_n();
 int32_t sweep_waves();  // wavefronts per sweep work-group
+int32_t tile_max_quads();  // vertex quads a tile-resident sweep holds in LDS
+int64_t tile_lds_bytes(int32_t nq, int32_t rows);  // its LDS: spins, table, a class's gathered rows
+int64_t tile_lds_limit();
 hipError_t prepare_kernel_lds();
 
 // controller pieces (sparse.hip) shared with the dense path

@@ -329,6 +329,138 @@ __global__ void __launch_bounds__(256) k_sweep_pull(const Desc* __restrict__ D,
 }
 
 // ---------------------------------------------------------------------------
+// All of a step's sweeps of one replica tile in one work-group, for small
+// instances (gathered fields, at most kTileMaxQuads vertex quads): the
+// tile's spin words live in LDS for the whole launch, and the work-group
+// walks the sweeps and, in each, the colour classes in the sweep's order,
+// its four waves sharing a class's quads, with a barrier between classes.
+// Replica tiles never interact within a step, so no other synchronisation
+// is needed; the decisions are those of k_sweep_pull (same fields, same
+// Philox words, same thresholds), so the trajectory is the same, while a
+// step is one launch instead of sweeps x classes.
+// ---------------------------------------------------------------------------
+constexpr int kTileMaxQuads = 512;      // 128 KB of LDS spin words: n <= 2048
+constexpr int kTileWaves = 16;          // waves of a tile-resident work-group
+constexpr int kTileLdsBytes = 150 * 1024;  // dynamic LDS: spins, table, one class's rows (8 KB static beside)
+
+template <int JM>
+__global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tile(const Desc* __restrict__ D,
+                                                                const uint64_t* __restrict__ map) {
+  // LDS: [nq][64] spin words, the threshold table (kThrLds words), then the
+  // current class's gathered rows (columns, then couplings; d.tile_rows
+  // entries each at most)
+  extern __shared__ uint32_t tl[];
+  __shared__ int64_t red[kTileWaves][kLanes];
+  __shared__ int32_t fred[kTileWaves];
+  int inst, tile;
+  if (!resolve(map, inst, tile)) return;
+  const Desc& d = D[inst];
+  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
+  const int nsw = st->nsweeps_now;
+  if (!st->active || nsw <= 0) return;
+  const int cur = st->cur;
+  const int nq = d.nq;
+  const int32_t Xt = (int32_t)st->table_x;
+  PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0) + (size_t)tile * nq * kLanes;
+  PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
+  const PAMC_GLOBAL uint32_t* __restrict__ thr_g = gmem((const uint32_t*)d.thr);
+  const PAMC_GLOBAL int32_t* __restrict__ order = gmem((const int32_t*)d.order);
+  const PAMC_GLOBAL int32_t* __restrict__ class_ptr = gmem(d.class_ptr);
+  const PAMC_GLOBAL int32_t* __restrict__ grow = gmem(d.grow);
+  const PAMC_GLOBAL int32_t* __restrict__ gcol = gmem(d.gcol);
+  const PAMC_GLOBAL int32_t* __restrict__ gJ = gmem(d.gJ);
+  uint32_t* Sl = tl;
+  uint32_t* thr_s = tl + (size_t)nq * kLanes;
+  int32_t* rc = reinterpret_cast<int32_t*>(thr_s + kThrLds);
+  int32_t* rj = rc + d.tile_rows;
+  for (int i = threadIdx.x; i < nq * kLanes; i += blockDim.x) Sl[i] = S[i];
+  for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t r = (uint32_t)(tile * kLanes + lane);
+  const bool metropolis = d.rule == 1;
+  int64_t dE = 0;
+  int32_t nflip = 0;
+  for (int sw_i = 0; sw_i < nsw; ++sw_i) {
+    const uint32_t gs = st->gs + (uint32_t)sw_i;
+    for (int p = 0; p < d.ncls; ++p) {
+      const int cls = order[sw_i * d.ncls + p];
+      const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
+      const int g0 = grow[v0], ng = grow[v1] - g0;
+      __syncthreads();  // the previous class is done with the row buffer (and its spins are in)
+      for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+        rc[i] = gcol[g0 + i];
+        rj[i] = gJ[g0 + i];
+      }
+      __syncthreads();
+      const int q0 = v0 >> 2, nqc = ((v1 + 3) >> 2) - q0;
+      for (int qi = wave; qi < nqc; qi += kTileWaves) {
+        const int q = q0 + qi;
+        uint32_t sw = Sl[q * kLanes + lane];
+        int32_t h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int v = 4 * q + k;
+          h[k] = 0;
+          if (v < v0 || v >= v1) continue;
+          const int e1 = grow[v + 1] - g0;
+          for (int e = grow[v] - g0; e < e1; e += 4) {
+            const i32x4 cj = *reinterpret_cast<const i32x4*>(rc + e);  // uniform: broadcast reads
+            const i32x4 cJ = *reinterpret_cast<const i32x4*>(rj + e);
+            const int j[4] = {cj.x, cj.y, cj.z, cj.w};
+            const int32_t c[4] = {cJ.x, cJ.y, cJ.z, cJ.w};
+            uint32_t w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] = Sl[(j[u] >> 2) + lane];  // the neighbour's word (byte offset / 4)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (JM == 2) {
+                h[k] = __builtin_amdgcn_sdot4((int)w[u], c[u], h[k], false);
+              } else {
+                const int32_t sv = __builtin_amdgcn_sbfe((int32_t)w[u], 8u * (uint32_t)(j[u] & 3), 8u);
+                h[k] += JM == 1 ? __mul24(c[u], sv) : c[u] * sv;
+              }
+            }
+          }
+        }
+        const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
+        uint32_t flipmask = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int v = 4 * q + k;
+          if (v < v0 || v >= v1) continue;
+          const int32_t s = __builtin_amdgcn_sbfe((int32_t)sw, 8u * k, 8u);
+          const int32_t x = __mul24(s, h[k]);
+          const int32_t xi = min(max(x, -Xt), Xt) + Xt;
+          const bool flip = (pick(rnd, k) < thr_s[xi]) || (metropolis && x <= 0);
+          dE += flip ? (int64_t)x : 0;
+          flipmask |= flip ? (0xFEu << (8 * k)) : 0u;
+          nflip += __popcll(__ballot(flip));
+        }
+        if (flipmask) Sl[q * kLanes + lane] = sw ^ flipmask;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nq * kLanes; i += blockDim.x) S[i] = Sl[i];
+  red[wave][lane] = 2 * dE;
+  if (lane == 0) fred[wave] = nflip;
+  __syncthreads();
+  if (wave == 0) {  // the work-group owns its tile's replicas: no atomics
+    int64_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < kTileWaves; ++w) sum += red[w][lane];
+    E[tile * kLanes + lane] += sum;
+    if (d.flip_ctr && lane == 0) {
+      int64_t f = 0;
+      for (int w = 0; w < kTileWaves; ++w) f += fred[w];
+      __hip_atomic_fetch_add((unsigned long long*)&d.flip_ctr[blockIdx.x & 255], (unsigned long long)f,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The same class phase with incremental fields: x = s*h from the field
 // array; on a flip E += 2x and every neighbour field gets 2 J s_new by a
 // coalesced no-return atomic.  Used where gathering is dearer (high degree,
@@ -1722,12 +1854,18 @@ __global__ void __launch_bounds__(256) k_pair_distance(const uint32_t* S0, const
 // ===========================================================================
 int32_t cluster_max_n() { return kClusterMaxN; }
 int32_t sweep_waves() { return kSweepWaves; }
+int32_t tile_max_quads() { return kTileMaxQuads; }
+int64_t tile_lds_bytes(int32_t nq, int32_t rows) { return (int64_t)nq * kLanes * 4 + kThrLds * 4 + 8 * (int64_t)rows; }
+int64_t tile_lds_limit() { return kTileLdsBytes; }
 
 // Kernels whose dynamic LDS may exceed the default limit.
 hipError_t prepare_kernel_lds() {
   hipError_t e = hipFuncSetAttribute((const void*)k_cl_mis, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      kClusterMaxN * 5 + 64);
   if (e != hipSuccess) return e;
+  for (const void* k : {(const void*)k_sweep_tile<0>, (const void*)k_sweep_tile<1>, (const void*)k_sweep_tile<2>})
+    if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kTileLdsBytes)) != hipSuccess)
+      return e;
   return hipFuncSetAttribute((const void*)k_rs_select, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)sizeof(uint64_t) * kRsMaxR);
 }
@@ -1791,6 +1929,7 @@ Desc make_desc(const pamc_instance* I) {
   d.shuffle = (I->flags & 1u) ? 0 : 1;
   d.tr_cap = I->tr_cap;
   d.qpw = I->qpw;
+  d.tile_rows = I->tile_rows;
   d.order_cap = I->order_cap;
   d.k0 = (uint32_t)I->seed;
   d.k1 = (uint32_t)(I->seed >> 32);
@@ -1827,6 +1966,12 @@ void Batch::free_device() {
     l.map = nullptr;
     l.grid = 0;
   }
+  for (Launch& l : tile) {
+    release(l.map);
+    l.map = nullptr;
+    l.grid = 0;
+  }
+  tile_lds = 0;
   arena_used = 0;
   if (step_graph) hipGraphExecDestroy(step_graph);
   step_graph = nullptr;
@@ -1942,7 +2087,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     }
   }
   std::vector<uint64_t> m_init, m_fields, m_thr, m_gather, m_mis, m_apply;
-  std::vector<std::vector<uint64_t>> m_sweep(Batch::kGroups);
+  std::vector<std::vector<uint64_t>> m_sweep(Batch::kGroups), m_tile(3);
   b.max_ncls = 0;
   for (int g = 0; g < Batch::kGroups; ++g) b.group_ncls[g] = 0;
   b.max_sweeps = 1;
@@ -1957,10 +2102,15 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     add_blocks(m_fields, i, field_blocks(I), false);
     add_blocks(m_thr, i, kThrBlocks, false);
     add_blocks(m_gather, i, (int64_t)I->T * ((I->nq + kGatherQuadsPerBlock - 1) / kGatherQuadsPerBlock), true);
-    const int grp = Batch::group_of(I);
-    add_blocks(m_sweep[grp], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_chunks(I), true);
-    b.max_ncls = std::max(b.max_ncls, I->ncls);
-    b.group_ncls[grp] = std::max(b.group_ncls[grp], I->ncls);
+    if (I->tile) {  // one work-group per replica tile walks the whole step
+      add_blocks(m_tile[I->jmode], i, I->T, false);
+      b.tile_lds = std::max<int64_t>(b.tile_lds, tile_lds_bytes(I->nq, I->tile_rows));
+    } else {
+      const int grp = Batch::group_of(I);
+      add_blocks(m_sweep[grp], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_chunks(I), true);
+      b.max_ncls = std::max(b.max_ncls, I->ncls);
+      b.group_ncls[grp] = std::max(b.group_ncls[grp], I->ncls);
+    }
     const int nt = cl_top[i];
     if (nt > 0 && cl_trials[i] > 0) {
       add_blocks(m_mis, i, (int64_t)nt * cl_trials[i], false);
@@ -1995,11 +2145,14 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
   if ((e = up(m_apply, b.cl_apply)) != hipSuccess) return e;
   for (int g = 0; g < Batch::kGroups; ++g)
     if ((e = up(m_sweep[g], b.sweep[g])) != hipSuccess) return e;
+  for (int g = 0; g < 3; ++g)
+    if ((e = up(m_tile[g], b.tile[g])) != hipSuccess) return e;
   // the staging vectors are local: wait for the copies before they go
   return hipStreamSynchronize(b.stream);
 }
 
 using SweepKernel = void (*)(const Desc*, const uint64_t*, int, int);
+using SweepTileKernel = void (*)(const Desc*, const uint64_t*);
 
 template <bool WIDE, bool HUB>
 static SweepKernel pull_kernel(int jm, int ti) {
@@ -2047,6 +2200,12 @@ static hipError_t batch_sweeps(Batch& b, int32_t nsweeps, int32_t commit = -1) {
   if (b.thr.grid) k_thresholds<<<b.thr.grid, 256, 0, b.stream>>>(b.d_desc, b.thr.map, commit);
   int64_t launches = 0;
   if (prof) hipEventRecord(next_event(P), b.stream);
+  static const SweepTileKernel tile_kernels[3] = {k_sweep_tile<0>, k_sweep_tile<1>, k_sweep_tile<2>};
+  for (int g = 0; g < 3; ++g)
+    if (b.tile[g].grid) {  // every sweep of the step, in one launch
+      tile_kernels[g]<<<b.tile[g].grid, kTileWaves * 64, b.tile_lds, b.stream>>>(b.d_desc, b.tile[g].map);
+      ++launches;
+    }
   for (int s = 0; s < nsweeps; ++s) {
     for (int p = 0; p < b.max_ncls; ++p) {
       for (int g = 0; g < Batch::kGroups; ++g) {

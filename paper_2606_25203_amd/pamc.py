@@ -99,7 +99,8 @@ class pamc_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("replicas", C.c_int32), ("num_classes", C.c_int32),
                 ("dense", C.c_int32), ("pull", C.c_int32), ("nnz", C.c_int64), ("W", C.c_int64), ("X", C.c_int64),
                 ("device_bytes", C.c_int64), ("tiles_per_wave", C.c_int32), ("quads_per_wave", C.c_int32),
-                ("coupling_mode", C.c_int32), ("potts_K", C.c_int32)]
+                ("coupling_mode", C.c_int32), ("potts_K", C.c_int32), ("tile_sweeps", C.c_int32),
+                ("hubs", C.c_int32)]
 
 
 class pamc_schedule(C.Structure):

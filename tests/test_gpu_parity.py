@@ -337,6 +337,7 @@ def weighted_int8_graph(n, m, seed):
 @pytest.mark.parametrize("tpw", [1, 2, 4])
 @pytest.mark.parametrize("rule", [0, 1])
 def test_gathered_field_variants(pamc, monkeypatch, jmode, tpw, rule):
+    monkeypatch.setenv("PAMC_TILE", "0")  # the per-class launches, not the tile-resident sweep
     """Every gathered-field kernel variant (coupling mode x tiles per wave)
     on int8 weights, where all three coupling modes apply."""
     g = weighted_int8_graph(203, 1400, 17)
@@ -355,6 +356,7 @@ def test_gathered_field_variants(pamc, monkeypatch, jmode, tpw, rule):
 @pytest.mark.parametrize("qpw", [1, 2, 4])
 @pytest.mark.parametrize("fields", FIELDS)
 def test_quads_per_wave(pamc, monkeypatch, qpw, fields):
+    monkeypatch.setenv("PAMC_TILE", "0")
     """Work-group shapes with 1, 2 and 4 vertex quads per wavefront over
     classes spanning many work-groups with a ragged last one (n = 1,599)."""
     g = synth.random_graph(1599, 5000, 23, weights="pm1")
@@ -430,11 +432,12 @@ def test_kept_hub_fields(pamc, monkeypatch, hubs, wmax, jmode, tpw):
     g = hub_graph(300, 700, hubs, 40 + hubs + tpw, wmax)
     monkeypatch.setenv("PAMC_JMODE", str(jmode))
     monkeypatch.setenv("PAMC_TPW", str(tpw))
+    monkeypatch.setenv("PAMC_TILE", "0")  # a graph this small would otherwise sweep tile-resident
     R = 256
     say(f"case kept hub fields hubs={hubs} wmax={wmax} jmode={jmode} tpw={tpw}")
     inst = pamc.Instance.csr(g, replicas=R, seed=5, objective=pamc.ISING, fields="pull")
     info = inst.info()
-    assert info.pull == 1 and info.tiles_per_wave == tpw
+    assert info.pull == 1 and info.tiles_per_wave == tpw and info.hubs == hubs and info.tile_sweeps == 0
     o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 5, objective=oracle.ISING)
     same_state(inst, o, "init")
     scale = 1.0 / wmax
@@ -442,3 +445,52 @@ def test_kept_hub_fields(pamc, monkeypatch, hubs, wmax, jmode, tpw):
                                        z_rst=45, n_top=16, mis_trials=3, win_short=4, win_long=6,
                                        max_distinct_short=2, max_distinct_long=3, tau=3))
     inst.close()
+
+
+@pytest.mark.parametrize("jmode", [0, 1, 2])
+@pytest.mark.parametrize("rule", [0, 1])
+@pytest.mark.parametrize("gname,R", [("c1_shape_small", 192), ("torus_pm1", 64), ("dense_ish", 128)])
+def test_tile_resident_sweeps(pamc, monkeypatch, jmode, rule, gname, R):
+    """Small instances sweep a replica tile per work-group with the tile's
+    spins in LDS, all of a step's sweeps in one launch: the same trajectory
+    as the oracle (and as the per-class launches), through sweeps,
+    resampling, cluster moves and the controller."""
+    g = GRAPHS[gname]()
+    monkeypatch.setenv("PAMC_JMODE", str(jmode))
+    say(f"case tile-resident sweeps {gname} R={R} jmode={jmode} rule={rule}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=17, rule=rule, fields="pull")
+    info = inst.info()
+    assert info.tile_sweeps == 1
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 17, rule=rule)
+    inst.sweep(0.3, 3)
+    o.sweep(0.3, 3)
+    same_state(inst, o, "sweeps")
+    compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.05, steps=50, sweeps=3, augmented=1, z_rst=40,
+                                       n_top=6, mis_trials=3, win_short=4, win_long=6, max_distinct_short=2,
+                                       max_distinct_long=3, tau=3))
+    inst.close()
+
+
+def test_tile_resident_largest_and_mixed_batch(pamc):
+    """A large tile-resident instance (1792 vertices: 112 KB of LDS spin
+    words beside the table and a class's rows) and a batch mixing
+    tile-resident and per-class instances."""
+    g = synth.random_graph(1792, 3000, 8)
+    say("case tile-resident n=1792")
+    inst = pamc.Instance.csr(g, replicas=128, seed=3)
+    assert inst.info().tile_sweeps == 1
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 128, 3)
+    compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.2, steps=12, sweeps=2))
+    inst.close()
+    big = synth.random_graph(2052, 3000, 8)
+    a = pamc.Instance.csr(big, replicas=128, seed=4)
+    assert a.info().tile_sweeps == 0  # 513 quads: per-class launches
+    b = pamc.Instance.csr(g, replicas=128, seed=5)
+    sched = pamc.schedule(beta0=0.1, dbeta=0.2, steps=10, sweeps=2)
+    rb = pamc.anneal_batch([a, b], [sched, sched])
+    for inst_, gg, seed, r in ((a, big, 4, rb[0]), (b, g, 5, rb[1])):
+        o = oracle.Oracle.sparse(gg.n, gg.row_ptr, gg.col, gg.w, 128, seed)
+        ores = o.anneal(oracle.default_schedule(beta0=0.1, dbeta=0.2, steps=10, sweeps=2))
+        assert r.best_cut == ores.best_cut
+        same_state(inst_, o, "mixed batch")
+        inst_.close()
