@@ -350,6 +350,25 @@ pamc_status pamc_profile_read(pamc_instance* inst, double* ms, int64_t* launches
 
 pamc_status pamc_synchronize(pamc_instance* inst);
 
+/* Autotuner of the sweep kernels' shape.  Candidates: tile-resident sweeps
+ * on or off (where the instance allows them), 1, 2 or 4 replica tiles per
+ * wavefront (gathered fields), 1, 2 or 4 vertex quads per wavefront.  Each
+ * is timed on `sweeps` sweeps at `beta` run on the instance's own
+ * population, which is saved first and restored, with the stream counters,
+ * after every candidate, so tuning never changes a trajectory.  The fastest
+ * shape is kept and remembered per instance shape (n, edges, replicas,
+ * colour classes, field mode, coupling mode) for this process: a later call
+ * for an instance of the same shape takes it without timing unless force is
+ * set.  Sparse instances only; waits. */
+typedef struct {
+  int32_t tile_sweeps, tiles_per_wave, quads_per_wave; /* the chosen shape */
+  int32_t candidates;                                   /* shapes timed (0 if taken from the cache) */
+  int32_t cached;                                       /* 1: the shape came from the cache */
+  double best_ms_per_sweep, default_ms_per_sweep;       /* chosen and creation-time shapes */
+} pamc_tune_result;
+pamc_status pamc_autotune(pamc_instance* inst, double beta, int32_t sweeps, int32_t force,
+                          pamc_tune_result* out);
+
 /* ---------------------------------------------------------------------------
  * Batched and served runs.  Many independent runs share every kernel launch:
  * each kernel reads a per-instance descriptor and a block-to-instance map,

@@ -213,6 +213,7 @@ struct HostSparse {
   int32_t small_j = 0, jmode = 0, pull = 0, tpw = 1, qpw = 1;
   int32_t nhub = 0, hub_v[pamc::kMaxHubs] = {-1, -1};  // internal ids of the hubs (pull mode)
   int32_t tile = 0;  // a step's sweeps of a replica tile in one work-group
+  int32_t tile_ok = 0;  // tile-resident sweeps possible (the autotuner may switch them)
   int32_t tile_rows = 0;  // gathered-CSR entries of the largest colour class
   int64_t nnz = 0, W = 0, X = 0;
   std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, grow, gcol, gJ, hubJ;
@@ -369,19 +370,21 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
       }
     }
   }
-  if (h.tile) {  // a class's gathered rows are staged in LDS next to the spins
+  const bool tile_candidate = h.pull && !h.nhub && !h.potts_K && tile_fits(h.nq, X);
+  if (tile_candidate) {  // a class's gathered rows are staged in LDS next to the spins
     for (int32_t c = 0; c < h.ncls; ++c)
       h.tile_rows = std::max(h.tile_rows, h.grow[h.class_ptr[c + 1]] - h.grow[h.class_ptr[c]]);
     h.tile_rows = (h.tile_rows + 3) & ~3;
-    if (pamc::tile_lds_bytes(h.nq, h.tile_rows) > pamc::tile_lds_limit()) {
-      h.tile = 0;
-      h.tile_rows = 0;
-      if (!choose_fields(n, rp, flags, false, &hubs)) {  // back to the field storage it would have had
-        h.pull = 0;
-        h.grow.clear();
-        h.gcol.clear();
-        h.gJ.clear();
-      }
+    h.tile_ok = pamc::tile_lds_bytes(h.nq, h.tile_rows) <= pamc::tile_lds_limit() ? 1 : 0;
+    if (!h.tile_ok) h.tile_rows = 0;
+  }
+  if (h.tile && !h.tile_ok) {  // the rows do not fit: per-class launches
+    h.tile = 0;
+    if (!choose_fields(n, rp, flags, false, &hubs)) {  // back to the field storage it would have had
+      h.pull = 0;
+      h.grow.clear();
+      h.gcol.clear();
+      h.gJ.clear();
     }
   }
   // Tiles per wavefront: share the per-vertex scalar work among up to 4
@@ -416,6 +419,37 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   return PAMC_OK;
 }
 
+// Sweep shapes chosen by pamc_autotune, per instance shape (this process).
+struct TuneShape {
+  int32_t tile, tpw, qpw;
+};
+
+std::mutex g_tune_mutex;
+std::unordered_map<std::string, TuneShape> g_tune_cache;
+
+std::string tune_key(const pamc_instance* I) {
+  return std::to_string(I->n) + "/" + std::to_string(I->nnz) + "/" + std::to_string(I->R) + "/" +
+         std::to_string(I->ncls) + "/" + std::to_string(I->max_class_quads) + "/" + std::to_string(I->pull) + "/" +
+         std::to_string(I->jmode) + "/" + std::to_string(I->potts_K) + "/" + std::to_string(I->nhub) + "/" +
+         std::to_string(I->tile_ok) + "/" + std::to_string(I->rule);
+}
+
+void apply_shape(pamc_instance* I, const TuneShape& t) {
+  I->tile = t.tile;
+  I->tpw = t.tpw;
+  I->qpw = t.qpw;
+  I->self_dirty = true;
+}
+
+// A new instance of a shape the autotuner has seen takes its choice (unless
+// a shape is forced from the environment).
+void apply_cached_shape(pamc_instance* I) {
+  if (getenv("PAMC_TPW") || getenv("PAMC_QPW") || getenv("PAMC_TILE")) return;
+  std::lock_guard<std::mutex> g(g_tune_mutex);
+  auto it = g_tune_cache.find(tune_key(I));
+  if (it != g_tune_cache.end()) apply_shape(I, it->second);
+}
+
 // Device half: buffers, upload and the initial population (waits).
 pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   const int32_t n = h.n, ncls = h.ncls;
@@ -430,6 +464,7 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   I->jmode = h.jmode;
   I->pull = h.pull;
   I->tile = h.tile;
+  I->tile_ok = h.tile_ok;
   I->tile_rows = h.tile_rows;
   I->nhub = h.nhub;
   for (int k = 0; k < pamc::kMaxHubs; ++k) I->hub_v[k] = h.hub_v[k];
@@ -488,6 +523,7 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
     HIP_TRY(hipMemcpyAsync(I->g.hubJ, h.hubJ.data(), sizeof(int32_t) * h.hubJ.size(), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->to_internal_dev, I->to_internal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::prepare_kernel_lds(), "hipFuncSetAttribute");
+  apply_cached_shape(I);
   SELF_BATCH(I, b);
   HIP_TRY(pamc::batch_init(*b), "init kernels");
   // the host arrays are read by the queued copies: wait before they go
@@ -1542,6 +1578,133 @@ pamc_status pamc_set_checkpoint(pamc_instance* I, const void* buf, int64_t bytes
   r.active = 0;
   I->trace_ok = false;
   return write_state(I, r);
+}
+
+}  // extern "C"
+
+namespace {
+
+
+// The population buffers a sweep changes (spins, kept fields, energies)
+// and their byte sizes.
+std::vector<std::pair<void*, size_t>> sweep_state(pamc_instance* I, int cur) {
+  std::vector<std::pair<void*, size_t>> v;
+  v.push_back({I->pop.S[cur], sizeof(uint32_t) * (size_t)I->T * I->nq * 64});
+  if (I->pop.H[cur]) v.push_back({I->pop.H[cur], sizeof(int32_t) * (size_t)I->T * I->np * 64});
+  if (I->pop.HF[cur]) v.push_back({I->pop.HF[cur], sizeof(int32_t) * (size_t)pamc::kMaxHubs * I->R});
+  v.push_back({I->pop.E[cur], sizeof(int64_t) * (size_t)I->R});
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+pamc_status pamc_autotune(pamc_instance* I, double beta, int32_t sweeps, int32_t force, pamc_tune_result* out) {
+  if (!I || !out) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  if (I->dense) return fail(PAMC_ERR_UNSUPPORTED, "the autotuner is for sparse instances");
+  if (sweeps <= 0 || !std::isfinite(beta) || (I->potts_K && beta < 0))
+    return fail(PAMC_ERR_INVALID_ARG, "bad tuning sweeps or beta");
+  hipSetDevice(I->device);
+  memset(out, 0, sizeof *out);
+  const TuneShape initial{I->tile, I->tpw, I->qpw};
+  const std::string key = tune_key(I);
+  if (!force) {
+    std::lock_guard<std::mutex> g(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      apply_shape(I, it->second);
+      out->tile_sweeps = I->tile;
+      out->tiles_per_wave = I->tpw;
+      out->quads_per_wave = I->qpw;
+      out->cached = 1;
+      return PAMC_OK;
+    }
+  }
+  std::vector<TuneShape> cand;
+  for (int tile : {0, 1}) {
+    if (tile && !I->tile_ok) continue;
+    if (tile) {
+      cand.push_back({1, initial.tpw, initial.qpw});  // the tile-resident sweep ignores the wave shape
+      continue;
+    }
+    for (int tpw : {1, 2, 4}) {
+      if (tpw > 1 && (!I->pull || I->potts_K || I->T % tpw)) continue;
+      for (int qpw : {1, 2, 4}) cand.push_back({0, tpw, qpw});
+    }
+  }
+  // scratch copy of the run state and of what sweeps change
+  pamc::RunState st0;
+  pamc_status st = read_state(I, &st0);
+  if (st) return st;
+  auto bufs = sweep_state(I, st0.cur);
+  std::vector<void*> saved(bufs.size(), nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < bufs.size() && e == hipSuccess; ++i) {
+    e = dev_alloc(I, &saved[i], bufs[i].second);
+    if (e == hipSuccess) e = hipMemcpyAsync(saved[i], bufs[i].first, bufs[i].second, hipMemcpyDeviceToDevice, I->stream);
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  const bool prof = I->prof;
+  I->prof = false;  // no library events inside the timed region
+  auto restore = [&]() -> hipError_t {
+    hipError_t r = hipSuccess;
+    for (size_t i = 0; i < bufs.size() && r == hipSuccess; ++i)
+      r = hipMemcpyAsync(bufs[i].first, saved[i], bufs[i].second, hipMemcpyDeviceToDevice, I->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(I->stream);
+    if (r == hipSuccess) r = hipMemcpy(I->st, &st0, sizeof st0, hipMemcpyHostToDevice);
+    return r;
+  };
+  double best = 1e300, dflt = -1.0;
+  TuneShape best_shape = initial;
+  for (const TuneShape& c : cand) {
+    if (e != hipSuccess) break;
+    apply_shape(I, c);
+    hipError_t be;
+    pamc::Batch* b = self_batch(I, &be);
+    if (!b) {
+      e = be;
+      break;
+    }
+    float ms = 1e30f;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the second of two timings
+      e = hipEventRecord(ev[0], I->stream);
+      if (e == hipSuccess) e = pamc::prim_sweep(*b, beta, sweeps);
+      if (e == hipSuccess) e = hipEventRecord(ev[1], I->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e == hipSuccess) e = restore();
+    }
+    if (e != hipSuccess) break;
+    const double per = ms / sweeps;
+    if (c.tile == initial.tile && c.tpw == initial.tpw && c.qpw == initial.qpw) dflt = per;
+    if (per < best) {
+      best = per;
+      best_shape = c;
+    }
+    out->candidates += 1;
+  }
+  I->prof = prof;
+  for (hipEvent_t x : ev)
+    if (x) hipEventDestroy(x);
+  for (void* p : saved) dev_free(I, p);
+  if (e != hipSuccess) {
+    apply_shape(I, initial);
+    return dev_fail(e, "autotune");
+  }
+  apply_shape(I, best_shape);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mutex);
+    g_tune_cache[key] = best_shape;
+  }
+  out->tile_sweeps = I->tile;
+  out->tiles_per_wave = I->tpw;
+  out->quads_per_wave = I->qpw;
+  out->best_ms_per_sweep = best;
+  out->default_ms_per_sweep = dflt;
+  return PAMC_OK;
 }
 
 pamc_status pamc_profile_enable(pamc_instance* I, int32_t on) {

@@ -64,6 +64,7 @@ struct pamc_instance {
   int32_t pull = 0;       // 1: fields gathered at visit time (no field array)
   int32_t tile = 0;       // 1: a step's sweeps of a replica tile in one work-group (small pull instances)
   int32_t tile_rows = 0;  // gathered-CSR entries of the largest colour class (staged in LDS by tile sweeps)
+  int32_t tile_ok = 0;    // tile-resident sweeps possible
   int32_t nhub = 0;       // hubs (pull mode): vertices whose fields are kept incrementally
   int32_t hub_v[pamc::kMaxHubs] = {-1, -1};  // their internal ids
   int32_t tpw = 1;        // replica tiles per wavefront in the gathered-field sweep

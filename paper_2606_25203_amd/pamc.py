@@ -31,7 +31,7 @@ EXPORTED = [
     "pamc_sweep", "pamc_resample", "pamc_cluster_move", "pamc_update_best", "pamc_best",
     "pamc_get_state", "pamc_get_trace", "pamc_max3cut_decode", "pamc_pair_distance",
     "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
-    "pamc_set_state", "pamc_checkpoint_size", "pamc_get_checkpoint", "pamc_set_checkpoint",
+    "pamc_set_state", "pamc_checkpoint_size", "pamc_get_checkpoint", "pamc_set_checkpoint", "pamc_autotune",
     "pamc_anneal_batch", "pamc_anneal_batch_noalloc", "pamc_server_create", "pamc_server_submit",
     "pamc_server_tick",
     "pamc_server_drain", "pamc_server_poll", "pamc_server_latency", "pamc_server_forget",
@@ -121,6 +121,12 @@ class pamc_result(C.Structure):
                 ("seconds_total", C.c_double), ("seconds_to_target", C.c_double)]
 
 
+class pamc_tune_result(C.Structure):
+    _fields_ = [("tile_sweeps", C.c_int32), ("tiles_per_wave", C.c_int32), ("quads_per_wave", C.c_int32),
+                ("candidates", C.c_int32), ("cached", C.c_int32), ("best_ms_per_sweep", C.c_double),
+                ("default_ms_per_sweep", C.c_double)]
+
+
 class pamc_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("finished", C.c_int64), ("failed", C.c_int64), ("ticks", C.c_int64),
                 ("steps", C.c_int64), ("request_steps", C.c_int64), ("prep_seconds", C.c_double),
@@ -185,6 +191,7 @@ def _load():
         "pamc_profile_read": [P, P, P, P, P],
         "pamc_synchronize": [P],
         "pamc_set_state": [P, P, P, P],
+        "pamc_autotune": [P, C.c_double, C.c_int32, C.c_int32, C.POINTER(pamc_tune_result)],
         "pamc_checkpoint_size": [P, C.POINTER(C.c_int64)],
         "pamc_get_checkpoint": [P, P, C.c_int64],
         "pamc_set_checkpoint": [P, P, C.c_int64],
@@ -371,6 +378,12 @@ def pamc_profile_read(h):
 
 def pamc_synchronize(h):
     _check(lib.pamc_synchronize(h))
+
+
+def pamc_autotune(h, beta, sweeps=4, force=False) -> pamc_tune_result:
+    r = pamc_tune_result()
+    _check(lib.pamc_autotune(h, float(beta), int(sweeps), int(bool(force)), C.byref(r)))
+    return r
 
 
 def pamc_set_state(h, spins, family=None, counters=None):
@@ -568,6 +581,9 @@ class Instance:
 
     def pair_distance(self):
         return pamc_pair_distance(self.h)
+
+    def autotune(self, beta, sweeps=4, force=False):
+        return pamc_autotune(self.h, beta, sweeps, force)
 
     def set_state(self, spins, family=None, counters=None):
         pamc_set_state(self.h, spins, family, counters)
