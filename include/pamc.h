@@ -225,6 +225,11 @@ typedef struct {
    * until the steps run reach steps (or M* reaches the target).  The trace
    * holds this call's steps at their absolute step indices. */
   int32_t resume;
+  /* > 0: record the population's mean normalised pair distance d_H (see
+   * pamc_pair_distance) every dh_every steps, after the step's sweeps
+   * (pamc_get_dh_trace).  Each sample compares all R(R-1)/2 pairs:
+   * O(R^2 n / 32) word reads. */
+  int32_t dh_every;
 } pamc_schedule;
 
 typedef struct {
@@ -284,6 +289,19 @@ pamc_status pamc_max3cut_decode(pamc_instance* inst, const int8_t* spins, int32_
 /* Mean normalised pairwise Hamming distance d_H = min(d, 1-d) over all
  * replica pairs (Supplement, Hamming distance).  Waits. */
 pamc_status pamc_pair_distance(pamc_instance* inst, double* mean);
+
+/* The distribution of d_H over all R(R-1)/2 replica pairs (the diversity
+ * histograms of the Supplement's Hamming-distance method): counts[nbins]
+ * receives the number of pairs with floor(2 nbins min(d, n-d) / n) = k
+ * (the last bin also takes d_H = 1/2), i.e. bins of width 1/(2 nbins) on
+ * [0, 1/2]; mean (may be NULL) the mean d_H.  1 <= nbins <= 4096; Ising
+ * spins only.  Waits. */
+pamc_status pamc_pair_distance_hist(pamc_instance* inst, int32_t nbins, int64_t* counts, double* mean);
+
+/* Per-step mean d_H of the last pamc_anneal run with dh_every > 0: dh
+ * (capacity entries) receives, per step, the mean over all pairs after the
+ * step's sweeps, or -1 on steps not sampled; *steps the number recorded. */
+pamc_status pamc_get_dh_trace(pamc_instance* inst, int32_t capacity, double* dh, int32_t* steps);
 
 /* ---------------------------------------------------------------------------
  * Checkpoint and resume.  A run of Algorithm 1 is a function of the

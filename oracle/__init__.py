@@ -42,7 +42,8 @@ class Schedule(C.Structure):
                 ("max_distinct_short", C.c_int32), ("max_distinct_long", C.c_int32),
                 ("reheat", C.c_double), ("tau", C.c_int32), ("n_top", C.c_int32),
                 ("mis_trials", C.c_int32), ("target", C.c_int64),
-                ("stop_at_target", C.c_int32), ("literal_break", C.c_int32), ("resume", C.c_int32)]
+                ("stop_at_target", C.c_int32), ("literal_break", C.c_int32), ("resume", C.c_int32),
+                ("dh_every", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -55,7 +56,8 @@ class Result(C.Structure):
 
 class Trace(C.Structure):
     _fields_ = [("mstar", C.POINTER(C.c_int64)), ("beta", C.POINTER(C.c_double)),
-                ("lnq", C.POINTER(C.c_double)), ("events", C.POINTER(C.c_int32))]
+                ("lnq", C.POINTER(C.c_double)), ("events", C.POINTER(C.c_int32)),
+                ("dh", C.POINTER(C.c_double))]
 
 
 class Ctrl(C.Structure):
@@ -183,7 +185,7 @@ def default_schedule(**kw) -> Schedule:
     s = Schedule(beta0=0.1, dbeta=0.02, steps=10, sweeps=1, z_rst=0, augmented=0, resample=1,
                  win_short=25, win_long=40, max_distinct_short=3, max_distinct_long=5,
                  reheat=0.8, tau=25, n_top=1, mis_trials=4, target=2**62,
-                 stop_at_target=0, literal_break=0, resume=0)
+                 stop_at_target=0, literal_break=0, resume=0, dh_every=0)
     for k, v in kw.items():
         setattr(s, k, v)
     return s
@@ -319,14 +321,16 @@ class Oracle:
         if trace:
             n = sched.steps
             arrays = (np.zeros(n, np.int64), np.zeros(n, np.float64), np.zeros(n, np.float64),
-                      np.zeros(n, np.int32))
+                      np.zeros(n, np.int32), np.full(n, -1.0))
             tr = Trace(arrays[0].ctypes.data_as(C.POINTER(C.c_int64)),
                        arrays[1].ctypes.data_as(C.POINTER(C.c_double)),
                        arrays[2].ctypes.data_as(C.POINTER(C.c_double)),
-                       arrays[3].ctypes.data_as(C.POINTER(C.c_int32)))
+                       arrays[3].ctypes.data_as(C.POINTER(C.c_int32)),
+                       arrays[4].ctypes.data_as(C.POINTER(C.c_double)))
         lib().orc_anneal(self._h, C.byref(sched), C.byref(res), C.byref(tr) if tr is not None else None)
         if trace:
-            return res, {"mstar": arrays[0], "beta": arrays[1], "lnq": arrays[2], "events": arrays[3]}
+            return res, {"mstar": arrays[0], "beta": arrays[1], "lnq": arrays[2], "events": arrays[3],
+                         "dh": arrays[4]}
         return res
 
     def max3cut_decode(self, spins):

@@ -978,6 +978,8 @@ void orc_anneal(orc* o, const orc_schedule* s, orc_result* res, orc_trace* tr) {
     }
     double beta_used = c->beta;
     orc_sweep(o, c->beta, s->sweeps);
+    if (tr && tr->dh && s->dh_every > 0)
+      tr->dh[step] = (step % s->dh_every == 0) ? orc_mean_pair_distance(o) : -1.0;
     int64_t m = orc_update_best(o);
     if (run->step_reached < 0 && m >= s->target) run->step_reached = step;
     ev |= orc_controller_step(c, s, m);

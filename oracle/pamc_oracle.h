@@ -61,6 +61,7 @@ typedef struct {
   int32_t literal_break;  /* 1: end the run where Algorithm 1 prints "break" */
   int32_t resume;         /* 1: continue the run the instance holds (controller,
                              M*, history, counts and steps run kept) */
+  int32_t dh_every;       /* > 0: record the mean pair distance every dh_every steps */
 } orc_schedule;
 
 typedef struct {
@@ -76,6 +77,7 @@ typedef struct {
   double* beta;       /* beta used for the sweeps of the step */
   double* lnq;        /* ln Q of the step's resampling (0 if none) */
   int32_t* events;    /* bit0 resampled, bit1 cluster move, bit2 strong, bit3 mild, bit4 restart */
+  double* dh;         /* mean pair distance after the step's sweeps (-1 if not sampled) */
 } orc_trace;
 
 /* ---- primitives exposed for pins ---- */

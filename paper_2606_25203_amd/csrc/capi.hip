@@ -97,7 +97,7 @@ void free_instance(pamc_instance* I) {
                   I->pop.H[0], I->pop.H[1], I->pop.E[0], I->pop.E[1], I->pop.fam[0],
                   I->pop.fam[1], I->best, I->to_internal_dev, I->st, I->thr, I->order,
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
-                  I->tr_lnq, I->tr_events, I->tr_time, I->m3_row_ptr, I->m3_col, I->m3_w,
+                  I->tr_lnq, I->tr_events, I->tr_time, I->tr_dh, I->m3_row_ptr, I->m3_col, I->m3_w,
                   I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Cd, I->Ed[0], I->Ed[1],
                   I->flip_ctr, I->H_scratch, I->ptab, I->g.hubJ, I->pop.HF[0], I->pop.HF[1]};
   for (void* p : ptrs) dev_free(I, p);
@@ -561,7 +561,7 @@ Schedule to_sched(const pamc_schedule* s) {
   d.stop_at_target = s->stop_at_target;
   d.literal_break = s->literal_break;
   d.resume = s->resume ? 1 : 0;
-  d.pad = 0;
+  d.dh_every = s->dh_every > 0 ? s->dh_every : 0;
   return d;
 }
 
@@ -605,6 +605,7 @@ pamc_status ensure_trace(pamc_instance* I, int32_t steps) {
   dfree(I, I->tr_lnq, I->tr_cap);
   dfree(I, I->tr_events, I->tr_cap);
   dfree(I, I->tr_time, I->tr_cap);
+  dfree(I, I->tr_dh, I->tr_cap);
   I->tr_cap = 0;
   I->self_dirty = true;
   hipError_t e = dalloc(I, &I->tr_mstar, steps);
@@ -612,12 +613,14 @@ pamc_status ensure_trace(pamc_instance* I, int32_t steps) {
   if (e == hipSuccess) e = dalloc(I, &I->tr_lnq, steps);
   if (e == hipSuccess) e = dalloc(I, &I->tr_events, steps);
   if (e == hipSuccess) e = dalloc(I, &I->tr_time, steps);
+  if (e == hipSuccess) e = dalloc(I, &I->tr_dh, steps);
   if (e != hipSuccess) {
     dfree(I, I->tr_mstar, steps);
     dfree(I, I->tr_beta, steps);
     dfree(I, I->tr_lnq, steps);
     dfree(I, I->tr_events, steps);
     dfree(I, I->tr_time, steps);
+    dfree(I, I->tr_dh, steps);
     return dev_fail(e, "alloc trace");
   }
   I->tr_cap = steps;
@@ -1171,6 +1174,7 @@ pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_resul
   SELF_BATCH(I, b);
   b->max_sweeps = std::max(s.sweeps, 1);
   b->any_cluster = cluster_possible(s);
+  b->any_dh = s.dh_every > 0 && b->dh.grid > 0;
   if (!I->d_sched) HIP_TRY(dev_alloc(I, &I->d_sched, sizeof(Schedule)), "alloc");
   HIP_TRY(hipMemcpyAsync(I->d_sched, &s, sizeof(Schedule), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::batch_anneal_setup(*b, (const Schedule*)I->d_sched, nullptr, 1), "anneal setup");
@@ -1707,6 +1711,37 @@ pamc_status pamc_autotune(pamc_instance* I, double beta, int32_t sweeps, int32_t
   return PAMC_OK;
 }
 
+pamc_status pamc_pair_distance_hist(pamc_instance* I, int32_t nbins, int64_t* counts, double* mean) {
+  if (!I || !counts) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  if (nbins < 1 || nbins > 4096) return fail(PAMC_ERR_INVALID_ARG, "nbins must lie in [1, 4096]");
+  if (I->dense) return fail(PAMC_ERR_UNSUPPORTED, "pair distance on dense instances");
+  if (I->potts_K) return fail(PAMC_ERR_UNSUPPORTED, "pair distance on Potts labels");
+  hipSetDevice(I->device);
+  int64_t* d = nullptr;
+  HIP_TRY(dev_alloc(I, (void**)&d, sizeof(int64_t) * (nbins + 1)), "alloc");
+  hipError_t e = pamc::launch_pair_hist(I, nbins, d, d + nbins);
+  int64_t sum = 0;
+  if (e == hipSuccess) e = hipStreamSynchronize(I->stream);
+  if (e == hipSuccess) e = hipMemcpy(counts, d, sizeof(int64_t) * nbins, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&sum, d + nbins, sizeof(int64_t), hipMemcpyDeviceToHost);
+  dev_free(I, d);
+  if (e != hipSuccess) return dev_fail(e, "pair distance histogram");
+  if (mean) *mean = I->R > 1 ? (double)sum / ((double)I->n * (0.5 * (double)I->R * (double)(I->R - 1))) : 0.0;
+  return PAMC_OK;
+}
+
+pamc_status pamc_get_dh_trace(pamc_instance* I, int32_t capacity, double* dh, int32_t* steps) {
+  if (!I || !dh) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
+  hipSetDevice(I->device);
+  pamc::RunState r;
+  pamc_status st = read_state(I, &r);
+  if (st) return st;
+  const int32_t k = (I->trace_ok && r.dh_every > 0) ? std::min(std::min(capacity, r.steps_run), I->tr_cap) : 0;
+  if (steps) *steps = k;
+  if (k > 0) HIP_TRY(hipMemcpy(dh, I->tr_dh, sizeof(double) * k, hipMemcpyDeviceToHost), "readback");
+  return PAMC_OK;
+}
+
 pamc_status pamc_profile_enable(pamc_instance* I, int32_t on) {
   if (!I) return fail(PAMC_ERR_INVALID_ARG, "NULL instance");
   hipSetDevice(I->device);
@@ -1908,7 +1943,7 @@ int64_t estimate_bytes(int32_t n, const int32_t* rp, const int32_t* w, const pam
   b += a(4 * (2 * X + 1));                                                     // threshold table
   b += a(4 * std::max<int64_t>(64, sc.sweeps) * ncls);                        // class orders
   b += a(4 * R) + a(8 * 512);                                                  // parents, counters
-  b += 3 * a(8 * (int64_t)std::max(sc.steps, 1)) + a(4 * (int64_t)std::max(sc.steps, 1)) +
+  b += 4 * a(8 * (int64_t)std::max(sc.steps, 1)) + a(4 * (int64_t)std::max(sc.steps, 1)) +
        a(8 * (int64_t)std::max(sc.steps, 1));                                  // trace
   if (sc.augmented && sc.resample && sc.n_top > 0 && sc.mis_trials > 0) {    // cluster scratch
     const int64_t t = std::min<int64_t>(sc.n_top, R);

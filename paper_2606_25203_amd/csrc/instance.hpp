@@ -97,6 +97,7 @@ struct pamc_instance {
   double* tr_lnq = nullptr;
   int32_t* tr_events = nullptr;
   uint64_t* tr_time = nullptr;
+  double* tr_dh = nullptr;  // mean pair distance per step (-1: not measured)
   int32_t tr_cap = 0;
   bool trace_ok = false;  // the trace describes the last run (not one without a trace)
   double clock_hz = 100e6;
@@ -138,7 +139,7 @@ struct Schedule {
   int32_t steps, sweeps, z_rst, augmented, resample;
   int32_t win_short, win_long, max_ds, max_dl, tau, n_top, mis_trials;
   int32_t stop_at_target, literal_break;
-  int32_t resume, pad;
+  int32_t resume, dh_every;
 };
 
 // Per-instance descriptor read by every batched kernel: the device pointers
@@ -173,6 +174,7 @@ struct Desc {
   double* tr_lnq;
   int32_t* tr_events;
   uint64_t* tr_time;
+  double* tr_dh;
   int64_t* flip_ctr;      // null unless profiling
   const int8_t *D0, *D1;  // dense instances: replica-major spins [R][np]
   double* ptab;           // Potts labels: e^{-beta d}, d = 0..table_x
@@ -193,7 +195,7 @@ struct Batch {
     uint64_t* map = nullptr;
     int32_t grid = 0;
   };
-  Launch init_spins, init_fields, thr, thr_dense, gather, cl_mis, cl_apply;
+  Launch init_spins, init_fields, thr, thr_dense, gather, cl_mis, cl_apply, dh;
   Launch sweep[kGroups];
   Launch tile[3];          // tile-resident sweeps, per coupling mode
   int64_t tile_lds = 0;    // their dynamic LDS bytes
@@ -201,7 +203,7 @@ struct Batch {
   int32_t n = 0;
   hipStream_t stream = nullptr;
   std::vector<pamc_instance*> I;
-  int32_t max_ncls = 0, max_sweeps = 1, any_cluster = 0;
+  int32_t max_ncls = 0, max_sweeps = 1, any_cluster = 0, any_dh = 0;
   int32_t group_ncls[kGroups] = {};  // most colour classes of an instance in each sweep group
   int64_t max_lds = 0;
   int32_t max_R = 0;  // most replicas of an instance (resampling LDS)
@@ -256,6 +258,9 @@ hipError_t launch_fields(Batch& b, int32_t buf, int32_t* H);
 hipError_t launch_load_population(Batch& b);
 hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
 hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
+// histogram of min(d, n - d) over all replica pairs into nbins bins of
+// [0, 1/2] (bin = floor(2 nbins min(d, n-d) / n), capped) plus its sum
+hipError_t launch_pair_hist(pamc_instance* I, int32_t nbins, int64_t* hist_dev, int64_t* sum_dev);
 int32_t cluster_max_n();
 int32_t sweep_waves();  // wavefronts per sweep work-group
 int32_t tile_max_quads();  // vertex quads a tile-resident sweep holds in LDS

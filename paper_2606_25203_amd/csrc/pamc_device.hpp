@@ -178,6 +178,9 @@ struct RunState {
   int32_t n_cluster_moves, n_reheats, n_reversals, n_restarts;
   int64_t flips, attempts, cl_flipped;
   uint64_t t_start, t_reached, t_last;  // device wall clock (100 MHz)
+  // population diversity: mean pair distance every dh_every steps (0: off)
+  int32_t dh_every, pad3;
+  int64_t dh_sum;  // sum over pairs of min(d, n - d) for the step being measured
 };
 
 }  // namespace pamc

@@ -963,6 +963,8 @@ __global__ void k_anneal_setup(const Desc* __restrict__ D, const Schedule* __res
   st->literal_break = s.literal_break;
   st->stopped = 0;
   st->active = 0;
+  st->dh_every = s.dh_every;
+  st->dh_sum = 0;
   st->t_start = wall_clock64();
   st->t_last = st->t_start;
   if (s.resume) {  // the run goes on from the controller it holds
@@ -1847,6 +1849,82 @@ __global__ void __launch_bounds__(256) k_pair_distance(const uint32_t* S0, const
   atomicAdd(out, acc);
 }
 
+// Number of spins in which replicas a and b differ, folded by the global flip:
+// min(d, n - d).  Spins are 0x01 / 0xFF bytes, so a byte of the xor is
+// nonzero iff the spins differ.
+__device__ __forceinline__ int32_t pair_dist(const uint32_t* S, int nq, int n, int a, int b) {
+  int dd = 0;
+  for (int q = 0; q < nq; ++q) {
+    const uint32_t x = S[((size_t)(a >> 6) * nq + q) * kLanes + (a & 63)];
+    const uint32_t y = S[((size_t)(b >> 6) * nq + q) * kLanes + (b & 63)];
+    uint32_t diff = x ^ y;
+    diff = (diff | (diff >> 1) | (diff >> 2) | (diff >> 3) | (diff >> 4) | (diff >> 5) | (diff >> 6) |
+            (diff >> 7)) & 0x01010101u;
+    dd += __popc(diff);
+  }
+  return dd < n - dd ? dd : n - dd;
+}
+
+// Work-group a: the pairs (a, b > a); histogram in LDS, then to memory.
+__global__ void __launch_bounds__(256) k_pair_hist(const uint32_t* S0, const uint32_t* S1, const RunState* st,
+                                                   int32_t n, int32_t nq, int32_t R, int32_t nbins,
+                                                   int64_t* hist, int64_t* sum) {
+  extern __shared__ int32_t hl[];
+  const uint32_t* S = st->cur ? S1 : S0;
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x) hl[i] = 0;
+  __syncthreads();
+  const int a = blockIdx.x;
+  int64_t acc = 0;
+  for (int b = a + 1 + threadIdx.x; b < R; b += blockDim.x) {
+    const int32_t dh = pair_dist(S, nq, n, a, b);
+    acc += dh;
+    const int bin = (int)min((int64_t)nbins - 1, (2 * (int64_t)nbins * dh) / n);
+    atomicAdd(&hl[bin], 1);
+  }
+  acc = wave_sum_i64(acc);
+  if ((threadIdx.x & 63) == 0 && acc)
+    __hip_atomic_fetch_add((unsigned long long*)sum, (unsigned long long)acc, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+    if (hl[i])
+      __hip_atomic_fetch_add((unsigned long long*)&hist[i], (unsigned long long)hl[i], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// In a run with a diversity trace: local block a of an instance sums
+// min(d, n - d) over the pairs (a, b > a) of the population just swept, on
+// the steps the trace samples.
+__global__ void __launch_bounds__(256) k_step_dh(const Desc* __restrict__ D, const uint64_t* __restrict__ map) {
+  int inst, a;
+  if (!resolve(map, inst, a)) return;
+  const Desc& d = D[inst];
+  RunState* st = d.st;
+  if (!st->active || st->dh_every <= 0 || st->step % st->dh_every != 0) return;
+  const uint32_t* S = st->cur ? d.S1 : d.S0;
+  int64_t acc = 0;
+  for (int b = a + 1 + threadIdx.x; b < d.R; b += blockDim.x) acc += pair_dist(S, d.nq, d.n, a, b);
+  acc = wave_sum_i64(acc);
+  if ((threadIdx.x & 63) == 0 && acc)
+    __hip_atomic_fetch_add((unsigned long long*)&st->dh_sum, (unsigned long long)acc, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The sampled step's mean d_H into the trace (-1 on steps not sampled).
+__global__ void k_step_dh_finish(const Desc* __restrict__ D, int32_t ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  const Desc& d = D[i];
+  RunState* st = d.st;
+  if (!st->active || st->dh_every <= 0) return;
+  const int step = st->step;
+  if (step < d.tr_cap && d.tr_dh) {
+    const double pairs = 0.5 * (double)d.R * (double)(d.R - 1);
+    d.tr_dh[step] = (step % st->dh_every == 0 && d.R > 1) ? (double)st->dh_sum / ((double)d.n * pairs) : -1.0;
+  }
+  st->dh_sum = 0;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1908,6 +1986,7 @@ Desc make_desc(const pamc_instance* I) {
   d.tr_lnq = I->tr_lnq;
   d.tr_events = I->tr_events;
   d.tr_time = I->tr_time;
+  d.tr_dh = I->tr_dh;
   d.flip_ctr = I->prof ? I->flip_ctr : nullptr;
   d.D0 = I->Sd;
   d.D1 = I->Sd2;
@@ -1955,7 +2034,7 @@ void Batch::free_device() {
   };
   release(d_desc);
   d_desc = nullptr;
-  Launch* all[] = {&init_spins, &init_fields, &thr, &thr_dense, &gather, &cl_mis, &cl_apply};
+  Launch* all[] = {&init_spins, &init_fields, &thr, &thr_dense, &gather, &cl_mis, &cl_apply, &dh};
   for (Launch* l : all) {
     release(l->map);
     l->map = nullptr;
@@ -2086,7 +2165,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
       }
     }
   }
-  std::vector<uint64_t> m_init, m_fields, m_thr, m_gather, m_mis, m_apply;
+  std::vector<uint64_t> m_init, m_fields, m_thr, m_gather, m_mis, m_apply, m_dh;
   std::vector<std::vector<uint64_t>> m_sweep(Batch::kGroups), m_tile(3);
   b.max_ncls = 0;
   for (int g = 0; g < Batch::kGroups; ++g) b.group_ncls[g] = 0;
@@ -2118,12 +2197,19 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
       b.max_lds = std::max<int64_t>(b.max_lds, (int64_t)I->np * 5);
     }
   }
-  if (scheds) {
-    for (int i = 0; i < b.n; ++i) {
+  // diversity samples: one work-group per replica.  A batch without
+  // schedules (an instance's own) keeps the map; its runs switch it on.
+  b.any_dh = 0;
+  for (int i = 0; i < b.n; ++i) {
+    if (scheds) {
       const Schedule& s = (*scheds)[i];
       b.max_sweeps = std::max(b.max_sweeps, s.sweeps);
       if (s.augmented && s.resample && s.n_top > 0 && s.mis_trials > 0) b.any_cluster = 1;
+      if (s.dh_every <= 0) continue;
     }
+    if (insts[i]->dense || insts[i]->potts_K) continue;
+    add_blocks(m_dh, i, insts[i]->R, false);
+    if (scheds) b.any_dh = 1;
   }
   hipError_t e = batch_alloc(b, (void**)&b.d_desc, sizeof(Desc) * b.n);
   if (e != hipSuccess) return e;
@@ -2143,6 +2229,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
   if ((e = up(m_gather, b.gather)) != hipSuccess) return e;
   if ((e = up(m_mis, b.cl_mis)) != hipSuccess) return e;
   if ((e = up(m_apply, b.cl_apply)) != hipSuccess) return e;
+  if ((e = up(m_dh, b.dh)) != hipSuccess) return e;
   for (int g = 0; g < Batch::kGroups; ++g)
     if ((e = up(m_sweep[g], b.sweep[g])) != hipSuccess) return e;
   for (int g = 0; g < 3; ++g)
@@ -2260,6 +2347,10 @@ hipError_t batch_step(Batch& b) {
   if (b.any_cluster) batch_cluster(b, false);
   hipError_t e = batch_sweeps(b, b.max_sweeps, 1);
   if (e != hipSuccess) return e;
+  if (b.any_dh && b.dh.grid) {  // diversity of the swept population, on sampled steps
+    k_step_dh<<<b.dh.grid, 256, 0, b.stream>>>(b.d_desc, b.dh.map);
+    k_step_dh_finish<<<tgrid(b.n), 64, 0, b.stream>>>(b.d_desc, b.n);
+  }
   k_step_end<<<b.n, 1024, 0, b.stream>>>(b.d_desc, 1);
   return hipGetLastError();
 }
@@ -2271,7 +2362,7 @@ hipError_t batch_step(Batch& b) {
 hipError_t batch_run_steps(Batch& b, int32_t k) {
   const char* ng = getenv("PAMC_NO_GRAPH");
   const bool no_graph = ng && atoi(ng) != 0;
-  const int64_t key = ((int64_t)b.max_sweeps << 1) | (b.any_cluster ? 1 : 0);
+  const int64_t key = ((int64_t)b.max_sweeps << 2) | (b.any_dh ? 2 : 0) | (b.any_cluster ? 1 : 0);
   bool use_graph = !no_graph && !b.arena && !b.I[0]->prof && !b.graph_failed && k > 1;
   if (use_graph && (!b.step_graph || b.graph_key != key)) {
     if (b.step_graph) hipGraphExecDestroy(b.step_graph);
@@ -2362,6 +2453,14 @@ hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev) 
   k_m3_decode<<<grid, 256, 0, I->stream>>>(spins_internal_dev, I->to_internal_dev, I->m3_n, I->m3_labels);
   k_m3_cut<<<grid, 256, 0, I->stream>>>(I->m3_labels, I->m3_n, I->m3_row_ptr, I->m3_col, I->m3_w,
                                         I->m3_cut);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_hist(pamc_instance* I, int32_t nbins, int64_t* hist_dev, int64_t* sum_dev) {
+  hipMemsetAsync(hist_dev, 0, sizeof(int64_t) * nbins, I->stream);
+  hipMemsetAsync(sum_dev, 0, sizeof(int64_t), I->stream);
+  k_pair_hist<<<I->R, 256, sizeof(int32_t) * nbins, I->stream>>>(I->pop.S[0], I->pop.S[1], I->st, I->n, I->nq, I->R,
+                                                                 nbins, hist_dev, sum_dev);
   return hipGetLastError();
 }
 

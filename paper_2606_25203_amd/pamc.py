@@ -32,6 +32,7 @@ EXPORTED = [
     "pamc_get_state", "pamc_get_trace", "pamc_max3cut_decode", "pamc_pair_distance",
     "pamc_profile_enable", "pamc_profile_read", "pamc_synchronize", "pamc_last_error",
     "pamc_set_state", "pamc_checkpoint_size", "pamc_get_checkpoint", "pamc_set_checkpoint", "pamc_autotune",
+    "pamc_pair_distance_hist", "pamc_get_dh_trace",
     "pamc_anneal_batch", "pamc_anneal_batch_noalloc", "pamc_server_create", "pamc_server_submit",
     "pamc_server_tick",
     "pamc_server_drain", "pamc_server_poll", "pamc_server_latency", "pamc_server_forget",
@@ -110,7 +111,7 @@ class pamc_schedule(C.Structure):
                 ("max_distinct_short", C.c_int32), ("max_distinct_long", C.c_int32),
                 ("reheat", C.c_double), ("tau", C.c_int32), ("n_top", C.c_int32),
                 ("mis_trials", C.c_int32), ("target", C.c_int64), ("stop_at_target", C.c_int32),
-                ("literal_break", C.c_int32), ("resume", C.c_int32)]
+                ("literal_break", C.c_int32), ("resume", C.c_int32), ("dh_every", C.c_int32)]
 
 
 class pamc_result(C.Structure):
@@ -144,7 +145,7 @@ def schedule(**kw) -> pamc_schedule:
     s = pamc_schedule(beta0=0.1, dbeta=0.02, steps=10, sweeps=1, z_rst=0, augmented=0, resample=1,
                       win_short=25, win_long=40, max_distinct_short=3, max_distinct_long=5,
                       reheat=0.8, tau=25, n_top=1, mis_trials=4, target=2**62, stop_at_target=0,
-                      literal_break=0, resume=0)
+                      literal_break=0, resume=0, dh_every=0)
     for k, v in kw.items():
         setattr(s, k, v)
     return s
@@ -192,6 +193,8 @@ def _load():
         "pamc_synchronize": [P],
         "pamc_set_state": [P, P, P, P],
         "pamc_autotune": [P, C.c_double, C.c_int32, C.c_int32, C.POINTER(pamc_tune_result)],
+        "pamc_pair_distance_hist": [P, C.c_int32, P, P],
+        "pamc_get_dh_trace": [P, C.c_int32, P, P],
         "pamc_checkpoint_size": [P, C.POINTER(C.c_int64)],
         "pamc_get_checkpoint": [P, P, C.c_int64],
         "pamc_set_checkpoint": [P, P, C.c_int64],
@@ -378,6 +381,20 @@ def pamc_profile_read(h):
 
 def pamc_synchronize(h):
     _check(lib.pamc_synchronize(h))
+
+
+def pamc_pair_distance_hist(h, nbins):
+    counts = np.zeros(int(nbins), np.int64)
+    mean = C.c_double()
+    _check(lib.pamc_pair_distance_hist(h, int(nbins), _ptr(counts), C.byref(mean)))
+    return counts, mean.value
+
+
+def pamc_get_dh_trace(h, capacity):
+    dh = np.zeros(int(capacity), np.float64)
+    k = C.c_int32()
+    _check(lib.pamc_get_dh_trace(h, int(capacity), _ptr(dh), C.byref(k)))
+    return dh[:k.value]
 
 
 def pamc_autotune(h, beta, sweeps=4, force=False) -> pamc_tune_result:
@@ -581,6 +598,12 @@ class Instance:
 
     def pair_distance(self):
         return pamc_pair_distance(self.h)
+
+    def pair_distance_hist(self, nbins):
+        return pamc_pair_distance_hist(self.h, nbins)
+
+    def dh_trace(self, capacity):
+        return pamc_get_dh_trace(self.h, capacity)
 
     def autotune(self, beta, sweeps=4, force=False):
         return pamc_autotune(self.h, beta, sweeps, force)

@@ -494,3 +494,61 @@ def test_tile_resident_largest_and_mixed_batch(pamc):
         assert r.best_cut == ores.best_cut
         same_state(inst_, o, "mixed batch")
         inst_.close()
+
+
+def expected_hist(dists, n, nbins):
+    """Bins of d_H = min(d, n - d)/n as the library documents them:
+    floor(2 nbins min(d, n - d) / n), the last bin also taking d_H = 1/2."""
+    dd = np.rint(np.asarray(dists) * n).astype(np.int64)
+    return np.bincount(np.minimum(nbins - 1, (2 * nbins * dd) // n), minlength=nbins).astype(np.int64)
+
+
+@pytest.mark.parametrize("fields", FIELDS)
+@pytest.mark.parametrize("nbins", [1, 7, 64])
+def test_pair_distance_histogram(pamc, fields, nbins):
+    """Distribution of d_H over all R(R-1)/2 pairs (Supplement, Hamming
+    distance): integer bin counts equal to those of the oracle's pair
+    distances, on a population with copies (distance 0) after resampling."""
+    g = synth.random_graph(333, 2400, 5)
+    R = 192
+    say(f"case pair distance histogram fields={fields} nbins={nbins}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=13, fields=fields)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 13)
+    for beta, delta in ((0.6, 0.4), (1.5, 0.5)):
+        inst.sweep(beta, 3)
+        o.sweep(beta, 3)
+        inst.resample(delta)
+        o.resample(delta)
+    same_state(inst, o, "histogram")
+    counts, mean = inst.pair_distance_hist(nbins)
+    want = expected_hist(o.pair_distances(), g.n, nbins)
+    assert np.array_equal(counts, want), (counts, want)
+    assert counts.sum() == R * (R - 1) // 2
+    assert close_lnq(mean, o.mean_pair_distance())
+    inst.close()
+
+
+@pytest.mark.parametrize("fields", FIELDS)
+def test_diversity_trace_matches_oracle(pamc, fields):
+    """Per-step mean d_H of the swept population on every third step of an
+    augmented run (reheats, cluster moves and a restart in between), -1 on
+    the others, against the oracle's trace; 1e-12 relative."""
+    g = synth.torus(24, 20, 5)
+    say(f"case diversity trace fields={fields}")
+    kw = dict(beta0=0.1, dbeta=0.02, steps=200, sweeps=3, augmented=1, z_rst=120, n_top=8, mis_trials=4,
+              tau=25, dh_every=3)
+    inst = pamc.Instance.csr(g, replicas=128, seed=99, fields=fields)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 128, 99)
+    res, ores = compare_anneal(pamc, inst, o, kw)
+    k = ores.steps_run
+    _, otr = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 128, 99).anneal(
+        oracle.default_schedule(**kw), trace=True)
+    dh = inst.dh_trace(kw["steps"])
+    assert len(dh) == k
+    want = otr["dh"][:k]
+    assert np.array_equal(dh < 0, want < 0) and np.all(want[::3] >= 0) and np.all(want[1::3] < 0)
+    assert all(close_lnq(a, b) for a, b in zip(dh[::3], want[::3]))
+    # a run without the trace records none
+    inst.anneal(pamc.schedule(beta0=0.1, dbeta=0.02, steps=5, sweeps=1))
+    assert len(inst.dh_trace(5)) == 0
+    inst.close()

@@ -571,6 +571,34 @@ def test_pair_distance_global_flip_symmetry(oracle_lib):
     assert o.mean_pair_distance() == 0.0
 
 
+def test_diversity_trace_of_independent_random_chains(oracle_lib):
+    """At beta = 0 the heat-bath rule flips each spin with probability 1/2,
+    so without resampling every sampled population is R independent uniform
+    configurations and E[d_H] = E[min(d, n - d)] / n with d ~ Binomial(n, 1/2),
+    summed exactly.  Sampled steps follow dh_every, the others hold -1, and
+    the steps' average lies within 6 standard errors (pairs of one step are
+    correlated, which the bound over steps allows for)."""
+    n, R, steps = 200, 64, 40
+    g = synth.random_graph(n, 600, 9)
+    o = oracle_lib.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 21)
+    _, tr = o.anneal(oracle_lib.default_schedule(beta0=0.0, dbeta=0.0, steps=steps, sweeps=2, resample=0,
+                                                 dh_every=2), trace=True)
+    dh = tr["dh"]
+    assert np.all(dh[1::2] == -1.0) and np.all(dh[0::2] >= 0)
+    want = sum(math.comb(n, d) * min(d, n - d) for d in range(n + 1)) / 2 ** n / n
+    assert want == pytest.approx(0.5 - math.sqrt(n / (2 * math.pi)) / n, abs=2e-3)
+    got = dh[0::2]
+    se = np.std(got, ddof=1) / math.sqrt(len(got))
+    assert abs(got.mean() - want) < max(6 * se, 1e-3), (got.mean(), want, se)
+    # a sample is the population right after the step's sweeps: one step
+    o1 = oracle_lib.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 21)
+    _, t1 = o1.anneal(oracle_lib.default_schedule(beta0=0.7, dbeta=0.1, steps=1, sweeps=3, dh_every=1),
+                      trace=True)
+    o2 = oracle_lib.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 21)
+    o2.sweep(0.7, 3)
+    assert t1["dh"][0] == o2.mean_pair_distance()
+
+
 def test_invalid_inputs_rejected(oracle_lib):
     g = synth.random_graph(20, 40, 1)
     bad = g.col.copy()
