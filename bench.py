@@ -17,14 +17,15 @@ reported as final_3cuts); c4p / c4c = the same graph with 3-state Potts
 labels (softmax-perturbed argmax / cascaded p-bits).
 
 Printed (one JSON line): flip attempts per second over the timed runs,
-time-to-target p50/p99 (target = median final best cut of the timed runs),
+time-to-target p50/p99 and TTS (Eq. 5) against the workload's recorded
+target cut (paper_2606_25203_amd/targets.json; else the median final best
+cut of the timed runs),
 the dominant kernel's roofline position measured with HIP events around
 every launch of it, and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -34,9 +35,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2606_25203_amd.tts import recorded_target, scan as tts_scan  # noqa: E402
+from paper_2606_25203_amd.workloads import make_instance, workload  # noqa: E402
+
 HBM_PEAK_GBS = 8000.0
 MFMA_I8_PEAK_TOPS = 5000.0
-CSRC = os.path.join(ROOT, "paper_2606_25203_amd", "csrc")
 
 
 def log(*a):
@@ -52,31 +55,23 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def tts99(hit_times, n_runs):
-    """Eq. 5: TTS(T) = T ln(1 - 0.99) / ln(1 - P_s(T)) with P_s(T) the
-    fraction of runs that reached the target within T (device time from the
-    start of the run), minimised over the observed hit times T.  None when no
-    run reached the target."""
-    best = None
-    for T in sorted(hit_times):
-        ps = sum(1 for t in hit_times if t <= T) / n_runs
-        tts = T if ps >= 0.99 else T * math.log(0.01) / math.log(1.0 - ps)
-        best = tts if best is None else min(best, tts)
-    return best
+def survey_bytes_per_attempt(p_flip: float, degree: float) -> float:
+    """Algorithmic HBM bytes of one (replica, vertex) visit of a sparse sweep
+    in the incremental-field layout (the reference model of the method's
+    data movement): read the spin (1 B) and the field (4 B); on a flip
+    (probability p) write the spin (1 B) and read-modify-write every
+    neighbour's int32 field (8 B each); the CSR row (column + coupling,
+    8 B per neighbour) is shared by the 64 lanes of a wavefront.  The
+    gathered-field kernel computes the same fields from the spins instead,
+    so its measured traffic (`traffic`) is below this."""
+    return 5.0 + p_flip * (1.0 + 8.0 * degree) + 8.0 * degree / 64.0
 
 
-def sweep_bytes_per_attempt(p_flip: float, degree: float, pull: bool) -> float:
-    """Algorithmic HBM bytes of one (replica, vertex) visit of the sparse sweep.
-    Incremental fields (push): read the spin (1 B) and the field (4 B); on a
-    flip (probability p) write the spin (1 B) and read-modify-write every
-    neighbour field (8 B each).  Gathered fields (pull): read the spin (1 B)
-    and, over a sweep, every other spin once more as a neighbour (1 B); write
-    the spin on a flip.  The CSR row (column + coupling, 8 B per neighbour)
-    is shared by the 64 lanes of a wavefront in both."""
-    csr = 8.0 * degree / 64.0
-    if pull:
-        return 2.0 + p_flip + csr
-    return 5.0 + p_flip * (1.0 + 8.0 * degree) + csr
+def pull_bytes_per_attempt(p_flip: float, degree: float) -> float:
+    """Bytes the gathered-field kernel needs at least: read the spin (1 B),
+    every spin once more as a neighbour (1 B), write the spin on a flip, and
+    the CSR row shared by a wavefront."""
+    return 2.0 + p_flip + 8.0 * degree / 64.0
 
 
 VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12   # 39.3 T int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
@@ -109,67 +104,24 @@ def potts_slots_per_attempt(degree: float, K: int, X: int) -> float:
     return 126.5 + per_entry * 4.0 * math.ceil(degree / 4.0)
 
 
-def counters_traffic(name: str, src: str):
-    """HBM bytes per launch from a committed rocprofv3 FETCH/WRITE pass, or
-    None if the kernel source changed since the counters were taken."""
+def counters(name: str, src: str, kernel: str):
+    """Per-dispatch hardware counters of one kernel from a committed
+    rocprofv3 summary (profiles/<name>_counters.json, made by
+    paper_2606_25203_amd/counters_summary.py): HBM bytes (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy kernel of known size), the SQ counters taken
+    and, for the sweep kernel, the attempts per dispatch.  None if the
+    summary is missing or the kernel sources changed since the counters
+    were taken."""
+    from paper_2606_25203_amd.profile_kernels import kernel_source_sha256
     path = os.path.join(ROOT, "profiles", f"{name}_counters.json")
     try:
         with open(path) as f:
             c = json.load(f)
-        sha = hashlib.sha256(open(os.path.join(CSRC, src), "rb").read()).hexdigest()
-        if c.get("source_sha256") != sha:
+        if c.get("facts", {}).get("source_sha256") != kernel_source_sha256(src):
             return None
-        return c["hbm_bytes_per_launch"]
+        return c["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None
-
-
-# ----------------------------------------------------------------- workloads
-def workload(name):
-    import synth
-    if name == "c2":
-        g = synth.torus(100, 200, seed=1)
-        return dict(kind="csr", graph=g, R=4096, steps=500, sweeps=10,
-                    sched=dict(beta0=0.1, dbeta=0.02, steps=500, sweeps=10, augmented=1, z_rst=400, n_top=128,
-                               mis_trials=4, tau=25),
-                    desc="augmented PAMC, 100x200 torus +-1 weights (n=20000, degree 4), R=4096, "
-                         "500 beta steps x 10 sweeps",
-                    counters="sweep_torus100x200_R4096", cpu=dict(R=64, step_s=1.2))
-    if name == "c1":
-        g = synth.random_graph(800, 19176, seed=1)
-        return dict(kind="csr", graph=g, R=256, steps=50, sweeps=5,
-                    sched=dict(beta0=0.1, dbeta=2.9 / 49, steps=50, sweeps=5),
-                    desc="plain PAMC, random graph n=800 m=19176 w=+1, R=256, 50 beta steps 0.1->3.0 x 5 sweeps",
-                    counters="sweep_gnm800_R256", cpu=dict(R=256, step_s=0.3))
-    if name == "c3":
-        n = 100_000
-        return dict(kind="dense", n=n, R=256, steps=200, sweeps=1,
-                    sched=dict(beta0=0.1 / math.sqrt(n), dbeta=2.9 / math.sqrt(n) / 199, steps=200, sweeps=1),
-                    desc="plain PAMC, dense +-1 Ising n=100000 (int8 J, 10 GB), R=256, "
-                         "200 beta steps 0.1/sqrt(n)->3.0/sqrt(n) x 1 sweep",
-                    counters="dense_gemm_n100000_R256", cpu=None)
-    if name == "c4":
-        g = synth.random_graph(7000, 21000, seed=1)
-        return dict(kind="max3cut", graph=g, R=2048, steps=300, sweeps=10,
-                    sched=dict(beta0=0.1, dbeta=0.02, steps=300, sweeps=10, augmented=1, z_rst=400, n_top=64,
-                               mis_trials=4, tau=25),
-                    desc="augmented PAMC, Max-3-Cut one-hot embedding of G(7000, 21000) (n=21001), R=2048, "
-                         "300 beta steps x 10 sweeps",
-                    counters="sweep_max3cut7000_R2048", cpu=dict(R=64, step_s=1.5))
-    if name in ("c4p", "c4c"):
-        # the paper's own Max-3-Cut formulation on C4's graph: one 3-state
-        # Potts label per vertex (n = 7000 instead of the embedding's 21001)
-        g = synth.random_graph(7000, 21000, seed=1)
-        cascade = name == "c4c"
-        return dict(kind="potts", graph=g, K=3, potts_rule=1 if cascade else 0, gamma=0.0 if cascade else 1.0,
-                    R=2048, steps=300, sweeps=10,
-                    sched=dict(beta0=0.1, dbeta=0.02, steps=300, sweeps=10, augmented=1, z_rst=400, n_top=64,
-                               mis_trials=4, tau=25),
-                    desc="augmented PAMC, Max-3-Cut with 3-state Potts labels (" +
-                         ("cascaded p-bit sampler" if cascade else "softmax-perturbed argmax, gamma=1") +
-                         ") on G(7000, 21000), R=2048, 300 beta steps x 10 sweeps",
-                    counters="sweep_potts7000_R2048", cpu=dict(R=64, step_s=0.6))
-    raise SystemExit(f"unknown workload {name}")
 
 
 def cpu_baseline(w, seconds_budget: float):
@@ -203,14 +155,6 @@ def cpu_baseline(w, seconds_budget: float):
 BATCH_SEEDS = {"c1": 256, "c2": 8, "c4": 16}
 
 
-def make_instance(pamc, w, seed, fields=None):
-    if w["kind"] == "csr":
-        return pamc.Instance.csr(w["graph"], replicas=w["R"], seed=seed, fields=fields)
-    if w["kind"] == "max3cut":
-        return pamc.Instance.max3cut(w["graph"], replicas=w["R"], seed=seed, fields=fields)
-    raise SystemExit("batched runs take sparse workloads")
-
-
 def bench_batched(pamc, torch, name, count=None):
     """The same set of runs (one instance, count seeds) made one after the
     other through pamc_anneal and together through pamc_anneal_batch;
@@ -221,6 +165,9 @@ def bench_batched(pamc, torch, name, count=None):
     seeds = list(range(1000, 1000 + count))
     insts = [make_instance(pamc, w, s) for s in seeds]
     n = insts[0].info().n
+    tune = insts[0].autotune(w["sched"]["beta0"] + w["sched"]["dbeta"] * w["steps"] / 2, sweeps=2)
+    for i in insts[1:]:  # the same shape: the tuner's cached choice
+        i.autotune(0.5)
     # warm-up of both paths on the first instance
     insts[0].anneal(sched)
     pamc.anneal_batch(insts[:2], [sched] * 2)
@@ -246,6 +193,8 @@ def bench_batched(pamc, torch, name, count=None):
     return {"workload": w["desc"], "runs": count, "plain_attempts_per_s": att / t_plain,
             "batched_attempts_per_s": att / t_batch, "speedup": t_plain / t_batch,
             "plain_s": t_plain, "batched_s": t_batch, "identical_results": same,
+            "autotuned_shape": {"tile_sweeps": tune.tile_sweeps, "tiles_per_wave": tune.tiles_per_wave,
+                                "quads_per_wave": tune.quads_per_wave},
             "cuts": sorted(r.best_cut for r in batched)[count // 2]}
 
 
@@ -280,6 +229,8 @@ def bench_served(pamc, torch, count, budget_gb=16.0, slots=256, tick_steps=8, se
         plain[q.index] = inst.anneal(sched).best_cut
         inst.close()
         service.append(time.perf_counter() - t1)
+        if len(service) % 250 == 0:
+            log(f"served bench: plain {len(service)} of {count} requests")
     t_plain = time.perf_counter() - t0
     log(f"served bench: plain {count} requests in {t_plain:.2f} s")
     out = {"requests": count, "replicas": R, "beta_steps": C5_SCHED["steps"], "sweeps": C5_SCHED["sweeps"],
@@ -300,8 +251,12 @@ def bench_served(pamc, torch, count, budget_gb=16.0, slots=256, tick_steps=8, se
         tickets = {}
         t0 = time.perf_counter()
         nxt = 0
+        t_log = 0.0
         while True:
             now = time.perf_counter() - t0
+            if now - t_log > 20.0:
+                t_log = now
+                log(f"served bench: {mode} {nxt} of {count} submitted at {now:.0f} s")
             while nxt < count and arrivals[nxt] <= now:
                 q = reqs[nxt]
                 tickets[srv.submit(q.graph, q.seed, sched)] = q.index
@@ -369,18 +324,11 @@ def main():
 
     import torch
     from paper_2606_25203_amd import pamc
+    from paper_2606_25203_amd.profile_kernels import sweep_kernel
 
     w = workload(args.workload)
     fields = None if args.fields == "auto" else args.fields
-    if w["kind"] == "csr":
-        inst = pamc.Instance.csr(w["graph"], replicas=w["R"], seed=0, fields=fields)
-    elif w["kind"] == "max3cut":
-        inst = pamc.Instance.max3cut(w["graph"], replicas=w["R"], seed=0, fields=fields)
-    elif w["kind"] == "potts":
-        inst = pamc.Instance.potts(w["graph"], w["K"], replicas=w["R"], seed=0, potts_rule=w["potts_rule"],
-                                   gamma=w["gamma"])
-    else:
-        inst = pamc.Instance.dense_random(w["n"], 1, replicas=w["R"], seed=0)
+    inst = make_instance(pamc, w, 0, fields=fields)
     info = inst.info()
     n = info.n
     sched = pamc.schedule(**w["sched"])
@@ -410,7 +358,12 @@ def main():
     attempts = sum(r.steps_run for r, _ in runs) * w["sweeps"] * n * w["R"]
     finals = [r.best_cut for r, _ in runs]
     finals3 = [c for c in decoded] if decoded else None
-    target = int(percentile(finals, 0.5))
+    # the workload's recorded target (the plain path's median final M* over
+    # fixed seeds, paper_2606_25203_amd/targets.json), else these runs' median
+    target = recorded_target(args.workload)
+    target_source = "recorded (paper_2606_25203_amd/targets.json)"
+    if target is None:
+        target, target_source = int(percentile(finals, 0.5)), "median final best cut of the timed runs"
     ttt = []
     for res, tr in runs:
         hit = [t for m, t in zip(tr["mstar"], tr["seconds"]) if m >= target]
@@ -431,39 +384,61 @@ def main():
         achieved = ops / (launch_ms * 1e-3) / 1e12
         roof = {"kernel": "k_dense_step (+ k_dense_gemm)", "bound": "mfma", "achieved": achieved,
                 "peak": MFMA_I8_PEAK_TOPS, "unit": "TOP/s (int8)", "frac": achieved / MFMA_I8_PEAK_TOPS,
-                "traffic": counters_traffic(w["counters"], "dense.hip"), "launch_ms": launch_ms,
-                "launches": prof["launches"], "ops_per_launch": ops, "flip_rate": p_flip}
+                "traffic": None, "launch_ms": launch_ms, "launches": prof["launches"], "ops_per_launch": ops,
+                "flip_rate": p_flip}
+        step_c = counters(w["counters"], "dense.hip", "k_dense_step<0>")
+        gemm_c = counters(w["counters"], "dense.hip", "k_dense_gemm")
+        if step_c and gemm_c:
+            # one launch unit = one k_dense_step and one k_dense_gemm dispatch
+            roof["traffic"] = step_c["hbm_bytes_per_dispatch"] + gemm_c["hbm_bytes_per_dispatch"]
+            roof["traffic_gbs"] = roof["traffic"] / (launch_ms * 1e-3) / 1e9
+            roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS
+            mops = step_c.get("SQ_INSTS_VALU_MFMA_MOPS_I8", 0.0) + gemm_c.get("SQ_INSTS_VALU_MFMA_MOPS_I8", 0.0)
+            roof["counter_mfma_ops_per_launch"] = 512.0 * mops  # the counter counts units of 512 ops
     else:
         degree = info.nnz / n
         pull = bool(info.pull)
-        bpa = sweep_bytes_per_attempt(p_flip, degree, pull)
         apl = prof["attempts"] / max(prof["launches"], 1)
         rate = apl / (launch_ms * 1e-3)
-        hbm = bpa * rate / 1e9
         shape = {"tiles_per_wave": info.tiles_per_wave, "quads_per_wave": info.quads_per_wave,
-                 "coupling_mode": info.coupling_mode}
+                 "coupling_mode": info.coupling_mode, "tile_sweeps": info.tile_sweeps, "hubs": info.hubs}
+        kname = sweep_kernel(info, w["kind"] == "potts")
         if w["kind"] == "potts":
             slots = potts_slots_per_attempt(degree, info.potts_K, info.X)
             achieved = slots * rate / 1e12
-            roof = {"kernel": "k_sweep_potts<3>", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
+            roof = {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
                     "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
-                    "alu_slots_per_attempt": slots, "hbm_algorithmic_gbs": hbm,
-                    "hbm_algorithmic_frac": hbm / HBM_PEAK_GBS}
-        elif pull:
-            # issue-bound: vector ALU slots per attempt (see alu_slots_per_attempt)
-            slots = alu_slots_per_attempt(degree, info.coupling_mode)
-            achieved = slots * rate / 1e12
-            roof = {"kernel": "k_sweep_pull", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
-                    "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
-                    "alu_slots_per_attempt": slots, "hbm_algorithmic_gbs": hbm,
-                    "hbm_algorithmic_frac": hbm / HBM_PEAK_GBS}
+                    "alu_slots_per_attempt": slots}
         else:
-            roof = {"kernel": "k_sweep_push", "bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS}
-        roof.update({"traffic": counters_traffic(w["counters"], "sparse.hip"), "launch_ms": launch_ms,
-                     "launches": prof["launches"], "attempts_per_launch": apl, "flip_rate": p_flip,
-                     "algorithmic_bytes_per_attempt": bpa, "fields": "pull" if pull else "push",
+            # achieved = the algorithmic bytes of the visits one launch makes
+            # (incremental-field layout) over the launch's measured duration
+            b_alg = survey_bytes_per_attempt(p_flip, degree)
+            achieved = b_alg * rate / 1e9
+            roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_attempt": b_alg,
+                    "algorithmic_model": "5 + p(1 + 8 deg) + 8 deg / 64 bytes per attempt"}
+            if pull:
+                slots = alu_slots_per_attempt(degree, info.coupling_mode)
+                roof["alu_model"] = {"slots_per_attempt": slots, "achieved_tslots": slots * rate / 1e12,
+                                     "peak_tslots": VALU_PEAK_TSLOTS,
+                                     "frac": slots * rate / 1e12 / VALU_PEAK_TSLOTS,
+                                     "kernel_min_bytes_per_attempt": pull_bytes_per_attempt(p_flip, degree)}
+        roof.update({"traffic": None, "launch_ms": launch_ms, "launches": prof["launches"],
+                     "attempts_per_launch": apl, "flip_rate": p_flip, "fields": "pull" if pull else "push",
                      "kernel_shape": shape, "attempts_per_s_in_kernel": rate})
+        c = counters(w["counters"], "sparse.hip", kname)
+        if c and "hbm_bytes_per_dispatch" in c:
+            # measured bytes per dispatch of the counted sweeps (at the
+            # profiling driver's temperature), scaled to this run's launches
+            roof["traffic"] = c["hbm_bytes_per_dispatch"] * apl / c.get("attempts_per_dispatch", apl)
+            roof["traffic_gbs"] = roof["traffic"] / (launch_ms * 1e-3) / 1e9
+            roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS
+            roof["traffic_bytes_per_attempt"] = roof["traffic"] / apl
+            if "SQ_INSTS_VALU" in c and c.get("mean_dispatch_ns_under_counters"):
+                # VALU wave-instructions per CU and cycle (one per cycle is the
+                # issue limit of a CU's four SIMDs for wave64 instructions)
+                cyc = c["mean_dispatch_ns_under_counters"] * 1e-9 * 2.4e9
+                roof["counter_valu_issue_frac"] = c["SQ_INSTS_VALU"] / (256 * cyc)
     out = {
         "metric": "spin-flip attempts/s + time-to-target-cut (plain vs batched/served), p50/p99",
         "value": attempts / wall,
@@ -481,7 +456,9 @@ def main():
                    "sweeps": w["sweeps"], "mode": "plain (one instance per launch sequence)",
                    "parallelism": "1 GPU"},
         "time_to_target": {"target_cut": target, "p50_s": percentile(ttt, 0.5), "p99_s": percentile(ttt, 0.99),
-                           "success_fraction": len(ttt) / len(runs), "tts99_s": tts99(ttt, len(runs)),
+                           "success_fraction": len(ttt) / len(runs),
+                           "tts99_s": (tts_scan(ttt, len(runs))[1] or (None, None, None))[2],
+                           "target_source": target_source,
                            "final_cuts": finals},
         **({"final_3cuts": finals3} if finals3 else {}),
         "roofline": roof,

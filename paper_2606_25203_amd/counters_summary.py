@@ -3,10 +3,15 @@
 into per-kernel means, scaled to bytes with a copy-kernel calibration.
 
 Usage: counters_summary.py OUT.json --copy-fetch DIR --copy-write DIR
-           --pass NAME=DIR[:SKIP] [--pass ...] [--note TEXT] [--command TEXT ...]
+           --pass NAME=DIR [--pass ...] [--extra FACTS.json] [--note TEXT]
+           [--command TEXT ...]
 
-SKIP drops each kernel's first SKIP dispatches of that pass (the settling
-sweeps the profiling driver makes before the counted ones).
+The profiling driver settles its population, idles for a second, then makes
+the counted sweeps: dispatches before the first gap of at least half a
+second between dispatch starts are left out (a pass with no such gap is
+taken whole).  FACTS.json (the driver's own output) names the sweep kernel
+and the attempts of the counted sweeps; that kernel gets the attempts per
+dispatch.
 
 FETCH_SIZE and WRITE_SIZE are reported by the profiler in KiB per
 dispatch; the calibration passes ran an elementwise int32 copy that reads
@@ -23,28 +28,37 @@ import statistics
 
 
 def short(name):
-    name = name.split("(pamc::")[0].split("(int,")[0]
+    """The kernel's name and template arguments, without namespace, return
+    type or argument list."""
     for p in ("void ", "pamc::(anonymous namespace)::"):
         name = name.replace(p, "")
+    depth = 0
+    for i, ch in enumerate(name):
+        depth += (ch == "<") - (ch == ">")
+        if ch == "(" and depth == 0:
+            return name[:i].strip()
     return name.strip()
 
 
-def load(d, skip=0):
+GAP_NS = 500_000_000
+
+
+def load(d):
     files = glob.glob(os.path.join(d, "*_counter_collection.csv"))
     if not files:
         raise SystemExit(f"no counter CSV under {d}")
     rows = sorted(csv.DictReader(open(files[0])), key=lambda r: int(r["Dispatch_Id"]))
-    seen = collections.defaultdict(list)  # kernel -> dispatch ids in order
-    for row in rows:
-        k = short(row["Kernel_Name"])
-        if row["Dispatch_Id"] not in seen[k]:
-            seen[k].append(row["Dispatch_Id"])
-    keep = {k: set(ids[skip:]) for k, ids in seen.items()}
+    starts = sorted({(int(r["Start_Timestamp"]), r["Dispatch_Id"]) for r in rows})
+    first = None  # the first dispatch after the settling gap
+    for (t0, _), (t1, i1) in zip(starts, starts[1:]):
+        if t1 - t0 >= GAP_NS:
+            first = t1
+            break
     per = collections.defaultdict(lambda: collections.defaultdict(list))
     dur = collections.defaultdict(dict)
     for row in rows:
         k = short(row["Kernel_Name"])
-        if row["Dispatch_Id"] not in keep[k]:
+        if first is not None and int(row["Start_Timestamp"]) < first:
             continue
         per[k][row["Counter_Name"]].append(float(row["Counter_Value"]))
         dur[k][row["Dispatch_Id"]] = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
@@ -59,7 +73,7 @@ def main():
     ap.add_argument("--pass", dest="passes", action="append", default=[])
     ap.add_argument("--note", default="")
     ap.add_argument("--command", action="append", default=[], help="a command that made the passes")
-    ap.add_argument("--extra", default=None, help="JSON file of further facts to record (flip rates, ...)")
+    ap.add_argument("--extra", default=None, help="the profiling driver's JSON output (kernel, attempts, ...)")
     a = ap.parse_args()
     cf, _ = load(a.copy_fetch)
     cw, _ = load(a.copy_write)
@@ -70,11 +84,7 @@ def main():
     kernels = collections.defaultdict(dict)
     for spec in a.passes:
         name, d = spec.split("=", 1)
-        skip = 0
-        if ":" in d:
-            d, sk = d.rsplit(":", 1)
-            skip = int(sk)
-        per, dur = load(d, skip)
+        per, dur = load(d)
         for k, ctrs in per.items():
             e = kernels[k]
             for c, xs in ctrs.items():
@@ -88,8 +98,14 @@ def main():
             e["hbm_write_bytes_per_dispatch"] = e["WRITE_SIZE"] * 1024 * write_scale
         if "FETCH_SIZE" in e and "WRITE_SIZE" in e:
             e["hbm_bytes_per_dispatch"] = e["hbm_fetch_bytes_per_dispatch"] + e["hbm_write_bytes_per_dispatch"]
-    out = {"note": a.note, "commands": a.command,
-           **({"facts": json.load(open(a.extra))} if a.extra else {}),
+    facts = json.load(open(a.extra)) if a.extra else {}
+    main_k = facts.get("kernel")
+    if main_k in kernels and facts.get("attempts"):
+        kernels[main_k]["attempts_per_dispatch"] = facts["attempts"] / kernels[main_k]["dispatches"]
+        if "hbm_bytes_per_dispatch" in kernels[main_k]:
+            kernels[main_k]["hbm_bytes_per_attempt"] = (kernels[main_k]["hbm_bytes_per_dispatch"] /
+                                                        kernels[main_k]["attempts_per_dispatch"])
+    out = {"note": a.note, "commands": a.command, "facts": facts,
            "copy_calibration": {"kernel": cfk[:80], "bytes_read": 1 << 30, "bytes_written": 1 << 30,
                                 "FETCH_SIZE_KiB": statistics.mean(cf[cfk]["FETCH_SIZE"]),
                                 "WRITE_SIZE_KiB": statistics.mean(cw[cwk]["WRITE_SIZE"]),

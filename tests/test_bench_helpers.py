@@ -16,15 +16,26 @@ def bench():
     return m
 
 
-def test_tts99_eq5(bench):
-    # Eq. 5: TTS = T ln(0.01) / ln(1 - P_s), minimised over T
-    assert bench.tts99([], 4) is None
-    assert bench.tts99([0.3, 0.3, 0.4, 0.5], 4) == 0.5          # every run hit by 0.5 s
+def test_tts_scan_eq5():
+    # Eq. 5: TTS = T ln(0.01) / ln(1 - P_s), minimised over the candidate T
+    from paper_2606_25203_amd.tts import scan
+
+    def best(times, n):
+        r = scan(times, n)[1]
+        return None if r is None else r[2]
+    assert best([], 4) is None
+    assert best([0.3, 0.3, 0.4, 0.5], 4) == 0.5          # every run hit by 0.5 s
     half = 0.5 * math.log(0.01) / math.log(0.5)
     quarter = 0.4 * math.log(0.01) / math.log(0.75)
-    assert bench.tts99([0.4, 0.5], 4) == pytest.approx(min(half, quarter))
+    assert best([0.4, 0.5], 4) == pytest.approx(min(half, quarter))
     # a later T with a higher success fraction can win
-    assert bench.tts99([1.0, 1.1, 1.2], 4) == pytest.approx(1.2 * math.log(0.01) / math.log(0.25))
+    assert best([1.0, 1.1, 1.2], 4) == pytest.approx(1.2 * math.log(0.01) / math.log(0.25))
+
+
+def test_survey_bytes(bench):
+    # 5 + p (1 + 8 deg) + 8 deg / 64 at the torus's degree 4
+    assert bench.survey_bytes_per_attempt(0.0, 4.0) == pytest.approx(5.5)
+    assert bench.survey_bytes_per_attempt(0.1, 4.0) == pytest.approx(5.5 + 3.3)
 
 
 def test_percentile(bench):
