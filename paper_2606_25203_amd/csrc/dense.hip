@@ -548,6 +548,16 @@ struct SeqLds {
   __attribute__((aligned(16))) v4i crit[kDB / 4][64];     // the block's critical fields, [group][replica]
 };
 
+// Barrier for work-groups whose waves exchange data through LDS only: the
+// waves' LDS writes complete before it, and their global loads and stores
+// in flight stay in flight (a full __syncthreads would wait for those too,
+// e.g. for the deciding wave's spin write-back).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int RULE, bool WIDE, bool J4>
 __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t sweep_idx, int32_t row0, int32_t rows,
                                          SeqLds& L) {
@@ -749,34 +759,39 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       // block.  The global reads of a part are issued before any of them
       // is used, so that their latencies overlap.
       const int h = b / 2;
-      v4i av[kSB / kDB - 2];  // b <= kSB / kDB - 2 when there is a next block
-      int32_t gv[16];
-      uint2 dj[kPairPer];
-      uint32_t dsw[kDiagPer];
-      if (wave == 3 && next) {
-        // the diagonal block first, so that its registers are free before
-        // the strip's
-        fetch_diag(b + 1, lane, dj, dsw);
-        put_diag(cb ^ 1, lane, dj, dsw);
-      }
       if (next) {
 #pragma unroll
         for (int i = 0; i < kCritPerHelper; ++i)
           if (i < crit_cnt) crit_next[i] = crit_group(b + 1, crit_g0 + i);
-        load_frags(b + 1, wave - 1, 0, b, av);
-        load_g(b + 1, wave - 1, gv);
         v4i acc[4] = {zero, zero, zero, zero};
-        strip_product(0, b, av, acc);
-        add_strip(b + 1, cb ^ 1, wave - 1, acc, gv);
-        if (wave <= 2) {
+        v4i av[kSB / kDB - 2];  // b <= kSB / kDB - 2 when there is a next block
+        int32_t gv[16];
+        if (wave == 3) {
+          // every read of the wave for block b+1 (diagonal block, strip,
+          // fields) in flight together
+          uint2 dj[kPairPer];
+          uint32_t dsw[kDiagPer];
+          fetch_diag(b + 1, lane, dj, dsw);
+          load_frags(b + 1, 2, 0, b, av);
+          load_g(b + 1, 2, gv);
+          put_diag(cb ^ 1, lane, dj, dsw);
+          strip_product(0, b, av, acc);
+          add_strip(b + 1, cb ^ 1, 2, acc, gv);
+        } else {
+          // the wave's strip and its part of strip 3, read together
           v4i a3[(kSB / kDB - 1) / 2];
+          int32_t gv3[16];
           const int kb = wave == 1 ? 0 : h, ke = wave == 1 ? h : b;
+          load_frags(b + 1, wave - 1, 0, b, av);
+          load_g(b + 1, wave - 1, gv);
           load_frags(b + 1, 3, kb, ke, a3);
-          if (wave == 1) load_g(b + 1, 3, gv);
+          if (wave == 1) load_g(b + 1, 3, gv3);
+          strip_product(0, b, av, acc);
+          add_strip(b + 1, cb ^ 1, wave - 1, acc, gv);
           v4i acc3[4] = {zero, zero, zero, zero};
           strip_product(kb, ke, a3, acc3);
           if (wave == 1) {
-            add_strip(b + 1, cb ^ 1, 3, acc3, gv);
+            add_strip(b + 1, cb ^ 1, 3, acc3, gv3);
           } else {
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
@@ -786,7 +801,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (next) {
       if (wave != 0) {
 #pragma unroll
@@ -809,7 +824,7 @@ __device__ __forceinline__ void seq_body(const SeqArgs a, int tile, int32_t swee
       }
       add_strip(b + 1, cb ^ 1, wave, acc, nullptr);
     }
-    __syncthreads();
+    lds_barrier();
   }
   if (wave != 0) return;
   if (dE != 0)
