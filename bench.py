@@ -289,51 +289,21 @@ def bench_served(pamc, torch, count, budget_gb=16.0, slots=256, tick_steps=8, se
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4p", "c4c"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fields", choices=["auto", "push", "pull"], default="auto")
-    ap.add_argument("--batched", default="c1",
-                    help="comma-separated workloads for the plain-vs-batched comparison ('' to skip)")
-    ap.add_argument("--batch-count", type=int, default=0, help="runs per batched comparison (0: default)")
-    ap.add_argument("--served", type=int, default=64,
-                    help="requests of the stream for the plain-vs-served comparison (0 to skip)")
-    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
-                    help="only run an elementwise copy of this many MiB (int32 in, int32 out) five "
-                         "times; used to scale the HBM byte counters of rocprofv3")
-    args = ap.parse_args()
-    if args.calibrate_copy_mib:
-        import torch
-        n = args.calibrate_copy_mib * (1 << 20) // 4
-        x = torch.arange(n, dtype=torch.int32, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(5):
-            torch.neg(x, out=y)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "kernel": "neg (elementwise)"}))
-        return
-    if args.gpus != 1:
-        print("bench.py: the benchmark runs on one GPU; sharding the population across GPUs is not "
-              "implemented. Use --gpus 1.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2606_25203_amd import pamc
+def measure(pamc, torch, name, steps, warmup, fields=None):
+    """Times `steps` complete runs of a workload on one resident instance
+    (after `warmup` untimed runs) and places its sweep kernel on its
+    roofline: HIP events bracket each step's sweep launches, the algorithmic
+    bytes (or ops) per launch come from the model of the workload's path,
+    and the HBM traffic per launch from the committed counter summary."""
     from paper_2606_25203_amd.profile_kernels import sweep_kernel
 
-    w = workload(args.workload)
-    fields = None if args.fields == "auto" else args.fields
+    w = workload(name)
     inst = make_instance(pamc, w, 0, fields=fields)
     info = inst.info()
     n = info.n
     sched = pamc.schedule(**w["sched"])
     pamc.pamc_profile_enable(inst.h, True)   # warm-up also fills the event pool
-    for k in range(args.warmup):
+    for k in range(warmup):
         inst.reset(10_000 + k)
         inst.anneal(sched)
         log(f"warmup {k} done")
@@ -342,7 +312,7 @@ def main():
     t0 = time.perf_counter()
     runs = []
     decoded = []
-    for k in range(args.steps):
+    for k in range(steps):
         inst.reset(k)
         res = inst.anneal(sched)
         tr = inst.trace(w["steps"])
@@ -360,7 +330,7 @@ def main():
     finals3 = [c for c in decoded] if decoded else None
     # the workload's recorded target (the plain path's median final M* over
     # fixed seeds, paper_2606_25203_amd/targets.json), else these runs' median
-    target = recorded_target(args.workload)
+    target = recorded_target(name)
     target_source = "recorded (paper_2606_25203_amd/targets.json)"
     if target is None:
         target, target_source = int(percentile(finals, 0.5)), "median final best cut of the timed runs"
@@ -409,6 +379,17 @@ def main():
             roof = {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
                     "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
                     "alu_slots_per_attempt": slots}
+        elif info.tile_sweeps:
+            # one work-group per 64-replica tile holds the tile's spins in
+            # LDS for all of a step's sweeps: HBM is idle, and a single
+            # instance occupies R/64 compute units; the vector-issue model
+            # over the whole chip, with the share of the units it runs on
+            slots = alu_slots_per_attempt(degree, info.coupling_mode)
+            achieved = slots * rate / 1e12
+            roof = {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
+                    "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
+                    "alu_slots_per_attempt": slots, "cus_used": w["R"] // 64,
+                    "hbm_algorithmic_bytes_per_attempt": survey_bytes_per_attempt(p_flip, degree)}
         else:
             # achieved = the algorithmic bytes of the visits one launch makes
             # (incremental-field layout) over the launch's measured duration
@@ -439,31 +420,119 @@ def main():
                 # issue limit of a CU's four SIMDs for wave64 instructions)
                 cyc = c["mean_dispatch_ns_under_counters"] * 1e-9 * 2.4e9
                 roof["counter_valu_issue_frac"] = c["SQ_INSTS_VALU"] / (256 * cyc)
+                if "cus_used" in roof:
+                    roof["counter_valu_issue_frac_of_cus_used"] = c["SQ_INSTS_VALU"] / (roof["cus_used"] * cyc)
+    inst.close()
+    return {"value": attempts / wall, "wall_s": wall, "ms_per_step": wall / steps * 1e3,
+            "config": {"workload": w["desc"], "n": n, "replicas": w["R"], "beta_steps": w["steps"],
+                       "sweeps": w["sweeps"], "mode": "plain (one instance per launch sequence)",
+                       "parallelism": "1 GPU"},
+            "time_to_target": {"target_cut": target, "p50_s": percentile(ttt, 0.5),
+                               "p99_s": percentile(ttt, 0.99), "success_fraction": len(ttt) / len(runs),
+                               "tts99_s": (tts_scan(ttt, len(runs))[1] or (None, None, None))[2],
+                               "target_source": target_source, "final_cuts": finals},
+            **({"final_3cuts": finals3} if finals3 else {}),
+            "roofline": roof}
+
+
+def recorded_runs():
+    """Key figures of the committed long measurements that a default run
+    does not repeat (they take minutes): the full 2,000-request served
+    stream and the time-to-solution scans (Eq. 5, 100 runs each)."""
+    out = {}
+    prof = os.path.join(ROOT, "profiles")
+    try:
+        with open(os.path.join(prof, "served_c5_2000req_R512.json")) as f:
+            s = json.load(f)["served"]
+        out["served_c5_2000_requests"] = {
+            "command": "python bench.py --steps 1 --warmup 0 --no-cpu-baseline --batched= --served 2000 "
+                       "--workload c1",
+            "file": "profiles/served_c5_2000req_R512.json", "requests": s["requests"],
+            **{m: {k: s[m][k] for k in ("speedup_vs_plain", "latency_p50_s", "latency_p99_s",
+                                        "plain_latency_p50_s", "plain_latency_p99_s", "identical_results")}
+               for m in ("burst", "poisson", "poisson_overload")}}
+    except (OSError, KeyError, ValueError):
+        pass
+    scans = {}
+    for fn in sorted(os.listdir(prof)) if os.path.isdir(prof) else []:
+        if fn.startswith("tts_") and fn.endswith("_scan.json"):
+            try:
+                with open(os.path.join(prof, fn)) as f:
+                    d = json.load(f)
+                scans[fn[:-len("_scan.json")]] = {k: d[k] for k in ("workload", "mode", "target", "runs",
+                                                                     "successes", "tts99_s", "at")}
+            except (OSError, KeyError, ValueError):
+                pass
+    if scans:
+        out["tts_scans"] = {"command": "python -m paper_2606_25203_amd.tts scan --workload <c1|c2|c4> "
+                                       "[--sa] --runs 100", **scans}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4p", "c4c"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fields", choices=["auto", "push", "pull"], default="auto")
+    ap.add_argument("--batched", default="c1",
+                    help="comma-separated workloads for the plain-vs-batched comparison ('' to skip)")
+    ap.add_argument("--batch-count", type=int, default=0, help="runs per batched comparison (0: default)")
+    ap.add_argument("--side", default="c1,c3,c4,c4p",
+                    help="comma-separated workloads timed once each beside the headline ('' to skip)")
+    ap.add_argument("--served", type=int, default=256,
+                    help="requests of the stream for the plain-vs-served comparison (0 to skip)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run an elementwise copy of this many MiB (int32 in, int32 out) five "
+                         "times; used to scale the HBM byte counters of rocprofv3")
+    args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        x = torch.arange(n, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "kernel": "neg (elementwise)"}))
+        return
+    if args.gpus != 1:
+        print("bench.py: the benchmark runs on one GPU; sharding the population across GPUs is not "
+              "implemented. Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_25203_amd import pamc
+
+    w = workload(args.workload)
+    fields = None if args.fields == "auto" else args.fields
+    m = measure(pamc, torch, args.workload, args.steps, args.warmup, fields)
     out = {
         "metric": "spin-flip attempts/s + time-to-target-cut (plain vs batched/served), p50/p99",
-        "value": attempts / wall,
+        "value": m["value"],
         "unit": "flip attempts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": w["desc"], "n": n, "replicas": w["R"], "beta_steps": w["steps"],
-                   "sweeps": w["sweeps"], "mode": "plain (one instance per launch sequence)",
-                   "parallelism": "1 GPU"},
-        "time_to_target": {"target_cut": target, "p50_s": percentile(ttt, 0.5), "p99_s": percentile(ttt, 0.99),
-                           "success_fraction": len(ttt) / len(runs),
-                           "tts99_s": (tts_scan(ttt, len(runs))[1] or (None, None, None))[2],
-                           "target_source": target_source,
-                           "final_cuts": finals},
-        **({"final_3cuts": finals3} if finals3 else {}),
-        "roofline": roof,
+        "config": m["config"],
+        "time_to_target": m["time_to_target"],
+        **({"final_3cuts": m["final_3cuts"]} if "final_3cuts" in m else {}),
+        "roofline": m["roofline"],
     }
-    inst.close()
+    if args.side:
+        out["other_workloads"] = {}
+        for name in args.side.split(","):
+            log(f"workload {name}: one timed run ...")
+            out["other_workloads"][name] = measure(pamc, torch, name, 1, 1)
     if args.batched:
         out["batched"] = []
         for name in args.batched.split(","):
@@ -472,6 +541,9 @@ def main():
     if args.served:
         log("served comparison ...")
         out["served"] = bench_served(pamc, torch, args.served)
+    rec = recorded_runs()
+    if rec:
+        out["recorded"] = rec
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         cb = cpu_baseline(w, args.cpu_seconds)
