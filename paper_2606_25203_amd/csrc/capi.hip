@@ -215,6 +215,8 @@ struct HostSparse {
   int32_t tile = 0;  // a step's sweeps of a replica tile in one work-group
   int32_t tile_ok = 0;  // tile-resident sweeps possible (the autotuner may switch them)
   int32_t tile_rows = 0;  // gathered-CSR entries of the largest colour class
+  int32_t dual = 0;  // both field forms kept (hub graphs; see dual_field_step)
+  int32_t hub_tpw = 1, hub_qpw = 1, push_tpw = 1, push_qpw = 1;  // the two forms' wave shapes
   int64_t nnz = 0, W = 0, X = 0;
   std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, grow, gcol, gJ, hubJ;
 };
@@ -255,7 +257,7 @@ bool choose_fields(int32_t n, const int32_t* rp, uint32_t flags, bool potts, std
 }
 
 pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const int32_t* col,
-                           const std::vector<int32_t>& Jin, uint32_t flags, int32_t T) {
+                           const std::vector<int32_t>& Jin, uint32_t flags, int32_t T, bool allow_dual = true) {
   h.n = n;
   h.np = (n + 3) & ~3;
   h.nq = h.np / 4;
@@ -338,7 +340,22 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
     h.pull = 1;
     hubs.clear();
   }
-  h.nhub = h.pull ? (int32_t)hubs.size() : 0;
+  // Graphs whose only long rows are a few hubs (at most kMaxHubs rows of
+  // more than 64 entries) keep both field forms when no form is forced: a
+  // run takes gathered fields with the hubs' fields kept while its
+  // schedule's beta is low, where incremental fields would walk a hub's
+  // whole row from one wavefront at each of its frequent flips, and
+  // incremental fields afterwards (dual_field_step).
+  if (allow_dual && !h.pull && !h.tile && !h.potts_K &&
+      !(flags & (PAMC_FLAG_FIELDS_PUSH | PAMC_FLAG_FIELDS_PULL))) {
+    std::vector<int32_t> hh;
+    choose_fields(n, rp, PAMC_FLAG_FIELDS_PULL, false, &hh);
+    if (!hh.empty()) {
+      h.dual = 1;
+      hubs = hh;
+    }
+  }
+  h.nhub = (h.pull || h.dual) ? (int32_t)hubs.size() : 0;
   for (int32_t k = 0; k < h.nhub; ++k) h.hub_v[k] = h.to_internal[hubs[k]];
   if (h.nhub) {  // couplings of every vertex to each hub
     h.hubJ.assign((size_t)h.np * pamc::kMaxHubs, 0);
@@ -353,7 +370,7 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   // coupling in the neighbour's byte).
   // Potts labels are read with a byte index: coupling mode 0 or 1 layout
   if (h.potts_K && h.jmode == 2) h.jmode = h.small_j ? 1 : 0;
-  if (h.pull) {
+  if (h.pull || h.dual) {
     // a hub's row is not gathered (its field is kept), so it stays empty here
     auto is_hub = [&](int32_t iv) { return h.nhub && (iv == h.hub_v[0] || iv == h.hub_v[1]); };
     h.grow.assign(n + 1, 0);
@@ -400,7 +417,7 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
         h.tpw = t;
         break;
       }
-  if (h.nhub)  // the measured best shape of the kept-hub mode on the Max-3-Cut embedding: 4 x 1
+  if (h.nhub && !h.dual)  // the measured best shape of the kept-hub mode on the Max-3-Cut embedding: 4 x 1
     h.tpw = (T % 4 == 0) ? 4 : ((T % 2 == 0) ? 2 : 1);
   if (const char* e = getenv("PAMC_TPW")) {
     const int t = atoi(e);
@@ -408,14 +425,20 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   }
   h.qpw = 1;
   for (int q : {4, 2})
-    if (!h.nhub && (T / h.tpw) * ((h.max_class_quads + W4 * q - 1) / (W4 * q)) >= 4096) {
+    if ((!h.nhub || h.dual) && (T / h.tpw) * ((h.max_class_quads + W4 * q - 1) / (W4 * q)) >= 4096) {
       h.qpw = q;
       break;
     }
+  if (h.dual) {  // starts with incremental fields; the kept-hub shape as measured (4 x 1)
+    h.hub_tpw = (T % 4 == 0) ? 4 : ((T % 2 == 0) ? 2 : 1);
+    h.hub_qpw = 1;
+  }
   if (const char* e = getenv("PAMC_QPW")) {
     const int q = atoi(e);
     if (q == 1 || q == 2 || q == 4) h.qpw = q;
   }
+  h.push_tpw = h.tpw;
+  h.push_qpw = h.qpw;
   return PAMC_OK;
 }
 
@@ -438,6 +461,10 @@ void apply_shape(pamc_instance* I, const TuneShape& t) {
   I->tile = t.tile;
   I->tpw = t.tpw;
   I->qpw = t.qpw;
+  if (I->dual && !I->pull) {  // the incremental-field form's shape
+    I->push_tpw = t.tpw;
+    I->push_qpw = t.qpw;
+  }
   I->self_dirty = true;
 }
 
@@ -470,6 +497,11 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   for (int k = 0; k < pamc::kMaxHubs; ++k) I->hub_v[k] = h.hub_v[k];
   I->tpw = h.tpw;
   I->qpw = h.qpw;
+  I->dual = h.dual;
+  I->hub_tpw = h.hub_tpw;
+  I->hub_qpw = h.hub_qpw;
+  I->push_tpw = h.push_tpw;
+  I->push_qpw = h.push_qpw;
   I->max_class_quads = h.max_class_quads;
   I->class_ptr = std::move(h.class_ptr);
   I->to_internal = std::move(h.to_internal);
@@ -479,7 +511,7 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(dalloc(I, &I->g.row_ptr, n + 1), "alloc");
   HIP_TRY(dalloc(I, &I->g.col, nnz), "alloc");
   HIP_TRY(dalloc(I, &I->g.J, nnz), "alloc");
-  const bool gathered = I->pull;
+  const bool gathered = I->pull || I->dual;
   if (gathered) {
     HIP_TRY(dalloc(I, &I->g.grow, n + 1), "alloc");
     HIP_TRY(dalloc(I, &I->g.gcol, h.gcol.size()), "alloc");
@@ -1163,6 +1195,39 @@ pamc_status pamc_get_state(pamc_instance* I, int8_t* spins, int32_t* fields, int
   return PAMC_OK;
 }
 
+// An instance keeping both field forms (hub graphs) switches between them:
+// the fields the new form keeps are recomputed from the current population,
+// so the trajectory is the same in either (the fields are exact integers).
+static pamc_status set_field_mode(pamc_instance* I, bool pull) {
+  if (!I->dual || (I->pull != 0) == pull) return PAMC_OK;
+  I->pull = pull ? 1 : 0;
+  I->tpw = pull ? I->hub_tpw : I->push_tpw;
+  I->qpw = pull ? I->hub_qpw : I->push_qpw;
+  I->self_dirty = true;
+  SELF_BATCH(I, b);
+  HIP_TRY(pamc::launch_refresh_fields(*b), "fields");
+  return PAMC_OK;
+}
+
+// The steps a run of an instance keeping both field forms makes with
+// gathered fields (the hubs' fields kept) before it switches to incremental
+// ones: those whose scheduled beta, beta0 + k dbeta (before any reheat),
+// lies below kDualSwitchBeta.  At low beta a hub flips often, and with
+// incremental fields every such flip walks the hub's whole row from one
+// wavefront; at higher beta incremental fields cost less per attempt.  On
+// the Max-3-Cut embedding of G(7000, 21000) the per-step times of the two
+// forms cross near beta 0.7-0.8 (PAMC_HUB_SWITCH_BETA overrides).  Resumed
+// runs keep the current form.
+constexpr double kDualSwitchBeta = 0.8;
+static int32_t dual_field_steps(const pamc_instance* I, const Schedule& s) {
+  if (!I->dual || s.resume || s.steps <= 0) return 0;
+  double bsw = kDualSwitchBeta;
+  if (const char* e = getenv("PAMC_HUB_SWITCH_BETA")) bsw = atof(e);
+  if (!(s.dbeta > 0.0)) return s.beta0 < bsw ? s.steps : 0;
+  const double k = std::ceil((bsw - s.beta0) / s.dbeta);
+  return (int32_t)std::max(0.0, std::min((double)s.steps, k));
+}
+
 pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_result* out) {
   if (!I || !sched || !out) return fail(PAMC_ERR_INVALID_ARG, "NULL argument");
   pamc_status st = check_schedule(I, sched);
@@ -1171,28 +1236,50 @@ pamc_status pamc_anneal(pamc_instance* I, const pamc_schedule* sched, pamc_resul
   Schedule s = to_sched(sched);
   st = prepare_run(I, s);
   if (st) return st;
+  const int32_t kd = dual_field_steps(I, s);
+  if (kd > 0) {
+    st = set_field_mode(I, true);
+    if (st) return st;
+  }
   SELF_BATCH(I, b);
-  b->max_sweeps = std::max(s.sweeps, 1);
-  b->any_cluster = cluster_possible(s);
-  b->any_dh = s.dh_every > 0 && b->dh.grid > 0;
+  auto run_flags = [&](pamc::Batch* x) {
+    x->max_sweeps = std::max(s.sweeps, 1);
+    x->any_cluster = cluster_possible(s);
+    x->any_dh = s.dh_every > 0 && x->dh.grid > 0;
+  };
+  run_flags(b);
   if (!I->d_sched) HIP_TRY(dev_alloc(I, &I->d_sched, sizeof(Schedule)), "alloc");
   HIP_TRY(hipMemcpyAsync(I->d_sched, &s, sizeof(Schedule), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::batch_anneal_setup(*b, (const Schedule*)I->d_sched, nullptr, 1), "anneal setup");
   // steps in chunks of 16 between polls of the stop flag when stopping at
-  // the target, else all at once
+  // the target, else all at once (and the switch of field form, if any)
   const int32_t chunk = s.stop_at_target ? 16 : std::max(s.steps, 1);
-  for (int32_t done = 0; done < s.steps; done += chunk) {
-    const int32_t k = std::min(chunk, s.steps - done);
+  for (int32_t done = 0; done < s.steps;) {
+    int32_t k = std::min(chunk, s.steps - done);
+    if (kd > done) k = std::min(k, kd - done);
     if (I->dense) {
       for (int32_t i = 0; i < k; ++i) HIP_TRY(pamc::launch_dense_step(*b, s.sweeps, s.resample), "dense step");
     } else {
       HIP_TRY(pamc::batch_run_steps(*b, k), "step");
     }
-    if (s.stop_at_target && done + k < s.steps) {
+    done += k;
+    if (done == kd && I->pull) {
+      st = set_field_mode(I, false);
+      if (st) return st;
+      hipError_t e2;
+      b = self_batch(I, &e2);
+      if (!b) return dev_fail(e2, "batch descriptors");
+      run_flags(b);
+    }
+    if (s.stop_at_target && done < s.steps) {
       HIP_TRY(hipMemcpyAsync(I->pinned, &I->st->stopped, sizeof(int32_t), hipMemcpyDeviceToHost, I->stream), "poll");
       HIP_TRY(hipStreamSynchronize(I->stream), "poll");
       if (*(volatile int32_t*)I->pinned) break;
     }
+  }
+  if (I->dual && I->pull) {  // a run that stopped before the switch
+    st = set_field_mode(I, false);
+    if (st) return st;
   }
   pamc::RunState r;
   st = read_state(I, &r);
@@ -1958,7 +2045,7 @@ void server_prepare(ServerPrep& p, uint32_t flags, int32_t T) {
   if (!st) {
     std::vector<int32_t> J(std::max(p.rp[p.n], 1));
     for (int32_t e = 0; e < p.rp[p.n]; ++e) J[e] = p.objective == PAMC_OBJ_MAXCUT ? -p.w[e] : p.w[e];
-    st = prepare_sparse(p.h, p.n, p.rp.data(), p.col.data(), J, flags, T);
+    st = prepare_sparse(p.h, p.n, p.rp.data(), p.col.data(), J, flags, T, false);
   }
   std::lock_guard<std::mutex> g(p.m);
   p.status = st;

@@ -67,6 +67,8 @@ struct pamc_instance {
   int32_t tile_ok = 0;    // tile-resident sweeps possible
   int32_t nhub = 0;       // hubs (pull mode): vertices whose fields are kept incrementally
   int32_t hub_v[pamc::kMaxHubs] = {-1, -1};  // their internal ids
+  int32_t dual = 0;       // both field forms kept: pull (with kept hub fields) and push
+  int32_t hub_tpw = 1, hub_qpw = 1, push_tpw = 1, push_qpw = 1;  // wave shapes of the two forms
   int32_t tpw = 1;        // replica tiles per wavefront in the gathered-field sweep
   int32_t qpw = 1;        // vertex quads per wavefront in a sweep work-group (1, 2, 4)
   int32_t small_j = 0;    // 1: every |J| < 2^23 (24-bit multiplies are exact)
@@ -260,6 +262,7 @@ hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev);
 hipError_t launch_pair_distance(pamc_instance* I, double* out_dev);
 // histogram of min(d, n - d) over all replica pairs into nbins bins of
 // [0, 1/2] (bin = floor(2 nbins min(d, n-d) / n), capped) plus its sum
+hipError_t launch_refresh_fields(Batch& b);
 hipError_t launch_pair_hist(pamc_instance* I, int32_t nbins, int64_t* hist_dev, int64_t* sum_dev);
 int32_t cluster_max_n();
 int32_t sweep_waves();  // wavefronts per sweep work-group

@@ -1968,8 +1968,10 @@ Desc make_desc(const pamc_instance* I) {
   d.thr = I->thr;
   d.S0 = I->pop.S[0];
   d.S1 = I->pop.S[1];
-  d.H0 = I->pop.H[0];
-  d.H1 = I->pop.H[1];
+  // incremental fields only in push mode (an instance keeping both forms
+  // has them allocated in pull mode too, stale there)
+  d.H0 = I->pull ? nullptr : I->pop.H[0];
+  d.H1 = I->pull ? nullptr : I->pop.H[1];
   d.E0 = I->pop.E[0];
   d.E1 = I->pop.E[1];
   d.F0 = I->pop.fam[0];
@@ -2453,6 +2455,15 @@ hipError_t launch_m3_decode(pamc_instance* I, const int8_t* spins_internal_dev) 
   k_m3_decode<<<grid, 256, 0, I->stream>>>(spins_internal_dev, I->to_internal_dev, I->m3_n, I->m3_labels);
   k_m3_cut<<<grid, 256, 0, I->stream>>>(I->m3_labels, I->m3_n, I->m3_row_ptr, I->m3_col, I->m3_w,
                                         I->m3_cut);
+  return hipGetLastError();
+}
+
+// The fields the instance's current form keeps, recomputed from the current
+// population (no energy change): the incremental fields in push mode, the
+// kept hub fields.
+hipError_t launch_refresh_fields(Batch& b) {
+  if (b.init_fields.grid)
+    k_init_fields<<<b.init_fields.grid, 256, 0, b.stream>>>(b.d_desc, b.init_fields.map, -1, nullptr, 0);
   return hipGetLastError();
 }
 

@@ -552,3 +552,55 @@ def test_diversity_trace_matches_oracle(pamc, fields):
     inst.anneal(pamc.schedule(beta0=0.1, dbeta=0.02, steps=5, sweeps=1))
     assert len(inst.dh_trace(5)) == 0
     inst.close()
+
+
+@pytest.mark.parametrize("hubs", [1, 2])
+@pytest.mark.parametrize("switch", ["0.5", "0.0", "100"])
+def test_hub_graph_switches_field_form(pamc, monkeypatch, hubs, switch):
+    """A hub graph with no field form forced keeps both: a run makes the
+    steps whose scheduled beta lies below the switch point with gathered
+    fields (hub fields kept) and the rest with incremental fields, each
+    recomputed from the population at the switch.  Against the oracle,
+    across the switch (cluster moves and reheats included), with the switch
+    at the start (incremental only) and never (gathered only); the instance
+    ends in the incremental form either way."""
+    g = hub_graph(300, 700, hubs, 60 + hubs, 3)
+    monkeypatch.setenv("PAMC_TILE", "0")
+    monkeypatch.setenv("PAMC_HUB_SWITCH_BETA", switch)
+    R = 256
+    say(f"case field-form switch hubs={hubs} switch beta={switch}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=9)
+    info = inst.info()
+    assert info.pull == 0 and info.hubs == hubs
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 9)
+    compare_anneal(pamc, inst, o, dict(beta0=0.05, dbeta=0.03, steps=40, sweeps=2, augmented=1, z_rst=30,
+                                       n_top=16, mis_trials=3, win_short=4, win_long=6, max_distinct_short=2,
+                                       max_distinct_long=3, tau=3))
+    assert inst.info().pull == 0
+    # the incremental fields left by the switch back carry on: sweeps and a
+    # resampling after the run
+    inst.sweep(0.9, 2)
+    o.sweep(0.9, 2)
+    inst.resample(0.2)
+    o.resample(0.2)
+    same_state(inst, o, "after the run")
+    inst.close()
+
+
+def test_hub_graph_run_stopping_before_the_switch(pamc, monkeypatch):
+    """A run that stops at its target while still in the gathered form
+    switches back to incremental fields on the way out."""
+    g = hub_graph(300, 700, 1, 71, 2)
+    monkeypatch.setenv("PAMC_TILE", "0")
+    monkeypatch.setenv("PAMC_HUB_SWITCH_BETA", "100")
+    R = 128
+    say("case field-form switch, stop at target first")
+    inst = pamc.Instance.csr(g, replicas=R, seed=4)
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 4)
+    res, ores = compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.05, steps=80, sweeps=2, target=1,
+                                                   stop_at_target=1))
+    assert ores.steps_run < 80 and inst.info().pull == 0
+    inst.sweep(1.0, 3)
+    o.sweep(1.0, 3)
+    same_state(inst, o, "after the stopped run")
+    inst.close()
