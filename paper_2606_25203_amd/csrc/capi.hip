@@ -1314,6 +1314,19 @@ pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* 
     max_steps = std::max(max_steps, s[i].steps);
     any_stop |= s[i].stop_at_target;
   }
+  // instances keeping both field forms start in the gathered one and switch
+  // at their own step (dual_field_steps); the batch is rebuilt there
+  std::vector<int32_t> kd(count), cuts;
+  for (int32_t i = 0; i < count; ++i) {
+    kd[i] = dual_field_steps(v[i], s[i]);
+    if (kd[i] > 0) {
+      pamc_status st = set_field_mode(v[i], true);
+      if (st) return st;
+      if (kd[i] < max_steps) cuts.push_back(kd[i]);
+    }
+  }
+  std::sort(cuts.begin(), cuts.end());
+  cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
   // every instance's queued work is finished before the batch takes over
   for (pamc_instance* I : v) HIP_TRY(hipStreamSynchronize(I->stream), "sync");
   pamc::Batch b;
@@ -1327,9 +1340,25 @@ pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* 
   if (e == hipSuccess) e = pamc::batch_anneal_setup(b, d_sched, nullptr, count);
   std::vector<int32_t> status(count);
   const int32_t chunk = any_stop ? 16 : std::max(max_steps, 1);
-  for (int32_t done = 0; done < max_steps && e == hipSuccess; done += chunk) {
-    e = pamc::batch_run_steps(b, std::min(chunk, max_steps - done));
-    if (e == hipSuccess && any_stop && done + chunk < max_steps) {
+  size_t next_cut = 0;
+  pamc_status sw = PAMC_OK;
+  for (int32_t done = 0; done < max_steps && e == hipSuccess && !sw;) {
+    int32_t k = std::min(chunk, max_steps - done);
+    if (next_cut < cuts.size()) k = std::min(k, cuts[next_cut] - done);
+    e = pamc::batch_run_steps(b, k);
+    done += k;
+    if (e == hipSuccess && next_cut < cuts.size() && done == cuts[next_cut]) {
+      // the instances whose switch falls here take incremental fields
+      e = hipStreamSynchronize(b.stream);
+      for (int32_t i = 0; i < count && e == hipSuccess && !sw; ++i)
+        if (kd[i] == done) {
+          sw = set_field_mode(v[i], false);
+          if (!sw) e = hipStreamSynchronize(v[i]->stream);
+        }
+      if (e == hipSuccess && !sw) e = pamc::batch_build(b, v, &s);
+      ++next_cut;
+    }
+    if (e == hipSuccess && !sw && any_stop && done < max_steps) {
       e = pamc::batch_status(b, d_status);
       if (e == hipSuccess) e = hipMemcpyAsync(status.data(), d_status, sizeof(int32_t) * count, hipMemcpyDeviceToHost, b.stream);
       if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
@@ -1339,6 +1368,9 @@ pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* 
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+  // instances that stopped before their switch
+  for (int32_t i = 0; i < count && e == hipSuccess && !sw; ++i)
+    if (v[i]->dual && v[i]->pull) sw = set_field_mode(v[i], false);
   for (void* p : {(void*)d_sched, (void*)d_status}) {
     if (!p) continue;
     if (b.al)
@@ -1346,6 +1378,7 @@ pamc_status pamc_anneal_batch(pamc_instance* const* insts, const pamc_schedule* 
     else
       hipFree(p);
   }
+  if (sw) return sw;
   if (e != hipSuccess) return dev_fail(e, "batched run");
   for (int32_t i = 0; i < count; ++i) {
     pamc::RunState r;

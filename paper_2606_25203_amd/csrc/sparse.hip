@@ -887,9 +887,17 @@ __global__ void __launch_bounds__(256) k_init_fields(const Desc* __restrict__ D,
         if (H) H[((size_t)tile * d.np + v) * kLanes + lane] = 0;
         continue;
       }
-      int64_t h = 0;
-      for (int e = d.row_ptr[v]; e < d.row_ptr[v + 1]; ++e)
-        h += (int64_t)d.J[e] * spin_at(S, d.nq, tile, d.col[e], lane);
+      // four independent sums, so that a long (hub) row has several spin
+      // reads in flight rather than one at a time
+      const int e0 = d.row_ptr[v], e1 = d.row_ptr[v + 1];
+      int64_t hp[4] = {0, 0, 0, 0};
+      int e = e0;
+      for (; e + 4 <= e1; e += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hp[u] += (int64_t)d.J[e + u] * spin_at(S, d.nq, tile, d.col[e + u], lane);
+      }
+      for (; e < e1; ++e) hp[0] += (int64_t)d.J[e] * spin_at(S, d.nq, tile, d.col[e], lane);
+      const int64_t h = (hp[0] + hp[1]) + (hp[2] + hp[3]);
       if (H) H[((size_t)tile * d.np + v) * kLanes + lane] = (int32_t)h;
       if (!Hout && d.nhub && (v == d.hub_v0 || v == d.hub_v1))  // the kept hub fields
         (b ? d.HF1 : d.HF0)[(v == d.hub_v0 ? 0 : 1) * d.R + tile * kLanes + lane] = (int32_t)h;

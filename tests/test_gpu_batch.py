@@ -275,3 +275,52 @@ def test_server_budget_with_large_weights(pamc):
         srv.submit(g, 1, sched)
     assert ex.value.status == pamc.PAMC_ERR_OUT_OF_MEMORY
     srv.close()
+
+
+def hub_graph(n, m, seed):
+    """A random graph plus one vertex joined to most others (a hub row)."""
+    rng = np.random.default_rng(seed)
+    base = synth.random_graph(n, m, seed)
+    us, vs = [], []
+    for v in range(n):
+        for e in range(base.row_ptr[v], base.row_ptr[v + 1]):
+            if base.col[e] > v:
+                us.append(v)
+                vs.append(int(base.col[e]))
+    for v in range(n):
+        if rng.random() < 0.7:
+            us.append(v)
+            vs.append(n)
+    w = rng.integers(1, 3, size=len(us)) * rng.choice([-1, 1], size=len(us))
+    return synth.csr_from_edges(n + 1, np.array(us), np.array(vs), w.astype(np.int32))
+
+
+def test_batch_switches_field_forms_per_instance(pamc, monkeypatch):
+    """Hub-graph instances keep both field forms and switch from gathered to
+    incremental fields at their own step inside one batched run (the batch
+    is rebuilt there); each run against the oracle, bit for bit, next to an
+    instance without hubs."""
+    monkeypatch.setenv("PAMC_TILE", "0")
+    monkeypatch.setenv("PAMC_HUB_SWITCH_BETA", "0.6")
+    g1, g2, g3 = hub_graph(280, 600, 1), hub_graph(300, 650, 2), synth.torus(16, 12, 3)
+    base = dict(steps=40, sweeps=2, augmented=1, z_rst=35, n_top=8, mis_trials=3, win_short=4, win_long=6,
+                max_distinct_short=2, max_distinct_long=3, tau=3)
+    cases = [(g1, 128, 5, dict(base, beta0=0.1, dbeta=0.03)),    # switches at step 17
+             (g2, 192, 6, dict(base, beta0=0.2, dbeta=0.05)),    # at step 8
+             (g1, 64, 7, dict(base, beta0=0.05, dbeta=0.01)),    # never (beta stays below 0.6)
+             (g3, 64, 8, dict(base, beta0=0.1, dbeta=0.05))]     # no hubs
+    say("case batch with field-form switches")
+    insts = [pamc.Instance.csr(g, replicas=R, seed=sd) for g, R, sd, _ in cases]
+    assert [i.info().hubs for i in insts] == [1, 1, 1, 0]
+    res = pamc.anneal_batch(insts, [pamc.schedule(**kw) for *_, kw in cases])
+    for (g, R, sd, kw), inst, r in zip(cases, insts, res):
+        o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, sd)
+        ores, otr = o.anneal(oracle.default_schedule(**kw), trace=True)
+        assert (r.best_cut, r.steps_run, r.n_cluster_moves, r.n_reheats) == \
+            (ores.best_cut, ores.steps_run, ores.n_cluster_moves, ores.n_reheats)
+        assert np.array_equal(inst.trace(kw["steps"])["mstar"], otr["mstar"])
+        s, h, E, f = inst.state()
+        os_, oh, oE, of = o.state()
+        assert np.array_equal(s, os_) and np.array_equal(h, oh) and np.array_equal(E, oE) and np.array_equal(f, of)
+        assert inst.info().pull == 0 or inst.info().hubs == 0
+        inst.close()
