@@ -404,6 +404,10 @@ def measure(pamc, torch, name, steps, warmup, fields=None):
                                      "peak_tslots": VALU_PEAK_TSLOTS,
                                      "frac": slots * rate / 1e12 / VALU_PEAK_TSLOTS,
                                      "kernel_min_bytes_per_attempt": pull_bytes_per_attempt(p_flip, degree)}
+        if info.hubs and not pull and not info.tile_sweeps:
+            roof["field_forms"] = ("both kept: the launches of the steps below beta 0.8 gather fields "
+                                   "(hub fields kept, k_sweep_pull), the rest keep them incrementally "
+                                   "(k_sweep_push); launch_ms averages both")
         roof.update({"traffic": None, "launch_ms": launch_ms, "launches": prof["launches"],
                      "attempts_per_launch": apl, "flip_rate": p_flip, "fields": "pull" if pull else "push",
                      "kernel_shape": shape, "attempts_per_s_in_kernel": rate})
