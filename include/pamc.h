@@ -71,7 +71,12 @@ typedef enum { PAMC_MEM_HOST = 0, PAMC_MEM_DEVICE = 1 } pamc_mem;
  * the neighbours' spins when a spin is visited.  The integer fields, hence
  * every decision and the trajectory, are the same; the default picks PULL
  * when the average degree is at most 16 and no vertex has more than 64
- * neighbours. */
+ * neighbours.  PULL with at most two longer rows ("hubs") keeps the hubs'
+ * fields.  With neither flag, a graph whose only long rows are one or two
+ * hubs keeps both forms: pamc_anneal and pamc_anneal_batch sweep with PULL
+ * while the scheduled beta is below 0.8 and with PUSH after, recomputing
+ * the fields at the switch (pamc_get_info reports the form in use, PUSH
+ * between runs). */
 #define PAMC_FLAG_FIELDS_PUSH 2u
 #define PAMC_FLAG_FIELDS_PULL 4u
 
