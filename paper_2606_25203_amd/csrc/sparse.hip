@@ -376,6 +376,7 @@ __global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tile(const Desc* __re
   for (int i = threadIdx.x; i < nq * kLanes; i += blockDim.x) Sl[i] = S[i];
   for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
   const int lane = threadIdx.x & 63;
+  const int lane4 = 4 * lane;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t r = (uint32_t)(tile * kLanes + lane);
   const bool metropolis = d.rule == 1;
@@ -409,9 +410,14 @@ __global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tile(const Desc* __re
             const i32x4 cJ = *reinterpret_cast<const i32x4*>(rj + e);
             const int j[4] = {cj.x, cj.y, cj.z, cj.w};
             const int32_t c[4] = {cJ.x, cJ.y, cJ.z, cJ.w};
+            // the neighbour's word: j is its byte offset in the tile (plus
+            // its byte index in modes 0 and 1), so one add per neighbour
+            // addresses it
             uint32_t w[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) w[u] = Sl[(j[u] >> 2) + lane];  // the neighbour's word (byte offset / 4)
+            for (int u = 0; u < 4; ++u)
+              w[u] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(Sl) +
+                                                        (JM == 2 ? j[u] : (j[u] & ~3)) + lane4);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               if (JM == 2) {
