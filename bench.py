@@ -55,7 +55,7 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def survey_bytes_per_attempt(p_flip: float, degree: float) -> float:
+def incremental_field_bytes_per_attempt(p_flip: float, degree: float) -> float:
     """Algorithmic HBM bytes of one (replica, vertex) visit of a sparse sweep
     in the incremental-field layout (the reference model of the method's
     data movement): read the spin (1 B) and the field (4 B); on a flip
@@ -389,11 +389,11 @@ def measure(pamc, torch, name, steps, warmup, fields=None):
             roof = {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
                     "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
                     "alu_slots_per_attempt": slots, "cus_used": w["R"] // 64,
-                    "hbm_algorithmic_bytes_per_attempt": survey_bytes_per_attempt(p_flip, degree)}
+                    "hbm_algorithmic_bytes_per_attempt": incremental_field_bytes_per_attempt(p_flip, degree)}
         else:
             # achieved = the algorithmic bytes of the visits one launch makes
             # (incremental-field layout) over the launch's measured duration
-            b_alg = survey_bytes_per_attempt(p_flip, degree)
+            b_alg = incremental_field_bytes_per_attempt(p_flip, degree)
             achieved = b_alg * rate / 1e9
             roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_attempt": b_alg,

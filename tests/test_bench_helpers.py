@@ -32,10 +32,10 @@ def test_tts_scan_eq5():
     assert best([1.0, 1.1, 1.2], 4) == pytest.approx(1.2 * math.log(0.01) / math.log(0.25))
 
 
-def test_survey_bytes(bench):
+def test_incremental_field_bytes(bench):
     # 5 + p (1 + 8 deg) + 8 deg / 64 at the torus's degree 4
-    assert bench.survey_bytes_per_attempt(0.0, 4.0) == pytest.approx(5.5)
-    assert bench.survey_bytes_per_attempt(0.1, 4.0) == pytest.approx(5.5 + 3.3)
+    assert bench.incremental_field_bytes_per_attempt(0.0, 4.0) == pytest.approx(5.5)
+    assert bench.incremental_field_bytes_per_attempt(0.1, 4.0) == pytest.approx(5.5 + 3.3)
 
 
 def test_percentile(bench):
