@@ -1200,12 +1200,21 @@ pamc_status pamc_get_state(pamc_instance* I, int8_t* spins, int32_t* fields, int
 // so the trajectory is the same in either (the fields are exact integers).
 static pamc_status set_field_mode(pamc_instance* I, bool pull) {
   if (!I->dual || (I->pull != 0) == pull) return PAMC_OK;
+  const int32_t was_pull = I->pull, was_tpw = I->tpw, was_qpw = I->qpw;
   I->pull = pull ? 1 : 0;
   I->tpw = pull ? I->hub_tpw : I->push_tpw;
   I->qpw = pull ? I->hub_qpw : I->push_qpw;
   I->self_dirty = true;
-  SELF_BATCH(I, b);
-  HIP_TRY(pamc::launch_refresh_fields(*b), "fields");
+  hipError_t e;
+  pamc::Batch* b = self_batch(I, &e);
+  if (b) e = pamc::launch_refresh_fields(*b);
+  if (e != hipSuccess) {  // the previous form's fields are still current: keep it
+    I->pull = was_pull;
+    I->tpw = was_tpw;
+    I->qpw = was_qpw;
+    I->self_dirty = true;
+    return dev_fail(e, "field form switch");
+  }
   return PAMC_OK;
 }
 
