@@ -121,9 +121,34 @@ def test_allocation_failure_anywhere_in_creation(pamc, torch):
         assert not c.live, f"request {k}: {len(c.live)} blocks leaked"
 
 
-def test_allocation_failure_in_a_run(pamc, torch):
-    g = synth.torus(14, 10, 2)
-    sched = pamc.schedule(steps=40, sweeps=2, **AUG)
+def hub_graph(n, m, seed):
+    """A random graph plus one vertex joined to most others (its instances
+    keep both field forms and switch within a run)."""
+    rng = np.random.default_rng(seed)
+    base = synth.random_graph(n, m, seed)
+    us, vs = [], []
+    for v in range(n):
+        for e in range(base.row_ptr[v], base.row_ptr[v + 1]):
+            if base.col[e] > v:
+                us.append(v)
+                vs.append(int(base.col[e]))
+    for v in range(n):
+        if rng.random() < 0.7:
+            us.append(v)
+            vs.append(n)
+    return synth.csr_from_edges(n + 1, np.array(us), np.array(vs), np.ones(len(us), np.int32))
+
+
+@pytest.mark.parametrize("graph", ["torus", "hub"])
+def test_allocation_failure_in_a_run(pamc, torch, monkeypatch, graph):
+    if graph == "hub":  # both field forms, switching at the step where beta reaches 0.8
+        monkeypatch.setenv("PAMC_TILE", "0")
+        g = hub_graph(200, 500, 3)
+        sched = pamc.schedule(beta0=0.1, dbeta=0.05, steps=30, sweeps=2, augmented=1, z_rst=25, n_top=4,
+                              mis_trials=2, tau=3)
+    else:
+        g = synth.torus(14, 10, 2)
+        sched = pamc.schedule(steps=40, sweeps=2, **AUG)
     ref = pamc.Instance.csr(g, replicas=64, seed=4)
     want = run(pamc, ref, sched)
     ref.close()
@@ -134,7 +159,7 @@ def test_allocation_failure_in_a_run(pamc, torch):
     n_run = probe.calls - n0  # the requests of the run itself (not of the snapshots after it)
     inst.close()
     assert n_run > 0
-    say(f"case allocation failure at each of {n_run} run requests")
+    say(f"case allocation failure at each of {n_run} run requests ({graph})")
     for k in range(1, n_run + 1):
         c = Counting(pamc, torch)
         inst = pamc.Instance.csr(g, replicas=64, seed=4, allocator=c.al)
