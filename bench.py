@@ -482,7 +482,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fields", choices=["auto", "push", "pull"], default="auto")
-    ap.add_argument("--batched", default="c1",
+    ap.add_argument("--batched", default="c1,c2,c4",
                     help="comma-separated workloads for the plain-vs-batched comparison ('' to skip)")
     ap.add_argument("--batch-count", type=int, default=0, help="runs per batched comparison (0: default)")
     ap.add_argument("--side", default="c1,c3,c4,c4p",
