@@ -436,6 +436,11 @@ def measure(pamc, torch, name, steps, warmup, fields=None):
                                "tts99_s": (tts_scan(ttt, len(runs))[1] or (None, None, None))[2],
                                "target_source": target_source, "final_cuts": finals},
             **({"final_3cuts": finals3} if finals3 else {}),
+            # the dense +-1 instance is of the Sherrington-Kirkpatrick kind:
+            # its best energy per n^1.5 next to Parisi's ground-state value
+            # (context, not a target)
+            **({"energy_per_n_1_5": [r.best_energy / n ** 1.5 for r, _ in runs], "parisi_reference": -0.7633}
+               if w["kind"] == "dense" else {}),
             "roofline": roof}
 
 
