@@ -33,7 +33,7 @@ def workload(name):
                                mis_trials=4, tau=25),
                     desc="augmented PAMC, 100x200 torus +-1 weights (n=20000, degree 4), R=4096, "
                          "500 beta steps x 10 sweeps",
-                    counters="k_sweep_pull_torus100x200_R4096", cpu=dict(R=64, step_s=1.2))
+                    counters="k_sweep_pull_torus100x200_R4096", cpu=dict(R=64, step_s=0.4))
     if name == "c1":
         g = synth.random_graph(800, 19176, seed=1)
         return dict(kind="csr", graph=g, R=256, steps=50, sweeps=5,
