@@ -384,12 +384,20 @@ def measure(pamc, torch, name, steps, warmup, fields=None):
             # LDS for all of a step's sweeps: HBM is idle, and a single
             # instance occupies R/64 compute units; the vector-issue model
             # over the whole chip, with the share of the units it runs on
-            slots = alu_slots_per_attempt(degree, info.coupling_mode)
+            # (with matrix-core fields, the vector work is Philox and the
+            # decision alone, and the products go to the int8 MFMA peak)
+            mma = info.tile_sweeps == 2
+            slots = 25.0 + 9.0 if mma else alu_slots_per_attempt(degree, info.coupling_mode)
             achieved = slots * rate / 1e12
             roof = {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
                     "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
                     "alu_slots_per_attempt": slots, "cus_used": w["R"] // 64,
+                    "frac_of_cus_used": achieved / VALU_PEAK_TSLOTS * 256 / (w["R"] // 64),
                     "hbm_algorithmic_bytes_per_attempt": incremental_field_bytes_per_attempt(p_flip, degree)}
+            if mma:
+                ops = 2.0 * degree * rate / 1e12  # the sparse product's multiply-adds, not the zero blocks
+                roof["mfma_model"] = {"useful_int8_ops_per_attempt": 2.0 * degree, "achieved_tops": ops,
+                                      "peak_tops": MFMA_I8_PEAK_TOPS, "frac": ops / MFMA_I8_PEAK_TOPS}
         else:
             # achieved = the algorithmic bytes of the visits one launch makes
             # (incremental-field layout) over the launch's measured duration

@@ -99,7 +99,7 @@ void free_instance(pamc_instance* I) {
                   I->rs_parent, I->cl_targets, I->cl_sel, I->cl_sizes, I->tr_mstar, I->tr_beta,
                   I->tr_lnq, I->tr_events, I->tr_time, I->tr_dh, I->m3_row_ptr, I->m3_col, I->m3_w,
                   I->m3_labels, I->m3_cut, I->Jd, I->Sd, I->Sd2, I->Gd, I->Cd, I->Ed[0], I->Ed[1],
-                  I->flip_ctr, I->H_scratch, I->ptab, I->g.hubJ, I->pop.HF[0], I->pop.HF[1]};
+                  I->flip_ctr, I->H_scratch, I->ptab, I->g.hubJ, I->pop.HF[0], I->pop.HF[1], I->g.Jt};
   for (void* p : ptrs) dev_free(I, p);
   if (I->pinned) hipHostFree(I->pinned);
   for (hipEvent_t e : I->ev_pool) hipEventDestroy(e);
@@ -216,6 +216,8 @@ struct HostSparse {
   int32_t tile_ok = 0;  // tile-resident sweeps possible (the autotuner may switch them)
   int32_t tile_rows = 0;  // gathered-CSR entries of the largest colour class
   int32_t dual = 0;  // both field forms kept (hub graphs; see dual_field_step)
+  int32_t tmma_ok = 0, nks = 0;  // the matrix-core tile form possible; its 64-column steps
+  std::vector<int8_t> Jt;        // J as matrix-core A fragments
   int32_t hub_tpw = 1, hub_qpw = 1, push_tpw = 1, push_qpw = 1;  // the two forms' wave shapes
   int64_t nnz = 0, W = 0, X = 0;
   std::vector<int32_t> class_ptr, to_internal, to_input, rp2, col2, J2, grow, gcol, gJ, hubJ;
@@ -395,7 +397,29 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
     h.tile_ok = pamc::tile_lds_bytes(h.nq, h.tile_rows) <= pamc::tile_lds_limit() ? 1 : 0;
     if (!h.tile_ok) h.tile_rows = 0;
   }
-  if (h.tile && !h.tile_ok) {  // the rows do not fit: per-class launches
+  // Small instances with int8 couplings can also compute a class's fields
+  // on the matrix cores (k_sweep_tmma): J as 16-row x 64-column A fragments
+  // in the order the kernel reads them (lane l: row 16 t + l % 16, columns
+  // 64 ks + 16 (l / 16) .. + 15).  Dense-ish graphs take that form (a
+  // gathered neighbour costs a read, an add and a dot product; a fragment
+  // covers 16 rows x 64 columns in one instruction), and so do those whose
+  // gathered rows do not fit LDS; PAMC_TILE = 0, 1 or 2 forces none, the
+  // gathered form or this one where it applies.
+  if (allow_dual && h.tile && h.jmode == 2 && h.np <= pamc::tmma_max_n() && 2 * X + 1 <= 2048) {
+    h.tmma_ok = 1;
+    h.nks = (h.np + 63) / 64;
+    const int32_t nrt = (h.np + 15) / 16;
+    h.Jt.assign((size_t)nrt * h.nks * 1024, 0);
+    for (int32_t iv = 0; iv < n; ++iv)
+      for (int32_t e = h.rp2[iv]; e < h.rp2[iv + 1]; ++e) {
+        const int32_t c = h.col2[e], t = iv >> 4, ks = c >> 6, lane = (iv & 15) + 16 * ((c & 63) >> 4);
+        h.Jt[(((size_t)t * h.nks + ks) * 64 + lane) * 16 + (c & 15)] = (int8_t)h.J2[e];
+      }
+    const char* te = getenv("PAMC_TILE");
+    const bool dense_ish = (int64_t)h.nnz >= 16 * (int64_t)n;
+    if (te ? atoi(te) == 2 || !h.tile_ok : dense_ish || !h.tile_ok) h.tile = 2;
+  }
+  if (h.tile == 1 && !h.tile_ok) {  // the rows do not fit: per-class launches
     h.tile = 0;
     if (!choose_fields(n, rp, flags, false, &hubs)) {  // back to the field storage it would have had
       h.pull = 0;
@@ -454,7 +478,7 @@ std::string tune_key(const pamc_instance* I) {
   return std::to_string(I->n) + "/" + std::to_string(I->nnz) + "/" + std::to_string(I->R) + "/" +
          std::to_string(I->ncls) + "/" + std::to_string(I->max_class_quads) + "/" + std::to_string(I->pull) + "/" +
          std::to_string(I->jmode) + "/" + std::to_string(I->potts_K) + "/" + std::to_string(I->nhub) + "/" +
-         std::to_string(I->tile_ok) + "/" + std::to_string(I->rule);
+         std::to_string(I->tile_ok) + "/" + std::to_string(I->tmma_ok) + "/" + std::to_string(I->rule);
 }
 
 void apply_shape(pamc_instance* I, const TuneShape& t) {
@@ -492,6 +516,8 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   I->pull = h.pull;
   I->tile = h.tile;
   I->tile_ok = h.tile_ok;
+  I->tmma_ok = h.tmma_ok;
+  I->nks = h.nks;
   I->tile_rows = h.tile_rows;
   I->nhub = h.nhub;
   for (int k = 0; k < pamc::kMaxHubs; ++k) I->hub_v[k] = h.hub_v[k];
@@ -519,6 +545,7 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   }
   HIP_TRY(dalloc(I, &I->g.class_ptr, ncls + 1), "alloc");
   if (I->nhub) HIP_TRY(dalloc(I, &I->g.hubJ, h.hubJ.size()), "alloc");
+  if (I->tmma_ok) HIP_TRY(dalloc(I, &I->g.Jt, h.Jt.size()), "alloc");
   for (int b = 0; b < 2; ++b) {
     HIP_TRY(dalloc(I, &I->pop.S[b], words), "alloc population");
     if (!I->pull) HIP_TRY(dalloc(I, &I->pop.H[b], hs), "alloc population");
@@ -553,6 +580,8 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
   HIP_TRY(hipMemcpyAsync(I->g.class_ptr, I->class_ptr.data(), sizeof(int32_t) * (ncls + 1), hipMemcpyHostToDevice, I->stream), "upload");
   if (I->nhub)
     HIP_TRY(hipMemcpyAsync(I->g.hubJ, h.hubJ.data(), sizeof(int32_t) * h.hubJ.size(), hipMemcpyHostToDevice, I->stream), "upload");
+  if (I->tmma_ok)
+    HIP_TRY(hipMemcpyAsync(I->g.Jt, h.Jt.data(), h.Jt.size(), hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(hipMemcpyAsync(I->to_internal_dev, I->to_internal.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, I->stream), "upload");
   HIP_TRY(pamc::prepare_kernel_lds(), "hipFuncSetAttribute");
   apply_cached_shape(I);
@@ -1755,6 +1784,7 @@ pamc_status pamc_autotune(pamc_instance* I, double beta, int32_t sweeps, int32_t
     }
   }
   std::vector<TuneShape> cand;
+  if (I->tmma_ok) cand.push_back({2, initial.tpw, initial.qpw});  // matrix-core fields
   for (int tile : {0, 1}) {
     if (tile && !I->tile_ok) continue;
     if (tile) {

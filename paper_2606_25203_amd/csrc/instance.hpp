@@ -41,6 +41,9 @@ struct GraphDev {
   int32_t* gcol = nullptr;
   int32_t* gJ = nullptr;
   int32_t* class_ptr = nullptr;
+  // small int8-coupling instances: J as 16-row x 64-column matrix-core A
+  // fragments, [row tile][column step][lane][16 bytes]
+  int8_t* Jt = nullptr;
   // hubs of the gathered-field mode: J between each vertex and each hub
   // [np][kMaxHubs] (0 where not adjacent)
   int32_t* hubJ = nullptr;
@@ -62,7 +65,10 @@ struct pamc_instance {
   std::vector<int32_t> to_internal, to_input, class_ptr;
   int32_t max_class_quads = 0;
   int32_t pull = 0;       // 1: fields gathered at visit time (no field array)
-  int32_t tile = 0;       // 1: a step's sweeps of a replica tile in one work-group (small pull instances)
+  int32_t tile = 0;       // a step's sweeps of a replica tile in one work-group (small pull instances):
+                          // 1 fields gathered from LDS, 2 fields from matrix-core products
+  int32_t tmma_ok = 0;    // the matrix-core tile form possible (int8 couplings, n <= 1024)
+  int32_t nks = 0;        // its 64-column steps
   int32_t tile_rows = 0;  // gathered-CSR entries of the largest colour class (staged in LDS by tile sweeps)
   int32_t tile_ok = 0;    // tile-resident sweeps possible
   int32_t nhub = 0;       // hubs (pull mode): vertices whose fields are kept incrementally
@@ -158,6 +164,8 @@ struct Desc {
   int32_t *HF0, *HF1;     // hub fields [kMaxHubs][R], one per population buffer
   int32_t nhub, hub_v0, hub_v1;
   int32_t tile_rows;      // tile sweeps: gathered-CSR entries of the largest class
+  const int8_t* Jt;       // matrix-core tile sweeps: J fragments
+  int32_t nks;            // their 64-column steps
   int32_t* order;
   uint32_t* thr;
   uint32_t *S0, *S1;
@@ -199,7 +207,7 @@ struct Batch {
   };
   Launch init_spins, init_fields, thr, thr_dense, gather, cl_mis, cl_apply, dh;
   Launch sweep[kGroups];
-  Launch tile[3];          // tile-resident sweeps, per coupling mode
+  Launch tile[4];          // tile-resident sweeps: per coupling mode, then the matrix-core form
   int64_t tile_lds = 0;    // their dynamic LDS bytes
   Desc* d_desc = nullptr;
   int32_t n = 0;
@@ -268,6 +276,8 @@ int32_t cluster_max_n();
 int32_t sweep_waves();  // wavefronts per sweep work-group
 int32_t tile_max_quads();  // vertex quads a tile-resident sweep holds in LDS
 int64_t tile_lds_bytes(int32_t nq, int32_t rows);  // its LDS: spins, table, a class's gathered rows
+int32_t tmma_max_n();                               // largest padded n of the matrix-core tile form
+int64_t tmma_lds_bytes(int32_t nks);                // its LDS: replica-major spins, table
 int64_t tile_lds_limit();
 hipError_t prepare_kernel_lds();
 

@@ -467,6 +467,134 @@ __global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tile(const Desc* __re
 }
 
 // ---------------------------------------------------------------------------
+// The tile-resident step with the fields of a colour class computed on the
+// matrix cores, for small instances with int8 couplings (at most
+// kTmmaMaxN vertices): the class's fields for the tile's 64 replicas are
+// h = J[class rows, :] . S, an int8 x int8 -> int32 product (exact: |h| <=
+// 127 n), so a dense-ish graph costs one v_mfma_i32_16x16x64_i8 per 16
+// rows, 16 replicas and 64 vertices instead of a gather per neighbour.
+// The spins sit in LDS replica-major (int8 [64][npk + 16], the B operand);
+// J sits in HBM as 16-row x 64-column fragments in the order the A operand
+// wants them (1 KB per fragment: lane l holds bytes 16 (l / 16) .. + 15 of
+// row l % 16).  Vertices of one class share no edge (J = 0 between them),
+// so the product may read the class's spins while they change.  Each wave
+// keeps one group of 16 replicas (wave % 4) and takes 16-row tiles of the
+// class in turn; the product leaves in each lane the four fields of one
+// vertex quad for one replica, exactly the unit of one Philox block, and
+// the decisions are those of the other sweep kernels (same fields, words
+// and thresholds), so the trajectory is the same.
+// ---------------------------------------------------------------------------
+constexpr int kTmmaMaxN = 1024;  // vertices (padded): 64 x 1040 B of LDS spins
+constexpr int kTmmaMaxKs = kTmmaMaxN / 64;
+
+__global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tmma(const Desc* __restrict__ D,
+                                                                const uint64_t* __restrict__ map) {
+  extern __shared__ uint32_t tl[];  // int8 spins [64][rowb], then the threshold table
+  __shared__ int64_t red[kTileWaves][kLanes];
+  __shared__ int32_t fred[kTileWaves];
+  int inst, tile;
+  if (!resolve(map, inst, tile)) return;
+  const Desc& d = D[inst];
+  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
+  const int nsw = st->nsweeps_now;
+  if (!st->active || nsw <= 0) return;
+  const int cur = st->cur;
+  const int nq = d.nq, nks = d.nks;
+  const int rowb = 64 * nks + 16;  // bytes per replica row (padded against bank conflicts)
+  const int32_t Xt = (int32_t)st->table_x;
+  PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0) + (size_t)tile * nq * kLanes;
+  PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
+  const PAMC_GLOBAL uint32_t* __restrict__ thr_g = gmem((const uint32_t*)d.thr);
+  const PAMC_GLOBAL int32_t* __restrict__ order = gmem((const int32_t*)d.order);
+  const PAMC_GLOBAL int32_t* __restrict__ class_ptr = gmem(d.class_ptr);
+  const PAMC_GLOBAL int8_t* __restrict__ Jt = gmem(d.Jt);
+  int8_t* Sb = reinterpret_cast<int8_t*>(tl);
+  uint32_t* thr_s = tl + 16 * rowb;  // 64 rowb bytes
+  // the tile's spin words into replica-major rows: word (q, l) holds the
+  // bytes of vertices 4q .. 4q + 3 of replica l
+  for (int i = threadIdx.x; i < nq * kLanes; i += blockDim.x)
+    *reinterpret_cast<uint32_t*>(Sb + (i & 63) * rowb + 4 * (i >> 6)) = S[i];
+  for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int grp = wave & 3;                 // the wave's 16 replicas
+  const int rl = 16 * grp + (lane & 15);    // the lane's replica in the tile
+  const uint32_t r = (uint32_t)(tile * kLanes + rl);
+  const int kq = lane >> 4;                 // the lane's quad within a 16-row tile
+  const int8_t* brow = Sb + rl * rowb + 16 * kq;  // B operand: replica rl, bytes 16 kq ..
+  const bool metropolis = d.rule == 1;
+  int64_t dE = 0;
+  int32_t nflip = 0;
+  for (int sw_i = 0; sw_i < nsw; ++sw_i) {
+    const uint32_t gs = st->gs + (uint32_t)sw_i;
+    for (int p = 0; p < d.ncls; ++p) {
+      const int cls = order[sw_i * d.ncls + p];
+      const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
+      const int q0 = v0 >> 2, q1 = (v1 + 3) >> 2;  // the class's quads
+      const int t0 = q0 >> 2, t1 = (q1 + 3) >> 2;  // its 16-row tiles
+      __syncthreads();  // the previous class's spins are in
+      for (int t = t0 + (wave >> 2); t < t1; t += kTileWaves / 4) {
+        // every A fragment of the row tile first, then the products
+        const PAMC_GLOBAL int8_t* arow = Jt + ((size_t)t * nks * 64 + lane) * 16;
+        i32x4 av[kTmmaMaxKs];
+#pragma unroll
+        for (int ks = 0; ks < kTmmaMaxKs; ++ks)
+          if (ks < nks) av[ks] = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(arow + (size_t)ks * 1024);
+        i32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < kTmmaMaxKs; ++ks)
+          if (ks < nks)
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[ks], *reinterpret_cast<const i32x4*>(brow + 64 * ks),
+                                                        acc, 0, 0, 0);
+        // the lane's quad: vertices 4q .. 4q + 3 of the tile, replica rl
+        const int q = 4 * t + kq;
+        if (q < q0 || q >= q1) continue;
+        uint32_t* wp = reinterpret_cast<uint32_t*>(Sb + rl * rowb + 4 * q);
+        const uint32_t sw = *wp;
+        const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
+        uint32_t flipmask = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int v = 4 * q + k;
+          if (v < v0 || v >= v1) continue;
+          const int32_t s = __builtin_amdgcn_sbfe((int32_t)sw, 8u * k, 8u);
+          const int32_t x = __mul24(s, acc[k]);
+          const int32_t xi = min(max(x, -Xt), Xt) + Xt;
+          const bool flip = (pick(rnd, k) < thr_s[xi]) || (metropolis && x <= 0);
+          dE += flip ? (int64_t)x : 0;
+          flipmask |= flip ? (0xFEu << (8 * k)) : 0u;
+          nflip += flip ? 1 : 0;
+        }
+        if (flipmask) *wp = sw ^ flipmask;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nq * kLanes; i += blockDim.x)
+    S[i] = *reinterpret_cast<const uint32_t*>(Sb + (i & 63) * rowb + 4 * (i >> 6));
+  red[wave][lane] = 2 * dE;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nflip += __shfl_xor(nflip, o, 64);
+  if (lane == 0) fred[wave] = nflip;
+  __syncthreads();
+  if (wave == 0) {  // replica rl = 16 (w % 4) + (l % 16): the waves w and lanes l holding it
+    const int g = lane >> 4, c = lane & 15;
+    int64_t sum = 0;
+#pragma unroll
+    for (int w = g; w < kTileWaves; w += 4)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) sum += red[w][16 * kk + c];
+    E[tile * kLanes + lane] += sum;
+    if (d.flip_ctr && lane == 0) {
+      int64_t f = 0;
+      for (int w = 0; w < kTileWaves; ++w) f += fred[w];
+      __hip_atomic_fetch_add((unsigned long long*)&d.flip_ctr[blockIdx.x & 255], (unsigned long long)f,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The same class phase with incremental fields: x = s*h from the field
 // array; on a flip E += 2x and every neighbour field gets 2 J s_new by a
 // coalesced no-return atomic.  Used where gathering is dearer (high degree,
@@ -1949,13 +2077,16 @@ int32_t sweep_waves() { return kSweepWaves; }
 int32_t tile_max_quads() { return kTileMaxQuads; }
 int64_t tile_lds_bytes(int32_t nq, int32_t rows) { return (int64_t)nq * kLanes * 4 + kThrLds * 4 + 8 * (int64_t)rows; }
 int64_t tile_lds_limit() { return kTileLdsBytes; }
+int32_t tmma_max_n() { return kTmmaMaxN; }
+int64_t tmma_lds_bytes(int32_t nks) { return 64 * (64 * (int64_t)nks + 16) + kThrLds * 4; }
 
 // Kernels whose dynamic LDS may exceed the default limit.
 hipError_t prepare_kernel_lds() {
   hipError_t e = hipFuncSetAttribute((const void*)k_cl_mis, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      kClusterMaxN * 5 + 64);
   if (e != hipSuccess) return e;
-  for (const void* k : {(const void*)k_sweep_tile<0>, (const void*)k_sweep_tile<1>, (const void*)k_sweep_tile<2>})
+  for (const void* k : {(const void*)k_sweep_tile<0>, (const void*)k_sweep_tile<1>, (const void*)k_sweep_tile<2>,
+                        (const void*)k_sweep_tmma})
     if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kTileLdsBytes)) != hipSuccess)
       return e;
   return hipFuncSetAttribute((const void*)k_rs_select, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2025,6 +2156,8 @@ Desc make_desc(const pamc_instance* I) {
   d.tr_cap = I->tr_cap;
   d.qpw = I->qpw;
   d.tile_rows = I->tile_rows;
+  d.Jt = I->g.Jt;
+  d.nks = I->nks;
   d.order_cap = I->order_cap;
   d.k0 = (uint32_t)I->seed;
   d.k1 = (uint32_t)(I->seed >> 32);
@@ -2182,7 +2315,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     }
   }
   std::vector<uint64_t> m_init, m_fields, m_thr, m_gather, m_mis, m_apply, m_dh;
-  std::vector<std::vector<uint64_t>> m_sweep(Batch::kGroups), m_tile(3);
+  std::vector<std::vector<uint64_t>> m_sweep(Batch::kGroups), m_tile(4);
   b.max_ncls = 0;
   for (int g = 0; g < Batch::kGroups; ++g) b.group_ncls[g] = 0;
   b.max_sweeps = 1;
@@ -2197,7 +2330,10 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     add_blocks(m_fields, i, field_blocks(I), false);
     add_blocks(m_thr, i, kThrBlocks, false);
     add_blocks(m_gather, i, (int64_t)I->T * ((I->nq + kGatherQuadsPerBlock - 1) / kGatherQuadsPerBlock), true);
-    if (I->tile) {  // one work-group per replica tile walks the whole step
+    if (I->tile == 2) {  // the same with matrix-core fields
+      add_blocks(m_tile[3], i, I->T, false);
+      b.tile_lds = std::max<int64_t>(b.tile_lds, tmma_lds_bytes(I->nks));
+    } else if (I->tile) {  // one work-group per replica tile walks the whole step
       add_blocks(m_tile[I->jmode], i, I->T, false);
       b.tile_lds = std::max<int64_t>(b.tile_lds, tile_lds_bytes(I->nq, I->tile_rows));
     } else {
@@ -2248,7 +2384,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
   if ((e = up(m_dh, b.dh)) != hipSuccess) return e;
   for (int g = 0; g < Batch::kGroups; ++g)
     if ((e = up(m_sweep[g], b.sweep[g])) != hipSuccess) return e;
-  for (int g = 0; g < 3; ++g)
+  for (int g = 0; g < 4; ++g)
     if ((e = up(m_tile[g], b.tile[g])) != hipSuccess) return e;
   // the staging vectors are local: wait for the copies before they go
   return hipStreamSynchronize(b.stream);
@@ -2303,8 +2439,8 @@ static hipError_t batch_sweeps(Batch& b, int32_t nsweeps, int32_t commit = -1) {
   if (b.thr.grid) k_thresholds<<<b.thr.grid, 256, 0, b.stream>>>(b.d_desc, b.thr.map, commit);
   int64_t launches = 0;
   if (prof) hipEventRecord(next_event(P), b.stream);
-  static const SweepTileKernel tile_kernels[3] = {k_sweep_tile<0>, k_sweep_tile<1>, k_sweep_tile<2>};
-  for (int g = 0; g < 3; ++g)
+  static const SweepTileKernel tile_kernels[4] = {k_sweep_tile<0>, k_sweep_tile<1>, k_sweep_tile<2>, k_sweep_tmma};
+  for (int g = 0; g < 4; ++g)
     if (b.tile[g].grid) {  // every sweep of the step, in one launch
       tile_kernels[g]<<<b.tile[g].grid, kTileWaves * 64, b.tile_lds, b.stream>>>(b.d_desc, b.tile[g].map);
       ++launches;

@@ -457,6 +457,7 @@ def test_tile_resident_sweeps(pamc, monkeypatch, jmode, rule, gname, R):
     resampling, cluster moves and the controller."""
     g = GRAPHS[gname]()
     monkeypatch.setenv("PAMC_JMODE", str(jmode))
+    monkeypatch.setenv("PAMC_TILE", "1")  # the gathered form, also where the matrix-core one would be taken
     say(f"case tile-resident sweeps {gname} R={R} jmode={jmode} rule={rule}")
     inst = pamc.Instance.csr(g, replicas=R, seed=17, rule=rule, fields="pull")
     info = inst.info()
@@ -469,6 +470,81 @@ def test_tile_resident_sweeps(pamc, monkeypatch, jmode, rule, gname, R):
                                        n_top=6, mis_trials=3, win_short=4, win_long=6, max_distinct_short=2,
                                        max_distinct_long=3, tau=3))
     inst.close()
+
+
+def int8_graph(n, m, seed):
+    """A random graph with weights +-1, +-2 and (one in ten) +-127: the
+    extremes of int8, with row sums of |w| within the tile forms' table."""
+    rng = np.random.default_rng(seed)
+    g = synth.random_graph(n, m, seed)
+    us, vs = [], []
+    for v in range(n):
+        for e in range(g.row_ptr[v], g.row_ptr[v + 1]):
+            if g.col[e] > v:
+                us.append(v)
+                vs.append(int(g.col[e]))
+    w = rng.choice([1, 2, 127], p=[0.45, 0.45, 0.1], size=len(us)) * rng.choice([-1, 1], size=len(us))
+    return synth.csr_from_edges(n, np.array(us), np.array(vs), w.astype(np.int32))
+
+
+MMA_GRAPHS = {
+    "c1_shape_small": GRAPHS["c1_shape_small"],   # n = 301: a ragged last quad and row tile
+    "torus_pm1": GRAPHS["torus_pm1"],             # sparse: most 16 x 64 blocks are zero
+    "dense_ish": GRAPHS["dense_ish"],             # one 64-column block
+    "int8_weights": lambda: int8_graph(200, 1700, 6),
+    "n1024": lambda: synth.random_graph(1024, 12000, 9),  # the largest: 16 column blocks
+    "n1021": lambda: synth.random_graph(1021, 9000, 10),
+}
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+@pytest.mark.parametrize("gname,R", [("c1_shape_small", 192), ("torus_pm1", 64), ("dense_ish", 128),
+                                     ("int8_weights", 64), ("n1024", 128), ("n1021", 64)])
+def test_tile_mfma_sweeps(pamc, monkeypatch, rule, gname, R):
+    """The tile-resident step with each colour class's fields computed on the
+    matrix cores (int8 couplings x int8 spins, 16 x 64 blocks): the same
+    trajectory as the oracle through sweeps, resampling, cluster moves and
+    the controller."""
+    g = MMA_GRAPHS[gname]()
+    monkeypatch.setenv("PAMC_TILE", "2")
+    say(f"case tile-resident matrix-core sweeps {gname} n={g.n} R={R} rule={rule}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=23, rule=rule)
+    info = inst.info()
+    assert info.tile_sweeps == 2 and info.coupling_mode == 2
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 23, rule=rule)
+    inst.sweep(0.3 / (40 if gname == "int8_weights" else 1), 3)
+    o.sweep(0.3 / (40 if gname == "int8_weights" else 1), 3)
+    same_state(inst, o, "sweeps")
+    scale = 1 / 40 if gname == "int8_weights" else 1
+    compare_anneal(pamc, inst, o, dict(beta0=0.1 * scale, dbeta=0.05 * scale, steps=40, sweeps=3, augmented=1,
+                                       z_rst=30, n_top=6, mis_trials=3, win_short=4, win_long=6,
+                                       max_distinct_short=2, max_distinct_long=3, tau=3))
+    inst.close()
+
+
+def test_tile_mfma_default_and_mixed_batch(pamc):
+    """Dense-ish int8 instances take the matrix-core form by default, sparse
+    ones and those with wider couplings the gathered form, and more than
+    1024 vertices neither.  A batch mixing both tile forms and per-class launches follows
+    the oracle on every instance."""
+    dense = synth.random_graph(301, 2500, 3)     # 16.6 entries per row
+    sparse = synth.torus(14, 10, 2)              # 4 per row
+    t = synth.torus(12, 9, 5)
+    wide = synth.Graph(t.n, t.row_ptr, t.col, (200 * t.w).astype(np.int32))  # beyond int8: 24-bit products
+    big = synth.random_graph(2052, 3000, 8)
+    say("case matrix-core tile form by default, mixed batch")
+    insts = [pamc.Instance.csr(g, replicas=128, seed=s) for g, s in ((dense, 1), (sparse, 2), (wide, 3), (big, 4))]
+    assert [i.info().tile_sweeps for i in insts] == [2, 1, 1, 0]
+    assert insts[2].info().coupling_mode == 1
+    sched = pamc.schedule(beta0=0.1, dbeta=0.1, steps=12, sweeps=2, augmented=1, z_rst=10, n_top=4, tau=3)
+    res = pamc.anneal_batch(insts, [sched] * 4)
+    for inst, g, s, r in zip(insts, (dense, sparse, wide, big), (1, 2, 3, 4), res):
+        o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, 128, s)
+        ores = o.anneal(oracle.default_schedule(beta0=0.1, dbeta=0.1, steps=12, sweeps=2, augmented=1, z_rst=10,
+                                                n_top=4, tau=3))
+        assert (r.best_cut, r.n_cluster_moves, r.n_reheats) == (ores.best_cut, ores.n_cluster_moves, ores.n_reheats)
+        same_state(inst, o, "mixed tile forms")
+        inst.close()
 
 
 def test_tile_resident_largest_and_mixed_batch(pamc):
