@@ -196,10 +196,12 @@ pamc_status pamc_reset_population(pamc_instance* inst, uint64_t seed);
  * 1 (24-bit) or 2 (int8 couplings with 4-way dot products); tile_sweeps 1:
  * small instance whose step's sweeps run in one launch, one work-group per
  * replica tile holding the tile's spins in LDS and gathering its neighbours;
- * tile_sweeps 2: the same launch shape, with each colour class's fields
- * computed on the matrix cores as int8 products of 16 x 64 coupling blocks
- * with the tile's spins (n <= 1024, int8 couplings); hubs: vertices whose
- * fields are kept while the others are gathered. */
+ * tile_sweeps 2: one launch per step as well, with each colour class's
+ * fields computed on the matrix cores as int8 products of 16 x 64 coupling
+ * blocks with the spins (n <= 1024, int8 couplings), one work-group per
+ * 16-replica group of a tile while the launch has at most 128 tiles, else
+ * one per tile; hubs: vertices whose fields are kept while the others are
+ * gathered. */
 typedef struct {
   int32_t n, replicas, num_classes, dense, pull;
   int64_t nnz, W, X; /* X = max_v sum_j |J_vj| */

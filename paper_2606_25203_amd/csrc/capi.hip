@@ -400,11 +400,13 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
   // Small instances with int8 couplings can also compute a class's fields
   // on the matrix cores (k_sweep_tmma): J as 16-row x 64-column A fragments
   // in the order the kernel reads them (lane l: row 16 t + l % 16, columns
-  // 64 ks + 16 (l / 16) .. + 15).  Dense-ish graphs take that form (a
-  // gathered neighbour costs a read, an add and a dot product; a fragment
-  // covers 16 rows x 64 columns in one instruction), and so do those whose
-  // gathered rows do not fit LDS; PAMC_TILE = 0, 1 or 2 forces none, the
-  // gathered form or this one where it applies.
+  // 64 ks + 16 (l / 16) .. + 15).  Per attempt the gathered form reads 4
+  // bytes of LDS per neighbour and this one 4 bytes of fragments per 64
+  // columns through the vector L1, which moves half as many bytes per
+  // cycle: so graphs whose average degree is at least n_pad / 32 (and 8)
+  // take this form, and so do those whose gathered rows do not fit LDS.
+  // PAMC_TILE = 0, 1 or 2 forces none, the gathered form or this one where
+  // it applies.
   if (allow_dual && h.tile && h.jmode == 2 && h.np <= pamc::tmma_max_n() && 2 * X + 1 <= 2048) {
     h.tmma_ok = 1;
     h.nks = (h.np + 63) / 64;
@@ -416,7 +418,7 @@ pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const in
         h.Jt[(((size_t)t * h.nks + ks) * 64 + lane) * 16 + (c & 15)] = (int8_t)h.J2[e];
       }
     const char* te = getenv("PAMC_TILE");
-    const bool dense_ish = (int64_t)h.nnz >= 16 * (int64_t)n;
+    const bool dense_ish = (int64_t)h.nnz >= 8 * (int64_t)n && 32 * (int64_t)h.nnz >= (int64_t)n * h.np;
     if (te ? atoi(te) == 2 || !h.tile_ok : dense_ish || !h.tile_ok) h.tile = 2;
   }
   if (h.tile == 1 && !h.tile_ok) {  // the rows do not fit: per-class launches

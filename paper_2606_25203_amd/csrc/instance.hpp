@@ -208,7 +208,9 @@ struct Batch {
   Launch init_spins, init_fields, thr, thr_dense, gather, cl_mis, cl_apply, dh;
   Launch sweep[kGroups];
   Launch tile[4];          // tile-resident sweeps: per coupling mode, then the matrix-core form
-  int64_t tile_lds = 0;    // their dynamic LDS bytes
+  int64_t tile_lds[4] = {0, 0, 0, 0};  // their dynamic LDS bytes
+  int32_t tmma_waves = 16;             // waves per work-group of the matrix-core form (16 or 8)
+  bool tmma_groups = false;            // matrix-core form: one work-group per 16-replica group
   Desc* d_desc = nullptr;
   int32_t n = 0;
   hipStream_t stream = nullptr;
@@ -277,7 +279,7 @@ int32_t sweep_waves();  // wavefronts per sweep work-group
 int32_t tile_max_quads();  // vertex quads a tile-resident sweep holds in LDS
 int64_t tile_lds_bytes(int32_t nq, int32_t rows);  // its LDS: spins, table, a class's gathered rows
 int32_t tmma_max_n();                               // largest padded n of the matrix-core tile form
-int64_t tmma_lds_bytes(int32_t nks);                // its LDS: replica-major spins, table
+int64_t tmma_lds_bytes(int32_t nks, int32_t rows);                // its LDS: replica-major spins, table
 int64_t tile_lds_limit();
 hipError_t prepare_kernel_lds();
 

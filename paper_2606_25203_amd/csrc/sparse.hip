@@ -484,14 +484,18 @@ __global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tile(const Desc* __re
 // the decisions are those of the other sweep kernels (same fields, words
 // and thresholds), so the trajectory is the same.
 // ---------------------------------------------------------------------------
+constexpr int kComputeUnits = 256;      // MI355X
+constexpr int64_t kCuLdsBytes = 160 * 1024;
 constexpr int kTmmaMaxN = 1024;  // vertices (padded): 64 x 1040 B of LDS spins
 constexpr int kTmmaMaxKs = kTmmaMaxN / 64;
 
-__global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tmma(const Desc* __restrict__ D,
-                                                                const uint64_t* __restrict__ map) {
+// NW waves per work-group (16, or 8 so that two work-groups share a
+// compute unit when a batch has enough of them).
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) k_sweep_tmma(const Desc* __restrict__ D, const uint64_t* __restrict__ map) {
   extern __shared__ uint32_t tl[];  // int8 spins [64][rowb], then the threshold table
-  __shared__ int64_t red[kTileWaves][kLanes];
-  __shared__ int32_t fred[kTileWaves];
+  __shared__ int64_t red[NW][kLanes];
+  __shared__ int32_t fred[NW];
   int inst, tile;
   if (!resolve(map, inst, tile)) return;
   const Desc& d = D[inst];
@@ -533,25 +537,28 @@ __global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tmma(const Desc* __re
       const int q0 = v0 >> 2, q1 = (v1 + 3) >> 2;  // the class's quads
       const int t0 = q0 >> 2, t1 = (q1 + 3) >> 2;  // its 16-row tiles
       __syncthreads();  // the previous class's spins are in
-      for (int t = t0 + (wave >> 2); t < t1; t += kTileWaves / 4) {
-        // every A fragment of the row tile first, then the products
+      for (int t = t0 + (wave >> 2); t < t1; t += NW / 4) {
+        // every A fragment of the row tile first; the lane's random words
+        // (they do not depend on the fields) while the fragments arrive;
+        // then the products
         const PAMC_GLOBAL int8_t* arow = Jt + ((size_t)t * nks * 64 + lane) * 16;
         i32x4 av[kTmmaMaxKs];
 #pragma unroll
         for (int ks = 0; ks < kTmmaMaxKs; ++ks)
           if (ks < nks) av[ks] = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(arow + (size_t)ks * 1024);
+        // the lane's quad: vertices 4q .. 4q + 3 of the tile, replica rl
+        const int q = 4 * t + kq;
+        const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
+        __builtin_amdgcn_sched_barrier(0);
         i32x4 acc = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < kTmmaMaxKs; ++ks)
           if (ks < nks)
             acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[ks], *reinterpret_cast<const i32x4*>(brow + 64 * ks),
                                                         acc, 0, 0, 0);
-        // the lane's quad: vertices 4q .. 4q + 3 of the tile, replica rl
-        const int q = 4 * t + kq;
         if (q < q0 || q >= q1) continue;
         uint32_t* wp = reinterpret_cast<uint32_t*>(Sb + rl * rowb + 4 * q);
         const uint32_t sw = *wp;
-        const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
         uint32_t flipmask = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -581,13 +588,123 @@ __global__ void __launch_bounds__(kTileWaves * 64) k_sweep_tmma(const Desc* __re
     const int g = lane >> 4, c = lane & 15;
     int64_t sum = 0;
 #pragma unroll
-    for (int w = g; w < kTileWaves; w += 4)
+    for (int w = g; w < NW; w += 4)
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) sum += red[w][16 * kk + c];
     E[tile * kLanes + lane] += sum;
     if (d.flip_ctr && lane == 0) {
       int64_t f = 0;
-      for (int w = 0; w < kTileWaves; ++w) f += fred[w];
+      for (int w = 0; w < NW; ++w) f += fred[w];
+      __hip_atomic_fetch_add((unsigned long long*)&d.flip_ctr[blockIdx.x & 255], (unsigned long long)f,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// The same step with one work-group per 16-replica group of a tile (four
+// per tile): a single instance spreads over four times the compute units,
+// each holding a quarter of the tile's spins.  Wave w takes the class's
+// 16-row tiles w, w + NW, ...; lane l's replica is 16 g + l % 16 and its
+// quad 4 t + l / 16, as above.
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) k_sweep_tmma_g(const Desc* __restrict__ D,
+                                                          const uint64_t* __restrict__ map) {
+  extern __shared__ uint32_t tl[];  // int8 spins [16][rowb], then the threshold table
+  __shared__ int64_t red[NW][kLanes];
+  __shared__ int32_t fred[NW];
+  int inst, lb;
+  if (!resolve(map, inst, lb)) return;
+  const Desc& d = D[inst];
+  const PAMC_GLOBAL RunState* __restrict__ st = gmem((const RunState*)d.st);
+  const int nsw = st->nsweeps_now;
+  if (!st->active || nsw <= 0) return;
+  const int tile = lb >> 2, grp = lb & 3;
+  const int cur = st->cur;
+  const int nq = d.nq, nks = d.nks;
+  const int rowb = 64 * nks + 16;  // bytes per replica row (padded against bank conflicts)
+  const int32_t Xt = (int32_t)st->table_x;
+  PAMC_GLOBAL uint32_t* __restrict__ S = gmem(cur ? d.S1 : d.S0) + (size_t)tile * nq * kLanes + 16 * grp;
+  PAMC_GLOBAL int64_t* __restrict__ E = gmem(cur ? d.E1 : d.E0);
+  const PAMC_GLOBAL uint32_t* __restrict__ thr_g = gmem((const uint32_t*)d.thr);
+  const PAMC_GLOBAL int32_t* __restrict__ order = gmem((const int32_t*)d.order);
+  const PAMC_GLOBAL int32_t* __restrict__ class_ptr = gmem(d.class_ptr);
+  const PAMC_GLOBAL int8_t* __restrict__ Jt = gmem(d.Jt);
+  int8_t* Sb = reinterpret_cast<int8_t*>(tl);
+  uint32_t* thr_s = tl + 4 * rowb;  // 16 rowb bytes
+  // the group's spin words (q, 16 grp + c) into replica-major rows
+  for (int i = threadIdx.x; i < nq * 16; i += blockDim.x)
+    *reinterpret_cast<uint32_t*>(Sb + (i & 15) * rowb + 4 * (i >> 4)) = S[(i >> 4) * kLanes + (i & 15)];
+  for (int i = threadIdx.x; i <= 2 * Xt; i += blockDim.x) thr_s[i] = thr_g[i];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = lane & 15;                  // the lane's replica in the group
+  const uint32_t r = (uint32_t)(tile * kLanes + 16 * grp + c);
+  const int kq = lane >> 4;                 // the lane's quad within a 16-row tile
+  const int8_t* brow = Sb + c * rowb + 16 * kq;  // B operand: replica c, bytes 16 kq ..
+  const bool metropolis = d.rule == 1;
+  int64_t dE = 0;
+  int32_t nflip = 0;
+  for (int sw_i = 0; sw_i < nsw; ++sw_i) {
+    const uint32_t gs = st->gs + (uint32_t)sw_i;
+    for (int p = 0; p < d.ncls; ++p) {
+      const int cls = order[sw_i * d.ncls + p];
+      const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
+      const int q0 = v0 >> 2, q1 = (v1 + 3) >> 2;  // the class's quads
+      const int t0 = q0 >> 2, t1 = (q1 + 3) >> 2;  // its 16-row tiles
+      __syncthreads();  // the previous class's spins are in
+      for (int t = t0 + wave; t < t1; t += NW) {
+        const PAMC_GLOBAL int8_t* arow = Jt + ((size_t)t * nks * 64 + lane) * 16;
+        i32x4 av[kTmmaMaxKs];
+#pragma unroll
+        for (int ks = 0; ks < kTmmaMaxKs; ++ks)
+          if (ks < nks) av[ks] = *reinterpret_cast<const PAMC_GLOBAL i32x4*>(arow + (size_t)ks * 1024);
+        const int q = 4 * t + kq;
+        const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
+        __builtin_amdgcn_sched_barrier(0);
+        i32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < kTmmaMaxKs; ++ks)
+          if (ks < nks)
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[ks], *reinterpret_cast<const i32x4*>(brow + 64 * ks),
+                                                        acc, 0, 0, 0);
+        if (q < q0 || q >= q1) continue;
+        uint32_t* wp = reinterpret_cast<uint32_t*>(Sb + c * rowb + 4 * q);
+        const uint32_t sw = *wp;
+        uint32_t flipmask = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int v = 4 * q + k;
+          if (v < v0 || v >= v1) continue;
+          const int32_t s = __builtin_amdgcn_sbfe((int32_t)sw, 8u * k, 8u);
+          const int32_t x = __mul24(s, acc[k]);
+          const int32_t xi = min(max(x, -Xt), Xt) + Xt;
+          const bool flip = (pick(rnd, k) < thr_s[xi]) || (metropolis && x <= 0);
+          dE += flip ? (int64_t)x : 0;
+          flipmask |= flip ? (0xFEu << (8 * k)) : 0u;
+          nflip += flip ? 1 : 0;
+        }
+        if (flipmask) *wp = sw ^ flipmask;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nq * 16; i += blockDim.x)
+    S[(i >> 4) * kLanes + (i & 15)] = *reinterpret_cast<const uint32_t*>(Sb + (i & 15) * rowb + 4 * (i >> 4));
+  red[wave][lane] = dE;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nflip += __shfl_xor(nflip, o, 64);
+  if (lane == 0) fred[wave] = nflip;
+  __syncthreads();
+  if (wave == 0 && lane < 16) {  // replica 16 grp + lane: lanes lane, 16 + lane, ... of every wave
+    int64_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) sum += red[w][16 * kk + lane];
+    E[tile * kLanes + 16 * grp + lane] += 2 * sum;
+    if (d.flip_ctr && lane == 0) {
+      int64_t f = 0;
+      for (int w = 0; w < NW; ++w) f += fred[w];
       __hip_atomic_fetch_add((unsigned long long*)&d.flip_ctr[blockIdx.x & 255], (unsigned long long)f,
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -2078,7 +2195,7 @@ int32_t tile_max_quads() { return kTileMaxQuads; }
 int64_t tile_lds_bytes(int32_t nq, int32_t rows) { return (int64_t)nq * kLanes * 4 + kThrLds * 4 + 8 * (int64_t)rows; }
 int64_t tile_lds_limit() { return kTileLdsBytes; }
 int32_t tmma_max_n() { return kTmmaMaxN; }
-int64_t tmma_lds_bytes(int32_t nks) { return 64 * (64 * (int64_t)nks + 16) + kThrLds * 4; }
+int64_t tmma_lds_bytes(int32_t nks, int32_t rows) { return rows * (64 * (int64_t)nks + 16) + kThrLds * 4; }
 
 // Kernels whose dynamic LDS may exceed the default limit.
 hipError_t prepare_kernel_lds() {
@@ -2086,7 +2203,7 @@ hipError_t prepare_kernel_lds() {
                                      kClusterMaxN * 5 + 64);
   if (e != hipSuccess) return e;
   for (const void* k : {(const void*)k_sweep_tile<0>, (const void*)k_sweep_tile<1>, (const void*)k_sweep_tile<2>,
-                        (const void*)k_sweep_tmma})
+                        (const void*)k_sweep_tmma<16>, (const void*)k_sweep_tmma<8>, (const void*)k_sweep_tmma_g<8>})
     if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kTileLdsBytes)) != hipSuccess)
       return e;
   return hipFuncSetAttribute((const void*)k_rs_select, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2199,7 +2316,8 @@ void Batch::free_device() {
     l.map = nullptr;
     l.grid = 0;
   }
-  tile_lds = 0;
+  for (int64_t& x : tile_lds) x = 0;
+  tmma_waves = 16;
   arena_used = 0;
   if (step_graph) hipGraphExecDestroy(step_graph);
   step_graph = nullptr;
@@ -2322,6 +2440,19 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
   b.any_cluster = 0;
   b.max_lds = 0;
   b.max_R = 0;
+  // Matrix-core tiles: while the batch has at most 128 of them, one
+  // work-group per 16-replica group spreads them over four times the
+  // compute units (a single instance's step is 1.4x faster); beyond, one
+  // work-group per tile shares each coupling block between its four groups
+  // in the unit's L1 (1.7x the throughput of group work-groups with 1,024
+  // tiles).  PAMC_TMMA_GROUPS = 0 or 1 forces one.
+  {
+    int64_t mt = 0;
+    for (int i = 0; i < b.n; ++i)
+      if (!insts[i]->dense && insts[i]->tile == 2) mt += insts[i]->T;
+    b.tmma_groups = mt <= 128;
+    if (const char* g = getenv("PAMC_TMMA_GROUPS")) b.tmma_groups = atoi(g) != 0;
+  }
   for (int i = 0; i < b.n; ++i) {
     pamc_instance* I = insts[i];
     b.max_R = std::max(b.max_R, I->R);
@@ -2331,11 +2462,11 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     add_blocks(m_thr, i, kThrBlocks, false);
     add_blocks(m_gather, i, (int64_t)I->T * ((I->nq + kGatherQuadsPerBlock - 1) / kGatherQuadsPerBlock), true);
     if (I->tile == 2) {  // the same with matrix-core fields
-      add_blocks(m_tile[3], i, I->T, false);
-      b.tile_lds = std::max<int64_t>(b.tile_lds, tmma_lds_bytes(I->nks));
+      add_blocks(m_tile[3], i, (int64_t)I->T * (b.tmma_groups ? 4 : 1), false);
+      b.tile_lds[3] = std::max<int64_t>(b.tile_lds[3], tmma_lds_bytes(I->nks, b.tmma_groups ? 16 : 64));
     } else if (I->tile) {  // one work-group per replica tile walks the whole step
       add_blocks(m_tile[I->jmode], i, I->T, false);
-      b.tile_lds = std::max<int64_t>(b.tile_lds, tile_lds_bytes(I->nq, I->tile_rows));
+      b.tile_lds[I->jmode] = std::max<int64_t>(b.tile_lds[I->jmode], tile_lds_bytes(I->nq, I->tile_rows));
     } else {
       const int grp = Batch::group_of(I);
       add_blocks(m_sweep[grp], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_chunks(I), true);
@@ -2386,6 +2517,14 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
     if ((e = up(m_sweep[g], b.sweep[g])) != hipSuccess) return e;
   for (int g = 0; g < 4; ++g)
     if ((e = up(m_tile[g], b.tile[g])) != hipSuccess) return e;
+  // matrix-core tiles: 8-wave work-groups, two per compute unit, once the
+  // launch has at least two per unit and two fit the unit's LDS
+  // (PAMC_TMMA_WAVES = 8 or 16 forces a size)
+  b.tmma_waves = ((int64_t)m_tile[3].size() >= 2 * kComputeUnits &&
+                  2 * (b.tile_lds[3] + (int64_t)sizeof(int64_t) * 8 * kLanes + 64) <= kCuLdsBytes)
+                     ? 8
+                     : 16;
+  if (const char* w = getenv("PAMC_TMMA_WAVES")) b.tmma_waves = atoi(w) == 8 ? 8 : 16;
   // the staging vectors are local: wait for the copies before they go
   return hipStreamSynchronize(b.stream);
 }
@@ -2439,12 +2578,21 @@ static hipError_t batch_sweeps(Batch& b, int32_t nsweeps, int32_t commit = -1) {
   if (b.thr.grid) k_thresholds<<<b.thr.grid, 256, 0, b.stream>>>(b.d_desc, b.thr.map, commit);
   int64_t launches = 0;
   if (prof) hipEventRecord(next_event(P), b.stream);
-  static const SweepTileKernel tile_kernels[4] = {k_sweep_tile<0>, k_sweep_tile<1>, k_sweep_tile<2>, k_sweep_tmma};
-  for (int g = 0; g < 4; ++g)
+  static const SweepTileKernel tile_kernels[3] = {k_sweep_tile<0>, k_sweep_tile<1>, k_sweep_tile<2>};
+  for (int g = 0; g < 3; ++g)
     if (b.tile[g].grid) {  // every sweep of the step, in one launch
-      tile_kernels[g]<<<b.tile[g].grid, kTileWaves * 64, b.tile_lds, b.stream>>>(b.d_desc, b.tile[g].map);
+      tile_kernels[g]<<<b.tile[g].grid, kTileWaves * 64, b.tile_lds[g], b.stream>>>(b.d_desc, b.tile[g].map);
       ++launches;
     }
+  if (b.tile[3].grid) {
+    if (b.tmma_groups)
+      k_sweep_tmma_g<8><<<b.tile[3].grid, 8 * 64, b.tile_lds[3], b.stream>>>(b.d_desc, b.tile[3].map);
+    else if (b.tmma_waves == 8)
+      k_sweep_tmma<8><<<b.tile[3].grid, 8 * 64, b.tile_lds[3], b.stream>>>(b.d_desc, b.tile[3].map);
+    else
+      k_sweep_tmma<16><<<b.tile[3].grid, 16 * 64, b.tile_lds[3], b.stream>>>(b.d_desc, b.tile[3].map);
+    ++launches;
+  }
   for (int s = 0; s < nsweeps; ++s) {
     for (int p = 0; p < b.max_ncls; ++p) {
       for (int g = 0; g < Batch::kGroups; ++g) {

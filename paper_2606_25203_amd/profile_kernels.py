@@ -55,8 +55,8 @@ def sweep_kernel(info, potts=False):
         return "k_dense_step<0>"
     if potts:
         return f"k_sweep_potts<{info.potts_K}>"
-    if info.tile_sweeps == 2:
-        return "k_sweep_tmma"
+    if info.tile_sweeps == 2:  # one instance (at most 128 tiles): a work-group per 16-replica group
+        return "k_sweep_tmma_g<8>"
     if info.tile_sweeps:
         return f"k_sweep_tile<{info.coupling_mode}>"
     if info.pull:

@@ -39,7 +39,7 @@ def workload(name):
         return dict(kind="csr", graph=g, R=256, steps=50, sweeps=5,
                     sched=dict(beta0=0.1, dbeta=2.9 / 49, steps=50, sweeps=5),
                     desc="plain PAMC, random graph n=800 m=19176 w=+1, R=256, 50 beta steps 0.1->3.0 x 5 sweeps",
-                    counters="k_sweep_tile_gnm800_R256", cpu=dict(R=256, step_s=0.3))
+                    counters="k_sweep_tmma_gnm800_R256", cpu=dict(R=256, step_s=0.3))
     if name == "c3":
         n = 100_000
         return dict(kind="dense", n=n, R=256, steps=200, sweeps=1,

@@ -324,3 +324,26 @@ def test_batch_switches_field_forms_per_instance(pamc, monkeypatch):
         assert np.array_equal(s, os_) and np.array_equal(h, oh) and np.array_equal(E, oE) and np.array_equal(f, of)
         assert inst.info().pull == 0 or inst.info().hubs == 0
         inst.close()
+
+
+@pytest.mark.parametrize("count", [40, 130])
+def test_batch_of_matrix_core_tiles(pamc, count):
+    """Batches of dense-ish int8 instances that take the matrix-core tile
+    form: 40 instances of 4 tiles run one 16-wave work-group per tile, 130
+    (520 work-groups, two per compute unit) 8-wave ones; a single instance
+    runs one work-group per 16-replica group.  Every batched run equals its
+    plain run."""
+    g = synth.random_graph(301, 2500, 3)
+    sched = pamc.schedule(beta0=0.1, dbeta=0.1, steps=10, sweeps=2, augmented=1, z_rst=8, n_top=4, tau=3)
+    say(f"case batch of {count} matrix-core tile instances")
+    insts = [pamc.Instance.csr(g, replicas=256, seed=100 + k) for k in range(count)]
+    assert insts[0].info().tile_sweeps == 2
+    res = pamc.anneal_batch(insts, [sched] * count)
+    for k in range(0, count, 13 if count > 40 else 3):
+        want, wbest, wstate, _ = plain_run(pamc, g, 256, 100 + k, sched)
+        same_result(res[k], want, f"instance {k}")
+        assert np.array_equal(insts[k].best()[2], wbest)
+        for x, y in zip(insts[k].state(), wstate):
+            assert np.array_equal(x, y)
+    for i in insts:
+        i.close()

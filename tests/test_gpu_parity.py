@@ -497,25 +497,33 @@ MMA_GRAPHS = {
 }
 
 
+MMA_FORMS = {"groups": dict(PAMC_TMMA_GROUPS="1"),                       # a work-group per 16 replicas
+             "tile16": dict(PAMC_TMMA_GROUPS="0", PAMC_TMMA_WAVES="16"),  # a 16-wave work-group per tile
+             "tile8": dict(PAMC_TMMA_GROUPS="0", PAMC_TMMA_WAVES="8")}    # an 8-wave one (large batches)
+
+
+@pytest.mark.parametrize("form", list(MMA_FORMS))
 @pytest.mark.parametrize("rule", [0, 1])
 @pytest.mark.parametrize("gname,R", [("c1_shape_small", 192), ("torus_pm1", 64), ("dense_ish", 128),
                                      ("int8_weights", 64), ("n1024", 128), ("n1021", 64)])
-def test_tile_mfma_sweeps(pamc, monkeypatch, rule, gname, R):
+def test_tile_mfma_sweeps(pamc, monkeypatch, form, rule, gname, R):
     """The tile-resident step with each colour class's fields computed on the
-    matrix cores (int8 couplings x int8 spins, 16 x 64 blocks): the same
-    trajectory as the oracle through sweeps, resampling, cluster moves and
-    the controller."""
+    matrix cores (int8 couplings x int8 spins, 16 x 64 blocks), in each of
+    its work-group forms: the same trajectory as the oracle through sweeps,
+    resampling, cluster moves and the controller."""
     g = MMA_GRAPHS[gname]()
     monkeypatch.setenv("PAMC_TILE", "2")
-    say(f"case tile-resident matrix-core sweeps {gname} n={g.n} R={R} rule={rule}")
+    for k, v in MMA_FORMS[form].items():
+        monkeypatch.setenv(k, v)
+    say(f"case tile-resident matrix-core sweeps {gname} n={g.n} R={R} rule={rule} form={form}")
     inst = pamc.Instance.csr(g, replicas=R, seed=23, rule=rule)
     info = inst.info()
     assert info.tile_sweeps == 2 and info.coupling_mode == 2
     o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 23, rule=rule)
-    inst.sweep(0.3 / (40 if gname == "int8_weights" else 1), 3)
-    o.sweep(0.3 / (40 if gname == "int8_weights" else 1), 3)
-    same_state(inst, o, "sweeps")
     scale = 1 / 40 if gname == "int8_weights" else 1
+    inst.sweep(0.3 * scale, 3)
+    o.sweep(0.3 * scale, 3)
+    same_state(inst, o, "sweeps")
     compare_anneal(pamc, inst, o, dict(beta0=0.1 * scale, dbeta=0.05 * scale, steps=40, sweeps=3, augmented=1,
                                        z_rst=30, n_top=6, mis_trials=3, win_short=4, win_long=6,
                                        max_distinct_short=2, max_distinct_long=3, tau=3))
