@@ -388,11 +388,14 @@ def measure(pamc, torch, name, steps, warmup, fields=None):
             # decision alone, and the products go to the int8 MFMA peak)
             mma = info.tile_sweeps == 2
             slots = 25.0 + 9.0 if mma else alu_slots_per_attempt(degree, info.coupling_mode)
+            # one work-group per 64-replica tile, or per 16-replica group in
+            # the matrix-core form of a launch with at most 128 tiles
+            cus = w["R"] // 16 if mma and w["R"] // 64 <= 128 else w["R"] // 64
             achieved = slots * rate / 1e12
             roof = {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TSLOTS,
                     "unit": "T int32 lane-op slots/s", "frac": achieved / VALU_PEAK_TSLOTS,
-                    "alu_slots_per_attempt": slots, "cus_used": w["R"] // 64,
-                    "frac_of_cus_used": achieved / VALU_PEAK_TSLOTS * 256 / (w["R"] // 64),
+                    "alu_slots_per_attempt": slots, "cus_used": cus,
+                    "frac_of_cus_used": achieved / VALU_PEAK_TSLOTS * 256 / cus,
                     "hbm_algorithmic_bytes_per_attempt": incremental_field_bytes_per_attempt(p_flip, degree)}
             if mma:
                 ops = 2.0 * degree * rate / 1e12  # the sparse product's multiply-adds, not the zero blocks
@@ -434,6 +437,14 @@ def measure(pamc, torch, name, steps, warmup, fields=None):
                 roof["counter_valu_issue_frac"] = c["SQ_INSTS_VALU"] / (256 * cyc)
                 if "cus_used" in roof:
                     roof["counter_valu_issue_frac_of_cus_used"] = c["SQ_INSTS_VALU"] / (roof["cus_used"] * cyc)
+            if "SQ_INSTS_VALU_MFMA_MOPS_I8" in c:
+                # the matrix-core products as issued (whole 16 x 64 blocks,
+                # zeros included; the counter counts units of 512 ops)
+                apd = c.get("attempts_per_dispatch", apl)
+                roof["counter_mfma_ops_per_attempt"] = 512.0 * c["SQ_INSTS_VALU_MFMA_MOPS_I8"] / apd
+                if c.get("mean_dispatch_ns_under_counters"):
+                    roof["counter_mfma_busy_frac_of_cus_used"] = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (
+                        4 * roof.get("cus_used", 256) * c["mean_dispatch_ns_under_counters"] * 1e-9 * 2.4e9)
     inst.close()
     return {"value": attempts / wall, "wall_s": wall, "ms_per_step": wall / steps * 1e3,
             "config": {"workload": w["desc"], "n": n, "replicas": w["R"], "beta_steps": w["steps"],
