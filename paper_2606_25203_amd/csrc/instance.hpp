@@ -193,6 +193,7 @@ struct Desc {
   int32_t potts_rule;     // 0 softmax-perturbed argmax, 1 cascaded p-bits (K = 3)
   int64_t W, X;
   int32_t n, np, nq, R, T, ncls, rule, pull, dense, shuffle, tr_cap, order_cap, qpw;
+  int32_t sweep_stride;   // incremental-field sweeps: a tile's work-groups take chunks c, c + stride, ...
   uint32_t k0, k1;
 };
 

@@ -30,6 +30,8 @@ namespace {
 
 constexpr int kSweepWaves = 4;             // waves per sweep workgroup
 constexpr int kMaxQuadsPerWave = 4;        // quads per wave per sweep work-group: 1, 2 or 4 (Desc::qpw)
+constexpr int kPushWorkGroups = 2048;      // incremental-field sweep work-groups of a lone instance (8 per CU)
+constexpr int kPushMinWorkGroups = 512;    // ... and the least per instance of a batch
 constexpr int kGatherQuadsPerBlock = 64;
 constexpr int kClusterMaxN = 26000;        // LDS: 5 bytes per vertex
 constexpr int kRsMaxR = 16384;
@@ -736,9 +738,9 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
   const int v0 = class_ptr[cls], v1 = class_ptr[cls + 1];
   const int q0 = v0 >> 2;
   const int nqc = ((v1 + 3) >> 2) - q0;
-  int tile, chunk;
-  group_chunk(d.T, lb, tile, chunk);
-  if (chunk * (kSweepWaves * d.qpw) >= nqc) return;
+  int tile, chunk0;
+  group_chunk(d.T, lb, tile, chunk0);
+  if (chunk0 * (kSweepWaves * d.qpw) >= nqc) return;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
   const int rule = d.rule;
   const int32_t Xt = (int32_t)st->table_x;
@@ -753,63 +755,67 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
   const size_t hbase = (size_t)tile * d.np;
   int64_t dE = 0;
   int32_t nflip = 0;
-  // the spin words and fields of all of the wave's quads up front: the
-  // vertices of one class are not neighbours, so no flip of this phase
-  // changes them (v < np always)
-  constexpr int kMaxQpw = 4;
-  uint32_t swq[kMaxQpw];
-  int32_t hqq[kMaxQpw][4];
+  // the work-group's chunks of the class: chunk0, chunk0 + stride, ... (the
+  // tile stays the same, so the energy sums stay per tile)
+  for (int chunk = chunk0; chunk * (kSweepWaves * d.qpw) < nqc; chunk += d.sweep_stride) {
+    // the spin words and fields of all of the wave's quads up front: the
+    // vertices of one class are not neighbours, so no flip of this phase
+    // changes them (v < np always)
+    constexpr int kMaxQpw = 4;
+    uint32_t swq[kMaxQpw];
+    int32_t hqq[kMaxQpw][4];
 #pragma unroll
-  for (int i = 0; i < kMaxQpw; ++i) {
-    const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
-    if (i < d.qpw && qi < nqc) {
-      const int q = q0 + qi;
-      swq[i] = S[((size_t)tile * d.nq + q) * kLanes + lane];
+    for (int i = 0; i < kMaxQpw; ++i) {
+      const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
+      if (i < d.qpw && qi < nqc) {
+        const int q = q0 + qi;
+        swq[i] = S[((size_t)tile * d.nq + q) * kLanes + lane];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) hqq[i][k] = H[(hbase + 4 * q + k) * kLanes + lane];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < kMaxQpw; ++i) {
-    if (i >= d.qpw) break;
-    const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
-    if (qi >= nqc) break;
-    const int q = q0 + qi;
-    const size_t sidx = ((size_t)tile * d.nq + q) * kLanes + lane;
-    uint32_t sw = swq[i];
-    const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
-    const int32_t (&hq)[4] = hqq[i];
-    bool dirty = false;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int v = 4 * q + k;
-      if (v < v0 || v >= v1) continue;
-      const int32_t h = hq[k];
-      const int32_t s = (int32_t)(int8_t)(sw >> (8 * k));
-      const int32_t x = s * h;
-      const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
-      const uint32_t T = thr[xi + Xt];
-      const bool flip = (rule == 1 && x <= 0) || (pick(rnd, k) < T);
-      const int32_t snew = -s;
-      if (flip) {
-        dE += 2 * (int64_t)x;
-        sw ^= (0xFEu << (8 * k));
-        dirty = true;
-        ++nflip;
+        for (int k = 0; k < 4; ++k) hqq[i][k] = H[(hbase + 4 * q + k) * kLanes + lane];
       }
-      if (__ballot(flip)) {
-        const int e0 = row_ptr[v], e1 = row_ptr[v + 1];
-        const int32_t dd = 2 * snew;
-        for (int e = e0; e < e1; ++e) {
-          const int j = col[e];
-          const int32_t add = Jc[e] * dd;
-          if (flip)
-            __hip_atomic_fetch_add(&H[(hbase + j) * kLanes + lane], add, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxQpw; ++i) {
+      if (i >= d.qpw) break;
+      const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
+      if (qi >= nqc) break;
+      const int q = q0 + qi;
+      const size_t sidx = ((size_t)tile * d.nq + q) * kLanes + lane;
+      uint32_t sw = swq[i];
+      const u32x4 rnd = philox10((uint32_t)q, gs, r, kTagSweep, d.k0, d.k1);
+      const int32_t (&hq)[4] = hqq[i];
+      bool dirty = false;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int v = 4 * q + k;
+        if (v < v0 || v >= v1) continue;
+        const int32_t h = hq[k];
+        const int32_t s = (int32_t)(int8_t)(sw >> (8 * k));
+        const int32_t x = s * h;
+        const int32_t xi = x < -Xt ? -Xt : (x > Xt ? Xt : x);
+        const uint32_t T = thr[xi + Xt];
+        const bool flip = (rule == 1 && x <= 0) || (pick(rnd, k) < T);
+        const int32_t snew = -s;
+        if (flip) {
+          dE += 2 * (int64_t)x;
+          sw ^= (0xFEu << (8 * k));
+          dirty = true;
+          ++nflip;
+        }
+        if (__ballot(flip)) {
+          const int e0 = row_ptr[v], e1 = row_ptr[v + 1];
+          const int32_t dd = 2 * snew;
+          for (int e = e0; e < e1; ++e) {
+            const int j = col[e];
+            const int32_t add = Jc[e] * dd;
+            if (flip)
+              __hip_atomic_fetch_add(&H[(hbase + j) * kLanes + lane], add, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+          }
         }
       }
+      if (dirty) S[sidx] = sw;
     }
-    if (dirty) S[sidx] = sw;
   }
   red[wave][lane] = dE;
   if (d.flip_ctr) {
@@ -2210,6 +2216,34 @@ hipError_t prepare_kernel_lds() {
                              (int)sizeof(uint64_t) * kRsMaxR);
 }
 
+static int64_t sweep_chunks(const pamc_instance* I) {
+  const int qpb = kSweepWaves * I->qpw;
+  return (I->max_class_quads + qpb - 1) / qpb;
+}
+
+// Work-groups per replica tile of a sweep launch.  Incremental-field sweeps
+// keep about `budget` per instance that loop over the class's chunks (a
+// launch sized for the largest class then costs a small class little: its
+// idle work-groups are few), the others one per chunk.
+static int64_t sweep_slots(const pamc_instance* I, int64_t budget) {
+  const int64_t chunks = sweep_chunks(I);
+  if (I->pull || I->potts_K) return chunks;
+  return std::min<int64_t>(chunks, std::max<int64_t>(1, budget / I->T));
+}
+
+// The budget: kPushWorkGroups for a lone instance, shared by the batch's
+// incremental-field instances down to kPushMinWorkGroups each (C4: 2,048
+// work-groups alone 3.21e11 attempts/s against 3.04e11 with 1,024 and
+// 3.11e11 with 4,096; 16 instances 5.14e11 with 512 each against 4.83e11
+// with 2,048).  PAMC_PUSH_WGS overrides.
+static int64_t push_budget(const std::vector<pamc_instance*>& insts) {
+  if (const char* e = getenv("PAMC_PUSH_WGS")) return std::max(1, atoi(e));
+  int64_t n_push = 0;
+  for (const pamc_instance* I : insts)
+    if (!I->dense && !I->potts_K && !I->pull && !I->tile) ++n_push;
+  return std::max<int64_t>(kPushMinWorkGroups, kPushWorkGroups / std::max<int64_t>(1, n_push));
+}
+
 Desc make_desc(const pamc_instance* I) {
   Desc d;
   memset(&d, 0, sizeof d);
@@ -2272,6 +2306,7 @@ Desc make_desc(const pamc_instance* I) {
   d.shuffle = (I->flags & 1u) ? 0 : 1;
   d.tr_cap = I->tr_cap;
   d.qpw = I->qpw;
+  d.sweep_stride = (int32_t)sweep_slots(I, kPushWorkGroups);  // batch_build sets the batch's
   d.tile_rows = I->tile_rows;
   d.Jt = I->g.Jt;
   d.nks = I->nks;
@@ -2368,10 +2403,6 @@ hipError_t fixed_scratch(void** ptr, size_t* bytes) {
   return hipSuccess;
 }
 
-static int64_t sweep_chunks(const pamc_instance* I) {
-  const int qpb = kSweepWaves * I->qpw;
-  return (I->max_class_quads + qpb - 1) / qpb;
-}
 
 // Appends an instance's local blocks to a map.  With align8 the instance's
 // first block is placed at a multiple of 8 (idle blocks fill the gap), so
@@ -2400,7 +2431,11 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
   if (b.n == 0) return hipSuccess;
   b.stream = insts[0]->stream;
   std::vector<Desc> desc(b.n);
-  for (int i = 0; i < b.n; ++i) desc[i] = make_desc(insts[i]);
+  const int64_t push_wgs = push_budget(insts);
+  for (int i = 0; i < b.n; ++i) {
+    desc[i] = make_desc(insts[i]);
+    desc[i].sweep_stride = (int32_t)sweep_slots(insts[i], push_wgs);
+  }
   // arena mode: per-run scratch sized for each instance's schedule
   std::vector<int32_t> cl_top(b.n), cl_trials(b.n);
   for (int i = 0; i < b.n; ++i) {
@@ -2469,7 +2504,7 @@ hipError_t batch_build(Batch& b, const std::vector<pamc_instance*>& insts, const
       b.tile_lds[I->jmode] = std::max<int64_t>(b.tile_lds[I->jmode], tile_lds_bytes(I->nq, I->tile_rows));
     } else {
       const int grp = Batch::group_of(I);
-      add_blocks(m_sweep[grp], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_chunks(I), true);
+      add_blocks(m_sweep[grp], i, (int64_t)(I->T / (I->pull ? I->tpw : 1)) * sweep_slots(I, push_wgs), true);
       b.max_ncls = std::max(b.max_ncls, I->ncls);
       b.group_ncls[grp] = std::max(b.group_ncls[grp], I->ncls);
     }
