@@ -356,9 +356,9 @@ def test_gathered_field_variants(pamc, monkeypatch, jmode, tpw, rule):
 @pytest.mark.parametrize("qpw", [1, 2, 4])
 @pytest.mark.parametrize("fields", FIELDS)
 def test_quads_per_wave(pamc, monkeypatch, qpw, fields):
-    monkeypatch.setenv("PAMC_TILE", "0")
     """Work-group shapes with 1, 2 and 4 vertex quads per wavefront over
     classes spanning many work-groups with a ragged last one (n = 1,599)."""
+    monkeypatch.setenv("PAMC_TILE", "0")
     g = synth.random_graph(1599, 5000, 23, weights="pm1")
     monkeypatch.setenv("PAMC_QPW", str(qpw))
     say(f"case qpw={qpw} fields={fields}")
@@ -369,6 +369,29 @@ def test_quads_per_wave(pamc, monkeypatch, qpw, fields):
         inst.sweep(beta, k)
         o.sweep(beta, k)
         same_state(inst, o, f"beta={beta}")
+    inst.close()
+
+
+@pytest.mark.parametrize("R,wgs", [(256, 4), (256, 12), (512, 24), (512, 80)])
+@pytest.mark.parametrize("qpw", [1, 4])
+def test_push_work_groups_loop_over_chunks(pamc, monkeypatch, R, wgs, qpw):
+    """Incremental-field sweeps with a small work-group budget per instance:
+    each of a tile's work-groups takes chunks c, c + stride, ... of the class
+    (here 1 to 10 work-groups per tile over classes of up to 20 chunks, with
+    4 tiles and with 8, the XCD-aware mapping): the oracle's trajectory
+    through an augmented run."""
+    monkeypatch.setenv("PAMC_TILE", "0")
+    monkeypatch.setenv("PAMC_PUSH_WGS", str(wgs))
+    monkeypatch.setenv("PAMC_QPW", str(qpw))
+    g = synth.random_graph(1599, 5000, 23, weights="pm1")
+    say(f"case push work-groups R={R} budget={wgs} qpw={qpw}")
+    inst = pamc.Instance.csr(g, replicas=R, seed=37, fields="push")
+    info = inst.info()
+    assert info.pull == 0 and info.quads_per_wave == qpw
+    o = oracle.Oracle.sparse(g.n, g.row_ptr, g.col, g.w, R, 37)
+    compare_anneal(pamc, inst, o, dict(beta0=0.1, dbeta=0.08, steps=25, sweeps=2, augmented=1, z_rst=20, n_top=8,
+                                       mis_trials=3, win_short=4, win_long=6, max_distinct_short=2,
+                                       max_distinct_long=3, tau=3))
     inst.close()
 
 
