@@ -425,7 +425,7 @@ def measure(pamc, torch, name, steps, warmup, fields=None):
         c = counters(w["counters"], "sparse.hip", kname)
         if c and "hbm_bytes_per_dispatch" in c:
             # measured bytes per dispatch of the counted sweeps (at the
-            # profiling driver's temperature), scaled to this run's launches
+            # profiling script's temperature), scaled to this run's launches
             roof["traffic"] = c["hbm_bytes_per_dispatch"] * apl / c.get("attempts_per_dispatch", apl)
             roof["traffic_gbs"] = roof["traffic"] / (launch_ms * 1e-3) / 1e9
             roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS

@@ -6,10 +6,10 @@ Usage: counters_summary.py OUT.json --copy-fetch DIR --copy-write DIR
            --pass NAME=DIR [--pass ...] [--extra FACTS.json] [--note TEXT]
            [--command TEXT ...]
 
-The profiling driver settles its population, idles for a second, then makes
+The profiling script settles its population, idles for a second, then makes
 the counted sweeps: dispatches before the first gap of at least half a
 second between dispatch starts are left out (a pass with no such gap is
-taken whole).  FACTS.json (the driver's own output) names the sweep kernel
+taken whole).  FACTS.json (the profiling script's own output) names the sweep kernel
 and the attempts of the counted sweeps; that kernel gets the attempts per
 dispatch.
 
@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--pass", dest="passes", action="append", default=[])
     ap.add_argument("--note", default="")
     ap.add_argument("--command", action="append", default=[], help="a command that made the passes")
-    ap.add_argument("--extra", default=None, help="the profiling driver's JSON output (kernel, attempts, ...)")
+    ap.add_argument("--extra", default=None, help="the profiling script's JSON output (kernel, attempts, ...)")
     a = ap.parse_args()
     cf, _ = load(a.copy_fetch)
     cw, _ = load(a.copy_write)

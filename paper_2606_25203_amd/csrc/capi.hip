@@ -1,6 +1,6 @@
 // capi.hip -- the C ABI (include/pamc.h): instance construction on the host
 // (validation, first-fit colouring, class-major relabelling, Max-3-Cut
-// embedding), device memory, and the drivers that enqueue the kernels.
+// embedding), device memory, and the host code that enqueues the kernels.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>

@@ -15,7 +15,7 @@ sees that kernel (and the small per-call setup kernels) and nothing else:
        (k_sweep_potts<3>)
 Before the counted sweeps the population is brought to the inverse
 temperature the workload's runs spend most sweeps near, so flip rates (and
-hence bytes) are representative; then the driver idles for a second, a gap
+hence bytes) are representative; then the script idles for a second, a gap
 the counter summary uses to leave the settling dispatches out.  Prints one
 JSON line: sweeps, attempts, launches, flips (from the library's counters),
 wall time, the name of the sweep kernel and the hash of the kernel sources
