@@ -1,10 +1,11 @@
 """Randomised parity: many small instances drawn from a fixed seed — graph
-shapes (random, torus, with a hub), weight ranges, objectives, Max-3-Cut
-embeddings and Potts labels, replica counts, update rules, field forms and
-schedules (plain, augmented with short stagnation windows and restarts, SA,
-stop at target, diversity trace) — each run through the library and the
-oracle and compared bit for bit: results, per-step traces, final
-populations, best configurations (ln Q sums to 1e-12 relative)."""
+shapes (random, torus, with a hub, dense-ish with int8 weights), weight
+ranges, objectives, Max-3-Cut embeddings and Potts labels, replica counts,
+update rules, field forms and schedules (plain, augmented with short
+stagnation windows and restarts, SA, stop at target, diversity trace) — each
+run through the library and the oracle and compared bit for bit: results,
+per-step traces, final populations, best configurations (ln Q sums to 1e-12
+relative)."""
 import sys
 
 import numpy as np
@@ -15,7 +16,8 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-CASES = 96
+CASES = 96        # the first six kinds, drawn by k % 6
+DENSE_CASES = 16  # dense-ish int8 graphs (the matrix-core tile form), after them
 
 
 @pytest.fixture(scope="module")
@@ -61,7 +63,44 @@ def with_weights(rng, g, wmax, positive=False):
     return synth.csr_from_edges(g.n, np.array(us), np.array(vs), w.astype(np.int32))
 
 
+def int8_mix(rng, g):
+    """The graph with weights +-1, +-2 and (one in twenty) +-127."""
+    us, vs = [], []
+    for v in range(g.n):
+        for e in range(g.row_ptr[v], g.row_ptr[v + 1]):
+            if g.col[e] > v:
+                us.append(v)
+                vs.append(int(g.col[e]))
+    w = rng.choice([1, 2, 127], p=[0.5, 0.45, 0.05], size=len(us)) * rng.choice([-1, 1], size=len(us))
+    return synth.csr_from_edges(g.n, np.array(us), np.array(vs), w.astype(np.int32))
+
+
+def draw_dense_case(k):
+    rng = np.random.default_rng(9000 + k)
+    n = int(rng.integers(24, 420))
+    m = min(int(rng.integers(4 * n, 14 * n)), n * (n - 1) // 2)
+    g = synth.random_graph(n, m, int(rng.integers(1 << 30)))
+    if rng.random() < 0.5:
+        g = int8_mix(rng, g)
+    R = int(rng.choice([64, 128, 192, 256]))
+    steps = int(rng.integers(8, 30))
+    sched = dict(beta0=float(rng.uniform(0.02, 0.3)), dbeta=float(rng.uniform(0.01, 0.06)), steps=steps,
+                 sweeps=int(rng.integers(1, 4)))
+    mode = str(rng.choice(["plain", "augmented", "augmented", "target"]))
+    if mode == "augmented":
+        sched.update(augmented=1, z_rst=int(rng.integers(steps // 2, steps + 5)), n_top=int(rng.integers(1, R // 8 + 1)),
+                     mis_trials=int(rng.integers(1, 5)), win_short=4, win_long=6, max_distinct_short=2,
+                     max_distinct_long=3, tau=int(rng.integers(1, 6)))
+    elif mode == "target":
+        sched.update(target=1, stop_at_target=1)
+    return dict(kind="dense_ish", g=g, R=R, rule=int(rng.integers(0, 2)), fields=None,
+                objective=int(rng.integers(0, 2)), sched=sched, seed=int(rng.integers(1, 1 << 40)), K=0, prule=0,
+                gamma=0.0, mode=mode, wmax=int(np.abs(g.w).max()))
+
+
 def draw_case(k):
+    if k >= CASES:
+        return draw_dense_case(k)
     rng = np.random.default_rng(7000 + k)
     kind = ["csr", "csr", "csr", "hub", "max3cut", "potts"][k % 6]
     n = int(rng.integers(24, 420))
@@ -125,7 +164,7 @@ def close(a, b):
     return abs(a - b) <= 1e-12 * max(1.0, abs(b))
 
 
-@pytest.mark.parametrize("k", range(CASES))
+@pytest.mark.parametrize("k", range(CASES + DENSE_CASES))
 def test_random_instance_matches_oracle(pamc, k):
     c = draw_case(k)
     say(f"case fuzz {k}: {c['kind']} n={c['g'].n} R={c['R']} rule={c['rule']} fields={c['fields']} "
