@@ -740,7 +740,11 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
   const int nqc = ((v1 + 3) >> 2) - q0;
   int tile, chunk0;
   group_chunk(d.T, lb, tile, chunk0);
-  if (chunk0 * (kSweepWaves * d.qpw) >= nqc) return;
+  // a class whose quads fit one pass of the tile's work-groups at one quad
+  // per wave takes one (a shorter chain per wave); larger ones the
+  // instance's quads per wave
+  const int qpw = (nqc + kSweepWaves - 1) / kSweepWaves <= d.sweep_stride ? 1 : d.qpw;
+  if (chunk0 * (kSweepWaves * qpw) >= nqc) return;
   const uint32_t gs = st->gs + (uint32_t)sweep_idx;
   const int rule = d.rule;
   const int32_t Xt = (int32_t)st->table_x;
@@ -757,7 +761,7 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
   int32_t nflip = 0;
   // the work-group's chunks of the class: chunk0, chunk0 + stride, ... (the
   // tile stays the same, so the energy sums stay per tile)
-  for (int chunk = chunk0; chunk * (kSweepWaves * d.qpw) < nqc; chunk += d.sweep_stride) {
+  for (int chunk = chunk0; chunk * (kSweepWaves * qpw) < nqc; chunk += d.sweep_stride) {
     // the spin words and fields of all of the wave's quads up front: the
     // vertices of one class are not neighbours, so no flip of this phase
     // changes them (v < np always)
@@ -766,8 +770,8 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
     int32_t hqq[kMaxQpw][4];
 #pragma unroll
     for (int i = 0; i < kMaxQpw; ++i) {
-      const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
-      if (i < d.qpw && qi < nqc) {
+      const int qi = chunk * (kSweepWaves * qpw) + i * kSweepWaves + wave;
+      if (i < qpw && qi < nqc) {
         const int q = q0 + qi;
         swq[i] = S[((size_t)tile * d.nq + q) * kLanes + lane];
 #pragma unroll
@@ -776,8 +780,8 @@ __device__ __forceinline__ void sweep_push_body(const PAMC_GLOBAL int32_t* __res
     }
 #pragma unroll
     for (int i = 0; i < kMaxQpw; ++i) {
-      if (i >= d.qpw) break;
-      const int qi = chunk * (kSweepWaves * d.qpw) + i * kSweepWaves + wave;
+      if (i >= qpw) break;
+      const int qi = chunk * (kSweepWaves * qpw) + i * kSweepWaves + wave;
       if (qi >= nqc) break;
       const int q = q0 + qi;
       const size_t sidx = ((size_t)tile * d.nq + q) * kLanes + lane;
