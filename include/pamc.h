@@ -108,9 +108,12 @@ typedef struct {
 /* Sparse instance from a symmetric CSR graph (both directions stored, no
  * self loops, no duplicate or zero entries, symmetric weights).
  * row_ptr[n+1], col[nnz], w[nnz] with nnz = row_ptr[n], int32.  Vertices are
- * coloured first-fit in id order and swept class by class (spins of a class
- * are mutually uncoupled, so this equals a one-spin-at-a-time sweep in that
- * order; Eq. 4, with the class sequence reshuffled every sweep).  Fails with
+ * coloured by saturation degree (DSATUR: next the uncoloured vertex with the
+ * most distinct neighbour colours, ties to the larger degree, then the lower
+ * id; it takes the least colour free among its neighbours) and swept class
+ * by class (spins of a class are mutually uncoupled, so this equals a
+ * one-spin-at-a-time sweep in that order; Eq. 4, with the class sequence
+ * reshuffled every sweep).  Fails with
  * PAMC_ERR_INVALID_ARG if 2*max_v sum_j |J_vj| does not fit int32. */
 pamc_status pamc_create_instance_csr(int32_t n, const int32_t* row_ptr, const int32_t* col,
                                      const int32_t* w, pamc_mem where, int32_t objective,
@@ -142,7 +145,10 @@ pamc_status pamc_create_instance_dense_random(int32_t n, uint64_t graph_seed,
  * one ancilla with id 3n.  With weighted degree d_i and A_i = floor(d_i/3)+1:
  * J_{(i,a),anc} = -(2A_i + d_i), J_{(i,a),(i,b)} = -2A_i,
  * J_{(i,a),(j,a)} = -w_ij.  Ground states are one-hot and decode to maximum
- * 3-cuts (see pamc_max3cut_decode). */
+ * 3-cuts (see pamc_max3cut_decode).  The sweep's colour classes come from
+ * the input graph's colouring c (as for pamc_create_instance_csr, k colours):
+ * spin (i,a) is in class (c(i) + a) mod max(k, 3), the ancilla in class
+ * max(k, 3). */
 pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, const int32_t* col,
                                          const int32_t* w, const pamc_config* cfg,
                                          pamc_instance** out);

@@ -86,6 +86,8 @@ def lib():
         L.orc_threshold.restype = C.c_uint32
         L.orc_colour.argtypes = [C.c_int32, i32p, i32p, i32p]
         L.orc_colour.restype = C.c_int32
+        L.orc_max3cut_colour.argtypes = [C.c_int32, i32p, i32p, i32p]
+        L.orc_max3cut_colour.restype = C.c_int32
         L.orc_dense_random.argtypes = [C.c_int32, C.c_uint64, i8p]
         L.orc_create_sparse.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_int32, C.c_int32,
                                         C.c_uint64, C.c_int32, C.c_int32, C.c_char_p, C.c_int32]
@@ -163,6 +165,15 @@ def threshold(beta: float, rule: int, x: int) -> int:
 def colour(n, row_ptr, col):
     out = np.zeros(n, dtype=np.int32)
     k = lib().orc_colour(n, np.ascontiguousarray(row_ptr, np.int32), np.ascontiguousarray(col, np.int32), out)
+    return k, out
+
+
+def max3cut_colour(n, row_ptr, col):
+    """The Max-3-Cut embedding's colouring (3n + 1 spins) from the base
+    graph (n vertices): (class count, colour per spin)."""
+    out = np.zeros(3 * n + 1, dtype=np.int32)
+    k = lib().orc_max3cut_colour(n, np.ascontiguousarray(row_ptr, np.int32), np.ascontiguousarray(col, np.int32),
+                                 out)
     return k, out
 
 

@@ -163,21 +163,44 @@ static void set_err(char* err, int32_t errlen, const char* msg) {
 }
 
 int32_t orc_colour(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* colour) {
-  /* c(v) = least k >= 0 not used by a neighbour u < v, v ascending. */
+  /* Saturation-degree (DSATUR) colouring: repeatedly take the uncoloured
+   * vertex with the most distinct colours among its neighbours, ties to the
+   * larger degree, then to the lower id, and give it the least colour no
+   * neighbour has.  A plain O(n^2) scan: the selection rule is written out
+   * as stated. */
   int32_t ncls = 0;
+  int32_t* sat = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
   int32_t* seen = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  for (int32_t v = 0; v < n; ++v) colour[v] = -1;
   for (int32_t k = 0; k <= n; ++k) seen[k] = -1;
-  for (int32_t v = 0; v < n; ++v) {
-    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-      int32_t u = col[e];
-      if (u < v) seen[colour[u]] = v;
+  for (int32_t step = 0; step < n; ++step) {
+    int32_t best = -1;
+    for (int32_t v = 0; v < n; ++v) {
+      if (colour[v] >= 0) continue;
+      if (best < 0 || sat[v] > sat[best] ||
+          (sat[v] == sat[best] && row_ptr[v + 1] - row_ptr[v] > row_ptr[best + 1] - row_ptr[best]))
+        best = v;
     }
+    const int32_t v = best;
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+      if (colour[col[e]] >= 0) seen[colour[col[e]]] = v;
     int32_t k = 0;
     while (seen[k] == v) ++k;
     colour[v] = k;
     if (k + 1 > ncls) ncls = k + 1;
+    /* the neighbours' saturation: colour k is new to u unless another
+     * coloured neighbour of u has it */
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      const int32_t u = col[e];
+      if (colour[u] >= 0) continue;
+      int has = 0;
+      for (int32_t f = row_ptr[u]; f < row_ptr[u + 1] && !has; ++f)
+        if (col[f] != v && colour[col[f]] == k) has = 1;
+      if (!has) sat[u]++;
+    }
   }
   free(seen);
+  free(sat);
   return ncls;
 }
 
@@ -264,13 +287,35 @@ static void init_population(orc* o) {
 
 /* Builds the internal graph from a validated CSR over input ids.  colour
  * classes give the sweep order; internal id = rank in (class, input id). */
+int32_t orc_max3cut_colour(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* colour) {
+  /* The embedding's classes from the base graph's colouring c (orc_colour,
+   * k colours): spin (i, a) takes (c(i) + a) mod m, m = max(k, 3), and the
+   * ancilla colour m.  Spins of one vertex differ by 1 or 2 < m; spins
+   * (i, a), (j, a) of an edge ij differ as c(i) != c(j) (both < m); the
+   * ancilla meets every spin.  So the colouring is proper, with m + 1
+   * classes of about 3n/m spins each and the ancilla alone. */
+  int32_t* c = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t k = n > 0 ? orc_colour(n, row_ptr, col, c) : 0;
+  int32_t m = k > 3 ? k : 3;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t a = 0; a < 3; ++a) colour[3 * i + a] = (c[i] + a) % m;
+  colour[3 * n] = m;
+  free(c);
+  return m + 1;
+}
+
+/* The relabelled graph, from a given colouring (colour_in, ncls_in) or, with
+ * colour_in NULL, orc_colour's (every vertex its own class when dense). */
 static void build_graph(orc* o, const int32_t* row_ptr, const int32_t* col,
-                        const int32_t* Jin, int32_t dense) {
+                        const int32_t* Jin, int32_t dense, const int32_t* colour_in, int32_t ncls_in) {
   int32_t n = o->n, nnz = row_ptr[n];
   o->nnz = nnz;
   o->dense = dense;
   int32_t* colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-  if (dense) {
+  if (colour_in) {
+    for (int32_t v = 0; v < n; ++v) colour[v] = colour_in[v];
+    o->ncls = ncls_in;
+  } else if (dense) {
     for (int32_t v = 0; v < n; ++v) colour[v] = v;
     o->ncls = n;
   } else {
@@ -334,7 +379,7 @@ orc* orc_create_sparse(int32_t n, const int32_t* row_ptr, const int32_t* col,
   o->seed = seed;
   o->rule = rule;
   o->shuffle = shuffle_classes;
-  build_graph(o, row_ptr, col, Jin, 0);
+  build_graph(o, row_ptr, col, Jin, 0, NULL, 0);
   free(Jin);
   init_population(o);
   return o;
@@ -401,7 +446,7 @@ orc* orc_create_potts(int32_t n, const int32_t* row_ptr, const int32_t* col,
   o->potts_K = K;
   o->potts_rule = potts_rule;
   o->potts_gamma = gamma;
-  build_graph(o, row_ptr, col, Jin, 0);
+  build_graph(o, row_ptr, col, Jin, 0, NULL, 0);
   free(Jin);
   init_potts(o);
   return o;
@@ -434,7 +479,7 @@ orc* orc_create_dense(int32_t n, const int8_t* J, int32_t objective,
   o->seed = seed;
   o->rule = rule;
   o->shuffle = 0;
-  build_graph(o, rp, cl, jj, 1);
+  build_graph(o, rp, cl, jj, 1, NULL, 0);
   free(rp); free(cl); free(jj);
   init_population(o);
   return o;
@@ -515,7 +560,10 @@ orc* orc_create_max3cut(int32_t n, const int32_t* row_ptr, const int32_t* col,
   o->seed = seed;
   o->rule = rule;
   o->shuffle = shuffle_classes;
-  build_graph(o, rp, cl, jj, 0);
+  int32_t* m3c = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t m3k = orc_max3cut_colour(n, row_ptr, col, m3c);
+  build_graph(o, rp, cl, jj, 0, m3c, m3k);
+  free(m3c);
   free(rp); free(cl); free(jj);
   o->m3_n = n;
   o->m3_row_ptr = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));

@@ -84,8 +84,15 @@ typedef struct {
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_pexp(double x);
 uint32_t orc_threshold(double beta, int32_t rule, int64_t x);
-/* first-fit colouring in vertex order; colour[v] out; returns number of classes */
+/* Saturation-degree (DSATUR) colouring: the uncoloured vertex with the most
+ * distinct neighbour colours next (ties: larger degree, then lower id), the
+ * least colour free among its neighbours; colour[v] out; returns the number
+ * of classes. */
 int32_t orc_colour(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* colour);
+/* The Max-3-Cut embedding's colouring (3n + 1 spins, spin 3i + a, ancilla
+ * 3n) from the base graph's colouring c (orc_colour) with k colours: (c(i) + a)
+ * mod max(k, 3), the ancilla max(k, 3).  Returns the class count. */
+int32_t orc_max3cut_colour(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* colour);
 /* dense +-1 couplings from a counter-based hash of (seed, i, j) */
 void orc_dense_random(int32_t n, uint64_t seed, int8_t* J);
 

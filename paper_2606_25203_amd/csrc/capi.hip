@@ -1,5 +1,5 @@
 // capi.hip -- the C ABI (include/pamc.h): instance construction on the host
-// (validation, first-fit colouring, class-major relabelling, Max-3-Cut
+// (validation, DSATUR colouring, class-major relabelling, Max-3-Cut
 // embedding), device memory, and the host code that enqueues the kernels.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -15,6 +15,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <string>
@@ -204,7 +205,7 @@ pamc::Batch* self_batch(pamc_instance* I, hipError_t* err) {
   if (!var) return dev_fail(var##_err, "batch descriptors")
 
 // Host half of building a sparse instance (no device calls, safe on any
-// thread): first-fit colouring, class-major relabelling, the relabelled and
+// thread): colouring, class-major relabelling, the relabelled and
 // padded CSR, W, X and the choice of sweep kernel.  Jin: couplings J in
 // caller ids (already validated).  T: replica tiles.
 struct HostSparse {
@@ -258,22 +259,59 @@ bool choose_fields(int32_t n, const int32_t* rp, uint32_t flags, bool potts, std
   return h.empty() && (int64_t)rp[n] <= 16 * (int64_t)n;
 }
 
-pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const int32_t* col,
-                           const std::vector<int32_t>& Jin, uint32_t flags, int32_t T, bool allow_dual = true) {
-  h.n = n;
-  h.np = (n + 3) & ~3;
-  h.nq = h.np / 4;
-  h.nnz = rp[n];
-  // first-fit colouring in id order: least colour unused by earlier neighbours
-  std::vector<int32_t> colour(n, -1), stamp(n + 1, -1);
+// Saturation-degree (DSATUR) colouring: the next vertex is the uncoloured
+// one with the most distinct colours among its coloured neighbours (ties:
+// the longer row, then the lower id); it takes the least colour none of its
+// neighbours has.  Candidates sit in an ordered set keyed (-saturation,
+// -degree, id); each vertex keeps the sorted colours its neighbours have
+// taken.  Returns the number of colours.
+int32_t dsatur_colour(int32_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& colour) {
+  colour.assign(n, -1);
+  std::vector<std::vector<int32_t>> seen(n);  // per vertex: its neighbours' colours, sorted
+  std::set<std::tuple<int32_t, int32_t, int32_t>> cand;
+  for (int32_t v = 0; v < n; ++v) cand.insert({0, -(rp[v + 1] - rp[v]), v});
+  std::vector<int32_t> stamp(n + 1, -1);
   int32_t ncls = 0;
-  for (int32_t v = 0; v < n; ++v) {
+  while (!cand.empty()) {
+    const int32_t v = std::get<2>(*cand.begin());
+    cand.erase(cand.begin());
     for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
-      if (col[e] < v) stamp[colour[col[e]]] = v;
+      if (colour[col[e]] >= 0) stamp[colour[col[e]]] = v;
     int32_t c = 0;
     while (stamp[c] == v) ++c;
     colour[v] = c;
     ncls = std::max(ncls, c + 1);
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+      const int32_t u = col[e];
+      if (colour[u] >= 0) continue;
+      std::vector<int32_t>& su = seen[u];
+      const auto it = std::lower_bound(su.begin(), su.end(), c);
+      if (it != su.end() && *it == c) continue;  // u has a neighbour of colour c already
+      const int32_t du = -(rp[u + 1] - rp[u]);
+      cand.erase({-(int32_t)su.size(), du, u});
+      su.insert(it, c);
+      cand.insert({-(int32_t)su.size(), du, u});
+    }
+  }
+  return ncls;
+}
+
+pamc_status prepare_sparse(HostSparse& h, int32_t n, const int32_t* rp, const int32_t* col,
+                           const std::vector<int32_t>& Jin, uint32_t flags, int32_t T, bool allow_dual = true,
+                           const std::vector<int32_t>* colour_in = nullptr) {
+  h.n = n;
+  h.np = (n + 3) & ~3;
+  h.nq = h.np / 4;
+  h.nnz = rp[n];
+  // the visit order's colour classes: the given colouring (the Max-3-Cut
+  // embedding's) or the DSATUR one
+  std::vector<int32_t> colour;
+  int32_t ncls = 0;
+  if (colour_in) {
+    colour = *colour_in;
+    for (int32_t v = 0; v < n; ++v) ncls = std::max(ncls, colour[v] + 1);
+  } else {
+    ncls = dsatur_colour(n, rp, col, colour);
   }
   h.ncls = ncls;
   h.class_ptr.assign(ncls + 1, 0);
@@ -595,10 +633,10 @@ pamc_status upload_sparse(pamc_instance* I, HostSparse& h) {
 }
 
 pamc_status build_sparse(pamc_instance* I, int32_t n, const int32_t* rp, const int32_t* col,
-                         const std::vector<int32_t>& Jin) {
+                         const std::vector<int32_t>& Jin, const std::vector<int32_t>* colour = nullptr) {
   HostSparse h;
   h.potts_K = I->potts_K;
-  pamc_status st = prepare_sparse(h, n, rp, col, Jin, I->flags, I->T);
+  pamc_status st = prepare_sparse(h, n, rp, col, Jin, I->flags, I->T, true, colour);
   if (st) return st;
   return upload_sparse(I, h);
 }
@@ -927,10 +965,21 @@ pamc_status pamc_create_instance_max3cut(int32_t n, const int32_t* row_ptr, cons
     if (2 * ab >= INT32_MAX) return fail(PAMC_ERR_INVALID_ARG, "local field range exceeds int32");
     rp[u + 1] = (int32_t)cl.size();
   }
+  // the embedding's colour classes from the base graph's colouring c with
+  // k colours: spin (i, a) takes (c(i) + a) mod max(k, 3) (the spins of one
+  // vertex differ by 1 or 2, those of an edge ij by c(i) != c(j)), the
+  // ancilla a class of its own: max(k, 3) classes of about 3n / max(k, 3)
+  // spins instead of the long tail of small classes a colouring of the
+  // embedding itself gives
+  std::vector<int32_t> base, m3colour(N);
+  const int32_t k = dsatur_colour(n, row_ptr, col, base), m = std::max(k, 3);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t a = 0; a < 3; ++a) m3colour[3 * i + a] = (base[i] + a) % m;
+  m3colour[anc] = m;
   pamc_instance* I = new (std::nothrow) pamc_instance();
   if (!I) return fail(PAMC_ERR_OUT_OF_MEMORY, "host allocation");
   st = open_device(I, cfg);
-  if (!st) st = build_sparse(I, N, rp.data(), cl.data(), J);
+  if (!st) st = build_sparse(I, N, rp.data(), cl.data(), J, &m3colour);
   if (!st) {
     I->m3_n = n;
     const int32_t nnz = row_ptr[n];

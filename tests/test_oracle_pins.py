@@ -134,6 +134,31 @@ def test_thresholds_vs_mpmath(oracle_lib, rule):
 
 
 # ----------------------------------------------------------------- colouring
+def dsatur(g):
+    """Saturation-degree colouring written out plainly: repeatedly the
+    uncoloured vertex with the most distinct colours among its coloured
+    neighbours (ties: the higher degree, then the lower id) takes the least
+    colour none of its neighbours has."""
+    col = [-1] * g.n
+    deg = [int(g.row_ptr[v + 1] - g.row_ptr[v]) for v in range(g.n)]
+    nbrs = [[int(u) for u in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]] for v in range(g.n)]
+    for _ in range(g.n):
+        best = None
+        for v in range(g.n):
+            if col[v] >= 0:
+                continue
+            key = (len({col[u] for u in nbrs[v] if col[u] >= 0}), deg[v], -v)
+            if best is None or key > best[0]:
+                best = (key, v)
+        v = best[1]
+        used = {col[u] for u in nbrs[v]}
+        k = 0
+        while k in used:
+            k += 1
+        col[v] = k
+    return col
+
+
 def first_fit(g):
     col = [-1] * g.n
     for v in range(g.n):
@@ -145,17 +170,42 @@ def first_fit(g):
     return col
 
 
-def test_colouring_is_first_fit_and_valid(oracle_lib):
-    for g in [synth.random_graph(300, 2000, 3), synth.torus(10, 8, 1), synth.random_graph(50, 600, 9)]:
+def test_colouring_is_dsatur_and_valid(oracle_lib):
+    for g in [synth.random_graph(300, 2000, 3), synth.torus(10, 8, 1), synth.random_graph(50, 600, 9),
+              synth.random_graph(120, 200, 5)]:
         k, col = oracle_lib.colour(g.n, g.row_ptr, g.col)
-        assert list(col) == first_fit(g)
+        assert list(col) == dsatur(g)
         assert k == max(col) + 1
         for v in range(g.n):
             for u in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]:
                 assert col[u] != col[v]
+        assert k <= max(first_fit(g)) + 1  # no more colours than first-fit on these graphs
     g = synth.config_c2_graph()
     k, col = oracle_lib.colour(g.n, g.row_ptr, g.col)
     assert k == 2  # even torus is bipartite
+    assert list(col) == first_fit(g)  # the same two classes as a first-fit colouring in id order
+
+
+def test_max3cut_colouring_is_proper_and_balanced(oracle_lib):
+    """The embedding's classes: spin (i, a) in (c(i) + a) mod max(k, 3), the
+    ancilla alone; a proper colouring of the embedded graph, checked edge by
+    edge, and the oracle's instance takes these classes."""
+    for g in [synth.random_graph(60, 150, 3), synth.random_graph(7, 13, 4), synth.config_c4_graph()]:
+        k, c = oracle_lib.colour(g.n, g.row_ptr, g.col)
+        m3k, m3 = oracle_lib.max3cut_colour(g.n, g.row_ptr, g.col)
+        m = max(k, 3)
+        assert m3k == m + 1 and m3[3 * g.n] == m
+        assert all(m3[3 * i + a] == (c[i] + a) % m for i in range(g.n) for a in range(3))
+        # the embedding's edges: the three spins of a vertex, the spins of an
+        # edge in one layer, the ancilla with every spin
+        for i in range(g.n):
+            assert len({m3[3 * i], m3[3 * i + 1], m3[3 * i + 2]}) == 3
+            for j in g.col[g.row_ptr[i]:g.row_ptr[i + 1]]:
+                for a in range(3):
+                    assert m3[3 * i + a] != m3[3 * j + a]
+        assert np.count_nonzero(m3 == m) == 1
+        o = oracle_lib.Oracle.max3cut(g.n, g.row_ptr, g.col, g.w, 64, 1)
+        assert np.array_equal(np.diff(o.class_ptr()), np.bincount(m3, minlength=m + 1))
 
 
 def test_internal_order_is_class_major(oracle_lib):
@@ -445,8 +495,8 @@ def test_dense_random_couplings(oracle_lib):
 
 
 def test_dense_matches_sparse_on_same_couplings_and_order(oracle_lib):
-    # a dense instance sweeps in vertex order; on a complete graph first-fit
-    # colouring also gives singleton classes in vertex order.
+    # a dense instance sweeps in vertex order; on a complete graph the
+    # DSATUR colouring also gives singleton classes in vertex order.
     J = oracle_lib.dense_random(40, 3)
     g = synth.csr_from_dense(J)
     a = oracle_lib.Oracle.dense(J, 64, 11)
