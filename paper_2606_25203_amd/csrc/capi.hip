@@ -15,7 +15,6 @@
 #include <memory>
 #include <mutex>
 #include <new>
-#include <set>
 #include <thread>
 #include <unordered_map>
 #include <string>
@@ -262,35 +261,54 @@ bool choose_fields(int32_t n, const int32_t* rp, uint32_t flags, bool potts, std
 // Saturation-degree (DSATUR) colouring: the next vertex is the uncoloured
 // one with the most distinct colours among its coloured neighbours (ties:
 // the longer row, then the lower id); it takes the least colour none of its
-// neighbours has.  Candidates sit in an ordered set keyed (-saturation,
-// -degree, id); each vertex keeps the sorted colours its neighbours have
-// taken.  Returns the number of colours.
+// neighbours has.  Vertices are ranked once by (row length descending, id);
+// each saturation level keeps a min-heap of ranks, a vertex being pushed
+// again at its new level when its saturation grows (entries for coloured
+// vertices or for an older level are skipped when they come up); each
+// vertex keeps the sorted colours its neighbours have taken.  Returns the
+// number of colours.
 int32_t dsatur_colour(int32_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& colour) {
   colour.assign(n, -1);
-  std::vector<std::vector<int32_t>> seen(n);  // per vertex: its neighbours' colours, sorted
-  std::set<std::tuple<int32_t, int32_t, int32_t>> cand;
-  for (int32_t v = 0; v < n; ++v) cand.insert({0, -(rp[v + 1] - rp[v]), v});
+  std::vector<int32_t> order(n), rank(n), sat(n, 0);
+  for (int32_t v = 0; v < n; ++v) order[v] = v;
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    const int32_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
+    return da != db ? da > db : a < b;
+  });
+  for (int32_t i = 0; i < n; ++i) rank[order[i]] = i;
+  std::vector<std::vector<int32_t>> level(1);  // level[s]: min-heap of ranks at saturation s
+  auto push = [&](int32_t s, int32_t r) {
+    if ((int32_t)level.size() <= s) level.resize(s + 1);
+    level[s].push_back(r);
+    std::push_heap(level[s].begin(), level[s].end(), std::greater<int32_t>());
+  };
+  level[0] = order.empty() ? std::vector<int32_t>() : std::vector<int32_t>(n);
+  for (int32_t i = 0; i < n; ++i) level[0][i] = i;  // ascending: already a min-heap
+  std::vector<std::vector<int32_t>> seen(n);        // per vertex: its neighbours' colours, sorted
   std::vector<int32_t> stamp(n + 1, -1);
-  int32_t ncls = 0;
-  while (!cand.empty()) {
-    const int32_t v = std::get<2>(*cand.begin());
-    cand.erase(cand.begin());
+  int32_t ncls = 0, top = 0;
+  for (int32_t done = 0; done < n;) {
+    while (level[top].empty()) --top;
+    std::pop_heap(level[top].begin(), level[top].end(), std::greater<int32_t>());
+    const int32_t v = order[level[top].back()];
+    level[top].pop_back();
+    if (colour[v] >= 0 || sat[v] != top) continue;  // coloured, or now at a higher level
     for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
       if (colour[col[e]] >= 0) stamp[colour[col[e]]] = v;
     int32_t c = 0;
     while (stamp[c] == v) ++c;
     colour[v] = c;
     ncls = std::max(ncls, c + 1);
+    ++done;
     for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
       const int32_t u = col[e];
       if (colour[u] >= 0) continue;
       std::vector<int32_t>& su = seen[u];
       const auto it = std::lower_bound(su.begin(), su.end(), c);
       if (it != su.end() && *it == c) continue;  // u has a neighbour of colour c already
-      const int32_t du = -(rp[u + 1] - rp[u]);
-      cand.erase({-(int32_t)su.size(), du, u});
       su.insert(it, c);
-      cand.insert({-(int32_t)su.size(), du, u});
+      push(++sat[u], rank[u]);
+      top = std::max(top, sat[u]);
     }
   }
   return ncls;
